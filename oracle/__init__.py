@@ -1,0 +1,8 @@
+"""CPU FP64 oracle for the X2C Hamiltonian -- test infrastructure only.
+
+Imported by the tests, the smoke check and the benchmark's CPU-baseline leg;
+never by the GPU library or its Python binding.
+"""
+from .routes import (X2CError, assemble_w, dirac_matrices, dirac_positive_spectrum,  # noqa: F401
+                  reduced_dirac, spectrum_of, spin_blockdiag, spinor_matrices,
+                  x2c, x2c_direct, x2c_kbasis, x2c_polar)
