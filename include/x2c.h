@@ -1,0 +1,135 @@
+/*
+ * x2c.h -- C ABI of libx2c: the exact-decoupling (X2C) one-electron
+ * Hamiltonian of uncontracted atomic blocks on an AMD MI355X (gfx950).
+ *
+ * What is computed (Peng, Middendorf, Weigend, Reiher, J. Chem. Phys. 138,
+ * 184105 (2013)):  h = H(S, T, V, W) of Sec. II, Eq. r2ctrans, for one block
+ * or for a batch of independent atomic blocks as in the local DLU scheme
+ * (Sec. III.A, Eqs. dlutrans and r2ctransatom).  Per block:
+ *   1. the modified Dirac equation D C = M C eps (Sec. II, Eq. moddiraceq),
+ *      D = [[V, T], [T, W/4c^2 - T]], M = diag(S, T/2c^2), is reduced with the
+ *      Cholesky factors of S and T to a standard Hermitian problem;
+ *   2. its positive-energy branch (eigenvalues with eps + c^2 > 0, Sec. II) is
+ *      found: the n eigenvalues and the invariant subspace they span;
+ *   3. X = C_S C_L^-1 (Appendix, Eq. defxmat);
+ *   4. S~ = S + X^H T X / 2c^2 and the renormalisation
+ *      R = S^-1/2 (S^-1/2 S~ S^-1/2)^-1/2 S^1/2 (Sec. II.A, Eq. ulnonortho),
+ *      evaluated in the equivalent Cholesky form L_S^-H (L_S^-1 S~ L_S^-H)^-1/2 L_S^H;
+ *   5. h = R^H L R with L = V + T X + X^H T + X^H (W/4c^2 - T) X, i.e.
+ *      Eq. utrans with U^L = R and U^S = X R (Eq. usnonortho).
+ *
+ * Modes: spin-free (real N x N matrices, W = W^0; Sec. II scalar
+ * approximation) and two-component (2N x 2N complex Hermitian h in the
+ * spin-orbital basis [all alpha; all beta], Eq. defstv, with W built from
+ * W^0, W^x, W^y, W^z as in Eq. defw).
+ *
+ * Conventions for every function below:
+ *   - All matrices are row-major float64.  Complex matrices are interleaved
+ *     (re, im) pairs, i.e. the layout of complex128.
+ *   - Every pointer argument except `opts`, `N` (batched) and the offset
+ *     arrays is a DEVICE pointer on the current HIP device.  `N`, `in_off`,
+ *     `h_off` and `eps_off` of x2c_build_batched are HOST arrays.
+ *   - The caller owns every buffer.  The library never frees caller memory
+ *     and allocates no device memory of its own on these paths: all scratch
+ *     lives in the caller's workspace (size from x2c_workspace_bytes).
+ *   - `stream` is a hipStream_t (NULL = default stream); all device work is
+ *     enqueued on it.
+ *   - Inputs are assumed symmetric (S, T, V, W^0) / antisymmetric
+ *     (W^x, W^y, W^z); this is not checked.
+ */
+#ifndef X2C_H
+#define X2C_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { X2C_SPINFREE = 1, X2C_TWOCOMP = 2 } x2c_mode;
+typedef enum { X2C_FP64 = 0, X2C_SPLIT_BF16 = 1 } x2c_prec;
+
+typedef struct {
+  int mode;          /* x2c_mode */
+  int prec;          /* x2c_prec: arithmetic of the X / L / S~ / R product chain */
+  int ozaki_slices;  /* split precision only: bf16 slices per operand, 0 = automatic */
+  double c;          /* speed of light in atomic units (> 0) */
+} x2c_options;
+
+/* return codes */
+enum {
+  X2C_OK = 0,
+  X2C_EINVAL = -1,  /* bad argument: NULL pointer, N <= 0 or > x2c_max_n, c <= 0,
+                       unknown mode/prec, workspace too small, overlapping layout */
+  X2C_EHIP = -2,    /* a HIP runtime call or kernel launch failed */
+  X2C_EBLOCK = -3   /* x2c_build only: the block failed; see its info code */
+};
+
+/* per-block status codes (info) */
+enum {
+  X2C_INFO_OK = 0,
+  X2C_INFO_S_NOT_SPD = 1,    /* Cholesky of S failed */
+  X2C_INFO_T_NOT_SPD = 2,    /* Cholesky of T failed */
+  X2C_INFO_EIGEN = 3,        /* positive-energy subspace degenerate (singular large-component block) */
+  X2C_INFO_BRANCH = 4,       /* number of eigenvalues with eps + c^2 > 0 differs from n */
+  X2C_INFO_RENORM = 5,       /* L_S^-1 S~ L_S^-H not positive definite */
+  X2C_INFO_NONFINITE = 6     /* NaN or Inf in S, T, V or W */
+};
+
+/* Largest supported scalar block size N for a mode (0 for an unknown mode). */
+int x2c_max_n(int mode);
+
+/*
+ * Workspace size in bytes needed by x2c_build_batched for `nblk` blocks of
+ * scalar sizes N[0..nblk) (host array), or by x2c_build with nblk = 1.
+ * Returns 0 for invalid arguments.
+ */
+size_t x2c_workspace_bytes(const x2c_options* opts, int nblk, const int* N);
+
+/*
+ * One block (blocking).
+ *   N        scalar basis size (1 <= N <= x2c_max_n(mode)).
+ *   S, T, V  N x N each (device).
+ *   W        spin-free: W^0 (N x N); two-component: W^0, W^x, W^y, W^z
+ *            contiguous (4 x N x N) (device).
+ *   h        output: spin-free N x N float64; two-component 2N x 2N complex128 (device).
+ *   eps      output: the n positive-energy eigenvalues of Eq. moddiraceq,
+ *            ascending, in Hartree (n = N or 2N) (device).
+ * Synchronises `stream`.  Returns X2C_OK, X2C_EINVAL, X2C_EHIP, or
+ * X2C_EBLOCK with *info_out (host, may be NULL) set to the block's info code;
+ * on X2C_EBLOCK h and eps are zero.
+ */
+int x2c_build(const x2c_options* opts, int N, const double* S, const double* T, const double* V,
+              const double* W, void* h, double* eps, void* workspace, size_t ws_bytes, void* stream,
+              int* info_out);
+
+/*
+ * A batch of independent blocks of uneven sizes (stream-ordered, does not
+ * synchronise).  Block b has scalar size N[b]:
+ *   S, T, V  its N_b x N_b matrix starts at element in_off[b] of each array;
+ *   W        spin-free: at in_off[b];  two-component: 4 matrices at 4*in_off[b];
+ *   h        output at double offset h_off[b] (N_b^2 doubles spin-free,
+ *            2 * (2 N_b)^2 doubles = (2N_b)^2 complex128 two-component);
+ *   eps      output at double offset eps_off[b] (n_b doubles);
+ *   info     nblk ints (device): per-block status, valid once `stream`
+ *            has completed.  A failed block gets zero h and eps; the others
+ *            are unaffected.
+ * Returns X2C_OK once all work is enqueued, or X2C_EINVAL / X2C_EHIP.
+ */
+int x2c_build_batched(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off,
+                      const double* S, const double* T, const double* V, const double* W,
+                      const int64_t* h_off, void* h, const int64_t* eps_off, double* eps, int* info,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* Static description of a return or info code. */
+const char* x2c_strerror(int code);
+
+/* Drop cached launch plans (host memory only). */
+void x2c_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* X2C_H */

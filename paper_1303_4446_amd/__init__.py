@@ -1,0 +1,5 @@
+"""MI355X-native X2C one-electron Hamiltonian for batches of atomic (DLU)
+blocks: a thin binding over the HIP library libx2c.so (include/x2c.h)."""
+from ._lib import (EBLOCK, EHIP, EINVAL, EXPORTED, FP64, OK, SPLIT_BF16, SPINFREE, TWOCOMP,  # noqa: F401
+                   Batch, X2CError, batch_to_device, build, build_batched, load, max_n, strerror,
+                   unpack_h, workspace_bytes)

@@ -1,0 +1,220 @@
+"""ctypes binding of libx2c (argument marshalling only).
+
+Device memory and streams come from PyTorch; every step of the X2C build runs
+in the HIP kernels of libx2c.so.  There is no CPU fallback: if the library is
+missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libx2c.so")
+
+SPINFREE, TWOCOMP = 1, 2
+FP64, SPLIT_BF16 = 0, 1
+
+OK, EINVAL, EHIP, EBLOCK = 0, -1, -2, -3
+INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subspace degenerate",
+              4: "positive-energy branch size != n", 5: "renormalisation matrix not PD", 6: "non-finite input"}
+
+EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_strerror",
+            "x2c_release")
+
+
+class X2CError(RuntimeError):
+    def __init__(self, code: int, msg: str, info=None):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+        self.info = info
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("prec", ctypes.c_int), ("ozaki_slices", ctypes.c_int),
+                ("c", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load libx2c.so (built in-tree by paper_1303_4446_amd.build)."""
+    global _LIB
+    if _LIB is not None and path is None:
+        return _LIB
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise FileNotFoundError(f"{p} not built; run `python -m paper_1303_4446_amd.build`")
+    lib = ctypes.CDLL(p)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)
+    optp = ctypes.POINTER(_Options)
+    lib.x2c_max_n.argtypes = [i32]
+    lib.x2c_max_n.restype = i32
+    lib.x2c_workspace_bytes.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int)]
+    lib.x2c_workspace_bytes.restype = ctypes.c_size_t
+    lib.x2c_build.argtypes = [optp, i32, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp,
+                              ctypes.POINTER(ctypes.c_int)]
+    lib.x2c_build.restype = i32
+    lib.x2c_build_batched.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp,
+                                      i64p, vp, i64p, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.x2c_build_batched.restype = i32
+    lib.x2c_strerror.argtypes = [i32]
+    lib.x2c_strerror.restype = ctypes.c_char_p
+    lib.x2c_release.argtypes = []
+    lib.x2c_release.restype = None
+    if path is None:
+        _LIB = lib
+    return lib
+
+
+def options(twocomp: bool, c: float, prec: int = FP64, slices: int = 0) -> _Options:
+    return _Options(TWOCOMP if twocomp else SPINFREE, prec, slices, float(c))
+
+
+def strerror(code: int) -> str:
+    return load().x2c_strerror(code).decode()
+
+
+def max_n(twocomp: bool) -> int:
+    return load().x2c_max_n(TWOCOMP if twocomp else SPINFREE)
+
+
+def workspace_bytes(Ns, twocomp: bool, c: float = 137.0, prec: int = FP64) -> int:
+    Ns = np.ascontiguousarray(Ns, dtype=np.int32)
+    opt = options(twocomp, c, prec)
+    n = load().x2c_workspace_bytes(ctypes.byref(opt), len(Ns), Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if n == 0:
+        raise X2CError(EINVAL, "invalid block sizes or options")
+    return int(n)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libx2c needs a ROCm GPU; torch.cuda.is_available() is False")
+    return torch
+
+
+def _dev(t, torch, dtype):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError("expected a contiguous device tensor of dtype %s" % dtype)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(torch, stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Batch:
+    """Packed inputs of a batch on the device (layout of include/x2c.h)."""
+    S: object
+    T: object
+    V: object
+    W: object
+    Ns: np.ndarray
+    in_off: np.ndarray
+    twocomp: bool
+
+    @property
+    def nblk(self) -> int:
+        return len(self.Ns)
+
+    def out_layout(self):
+        n = self.Ns.astype(np.int64) * (2 if self.twocomp else 1)
+        hsz = n * n * (2 if self.twocomp else 1)          # doubles
+        h_off = np.zeros(self.nblk, dtype=np.int64)
+        eps_off = np.zeros(self.nblk, dtype=np.int64)
+        if self.nblk > 1:
+            h_off[1:] = np.cumsum(hsz)[:-1]
+            eps_off[1:] = np.cumsum(n)[:-1]
+        return h_off, eps_off, int(hsz.sum()), int(n.sum())
+
+
+def batch_to_device(packed: dict, twocomp: bool, device="cuda") -> Batch:
+    torch = _torch()
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+    return Batch(f(packed["S"]), f(packed["T"]), f(packed["V"]), f(packed["W"]),
+                 np.asarray(packed["Ns"], dtype=np.int32), np.asarray(packed["in_off"], dtype=np.int64), twocomp)
+
+
+def build_batched(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspace=None, out=None,
+                  stream=None):
+    """Enqueue x2c_build_batched.  Returns (h_flat, eps_flat, info) device
+    tensors (h_flat float64; complex blocks interleaved) and the workspace."""
+    torch = _torch()
+    lib = load()
+    dev = batch.S.device
+    h_off, eps_off, hsz, esz = batch.out_layout()
+    if out is None:
+        h = torch.empty(hsz, dtype=torch.float64, device=dev)
+        eps = torch.empty(esz, dtype=torch.float64, device=dev)
+        info = torch.empty(batch.nblk, dtype=torch.int32, device=dev)
+    else:
+        h, eps, info = out
+    wsb = workspace_bytes(batch.Ns, batch.twocomp, c, prec)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    opt = options(batch.twocomp, c, prec, slices)
+    Ns = np.ascontiguousarray(batch.Ns, dtype=np.int32)
+    i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
+    in_off, ho, eo = i64(batch.in_off), i64(h_off), i64(eps_off)
+    P = ctypes.POINTER(ctypes.c_int64)
+    rc = lib.x2c_build_batched(
+        ctypes.byref(opt), batch.nblk, Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), in_off.ctypes.data_as(P),
+        _dev(batch.S, torch, torch.float64), _dev(batch.T, torch, torch.float64),
+        _dev(batch.V, torch, torch.float64), _dev(batch.W, torch, torch.float64),
+        ho.ctypes.data_as(P), _dev(h, torch, torch.float64), eo.ctypes.data_as(P),
+        _dev(eps, torch, torch.float64), _dev(info, torch, torch.int32),
+        ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()), _stream_ptr(torch, stream))
+    if rc != OK:
+        raise X2CError(rc, strerror(rc))
+    return (h, eps, info), workspace
+
+
+def unpack_h(h_flat: np.ndarray, Ns, twocomp: bool):
+    """Split a flat host copy of h into per-block matrices."""
+    out = []
+    o = 0
+    for N in Ns:
+        n = int(N) * (2 if twocomp else 1)
+        if twocomp:
+            blk = h_flat[o:o + 2 * n * n].view(np.complex128).reshape(n, n)
+            o += 2 * n * n
+        else:
+            blk = h_flat[o:o + n * n].reshape(n, n)
+            o += n * n
+        out.append(blk)
+    return out
+
+
+def build(S, T, V, W, c: float, twocomp: bool, prec: int = FP64, slices: int = 0, workspace=None, stream=None):
+    """x2c_build on one block given as device tensors (S, T, V: N x N;
+    W: N x N (spin-free) or 4 x N x N).  Returns (h, eps) device tensors.
+    Raises X2CError with .info on a failed block."""
+    torch = _torch()
+    lib = load()
+    N = int(S.shape[0])
+    n = 2 * N if twocomp else N
+    dev = S.device
+    h = torch.empty((n, n), dtype=torch.complex128 if twocomp else torch.float64, device=dev)
+    eps = torch.empty(n, dtype=torch.float64, device=dev)
+    opt = options(twocomp, c, prec, slices)
+    wsb = workspace_bytes([N], twocomp, c, prec)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    info = ctypes.c_int(0)
+    rc = lib.x2c_build(ctypes.byref(opt), N, _dev(S, torch, torch.float64), _dev(T, torch, torch.float64),
+                       _dev(V, torch, torch.float64), _dev(W, torch, torch.float64),
+                       ctypes.c_void_p(h.data_ptr()), _dev(eps, torch, torch.float64),
+                       ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()),
+                       _stream_ptr(torch, stream), ctypes.byref(info))
+    if rc != OK:
+        raise X2CError(rc, strerror(rc) + (f": {INFO_NAMES.get(info.value)}" if rc == EBLOCK else ""),
+                       info.value)
+    return h, eps

@@ -1,0 +1,380 @@
+// Input staging, Cholesky factorisation of S and T, triangular inverses and
+// assembly of the Cholesky-reduced modified Dirac matrix.
+//
+// The modified Dirac equation (Sec. II, Eq. moddiraceq) D C = M C eps with
+// D = [[V, T], [T, W/4c^2 - T]] and M = diag(S, T/2c^2) is reduced to a
+// standard Hermitian problem with M = L_M L_M^H, L_M = diag(L_S, L_T/(sqrt2 c)):
+//   A = L_M^-1 D L_M^-H
+//     = [[L_S^-1 V L_S^-H,         sqrt2 c L_S^-1 L_T          ],
+//        [sqrt2 c L_T^H L_S^-H,    1/2 L_T^-1 W L_T^-H - 2c^2 I]].
+// S, T, V are spin-block diagonal (Eq. defstv) so L_S, L_T and the first three
+// blocks are real scalar N x N matrices; W is assembled from W^0..z
+// (Eq. defw) after the scalar-level congruence L_T^-1 W^q L_T^-T.
+#include "x2c_device.h"
+#include "x2c_launch.h"
+
+namespace x2c {
+
+__global__ void k_init_info(int* info, int nblk) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nblk) info[i] = 0;
+}
+
+// Copy S, T, V, W^q into the block workspace and flag non-finite input.
+__global__ void k_unpack(const BlockDesc* D, char* ws, int* info, const double* S,
+                         const double* T, const double* V, const double* W, int twocomp) {
+  const BlockDesc& d = D[blockIdx.y];
+  const long long NN = (long long)d.N * d.N;
+  const double* Sb = S + d.in_off;
+  const double* Tb = T + d.in_off;
+  const double* Vb = V + d.in_off;
+  const double* Wb = W + (twocomp ? 4 * d.in_off : d.in_off);
+  double* s = bufp<double>(ws, d, R_S);
+  double* t = bufp<double>(ws, d, R_T);
+  double* v = bufp<double>(ws, d, R_V);
+  double* ls = bufp<double>(ws, d, R_LS);
+  double* lt = bufp<double>(ws, d, R_LT);
+  double* w[4] = {bufp<double>(ws, d, R_W0), bufp<double>(ws, d, R_W1), bufp<double>(ws, d, R_W2),
+                  bufp<double>(ws, d, R_W3)};
+  const int nw = twocomp ? 4 : 1;
+  bool bad = false;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < NN;
+       i += (long long)gridDim.x * blockDim.x) {
+    double a = Sb[i], b = Tb[i], c = Vb[i];
+    s[i] = a; ls[i] = a;
+    t[i] = b; lt[i] = b;
+    v[i] = c;
+    bad |= !isfinite(a) || !isfinite(b) || !isfinite(c);
+    for (int q = 0; q < nw; ++q) {
+      double x = Wb[q * NN + i];
+      w[q][i] = x;
+      bad |= !isfinite(x);
+    }
+  }
+  if (bad) info[blockIdx.y] = 6;
+}
+
+// Right-looking Cholesky S = L L^T (lower, row-major, in place) of the real
+// N x N matrix; one work-group per (block, matrix).  grid = (2, nblk).
+__global__ void __launch_bounds__(256) k_potrf(const BlockDesc* D, char* ws, int* info) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int which = blockIdx.x;
+  const int N = d.N;
+  double* A = bufp<double>(ws, d, which == 0 ? R_LS : R_LT);
+  __shared__ double col[1024];
+  __shared__ int fail;
+  if (threadIdx.x == 0) fail = 0;
+  __syncthreads();
+  for (int j = 0; j < N; ++j) {
+    double ajj = A[(long long)j * N + j];
+    if (!(ajj > 0.0) || !isfinite(ajj)) {
+      if (threadIdx.x == 0) fail = 1;
+      __syncthreads();
+      break;
+    }
+    double ljj = sqrt(ajj);
+    double inv = 1.0 / ljj;
+    for (int i = j + 1 + threadIdx.x; i < N; i += blockDim.x) {
+      double lij = A[(long long)i * N + j] * inv;
+      A[(long long)i * N + j] = lij;
+      col[i] = lij;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) A[(long long)j * N + j] = ljj;
+    // trailing update of the lower triangle: A[i][k] -= L[i][j] L[k][j], j < k <= i
+    const int len = N - j - 1;
+    const long long tot = (long long)len * len;
+    for (long long t = threadIdx.x; t < tot; t += blockDim.x) {
+      int i = j + 1 + (int)(t / len);
+      int k = j + 1 + (int)(t % len);
+      if (k <= i) A[(long long)i * N + k] -= col[i] * col[k];
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (threadIdx.x == 0) info[b] = which == 0 ? 1 : 2;
+    return;
+  }
+  // zero the strict upper triangle
+  const long long NN = (long long)N * N;
+  for (long long t = threadIdx.x; t < NN; t += blockDim.x) {
+    int i = (int)(t / N), k = (int)(t % N);
+    if (k > i) A[t] = 0.0;
+  }
+}
+
+// Inverse of a real lower-triangular matrix by column forward substitution;
+// thread j computes column j.  grid = (2, nblk): (L_S, L_T).
+__global__ void __launch_bounds__(256) k_trtri(const BlockDesc* D, char* ws, const int* info) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int N = d.N;
+  const double* L = bufp<double>(ws, d, blockIdx.x == 0 ? R_LS : R_LT);
+  double* X = bufp<double>(ws, d, blockIdx.x == 0 ? R_LSI : R_LTI);
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    for (int i = 0; i < j; ++i) X[(long long)i * N + j] = 0.0;
+    X[(long long)j * N + j] = 1.0 / L[(long long)j * N + j];
+    for (int i = j + 1; i < N; ++i) {
+      double s = 0.0;
+      const double* Li = L + (long long)i * N;
+      for (int k = j; k < i; ++k) s = fma(Li[k], X[(long long)k * N + j], s);
+      X[(long long)i * N + j] = -s / Li[i];
+    }
+  }
+}
+
+// Spin expansion of the scalar matrices into the T-typed n x n buffers used
+// by the GEMM chain: S, T, V, L_S, L_S^-1, L_T^-1 as diag(A, A) and
+// W'' = W/4c^2 - T with W from Eq. defw.  Spin-free: plain copies.
+template <class T>
+__global__ void k_expand(const BlockDesc* D, char* ws, const int* info, double c) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int N = d.N, n = d.n;
+  const long long nn = (long long)n * n;
+  const double q4 = 1.0 / (4.0 * c * c);
+  const double* s = bufp<double>(ws, d, R_S);
+  const double* t = bufp<double>(ws, d, R_T);
+  const double* v = bufp<double>(ws, d, R_V);
+  const double* ls = bufp<double>(ws, d, R_LS);
+  const double* lsi = bufp<double>(ws, d, R_LSI);
+  const double* lti = bufp<double>(ws, d, R_LTI);
+  const double* w0 = bufp<double>(ws, d, R_W0);
+  const double* wx = bufp<double>(ws, d, R_W1);
+  const double* wy = bufp<double>(ws, d, R_W2);
+  const double* wz = bufp<double>(ws, d, R_W3);
+  T* oS = bufp<T>(ws, d, C_S);
+  T* oT = bufp<T>(ws, d, C_T);
+  T* oV = bufp<T>(ws, d, C_V);
+  T* oW = bufp<T>(ws, d, C_WPP);
+  T* oLS = bufp<T>(ws, d, C_LS);
+  T* oLSI = bufp<T>(ws, d, C_LSI);
+  T* oLTI = bufp<T>(ws, d, C_LTI);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(e / n), j = (int)(e % n);
+    int si = i / N, sj = j / N;   // spin index (0 = alpha, 1 = beta); always 0 in spin-free mode
+    int a = i - si * N, bb = j - sj * N;
+    long long k = (long long)a * N + bb;
+    bool diag = (si == sj);
+    double tv = diag ? t[k] : 0.0;
+    oS[e] = treal<T>(diag ? s[k] : 0.0);
+    oT[e] = treal<T>(tv);
+    oV[e] = treal<T>(diag ? v[k] : 0.0);
+    oLS[e] = treal<T>(diag ? ls[k] : 0.0);
+    oLSI[e] = treal<T>(diag ? lsi[k] : 0.0);
+    oLTI[e] = treal<T>(diag ? lti[k] : 0.0);
+    double wr, wi;
+    if (n == N) {            // spin-free
+      wr = w0[k]; wi = 0.0;
+    } else if (si == 0 && sj == 0) {
+      wr = w0[k]; wi = wz[k];
+    } else if (si == 0) {
+      wr = wy[k]; wi = wx[k];
+    } else if (sj == 0) {
+      wr = -wy[k]; wi = wx[k];
+    } else {
+      wr = w0[k]; wi = -wz[k];
+    }
+    oW[e] = tmake<T>(wr * q4 - tv, wi * q4);
+  }
+}
+
+// A = L_M^-1 D L_M^-H from the reduced scalar blocks.
+template <class T>
+__global__ void k_assemble_A(const BlockDesc* D, char* ws, const int* info, double c) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int N = d.N, n = d.n, m = d.m;
+  const long long mm = (long long)m * m;
+  const double* all = bufp<double>(ws, d, R_ALL);
+  const double* bb = bufp<double>(ws, d, R_B);
+  const double* w0 = bufp<double>(ws, d, R_WR0);
+  const double* wx = bufp<double>(ws, d, R_WR1);
+  const double* wy = bufp<double>(ws, d, R_WR2);
+  const double* wz = bufp<double>(ws, d, R_WR3);
+  T* A = bufp<T>(ws, d, C_A);
+  const double sq2c = sqrt(2.0) * c, two_c2 = 2.0 * c * c;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < mm;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(e / m), j = (int)(e % m);
+    int qi = i / n, qj = j / n;            // 0 = large, 1 = small component
+    int ii = i - qi * n, jj = j - qj * n;
+    int si = ii / N, sj = jj / N;
+    int a = ii - si * N, c2 = jj - sj * N;
+    bool sd = (si == sj);
+    T val;
+    if (qi == 0 && qj == 0) {
+      val = treal<T>(sd ? all[(long long)a * N + c2] : 0.0);
+    } else if (qi == 0 && qj == 1) {
+      val = treal<T>(sd ? sq2c * bb[(long long)a * N + c2] : 0.0);
+    } else if (qi == 1 && qj == 0) {
+      val = treal<T>(sd ? sq2c * bb[(long long)c2 * N + a] : 0.0);
+    } else {
+      long long k = (long long)a * N + c2;
+      double wr, wi;
+      if (n == N) {
+        wr = w0[k]; wi = 0.0;
+      } else if (si == 0 && sj == 0) {
+        wr = w0[k]; wi = wz[k];
+      } else if (si == 0) {
+        wr = wy[k]; wi = wx[k];
+      } else if (sj == 0) {
+        wr = -wy[k]; wi = wx[k];
+      } else {
+        wr = w0[k]; wi = -wz[k];
+      }
+      val = tmake<T>(0.5 * wr - (ii == jj ? two_c2 : 0.0), 0.5 * wi);
+    }
+    A[e] = val;
+  }
+}
+
+// dst = src (same dims), n x n T-typed buffers
+template <class T>
+__global__ void k_copy(const BlockDesc* D, char* ws, const int* info, int dsel, int src, int dst) {
+  const BlockDesc& d = D[blockIdx.y];
+  if (info[blockIdx.y]) return;
+  const int n = seldim(d, dsel);
+  const long long nn = (long long)n * n;
+  const T* s = bufp<T>(ws, d, src);
+  T* o = bufp<T>(ws, d, dst);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x)
+    o[e] = s[e];
+}
+
+// dst += src + src^H   (n x n)
+template <class T>
+__global__ void k_add_herm(const BlockDesc* D, char* ws, const int* info, int src, int dst) {
+  const BlockDesc& d = D[blockIdx.y];
+  if (info[blockIdx.y]) return;
+  const int n = d.n;
+  const long long nn = (long long)n * n;
+  const T* s = bufp<T>(ws, d, src);
+  T* o = bufp<T>(ws, d, dst);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(e / n), j = (int)(e % n);
+    o[e] = o[e] + s[e] + conjg(s[(long long)j * n + i]);
+  }
+}
+
+// dst = src^H  (n x n)
+template <class T>
+__global__ void k_conj_transpose(const BlockDesc* D, char* ws, const int* info, int src, int dst) {
+  const BlockDesc& d = D[blockIdx.y];
+  if (info[blockIdx.y]) return;
+  const int n = d.n;
+  const T* s = bufp<T>(ws, d, src);
+  T* o = bufp<T>(ws, d, dst);
+  __shared__ T tile[32][33];
+  const int tiles = (n + 31) / 32;
+  for (int t = blockIdx.x; t < tiles * tiles; t += gridDim.x) {
+    int ti = t / tiles, tj = t % tiles;
+    int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;   // 256 threads: 32 x 8
+    for (int r = ly; r < 32; r += 8) {
+      int i = ti * 32 + r, j = tj * 32 + lx;
+      if (i < n && j < n) tile[r][lx] = s[(long long)i * n + j];
+    }
+    __syncthreads();
+    for (int r = ly; r < 32; r += 8) {
+      int i = tj * 32 + r, j = ti * 32 + lx;   // o[i][j] = conj(s[j][i])
+      if (i < n && j < n) o[(long long)i * n + j] = conjg(tile[lx][r]);
+    }
+    __syncthreads();
+  }
+}
+
+// Write h (and zero h, eps of failed blocks).
+template <class T>
+__global__ void k_write_h(const BlockDesc* D, char* ws, const int* info, double* h, double* eps) {
+  const BlockDesc& d = D[blockIdx.y];
+  const int n = d.n;
+  const long long nn = (long long)n * n;
+  const bool ok = info[blockIdx.y] == 0;
+  const T* src = bufp<T>(ws, d, C_H);
+  T* out = reinterpret_cast<T*>(h + d.h_off);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x)
+    out[e] = ok ? src[e] : tzero<T>();
+  if (!ok)
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+      eps[d.eps_off + k] = 0.0;
+}
+
+// ----------------------------------------------------------------- launchers
+void launch_init_info(hipStream_t s, int* info, int nblk) {
+  hipLaunchKernelGGL(k_init_info, dim3((nblk + 255) / 256), dim3(256), 0, s, info, nblk);
+}
+void launch_unpack(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN,
+                   const double* S, const double* T, const double* V, const double* W, int twocomp) {
+  long long nn = (long long)maxN * maxN;
+  int gx = (int)((nn + 255) / 256);
+  if (gx > 64) gx = 64;
+  hipLaunchKernelGGL(k_unpack, dim3(gx, nblk), dim3(256), 0, s, D, ws, info, S, T, V, W, twocomp);
+}
+void launch_potrf(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk) {
+  hipLaunchKernelGGL(k_potrf, dim3(2, nblk), dim3(256), 0, s, D, ws, info);
+}
+void launch_trtri(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk) {
+  hipLaunchKernelGGL(k_trtri, dim3(2, nblk), dim3(256), 0, s, D, ws, info);
+}
+static int grid_for(long long elems) {
+  long long g = (elems + 255) / 256;
+  if (g > 256) g = 256;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+template <class T>
+void launch_expand(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, double c) {
+  hipLaunchKernelGGL(k_expand<T>, dim3(grid_for((long long)maxn * maxn), nblk), dim3(256), 0, s, D, ws, info, c);
+}
+template <class T>
+void launch_assemble_A(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxm, double c) {
+  hipLaunchKernelGGL(k_assemble_A<T>, dim3(grid_for((long long)maxm * maxm), nblk), dim3(256), 0, s, D, ws, info, c);
+}
+template <class T>
+void launch_copy(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
+                 int src, int dst) {
+  hipLaunchKernelGGL(k_copy<T>, dim3(grid_for((long long)maxdim * maxdim), nblk), dim3(256), 0, s, D, ws, info,
+                     dsel, src, dst);
+}
+template <class T>
+void launch_add_herm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, int src,
+                     int dst) {
+  hipLaunchKernelGGL(k_add_herm<T>, dim3(grid_for((long long)maxn * maxn), nblk), dim3(256), 0, s, D, ws, info,
+                     src, dst);
+}
+template <class T>
+void launch_conj_transpose(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn,
+                           int src, int dst) {
+  int tiles = (maxn + 31) / 32;
+  int g = tiles * tiles;
+  if (g > 256) g = 256;
+  hipLaunchKernelGGL(k_conj_transpose<T>, dim3(g, nblk), dim3(256), 0, s, D, ws, info, src, dst);
+}
+template <class T>
+void launch_write_h(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, double* h,
+                    double* eps) {
+  hipLaunchKernelGGL(k_write_h<T>, dim3(grid_for((long long)maxn * maxn), nblk), dim3(256), 0, s, D, ws, info, h,
+                     eps);
+}
+
+#define X2C_INST(T)                                                                                      \
+  template void launch_expand<T>(hipStream_t, const BlockDesc*, char*, const int*, int, int, double);       \
+  template void launch_assemble_A<T>(hipStream_t, const BlockDesc*, char*, const int*, int, int, double);   \
+  template void launch_copy<T>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int);  \
+  template void launch_add_herm<T>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int);   \
+  template void launch_conj_transpose<T>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int,   \
+                                         int);                                                           \
+  template void launch_write_h<T>(hipStream_t, const BlockDesc*, char*, const int*, int, int, double*, double*);
+X2C_INST(double)
+X2C_INST(cplx)
+
+}  // namespace x2c

@@ -1,0 +1,481 @@
+// Spectrum of the tridiagonal matrices and the matrix functions taken on it.
+//
+// (1) Positive-energy branch of the reduced 4c matrix (Sec. II: eigenvalues
+//     with eps + c^2 > 0).  Sturm-sequence counts give the branch size (it
+//     must equal n) and, by bisection, the n positive-energy eigenvalues.
+// (2) Positive-energy invariant subspace.  X = C_S C_L^-1 (Appendix,
+//     Eq. defxmat) depends only on the span of the positive-energy
+//     eigenvectors, so instead of individual eigenvectors (ill-determined
+//     inside the exactly degenerate Kramers and m_j multiplets) the kernel
+//     applies the spectral projector P = (I + sign(T - sigma))/2, sigma = -c^2,
+//     to a fixed block of n vectors.  sign() is Zolotarev's best rational
+//     approximation on [-1,-l] U [l,1] (coefficients from Jacobi elliptic
+//     functions, computed with the arithmetic-geometric mean), evaluated on
+//     the tridiagonal by complex shifted tridiagonal solves.
+// (3) Inverse square root of the renormalisation matrix (Sec. III:
+//     A^-1/2 = C a^-1/2 C^H).  Evaluated as
+//     x^-1/2 = (2/pi) int_0^{pi/2} dphi / (x cos^2 phi + sin^2 phi) with the
+//     (exponentially convergent, periodic) midpoint rule, i.e. a sum of
+//     shifted SPD tridiagonal inverses, again without eigenvectors.
+#include "x2c_device.h"
+#include "x2c_launch.h"
+
+namespace x2c {
+
+// number of eigenvalues of tridiag(d, e) below x (e2 = e^2)
+__device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// idx-th smallest eigenvalue (0-based) by bisection in [lo, hi]
+__device__ inline double bisect(const double* d, const double* e2, int n, int idx, double lo, double hi,
+                                double pivmin) {
+  double a = lo, b = hi;
+  for (int it = 0; it < 256; ++it) {
+    double mid = 0.5 * (a + b);
+    if (!(mid > a && mid < b)) break;
+    if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b))) break;
+    if (sturm_count(d, e2, n, mid, pivmin) > idx) b = mid;
+    else a = mid;
+  }
+  return 0.5 * (a + b);
+}
+
+// Gershgorin bounds of tridiag(d, e); block-wide
+__device__ inline void gershgorin(const double* d, const double* e, int n, double* lo, double* hi, double* red) {
+  double l = 1e300, h = -1e300;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+    l = fmin(l, d[i] - r);
+    h = fmax(h, d[i] + r);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    l = fmin(l, __shfl_xor(l, o, 64));
+    h = fmax(h, __shfl_xor(h, o, 64));
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = l;
+    red[16 + (threadIdx.x >> 6)] = h;
+  }
+  __syncthreads();
+  l = 1e300; h = -1e300;
+  for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) {
+    l = fmin(l, red[i]);
+    h = fmax(h, red[16 + i]);
+  }
+  __syncthreads();
+  // widen slightly so bisection brackets every eigenvalue
+  double span = fmax(h - l, fmax(fabs(l), fabs(h))) * 4e-16 + 1e-300;
+  *lo = l - span;
+  *hi = h + span;
+}
+
+// ---------------------------------------------------------------- Zolotarev
+// Jacobi sn, cn of real argument u, modulus k, via the descending Landen
+// (arithmetic-geometric mean) sequence a_0 = 1, b_0 = k' , c_0 = k.
+struct AGMSeq {
+  double a[48], c[48];
+  int N;
+};
+__device__ inline void agm_seq(double kc, double k, AGMSeq& s) {
+  double a = 1.0, b = kc, c = k;
+  s.a[0] = a; s.c[0] = c;
+  int i = 0;
+  while (i < 46 && fabs(c) > 1e-17) {
+    double an = 0.5 * (a + b);
+    c = 0.5 * (a - b);
+    b = sqrt(a * b);
+    a = an;
+    ++i;
+    s.a[i] = a; s.c[i] = c;
+  }
+  s.N = i;
+}
+__device__ inline void ellip_sn_cn(double u, const AGMSeq& s, double* sn, double* cn) {
+  double phi = ldexp(s.a[s.N] * u, s.N);
+  for (int i = s.N; i > 0; --i) phi = 0.5 * (phi + asin(s.c[i] / s.a[i] * sin(phi)));
+  *sn = sin(phi);
+  *cn = cos(phi);
+}
+
+// best type (2r+1, 2r) rational approximation of sign on [-1,-l] U [l,1]:
+// Z(x) = M x (1 + sum_j a_j / (x^2 + codd_j)); returns the max error.
+__device__ double zolotarev(double ell, int r, double* a, double* codd, double* Mout) {
+  double cvals[2 * RMAX];
+  AGMSeq s;
+  const double kp = sqrt((1.0 - ell) * (1.0 + ell));
+  agm_seq(ell, kp, s);                                   // modulus kp, complementary ell
+  const double Kp = 3.14159265358979323846 / (2.0 * s.a[s.N]);   // K(kp)
+  for (int i = 1; i <= 2 * r; ++i) {
+    double sn, cn;
+    ellip_sn_cn(i * Kp / (2 * r + 1), s, &sn, &cn);
+    cvals[i - 1] = ell * ell * sn * sn / (cn * cn);
+  }
+  for (int j = 0; j < r; ++j) codd[j] = cvals[2 * j];
+  for (int j = 0; j < r; ++j) {
+    double num = 1.0, den = 1.0;
+    for (int k = 0; k < r; ++k) {
+      num *= cvals[2 * k + 1] - codd[j];
+      if (k != j) den *= codd[k] - codd[j];
+    }
+    a[j] = num / den;
+  }
+  auto zhat = [&](double x) {
+    double s2 = 1.0;
+    for (int j = 0; j < r; ++j) s2 += a[j] / (x * x + codd[j]);
+    return x * s2;
+  };
+  double zl = zhat(ell), z1 = zhat(1.0);
+  double M = 2.0 / (zl + z1);
+  *Mout = M;
+  return fabs(M * z1 - 1.0);
+}
+
+// ---------------------------------------------------------------- 4c branch
+// One work-group per block.  Writes eps (positive branch, ascending), the
+// branch-size check (info 4) and the projector filter parameters.
+__global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws, int* info, double* eps, double c) {
+  const int b = blockIdx.x;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int m = d.m, n = d.n;
+  const double* dg = bufp<double>(ws, d, V_D);
+  const double* eg = bufp<double>(ws, d, V_E);
+  double* pf = bufp<double>(ws, d, P_FILT);
+  extern __shared__ char smem[];
+  double* sd = reinterpret_cast<double*>(smem);
+  double* se = sd + m;
+  double* se2 = se + m;
+  double* lam = se2 + m;     // n + 1 values
+  __shared__ double red[64];
+  __shared__ double s_lo, s_hi, s_piv;
+  __shared__ int s_cnt;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    sd[i] = dg[i];
+    if (i < m - 1) {
+      se[i] = eg[i];
+      se2[i] = eg[i] * eg[i];
+    }
+  }
+  __syncthreads();
+  double lo, hi;
+  gershgorin(sd, se, m, &lo, &hi, red);
+  double emax = 0.0;
+  for (int i = threadIdx.x; i < m - 1; i += blockDim.x) emax = fmax(emax, se2[i]);
+  for (int o = 32; o > 0; o >>= 1) emax = fmax(emax, __shfl_xor(emax, o, 64));
+  if ((threadIdx.x & 63) == 0) red[32 + (threadIdx.x >> 6)] = emax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e = 0.0;
+    for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) e = fmax(e, red[32 + i]);
+    s_piv = 2.2e-308 * fmax(1.0, e) * 16.0;
+    s_lo = lo;
+    s_hi = hi;
+    s_cnt = sturm_count(sd, se2, m, -c * c, s_piv);
+  }
+  __syncthreads();
+  if (s_cnt != m - n) {
+    if (threadIdx.x == 0) info[b] = 4;
+    return;
+  }
+  for (int k = threadIdx.x; k <= n; k += blockDim.x) lam[k] = bisect(sd, se2, m, n - 1 + k, s_lo, s_hi, s_piv);
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += blockDim.x) eps[d.eps_off + k] = lam[k + 1];
+  if (threadIdx.x == 0) {
+    const double sigma = -c * c;
+    const double gam = fmin(lam[1] - sigma, sigma - lam[0]);
+    const double rho = fmax(s_hi - sigma, sigma - s_lo);
+    double ell = 0.9 * gam / rho;
+    ell = fmin(fmax(ell, 1e-14), 0.5);
+    double abest[RMAX], cbest[RMAX], Mbest = 1.0;
+    double at[RMAX], ct[RMAX], Mt;
+    int rbest = 0;
+    double prev = 1.0;
+    for (int r = 4; r <= RMAX; r += 2) {
+      double err = zolotarev(ell, r, at, ct, &Mt);
+      bool take = (rbest == 0) || err <= prev;
+      if (take) {
+        for (int j = 0; j < r; ++j) { abest[j] = at[j]; cbest[j] = ct[j]; }
+        Mbest = Mt;
+        rbest = r;
+      }
+      if (err < 1e-13 || err > 0.5 * prev) break;
+      prev = err;
+    }
+    pf[0] = sigma;
+    pf[1] = rho;
+    pf[2] = Mbest;
+    pf[3] = (double)rbest;
+    for (int j = 0; j < rbest; ++j) {
+      pf[4 + j] = abest[j];
+      pf[4 + RMAX + j] = sqrt(cbest[j]);
+    }
+  }
+}
+
+// LU with partial pivoting of (T_s - i beta_j I), T_s = (T - sigma)/rho, one
+// pole per work-group (thread 0).  Factor entry layout (5 complex):
+// {dl, 1/du0, du1, du2, (pivot, 0)}.
+__global__ void k_filter_factor(const BlockDesc* D, char* ws, const int* info) {
+  const int b = blockIdx.y, j = blockIdx.x;
+  const BlockDesc& d = D[b];
+  if (info[b] || threadIdx.x != 0) return;
+  const double* pf = bufp<double>(ws, d, P_FILT);
+  const int r = (int)pf[3];
+  if (j >= r) return;
+  const int m = d.m;
+  const double sigma = pf[0], rho = pf[1], beta = pf[4 + RMAX + j];
+  const double* dg = bufp<double>(ws, d, V_D);
+  const double* eg = bufp<double>(ws, d, V_E);
+  cplx* F = bufp<cplx>(ws, d, F_FAC) + (long long)j * m * 5;
+  const double ir = 1.0 / rho;
+  // running diagonal / superdiagonal of the current row (after elimination)
+  cplx dcur = {(dg[0] - sigma) * ir, -beta};
+  cplx ucur = {m > 1 ? eg[0] * ir : 0.0, 0.0};
+  for (int i = 0; i < m - 1; ++i) {
+    cplx sub = {eg[i] * ir, 0.0};                  // l_i = A[i+1][i]
+    cplx dnext = {(dg[i + 1] - sigma) * ir, -beta};
+    cplx unext = {i + 1 < m - 1 ? eg[i + 1] * ir : 0.0, 0.0};
+    cplx* f = F + (long long)i * 5;
+    if (abs1(dcur) >= abs1(sub)) {
+      cplx fact = cdiv(sub, dcur);
+      f[0] = fact;
+      f[1] = crecip(dcur);
+      f[2] = ucur;
+      f[3] = {0.0, 0.0};
+      f[4] = {0.0, 0.0};
+      dcur = dnext - fact * ucur;
+      ucur = unext;
+    } else {
+      // swap rows i and i+1
+      cplx fact = cdiv(dcur, sub);
+      f[0] = fact;
+      f[1] = crecip(sub);
+      f[2] = dnext;          // new u1 of row i
+      f[3] = unext;          // fill-in u2 of row i
+      f[4] = {1.0, 0.0};
+      cplx nd = ucur - fact * dnext;
+      cplx nu = -(fact * unext);
+      dcur = nd;
+      ucur = nu;
+    }
+  }
+  cplx* f = F + (long long)(m - 1) * 5;
+  f[0] = {0.0, 0.0};
+  f[1] = crecip(dcur);
+  f[2] = {0.0, 0.0};
+  f[3] = {0.0, 0.0};
+  f[4] = {0.0, 0.0};
+}
+
+// Columns j of Z = 1/2 (E + M [T_s E + sum_q a_q Re((T_s - i beta_q)^-1 E)]),
+// E_ij = hash(i, j); the result (real) goes to the T-typed m x n buffer.
+template <class T>
+__global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* ws, const int* info) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int m = d.m, n = d.n;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double* pf = bufp<double>(ws, d, P_FILT);
+  const double sigma = pf[0], rho = pf[1], M = pf[2];
+  const int r = (int)pf[3];
+  const double* dg = bufp<double>(ws, d, V_D);
+  const double* eg = bufp<double>(ws, d, V_E);
+  T* Y = bufp<T>(ws, d, C_Y);
+  cplx* scr = bufp<cplx>(ws, d, Z_SCR);
+  const double ir = 1.0 / rho;
+  // acc = T_s E_j
+  for (int i = 0; i < m; ++i) {
+    double t = (dg[i] - sigma) * hash_uniform(i, j);
+    if (i > 0) t += eg[i - 1] * hash_uniform(i - 1, j);
+    if (i < m - 1) t += eg[i] * hash_uniform(i + 1, j);
+    Y[(long long)i * n + j] = treal<T>(t * ir);
+  }
+  for (int q = 0; q < r; ++q) {
+    const cplx* F = bufp<cplx>(ws, d, F_FAC) + (long long)q * m * 5;
+    const double aq = pf[4 + q];
+    // forward: y = L^-1 P b, streamed
+    cplx carry = {hash_uniform(0, j), 0.0};
+    for (int i = 0; i < m - 1; ++i) {
+      const cplx* f = F + (long long)i * 5;
+      cplx bnext = {hash_uniform(i + 1, j), 0.0};
+      cplx yi;
+      if (f[4].x == 0.0) {
+        yi = carry;
+        carry = bnext - f[0] * carry;
+      } else {
+        yi = bnext;
+        carry = carry - f[0] * bnext;
+      }
+      scr[(long long)i * n + j] = yi;
+    }
+    scr[(long long)(m - 1) * n + j] = carry;
+    // backward: U x = y;  acc += a_q Re(x)
+    cplx x1 = {0.0, 0.0}, x2 = {0.0, 0.0};
+    for (int i = m - 1; i >= 0; --i) {
+      const cplx* f = F + (long long)i * 5;
+      cplx y = scr[(long long)i * n + j];
+      cplx t = y - f[2] * x1 - f[3] * x2;
+      cplx x = t * f[1];
+      long long idx = (long long)i * n + j;
+      Y[idx] = treal<T>(re(Y[idx]) + aq * x.x);
+      x2 = x1;
+      x1 = x;
+    }
+  }
+  for (int i = 0; i < m; ++i) {
+    long long idx = (long long)i * n + j;
+    Y[idx] = treal<T>(0.5 * (hash_uniform(i, j) + M * re(Y[idx])));
+  }
+}
+
+// ---------------------------------------------------------------- Q^-1/2
+// Extreme eigenvalues of tridiag(dq, eq) (must be > 0: info 5), quadrature
+// nodes, and the LDL^T factors of (T_Q + s_j I) for every node.
+__global__ void __launch_bounds__(256) k_tri_eig_q(const BlockDesc* D, char* ws, int* info) {
+  const int b = blockIdx.x;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = d.n;
+  const double* dg = bufp<double>(ws, d, V_DQ);
+  const double* eg = bufp<double>(ws, d, V_EQ);
+  double* pq = bufp<double>(ws, d, P_QUAD);
+  double* fac = bufp<double>(ws, d, Q_FAC);
+  extern __shared__ char smem[];
+  double* sd = reinterpret_cast<double*>(smem);
+  double* se = sd + n;
+  double* se2 = se + n;
+  __shared__ double red[64];
+  __shared__ double s_min, s_max;
+  __shared__ int s_nodes;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    sd[i] = dg[i];
+    if (i < n - 1) {
+      se[i] = eg[i];
+      se2[i] = eg[i] * eg[i];
+    }
+  }
+  __syncthreads();
+  double lo, hi;
+  gershgorin(sd, se, n, &lo, &hi, red);
+  const double piv = 2.2e-308 * 16.0 * fmax(1.0, hi * hi);
+  if (threadIdx.x == 0) s_min = bisect(sd, se2, n, 0, lo, hi, piv);
+  if (threadIdx.x == 64 || (blockDim.x <= 64 && threadIdx.x == 0)) s_max = bisect(sd, se2, n, n - 1, lo, hi, piv);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double lmin = s_min, lmax = s_max;
+    if (!(lmin > 0.0) || !isfinite(lmax)) {
+      info[b] = 5;
+      s_nodes = 0;
+    } else {
+      double s = sqrt(lmin * lmax);
+      double kap = lmax / lmin;
+      double rate = 4.0 * atanh(pow(kap, -0.25));
+      int N = (int)ceil(38.0 / rate) + 2;
+      if (N > QMAX) N = QMAX;
+      if (N < 2) N = 2;
+      pq[0] = N;
+      pq[1] = lmin;
+      pq[2] = lmax;
+      for (int j = 0; j < N; ++j) {
+        double phi = (j + 0.5) * 3.14159265358979323846 / (2.0 * N);
+        double cph = cos(phi), tph = tan(phi);
+        pq[3 + j] = sqrt(s) / (N * cph * cph);
+        pq[3 + QMAX + j] = s * tph * tph;
+      }
+      s_nodes = N;
+    }
+  }
+  __syncthreads();
+  const int N = s_nodes;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const double sh = pq[3 + QMAX + j];
+    double* f = fac + (long long)j * n * 2;
+    double dcur = sd[0] + sh;
+    for (int i = 0; i < n - 1; ++i) {
+      double l = se[i] / dcur;
+      f[2 * i] = l;
+      f[2 * i + 1] = 1.0 / dcur;
+      dcur = sd[i + 1] + sh - l * se[i];
+    }
+    f[2 * (n - 1)] = 0.0;
+    f[2 * (n - 1) + 1] = 1.0 / dcur;
+  }
+}
+
+// F[:, k] = sum_j w_j (T_Q + s_j I)^-1 e_k  (F written T-typed into C_TMP;
+// per-column scratch in C_TMP2).  grid = (ceil(n/256), nblk)
+template <class T>
+__global__ void __launch_bounds__(256) k_invsqrt_cols(const BlockDesc* D, char* ws, const int* info) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = d.n;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double* pq = bufp<double>(ws, d, P_QUAD);
+  const double* fac = bufp<double>(ws, d, Q_FAC);
+  T* F = bufp<T>(ws, d, C_TMP);
+  double* y = reinterpret_cast<double*>(bufp<T>(ws, d, C_TMP2));   // use as n x n doubles
+  const int N = (int)pq[0];
+  for (int i = 0; i < n; ++i) F[(long long)i * n + k] = tzero<T>();
+  for (int j = 0; j < N; ++j) {
+    const double* f = fac + (long long)j * n * 2;
+    const double w = pq[3 + j];
+    // forward L y = e_k (zeros above k), then z = D^-1 y
+    double yi = 1.0;
+    y[(long long)k * n + k] = yi * f[2 * k + 1];
+    for (int i = k + 1; i < n; ++i) {
+      yi = -f[2 * (i - 1)] * yi;
+      y[(long long)i * n + k] = yi * f[2 * i + 1];
+    }
+    // backward L^T x = z
+    double x = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+      double z = i >= k ? y[(long long)i * n + k] : 0.0;
+      x = z - f[2 * i] * x;
+      long long idx = (long long)i * n + k;
+      F[idx] = treal<T>(re(F[idx]) + w * x);
+    }
+  }
+}
+
+// ----------------------------------------------------------------- launchers
+void launch_tri_eig4c(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxm, double* eps,
+                      double c) {
+  size_t shm = (size_t)(4 * maxm + 2) * sizeof(double);
+  hipLaunchKernelGGL(k_tri_eig4c, dim3(nblk), dim3(512), shm, s, D, ws, info, eps, c);
+}
+void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk) {
+  hipLaunchKernelGGL(k_filter_factor, dim3(RMAX, nblk), dim3(64), 0, s, D, ws, info);
+}
+template <class T>
+void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn) {
+  hipLaunchKernelGGL(k_filter_solve<T>, dim3((maxn + 255) / 256, nblk), dim3(256), 0, s, D, ws, info);
+}
+void launch_tri_eig_q(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn) {
+  size_t shm = (size_t)(3 * maxn) * sizeof(double);
+  hipLaunchKernelGGL(k_tri_eig_q, dim3(nblk), dim3(256), shm, s, D, ws, info);
+}
+template <class T>
+void launch_invsqrt_cols(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn) {
+  hipLaunchKernelGGL(k_invsqrt_cols<T>, dim3((maxn + 255) / 256, nblk), dim3(256), 0, s, D, ws, info);
+}
+template void launch_filter_solve<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int);
+template void launch_filter_solve<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int);
+template void launch_invsqrt_cols<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int);
+template void launch_invsqrt_cols<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int);
+
+}  // namespace x2c

@@ -1,0 +1,287 @@
+// C ABI of libx2c: argument checking, workspace layout (the batch plan) and
+// the stage sequence of the X2C build (see include/x2c.h).
+#include "../../include/x2c.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "x2c_device.h"
+#include "x2c_launch.h"
+
+using namespace x2c;
+
+namespace {
+
+constexpr int MAX_N_2C = 256;   // 4c dimension 4N <= 1024
+constexpr int MAX_N_SF = 512;   // 4c dimension 2N <= 1024
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+  size_t head = 0;                 // info + descriptors
+  size_t info_off = 0, desc_off = 0;
+  size_t total = 0;
+  std::vector<BlockDesc> desc;
+  int maxN = 0, maxn = 0, maxm = 0;
+};
+
+// byte sizes of the named buffers for one block
+void block_sizes(int N, bool tc, size_t sz[NBUF]) {
+  const size_t n = tc ? 2 * (size_t)N : (size_t)N;
+  const size_t m = 2 * n;
+  const size_t es = tc ? 16 : 8;
+  const size_t NN = (size_t)N * N * 8;
+  for (int i = 0; i < NBUF; ++i) sz[i] = 0;
+  for (int i = R_S; i <= R_WR3; ++i) sz[i] = NN;
+  for (int i = C_S; i <= C_TMP2; ++i) sz[i] = n * n * es;
+  sz[C_A] = m * m * es;
+  sz[C_Y] = m * n * es;
+  sz[Z_SCR] = m * n * 16;
+  sz[V_D] = m * 8;
+  sz[V_E] = m * 8;
+  sz[V_TAU] = m * es;
+  sz[V_DQ] = n * 8;
+  sz[V_EQ] = n * 8;
+  sz[V_TAUQ] = n * es;
+  sz[V_PIV] = n * 4;
+  sz[P_FILT] = PF_SIZE * 8;
+  sz[P_QUAD] = PQ_SIZE * 8;
+  sz[F_FAC] = (size_t)RMAX * m * 5 * 16;
+  sz[Q_FAC] = (size_t)QMAX * n * 2 * 8;
+}
+
+bool valid_opts(const x2c_options* o) {
+  if (!o) return false;
+  if (o->mode != X2C_SPINFREE && o->mode != X2C_TWOCOMP) return false;
+  if (o->prec != X2C_FP64 && o->prec != X2C_SPLIT_BF16) return false;
+  if (!(o->c > 0.0) || !std::isfinite(o->c)) return false;
+  if (o->ozaki_slices < 0 || o->ozaki_slices > 16) return false;
+  return true;
+}
+
+int max_n(int mode) { return mode == X2C_TWOCOMP ? MAX_N_2C : (mode == X2C_SPINFREE ? MAX_N_SF : 0); }
+
+bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in_off, const int64_t* h_off,
+                 const int64_t* eps_off, Layout& L) {
+  if (nblk <= 0 || !N) return false;
+  const bool tc = o->mode == X2C_TWOCOMP;
+  const int mx = max_n(o->mode);
+  L.info_off = 0;
+  L.desc_off = align_up((size_t)nblk * sizeof(int));
+  L.head = align_up(L.desc_off + (size_t)nblk * sizeof(BlockDesc));
+  L.desc.resize(nblk);
+  size_t off = L.head;
+  L.maxN = L.maxn = L.maxm = 0;
+  for (int b = 0; b < nblk; ++b) {
+    if (N[b] <= 0 || N[b] > mx) return false;
+    BlockDesc& d = L.desc[b];
+    std::memset(&d, 0, sizeof(d));
+    d.N = N[b];
+    d.n = tc ? 2 * N[b] : N[b];
+    d.m = 2 * d.n;
+    d.in_off = in_off ? in_off[b] : 0;
+    d.h_off = h_off ? h_off[b] : 0;
+    d.eps_off = eps_off ? eps_off[b] : 0;
+    size_t sz[NBUF];
+    block_sizes(N[b], tc, sz);
+    for (int i = 0; i < NBUF; ++i) {
+      d.off[i] = (long long)off;
+      off += align_up(sz[i] ? sz[i] : 8);
+    }
+    if (d.N > L.maxN) L.maxN = d.N;
+    if (d.n > L.maxn) L.maxn = d.n;
+    if (d.m > L.maxm) L.maxm = d.m;
+  }
+  L.total = off;
+  return true;
+}
+
+// Host copies of descriptor tables stay alive here for as long as an
+// asynchronous upload may read them.
+std::mutex g_mu;
+std::map<std::vector<int64_t>, std::shared_ptr<Layout>> g_plans;
+
+std::shared_ptr<Layout> get_plan(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
+                                 const int64_t* h_off, const int64_t* eps_off) {
+  std::vector<int64_t> key;
+  key.reserve(4 * (size_t)nblk + 2);
+  key.push_back(o->mode);
+  key.push_back(nblk);
+  for (int b = 0; b < nblk; ++b) {
+    key.push_back(N[b]);
+    key.push_back(in_off ? in_off[b] : 0);
+    key.push_back(h_off ? h_off[b] : 0);
+    key.push_back(eps_off ? eps_off[b] : 0);
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) return it->second;
+  auto L = std::make_shared<Layout>();
+  if (!make_layout(o, nblk, N, in_off, h_off, eps_off, *L)) return nullptr;
+  if (g_plans.size() > 64) g_plans.clear();
+  g_plans.emplace(std::move(key), L);
+  return L;
+}
+
+template <class T>
+T tcast(double v) {
+  return treal<T>(v);
+}
+
+// The stage sequence for one batch (all blocks advance stage by stage).
+template <class T>
+int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S, const double* Tm, const double* V,
+               const double* W, double* h, double* eps, int* info, char* ws, hipStream_t s) {
+  const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off);
+  const bool tc = o->mode == X2C_TWOCOMP;
+  const double c = o->c;
+  const int maxN = L.maxN, maxn = L.maxn, maxm = L.maxm;
+  const T one = tcast<T>(1.0), zero = tcast<T>(0.0);
+  const int OPN = 0, OPH = 1;
+
+  launch_init_info(s, info, nblk);
+  launch_unpack(s, D, ws, info, nblk, maxN, S, Tm, V, W, tc ? 1 : 0);
+  launch_potrf(s, D, ws, info, nblk);
+  launch_trtri(s, D, ws, info, nblk);
+  launch_expand<T>(s, D, ws, info, nblk, maxn, c);
+
+  // scalar-level reduction: L_S^-1 V L_S^-T, L_S^-1 L_T, L_T^-1 W^q L_T^-T
+  launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPN, R_V, OPN, R_TMP, 1.0, 0.0);
+  launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LSI, OPH, R_ALL, 1.0, 0.0);
+  launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPN, R_LT, OPN, R_B, 1.0, 0.0);
+  const int nq = tc ? 4 : 1;
+  for (int q = 0; q < nq; ++q) {
+    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LTI, OPN, R_W0 + q, OPN, R_TMP, 1.0, 0.0);
+    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LTI, OPH, R_WR0 + q, 1.0, 0.0);
+  }
+  launch_assemble_A<T>(s, D, ws, info, nblk, maxm, c);
+
+  // positive-energy branch of the reduced 4c matrix
+  launch_hetrd<T>(s, D, ws, info, nblk, maxm, DIM_m, C_A, V_D, V_E, V_TAU);
+  launch_tri_eig4c(s, D, ws, info, nblk, maxm, eps, c);
+  launch_filter_factor(s, D, ws, info, nblk);
+  launch_filter_solve<T>(s, D, ws, info, nblk, maxn);
+  launch_ormtr<T>(s, D, ws, info, nblk, maxm, maxn, DIM_m, C_A, V_TAU, C_Y, DIM_n);
+
+  // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
+  launch_getrf<T>(s, D, ws, info, nblk);
+  launch_transpose<T>(s, D, ws, info, nblk, maxn, C_Y, 1, C_TMP2);
+  launch_rsolve<T>(s, D, ws, info, nblk, maxn);
+  launch_transpose<T>(s, D, ws, info, nblk, maxn, C_TMP2, 0, C_TMP);
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, OPN, C_LS, OPH, C_TMP2, one, zero);
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LTI, OPH, C_TMP2, OPN, C_X, tcast<T>(std::sqrt(2.0) * c), zero);
+
+  // S~ = S + X^H T X / 2c^2 ;  L = V + TX + (TX)^H + X^H (W/4c^2 - T) X
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_T, OPN, C_X, OPN, C_TX, one, zero);
+  launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_S, C_Q);
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_X, OPH, C_TX, OPN, C_Q, tcast<T>(1.0 / (2.0 * c * c)), one);
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_WPP, OPN, C_X, OPN, C_WX, one, zero);
+  launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_V, C_L);
+  launch_add_herm<T>(s, D, ws, info, nblk, maxn, C_TX, C_L);
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_X, OPH, C_WX, OPN, C_L, one, one);
+
+  // R = L_S^-H (L_S^-1 S~ L_S^-H)^-1/2 L_S^H
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LSI, OPN, C_Q, OPN, C_TMP, one, zero);
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, OPN, C_LSI, OPH, C_Q, one, zero);
+  launch_hetrd<T>(s, D, ws, info, nblk, maxn, DIM_n, C_Q, V_DQ, V_EQ, V_TAUQ);
+  launch_tri_eig_q(s, D, ws, info, nblk, maxn);
+  launch_invsqrt_cols<T>(s, D, ws, info, nblk, maxn);
+  launch_ormtr<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, C_TMP, DIM_n);
+  launch_conj_transpose<T>(s, D, ws, info, nblk, maxn, C_TMP, C_QMH);
+  launch_ormtr<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, C_QMH, DIM_n);
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_QMH, OPN, C_LS, OPH, C_TMP, one, zero);
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LSI, OPH, C_TMP, OPN, C_R, one, zero);
+
+  // h = R^H (L R)
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_L, OPN, C_R, OPN, C_LR, one, zero);
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_R, OPH, C_LR, OPN, C_H, one, zero);
+  launch_write_h<T>(s, D, ws, info, nblk, maxn, h, eps);
+  return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
+}
+
+int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off, const double* S, const double* T,
+            const double* V, const double* W, const int64_t* h_off, void* h, const int64_t* eps_off, double* eps,
+            int* info, void* workspace, size_t ws_bytes, hipStream_t s, const Layout** out_layout) {
+  if (!valid_opts(o) || nblk <= 0 || !N || !S || !T || !V || !W || !h || !eps || !workspace) return X2C_EINVAL;
+  std::shared_ptr<Layout> L = get_plan(o, nblk, N, in_off, h_off, eps_off);
+  if (!L) return X2C_EINVAL;
+  if (ws_bytes < L->total) return X2C_EINVAL;
+  if (out_layout) *out_layout = L.get();
+  char* ws = static_cast<char*>(workspace);
+  (void)hipGetLastError();
+  if (hipMemcpyAsync(ws + L->desc_off, L->desc.data(), L->desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice,
+                     s) != hipSuccess)
+    return X2C_EHIP;
+  if (!info) info = reinterpret_cast<int*>(ws + L->info_off);
+  if (o->mode == X2C_TWOCOMP)
+    return run_stages<cplx>(o, *L, nblk, S, T, V, W, static_cast<double*>(h), eps, info, ws, s);
+  return run_stages<double>(o, *L, nblk, S, T, V, W, static_cast<double*>(h), eps, info, ws, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int x2c_max_n(int mode) { return max_n(mode); }
+
+size_t x2c_workspace_bytes(const x2c_options* opts, int nblk, const int* N) {
+  if (!valid_opts(opts)) return 0;
+  Layout L;
+  if (!make_layout(opts, nblk, N, nullptr, nullptr, nullptr, L)) return 0;
+  return L.total;
+}
+
+int x2c_build(const x2c_options* opts, int N, const double* S, const double* T, const double* V, const double* W,
+              void* h, double* eps, void* workspace, size_t ws_bytes, void* stream, int* info_out) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t zero = 0;
+  const Layout* L = nullptr;
+  int rc = enqueue(opts, 1, &N, &zero, S, T, V, W, &zero, h, &zero, eps, nullptr, workspace, ws_bytes, s, &L);
+  if (rc != X2C_OK) return rc;
+  int info = 0;
+  if (hipMemcpyAsync(&info, static_cast<char*>(workspace) + L->info_off, sizeof(int), hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return X2C_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return X2C_EHIP;
+  if (info_out) *info_out = info;
+  return info == 0 ? X2C_OK : X2C_EBLOCK;
+}
+
+int x2c_build_batched(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off, const double* S,
+                      const double* T, const double* V, const double* W, const int64_t* h_off, void* h,
+                      const int64_t* eps_off, double* eps, int* info, void* workspace, size_t ws_bytes,
+                      void* stream) {
+  if (!in_off || !h_off || !eps_off || !info) return X2C_EINVAL;
+  return enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, info, workspace, ws_bytes,
+                 static_cast<hipStream_t>(stream), nullptr);
+}
+
+const char* x2c_strerror(int code) {
+  switch (code) {
+    case X2C_OK: return "ok";
+    case X2C_EINVAL: return "invalid argument";
+    case X2C_EHIP: return "HIP runtime error";
+    case X2C_EBLOCK: return "block failed (see info)";
+    case X2C_INFO_S_NOT_SPD: return "overlap matrix S not positive definite";
+    case X2C_INFO_T_NOT_SPD: return "kinetic matrix T not positive definite";
+    case X2C_INFO_EIGEN: return "positive-energy subspace degenerate";
+    case X2C_INFO_BRANCH: return "positive-energy branch size differs from n";
+    case X2C_INFO_RENORM: return "renormalisation matrix not positive definite";
+    case X2C_INFO_NONFINITE: return "non-finite input";
+    default: return "unknown code";
+  }
+}
+
+void x2c_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_plans.clear();
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Device-side types and helpers shared by the X2C kernels (gfx950).
+//
+// Scalar type T is `double` (spin-free mode, real matrices) or `cplx`
+// (two-component mode, complex Hermitian matrices in the spin-orbital basis
+// [all alpha; all beta], Sec. II Eqs. defstv/defw).  All matrices are
+// row-major.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace x2c {
+
+struct cplx {
+  double x, y;
+};
+
+// ---------------------------------------------------------------- arithmetic
+__host__ __device__ inline cplx operator+(cplx a, cplx b) { return {a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline cplx operator-(cplx a, cplx b) { return {a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline cplx operator-(cplx a) { return {-a.x, -a.y}; }
+__host__ __device__ inline cplx operator*(cplx a, cplx b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__host__ __device__ inline cplx operator*(double s, cplx a) { return {s * a.x, s * a.y}; }
+__host__ __device__ inline cplx operator*(cplx a, double s) { return {s * a.x, s * a.y}; }
+
+__host__ __device__ inline double conjg(double a) { return a; }
+__host__ __device__ inline cplx conjg(cplx a) { return {a.x, -a.y}; }
+__host__ __device__ inline double re(double a) { return a; }
+__host__ __device__ inline double re(cplx a) { return a.x; }
+__host__ __device__ inline double im(double) { return 0.0; }
+__host__ __device__ inline double im(cplx a) { return a.y; }
+__host__ __device__ inline double abs2(double a) { return a * a; }
+__host__ __device__ inline double abs2(cplx a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline double abs1(double a) { return fabs(a); }
+__host__ __device__ inline double abs1(cplx a) { return fabs(a.x) + fabs(a.y); }
+
+// c + a*b
+__device__ inline double mad(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline cplx mad(cplx a, cplx b, cplx c) {
+  return {fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y))};
+}
+__device__ inline cplx mad(double a, cplx b, cplx c) { return {fma(a, b.x, c.x), fma(a, b.y, c.y)}; }
+__device__ inline cplx mad(cplx a, double b, cplx c) { return {fma(a.x, b, c.x), fma(a.y, b, c.y)}; }
+
+template <class T> __host__ __device__ inline T tzero();
+template <> __host__ __device__ inline double tzero<double>() { return 0.0; }
+template <> __host__ __device__ inline cplx tzero<cplx>() { return {0.0, 0.0}; }
+template <class T> __host__ __device__ inline T treal(double a);
+template <> __host__ __device__ inline double treal<double>(double a) { return a; }
+template <> __host__ __device__ inline cplx treal<cplx>(double a) { return {a, 0.0}; }
+template <class T> __host__ __device__ inline T tmake(double a, double b);
+template <> __host__ __device__ inline double tmake<double>(double a, double) { return a; }
+template <> __host__ __device__ inline cplx tmake<cplx>(double a, double b) { return {a, b}; }
+
+__device__ inline cplx cdiv(cplx a, cplx b) {
+  // Smith's algorithm
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, den = b.x + b.y * r;
+    return {(a.x + a.y * r) / den, (a.y - a.x * r) / den};
+  } else {
+    double r = b.x / b.y, den = b.x * r + b.y;
+    return {(a.x * r + a.y) / den, (a.y * r - a.x) / den};
+  }
+}
+__device__ inline cplx crecip(cplx b) { return cdiv(cplx{1.0, 0.0}, b); }
+
+// ---------------------------------------------------------------- workspace
+// Named per-block buffers.  Offsets (bytes from the workspace base) are laid
+// out by the host plan; every block owns its own region.
+enum Buf : int {
+  // real N x N
+  R_S = 0, R_T, R_V, R_W0, R_W1, R_W2, R_W3,   // input copies
+  R_LS, R_LT, R_LSI, R_LTI,                     // Cholesky factors and inverses
+  R_TMP, R_ALL, R_B, R_WR0, R_WR1, R_WR2, R_WR3, // reduced blocks
+  // T-typed n x n
+  C_S, C_T, C_V, C_WPP, C_LS, C_LSI, C_LTI,
+  C_X, C_TX, C_Q, C_WX, C_L, C_QMH, C_R, C_LR, C_H, C_TMP, C_TMP2,
+  // T-typed m x m and m x n
+  C_A, C_Y,
+  // complex m x n scratch for the filter solves
+  Z_SCR,
+  // vectors
+  V_D, V_E, V_TAU, V_DQ, V_EQ, V_TAUQ, V_PIV,
+  // filter / quadrature parameters and factors
+  P_FILT, P_QUAD, F_FAC, Q_FAC,
+  NBUF
+};
+
+constexpr int RMAX = 48;   // max Zolotarev pole pairs
+constexpr int QMAX = 64;   // max quadrature nodes for the inverse square root
+// P_FILT layout (doubles): [0]=sigma [1]=rho [2]=M [3]=r [4..4+RMAX)=a_j [4+RMAX..4+2RMAX)=beta_j
+constexpr int PF_SIZE = 4 + 2 * RMAX;
+// P_QUAD layout: [0]=nodes [1]=lambda_min [2]=lambda_max [3..3+QMAX)=weights [3+QMAX..)=shifts
+constexpr int PQ_SIZE = 3 + 2 * QMAX;
+
+struct BlockDesc {
+  int N;      // scalar basis functions of the block
+  int n;      // dimension of h: N (spin-free) or 2N (two-component)
+  int m;      // 4c dimension 2n
+  int pad;
+  long long in_off;   // element offset of S, T, V (W: in_off, or 4*in_off in 2c)
+  long long h_off;    // double offset into h
+  long long eps_off;  // double offset into eps
+  long long off[NBUF];
+};
+
+template <class P>
+__device__ inline P* bufp(char* ws, const BlockDesc& d, int id) {
+  return reinterpret_cast<P*>(ws + d.off[id]);
+}
+
+// dimension selector used by the generic kernels
+enum Dim : int { DIM_N = 0, DIM_n = 1, DIM_m = 2 };
+__device__ inline int seldim(const BlockDesc& d, int s) { return s == DIM_N ? d.N : (s == DIM_n ? d.n : d.m); }
+
+// counter-based hash -> uniform(-1, 1) (SplitMix64 finaliser), used to draw the
+// fixed test block of the spectral-projector filter
+__host__ __device__ inline double hash_uniform(uint64_t i, uint64_t j) {
+  uint64_t z = (i * 0x9E3779B97F4A7C15ull) ^ (j + 0x632BE59BD9B4E019ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// block-wide sum over blockDim.x threads (<= 1024), result broadcast
+__device__ inline double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  int nw = (blockDim.x + 63) >> 6;
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+}  // namespace x2c

@@ -1,0 +1,59 @@
+// Host-side launchers of the X2C kernels (internal to libx2c).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "x2c_device.h"
+
+namespace x2c {
+
+void launch_init_info(hipStream_t s, int* info, int nblk);
+void launch_unpack(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN, const double* S,
+                   const double* T, const double* V, const double* W, int twocomp);
+void launch_potrf(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk);
+void launch_trtri(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk);
+template <class T>
+void launch_expand(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, double c);
+template <class T>
+void launch_assemble_A(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxm, double c);
+template <class T>
+void launch_copy(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
+                 int src, int dst);
+template <class T>
+void launch_add_herm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, int src,
+                     int dst);
+template <class T>
+void launch_conj_transpose(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn,
+                           int src, int dst);
+template <class T>
+void launch_write_h(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, double* h,
+                    double* eps);
+
+template <class T>
+void launch_gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
+                 int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta);
+
+template <class T>
+void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
+                  int bufA, int bufD, int bufE, int bufTau);
+template <class T>
+void launch_ormtr(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int maxcols,
+                  int dsel, int bufA, int bufTau, int bufY, int csel);
+
+void launch_tri_eig4c(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxm, double* eps,
+                      double c);
+void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk);
+template <class T>
+void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn);
+void launch_tri_eig_q(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn);
+template <class T>
+void launch_invsqrt_cols(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn);
+
+template <class T>
+void launch_getrf(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk);
+template <class T>
+void launch_transpose(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, int src,
+                      int row0sel, int dst);
+template <class T>
+void launch_rsolve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn);
+
+}  // namespace x2c
