@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark: batched DLU X2C builds on one MI355X.
+
+Default workload: the Ag309-like batch -- 309 two-component Z=47 atomic
+blocks (s22 p18 d12 f8, N = 192 scalar functions, 384 spinors, 4c dimension
+768), V and W^q of each block scaled by a seeded factor U(0.98, 1.02).
+
+A step is one x2c_build_batched call over the whole batch with inputs already
+resident in HBM.  W untimed warm-up steps, then K steps timed with HIP events
+on the stream the library launches on.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "DLU X2C blocks/sec at fixed max|dE| vs FP64 oracle; split-prec vs plain FP64"
+
+# MI355X peaks (AMD published figures)
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_flops(stage: str, N: int, twocomp: bool) -> float | None:
+    """Algorithmic real flops per block of a stage (complex multiply-add = 8
+    flops; products with Hermitian output counted at half; diagonal scalings
+    not counted)."""
+    n = 2 * N if twocomp else N
+    m = 2 * n
+    cm = 4.0 if twocomp else 1.0          # complex vs real arithmetic
+    if stage == "tridiag_4c":             # Householder tridiagonalisation: (4/3) m^3 mult-add pairs
+        return cm * (4.0 / 3.0) * m ** 3
+    if stage == "tridiag_Q":
+        return cm * (4.0 / 3.0) * n ** 3
+    if stage == "backtransform_4c":       # Q (m x m, m-1 reflectors) applied to m x n
+        return cm * 2.0 * m * m * n
+    return None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["ag309", "mixed512"], default="ag309")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--prec", choices=["fp64", "split"], default="fp64")
+    ap.add_argument("--check-blocks", type=int, default=3, help="blocks checked against the oracle")
+    ap.add_argument("--cpu-blocks", type=int, default=12, help="blocks in the CPU oracle sample (0 = skip)")
+    ap.add_argument("--no-trace", action="store_true")
+    return ap.parse_args()
+
+
+def workload(name: str, seed: int):
+    from x2c_inputs.configs import ag309_dlu, mixed_dlu
+    if name == "ag309":
+        blocks = ag309_dlu(seed)
+        desc = (f"ag309_dlu: 309 two-component Z=47 blocks (s22 p18 d12 f8, N=192, 384 spinors, 4c dim 768), "
+                f"V,W scaled U(0.98,1.02), seed {seed}")
+        return blocks, True, desc
+    blocks = mixed_dlu(seed, 512)
+    desc = f"mixed_dlu: 512 two-component blocks, Z uniform in {{1,6,8,17,29,47,79}}, seed {seed}"
+    return blocks, True, desc
+
+
+def accuracy_gate(blocks, hs, eps, twocomp, c, nsample, seed):
+    """max|dE| (Eh) of the GPU h against the oracle's positive-energy 4c
+    spectrum on a seeded sample of blocks, next to the oracle's own floor."""
+    import oracle
+    import oracle.routes as ox
+    rng = np.random.default_rng(seed + 77)
+    idx = rng.choice(len(blocks), size=min(nsample, len(blocks)), replace=False)
+    dmax_b = dmax_a = floor_a = floor_b = 0.0
+    for i in idx:
+        b = blocks[int(i)]
+        W = b.W if twocomp else b.W[0]
+        e4 = oracle.dirac_positive_spectrum(b.S, b.T, b.V, W, c, twocomp)
+        es = oracle.spectrum_of(hs[int(i)], b.S, twocomp)
+        h0, _ = ox.x2c_direct(b.S, b.T, b.V, W, c, twocomp)
+        e0 = oracle.spectrum_of(h0, b.S, twocomp)
+        d = np.abs(es - e4)
+        f = np.abs(e0 - e4)
+        bd = e4 < 0
+        dmax_a = max(dmax_a, float(d.max()))
+        floor_a = max(floor_a, float(f.max()))
+        if bd.any():
+            dmax_b = max(dmax_b, float(d[bd].max()))
+            floor_b = max(floor_b, float(f[bd].max()))
+    return dict(max_dE_bound_Eh=dmax_b, max_dE_all_Eh=dmax_a, oracle_floor_bound_Eh=floor_b,
+                oracle_floor_all_Eh=floor_a, checked_blocks=[int(i) for i in idx])
+
+
+def cpu_baseline(blocks, twocomp, c, nblk_sample):
+    """The oracle as it stands, timed on this host on a bounded sample."""
+    import oracle.routes as ox
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    sample = blocks[:nblk_sample]
+    t0 = time.perf_counter()
+    for b in sample:
+        ox.x2c_direct(b.S, b.T, b.V, b.W if twocomp else b.W[0], c, twocomp)
+    dt = time.perf_counter() - t0
+    return {"value": len(sample) / dt, "unit": "blocks/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {len(sample)} blocks of the same batch, sequential, x2c_direct with "
+                      f"threaded LAPACK ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the per-block DLU build shards over blocks, see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+    import paper_1303_4446_amd as px
+    from x2c_inputs import C_LIGHT, pack_blocks
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    c = C_LIGHT
+    blocks, twocomp, desc = workload(args.workload, args.seed)
+    prec = px.FP64 if args.prec == "fp64" else px.SPLIT_BF16
+    pk = pack_blocks(blocks, twocomp)
+    batch = px.batch_to_device(pk, twocomp)
+    stream = torch.cuda.current_stream()
+    print(f"# workload: {desc}; prec {args.prec}", file=sys.stderr, flush=True)
+
+    (h, eps, info), ws = px.build_batched(batch, c, prec=prec, stream=stream)
+    out = (h, eps, info)
+    for _ in range(max(0, args.warmup - 1)):
+        px.build_batched(batch, c, prec=prec, workspace=ws, out=out, stream=stream)
+    torch.cuda.synchronize()
+    print("# warm-up done", file=sys.stderr, flush=True)
+
+    if not args.no_trace:
+        px.trace_reset()
+        px.trace_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        px.build_batched(batch, c, prec=prec, workspace=ws, out=out, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    elapsed_ms = ev0.elapsed_time(ev1)
+    stages = {}
+    if not args.no_trace:
+        px.trace_enable(False)
+        stages = px.trace_read()
+    print(f"# timed {args.steps} steps: {elapsed_ms:.1f} ms", file=sys.stderr, flush=True)
+
+    info_h = info.cpu().numpy()
+    if np.any(info_h != 0):
+        raise SystemExit(f"blocks failed: {np.nonzero(info_h)[0][:10]} codes {info_h[info_h != 0][:10]}")
+    hs = px.unpack_h(h.cpu().numpy(), batch.Ns, twocomp)
+
+    nblk = len(blocks)
+    ms_step = elapsed_ms / args.steps
+    value = nblk * args.steps / (elapsed_ms / 1e3)
+
+    acc = accuracy_gate(blocks, hs, eps, twocomp, c, args.check_blocks, args.seed)
+    print(f"# accuracy {acc}", file=sys.stderr, flush=True)
+
+    stage_ms = {k: v[0] / max(1, v[1]) for k, v in stages.items()}
+    roofline = None
+    if stage_ms:
+        dom = max(stage_ms, key=stage_ms.get)
+        N = int(batch.Ns.max())
+        fl = algorithmic_flops(dom, N, twocomp)
+        if fl is not None:
+            achieved = fl * nblk / (stage_ms[dom] / 1e3) / 1e12
+            roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                        "launch_ms": stage_ms[dom], "work_per_launch_flop": fl * nblk}
+        else:
+            roofline = {"bound": None, "kernel": dom, "launch_ms": stage_ms[dom]}
+
+    cpu = cpu_baseline(blocks, twocomp, c, args.cpu_blocks) if args.cpu_blocks > 0 else None
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "blocks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "nblocks": nblk, "mode": "two-component" if twocomp else "spin-free",
+                   "prec": args.prec, **acc},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stages_ms_per_step": {k: round(v, 4) for k, v in sorted(stage_ms.items(), key=lambda kv: -kv[1])},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

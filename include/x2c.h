@@ -125,8 +125,22 @@ int x2c_build_batched(const x2c_options* opts, int nblk, const int* N, const int
 /* Static description of a return or info code. */
 const char* x2c_strerror(int code);
 
-/* Drop cached launch plans (host memory only). */
+/* Drop cached launch plans and trace events (host-side resources only). */
 void x2c_release(void);
+
+/*
+ * Tracing.  x2c_trace_enable(1) makes every later call bracket each of its
+ * stages with a pair of HIP events recorded on the call's stream (no device
+ * memory is allocated); x2c_trace_enable returns the previous setting.
+ * x2c_trace_read waits for the recorded events, folds them into per-stage
+ * totals and returns the number of stages seen; for 0 <= idx < that number
+ * it stores the stage name (static until x2c_trace_reset), the summed
+ * device time in ms and the number of calls.  x2c_trace_reset clears the
+ * totals.
+ */
+int x2c_trace_enable(int on);
+int x2c_trace_read(int idx, const char** name, double* total_ms, long long* count);
+void x2c_trace_reset(void);
 
 #ifdef __cplusplus
 }

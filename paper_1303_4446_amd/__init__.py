@@ -2,4 +2,4 @@
 blocks: a thin binding over the HIP library libx2c.so (include/x2c.h)."""
 from ._lib import (EBLOCK, EHIP, EINVAL, EXPORTED, FP64, OK, SPLIT_BF16, SPINFREE, TWOCOMP,  # noqa: F401
                    Batch, X2CError, batch_to_device, build, build_batched, load, max_n, strerror,
-                   unpack_h, workspace_bytes)
+                   trace_enable, trace_read, trace_reset, unpack_h, workspace_bytes)

@@ -23,7 +23,7 @@ INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subsp
               4: "positive-energy branch size != n", 5: "renormalisation matrix not PD", 6: "non-finite input"}
 
 EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_strerror",
-            "x2c_release")
+            "x2c_release", "x2c_trace_enable", "x2c_trace_read", "x2c_trace_reset")
 
 
 class X2CError(RuntimeError):
@@ -48,7 +48,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         return _LIB
     p = path or LIB_PATH
     if not os.path.exists(p):
-        raise FileNotFoundError(f"{p} not built; run `python -m paper_1303_4446_amd.build`")
+        raise FileNotFoundError(f"{p} not built; run `python -m paper_1303_4446_amd.builder`")
     lib = ctypes.CDLL(p)
     vp, i32, i64p = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)
     optp = ctypes.POINTER(_Options)
@@ -66,6 +66,13 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.x2c_strerror.restype = ctypes.c_char_p
     lib.x2c_release.argtypes = []
     lib.x2c_release.restype = None
+    lib.x2c_trace_enable.argtypes = [i32]
+    lib.x2c_trace_enable.restype = i32
+    lib.x2c_trace_read.argtypes = [i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_longlong)]
+    lib.x2c_trace_read.restype = i32
+    lib.x2c_trace_reset.argtypes = []
+    lib.x2c_trace_reset.restype = None
     if path is None:
         _LIB = lib
     return lib
@@ -90,6 +97,28 @@ def workspace_bytes(Ns, twocomp: bool, c: float = 137.0, prec: int = FP64) -> in
     if n == 0:
         raise X2CError(EINVAL, "invalid block sizes or options")
     return int(n)
+
+
+def trace_enable(on: bool) -> bool:
+    return bool(load().x2c_trace_enable(1 if on else 0))
+
+
+def trace_reset() -> None:
+    load().x2c_trace_reset()
+
+
+def trace_read() -> dict:
+    """{stage: (total_ms, calls)} for the calls made while tracing was on."""
+    lib = load()
+    name = ctypes.c_char_p()
+    ms = ctypes.c_double()
+    cnt = ctypes.c_longlong()
+    n = lib.x2c_trace_read(-1, None, None, None)
+    out = {}
+    for i in range(n):
+        lib.x2c_trace_read(i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(cnt))
+        out[name.value.decode()] = (ms.value, cnt.value)
+    return out
 
 
 def _torch():

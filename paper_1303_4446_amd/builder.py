@@ -1,6 +1,6 @@
 """Build libx2c.so (gfx950) in-tree with hipcc.
 
-Usage:  python -m paper_1303_4446_amd.build   (or call build())
+Usage:  python -m paper_1303_4446_amd.builder   (or call build())
 """
 from __future__ import annotations
 

@@ -94,7 +94,11 @@ __global__ void __launch_bounds__(256) k_potrf(const BlockDesc* D, char* ws, int
     __syncthreads();
   }
   if (fail) {
-    if (threadIdx.x == 0) info[b] = which == 0 ? 1 : 2;
+    // S failing takes precedence over T failing, whichever work-group ends first
+    if (threadIdx.x == 0) {
+      if (which == 0) atomicExch(&info[b], 1);
+      else atomicCAS(&info[b], 0, 2);
+    }
     return;
   }
   // zero the strict upper triangle

@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "x2c_device.h"
@@ -130,6 +131,73 @@ std::shared_ptr<Layout> get_plan(const x2c_options* o, int nblk, const int* N, c
   return L;
 }
 
+// ---------------------------------------------------------------- tracing
+// When enabled, each stage of a call is bracketed by a pair of HIP events
+// recorded on the call's stream; x2c_trace_read folds finished pairs into
+// per-stage totals.
+struct TraceRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_trace = false;
+std::vector<TraceRec> g_pending;
+std::vector<hipEvent_t> g_pool;
+std::vector<std::pair<std::string, std::pair<double, long long>>> g_totals;
+
+hipEvent_t ev_get() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct Stage {
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Stage(const char* nm, hipStream_t st) : name(nm), s(st) {
+    if (!g_trace) return;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    a = ev_get();
+    if (a) hipEventRecord(a, s);
+  }
+  ~Stage() {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    hipEvent_t b = ev_get();
+    if (!b) return;
+    hipEventRecord(b, s);
+    g_pending.push_back({name, a, b});
+  }
+};
+
+void trace_collect() {
+  for (auto& r : g_pending) {
+    float ms = 0.f;
+    hipEventSynchronize(r.b);
+    hipEventElapsedTime(&ms, r.a, r.b);
+    bool found = false;
+    for (auto& t : g_totals)
+      if (t.first == r.name) {
+        t.second.first += ms;
+        t.second.second += 1;
+        found = true;
+        break;
+      }
+    if (!found) g_totals.push_back({r.name, {(double)ms, 1}});
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_pending.clear();
+}
+
+#define STAGE(nm) Stage stage_guard_(nm, s)
+
 template <class T>
 T tcast(double v) {
   return treal<T>(v);
@@ -146,63 +214,102 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   const T one = tcast<T>(1.0), zero = tcast<T>(0.0);
   const int OPN = 0, OPH = 1;
 
-  launch_init_info(s, info, nblk);
-  launch_unpack(s, D, ws, info, nblk, maxN, S, Tm, V, W, tc ? 1 : 0);
-  launch_potrf(s, D, ws, info, nblk);
-  launch_trtri(s, D, ws, info, nblk);
-  launch_expand<T>(s, D, ws, info, nblk, maxn, c);
-
-  // scalar-level reduction: L_S^-1 V L_S^-T, L_S^-1 L_T, L_T^-1 W^q L_T^-T
-  launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPN, R_V, OPN, R_TMP, 1.0, 0.0);
-  launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LSI, OPH, R_ALL, 1.0, 0.0);
-  launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPN, R_LT, OPN, R_B, 1.0, 0.0);
-  const int nq = tc ? 4 : 1;
-  for (int q = 0; q < nq; ++q) {
-    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LTI, OPN, R_W0 + q, OPN, R_TMP, 1.0, 0.0);
-    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LTI, OPH, R_WR0 + q, 1.0, 0.0);
+  {
+    STAGE("prep");
+    launch_init_info(s, info, nblk);
+    launch_unpack(s, D, ws, info, nblk, maxN, S, Tm, V, W, tc ? 1 : 0);
+    launch_potrf(s, D, ws, info, nblk);
+    launch_trtri(s, D, ws, info, nblk);
+    launch_expand<T>(s, D, ws, info, nblk, maxn, c);
   }
-  launch_assemble_A<T>(s, D, ws, info, nblk, maxm, c);
-
+  {
+    // scalar-level reduction: L_S^-1 V L_S^-T, L_S^-1 L_T, L_T^-1 W^q L_T^-T
+    STAGE("reduce");
+    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPN, R_V, OPN, R_TMP, 1.0, 0.0);
+    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LSI, OPH, R_ALL, 1.0, 0.0);
+    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPN, R_LT, OPN, R_B, 1.0, 0.0);
+    const int nq = tc ? 4 : 1;
+    for (int q = 0; q < nq; ++q) {
+      launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LTI, OPN, R_W0 + q, OPN, R_TMP, 1.0, 0.0);
+      launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LTI, OPH, R_WR0 + q, 1.0, 0.0);
+    }
+    launch_assemble_A<T>(s, D, ws, info, nblk, maxm, c);
+  }
   // positive-energy branch of the reduced 4c matrix
-  launch_hetrd<T>(s, D, ws, info, nblk, maxm, DIM_m, C_A, V_D, V_E, V_TAU);
-  launch_tri_eig4c(s, D, ws, info, nblk, maxm, eps, c);
-  launch_filter_factor(s, D, ws, info, nblk);
-  launch_filter_solve<T>(s, D, ws, info, nblk, maxn);
-  launch_ormtr<T>(s, D, ws, info, nblk, maxm, maxn, DIM_m, C_A, V_TAU, C_Y, DIM_n);
-
-  // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
-  launch_getrf<T>(s, D, ws, info, nblk);
-  launch_transpose<T>(s, D, ws, info, nblk, maxn, C_Y, 1, C_TMP2);
-  launch_rsolve<T>(s, D, ws, info, nblk, maxn);
-  launch_transpose<T>(s, D, ws, info, nblk, maxn, C_TMP2, 0, C_TMP);
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, OPN, C_LS, OPH, C_TMP2, one, zero);
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LTI, OPH, C_TMP2, OPN, C_X, tcast<T>(std::sqrt(2.0) * c), zero);
-
-  // S~ = S + X^H T X / 2c^2 ;  L = V + TX + (TX)^H + X^H (W/4c^2 - T) X
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_T, OPN, C_X, OPN, C_TX, one, zero);
-  launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_S, C_Q);
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_X, OPH, C_TX, OPN, C_Q, tcast<T>(1.0 / (2.0 * c * c)), one);
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_WPP, OPN, C_X, OPN, C_WX, one, zero);
-  launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_V, C_L);
-  launch_add_herm<T>(s, D, ws, info, nblk, maxn, C_TX, C_L);
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_X, OPH, C_WX, OPN, C_L, one, one);
-
-  // R = L_S^-H (L_S^-1 S~ L_S^-H)^-1/2 L_S^H
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LSI, OPN, C_Q, OPN, C_TMP, one, zero);
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, OPN, C_LSI, OPH, C_Q, one, zero);
-  launch_hetrd<T>(s, D, ws, info, nblk, maxn, DIM_n, C_Q, V_DQ, V_EQ, V_TAUQ);
-  launch_tri_eig_q(s, D, ws, info, nblk, maxn);
-  launch_invsqrt_cols<T>(s, D, ws, info, nblk, maxn);
-  launch_ormtr<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, C_TMP, DIM_n);
-  launch_conj_transpose<T>(s, D, ws, info, nblk, maxn, C_TMP, C_QMH);
-  launch_ormtr<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, C_QMH, DIM_n);
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_QMH, OPN, C_LS, OPH, C_TMP, one, zero);
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LSI, OPH, C_TMP, OPN, C_R, one, zero);
-
-  // h = R^H (L R)
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_L, OPN, C_R, OPN, C_LR, one, zero);
-  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_R, OPH, C_LR, OPN, C_H, one, zero);
-  launch_write_h<T>(s, D, ws, info, nblk, maxn, h, eps);
+  {
+    STAGE("tridiag_4c");
+    launch_hetrd<T>(s, D, ws, info, nblk, maxm, DIM_m, C_A, V_D, V_E, V_TAU);
+  }
+  {
+    STAGE("branch_4c");
+    launch_tri_eig4c(s, D, ws, info, nblk, maxm, eps, c);
+  }
+  {
+    STAGE("projector_4c");
+    launch_filter_factor(s, D, ws, info, nblk);
+    launch_filter_solve<T>(s, D, ws, info, nblk, maxn);
+  }
+  {
+    STAGE("backtransform_4c");
+    launch_ormtr<T>(s, D, ws, info, nblk, maxm, maxn, DIM_m, C_A, V_TAU, C_Y, DIM_n);
+  }
+  {
+    // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
+    STAGE("x_solve");
+    launch_getrf<T>(s, D, ws, info, nblk);
+    launch_transpose<T>(s, D, ws, info, nblk, maxn, C_Y, 1, C_TMP2);
+    launch_rsolve<T>(s, D, ws, info, nblk, maxn);
+    launch_transpose<T>(s, D, ws, info, nblk, maxn, C_TMP2, 0, C_TMP);
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, OPN, C_LS, OPH, C_TMP2, one, zero);
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LTI, OPH, C_TMP2, OPN, C_X,
+                   tcast<T>(std::sqrt(2.0) * c), zero);
+  }
+  {
+    // S~ = S + X^H T X / 2c^2 ;  L = V + TX + (TX)^H + X^H (W/4c^2 - T) X
+    STAGE("chain_SL");
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_T, OPN, C_X, OPN, C_TX, one, zero);
+    launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_S, C_Q);
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_X, OPH, C_TX, OPN, C_Q, tcast<T>(1.0 / (2.0 * c * c)), one);
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_WPP, OPN, C_X, OPN, C_WX, one, zero);
+    launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_V, C_L);
+    launch_add_herm<T>(s, D, ws, info, nblk, maxn, C_TX, C_L);
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_X, OPH, C_WX, OPN, C_L, one, one);
+  }
+  {
+    // Q = L_S^-1 S~ L_S^-H
+    STAGE("chain_Q");
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LSI, OPN, C_Q, OPN, C_TMP, one, zero);
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, OPN, C_LSI, OPH, C_Q, one, zero);
+  }
+  {
+    STAGE("tridiag_Q");
+    launch_hetrd<T>(s, D, ws, info, nblk, maxn, DIM_n, C_Q, V_DQ, V_EQ, V_TAUQ);
+  }
+  {
+    // Q^-1/2 = Q_h F Q_h^H, F = T_Q^-1/2 by quadrature
+    STAGE("invsqrt_Q");
+    launch_tri_eig_q(s, D, ws, info, nblk, maxn);
+    launch_invsqrt_cols<T>(s, D, ws, info, nblk, maxn);
+    launch_ormtr<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, C_TMP, DIM_n);
+    launch_conj_transpose<T>(s, D, ws, info, nblk, maxn, C_TMP, C_QMH);
+    launch_ormtr<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, C_QMH, DIM_n);
+  }
+  {
+    // R = L_S^-H Q^-1/2 L_S^H
+    STAGE("chain_R");
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_QMH, OPN, C_LS, OPH, C_TMP, one, zero);
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LSI, OPH, C_TMP, OPN, C_R, one, zero);
+  }
+  {
+    // h = R^H (L R)
+    STAGE("chain_h");
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_L, OPN, C_R, OPN, C_LR, one, zero);
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_R, OPH, C_LR, OPN, C_H, one, zero);
+  }
+  {
+    STAGE("write");
+    launch_write_h<T>(s, D, ws, info, nblk, maxn, h, eps);
+  }
   return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
 }
 
@@ -258,6 +365,7 @@ int x2c_build_batched(const x2c_options* opts, int nblk, const int* N, const int
                       const double* T, const double* V, const double* W, const int64_t* h_off, void* h,
                       const int64_t* eps_off, double* eps, int* info, void* workspace, size_t ws_bytes,
                       void* stream) {
+  if (nblk == 0 && valid_opts(opts)) return X2C_OK;   // empty batch: nothing to do
   if (!in_off || !h_off || !eps_off || !info) return X2C_EINVAL;
   return enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, info, workspace, ws_bytes,
                  static_cast<hipStream_t>(stream), nullptr);
@@ -280,8 +388,39 @@ const char* x2c_strerror(int code) {
 }
 
 void x2c_release(void) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  g_plans.clear();
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_plans.clear();
+  }
+  std::lock_guard<std::mutex> lk(g_tmu);
+  trace_collect();
+  for (hipEvent_t e : g_pool) hipEventDestroy(e);
+  g_pool.clear();
+}
+
+int x2c_trace_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  int prev = g_trace ? 1 : 0;
+  g_trace = on != 0;
+  return prev;
+}
+
+int x2c_trace_read(int idx, const char** name, double* total_ms, long long* count) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  trace_collect();
+  const int n = (int)g_totals.size();
+  if (idx >= 0 && idx < n) {
+    if (name) *name = g_totals[idx].first.c_str();
+    if (total_ms) *total_ms = g_totals[idx].second.first;
+    if (count) *count = g_totals[idx].second.second;
+  }
+  return n;
+}
+
+void x2c_trace_reset(void) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  trace_collect();
+  g_totals.clear();
 }
 
 }  // extern "C"
