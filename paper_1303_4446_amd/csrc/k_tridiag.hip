@@ -16,6 +16,8 @@
 #include "x2c_device.h"
 #include "x2c_launch.h"
 
+#include <algorithm>
+
 namespace x2c {
 
 // Reflector for column k (rows k+1..n-1) into vout[0..len).  Returns through
@@ -232,6 +234,485 @@ __global__ void __launch_bounds__(256) k_ormtr(const BlockDesc* D, char* ws, con
   }
 }
 
+// element (r, a) of panel V whose first reflector is k0 (dimension nr)
+template <class T>
+__device__ inline T panel_v(const T* A, int nr, int k0, int r, int a) {
+  int row1 = k0 + a + 1;            // row of the implicit unit entry
+  if (r < row1) return tzero<T>();
+  if (r == row1) return treal<T>(1.0);
+  return A[(long long)r * nr + k0 + a];
+}
+
+// ---------------------------------------------------------------- blocked
+// Blocked reduction over the whole batch (panels of HB columns, lower
+// triangle only).  Inside a panel the trailing matrix is left as it was at
+// the panel start; with the panel's reflectors V and companion vectors W the
+// current trailing matrix is A - V W^H - W V^H.  Per column k:
+//   k_tri_col    (one work-group per block): reduce the previous column's
+//                matvec, subtract the panel corrections, form w (stored as
+//                column of W), update column k with the panel corrections and
+//                build reflector k (v_k -> global vector buffer);
+//   k_tri_matvec (one work-group per 64 x 64 lower super-tile): each wave
+//                stages a 32 x 32 tile in LDS and writes its row sums and
+//                (off the diagonal) its transposed column sums with v_k;
+// after the panel k_tri_her2k updates the trailing lower triangle.  The tile
+// sums are added in a fixed order, so results are bitwise reproducible.
+constexpr int HB = 32;        // panel width
+constexpr int HT = 32;        // matvec tile
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// phase: 0 = first column of a panel (no previous column to finish)
+//        1 = finish column k-1 (w), then build column k if it is in the panel
+//        2 = finish column k-1 only (last column of the panel)
+template <class T>
+__global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
+                                                 int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS, int k0,
+                                                 int i, int phase) {
+  const int b = blockIdx.x;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = seldim(d, dsel);
+  if (k0 >= n - 1) return;
+  const int kb = min(HB, n - 1 - k0);
+  T* A = bufp<T>(ws, d, bufA);
+  double* dd = bufp<double>(ws, d, bufD);
+  double* ee = bufp<double>(ws, d, bufE);
+  T* taus = bufp<T>(ws, d, bufTau);
+  T* Wp = bufp<T>(ws, d, bufW);
+  T* vg = bufp<T>(ws, d, bufV);
+  const T* HS = bufp<T>(ws, d, bufHS);
+  const int tid = threadIdx.x;
+  extern __shared__ char smem[];
+  T* v = reinterpret_cast<T*>(smem);
+  T* y = v + n;
+  __shared__ double red[32];
+  __shared__ T sh_tau;
+  __shared__ double sh_beta;
+  __shared__ T sh_alpha;
+  __shared__ T wk[HB], vk[HB], t1[HB], t2[HB];
+  __shared__ T part[8][HB][2];
+
+  if (phase != 0) {
+    const int ip = i - 1;              // column being finished
+    if (ip >= kb) return;
+    const int kp = k0 + ip;
+    const int off = kp + 1, len = n - kp - 1;
+    const T tau = taus[kp];
+    for (int r = tid; r < len; r += 256) v[r] = vg[r];
+    // fixed-order reduction of the super-tile partials of row r:
+    // row partials of super-tiles (r/64, SJ <= r/64), column partials of super-tiles (SI > r/64, r/64)
+    const int nst = (len + 63) / 64;
+    for (int r = tid; r < len; r += 256) {
+      const int Sr = r / 64;
+      T acc = tzero<T>();
+      for (int SJ = 0; SJ <= Sr; ++SJ) acc = acc + HS[(long long)SJ * len + r];
+      for (int SI = Sr + 1; SI < nst; ++SI) acc = acc + HS[(long long)(nst + SI) * len + r];
+      y[r] = acc;
+    }
+    __syncthreads();
+    if (ip > 0) {
+      const int j = tid & (HB - 1), g = tid >> 5;
+      T s1 = tzero<T>(), s2 = tzero<T>();
+      if (j < ip) {
+        for (int r = off + g; r < n; r += 8) {
+          const T vr = v[r - off];
+          s1 = mad(conjg(Wp[(long long)r * HB + j]), vr, s1);
+          s2 = mad(conjg(panel_v(A, n, k0, r, j)), vr, s2);
+        }
+      }
+      part[g][j][0] = s1;
+      part[g][j][1] = s2;
+      __syncthreads();
+      if (tid < HB) {
+        T a1 = tzero<T>(), a2 = tzero<T>();
+        for (int gg = 0; gg < 8; ++gg) {
+          a1 = a1 + part[gg][tid][0];
+          a2 = a2 + part[gg][tid][1];
+        }
+        t1[tid] = a1;
+        t2[tid] = a2;
+      }
+      __syncthreads();
+      for (int r = off + tid; r < n; r += 256) {
+        T acc = y[r - off];
+        for (int jj = 0; jj < ip; ++jj) {
+          acc = acc - panel_v(A, n, k0, r, jj) * t1[jj];
+          acc = acc - Wp[(long long)r * HB + jj] * t2[jj];
+        }
+        y[r - off] = acc;
+      }
+      __syncthreads();
+    }
+    double dr = 0.0, di = 0.0;
+    for (int r = tid; r < len; r += 256) {
+      T yt = tau * y[r];
+      y[r] = yt;
+      T pv = conjg(yt) * v[r];
+      dr += re(pv);
+      di += im(pv);
+    }
+    dr = block_sum(dr, red);
+    if (sizeof(T) != sizeof(double)) di = block_sum(di, red);
+    if (tid == 0) sh_alpha = (-0.5 * tau) * tmake<T>(dr, di);
+    __syncthreads();
+    const T alpha = sh_alpha;
+    for (int r = tid; r < len; r += 256) Wp[(long long)(off + r) * HB + ip] = mad(alpha, v[r], y[r]);
+    __syncthreads();
+    if (phase == 2 || i >= kb) return;
+  }
+  // build column k = k0 + i: corrections from the panel's columns 0..i-1, then the reflector
+  const int k = k0 + i;
+  if (tid < i) {
+    wk[tid] = conjg(Wp[(long long)k * HB + tid]);
+    vk[tid] = conjg(panel_v(A, n, k0, k, tid));
+  }
+  __syncthreads();
+  for (int r = k + tid; r < n; r += 256) {
+    T a = A[(long long)r * n + k];
+    for (int j = 0; j < i; ++j) {
+      a = a - panel_v(A, n, k0, r, j) * wk[j];
+      a = a - Wp[(long long)r * HB + j] * vk[j];
+    }
+    if (r == k) a = treal<T>(re(a));
+    A[(long long)r * n + k] = a;
+  }
+  __syncthreads();
+  make_reflector<T>(A, n, k, v, &sh_tau, &sh_beta, red);
+  const int len = n - k - 1;
+  for (int r = tid; r < len; r += 256) vg[r] = v[r];
+  if (tid == 0) {
+    dd[k] = re(A[(long long)k * n + k]);
+    ee[k] = sh_beta;
+    taus[k] = sh_tau;
+  }
+}
+
+// Lower-triangle matvec y = A[k+1:, k+1:] v_k.  One work-group per lower
+// 64 x 64 super-tile (SI, SJ); wave w stages sub-tile (w>>1, w&1) in LDS
+// (for a diagonal super-tile the upper sub-tile is the conjugate transpose
+// of its mirror, so the block acts as a full Hermitian block).  The four
+// waves' sums are combined in a fixed order; the super-tile writes its row
+// partial HS[SJ*len + r] and, off the diagonal, its column partial
+// HS[(nst + SI)*len + c].
+template <class T>
+__global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
+                                                    int bufV, int bufHS, int k) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = seldim(d, dsel);
+  const int off = k + 1, len = n - k - 1;
+  if (len <= 0) return;
+  const int nst = (len + 63) / 64;
+  const int st = blockIdx.x;
+  if (st >= nst * (nst + 1) / 2) return;
+  int SI = (int)((sqrt(8.0 * st + 1.0) - 1.0) * 0.5);
+  while ((SI + 1) * (SI + 2) / 2 <= st) ++SI;
+  while (SI * (SI + 1) / 2 > st) --SI;
+  const int SJ = st - SI * (SI + 1) / 2;
+  const bool diag = SI == SJ;
+  const T* A = bufp<T>(ws, d, bufA);
+  const T* vg = bufp<T>(ws, d, bufV);
+  T* HS = bufp<T>(ws, d, bufHS);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wi = wave >> 1, wj = wave & 1;
+  __shared__ T tiles[4][HT][HT + 1];
+  __shared__ T comb[4][HT];
+  __shared__ T vsh[4][2][HT];
+  T (*tl)[HT + 1] = tiles[wave];
+  const int rowbase = 64 * SI + 32 * wi, colbase = 64 * SJ + 32 * wj;
+  const bool upper = diag && wi < wj;
+  const bool dsub = diag && wi == wj;
+  // issue every load of the sub-tile first (16 per lane), then stage in LDS
+  const int lr0 = upper ? colbase : rowbase, lc0 = upper ? rowbase : colbase;
+  T regs[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int ii = (lane >> 5) + 2 * q, jj = lane & 31;
+    const int r = lr0 + ii, c = lc0 + jj;
+    regs[q] = (r < len && c < len && (!dsub || ii >= jj)) ? A[(long long)(off + r) * n + off + c] : tzero<T>();
+  }
+  if (lane < HT) {
+    const int c = colbase + lane;
+    vsh[wave][0][lane] = c < len ? vg[c] : tzero<T>();
+  } else {
+    const int r = rowbase + lane - HT;
+    vsh[wave][1][lane - HT] = r < len ? vg[r] : tzero<T>();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tl[(lane >> 5) + 2 * q][lane & 31] = regs[q];
+  wave_sync();
+  if (upper) {
+    for (int e = lane; e < HT * HT; e += 64) {
+      int ii = e / HT, jj = e % HT;
+      if (ii < jj) {
+        T x = tl[ii][jj];
+        tl[ii][jj] = conjg(tl[jj][ii]);
+        tl[jj][ii] = conjg(x);
+      } else if (ii == jj) {
+        tl[ii][ii] = conjg(tl[ii][ii]);
+      }
+    }
+    wave_sync();
+  } else if (dsub) {
+    for (int e = lane; e < HT * HT; e += 64) {
+      int ii = e / HT, jj = e % HT;
+      if (ii < jj) tl[ii][jj] = conjg(tl[jj][ii]);
+      else if (ii == jj) tl[ii][jj] = treal<T>(re(tl[ii][jj]));
+    }
+    wave_sync();
+  }
+  T sum = tzero<T>();
+  if (lane < HT) {
+#pragma unroll 8
+    for (int jj = 0; jj < HT; ++jj) sum = mad(tl[lane][jj], vsh[wave][0][jj], sum);
+  } else if (!diag) {
+    const int jj = lane - HT;
+#pragma unroll 8
+    for (int ii = 0; ii < HT; ++ii) sum = mad(conjg(tl[ii][jj]), vsh[wave][1][ii], sum);
+  }
+  // row partial of rows rowbase..: waves (wi,0) + (wi,1); column partial: waves (0,wj) + (1,wj)
+  if (lane < HT && wj == 1) comb[wi][lane] = sum;
+  if (lane >= HT && wi == 1) comb[2 + wj][lane - HT] = sum;
+  __syncthreads();
+  if (lane < HT && wj == 0) {
+    int r = rowbase + lane;
+    if (r < len) HS[(long long)SJ * len + r] = sum + comb[wi][lane];
+  }
+  if (!diag && lane >= HT && wi == 0) {
+    int c = colbase + lane - HT;
+    if (c < len) HS[(long long)(nst + SI) * len + c] = sum + comb[2 + wj][lane - HT];
+  }
+}
+
+// Trailing lower triangle (rows/cols >= k0 + kb): A -= V W^H + W V^H.
+// grid = (lower 32 x 32 tiles, nblk).
+template <class T>
+__global__ void __launch_bounds__(256) k_tri_her2k(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
+                                                   int bufW, int k0) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = seldim(d, dsel);
+  if (k0 >= n - 1) return;
+  const int kb = min(HB, n - 1 - k0);
+  const int c0 = k0 + kb;
+  const int len = n - c0;
+  if (len <= 0) return;
+  const int nt = (len + 31) / 32;
+  const int t = blockIdx.x;
+  if (t >= nt * (nt + 1) / 2) return;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  T* A = bufp<T>(ws, d, bufA);
+  const T* Wp = bufp<T>(ws, d, bufW);
+  __shared__ T Vr[32][HB + 1], Wr[32][HB + 1], Vc[32][HB + 1], Wc[32][HB + 1];
+  for (int e = threadIdx.x; e < 32 * HB; e += 256) {
+    int rr = e / HB, j = e % HB;
+    int r = c0 + 32 * I + rr, c = c0 + 32 * J + rr;
+    bool okr = r < n && j < kb, okc = c < n && j < kb;
+    Vr[rr][j] = okr ? panel_v(A, n, k0, r, j) : tzero<T>();
+    Wr[rr][j] = okr ? Wp[(long long)r * HB + j] : tzero<T>();
+    Vc[rr][j] = okc ? conjg(panel_v(A, n, k0, c, j)) : tzero<T>();
+    Wc[rr][j] = okc ? conjg(Wp[(long long)c * HB + j]) : tzero<T>();
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+    int rr = e >> 5, cc = e & 31;
+    int r = c0 + 32 * I + rr, c = c0 + 32 * J + cc;
+    if (r < n && c < n && c <= r) {
+      T s = tzero<T>();
+#pragma unroll 8
+      for (int j = 0; j < HB; ++j) {
+        s = mad(Vr[rr][j], Wc[cc][j], s);
+        s = mad(Wr[rr][j], Vc[cc][j], s);
+      }
+      long long idx = (long long)r * n + c;
+      A[idx] = A[idx] - s;
+    }
+  }
+}
+
+// last diagonal entry once every panel is applied
+template <class T>
+__global__ void k_tri_last(const BlockDesc* D, char* ws, const int* info, int nblk, int dsel, int bufA, int bufD) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk || info[b]) return;
+  const BlockDesc& d = D[b];
+  const int n = seldim(d, dsel);
+  const T* A = bufp<T>(ws, d, bufA);
+  bufp<double>(ws, d, bufD)[n - 1] = re(A[(long long)(n - 1) * n + (n - 1)]);
+}
+
+// ---------------------------------------------------------------- blocked Q
+// Panels of ORB reflectors H_k0 ... H_{k0+ORB-1} = I - V Tf V^H (forward,
+// columnwise compact WY form).  k_larft builds the ORB x ORB upper
+// triangular factor Tf of every panel:  Tf_ii = tau_i,
+// Tf[0:i, i] = -tau_i Tf[0:i, 0:i] (V[:, 0:i]^H v_i).
+constexpr int ORB = 32;
+
+template <class T>
+__global__ void __launch_bounds__(256) k_larft(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
+                                               int bufTau, int bufTf) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int nr = seldim(d, dsel);
+  const int k0 = blockIdx.x * ORB;
+  if (k0 >= nr - 1) return;
+  const int kb = min(ORB, nr - 1 - k0);
+  const T* A = bufp<T>(ws, d, bufA);
+  const T* taus = bufp<T>(ws, d, bufTau);
+  T* Tf = bufp<T>(ws, d, bufTf) + (long long)blockIdx.x * ORB * ORB;
+  __shared__ T Vs[64][ORB + 1];
+  __shared__ T G[ORB][ORB + 1];
+  __shared__ T Ts[ORB][ORB + 1];
+  // Gram matrix of the panel (upper part): thread t owns pairs p = t + 256 q
+  T acc[4];
+  for (int q = 0; q < 4; ++q) acc[q] = tzero<T>();
+  for (int r0 = k0 + 1; r0 < nr; r0 += 64) {
+    for (int l = threadIdx.x; l < 64 * ORB; l += 256) {
+      int rr = l / ORB, a = l % ORB;
+      int r = r0 + rr;
+      Vs[rr][a] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<T>();
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      int p = threadIdx.x + 256 * q;
+      int a = p / ORB, c = p % ORB;
+      if (a < c) {
+        T s = acc[q];
+        for (int rr = 0; rr < 64; ++rr) s = mad(conjg(Vs[rr][a]), Vs[rr][c], s);
+        acc[q] = s;
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < 4; ++q) {
+    int p = threadIdx.x + 256 * q;
+    G[p / ORB][p % ORB] = acc[q];
+  }
+  for (int l = threadIdx.x; l < ORB * ORB; l += 256) Ts[l / ORB][l % ORB] = tzero<T>();
+  __syncthreads();
+  if (threadIdx.x == 0) Ts[0][0] = taus[k0];
+  __syncthreads();
+  for (int i = 1; i < kb; ++i) {
+    const T ti = taus[k0 + i];
+    T z = tzero<T>();
+    const int a = threadIdx.x;
+    if (a < i) {
+      for (int j = a; j < i; ++j) z = mad(Ts[a][j], G[j][i], z);
+    }
+    __syncthreads();
+    if (a < i) Ts[a][i] = -(ti * z);
+    if (a == i) Ts[i][i] = ti;
+    __syncthreads();
+  }
+  for (int l = threadIdx.x; l < ORB * ORB; l += 256) Tf[l] = Ts[l / ORB][l % ORB];
+}
+
+// Y <- Q Y = P_0 (P_1 (... P_last Y)), P_j = I - V_j Tf_j V_j^H.  Work-group:
+// 64 columns of Y, all panels, 256 threads as (column c, group g of 4).
+template <class T>
+__global__ void __launch_bounds__(256) k_ormtr_blocked(const BlockDesc* D, char* ws, const int* info, int dsel,
+                                                       int bufA, int bufTf, int bufY, int csel) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int nr = seldim(d, dsel);
+  const int nc = seldim(d, csel);
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= nc || nr < 2) return;
+  const T* A = bufp<T>(ws, d, bufA);
+  const T* Tfb = bufp<T>(ws, d, bufTf);
+  T* Y = bufp<T>(ws, d, bufY);
+  __shared__ T Vs[32][ORB + 1];
+  __shared__ T Xs[ORB * 64];        // Y chunk (32 x 64) or W (ORB x 64)
+  __shared__ T Ts[ORB][ORB + 1];
+  const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int c = c0 + cl;
+  const bool cok = c < nc;
+  const int np = (nr - 1 + ORB - 1) / ORB;
+  for (int j = np - 1; j >= 0; --j) {
+    const int k0 = j * ORB;
+    const int kb = min(ORB, nr - 1 - k0);
+    const int r0 = k0 + 1;
+    for (int l = threadIdx.x; l < ORB * ORB; l += 256) Ts[l / ORB][l % ORB] = Tfb[(long long)j * ORB * ORB + l];
+    // W = V^H Y  (thread holds W[a][c] for a = g + 4 i)
+    T w[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = tzero<T>();
+    for (int rc0 = r0; rc0 < nr; rc0 += 32) {
+      __syncthreads();
+      for (int l = threadIdx.x; l < 32 * ORB; l += 256) {
+        int rr = l / ORB, a = l % ORB;
+        int r = rc0 + rr;
+        Vs[rr][a] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<T>();
+      }
+      for (int l = threadIdx.x; l < 32 * 64; l += 256) {
+        int rr = l >> 6, cc = l & 63;
+        int r = rc0 + rr;
+        Xs[l] = (r < nr && c0 + cc < nc) ? Y[(long long)r * nc + c0 + cc] : tzero<T>();
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int rr = 0; rr < 32; ++rr) {
+        T y = Xs[rr * 64 + cl];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] = mad(conjg(Vs[rr][g + 4 * i]), y, w[i]);
+      }
+    }
+    __syncthreads();
+    // W <- Tf W
+#pragma unroll
+    for (int i = 0; i < 8; ++i) Xs[(g + 4 * i) * 64 + cl] = w[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      int a = g + 4 * i;
+      T s = tzero<T>();
+      for (int bb = a; bb < ORB; ++bb) s = mad(Ts[a][bb], Xs[bb * 64 + cl], s);
+      w[i] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) Xs[(g + 4 * i) * 64 + cl] = w[i];
+    __syncthreads();
+    T wc[ORB];
+#pragma unroll
+    for (int a = 0; a < ORB; ++a) wc[a] = Xs[a * 64 + cl];
+    // Y -= V W
+    for (int rc0 = r0; rc0 < nr; rc0 += 32) {
+      __syncthreads();
+      for (int l = threadIdx.x; l < 32 * ORB; l += 256) {
+        int rr = l / ORB, a = l % ORB;
+        int r = rc0 + rr;
+        Vs[rr][a] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<T>();
+      }
+      __syncthreads();
+      if (cok) {
+        for (int rr = g; rr < 32; rr += 4) {
+          int r = rc0 + rr;
+          if (r >= nr) break;
+          T s = tzero<T>();
+#pragma unroll
+          for (int a = 0; a < ORB; ++a) s = mad(Vs[rr][a], wc[a], s);
+          long long idx = (long long)r * nc + c;
+          Y[idx] = Y[idx] - s;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <class T>
 void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                   int bufA, int bufD, int bufE, int bufTau) {
@@ -247,6 +728,56 @@ void launch_ormtr(hipStream_t s, const BlockDesc* D, char* ws, const int* info, 
                      bufTau, bufY, csel);
 }
 
+// Blocked multi-kernel reduction over the batch; falls back to the
+// one-work-group reduction when every block is small.
+template <class T>
+void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
+                     int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS) {
+  if (maxdim <= 96) {
+    launch_hetrd<T>(s, D, ws, info, nblk, maxdim, dsel, bufA, bufD, bufE, bufTau);
+    return;
+  }
+  const size_t shm = 2 * (size_t)maxdim * sizeof(T);
+  for (int k0 = 0; k0 < maxdim - 1; k0 += HB) {
+    const int kbmax = std::min(HB, maxdim - 1 - k0);
+    hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufW,
+                       bufV, bufHS, k0, 0, 0);
+    for (int i = 0; i < kbmax; ++i) {
+      const int k = k0 + i;
+      const int len = maxdim - k - 1;
+      const int nst = (len + 63) / 64;
+      hipLaunchKernelGGL(k_tri_matvec<T>, dim3(nst * (nst + 1) / 2, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
+                         bufV, bufHS, k);
+      hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau,
+                         bufW, bufV, bufHS, k0, i + 1, (i + 1 < kbmax) ? 1 : 2);
+    }
+    const int len2 = maxdim - (k0 + kbmax);
+    if (len2 > 0) {
+      const int nt2 = (len2 + 31) / 32;
+      hipLaunchKernelGGL(k_tri_her2k<T>, dim3(nt2 * (nt2 + 1) / 2, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
+                         bufW, k0);
+    }
+  }
+  hipLaunchKernelGGL(k_tri_last<T>, dim3((nblk + 255) / 256), dim3(256), 0, s, D, ws, info, nblk, dsel, bufA, bufD);
+}
+template void launch_hetrd_mk<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
+                                      int, int, int, int);
+template void launch_hetrd_mk<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
+                                    int, int, int, int);
+
+template <class T>
+void launch_ormtr_blocked(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim,
+                          int maxcols, int dsel, int bufA, int bufTau, int bufTf, int bufY, int csel) {
+  int np = (maxdim - 1 + ORB - 1) / ORB;
+  if (np < 1) np = 1;
+  hipLaunchKernelGGL(k_larft<T>, dim3(np, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA, bufTau, bufTf);
+  hipLaunchKernelGGL(k_ormtr_blocked<T>, dim3((maxcols + 63) / 64, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
+                     bufTf, bufY, csel);
+}
+template void launch_ormtr_blocked<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int,
+                                           int, int, int, int);
+template void launch_ormtr_blocked<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int,
+                                         int, int, int, int);
 template void launch_hetrd<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
                                    int);
 template void launch_hetrd<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int, int);

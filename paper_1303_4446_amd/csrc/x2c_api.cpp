@@ -56,6 +56,12 @@ void block_sizes(int N, bool tc, size_t sz[NBUF]) {
   sz[P_QUAD] = PQ_SIZE * 8;
   sz[F_FAC] = (size_t)RMAX * m * 5 * 16;
   sz[Q_FAC] = (size_t)QMAX * n * 2 * 8;
+  sz[W_TF4] = ((m - 1 + 31) / 32 + 1) * 32 * 32 * es;
+  sz[W_TFQ] = ((n - 1 + 31) / 32 + 1) * 32 * 32 * es;
+  sz[W_PAN] = m * 32 * es;
+  const size_t nst = (m + 63) / 64;
+  sz[W_HS] = 2 * nst * m * es;
+  sz[W_VCUR] = m * es;
 }
 
 bool valid_opts(const x2c_options* o) {
@@ -238,7 +244,7 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   // positive-energy branch of the reduced 4c matrix
   {
     STAGE("tridiag_4c");
-    launch_hetrd<T>(s, D, ws, info, nblk, maxm, DIM_m, C_A, V_D, V_E, V_TAU);
+    launch_hetrd_mk<T>(s, D, ws, info, nblk, maxm, DIM_m, C_A, V_D, V_E, V_TAU, W_PAN, W_VCUR, W_HS);
   }
   {
     STAGE("branch_4c");
@@ -251,7 +257,7 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   }
   {
     STAGE("backtransform_4c");
-    launch_ormtr<T>(s, D, ws, info, nblk, maxm, maxn, DIM_m, C_A, V_TAU, C_Y, DIM_n);
+    launch_ormtr_blocked<T>(s, D, ws, info, nblk, maxm, maxn, DIM_m, C_A, V_TAU, W_TF4, C_Y, DIM_n);
   }
   {
     // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
@@ -283,16 +289,16 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   }
   {
     STAGE("tridiag_Q");
-    launch_hetrd<T>(s, D, ws, info, nblk, maxn, DIM_n, C_Q, V_DQ, V_EQ, V_TAUQ);
+    launch_hetrd_mk<T>(s, D, ws, info, nblk, maxn, DIM_n, C_Q, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS);
   }
   {
     // Q^-1/2 = Q_h F Q_h^H, F = T_Q^-1/2 by quadrature
     STAGE("invsqrt_Q");
     launch_tri_eig_q(s, D, ws, info, nblk, maxn);
     launch_invsqrt_cols<T>(s, D, ws, info, nblk, maxn);
-    launch_ormtr<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, C_TMP, DIM_n);
+    launch_ormtr_blocked<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, W_TFQ, C_TMP, DIM_n);
     launch_conj_transpose<T>(s, D, ws, info, nblk, maxn, C_TMP, C_QMH);
-    launch_ormtr<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, C_QMH, DIM_n);
+    launch_ormtr_blocked<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, W_TFQ, C_QMH, DIM_n);
   }
   {
     // R = L_S^-H Q^-1/2 L_S^H

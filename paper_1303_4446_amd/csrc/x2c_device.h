@@ -85,6 +85,14 @@ enum Buf : int {
   V_D, V_E, V_TAU, V_DQ, V_EQ, V_TAUQ, V_PIV,
   // filter / quadrature parameters and factors
   P_FILT, P_QUAD, F_FAC, Q_FAC,
+  // compact-WY factors of the reflector panels (4c and Q)
+  W_TF4, W_TFQ,
+  // panel companion vectors of the blocked tridiagonalisation (m x 32)
+  W_PAN,
+  // per-tile matvec sums of the blocked tridiagonalisation
+  W_HS,
+  // current reflector of the blocked tridiagonalisation (m)
+  W_VCUR,
   NBUF
 };
 

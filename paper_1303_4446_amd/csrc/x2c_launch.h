@@ -39,6 +39,13 @@ template <class T>
 void launch_ormtr(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int maxcols,
                   int dsel, int bufA, int bufTau, int bufY, int csel);
 
+template <class T>
+void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
+                     int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS);
+template <class T>
+void launch_ormtr_blocked(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim,
+                          int maxcols, int dsel, int bufA, int bufTau, int bufTf, int bufY, int csel);
+
 void launch_tri_eig4c(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxm, double* eps,
                       double c);
 void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk);
