@@ -262,10 +262,7 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   {
     // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
     STAGE("x_solve");
-    launch_getrf<T>(s, D, ws, info, nblk);
-    launch_transpose<T>(s, D, ws, info, nblk, maxn, C_Y, 1, C_TMP2);
-    launch_rsolve<T>(s, D, ws, info, nblk, maxn);
-    launch_transpose<T>(s, D, ws, info, nblk, maxn, C_TMP2, 0, C_TMP);
+    launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn);
     launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, OPN, C_LS, OPH, C_TMP2, one, zero);
     launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LTI, OPH, C_TMP2, OPN, C_X,
                    tcast<T>(std::sqrt(2.0) * c), zero);

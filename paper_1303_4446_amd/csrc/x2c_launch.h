@@ -61,6 +61,8 @@ template <class T>
 void launch_transpose(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, int src,
                       int row0sel, int dst);
 template <class T>
+void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn);
+template <class T>
 void launch_rsolve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn);
 
 }  // namespace x2c

@@ -393,3 +393,16 @@ def test_planted_mistakes_are_caught(name, monkeypatch):
     monkeypatch.setattr(ox, func, repl)
     twocomp = func == "assemble_w"
     assert not _pins_pass(twocomp), f"mutant {name} survived the pins"
+
+
+def test_golden_dirac_reference_table():
+    """The stored Dirac-Coulomb table (written from the closed form) agrees
+    with the formula and with the hand value for Z = 10 1s."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "dirac_reference.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) >= 5
+    for Z, n, k, E in rows:
+        assert abs(dirac_energy(float(Z), int(n), int(k), C) - float(E)) < 1e-9
+    z10 = [float(r[3]) for r in rows if r[:3] == ["10", "1", "-1"]][0]
+    assert abs(z10 - (-50.066742016894)) < 1e-9
