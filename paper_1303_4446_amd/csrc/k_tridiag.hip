@@ -188,52 +188,6 @@ __global__ void __launch_bounds__(1024) k_hetrd(const BlockDesc* D, char* ws, co
   }
 }
 
-// Y <- Q Y with Q = H_0 H_1 ... H_{n-2} (reflectors stored in bufA/bufTau of
-// dimension nr = seldim(dsel)); Y is nr x ncols row-major (ncols =
-// seldim(csel)).  grid = (column chunks of 256, nblk).
-template <class T>
-__global__ void __launch_bounds__(256) k_ormtr(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
-                                               int bufTau, int bufY, int csel) {
-  const int b = blockIdx.y;
-  const BlockDesc& d = D[b];
-  if (info[b]) return;
-  const int nr = seldim(d, dsel);
-  const int nc = seldim(d, csel);
-  const int c0 = blockIdx.x * 256;
-  if (c0 >= nc) return;
-  const T* A = bufp<T>(ws, d, bufA);
-  const T* taus = bufp<T>(ws, d, bufTau);
-  T* Y = bufp<T>(ws, d, bufY);
-  extern __shared__ char smem[];
-  T* v = reinterpret_cast<T*>(smem);
-  const int c = c0 + threadIdx.x;
-  const bool act = c < nc;
-  for (int k = nr - 2; k >= 0; --k) {
-    const int len = nr - k - 1;
-    for (int i = threadIdx.x; i < len; i += blockDim.x)
-      v[i] = (i == 0) ? treal<T>(1.0) : A[(long long)(k + 1 + i) * nr + k];
-    __syncthreads();
-    const T tau = taus[k];
-    if (act && (re(tau) != 0.0 || im(tau) != 0.0)) {
-      T dot = tzero<T>();
-      T* Yc = Y + (long long)(k + 1) * nc + c;
-      int i = 0;
-      for (; i + 3 < len; i += 4) {
-        T y0 = Yc[(long long)i * nc], y1 = Yc[(long long)(i + 1) * nc];
-        T y2 = Yc[(long long)(i + 2) * nc], y3 = Yc[(long long)(i + 3) * nc];
-        dot = mad(conjg(v[i]), y0, dot);
-        dot = mad(conjg(v[i + 1]), y1, dot);
-        dot = mad(conjg(v[i + 2]), y2, dot);
-        dot = mad(conjg(v[i + 3]), y3, dot);
-      }
-      for (; i < len; ++i) dot = mad(conjg(v[i]), Yc[(long long)i * nc], dot);
-      const T f = -(tau * dot);
-      for (i = 0; i < len; ++i) Yc[(long long)i * nc] = mad(v[i], f, Yc[(long long)i * nc]);
-    }
-    __syncthreads();
-  }
-}
-
 // element (r, a) of panel V whose first reflector is k0 (dimension nr)
 template <class T>
 __device__ inline T panel_v(const T* A, int nr, int k0, int r, int a) {
@@ -290,63 +244,58 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
   extern __shared__ char smem[];
   T* v = reinterpret_cast<T*>(smem);
   T* y = v + n;
+  T* colacc = y + n;
   __shared__ double red[32];
   __shared__ T sh_tau;
   __shared__ double sh_beta;
   __shared__ T sh_alpha;
   __shared__ T wk[HB], vk[HB], t1[HB], t2[HB];
-  __shared__ T part[8][HB][2];
 
+  const int k = k0 + i;                 // column to build (if any)
+  const bool build = phase != 2 && i < kb;
   if (phase != 0) {
     const int ip = i - 1;              // column being finished
     if (ip >= kb) return;
     const int kp = k0 + ip;
     const int off = kp + 1, len = n - kp - 1;
     const T tau = taus[kp];
-    for (int r = tid; r < len; r += 256) v[r] = vg[r];
-    // fixed-order reduction of the super-tile partials of row r:
-    // row partials of super-tiles (r/64, SJ <= r/64), column partials of super-tiles (SI > r/64, r/64)
     const int nst = (len + 63) / 64;
+    for (int r = tid; r < len; r += 256) v[r] = vg[r];
+    if (build && tid < ip) {
+      wk[tid] = conjg(Wp[(long long)k * HB + tid]);
+      vk[tid] = conjg(panel_v(A, n, k0, k, tid));
+    }
+    // panel dot products t1 = W^H v, t2 = V^H v from the matvec's per-strip partials
+    if (tid < ip) {
+      T a1 = tzero<T>(), a2 = tzero<T>();
+      const T* TP = HS + (long long)2 * nst * len;
+      for (int S = 0; S < nst; ++S) {
+        a1 = a1 + TP[((long long)S * HB + tid) * 2];
+        a2 = a2 + TP[((long long)S * HB + tid) * 2 + 1];
+      }
+      t1[tid] = a1;
+      t2[tid] = a2;
+    }
+    __syncthreads();
+    // y_r = fixed-order sum of the super-tile partials minus the panel
+    // corrections; the same pass accumulates the panel part of the update of
+    // the next column
     for (int r = tid; r < len; r += 256) {
       const int Sr = r / 64;
       T acc = tzero<T>();
       for (int SJ = 0; SJ <= Sr; ++SJ) acc = acc + HS[(long long)SJ * len + r];
       for (int SI = Sr + 1; SI < nst; ++SI) acc = acc + HS[(long long)(nst + SI) * len + r];
+      T ca = tzero<T>();
+      const int rr = off + r;
+#pragma unroll 4
+      for (int j = 0; j < ip; ++j) {
+        const T Vrj = panel_v(A, n, k0, rr, j);
+        const T Wrj = Wp[(long long)rr * HB + j];
+        acc = acc - Vrj * t1[j] - Wrj * t2[j];
+        ca = ca + Vrj * wk[j] + Wrj * vk[j];
+      }
       y[r] = acc;
-    }
-    __syncthreads();
-    if (ip > 0) {
-      const int j = tid & (HB - 1), g = tid >> 5;
-      T s1 = tzero<T>(), s2 = tzero<T>();
-      if (j < ip) {
-        for (int r = off + g; r < n; r += 8) {
-          const T vr = v[r - off];
-          s1 = mad(conjg(Wp[(long long)r * HB + j]), vr, s1);
-          s2 = mad(conjg(panel_v(A, n, k0, r, j)), vr, s2);
-        }
-      }
-      part[g][j][0] = s1;
-      part[g][j][1] = s2;
-      __syncthreads();
-      if (tid < HB) {
-        T a1 = tzero<T>(), a2 = tzero<T>();
-        for (int gg = 0; gg < 8; ++gg) {
-          a1 = a1 + part[gg][tid][0];
-          a2 = a2 + part[gg][tid][1];
-        }
-        t1[tid] = a1;
-        t2[tid] = a2;
-      }
-      __syncthreads();
-      for (int r = off + tid; r < n; r += 256) {
-        T acc = y[r - off];
-        for (int jj = 0; jj < ip; ++jj) {
-          acc = acc - panel_v(A, n, k0, r, jj) * t1[jj];
-          acc = acc - Wp[(long long)r * HB + jj] * t2[jj];
-        }
-        y[r - off] = acc;
-      }
-      __syncthreads();
+      colacc[r] = ca;
     }
     double dr = 0.0, di = 0.0;
     for (int r = tid; r < len; r += 256) {
@@ -361,27 +310,28 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
     if (tid == 0) sh_alpha = (-0.5 * tau) * tmake<T>(dr, di);
     __syncthreads();
     const T alpha = sh_alpha;
-    for (int r = tid; r < len; r += 256) Wp[(long long)(off + r) * HB + ip] = mad(alpha, v[r], y[r]);
-    __syncthreads();
-    if (phase == 2 || i >= kb) return;
-  }
-  // build column k = k0 + i: corrections from the panel's columns 0..i-1, then the reflector
-  const int k = k0 + i;
-  if (tid < i) {
-    wk[tid] = conjg(Wp[(long long)k * HB + tid]);
-    vk[tid] = conjg(panel_v(A, n, k0, k, tid));
-  }
-  __syncthreads();
-  for (int r = k + tid; r < n; r += 256) {
-    T a = A[(long long)r * n + k];
-    for (int j = 0; j < i; ++j) {
-      a = a - panel_v(A, n, k0, r, j) * wk[j];
-      a = a - Wp[(long long)r * HB + j] * vk[j];
+    for (int r = tid; r < len; r += 256) {
+      T w = mad(alpha, v[r], y[r]);
+      y[r] = w;
+      Wp[(long long)(off + r) * HB + ip] = w;
     }
-    if (r == k) a = treal<T>(re(a));
-    A[(long long)r * n + k] = a;
+    __syncthreads();
+    if (!build) return;
+    // column k = off: A[r][k] -= (panel columns < ip) + v_r conj(w_0) + w_r conj(v_0), v_0 = 1
+    const T w0c = conjg(y[0]);
+    for (int r = tid; r < len; r += 256) {
+      long long idx = (long long)(off + r) * n + k;
+      T a = A[idx] - colacc[r] - v[r] * w0c - y[r];
+      if (r == 0) a = treal<T>(re(a));
+      A[idx] = a;
+    }
+    __syncthreads();
+  } else {
+    if (!build) return;
+    // first column of a panel is current after the previous trailing update
+    if (tid == 0) A[(long long)k * n + k] = treal<T>(re(A[(long long)k * n + k]));
+    __syncthreads();
   }
-  __syncthreads();
   make_reflector<T>(A, n, k, v, &sh_tau, &sh_beta, red);
   const int len = n - k - 1;
   for (int r = tid; r < len; r += 256) vg[r] = v[r];
@@ -401,7 +351,7 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
 // HS[(nst + SI)*len + c].
 template <class T>
 __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
-                                                    int bufV, int bufHS, int k) {
+                                                    int bufV, int bufHS, int bufW, int k0, int k) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
@@ -488,7 +438,41 @@ __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws
     int c = colbase + lane - HT;
     if (c < len) HS[(long long)(nst + SI) * len + c] = sum + comb[2 + wj][lane - HT];
   }
+  if (diag) {
+    // this strip's part of the panel dot products (j < k - k0):
+    // TP[SI][j] = (sum_r conj(W(off+r, j)) v_r, sum_r conj(V(off+r, j)) v_r)
+    const int ip = k - k0;
+    const T* Wp = bufp<T>(ws, d, bufW);
+    __shared__ T tpart[8][HB][2];
+    const int j = threadIdx.x & (HB - 1), g = threadIdx.x >> 5;
+    T s1 = tzero<T>(), s2 = tzero<T>();
+    if (j < ip) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int r = 64 * SI + 8 * g + q;
+        if (r < len) {
+          const T vr = vg[r];
+          s1 = mad(conjg(Wp[(long long)(off + r) * HB + j]), vr, s1);
+          s2 = mad(conjg(panel_v(A, n, k0, off + r, j)), vr, s2);
+        }
+      }
+    }
+    tpart[g][j][0] = s1;
+    tpart[g][j][1] = s2;
+    __syncthreads();
+    if (threadIdx.x < HB) {
+      T a1 = tzero<T>(), a2 = tzero<T>();
+      for (int gg = 0; gg < 8; ++gg) {
+        a1 = a1 + tpart[gg][threadIdx.x][0];
+        a2 = a2 + tpart[gg][threadIdx.x][1];
+      }
+      T* TP = HS + (long long)2 * nst * len;
+      TP[((long long)SI * HB + threadIdx.x) * 2] = a1;
+      TP[((long long)SI * HB + threadIdx.x) * 2 + 1] = a2;
+    }
+  }
 }
+
 
 // Trailing lower triangle (rows/cols >= k0 + kb): A -= V W^H + W V^H.
 // grid = (lower 32 x 32 tiles, nblk).
@@ -720,13 +704,6 @@ void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, 
   hipLaunchKernelGGL(k_hetrd<T>, dim3(nblk), dim3(1024), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau);
 }
 
-template <class T>
-void launch_ormtr(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int maxcols,
-                  int dsel, int bufA, int bufTau, int bufY, int csel) {
-  size_t shm = (size_t)maxdim * sizeof(T);
-  hipLaunchKernelGGL(k_ormtr<T>, dim3((maxcols + 255) / 256, nblk), dim3(256), shm, s, D, ws, info, dsel, bufA,
-                     bufTau, bufY, csel);
-}
 
 // Blocked multi-kernel reduction over the batch; falls back to the
 // one-work-group reduction when every block is small.
@@ -737,7 +714,7 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
     launch_hetrd<T>(s, D, ws, info, nblk, maxdim, dsel, bufA, bufD, bufE, bufTau);
     return;
   }
-  const size_t shm = 2 * (size_t)maxdim * sizeof(T);
+  const size_t shm = 3 * (size_t)maxdim * sizeof(T);
   for (int k0 = 0; k0 < maxdim - 1; k0 += HB) {
     const int kbmax = std::min(HB, maxdim - 1 - k0);
     hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufW,
@@ -747,7 +724,7 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
       const int len = maxdim - k - 1;
       const int nst = (len + 63) / 64;
       hipLaunchKernelGGL(k_tri_matvec<T>, dim3(nst * (nst + 1) / 2, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
-                         bufV, bufHS, k);
+                         bufV, bufHS, bufW, k0, k);
       hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau,
                          bufW, bufV, bufHS, k0, i + 1, (i + 1 < kbmax) ? 1 : 2);
     }
@@ -781,9 +758,5 @@ template void launch_ormtr_blocked<cplx>(hipStream_t, const BlockDesc*, char*, c
 template void launch_hetrd<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
                                    int);
 template void launch_hetrd<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int, int);
-template void launch_ormtr<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                   int, int);
-template void launch_ormtr<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int, int,
-                                 int);
 
 }  // namespace x2c

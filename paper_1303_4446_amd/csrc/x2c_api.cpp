@@ -60,7 +60,7 @@ void block_sizes(int N, bool tc, size_t sz[NBUF]) {
   sz[W_TFQ] = ((n - 1 + 31) / 32 + 1) * 32 * 32 * es;
   sz[W_PAN] = m * 32 * es;
   const size_t nst = (m + 63) / 64;
-  sz[W_HS] = 2 * nst * m * es;
+  sz[W_HS] = (2 * nst * m + nst * 32 * 2) * es;
   sz[W_VCUR] = m * es;
 }
 

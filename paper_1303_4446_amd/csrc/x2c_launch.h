@@ -35,9 +35,6 @@ void launch_gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, i
 template <class T>
 void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                   int bufA, int bufD, int bufE, int bufTau);
-template <class T>
-void launch_ormtr(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int maxcols,
-                  int dsel, int bufA, int bufTau, int bufY, int csel);
 
 template <class T>
 void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
@@ -56,13 +53,6 @@ template <class T>
 void launch_invsqrt_cols(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn);
 
 template <class T>
-void launch_getrf(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk);
-template <class T>
-void launch_transpose(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, int src,
-                      int row0sel, int dst);
-template <class T>
 void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn);
-template <class T>
-void launch_rsolve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn);
 
 }  // namespace x2c
