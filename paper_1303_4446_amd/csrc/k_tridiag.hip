@@ -342,137 +342,178 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
   }
 }
 
-// Lower-triangle matvec y = A[k+1:, k+1:] v_k.  One work-group per lower
-// 64 x 64 super-tile (SI, SJ); wave w stages sub-tile (w>>1, w&1) in LDS
-// (for a diagonal super-tile the upper sub-tile is the conjugate transpose
-// of its mirror, so the block acts as a full Hermitian block).  The four
-// waves' sums are combined in a fixed order; the super-tile writes its row
-// partial HS[SJ*len + r] and, off the diagonal, its column partial
-// HS[(nst + SI)*len + c].
-template <class T>
-__global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
-                                                    int bufV, int bufHS, int bufW, int k0, int k) {
-  const int b = blockIdx.y;
-  const BlockDesc& d = D[b];
-  if (info[b]) return;
-  const int n = seldim(d, dsel);
-  const int off = k + 1, len = n - k - 1;
-  if (len <= 0) return;
+// Lower-triangle matvec y = A[k+1:, k+1:] v_k, persistent over the batch.
+// Work items are (block, lower 64 x 64 super-tile (SI, SJ)); a work-group
+// walks items blockIdx.x, +gridDim.x, ... and prefetches the next item's
+// sub-tile into registers while reducing the current one.  Wave w stages
+// sub-tile (w>>1, w&1) in LDS (for a diagonal super-tile the upper sub-tile
+// is the conjugate transpose of its mirror, so the block acts as a full
+// Hermitian block).  The four waves' sums are combined in a fixed order; the
+// super-tile writes its row partial HS[SJ*len + r] and, off the diagonal,
+// its column partial HS[(nst + SI)*len + c]; a diagonal super-tile also
+// writes its strip's part of the panel dot products (W^H v, V^H v).
+struct MvItem {
+  int valid, b, SI, SJ, len, n, nst;
+};
+
+__device__ inline MvItem mv_decode(const BlockDesc* D, const int* info, int dsel, int k, int nblk, int nsmax,
+                                   int item) {
+  MvItem it{0, 0, 0, 0, 0, 0, 0};
+  const int b = item / nsmax, st = item - (item / nsmax) * nsmax;
+  if (b >= nblk || info[b]) return it;
+  const int n = seldim(D[b], dsel);
+  const int len = n - k - 1;
+  if (len <= 0) return it;
   const int nst = (len + 63) / 64;
-  const int st = blockIdx.x;
-  if (st >= nst * (nst + 1) / 2) return;
+  if (st >= nst * (nst + 1) / 2) return it;
   int SI = (int)((sqrt(8.0 * st + 1.0) - 1.0) * 0.5);
   while ((SI + 1) * (SI + 2) / 2 <= st) ++SI;
   while (SI * (SI + 1) / 2 > st) --SI;
-  const int SJ = st - SI * (SI + 1) / 2;
-  const bool diag = SI == SJ;
-  const T* A = bufp<T>(ws, d, bufA);
-  const T* vg = bufp<T>(ws, d, bufV);
-  T* HS = bufp<T>(ws, d, bufHS);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wi = wave >> 1, wj = wave & 1;
-  __shared__ T tiles[4][HT][HT + 1];
-  __shared__ T comb[4][HT];
-  __shared__ T vsh[4][2][HT];
-  T (*tl)[HT + 1] = tiles[wave];
-  const int rowbase = 64 * SI + 32 * wi, colbase = 64 * SJ + 32 * wj;
-  const bool upper = diag && wi < wj;
-  const bool dsub = diag && wi == wj;
-  // issue every load of the sub-tile first (16 per lane), then stage in LDS
+  it.valid = 1;
+  it.b = b;
+  it.SI = SI;
+  it.SJ = st - SI * (SI + 1) / 2;
+  it.len = len;
+  it.n = n;
+  it.nst = nst;
+  return it;
+}
+
+template <class T>
+__device__ inline void mv_load(const BlockDesc* D, char* ws, int bufA, int k, const MvItem& it, int wi, int wj,
+                               int lane, T* regs) {
+  const T* A = bufp<T>(ws, D[it.b], bufA);
+  const int off = k + 1, len = it.len, n = it.n;
+  const bool diag = it.SI == it.SJ;
+  const int rowbase = 64 * it.SI + 32 * wi, colbase = 64 * it.SJ + 32 * wj;
+  const bool upper = diag && wi < wj, dsub = diag && wi == wj;
   const int lr0 = upper ? colbase : rowbase, lc0 = upper ? rowbase : colbase;
-  T regs[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int ii = (lane >> 5) + 2 * q, jj = lane & 31;
     const int r = lr0 + ii, c = lc0 + jj;
     regs[q] = (r < len && c < len && (!dsub || ii >= jj)) ? A[(long long)(off + r) * n + off + c] : tzero<T>();
   }
-  if (lane < HT) {
-    const int c = colbase + lane;
-    vsh[wave][0][lane] = c < len ? vg[c] : tzero<T>();
-  } else {
-    const int r = rowbase + lane - HT;
-    vsh[wave][1][lane - HT] = r < len ? vg[r] : tzero<T>();
-  }
-#pragma unroll
-  for (int q = 0; q < 16; ++q) tl[(lane >> 5) + 2 * q][lane & 31] = regs[q];
-  wave_sync();
-  if (upper) {
-    for (int e = lane; e < HT * HT; e += 64) {
-      int ii = e / HT, jj = e % HT;
-      if (ii < jj) {
-        T x = tl[ii][jj];
-        tl[ii][jj] = conjg(tl[jj][ii]);
-        tl[jj][ii] = conjg(x);
-      } else if (ii == jj) {
-        tl[ii][ii] = conjg(tl[ii][ii]);
-      }
-    }
-    wave_sync();
-  } else if (dsub) {
-    for (int e = lane; e < HT * HT; e += 64) {
-      int ii = e / HT, jj = e % HT;
-      if (ii < jj) tl[ii][jj] = conjg(tl[jj][ii]);
-      else if (ii == jj) tl[ii][jj] = treal<T>(re(tl[ii][jj]));
-    }
-    wave_sync();
-  }
-  T sum = tzero<T>();
-  if (lane < HT) {
-#pragma unroll 8
-    for (int jj = 0; jj < HT; ++jj) sum = mad(tl[lane][jj], vsh[wave][0][jj], sum);
-  } else if (!diag) {
-    const int jj = lane - HT;
-#pragma unroll 8
-    for (int ii = 0; ii < HT; ++ii) sum = mad(conjg(tl[ii][jj]), vsh[wave][1][ii], sum);
-  }
-  // row partial of rows rowbase..: waves (wi,0) + (wi,1); column partial: waves (0,wj) + (1,wj)
-  if (lane < HT && wj == 1) comb[wi][lane] = sum;
-  if (lane >= HT && wi == 1) comb[2 + wj][lane - HT] = sum;
-  __syncthreads();
-  if (lane < HT && wj == 0) {
-    int r = rowbase + lane;
-    if (r < len) HS[(long long)SJ * len + r] = sum + comb[wi][lane];
-  }
-  if (!diag && lane >= HT && wi == 0) {
-    int c = colbase + lane - HT;
-    if (c < len) HS[(long long)(nst + SI) * len + c] = sum + comb[2 + wj][lane - HT];
-  }
-  if (diag) {
-    // this strip's part of the panel dot products (j < k - k0):
-    // TP[SI][j] = (sum_r conj(W(off+r, j)) v_r, sum_r conj(V(off+r, j)) v_r)
-    const int ip = k - k0;
-    const T* Wp = bufp<T>(ws, d, bufW);
-    __shared__ T tpart[8][HB][2];
-    const int j = threadIdx.x & (HB - 1), g = threadIdx.x >> 5;
-    T s1 = tzero<T>(), s2 = tzero<T>();
-    if (j < ip) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int r = 64 * SI + 8 * g + q;
-        if (r < len) {
-          const T vr = vg[r];
-          s1 = mad(conjg(Wp[(long long)(off + r) * HB + j]), vr, s1);
-          s2 = mad(conjg(panel_v(A, n, k0, off + r, j)), vr, s2);
-        }
-      }
-    }
-    tpart[g][j][0] = s1;
-    tpart[g][j][1] = s2;
-    __syncthreads();
-    if (threadIdx.x < HB) {
-      T a1 = tzero<T>(), a2 = tzero<T>();
-      for (int gg = 0; gg < 8; ++gg) {
-        a1 = a1 + tpart[gg][threadIdx.x][0];
-        a2 = a2 + tpart[gg][threadIdx.x][1];
-      }
-      T* TP = HS + (long long)2 * nst * len;
-      TP[((long long)SI * HB + threadIdx.x) * 2] = a1;
-      TP[((long long)SI * HB + threadIdx.x) * 2 + 1] = a2;
-    }
-  }
 }
 
+template <class T>
+__global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
+                                                    int bufV, int bufHS, int bufW, int k0, int k, int nblk,
+                                                    int nsmax) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wi = wave >> 1, wj = wave & 1;
+  __shared__ T tiles[4][HT][HT + 1];
+  __shared__ T comb[4][HT];
+  __shared__ T vsh[4][2][HT];
+  __shared__ T tpart[8][HB][2];
+  T (*tl)[HT + 1] = tiles[wave];
+  const int total = nblk * nsmax;
+  int item = blockIdx.x;
+  MvItem cur = mv_decode(D, info, dsel, k, nblk, nsmax, item);
+  T regs[16];
+  if (cur.valid) mv_load<T>(D, ws, bufA, k, cur, wi, wj, lane, regs);
+  while (item < total) {
+    const int nitem = item + gridDim.x;
+    const MvItem nxt = mv_decode(D, info, dsel, k, nblk, nsmax, nitem);
+    T nregs[16];
+    if (nxt.valid) mv_load<T>(D, ws, bufA, k, nxt, wi, wj, lane, nregs);
+    if (cur.valid) {
+      const BlockDesc& d = D[cur.b];
+      const T* vg = bufp<T>(ws, d, bufV);
+      T* HS = bufp<T>(ws, d, bufHS);
+      const int len = cur.len, nst = cur.nst, SI = cur.SI, SJ = cur.SJ;
+      const bool diag = SI == SJ;
+      const int rowbase = 64 * SI + 32 * wi, colbase = 64 * SJ + 32 * wj;
+      const bool upper = diag && wi < wj, dsub = diag && wi == wj;
+      if (lane < HT) {
+        const int c = colbase + lane;
+        vsh[wave][0][lane] = c < len ? vg[c] : tzero<T>();
+      } else {
+        const int r = rowbase + lane - HT;
+        vsh[wave][1][lane - HT] = r < len ? vg[r] : tzero<T>();
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) tl[(lane >> 5) + 2 * q][lane & 31] = regs[q];
+      wave_sync();
+      if (upper) {
+        for (int e = lane; e < HT * HT; e += 64) {
+          int ii = e / HT, jj = e % HT;
+          if (ii < jj) {
+            T x = tl[ii][jj];
+            tl[ii][jj] = conjg(tl[jj][ii]);
+            tl[jj][ii] = conjg(x);
+          } else if (ii == jj) {
+            tl[ii][ii] = conjg(tl[ii][ii]);
+          }
+        }
+        wave_sync();
+      } else if (dsub) {
+        for (int e = lane; e < HT * HT; e += 64) {
+          int ii = e / HT, jj = e % HT;
+          if (ii < jj) tl[ii][jj] = conjg(tl[jj][ii]);
+          else if (ii == jj) tl[ii][jj] = treal<T>(re(tl[ii][jj]));
+        }
+        wave_sync();
+      }
+      T sum = tzero<T>();
+      if (lane < HT) {
+#pragma unroll 8
+        for (int jj = 0; jj < HT; ++jj) sum = mad(tl[lane][jj], vsh[wave][0][jj], sum);
+      } else if (!diag) {
+        const int jj = lane - HT;
+#pragma unroll 8
+        for (int ii = 0; ii < HT; ++ii) sum = mad(conjg(tl[ii][jj]), vsh[wave][1][ii], sum);
+      }
+      if (lane < HT && wj == 1) comb[wi][lane] = sum;
+      if (lane >= HT && wi == 1) comb[2 + wj][lane - HT] = sum;
+      __syncthreads();
+      if (lane < HT && wj == 0) {
+        int r = rowbase + lane;
+        if (r < len) HS[(long long)SJ * len + r] = sum + comb[wi][lane];
+      }
+      if (!diag && lane >= HT && wi == 0) {
+        int c = colbase + lane - HT;
+        if (c < len) HS[(long long)(nst + SI) * len + c] = sum + comb[2 + wj][lane - HT];
+      }
+      if (diag) {
+        const int ip = k - k0, off = k + 1, n = cur.n;
+        const T* A = bufp<T>(ws, d, bufA);
+        const T* Wp = bufp<T>(ws, d, bufW);
+        const int j = threadIdx.x & (HB - 1), g = threadIdx.x >> 5;
+        T s1 = tzero<T>(), s2 = tzero<T>();
+        if (j < ip) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int r = 64 * SI + 8 * g + q;
+            if (r < len) {
+              const T vr = vg[r];
+              s1 = mad(conjg(Wp[(long long)(off + r) * HB + j]), vr, s1);
+              s2 = mad(conjg(panel_v(A, n, k0, off + r, j)), vr, s2);
+            }
+          }
+        }
+        tpart[g][j][0] = s1;
+        tpart[g][j][1] = s2;
+        __syncthreads();
+        if (threadIdx.x < HB) {
+          T a1 = tzero<T>(), a2 = tzero<T>();
+          for (int gg = 0; gg < 8; ++gg) {
+            a1 = a1 + tpart[gg][threadIdx.x][0];
+            a2 = a2 + tpart[gg][threadIdx.x][1];
+          }
+          T* TP = HS + (long long)2 * nst * len;
+          TP[((long long)SI * HB + threadIdx.x) * 2] = a1;
+          TP[((long long)SI * HB + threadIdx.x) * 2 + 1] = a2;
+        }
+      }
+      __syncthreads();
+    }
+    item = nitem;
+    cur = nxt;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) regs[q] = nregs[q];
+  }
+}
 
 // Trailing lower triangle (rows/cols >= k0 + kb): A -= V W^H + W V^H.
 // grid = (lower 32 x 32 tiles, nblk).
@@ -715,6 +756,9 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
     return;
   }
   const size_t shm = 3 * (size_t)maxdim * sizeof(T);
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int mv_grid = 2 * ncu;          // two resident work-groups per CU (LDS-bound)
   for (int k0 = 0; k0 < maxdim - 1; k0 += HB) {
     const int kbmax = std::min(HB, maxdim - 1 - k0);
     hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufW,
@@ -723,8 +767,11 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
       const int k = k0 + i;
       const int len = maxdim - k - 1;
       const int nst = (len + 63) / 64;
-      hipLaunchKernelGGL(k_tri_matvec<T>, dim3(nst * (nst + 1) / 2, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
-                         bufV, bufHS, bufW, k0, k);
+      const int nsmax = nst * (nst + 1) / 2;
+      const long long items = (long long)nsmax * nblk;
+      const int grid = (int)std::min<long long>(items, (long long)mv_grid);
+      hipLaunchKernelGGL(k_tri_matvec<T>, dim3(grid), dim3(256), 0, s, D, ws, info, dsel, bufA, bufV, bufHS, bufW,
+                         k0, k, nblk, nsmax);
       hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau,
                          bufW, bufV, bufHS, k0, i + 1, (i + 1 < kbmax) ? 1 : 2);
     }

@@ -30,7 +30,11 @@ struct Layout {
   size_t info_off = 0, desc_off = 0;
   size_t total = 0;
   std::vector<BlockDesc> desc;
+  BlockDesc* pinned = nullptr;     // page-locked copy of desc for the upload
   int maxN = 0, maxn = 0, maxm = 0;
+  ~Layout() {
+    if (pinned) (void)hipHostFree(pinned);
+  }
 };
 
 // byte sizes of the named buffers for one block
@@ -132,7 +136,16 @@ std::shared_ptr<Layout> get_plan(const x2c_options* o, int nblk, const int* N, c
   if (it != g_plans.end()) return it->second;
   auto L = std::make_shared<Layout>();
   if (!make_layout(o, nblk, N, in_off, h_off, eps_off, *L)) return nullptr;
-  if (g_plans.size() > 64) g_plans.clear();
+  void* pin = nullptr;
+  if (hipHostMalloc(&pin, L->desc.size() * sizeof(BlockDesc), hipHostMallocDefault) == hipSuccess && pin) {
+    std::memcpy(pin, L->desc.data(), L->desc.size() * sizeof(BlockDesc));
+    L->pinned = static_cast<BlockDesc*>(pin);
+  }
+  if (g_plans.size() > 64) {
+    // evicted plans free their page-locked descriptor copies: wait for pending uploads first
+    (void)hipDeviceSynchronize();
+    g_plans.clear();
+  }
   g_plans.emplace(std::move(key), L);
   return L;
 }
@@ -326,8 +339,9 @@ int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
   if (out_layout) *out_layout = L.get();
   char* ws = static_cast<char*>(workspace);
   (void)hipGetLastError();
-  if (hipMemcpyAsync(ws + L->desc_off, L->desc.data(), L->desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice,
-                     s) != hipSuccess)
+  const void* src = L->pinned ? static_cast<const void*>(L->pinned) : static_cast<const void*>(L->desc.data());
+  if (hipMemcpyAsync(ws + L->desc_off, src, L->desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
     return X2C_EHIP;
   if (!info) info = reinterpret_cast<int*>(ws + L->info_off);
   if (o->mode == X2C_TWOCOMP)
@@ -393,6 +407,7 @@ const char* x2c_strerror(int code) {
 void x2c_release(void) {
   {
     std::lock_guard<std::mutex> lk(g_mu);
+    (void)hipDeviceSynchronize();
     g_plans.clear();
   }
   std::lock_guard<std::mutex> lk(g_tmu);
