@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--workload", choices=["ag309", "mixed512"], default="ag309")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--prec", choices=["fp64", "split"], default="fp64")
+    ap.add_argument("--reduction", choices=["quaternion", "complex"], default="quaternion",
+                    help="two-component eigenproblem reduction")
     ap.add_argument("--check-blocks", type=int, default=3, help="blocks checked against the oracle")
     ap.add_argument("--cpu-blocks", type=int, default=12, help="blocks in the CPU oracle sample (0 = skip)")
     ap.add_argument("--no-trace", action="store_true")
@@ -119,8 +121,9 @@ def cpu_baseline(blocks, twocomp, c, nblk_sample):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the per-block DLU build shards over blocks, see DESIGN.md)"}))
+        print(json.dumps({"error": "this benchmark measures one GPU only; --gpus must be 1 "
+                                   "(the per-block DLU build shards over blocks: each GPU runs "
+                                   "its own share of the batch with no communication)"}))
         sys.exit(2)
     import torch
     import paper_1303_4446_amd as px
@@ -131,15 +134,16 @@ def main():
     c = C_LIGHT
     blocks, twocomp, desc = workload(args.workload, args.seed)
     prec = px.FP64 if args.prec == "fp64" else px.SPLIT_BF16
+    red = px.RED_QUATERNION if args.reduction == "quaternion" else px.RED_COMPLEX
     pk = pack_blocks(blocks, twocomp)
     batch = px.batch_to_device(pk, twocomp)
     stream = torch.cuda.current_stream()
     print(f"# workload: {desc}; prec {args.prec}", file=sys.stderr, flush=True)
 
-    (h, eps, info), ws = px.build_batched(batch, c, prec=prec, stream=stream)
+    (h, eps, info), ws = px.build_batched(batch, c, prec=prec, stream=stream, reduction=red)
     out = (h, eps, info)
     for _ in range(max(0, args.warmup - 1)):
-        px.build_batched(batch, c, prec=prec, workspace=ws, out=out, stream=stream)
+        px.build_batched(batch, c, prec=prec, workspace=ws, out=out, stream=stream, reduction=red)
     torch.cuda.synchronize()
     print("# warm-up done", file=sys.stderr, flush=True)
 
@@ -151,7 +155,7 @@ def main():
     torch.cuda.synchronize()
     ev0.record(stream)
     for _ in range(args.steps):
-        px.build_batched(batch, c, prec=prec, workspace=ws, out=out, stream=stream)
+        px.build_batched(batch, c, prec=prec, workspace=ws, out=out, stream=stream, reduction=red)
     ev1.record(stream)
     torch.cuda.synchronize()
     elapsed_ms = ev0.elapsed_time(ev1)
@@ -194,7 +198,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "nblocks": nblk, "mode": "two-component" if twocomp else "spin-free",
-                   "prec": args.prec, **acc},
+                   "prec": args.prec, "reduction": args.reduction, **acc},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: round(v, 4) for k, v in sorted(stage_ms.items(), key=lambda kv: -kv[1])},

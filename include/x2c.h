@@ -50,18 +50,30 @@ extern "C" {
 typedef enum { X2C_SPINFREE = 1, X2C_TWOCOMP = 2 } x2c_mode;
 typedef enum { X2C_FP64 = 0, X2C_SPLIT_BF16 = 1 } x2c_prec;
 
+/* Reduction of the two Hermitian eigenproblems of a two-component block.
+ * Every two-component matrix of the method has the time-reversal form
+ * [[A, B], [-B*, A*]] in the [all alpha; all beta] basis (Sec. III.A, Kramers
+ * pairs), i.e. it is the quaternion matrix A + B j of half the dimension.
+ * The quaternion reduction tridiagonalises that half-size form (one real
+ * eigenvalue per Kramers pair); the complex one treats the full complex
+ * Hermitian matrix.  Both give the same h to rounding.  Ignored for
+ * spin-free blocks. */
+typedef enum { X2C_RED_QUATERNION = 0, X2C_RED_COMPLEX = 1 } x2c_reduction;
+
 typedef struct {
   int mode;          /* x2c_mode */
   int prec;          /* x2c_prec: arithmetic of the X / L / S~ / R product chain */
   int ozaki_slices;  /* split precision only: bf16 slices per operand, 0 = automatic */
   double c;          /* speed of light in atomic units (> 0) */
+  int reduction;     /* x2c_reduction (two-component only); 0 = quaternion */
 } x2c_options;
 
 /* return codes */
 enum {
   X2C_OK = 0,
   X2C_EINVAL = -1,  /* bad argument: NULL pointer, N <= 0 or > x2c_max_n, c <= 0,
-                       unknown mode/prec, workspace too small, overlapping layout */
+                       unknown mode/prec/reduction, workspace too small,
+                       overlapping layout */
   X2C_EHIP = -2,    /* a HIP runtime call or kernel launch failed */
   X2C_EBLOCK = -3   /* x2c_build only: the block failed; see its info code */
 };

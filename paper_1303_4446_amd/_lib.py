@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libx2c.so")
 
 SPINFREE, TWOCOMP = 1, 2
 FP64, SPLIT_BF16 = 0, 1
+RED_QUATERNION, RED_COMPLEX = 0, 1
 
 OK, EINVAL, EHIP, EBLOCK = 0, -1, -2, -3
 INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subspace degenerate",
@@ -35,7 +36,7 @@ class X2CError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("prec", ctypes.c_int), ("ozaki_slices", ctypes.c_int),
-                ("c", ctypes.c_double)]
+                ("c", ctypes.c_double), ("reduction", ctypes.c_int)]
 
 
 _LIB = None
@@ -78,8 +79,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     return lib
 
 
-def options(twocomp: bool, c: float, prec: int = FP64, slices: int = 0) -> _Options:
-    return _Options(TWOCOMP if twocomp else SPINFREE, prec, slices, float(c))
+def options(twocomp: bool, c: float, prec: int = FP64, slices: int = 0,
+            reduction: int = RED_QUATERNION) -> _Options:
+    return _Options(TWOCOMP if twocomp else SPINFREE, prec, slices, float(c), reduction)
 
 
 def strerror(code: int) -> str:
@@ -173,7 +175,7 @@ def batch_to_device(packed: dict, twocomp: bool, device="cuda") -> Batch:
 
 
 def build_batched(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspace=None, out=None,
-                  stream=None):
+                  stream=None, reduction: int = RED_QUATERNION):
     """Enqueue x2c_build_batched.  Returns (h_flat, eps_flat, info) device
     tensors (h_flat float64; complex blocks interleaved) and the workspace."""
     torch = _torch()
@@ -189,7 +191,7 @@ def build_batched(batch: Batch, c: float, prec: int = FP64, slices: int = 0, wor
     wsb = workspace_bytes(batch.Ns, batch.twocomp, c, prec)
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
-    opt = options(batch.twocomp, c, prec, slices)
+    opt = options(batch.twocomp, c, prec, slices, reduction)
     Ns = np.ascontiguousarray(batch.Ns, dtype=np.int32)
     i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
     in_off, ho, eo = i64(batch.in_off), i64(h_off), i64(eps_off)
@@ -222,7 +224,8 @@ def unpack_h(h_flat: np.ndarray, Ns, twocomp: bool):
     return out
 
 
-def build(S, T, V, W, c: float, twocomp: bool, prec: int = FP64, slices: int = 0, workspace=None, stream=None):
+def build(S, T, V, W, c: float, twocomp: bool, prec: int = FP64, slices: int = 0, workspace=None, stream=None,
+          reduction: int = RED_QUATERNION):
     """x2c_build on one block given as device tensors (S, T, V: N x N;
     W: N x N (spin-free) or 4 x N x N).  Returns (h, eps) device tensors.
     Raises X2CError with .info on a failed block."""
@@ -233,7 +236,7 @@ def build(S, T, V, W, c: float, twocomp: bool, prec: int = FP64, slices: int = 0
     dev = S.device
     h = torch.empty((n, n), dtype=torch.complex128 if twocomp else torch.float64, device=dev)
     eps = torch.empty(n, dtype=torch.float64, device=dev)
-    opt = options(twocomp, c, prec, slices)
+    opt = options(twocomp, c, prec, slices, reduction)
     wsb = workspace_bytes([N], twocomp, c, prec)
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)

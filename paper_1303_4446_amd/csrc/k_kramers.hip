@@ -1,0 +1,189 @@
+// Time-reversal (Kramers) structure of the two-component matrices.
+//
+// In the spin-orbital basis [all alpha; all beta] every two-component matrix
+// of the method (S, T, V, W of Eqs. defstv/defw, the reduced 4c matrix, the
+// renormalisation matrix) has the form [[A, B], [-B*, A*]] (Sec. III.A), i.e.
+// it is the quaternion matrix A + B j of half the dimension.  Reducing the
+// quaternion form instead of the complex one halves the dimension of the
+// tridiagonalisation (a real symmetric tridiagonal whose eigenvalues are the
+// Kramers pairs) and quarters the bytes it streams.  This file builds the
+// quaternion matrices, the unit-quaternion phases that turn the quaternion
+// tridiagonal into a real one, and converts quaternion results back to the
+// complex spin-orbital layout used by the product chain.
+#include "x2c_device.h"
+#include "x2c_launch.h"
+
+namespace x2c {
+
+// Quaternion reduced 4c matrix (n x n, n = 2N): index i < N is the large
+// component of scalar function i, i >= N the small component of i - N;
+// element = (alpha-alpha entry) + (alpha-beta entry) j of the complex matrix
+// L_M^-1 D L_M^-H.
+__global__ void k_assemble_Aq(const BlockDesc* D, char* ws, const int* info, double c) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int N = d.N, n = d.n;
+  const long long nn = (long long)n * n;
+  const double* all = bufp<double>(ws, d, R_ALL);
+  const double* bb = bufp<double>(ws, d, R_B);
+  const double* w0 = bufp<double>(ws, d, R_WR0);
+  const double* wx = bufp<double>(ws, d, R_WR1);
+  const double* wy = bufp<double>(ws, d, R_WR2);
+  const double* wz = bufp<double>(ws, d, R_WR3);
+  quat* A = bufp<quat>(ws, d, C_A);
+  const double sq2c = sqrt(2.0) * c, two_c2 = 2.0 * c * c;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    const int qi = i / N, qj = j / N;
+    const int a = i - qi * N, c2 = j - qj * N;
+    quat val = tzero<quat>();
+    if (qi == 0 && qj == 0) {
+      val.a.x = all[(long long)a * N + c2];
+    } else if (qi == 0) {
+      val.a.x = sq2c * bb[(long long)a * N + c2];
+    } else if (qj == 0) {
+      val.a.x = sq2c * bb[(long long)c2 * N + a];
+    } else {
+      const long long k = (long long)a * N + c2;
+      val.a = {0.5 * w0[k] - (a == c2 ? two_c2 : 0.0), 0.5 * wz[k]};
+      val.b = {0.5 * wy[k], 0.5 * wx[k]};
+    }
+    A[e] = val;
+  }
+}
+
+// delta_0 = 1, delta_{k+1} = e_k delta_k / |e_k|: with D = diag(delta) the
+// quaternion tridiagonal T_q satisfies D^H T_q D = tridiag(d, |e|).
+__global__ void k_phase_q(const BlockDesc* D, char* ws, const int* info, int nblk, int dsel) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk || info[b]) return;
+  const BlockDesc& d = D[b];
+  const int dim = seldim(d, dsel);
+  const quat* et = bufp<quat>(ws, d, V_ET);
+  quat* del = bufp<quat>(ws, d, V_DEL);
+  quat cur = treal<quat>(1.0);
+  del[0] = cur;
+  for (int k = 0; k + 1 < dim; ++k) {
+    const quat q = et[k];
+    const double a = sqrt(abs2(q));
+    if (a > 0.0) {
+      cur = q * cur;
+      cur = (1.0 / sqrt(abs2(cur))) * cur;   // keep |delta| = 1 to rounding
+    }
+    del[k + 1] = cur;
+  }
+}
+
+// Quaternion subspace block Y_q (n x n/2, in C_Y) -> complex Y (m x n, in C_A)
+// with rows [L_alpha, L_beta, S_alpha, S_beta] and the Kramers pair of
+// columns (2j, 2j+1): q = a + b j gives (a, -b*) and (b, a*).
+__global__ void k_quat_to_cplx_Y(const BlockDesc* D, char* ws, const int* info) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int N = d.N, n = d.n, h = n / 2;
+  const quat* Yq = bufp<quat>(ws, d, C_Y);
+  cplx* Y = bufp<cplx>(ws, d, C_A);
+  const long long tot = (long long)n * h;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / h), j = (int)(e % h);
+    const quat q = Yq[e];
+    const int ia = i < N ? i : n + (i - N);
+    const int ib = i < N ? N + i : n + N + (i - N);
+    Y[(long long)ia * n + 2 * j] = q.a;
+    Y[(long long)ia * n + 2 * j + 1] = q.b;
+    Y[(long long)ib * n + 2 * j] = cplx{-q.b.x, q.b.y};
+    Y[(long long)ib * n + 2 * j + 1] = cplx{q.a.x, -q.a.y};
+  }
+}
+
+// complex n x n ([alpha; beta], Kramers-structured) -> quaternion N x N
+__global__ void k_cplx_to_quat(const BlockDesc* D, char* ws, const int* info, int src, int dst) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int N = d.N, n = d.n;
+  const cplx* C = bufp<cplx>(ws, d, src);
+  quat* Q = bufp<quat>(ws, d, dst);
+  const long long tot = (long long)N * N;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    Q[e] = quat{C[(long long)i * n + j], C[(long long)i * n + N + j]};
+  }
+}
+
+// quaternion N x N -> complex n x n (blocks [[a, b], [-b*, a*]])
+__global__ void k_quat_to_cplx(const BlockDesc* D, char* ws, const int* info, int src, int dst) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int N = d.N, n = d.n;
+  const quat* Q = bufp<quat>(ws, d, src);
+  cplx* C = bufp<cplx>(ws, d, dst);
+  const long long tot = (long long)N * N;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    const quat q = Q[e];
+    C[(long long)i * n + j] = q.a;
+    C[(long long)i * n + N + j] = q.b;
+    C[(long long)(N + i) * n + j] = cplx{-q.b.x, q.b.y};
+    C[(long long)(N + i) * n + N + j] = cplx{q.a.x, -q.a.y};
+  }
+}
+
+// out[i][j] = delta_i conj(in[j][i])  (N x N quaternions)
+__global__ void k_qct_scale(const BlockDesc* D, char* ws, const int* info, int src, int dst) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int N = d.N;
+  const quat* in = bufp<quat>(ws, d, src);
+  quat* out = bufp<quat>(ws, d, dst);
+  const quat* del = bufp<quat>(ws, d, V_DEL);
+  const long long tot = (long long)N * N;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    out[e] = del[i] * conjg(in[(long long)j * N + i]);
+  }
+}
+
+static int grid_for(long long elems) {
+  long long g = (elems + 255) / 256;
+  if (g > 256) g = 256;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+void launch_assemble_Aq(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, double c) {
+  hipLaunchKernelGGL(k_assemble_Aq, dim3(grid_for((long long)maxn * maxn), nblk), dim3(256), 0, s, D, ws, info, c);
+}
+void launch_phase_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int dsel) {
+  hipLaunchKernelGGL(k_phase_q, dim3((nblk + 63) / 64), dim3(64), 0, s, D, ws, info, nblk, dsel);
+}
+void launch_quat_to_cplx_Y(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn) {
+  hipLaunchKernelGGL(k_quat_to_cplx_Y, dim3(grid_for((long long)maxn * maxn / 2), nblk), dim3(256), 0, s, D, ws,
+                     info);
+}
+void launch_cplx_to_quat(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
+                         int dst) {
+  hipLaunchKernelGGL(k_cplx_to_quat, dim3(grid_for((long long)maxN * maxN), nblk), dim3(256), 0, s, D, ws, info, src,
+                     dst);
+}
+void launch_quat_to_cplx(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
+                         int dst) {
+  hipLaunchKernelGGL(k_quat_to_cplx, dim3(grid_for((long long)maxN * maxN), nblk), dim3(256), 0, s, D, ws, info, src,
+                     dst);
+}
+void launch_qct_scale(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
+                      int dst) {
+  hipLaunchKernelGGL(k_qct_scale, dim3(grid_for((long long)maxN * maxN), nblk), dim3(256), 0, s, D, ws, info, src,
+                     dst);
+}
+
+}  // namespace x2c

@@ -14,14 +14,14 @@ constexpr int LB = 32;
 
 // Factor panel J (columns LB*J .. +jb, rows LB*J .. n-1) of Y_L in place.
 template <class T>
-__global__ void __launch_bounds__(256) k_lu_panel(const BlockDesc* D, char* ws, int* info, int J) {
+__global__ void __launch_bounds__(256) k_lu_panel(const BlockDesc* D, char* ws, int* info, int J, int bufY) {
   const int b = blockIdx.x;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int n = d.n, j0 = LB * J;
   if (j0 >= n) return;
   const int jb = min(LB, n - j0);
-  T* A = bufp<T>(ws, d, C_Y);
+  T* A = bufp<T>(ws, d, bufY);
   int* piv = bufp<int>(ws, d, V_PIV);
   __shared__ double rv[4];
   __shared__ int ri[4];
@@ -85,14 +85,14 @@ __global__ void __launch_bounds__(256) k_lu_panel(const BlockDesc* D, char* ws, 
 
 // U12 = L11^-1 A12 for the block row of panel J (unit lower L11); thread per column.
 template <class T>
-__global__ void __launch_bounds__(256) k_lu_trsm12(const BlockDesc* D, char* ws, const int* info, int J) {
+__global__ void __launch_bounds__(256) k_lu_trsm12(const BlockDesc* D, char* ws, const int* info, int J, int bufY) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int n = d.n, j0 = LB * J;
   if (j0 >= n) return;
   const int jb = min(LB, n - j0);
-  T* A = bufp<T>(ws, d, C_Y);
+  T* A = bufp<T>(ws, d, bufY);
   __shared__ T L11[LB][LB + 1];
   for (int e = threadIdx.x; e < LB * LB; e += blockDim.x) {
     int i = e / LB, k = e % LB;
@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(256) k_lu_trsm12(const BlockDesc* D, char* ws,
 
 // A22 -= L21 U12 (trailing rows/cols >= LB*J + jb), 64 x 64 output tiles.
 template <class T>
-__global__ void __launch_bounds__(256) k_lu_update(const BlockDesc* D, char* ws, const int* info, int J) {
+__global__ void __launch_bounds__(256) k_lu_update(const BlockDesc* D, char* ws, const int* info, int J, int bufY) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) k_lu_update(const BlockDesc* D, char* ws,
   const int nt = (len + 63) / 64;
   if ((int)blockIdx.x >= nt * nt) return;
   const int r0 = t0 + 64 * (blockIdx.x / nt), c0 = t0 + 64 * (blockIdx.x % nt);
-  T* A = bufp<T>(ws, d, C_Y);
+  T* A = bufp<T>(ws, d, bufY);
   __shared__ T Ls[64][LB + 1];
   __shared__ T Us[LB][64 + 1];
   for (int e = threadIdx.x; e < 64 * LB; e += 256) {
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(256) k_lu_update(const BlockDesc* D, char* ws,
 //   lower: Z_J = (Z_J - Z_{>J} L_{>J,J}) L_JJ^-1, unit L (J descending)
 // Work-group: 64 rows x LB columns.
 template <class T, bool UPPER>
-__global__ void __launch_bounds__(256) k_rsolve_blk(const BlockDesc* D, char* ws, const int* info, int J) {
+__global__ void __launch_bounds__(256) k_rsolve_blk(const BlockDesc* D, char* ws, const int* info, int J, int bufY) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
@@ -184,8 +184,8 @@ __global__ void __launch_bounds__(256) k_rsolve_blk(const BlockDesc* D, char* ws
   const int jb = min(LB, n - j0);
   const int r0 = 64 * blockIdx.x;
   if (r0 >= n) return;
-  const T* LU = bufp<T>(ws, d, C_Y);
-  T* Z = bufp<T>(ws, d, C_Y) + (long long)n * n;      // Y_S block
+  const T* LU = bufp<T>(ws, d, bufY);
+  T* Z = bufp<T>(ws, d, bufY) + (long long)n * n;      // Y_S block
   __shared__ T Zs[64][LB + 1];
   __shared__ T Ms[LB][LB + 1];
   const int tx = threadIdx.x & 7, ty = threadIdx.x >> 3;   // 8 x 32: cols tx + 8j, rows ty + 32 i
@@ -261,13 +261,13 @@ __global__ void __launch_bounds__(256) k_rsolve_blk(const BlockDesc* D, char* ws
 // X~ = W P_{n-1} ... P_0 (column interchanges in reverse pivot order), as a
 // gather into C_TMP.  One work-group per block.
 template <class T>
-__global__ void __launch_bounds__(256) k_permute_cols(const BlockDesc* D, char* ws, const int* info) {
+__global__ void __launch_bounds__(256) k_permute_cols(const BlockDesc* D, char* ws, const int* info, int bufY) {
   const int b = blockIdx.x;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int n = d.n;
   const int* piv = bufp<int>(ws, d, V_PIV);
-  const T* W = bufp<T>(ws, d, C_Y) + (long long)n * n;
+  const T* W = bufp<T>(ws, d, bufY) + (long long)n * n;
   T* X = bufp<T>(ws, d, C_TMP);
   __shared__ int idx[1024];
   for (int c = threadIdx.x; c < n; c += blockDim.x) idx[c] = c;
@@ -286,25 +286,25 @@ __global__ void __launch_bounds__(256) k_permute_cols(const BlockDesc* D, char* 
 }
 
 template <class T>
-void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn) {
+void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn, int bufY) {
   const int nJ = (maxn + LB - 1) / LB;
   for (int J = 0; J < nJ; ++J) {
-    hipLaunchKernelGGL(k_lu_panel<T>, dim3(nblk), dim3(256), 0, s, D, ws, info, J);
+    hipLaunchKernelGGL(k_lu_panel<T>, dim3(nblk), dim3(256), 0, s, D, ws, info, J, bufY);
     const int rest = maxn - LB * J - LB;
     if (rest > 0) {
-      hipLaunchKernelGGL(k_lu_trsm12<T>, dim3((rest + 255) / 256, nblk), dim3(256), 0, s, D, ws, info, J);
+      hipLaunchKernelGGL(k_lu_trsm12<T>, dim3((rest + 255) / 256, nblk), dim3(256), 0, s, D, ws, info, J, bufY);
       const int nt = (rest + 63) / 64;
-      hipLaunchKernelGGL(k_lu_update<T>, dim3(nt * nt, nblk), dim3(256), 0, s, D, ws, info, J);
+      hipLaunchKernelGGL(k_lu_update<T>, dim3(nt * nt, nblk), dim3(256), 0, s, D, ws, info, J, bufY);
     }
   }
   const int nr = (maxn + 63) / 64;
   for (int J = 0; J < nJ; ++J)
-    hipLaunchKernelGGL((k_rsolve_blk<T, true>), dim3(nr, nblk), dim3(256), 0, s, D, ws, info, J);
+    hipLaunchKernelGGL((k_rsolve_blk<T, true>), dim3(nr, nblk), dim3(256), 0, s, D, ws, info, J, bufY);
   for (int J = nJ - 1; J >= 0; --J)
-    hipLaunchKernelGGL((k_rsolve_blk<T, false>), dim3(nr, nblk), dim3(256), 0, s, D, ws, info, J);
-  hipLaunchKernelGGL(k_permute_cols<T>, dim3(nblk), dim3(256), 0, s, D, ws, info);
+    hipLaunchKernelGGL((k_rsolve_blk<T, false>), dim3(nr, nblk), dim3(256), 0, s, D, ws, info, J, bufY);
+  hipLaunchKernelGGL(k_permute_cols<T>, dim3(nblk), dim3(256), 0, s, D, ws, info, bufY);
 }
-template void launch_xsolve_blk<double>(hipStream_t, const BlockDesc*, char*, int*, int, int);
-template void launch_xsolve_blk<cplx>(hipStream_t, const BlockDesc*, char*, int*, int, int);
+template void launch_xsolve_blk<double>(hipStream_t, const BlockDesc*, char*, int*, int, int, int);
+template void launch_xsolve_blk<cplx>(hipStream_t, const BlockDesc*, char*, int*, int, int, int);
 
 }  // namespace x2c

@@ -144,11 +144,15 @@ __device__ double zolotarev(double ell, int r, double* a, double* codd, double* 
 // ---------------------------------------------------------------- 4c branch
 // One work-group per block.  Writes eps (positive branch, ascending), the
 // branch-size check (info 4) and the projector filter parameters.
-__global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws, int* info, double* eps, double c) {
+// kramers = 1: the tridiagonal is the real form of the quaternion reduced
+// matrix (dimension n, one eigenvalue per Kramers pair); each positive-energy
+// eigenvalue is written twice.
+__global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws, int* info, double* eps, double c,
+                                                    int kramers) {
   const int b = blockIdx.x;
   const BlockDesc& d = D[b];
   if (info[b]) return;
-  const int m = d.m, n = d.n;
+  const int m = kramers ? d.n : d.m, n = kramers ? d.n / 2 : d.n;
   const double* dg = bufp<double>(ws, d, V_D);
   const double* eg = bufp<double>(ws, d, V_E);
   double* pf = bufp<double>(ws, d, P_FILT);
@@ -190,7 +194,14 @@ __global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws
   }
   for (int k = threadIdx.x; k <= n; k += blockDim.x) lam[k] = bisect(sd, se2, m, n - 1 + k, s_lo, s_hi, s_piv);
   __syncthreads();
-  for (int k = threadIdx.x; k < n; k += blockDim.x) eps[d.eps_off + k] = lam[k + 1];
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    if (kramers) {
+      eps[d.eps_off + 2 * k] = lam[k + 1];
+      eps[d.eps_off + 2 * k + 1] = lam[k + 1];
+    } else {
+      eps[d.eps_off + k] = lam[k + 1];
+    }
+  }
   if (threadIdx.x == 0) {
     const double sigma = -c * c;
     const double gam = fmin(lam[1] - sigma, sigma - lam[0]);
@@ -226,14 +237,14 @@ __global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws
 // LU with partial pivoting of (T_s - i beta_j I), T_s = (T - sigma)/rho, one
 // pole per work-group (thread 0).  Factor entry layout (5 complex):
 // {dl, 1/du0, du1, du2, (pivot, 0)}.
-__global__ void k_filter_factor(const BlockDesc* D, char* ws, const int* info) {
+__global__ void k_filter_factor(const BlockDesc* D, char* ws, const int* info, int kramers) {
   const int b = blockIdx.y, j = blockIdx.x;
   const BlockDesc& d = D[b];
   if (info[b] || threadIdx.x != 0) return;
   const double* pf = bufp<double>(ws, d, P_FILT);
   const int r = (int)pf[3];
   if (j >= r) return;
-  const int m = d.m;
+  const int m = kramers ? d.n : d.m;
   const double sigma = pf[0], rho = pf[1], beta = pf[4 + RMAX + j];
   const double* dg = bufp<double>(ws, d, V_D);
   const double* eg = bufp<double>(ws, d, V_E);
@@ -280,12 +291,13 @@ __global__ void k_filter_factor(const BlockDesc* D, char* ws, const int* info) {
 
 // Columns j of Z = 1/2 (E + M [T_s E + sum_q a_q Re((T_s - i beta_q)^-1 E)]),
 // E_ij = hash(i, j); the result (real) goes to the T-typed m x n buffer.
+// (quaternion form: rows are then scaled by the phases, Y_q = D Z)
 template <class T>
-__global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* ws, const int* info) {
+__global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* ws, const int* info, int kramers) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
-  const int m = d.m, n = d.n;
+  const int m = kramers ? d.n : d.m, n = kramers ? d.n / 2 : d.n;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const double* pf = bufp<double>(ws, d, P_FILT);
@@ -337,18 +349,20 @@ __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* 
   }
   for (int i = 0; i < m; ++i) {
     long long idx = (long long)i * n + j;
-    Y[idx] = treal<T>(0.5 * (hash_uniform(i, j) + M * re(Y[idx])));
+    const double z = 0.5 * (hash_uniform(i, j) + M * re(Y[idx]));
+    if constexpr (sizeof(T) == sizeof(quat)) Y[idx] = z * bufp<quat>(ws, d, V_DEL)[i];
+    else Y[idx] = treal<T>(z);
   }
 }
 
 // ---------------------------------------------------------------- Q^-1/2
 // Extreme eigenvalues of tridiag(dq, eq) (must be > 0: info 5), quadrature
 // nodes, and the LDL^T factors of (T_Q + s_j I) for every node.
-__global__ void __launch_bounds__(256) k_tri_eig_q(const BlockDesc* D, char* ws, int* info) {
+__global__ void __launch_bounds__(256) k_tri_eig_q(const BlockDesc* D, char* ws, int* info, int dsel) {
   const int b = blockIdx.x;
   const BlockDesc& d = D[b];
   if (info[b]) return;
-  const int n = d.n;
+  const int n = seldim(d, dsel);
   const double* dg = bufp<double>(ws, d, V_DQ);
   const double* eg = bufp<double>(ws, d, V_EQ);
   double* pq = bufp<double>(ws, d, P_QUAD);
@@ -417,18 +431,20 @@ __global__ void __launch_bounds__(256) k_tri_eig_q(const BlockDesc* D, char* ws,
 
 // F[:, k] = sum_j w_j (T_Q + s_j I)^-1 e_k  (F written T-typed into C_TMP;
 // per-column scratch in C_TMP2).  grid = (ceil(n/256), nblk)
+// (quaternion form: rows scaled by the phases, F_q = D F)
 template <class T>
-__global__ void __launch_bounds__(256) k_invsqrt_cols(const BlockDesc* D, char* ws, const int* info) {
+__global__ void __launch_bounds__(256) k_invsqrt_cols(const BlockDesc* D, char* ws, const int* info, int dsel,
+                                                      int bufScr) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
-  const int n = d.n;
+  const int n = seldim(d, dsel);
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const double* pq = bufp<double>(ws, d, P_QUAD);
   const double* fac = bufp<double>(ws, d, Q_FAC);
   T* F = bufp<T>(ws, d, C_TMP);
-  double* y = reinterpret_cast<double*>(bufp<T>(ws, d, C_TMP2));   // use as n x n doubles
+  double* y = bufp<double>(ws, d, bufScr);   // n x n doubles of scratch
   const int N = (int)pq[0];
   for (int i = 0; i < n; ++i) F[(long long)i * n + k] = tzero<T>();
   for (int j = 0; j < N; ++j) {
@@ -450,32 +466,44 @@ __global__ void __launch_bounds__(256) k_invsqrt_cols(const BlockDesc* D, char* 
       F[idx] = treal<T>(re(F[idx]) + w * x);
     }
   }
+  if constexpr (sizeof(T) == sizeof(quat)) {
+    const quat* del = bufp<quat>(ws, d, V_DEL);
+    for (int i = 0; i < n; ++i) {
+      long long idx = (long long)i * n + k;
+      F[idx] = re(F[idx]) * del[i];
+    }
+  }
 }
 
 // ----------------------------------------------------------------- launchers
 void launch_tri_eig4c(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxm, double* eps,
-                      double c) {
+                      double c, int kramers) {
   size_t shm = (size_t)(4 * maxm + 2) * sizeof(double);
-  hipLaunchKernelGGL(k_tri_eig4c, dim3(nblk), dim3(512), shm, s, D, ws, info, eps, c);
+  hipLaunchKernelGGL(k_tri_eig4c, dim3(nblk), dim3(512), shm, s, D, ws, info, eps, c, kramers);
 }
-void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk) {
-  hipLaunchKernelGGL(k_filter_factor, dim3(RMAX, nblk), dim3(64), 0, s, D, ws, info);
-}
-template <class T>
-void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn) {
-  hipLaunchKernelGGL(k_filter_solve<T>, dim3((maxn + 255) / 256, nblk), dim3(256), 0, s, D, ws, info);
-}
-void launch_tri_eig_q(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn) {
-  size_t shm = (size_t)(3 * maxn) * sizeof(double);
-  hipLaunchKernelGGL(k_tri_eig_q, dim3(nblk), dim3(256), shm, s, D, ws, info);
+void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int kramers) {
+  hipLaunchKernelGGL(k_filter_factor, dim3(RMAX, nblk), dim3(64), 0, s, D, ws, info, kramers);
 }
 template <class T>
-void launch_invsqrt_cols(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn) {
-  hipLaunchKernelGGL(k_invsqrt_cols<T>, dim3((maxn + 255) / 256, nblk), dim3(256), 0, s, D, ws, info);
+void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxrhs,
+                         int kramers) {
+  hipLaunchKernelGGL(k_filter_solve<T>, dim3((maxrhs + 255) / 256, nblk), dim3(256), 0, s, D, ws, info, kramers);
 }
-template void launch_filter_solve<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int);
-template void launch_filter_solve<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int);
-template void launch_invsqrt_cols<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int);
-template void launch_invsqrt_cols<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int);
+void launch_tri_eig_q(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxdim, int dsel) {
+  size_t shm = (size_t)(3 * maxdim) * sizeof(double);
+  hipLaunchKernelGGL(k_tri_eig_q, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel);
+}
+template <class T>
+void launch_invsqrt_cols(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
+                         int bufScr) {
+  hipLaunchKernelGGL(k_invsqrt_cols<T>, dim3((maxdim + 255) / 256, nblk), dim3(256), 0, s, D, ws, info, dsel,
+                     bufScr);
+}
+template void launch_filter_solve<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int);
+template void launch_filter_solve<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int);
+template void launch_filter_solve<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int);
+template void launch_invsqrt_cols<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int);
+template void launch_invsqrt_cols<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int);
+template void launch_invsqrt_cols<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int);
 
 }  // namespace x2c

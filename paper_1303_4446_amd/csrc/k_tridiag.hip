@@ -188,6 +188,69 @@ __global__ void __launch_bounds__(1024) k_hetrd(const BlockDesc* D, char* ws, co
   }
 }
 
+// Tile sizes per scalar type (quaternions are 32 bytes: smaller tiles keep
+// every kernel within the 160 KB of LDS per CU).
+template <class T>
+struct Tiles {
+  static constexpr int HT = 32;   // matvec sub-tile (super-tile / strip = 2 HT)
+  static constexpr int TT = 32;   // rank-2k update tile
+  static constexpr int LR = 64;   // larft row chunk
+  static constexpr int CW = 64;   // back-transformation columns per work-group
+  static constexpr int VR = 32;   // back-transformation V row chunk
+};
+template <>
+struct Tiles<quat> {
+  static constexpr int HT = 16;
+  static constexpr int TT = 16;
+  static constexpr int LR = 16;
+  static constexpr int CW = 32;
+  static constexpr int VR = 16;
+};
+template <class T>
+constexpr bool is_quat() {
+  return sizeof(T) == sizeof(quat);
+}
+
+// Quaternion Householder reflector for column k (rows k+1..n-1): with
+// x0 = A[k+1][k], sigma = (x0/|x0|) ||x||, u = x + sigma e1, the Hermitian
+// reflector I - 2 u u^H / u^H u maps x to -sigma e1.  Normalised to
+// v = u u0^-1 (v0 = 1) it is I - tau v v^H with real tau = 1 + |x0|/||x||.
+// beta_out = -sigma (quaternion sub-diagonal entry).
+__device__ void make_reflector_q(quat* A, int n, int k, quat* vout, quat* tau_out, quat* beta_out, double* red) {
+  const int len = n - k - 1;
+  double xn2 = 0.0;
+  for (int i = 1 + threadIdx.x; i < len; i += blockDim.x) xn2 += abs2(A[(long long)(k + 1 + i) * n + k]);
+  xn2 = block_sum(xn2, red);
+  const quat x0 = A[(long long)(k + 1) * n + k];
+  const double a0 = sqrt(abs2(x0));
+  const double xn = sqrt(a0 * a0 + xn2);
+  const bool trivial = (xn2 == 0.0 && x0.a.y == 0.0 && x0.b.x == 0.0 && x0.b.y == 0.0);
+  quat tau = tzero<quat>(), beta = x0, uinv = tzero<quat>();
+  if (!trivial) {
+    const quat ph = a0 > 0.0 ? (1.0 / a0) * x0 : treal<quat>(1.0);
+    const quat sig = xn * ph;
+    const quat u0 = x0 + sig;
+    uinv = (1.0 / abs2(u0)) * conjg(u0);
+    tau = treal<quat>(1.0 + a0 / xn);
+    beta = -sig;
+  }
+  for (int i = threadIdx.x; i < len; i += blockDim.x) {
+    if (i == 0) {
+      vout[0] = treal<quat>(1.0);
+    } else {
+      long long idx = (long long)(k + 1 + i) * n + k;
+      quat x = trivial ? tzero<quat>() : A[idx] * uinv;
+      vout[i] = x;
+      A[idx] = x;
+    }
+  }
+  if (threadIdx.x == 0) {
+    *tau_out = tau;
+    *beta_out = beta;
+  }
+  __syncthreads();
+}
+
 // element (r, a) of panel V whose first reflector is k0 (dimension nr)
 template <class T>
 __device__ inline T panel_v(const T* A, int nr, int k0, int r, int a) {
@@ -225,8 +288,9 @@ __device__ inline void wave_sync() {
 //        2 = finish column k-1 only (last column of the panel)
 template <class T>
 __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
-                                                 int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS, int k0,
-                                                 int i, int phase) {
+                                                 int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS,
+                                                 int bufET, int k0, int i, int phase) {
+  constexpr int ST = 2 * Tiles<T>::HT;
   const int b = blockIdx.x;
   const BlockDesc& d = D[b];
   if (info[b]) return;
@@ -259,7 +323,7 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
     const int kp = k0 + ip;
     const int off = kp + 1, len = n - kp - 1;
     const T tau = taus[kp];
-    const int nst = (len + 63) / 64;
+    const int nst = (len + ST - 1) / ST;
     for (int r = tid; r < len; r += 256) v[r] = vg[r];
     if (build && tid < ip) {
       wk[tid] = conjg(Wp[(long long)k * HB + tid]);
@@ -281,7 +345,7 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
     // corrections; the same pass accumulates the panel part of the update of
     // the next column
     for (int r = tid; r < len; r += 256) {
-      const int Sr = r / 64;
+      const int Sr = r / ST;
       T acc = tzero<T>();
       for (int SJ = 0; SJ <= Sr; ++SJ) acc = acc + HS[(long long)SJ * len + r];
       for (int SI = Sr + 1; SI < nst; ++SI) acc = acc + HS[(long long)(nst + SI) * len + r];
@@ -306,8 +370,11 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
       di += im(pv);
     }
     dr = block_sum(dr, red);
-    if (sizeof(T) != sizeof(double)) di = block_sum(di, red);
-    if (tid == 0) sh_alpha = (-0.5 * tau) * tmake<T>(dr, di);
+    if (sizeof(T) == sizeof(cplx)) di = block_sum(di, red);
+    if (tid == 0) {
+      if constexpr (is_quat<T>()) sh_alpha = treal<T>(-0.5 * re(tau) * dr);   // y^H v is real
+      else sh_alpha = (-0.5 * tau) * tmake<T>(dr, di);
+    }
     __syncthreads();
     const T alpha = sh_alpha;
     for (int r = tid; r < len; r += 256) {
@@ -332,18 +399,27 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
     if (tid == 0) A[(long long)k * n + k] = treal<T>(re(A[(long long)k * n + k]));
     __syncthreads();
   }
-  make_reflector<T>(A, n, k, v, &sh_tau, &sh_beta, red);
+  if constexpr (is_quat<T>()) {
+    __shared__ T sh_betaq;
+    make_reflector_q(A, n, k, v, &sh_tau, &sh_betaq, red);
+    if (tid == 0) {
+      ee[k] = sqrt(abs2(sh_betaq));
+      bufp<T>(ws, d, bufET)[k] = sh_betaq;
+    }
+  } else {
+    make_reflector<T>(A, n, k, v, &sh_tau, &sh_beta, red);
+    if (tid == 0) ee[k] = sh_beta;
+  }
   const int len = n - k - 1;
   for (int r = tid; r < len; r += 256) vg[r] = v[r];
   if (tid == 0) {
     dd[k] = re(A[(long long)k * n + k]);
-    ee[k] = sh_beta;
     taus[k] = sh_tau;
   }
 }
 
 // Lower-triangle matvec y = A[k+1:, k+1:] v_k, persistent over the batch.
-// Work items are (block, lower 64 x 64 super-tile (SI, SJ)); a work-group
+// Work items are (block, lower super-tile (SI, SJ) of 2 HT x 2 HT); a work-group
 // walks items blockIdx.x, +gridDim.x, ... and prefetches the next item's
 // sub-tile into registers while reducing the current one.  Wave w stages
 // sub-tile (w>>1, w&1) in LDS (for a diagonal super-tile the upper sub-tile
@@ -357,14 +433,14 @@ struct MvItem {
 };
 
 __device__ inline MvItem mv_decode(const BlockDesc* D, const int* info, int dsel, int k, int nblk, int nsmax,
-                                   int item) {
+                                   int item, int ST) {
   MvItem it{0, 0, 0, 0, 0, 0, 0};
   const int b = item / nsmax, st = item - (item / nsmax) * nsmax;
   if (b >= nblk || info[b]) return it;
   const int n = seldim(D[b], dsel);
   const int len = n - k - 1;
   if (len <= 0) return it;
-  const int nst = (len + 63) / 64;
+  const int nst = (len + ST - 1) / ST;
   if (st >= nst * (nst + 1) / 2) return it;
   int SI = (int)((sqrt(8.0 * st + 1.0) - 1.0) * 0.5);
   while ((SI + 1) * (SI + 2) / 2 <= st) ++SI;
@@ -382,15 +458,16 @@ __device__ inline MvItem mv_decode(const BlockDesc* D, const int* info, int dsel
 template <class T>
 __device__ inline void mv_load(const BlockDesc* D, char* ws, int bufA, int k, const MvItem& it, int wi, int wj,
                                int lane, T* regs) {
+  constexpr int HT = Tiles<T>::HT, ST = 2 * HT, EPL = HT * HT / 64, RPI = 64 / HT;
   const T* A = bufp<T>(ws, D[it.b], bufA);
   const int off = k + 1, len = it.len, n = it.n;
   const bool diag = it.SI == it.SJ;
-  const int rowbase = 64 * it.SI + 32 * wi, colbase = 64 * it.SJ + 32 * wj;
+  const int rowbase = ST * it.SI + HT * wi, colbase = ST * it.SJ + HT * wj;
   const bool upper = diag && wi < wj, dsub = diag && wi == wj;
   const int lr0 = upper ? colbase : rowbase, lc0 = upper ? rowbase : colbase;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int ii = (lane >> 5) + 2 * q, jj = lane & 31;
+  for (int q = 0; q < EPL; ++q) {
+    const int ii = lane / HT + RPI * q, jj = lane % HT;
     const int r = lr0 + ii, c = lc0 + jj;
     regs[q] = (r < len && c < len && (!dsub || ii >= jj)) ? A[(long long)(off + r) * n + off + c] : tzero<T>();
   }
@@ -400,6 +477,8 @@ template <class T>
 __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
                                                     int bufV, int bufHS, int bufW, int k0, int k, int nblk,
                                                     int nsmax) {
+  constexpr int HT = Tiles<T>::HT, ST = 2 * HT, EPL = HT * HT / 64, RPI = 64 / HT;
+  constexpr int RPG = ST / 8;          // rows per group in the panel dot products
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wi = wave >> 1, wj = wave & 1;
   __shared__ T tiles[4][HT][HT + 1];
@@ -409,13 +488,13 @@ __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws
   T (*tl)[HT + 1] = tiles[wave];
   const int total = nblk * nsmax;
   int item = blockIdx.x;
-  MvItem cur = mv_decode(D, info, dsel, k, nblk, nsmax, item);
-  T regs[16];
+  MvItem cur = mv_decode(D, info, dsel, k, nblk, nsmax, item, ST);
+  T regs[EPL];
   if (cur.valid) mv_load<T>(D, ws, bufA, k, cur, wi, wj, lane, regs);
   while (item < total) {
     const int nitem = item + gridDim.x;
-    const MvItem nxt = mv_decode(D, info, dsel, k, nblk, nsmax, nitem);
-    T nregs[16];
+    const MvItem nxt = mv_decode(D, info, dsel, k, nblk, nsmax, nitem, ST);
+    T nregs[EPL];
     if (nxt.valid) mv_load<T>(D, ws, bufA, k, nxt, wi, wj, lane, nregs);
     if (cur.valid) {
       const BlockDesc& d = D[cur.b];
@@ -423,17 +502,17 @@ __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws
       T* HS = bufp<T>(ws, d, bufHS);
       const int len = cur.len, nst = cur.nst, SI = cur.SI, SJ = cur.SJ;
       const bool diag = SI == SJ;
-      const int rowbase = 64 * SI + 32 * wi, colbase = 64 * SJ + 32 * wj;
+      const int rowbase = ST * SI + HT * wi, colbase = ST * SJ + HT * wj;
       const bool upper = diag && wi < wj, dsub = diag && wi == wj;
       if (lane < HT) {
         const int c = colbase + lane;
         vsh[wave][0][lane] = c < len ? vg[c] : tzero<T>();
-      } else {
+      } else if (lane < 2 * HT) {
         const int r = rowbase + lane - HT;
         vsh[wave][1][lane - HT] = r < len ? vg[r] : tzero<T>();
       }
 #pragma unroll
-      for (int q = 0; q < 16; ++q) tl[(lane >> 5) + 2 * q][lane & 31] = regs[q];
+      for (int q = 0; q < EPL; ++q) tl[lane / HT + RPI * q][lane % HT] = regs[q];
       wave_sync();
       if (upper) {
         for (int e = lane; e < HT * HT; e += 64) {
@@ -459,23 +538,25 @@ __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws
       if (lane < HT) {
 #pragma unroll 8
         for (int jj = 0; jj < HT; ++jj) sum = mad(tl[lane][jj], vsh[wave][0][jj], sum);
-      } else if (!diag) {
+      } else if (lane < 2 * HT && !diag) {
         const int jj = lane - HT;
 #pragma unroll 8
         for (int ii = 0; ii < HT; ++ii) sum = mad(conjg(tl[ii][jj]), vsh[wave][1][ii], sum);
       }
       if (lane < HT && wj == 1) comb[wi][lane] = sum;
-      if (lane >= HT && wi == 1) comb[2 + wj][lane - HT] = sum;
+      if (lane >= HT && lane < 2 * HT && wi == 1) comb[2 + wj][lane - HT] = sum;
       __syncthreads();
       if (lane < HT && wj == 0) {
         int r = rowbase + lane;
         if (r < len) HS[(long long)SJ * len + r] = sum + comb[wi][lane];
       }
-      if (!diag && lane >= HT && wi == 0) {
+      if (!diag && lane >= HT && lane < 2 * HT && wi == 0) {
         int c = colbase + lane - HT;
         if (c < len) HS[(long long)(nst + SI) * len + c] = sum + comb[2 + wj][lane - HT];
       }
       if (diag) {
+        // this strip's part of the panel dot products (j < k - k0):
+        // TP[SI][j] = (sum_r conj(W(off+r, j)) v_r, sum_r conj(V(off+r, j)) v_r)
         const int ip = k - k0, off = k + 1, n = cur.n;
         const T* A = bufp<T>(ws, d, bufA);
         const T* Wp = bufp<T>(ws, d, bufW);
@@ -483,8 +564,8 @@ __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws
         T s1 = tzero<T>(), s2 = tzero<T>();
         if (j < ip) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int r = 64 * SI + 8 * g + q;
+          for (int q = 0; q < RPG; ++q) {
+            const int r = ST * SI + RPG * g + q;
             if (r < len) {
               const T vr = vg[r];
               s1 = mad(conjg(Wp[(long long)(off + r) * HB + j]), vr, s1);
@@ -511,7 +592,7 @@ __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws
     item = nitem;
     cur = nxt;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) regs[q] = nregs[q];
+    for (int q = 0; q < EPL; ++q) regs[q] = nregs[q];
   }
 }
 
@@ -520,6 +601,7 @@ __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws
 template <class T>
 __global__ void __launch_bounds__(256) k_tri_her2k(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
                                                    int bufW, int k0) {
+  constexpr int TT = Tiles<T>::TT;
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
@@ -529,7 +611,7 @@ __global__ void __launch_bounds__(256) k_tri_her2k(const BlockDesc* D, char* ws,
   const int c0 = k0 + kb;
   const int len = n - c0;
   if (len <= 0) return;
-  const int nt = (len + 31) / 32;
+  const int nt = (len + TT - 1) / TT;
   const int t = blockIdx.x;
   if (t >= nt * (nt + 1) / 2) return;
   int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -538,10 +620,10 @@ __global__ void __launch_bounds__(256) k_tri_her2k(const BlockDesc* D, char* ws,
   const int J = t - I * (I + 1) / 2;
   T* A = bufp<T>(ws, d, bufA);
   const T* Wp = bufp<T>(ws, d, bufW);
-  __shared__ T Vr[32][HB + 1], Wr[32][HB + 1], Vc[32][HB + 1], Wc[32][HB + 1];
-  for (int e = threadIdx.x; e < 32 * HB; e += 256) {
+  __shared__ T Vr[TT][HB + 1], Wr[TT][HB + 1], Vc[TT][HB + 1], Wc[TT][HB + 1];
+  for (int e = threadIdx.x; e < TT * HB; e += 256) {
     int rr = e / HB, j = e % HB;
-    int r = c0 + 32 * I + rr, c = c0 + 32 * J + rr;
+    int r = c0 + TT * I + rr, c = c0 + TT * J + rr;
     bool okr = r < n && j < kb, okc = c < n && j < kb;
     Vr[rr][j] = okr ? panel_v(A, n, k0, r, j) : tzero<T>();
     Wr[rr][j] = okr ? Wp[(long long)r * HB + j] : tzero<T>();
@@ -549,9 +631,9 @@ __global__ void __launch_bounds__(256) k_tri_her2k(const BlockDesc* D, char* ws,
     Wc[rr][j] = okc ? conjg(Wp[(long long)c * HB + j]) : tzero<T>();
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
-    int rr = e >> 5, cc = e & 31;
-    int r = c0 + 32 * I + rr, c = c0 + 32 * J + cc;
+  for (int e = threadIdx.x; e < TT * TT; e += 256) {
+    int rr = e / TT, cc = e % TT;
+    int r = c0 + TT * I + rr, c = c0 + TT * J + cc;
     if (r < n && c < n && c <= r) {
       T s = tzero<T>();
 #pragma unroll 8
@@ -596,14 +678,15 @@ __global__ void __launch_bounds__(256) k_larft(const BlockDesc* D, char* ws, con
   const T* A = bufp<T>(ws, d, bufA);
   const T* taus = bufp<T>(ws, d, bufTau);
   T* Tf = bufp<T>(ws, d, bufTf) + (long long)blockIdx.x * ORB * ORB;
-  __shared__ T Vs[64][ORB + 1];
+  constexpr int LR = Tiles<T>::LR;
+  __shared__ T Vs[LR][ORB + 1];
   __shared__ T G[ORB][ORB + 1];
   __shared__ T Ts[ORB][ORB + 1];
   // Gram matrix of the panel (upper part): thread t owns pairs p = t + 256 q
   T acc[4];
   for (int q = 0; q < 4; ++q) acc[q] = tzero<T>();
-  for (int r0 = k0 + 1; r0 < nr; r0 += 64) {
-    for (int l = threadIdx.x; l < 64 * ORB; l += 256) {
+  for (int r0 = k0 + 1; r0 < nr; r0 += LR) {
+    for (int l = threadIdx.x; l < LR * ORB; l += 256) {
       int rr = l / ORB, a = l % ORB;
       int r = r0 + rr;
       Vs[rr][a] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<T>();
@@ -614,7 +697,7 @@ __global__ void __launch_bounds__(256) k_larft(const BlockDesc* D, char* ws, con
       int a = p / ORB, c = p % ORB;
       if (a < c) {
         T s = acc[q];
-        for (int rr = 0; rr < 64; ++rr) s = mad(conjg(Vs[rr][a]), Vs[rr][c], s);
+        for (int rr = 0; rr < LR; ++rr) s = mad(conjg(Vs[rr][a]), Vs[rr][c], s);
         acc[q] = s;
       }
     }
@@ -644,24 +727,25 @@ __global__ void __launch_bounds__(256) k_larft(const BlockDesc* D, char* ws, con
 }
 
 // Y <- Q Y = P_0 (P_1 (... P_last Y)), P_j = I - V_j Tf_j V_j^H.  Work-group:
-// 64 columns of Y, all panels, 256 threads as (column c, group g of 4).
+// CW columns of Y, all panels, 256 threads as (column c, group g of 256/CW).
 template <class T>
 __global__ void __launch_bounds__(256) k_ormtr_blocked(const BlockDesc* D, char* ws, const int* info, int dsel,
                                                        int bufA, int bufTf, int bufY, int csel) {
+  constexpr int CW = Tiles<T>::CW, VR = Tiles<T>::VR, G = 256 / CW, NA = ORB / G;
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int nr = seldim(d, dsel);
   const int nc = seldim(d, csel);
-  const int c0 = blockIdx.x * 64;
+  const int c0 = blockIdx.x * CW;
   if (c0 >= nc || nr < 2) return;
   const T* A = bufp<T>(ws, d, bufA);
   const T* Tfb = bufp<T>(ws, d, bufTf);
   T* Y = bufp<T>(ws, d, bufY);
-  __shared__ T Vs[32][ORB + 1];
-  __shared__ T Xs[ORB * 64];        // Y chunk (32 x 64) or W (ORB x 64)
+  __shared__ T Vs[VR][ORB + 1];
+  __shared__ T Xs[ORB * CW];        // Y chunk (VR x CW) or W (ORB x CW)
   __shared__ T Ts[ORB][ORB + 1];
-  const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int cl = threadIdx.x % CW, g = threadIdx.x / CW;
   const int c = c0 + cl;
   const bool cok = c < nc;
   const int np = (nr - 1 + ORB - 1) / ORB;
@@ -670,65 +754,61 @@ __global__ void __launch_bounds__(256) k_ormtr_blocked(const BlockDesc* D, char*
     const int kb = min(ORB, nr - 1 - k0);
     const int r0 = k0 + 1;
     for (int l = threadIdx.x; l < ORB * ORB; l += 256) Ts[l / ORB][l % ORB] = Tfb[(long long)j * ORB * ORB + l];
-    // W = V^H Y  (thread holds W[a][c] for a = g + 4 i)
-    T w[8];
+    // W = V^H Y  (thread holds W[a][c] for a = g + G i)
+    T w[NA];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) w[i] = tzero<T>();
-    for (int rc0 = r0; rc0 < nr; rc0 += 32) {
+    for (int i = 0; i < NA; ++i) w[i] = tzero<T>();
+    for (int rc0 = r0; rc0 < nr; rc0 += VR) {
       __syncthreads();
-      for (int l = threadIdx.x; l < 32 * ORB; l += 256) {
+      for (int l = threadIdx.x; l < VR * ORB; l += 256) {
         int rr = l / ORB, a = l % ORB;
         int r = rc0 + rr;
         Vs[rr][a] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<T>();
       }
-      for (int l = threadIdx.x; l < 32 * 64; l += 256) {
-        int rr = l >> 6, cc = l & 63;
+      for (int l = threadIdx.x; l < VR * CW; l += 256) {
+        int rr = l / CW, cc = l % CW;
         int r = rc0 + rr;
         Xs[l] = (r < nr && c0 + cc < nc) ? Y[(long long)r * nc + c0 + cc] : tzero<T>();
       }
       __syncthreads();
 #pragma unroll 4
-      for (int rr = 0; rr < 32; ++rr) {
-        T y = Xs[rr * 64 + cl];
+      for (int rr = 0; rr < VR; ++rr) {
+        T y = Xs[rr * CW + cl];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) w[i] = mad(conjg(Vs[rr][g + 4 * i]), y, w[i]);
+        for (int i = 0; i < NA; ++i) w[i] = mad(conjg(Vs[rr][g + G * i]), y, w[i]);
       }
     }
     __syncthreads();
     // W <- Tf W
 #pragma unroll
-    for (int i = 0; i < 8; ++i) Xs[(g + 4 * i) * 64 + cl] = w[i];
+    for (int i = 0; i < NA; ++i) Xs[(g + G * i) * CW + cl] = w[i];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      int a = g + 4 * i;
+    for (int i = 0; i < NA; ++i) {
+      int a = g + G * i;
       T s = tzero<T>();
-      for (int bb = a; bb < ORB; ++bb) s = mad(Ts[a][bb], Xs[bb * 64 + cl], s);
+      for (int bb = a; bb < ORB; ++bb) s = mad(Ts[a][bb], Xs[bb * CW + cl], s);
       w[i] = s;
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 8; ++i) Xs[(g + 4 * i) * 64 + cl] = w[i];
-    __syncthreads();
-    T wc[ORB];
-#pragma unroll
-    for (int a = 0; a < ORB; ++a) wc[a] = Xs[a * 64 + cl];
-    // Y -= V W
-    for (int rc0 = r0; rc0 < nr; rc0 += 32) {
+    for (int i = 0; i < NA; ++i) Xs[(g + G * i) * CW + cl] = w[i];
+    // Y -= V W   (W read from LDS: Xs[a * CW + cl])
+    for (int rc0 = r0; rc0 < nr; rc0 += VR) {
       __syncthreads();
-      for (int l = threadIdx.x; l < 32 * ORB; l += 256) {
+      for (int l = threadIdx.x; l < VR * ORB; l += 256) {
         int rr = l / ORB, a = l % ORB;
         int r = rc0 + rr;
         Vs[rr][a] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<T>();
       }
       __syncthreads();
       if (cok) {
-        for (int rr = g; rr < 32; rr += 4) {
+        for (int rr = g; rr < VR; rr += G) {
           int r = rc0 + rr;
           if (r >= nr) break;
           T s = tzero<T>();
-#pragma unroll
-          for (int a = 0; a < ORB; ++a) s = mad(Vs[rr][a], wc[a], s);
+#pragma unroll 8
+          for (int a = 0; a < ORB; ++a) s = mad(Vs[rr][a], Xs[a * CW + cl], s);
           long long idx = (long long)r * nc + c;
           Y[idx] = Y[idx] - s;
         }
@@ -745,15 +825,17 @@ void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, 
   hipLaunchKernelGGL(k_hetrd<T>, dim3(nblk), dim3(1024), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau);
 }
 
-
 // Blocked multi-kernel reduction over the batch; falls back to the
 // one-work-group reduction when every block is small.
 template <class T>
 void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
-                     int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS) {
-  if (maxdim <= 96) {
-    launch_hetrd<T>(s, D, ws, info, nblk, maxdim, dsel, bufA, bufD, bufE, bufTau);
-    return;
+                     int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS, int bufET) {
+  constexpr int ST = 2 * Tiles<T>::HT, TT = Tiles<T>::TT;
+  if constexpr (!is_quat<T>()) {
+    if (maxdim <= 96) {
+      launch_hetrd<T>(s, D, ws, info, nblk, maxdim, dsel, bufA, bufD, bufE, bufTau);
+      return;
+    }
   }
   const size_t shm = 3 * (size_t)maxdim * sizeof(T);
   int dev = 0, ncu = 256;
@@ -762,22 +844,22 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
   for (int k0 = 0; k0 < maxdim - 1; k0 += HB) {
     const int kbmax = std::min(HB, maxdim - 1 - k0);
     hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufW,
-                       bufV, bufHS, k0, 0, 0);
+                       bufV, bufHS, bufET, k0, 0, 0);
     for (int i = 0; i < kbmax; ++i) {
       const int k = k0 + i;
       const int len = maxdim - k - 1;
-      const int nst = (len + 63) / 64;
+      const int nst = (len + ST - 1) / ST;
       const int nsmax = nst * (nst + 1) / 2;
       const long long items = (long long)nsmax * nblk;
       const int grid = (int)std::min<long long>(items, (long long)mv_grid);
       hipLaunchKernelGGL(k_tri_matvec<T>, dim3(grid), dim3(256), 0, s, D, ws, info, dsel, bufA, bufV, bufHS, bufW,
                          k0, k, nblk, nsmax);
       hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau,
-                         bufW, bufV, bufHS, k0, i + 1, (i + 1 < kbmax) ? 1 : 2);
+                         bufW, bufV, bufHS, bufET, k0, i + 1, (i + 1 < kbmax) ? 1 : 2);
     }
     const int len2 = maxdim - (k0 + kbmax);
     if (len2 > 0) {
-      const int nt2 = (len2 + 31) / 32;
+      const int nt2 = (len2 + TT - 1) / TT;
       hipLaunchKernelGGL(k_tri_her2k<T>, dim3(nt2 * (nt2 + 1) / 2, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
                          bufW, k0);
     }
@@ -785,9 +867,11 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
   hipLaunchKernelGGL(k_tri_last<T>, dim3((nblk + 255) / 256), dim3(256), 0, s, D, ws, info, nblk, dsel, bufA, bufD);
 }
 template void launch_hetrd_mk<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                      int, int, int, int);
+                                      int, int, int, int, int);
 template void launch_hetrd_mk<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                    int, int, int, int);
+                                    int, int, int, int, int);
+template void launch_hetrd_mk<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
+                                    int, int, int, int, int);
 
 template <class T>
 void launch_ormtr_blocked(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim,
@@ -795,12 +879,15 @@ void launch_ormtr_blocked(hipStream_t s, const BlockDesc* D, char* ws, const int
   int np = (maxdim - 1 + ORB - 1) / ORB;
   if (np < 1) np = 1;
   hipLaunchKernelGGL(k_larft<T>, dim3(np, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA, bufTau, bufTf);
-  hipLaunchKernelGGL(k_ormtr_blocked<T>, dim3((maxcols + 63) / 64, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
+  constexpr int CW = Tiles<T>::CW;
+  hipLaunchKernelGGL(k_ormtr_blocked<T>, dim3((maxcols + CW - 1) / CW, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
                      bufTf, bufY, csel);
 }
 template void launch_ormtr_blocked<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int,
                                            int, int, int, int);
 template void launch_ormtr_blocked<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int,
+                                         int, int, int, int);
+template void launch_ormtr_blocked<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int,
                                          int, int, int, int);
 template void launch_hetrd<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
                                    int);

@@ -4,7 +4,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -62,9 +64,20 @@ void block_sizes(int N, bool tc, size_t sz[NBUF]) {
   sz[Q_FAC] = (size_t)QMAX * n * 2 * 8;
   sz[W_TF4] = ((m - 1 + 31) / 32 + 1) * 32 * 32 * es;
   sz[W_TFQ] = ((n - 1 + 31) / 32 + 1) * 32 * 32 * es;
+  if (tc) {
+    // quaternion reduction of the n x n (4c) and N x N (renormalisation) forms
+    sz[W_TF4] = std::max<size_t>(sz[W_TF4], ((n - 1 + 31) / 32 + 1) * 32 * 32 * 32);
+    sz[W_TFQ] = std::max<size_t>(sz[W_TFQ], ((n / 2 - 1 + 31) / 32 + 1) * 32 * 32 * 32 + 32);
+  }
   sz[W_PAN] = m * 32 * es;
   const size_t nst = (m + 63) / 64;
   sz[W_HS] = (2 * nst * m + nst * 32 * 2) * es;
+  if (tc) {
+    const size_t nsq = (n + 31) / 32;     // quaternion strips of 32
+    sz[W_HS] = std::max<size_t>(sz[W_HS], (2 * nsq * n + nsq * 32 * 2) * 32);
+  }
+  sz[V_ET] = n * 32;
+  sz[V_DEL] = n * 32;
   sz[W_VCUR] = m * es;
 }
 
@@ -74,6 +87,7 @@ bool valid_opts(const x2c_options* o) {
   if (o->prec != X2C_FP64 && o->prec != X2C_SPLIT_BF16) return false;
   if (!(o->c > 0.0) || !std::isfinite(o->c)) return false;
   if (o->ozaki_slices < 0 || o->ozaki_slices > 16) return false;
+  if (o->reduction != X2C_RED_QUATERNION && o->reduction != X2C_RED_COMPLEX) return false;
   return true;
 }
 
@@ -232,6 +246,7 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   const int maxN = L.maxN, maxn = L.maxn, maxm = L.maxm;
   const T one = tcast<T>(1.0), zero = tcast<T>(0.0);
   const int OPN = 0, OPH = 1;
+  const bool kramers = tc && o->reduction == X2C_RED_QUATERNION;
 
   {
     STAGE("prep");
@@ -252,30 +267,54 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
       launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LTI, OPN, R_W0 + q, OPN, R_TMP, 1.0, 0.0);
       launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LTI, OPH, R_WR0 + q, 1.0, 0.0);
     }
-    launch_assemble_A<T>(s, D, ws, info, nblk, maxm, c);
+    if (!kramers) launch_assemble_A<T>(s, D, ws, info, nblk, maxm, c);
+    else launch_assemble_Aq(s, D, ws, info, nblk, maxn, c);
   }
-  // positive-energy branch of the reduced 4c matrix
-  {
-    STAGE("tridiag_4c");
-    launch_hetrd_mk<T>(s, D, ws, info, nblk, maxm, DIM_m, C_A, V_D, V_E, V_TAU, W_PAN, W_VCUR, W_HS);
-  }
-  {
-    STAGE("branch_4c");
-    launch_tri_eig4c(s, D, ws, info, nblk, maxm, eps, c);
-  }
-  {
-    STAGE("projector_4c");
-    launch_filter_factor(s, D, ws, info, nblk);
-    launch_filter_solve<T>(s, D, ws, info, nblk, maxn);
-  }
-  {
-    STAGE("backtransform_4c");
-    launch_ormtr_blocked<T>(s, D, ws, info, nblk, maxm, maxn, DIM_m, C_A, V_TAU, W_TF4, C_Y, DIM_n);
+  if (!kramers) {
+    // positive-energy branch of the reduced 4c matrix (complex m x m form)
+    {
+      STAGE("tridiag_4c");
+      launch_hetrd_mk<T>(s, D, ws, info, nblk, maxm, DIM_m, C_A, V_D, V_E, V_TAU, W_PAN, W_VCUR, W_HS, V_ET);
+    }
+    {
+      STAGE("branch_4c");
+      launch_tri_eig4c(s, D, ws, info, nblk, maxm, eps, c, 0);
+    }
+    {
+      STAGE("projector_4c");
+      launch_filter_factor(s, D, ws, info, nblk, 0);
+      launch_filter_solve<T>(s, D, ws, info, nblk, maxn, 0);
+    }
+    {
+      STAGE("backtransform_4c");
+      launch_ormtr_blocked<T>(s, D, ws, info, nblk, maxm, maxn, DIM_m, C_A, V_TAU, W_TF4, C_Y, DIM_n);
+    }
+  } else {
+    // the same on the quaternion n x n form (time-reversal structure)
+    {
+      STAGE("tridiag_4c");
+      launch_hetrd_mk<quat>(s, D, ws, info, nblk, maxn, DIM_n, C_A, V_D, V_E, V_TAU, W_PAN, W_VCUR, W_HS, V_ET);
+      launch_phase_q(s, D, ws, info, nblk, DIM_n);
+    }
+    {
+      STAGE("branch_4c");
+      launch_tri_eig4c(s, D, ws, info, nblk, maxn, eps, c, 1);
+    }
+    {
+      STAGE("projector_4c");
+      launch_filter_factor(s, D, ws, info, nblk, 1);
+      launch_filter_solve<quat>(s, D, ws, info, nblk, maxn / 2, 1);
+    }
+    {
+      STAGE("backtransform_4c");
+      launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxn, maxN, DIM_n, C_A, V_TAU, W_TF4, C_Y, DIM_N);
+      launch_quat_to_cplx_Y(s, D, ws, info, nblk, maxn);
+    }
   }
   {
     // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
     STAGE("x_solve");
-    launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn);
+    launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn, kramers ? C_A : C_Y);
     launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, OPN, C_LS, OPH, C_TMP2, one, zero);
     launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LTI, OPH, C_TMP2, OPN, C_X,
                    tcast<T>(std::sqrt(2.0) * c), zero);
@@ -297,18 +336,38 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
     launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LSI, OPN, C_Q, OPN, C_TMP, one, zero);
     launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, OPN, C_LSI, OPH, C_Q, one, zero);
   }
-  {
-    STAGE("tridiag_Q");
-    launch_hetrd_mk<T>(s, D, ws, info, nblk, maxn, DIM_n, C_Q, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS);
-  }
-  {
-    // Q^-1/2 = Q_h F Q_h^H, F = T_Q^-1/2 by quadrature
-    STAGE("invsqrt_Q");
-    launch_tri_eig_q(s, D, ws, info, nblk, maxn);
-    launch_invsqrt_cols<T>(s, D, ws, info, nblk, maxn);
-    launch_ormtr_blocked<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, W_TFQ, C_TMP, DIM_n);
-    launch_conj_transpose<T>(s, D, ws, info, nblk, maxn, C_TMP, C_QMH);
-    launch_ormtr_blocked<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, W_TFQ, C_QMH, DIM_n);
+  if (!kramers) {
+    {
+      STAGE("tridiag_Q");
+      launch_hetrd_mk<T>(s, D, ws, info, nblk, maxn, DIM_n, C_Q, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS, V_ET);
+    }
+    {
+      // Q^-1/2 = Q_h F Q_h^H, F = T_Q^-1/2 by quadrature
+      STAGE("invsqrt_Q");
+      launch_tri_eig_q(s, D, ws, info, nblk, maxn, DIM_n);
+      launch_invsqrt_cols<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP2);
+      launch_ormtr_blocked<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, W_TFQ, C_TMP, DIM_n);
+      launch_conj_transpose<T>(s, D, ws, info, nblk, maxn, C_TMP, C_QMH);
+      launch_ormtr_blocked<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, W_TFQ, C_QMH, DIM_n);
+    }
+  } else {
+    {
+      STAGE("tridiag_Q");
+      launch_cplx_to_quat(s, D, ws, info, nblk, maxN, C_Q, C_TMP2);
+      launch_hetrd_mk<quat>(s, D, ws, info, nblk, maxN, DIM_N, C_TMP2, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS,
+                            V_ET);
+      launch_phase_q(s, D, ws, info, nblk, DIM_N);
+    }
+    {
+      // Q^-1/2 = (Q_h D) F (Q_h D)^H on the quaternion N x N form
+      STAGE("invsqrt_Q");
+      launch_tri_eig_q(s, D, ws, info, nblk, maxN, DIM_N);
+      launch_invsqrt_cols<quat>(s, D, ws, info, nblk, maxN, DIM_N, C_QMH);
+      launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxN, maxN, DIM_N, C_TMP2, V_TAUQ, W_TFQ, C_TMP, DIM_N);
+      launch_qct_scale(s, D, ws, info, nblk, maxN, C_TMP, C_LR);
+      launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxN, maxN, DIM_N, C_TMP2, V_TAUQ, W_TFQ, C_LR, DIM_N);
+      launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_LR, C_QMH);
+    }
   }
   {
     // R = L_S^-H Q^-1/2 L_S^H

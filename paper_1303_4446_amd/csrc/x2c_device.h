@@ -44,15 +44,43 @@ __device__ inline cplx mad(cplx a, cplx b, cplx c) {
 __device__ inline cplx mad(double a, cplx b, cplx c) { return {fma(a, b.x, c.x), fma(a, b.y, c.y)}; }
 __device__ inline cplx mad(cplx a, double b, cplx c) { return {fma(a.x, b, c.x), fma(a.y, b, c.y)}; }
 
+// ---------------------------------------------------------------- quaternions
+// q = a + b j with complex a, b (j z = conj(z) j).  A time-reversal symmetric
+// two-component operator [[A, B], [-B*, A*]] (Sec. III.A) is the quaternion
+// matrix A + B j; q corresponds to the 2x2 complex block [[a, b], [-b*, a*]].
+struct quat {
+  cplx a, b;
+};
+__host__ __device__ inline quat operator+(quat x, quat y) { return {x.a + y.a, x.b + y.b}; }
+__host__ __device__ inline quat operator-(quat x, quat y) { return {x.a - y.a, x.b - y.b}; }
+__host__ __device__ inline quat operator-(quat x) { return {-x.a, -x.b}; }
+// (a1 + b1 j)(a2 + b2 j) = (a1 a2 - b1 conj(b2)) + (a1 b2 + b1 conj(a2)) j
+__host__ __device__ inline quat operator*(quat x, quat y) {
+  cplx b2c = {y.b.x, -y.b.y}, a2c = {y.a.x, -y.a.y};
+  return {x.a * y.a - x.b * b2c, x.a * y.b + x.b * a2c};
+}
+__host__ __device__ inline quat operator*(double s, quat x) { return {s * x.a, s * x.b}; }
+__host__ __device__ inline quat operator*(quat x, double s) { return {s * x.a, s * x.b}; }
+__host__ __device__ inline quat conjg(quat x) { return {{x.a.x, -x.a.y}, {-x.b.x, -x.b.y}}; }
+__host__ __device__ inline double re(quat x) { return x.a.x; }
+__host__ __device__ inline double im(quat x) { return x.a.y; }
+__host__ __device__ inline double abs2(quat x) { return abs2(x.a) + abs2(x.b); }
+__host__ __device__ inline double abs1(quat x) { return abs1(x.a) + abs1(x.b); }
+__device__ inline quat mad(quat x, quat y, quat c) { return c + x * y; }
+__device__ inline quat mad(double s, quat y, quat c) { return {mad(s, y.a, c.a), mad(s, y.b, c.b)}; }
+
 template <class T> __host__ __device__ inline T tzero();
 template <> __host__ __device__ inline double tzero<double>() { return 0.0; }
 template <> __host__ __device__ inline cplx tzero<cplx>() { return {0.0, 0.0}; }
+template <> __host__ __device__ inline quat tzero<quat>() { return {{0.0, 0.0}, {0.0, 0.0}}; }
 template <class T> __host__ __device__ inline T treal(double a);
 template <> __host__ __device__ inline double treal<double>(double a) { return a; }
 template <> __host__ __device__ inline cplx treal<cplx>(double a) { return {a, 0.0}; }
+template <> __host__ __device__ inline quat treal<quat>(double a) { return {{a, 0.0}, {0.0, 0.0}}; }
 template <class T> __host__ __device__ inline T tmake(double a, double b);
 template <> __host__ __device__ inline double tmake<double>(double a, double) { return a; }
 template <> __host__ __device__ inline cplx tmake<cplx>(double a, double b) { return {a, b}; }
+template <> __host__ __device__ inline quat tmake<quat>(double a, double b) { return {{a, b}, {0.0, 0.0}}; }
 
 __device__ inline cplx cdiv(cplx a, cplx b) {
   // Smith's algorithm
@@ -93,6 +121,8 @@ enum Buf : int {
   W_HS,
   // current reflector of the blocked tridiagonalisation (m)
   W_VCUR,
+  // quaternion path: sub-diagonal quaternions and the phases making them real
+  V_ET, V_DEL,
   NBUF
 };
 

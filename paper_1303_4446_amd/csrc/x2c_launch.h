@@ -38,21 +38,33 @@ void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, 
 
 template <class T>
 void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
-                     int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS);
+                     int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS, int bufET);
 template <class T>
 void launch_ormtr_blocked(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim,
                           int maxcols, int dsel, int bufA, int bufTau, int bufTf, int bufY, int csel);
 
 void launch_tri_eig4c(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxm, double* eps,
-                      double c);
-void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk);
+                      double c, int kramers);
+void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int kramers);
 template <class T>
-void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn);
-void launch_tri_eig_q(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn);
+void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxrhs,
+                         int kramers);
+void launch_tri_eig_q(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxdim, int dsel);
 template <class T>
-void launch_invsqrt_cols(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn);
+void launch_invsqrt_cols(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
+                         int bufScr);
+
+void launch_assemble_Aq(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, double c);
+void launch_phase_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int dsel);
+void launch_quat_to_cplx_Y(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn);
+void launch_cplx_to_quat(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
+                         int dst);
+void launch_quat_to_cplx(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
+                         int dst);
+void launch_qct_scale(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
+                      int dst);
 
 template <class T>
-void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn);
+void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn, int bufY);
 
 }  // namespace x2c

@@ -44,8 +44,13 @@ def test_workspace_query_and_limits():
     opt = _lib.options(True, -1.0)
     N = (ctypes.c_int * 1)(10)
     assert lib.x2c_workspace_bytes(ctypes.byref(opt), 1, N) == 0
-    opt = _lib._Options(7, 0, 0, 137.0)
+    opt = _lib._Options(7, 0, 0, 137.0, 0)
     assert lib.x2c_workspace_bytes(ctypes.byref(opt), 1, N) == 0
+    opt = _lib.options(True, 137.0, reduction=2)      # unknown reduction
+    assert lib.x2c_workspace_bytes(ctypes.byref(opt), 1, N) == 0
+    for red in (px.RED_QUATERNION, px.RED_COMPLEX):
+        opt = _lib.options(True, 137.0, reduction=red)
+        assert lib.x2c_workspace_bytes(ctypes.byref(opt), 1, N) > 0
     # empty batch needs no workspace
     opt = _lib.options(True, 137.0)
     assert lib.x2c_workspace_bytes(ctypes.byref(opt), 0, N) == 0

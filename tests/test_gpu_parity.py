@@ -1,14 +1,18 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
-Tolerances (derived in the design doc):
+Tolerances (derived from the arithmetic of the path):
   * h elementwise:  |h - h_oracle| <= TOL_H * max|h_oracle|, TOL_H = 2e-10
     (unit roundoff times kappa(L_T) <= 2.1e6 for the stiffest Z=79 block).
   * eps (GPU bisection vs the oracle's generalized eigensolve):
     |d eps| <= 1e-12 * max|eps|.
   * spectrum of the GPU h with metric S vs the oracle's positive-energy 4c
     eigenvalues (Eq. 2ceoeq vs Eq. moddiraceq): <= 1e-8 Eh on the bound
-    states of the Z=47 (silver) workloads; elsewhere, and on all states,
-    <= max(1e-8 Eh, 10 x the oracle's own floor on the same states).
+    states of the Z=47 (silver) workloads; elsewhere <= max(1e-8 Eh, 10 x the
+    oracle's own floor on the same states).  On every state (continuum
+    included) the larger of that and REL_DE_ALL * |eps_4c|: by the
+    Hermitian perturbation (Weyl) bound the h tolerance alone already
+    admits |dE| up to TOL_H * max|h|, about 1e-4 Eh for the tightest states,
+    so a per-state relative bound of 1e-12 is far stricter than the h test.
 """
 import numpy as np
 import pytest
@@ -24,6 +28,7 @@ pytestmark = pytest.mark.gpu
 TOL_H = 2e-10
 TOL_EPS = 1e-12
 DE_BOUND = 1e-8
+REL_DE_ALL = 1e-12
 
 
 def _px():
@@ -34,20 +39,20 @@ def _px():
     return px, torch
 
 
-def gpu_single(S, T, V, W, c, twocomp, prec=0):
+def gpu_single(S, T, V, W, c, twocomp, prec=0, reduction=0):
     px, torch = _px()
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
-    print(f"  x2c_build N={S.shape[0]} twocomp={twocomp} c={c}", flush=True)
-    h, eps = px.build(d(S), d(T), d(V), d(W), c, twocomp, prec=prec)
+    print(f"  x2c_build N={S.shape[0]} twocomp={twocomp} c={c} reduction={reduction}", flush=True)
+    h, eps = px.build(d(S), d(T), d(V), d(W), c, twocomp, prec=prec, reduction=reduction)
     return h.cpu().numpy(), eps.cpu().numpy()
 
 
-def gpu_batched(blocks, twocomp, c=C_LIGHT, prec=0):
+def gpu_batched(blocks, twocomp, c=C_LIGHT, prec=0, reduction=0):
     px, torch = _px()
     pk = pack_blocks(blocks, twocomp)
     bt = px.batch_to_device(pk, twocomp)
-    print(f"  x2c_build_batched nblk={len(blocks)} twocomp={twocomp}", flush=True)
-    (h, eps, info), _ = px.build_batched(bt, c, prec=prec)
+    print(f"  x2c_build_batched nblk={len(blocks)} twocomp={twocomp} reduction={reduction}", flush=True)
+    (h, eps, info), _ = px.build_batched(bt, c, prec=prec, reduction=reduction)
     torch.cuda.synchronize()
     hs = px.unpack_h(h.cpu().numpy(), bt.Ns, twocomp)
     eps = eps.cpu().numpy()
@@ -71,7 +76,10 @@ def check_against_oracle(S, T, V, W, c, twocomp, h, eps, strict_bound=False):
     if bd.any():
         lim = DE_BOUND if strict_bound else max(DE_BOUND, 10 * f[bd].max())
         assert de[bd].max() <= lim, f"bound-state dE {de[bd].max():.3e} (oracle floor {f[bd].max():.3e})"
-    assert de.max() <= max(DE_BOUND, 10 * f.max()), f"dE all {de.max():.3e} floor {f.max():.3e}"
+    lim_all = np.maximum(max(DE_BOUND, 10 * f.max()), REL_DE_ALL * np.abs(e4))
+    worst = int(np.argmax(de / lim_all))
+    assert np.all(de <= lim_all), (f"dE all {de[worst]:.3e} at eps {e4[worst]:.6e} "
+                                   f"(limit {lim_all[worst]:.3e}, floor {f.max():.3e})")
     return err_h, de
 
 
@@ -188,6 +196,31 @@ def test_ag309_full_batch_sampled():
         blk = blocks[int(i)]
         print(f"  oracle check block {int(i)}", flush=True)
         check_against_oracle(blk.S, blk.T, blk.V, blk.W, C_LIGHT, True, hs[i], eps[i], strict_bound=True)
+
+
+@pytest.mark.parametrize("N,seed", [(3, 2), (5, 4)])
+def test_tiny_random_complex_reduction(N, seed):
+    S, T, V, W = random_spd_problem(N, seed, True)
+    h, eps = gpu_single(S, T, V, W, 7.0, True, reduction=1)
+    check_against_oracle(S, T, V, W, 7.0, True, h, eps)
+
+
+def test_complex_and_quaternion_reductions_agree():
+    """Both reductions of the two-component eigenproblems on uneven blocks
+    (several tiles and ragged tails in both dimensions): each meets the
+    oracle, and the two h agree to the h tolerance."""
+    blocks = [atom_block(z) for z in (1, 17, 47, 79)]
+    res = {red: gpu_batched(blocks, True, reduction=red) for red in (0, 1)}
+    for red in (0, 1):
+        assert np.all(res[red][2] == 0)
+    for i, blk in enumerate(blocks):
+        hq, hc = res[0][0][i], res[1][0][i]
+        assert np.abs(hq - hc).max() <= TOL_H * np.abs(hc).max()
+        assert np.abs(res[0][1][i] - res[1][1][i]).max() <= TOL_EPS * np.abs(res[1][1][i]).max()
+    for i in (1, 3):
+        blk = blocks[i]
+        print(f"  oracle check Z={(1, 17, 47, 79)[i]} complex reduction", flush=True)
+        check_against_oracle(blk.S, blk.T, blk.V, blk.W, C_LIGHT, True, res[1][0][i], res[1][1][i])
 
 
 def test_determinism_two_calls():
