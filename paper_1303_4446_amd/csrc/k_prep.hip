@@ -54,8 +54,13 @@ __global__ void k_unpack(const BlockDesc* D, char* ws, int* info, const double* 
   if (bad) info[blockIdx.y] = 6;
 }
 
-// Right-looking Cholesky S = L L^T (lower, row-major, in place) of the real
-// N x N matrix; one work-group per (block, matrix).  grid = (2, nblk).
+// Cholesky S = L L^T (lower, row-major, in place) of the real N x N matrix,
+// left-looking by panels of PB columns; one work-group per (block, matrix),
+// grid = (2, nblk).  The panel (rows p0.., PB columns) lives in LDS: it is
+// first updated with every finished column (k < p0, staged PK at a time),
+// then factored column by column.
+constexpr int PB = 32, PK = 64;
+
 __global__ void __launch_bounds__(256) k_potrf(const BlockDesc* D, char* ws, int* info) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
@@ -63,39 +68,69 @@ __global__ void __launch_bounds__(256) k_potrf(const BlockDesc* D, char* ws, int
   const int which = blockIdx.x;
   const int N = d.N;
   double* A = bufp<double>(ws, d, which == 0 ? R_LS : R_LT);
-  __shared__ double col[1024];
+  extern __shared__ double sm[];
+  double* P = sm;                           // N x (PB + 1)
+  double* Lt = sm + (size_t)N * (PB + 1);   // PB x (PK + 1)
   __shared__ int fail;
-  if (threadIdx.x == 0) fail = 0;
-  __syncthreads();
-  for (int j = 0; j < N; ++j) {
-    double ajj = A[(long long)j * N + j];
-    if (!(ajj > 0.0) || !isfinite(ajj)) {
-      if (threadIdx.x == 0) fail = 1;
-      __syncthreads();
-      break;
+  __shared__ double piv;
+  const int t = threadIdx.x, c = t & (PB - 1), g = t >> 5;
+  if (t == 0) fail = 0;
+  for (int p0 = 0; p0 < N; p0 += PB) {
+    const int nb = min(PB, N - p0), rows = N - p0;
+    for (int e = t; e < rows * PB; e += 256) {
+      const int r = e / PB, cc = e % PB;
+      P[r * (PB + 1) + cc] = (cc < nb && cc <= r) ? A[(long long)(p0 + r) * N + p0 + cc] : 0.0;
     }
-    double ljj = sqrt(ajj);
-    double inv = 1.0 / ljj;
-    for (int i = j + 1 + threadIdx.x; i < N; i += blockDim.x) {
-      double lij = A[(long long)i * N + j] * inv;
-      A[(long long)i * N + j] = lij;
-      col[i] = lij;
+    for (int kc = 0; kc < p0; kc += PK) {
+      const int kn = min(PK, p0 - kc);
+      __syncthreads();
+      for (int e = t; e < PB * PK; e += 256) {
+        const int cc = e / PK, kk = e % PK;
+        Lt[cc * (PK + 1) + kk] = (cc < nb && kk < kn) ? A[(long long)(p0 + cc) * N + kc + kk] : 0.0;
+      }
+      __syncthreads();
+      if (c < nb) {
+        for (int r = g; r < rows; r += 8) {
+          if (c > r) continue;
+          const double* Lr = A + (long long)(p0 + r) * N + kc;
+          double acc = 0.0;
+          for (int kk = 0; kk < kn; ++kk) acc = fma(Lr[kk], Lt[c * (PK + 1) + kk], acc);
+          P[r * (PB + 1) + c] -= acc;
+        }
+      }
     }
     __syncthreads();
-    if (threadIdx.x == 0) A[(long long)j * N + j] = ljj;
-    // trailing update of the lower triangle: A[i][k] -= L[i][j] L[k][j], j < k <= i
-    const int len = N - j - 1;
-    const long long tot = (long long)len * len;
-    for (long long t = threadIdx.x; t < tot; t += blockDim.x) {
-      int i = j + 1 + (int)(t / len);
-      int k = j + 1 + (int)(t % len);
-      if (k <= i) A[(long long)i * N + k] -= col[i] * col[k];
+    for (int j = 0; j < nb; ++j) {
+      if (t == 0) {
+        const double a = P[j * (PB + 1) + j];
+        if (!(a > 0.0) || !isfinite(a)) {
+          fail = 1;
+        } else {
+          piv = sqrt(a);
+          P[j * (PB + 1) + j] = piv;
+        }
+      }
+      __syncthreads();
+      if (fail) break;
+      const double inv = 1.0 / piv;
+      for (int r = j + 1 + t; r < rows; r += 256) P[r * (PB + 1) + j] *= inv;
+      __syncthreads();
+      for (int e = t; e < rows * PB; e += 256) {
+        const int r = e / PB, cc = e % PB;
+        if (cc > j && cc < nb && r >= cc) P[r * (PB + 1) + cc] -= P[r * (PB + 1) + j] * P[cc * (PB + 1) + j];
+      }
+      __syncthreads();
+    }
+    if (fail) break;
+    for (int e = t; e < rows * PB; e += 256) {
+      const int r = e / PB, cc = e % PB;
+      if (cc < nb && cc <= r) A[(long long)(p0 + r) * N + p0 + cc] = P[r * (PB + 1) + cc];
     }
     __syncthreads();
   }
   if (fail) {
     // S failing takes precedence over T failing, whichever work-group ends first
-    if (threadIdx.x == 0) {
+    if (t == 0) {
       if (which == 0) atomicExch(&info[b], 1);
       else atomicCAS(&info[b], 0, 2);
     }
@@ -103,30 +138,56 @@ __global__ void __launch_bounds__(256) k_potrf(const BlockDesc* D, char* ws, int
   }
   // zero the strict upper triangle
   const long long NN = (long long)N * N;
-  for (long long t = threadIdx.x; t < NN; t += blockDim.x) {
-    int i = (int)(t / N), k = (int)(t % N);
-    if (k > i) A[t] = 0.0;
+  for (long long e = t; e < NN; e += blockDim.x) {
+    const int i = (int)(e / N), k = (int)(e % N);
+    if (k > i) A[e] = 0.0;
   }
 }
 
-// Inverse of a real lower-triangular matrix by column forward substitution;
-// thread j computes column j.  grid = (2, nblk): (L_S, L_T).
+// Inverse X = L^-1 of a real lower-triangular matrix, PB columns per
+// work-group (grid = (ceil(N / PB), 2, nblk)).  Rows are taken PB at a time:
+// the contribution of the rows already solved is a dense product (all
+// threads), the PB x PB diagonal block a short forward substitution.
 __global__ void __launch_bounds__(256) k_trtri(const BlockDesc* D, char* ws, const int* info) {
-  const int b = blockIdx.y;
+  const int b = blockIdx.z;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int N = d.N;
-  const double* L = bufp<double>(ws, d, blockIdx.x == 0 ? R_LS : R_LT);
-  double* X = bufp<double>(ws, d, blockIdx.x == 0 ? R_LSI : R_LTI);
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    for (int i = 0; i < j; ++i) X[(long long)i * N + j] = 0.0;
-    X[(long long)j * N + j] = 1.0 / L[(long long)j * N + j];
-    for (int i = j + 1; i < N; ++i) {
-      double s = 0.0;
-      const double* Li = L + (long long)i * N;
-      for (int k = j; k < i; ++k) s = fma(Li[k], X[(long long)k * N + j], s);
-      X[(long long)i * N + j] = -s / Li[i];
+  const int j0 = blockIdx.x * PB;
+  if (j0 >= N) return;
+  const double* L = bufp<double>(ws, d, blockIdx.y == 0 ? R_LS : R_LT);
+  double* X = bufp<double>(ws, d, blockIdx.y == 0 ? R_LSI : R_LTI);
+  extern __shared__ double sm[];
+  double* xs = sm;                                  // rows j0.. x (PB + 1)
+  double* U = sm + (size_t)(N - j0) * (PB + 1);     // PB x (PB + 1)
+  const int t = threadIdx.x, c = t & (PB - 1), g = t >> 5;
+  const int nc = min(PB, N - j0);
+  for (int i0 = j0; i0 < N; i0 += PB) {
+    const int ib = min(PB, N - i0);
+#pragma unroll
+    for (int q = 0; q < PB / 8; ++q) {
+      const int ii = g + 8 * q;
+      if (ii < ib) {
+        const double* Li = L + (long long)(i0 + ii) * N;
+        double acc = 0.0;
+        for (int k = j0; k < i0; ++k) acc = fma(Li[k], xs[(k - j0) * (PB + 1) + c], acc);
+        U[ii * (PB + 1) + c] = acc;
+      }
     }
+    __syncthreads();
+    if (t < PB) {
+      for (int ii = 0; ii < ib; ++ii) {
+        const double* Li = L + (long long)(i0 + ii) * N;
+        double acc = ((i0 + ii) == (j0 + c) ? 1.0 : 0.0) - U[ii * (PB + 1) + c];
+        for (int kk = 0; kk < ii; ++kk) acc = fma(-Li[i0 + kk], xs[(i0 + kk - j0) * (PB + 1) + c], acc);
+        xs[(i0 + ii - j0) * (PB + 1) + c] = acc / Li[i0 + ii];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < N * PB; e += 256) {
+    const int i = e / PB, cc = e % PB;
+    if (cc < nc) X[(long long)i * N + j0 + cc] = i < j0 ? 0.0 : xs[(i - j0) * (PB + 1) + cc];
   }
 }
 
@@ -323,11 +384,15 @@ void launch_unpack(hipStream_t s, const BlockDesc* D, char* ws, int* info, int n
   if (gx > 64) gx = 64;
   hipLaunchKernelGGL(k_unpack, dim3(gx, nblk), dim3(256), 0, s, D, ws, info, S, T, V, W, twocomp);
 }
-void launch_potrf(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk) {
-  hipLaunchKernelGGL(k_potrf, dim3(2, nblk), dim3(256), 0, s, D, ws, info);
+void launch_potrf(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN) {
+  const size_t shm = ((size_t)maxN * (PB + 1) + (size_t)PB * (PK + 1)) * sizeof(double);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_potrf), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_potrf, dim3(2, nblk), dim3(256), shm, s, D, ws, info);
 }
-void launch_trtri(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk) {
-  hipLaunchKernelGGL(k_trtri, dim3(2, nblk), dim3(256), 0, s, D, ws, info);
+void launch_trtri(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN) {
+  const size_t shm = ((size_t)maxN * (PB + 1) + (size_t)PB * (PB + 1)) * sizeof(double);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trtri), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_trtri, dim3((maxN + PB - 1) / PB, 2, nblk), dim3(256), shm, s, D, ws, info);
 }
 static int grid_for(long long elems) {
   long long g = (elems + 255) / 256;

@@ -22,6 +22,16 @@
 
 namespace x2c {
 
+// 1/q from the hardware reciprocal estimate refined by two Newton steps
+// (error a few ulp; |q| >= pivmin keeps it finite)
+__device__ inline double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  double e = fma(-q, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-q, r, 1.0);
+  return fma(r, e, r);
+}
+
 // number of eigenvalues of tridiag(d, e) below x (e2 = e^2)
 __device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
   int cnt = 0;
@@ -29,25 +39,53 @@ __device__ inline int sturm_count(const double* d, const double* e2, int n, doub
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += q < 0.0;
   for (int i = 1; i < n; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
+    q = (d[i] - x) - e2[i - 1] * recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
   return cnt;
 }
 
-// idx-th smallest eigenvalue (0-based) by bisection in [lo, hi]
-__device__ inline double bisect(const double* d, const double* e2, int n, int idx, double lo, double hi,
-                                double pivmin) {
-  double a = lo, b = hi;
-  for (int it = 0; it < 256; ++it) {
-    double mid = 0.5 * (a + b);
-    if (!(mid > a && mid < b)) break;
-    if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b))) break;
-    if (sturm_count(d, e2, n, mid, pivmin) > idx) b = mid;
-    else a = mid;
+// Eigenvalues idx0 + k (k < ne, ascending indices) of tridiag(d, e) by
+// multisection over the whole work-group: the threads form groups of
+// P = blockDim / ne (at least 1); each group splits its eigenvalue's bracket
+// into P + 1 parts per step with one Sturm count per thread.  cbuf / xbuf:
+// blockDim ints / doubles of LDS.  Every thread must call it.
+__device__ void multisect(const double* d, const double* e2, int m, int idx0, int ne, double lo, double hi,
+                          double piv, double* out, int* cbuf, double* xbuf) {
+  const int P = max(1, (int)blockDim.x / max(ne, 1));
+  const int G = blockDim.x / P;
+  const int grp = threadIdx.x / P, p = threadIdx.x - grp * P;
+  for (int base = 0; base < ne; base += G) {
+    const int k = base + grp;
+    const bool act = grp < G && k < ne;
+    const int idx = idx0 + k;
+    double a = lo, b = hi;
+    for (int it = 0; it < 200; ++it) {
+      // converged once the bracket is relatively tight or cannot be split
+      const double mid = 0.5 * (a + b);
+      const bool live = act && mid > a && mid < b && (b - a > 2.2e-16 * fmax(fabs(a), fabs(b)));
+      const double x = a + (b - a) * ((double)(p + 1) / (double)(P + 1));
+      cbuf[threadIdx.x] = live ? sturm_count(d, e2, m, x, piv) : 0;
+      xbuf[threadIdx.x] = x;
+      __syncthreads();
+      if (live) {
+        double na = a, nb = b;
+        for (int q = 0; q < P; ++q) {
+          if (cbuf[grp * P + q] > idx) {
+            nb = xbuf[grp * P + q];
+            break;
+          }
+          na = xbuf[grp * P + q];
+        }
+        a = na;
+        b = nb;
+      }
+      if (!__syncthreads_or(live)) break;
+    }
+    if (act && p == 0) out[k] = 0.5 * (a + b);
+    __syncthreads();
   }
-  return 0.5 * (a + b);
 }
 
 // Gershgorin bounds of tridiag(d, e); block-wide
@@ -192,8 +230,9 @@ __global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws
     if (threadIdx.x == 0) info[b] = 4;
     return;
   }
-  for (int k = threadIdx.x; k <= n; k += blockDim.x) lam[k] = bisect(sd, se2, m, n - 1 + k, s_lo, s_hi, s_piv);
-  __syncthreads();
+  __shared__ int cbuf[1024];
+  __shared__ double xbuf[1024];
+  multisect(sd, se2, m, n - 1, n + 1, s_lo, s_hi, s_piv, lam, cbuf, xbuf);
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
     if (kramers) {
       eps[d.eps_off + 2 * k] = lam[k + 1];
@@ -202,34 +241,40 @@ __global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws
       eps[d.eps_off + k] = lam[k + 1];
     }
   }
+  // Zolotarev candidates r = 4, 6, ..., RMAX evaluated in parallel; the
+  // smallest r that reaches 1e-13 (or stops improving) is kept
+  constexpr int NCAND = (RMAX - 4) / 2 + 1;
+  __shared__ double zerr[NCAND], zM[NCAND];
+  __shared__ double za[NCAND * RMAX], zc[NCAND * RMAX];
+  const double sigma = -c * c;
+  const double gam = fmin(lam[1] - sigma, sigma - lam[0]);
+  const double rho = fmax(s_hi - sigma, sigma - s_lo);
+  double ell = 0.9 * gam / rho;
+  ell = fmin(fmax(ell, 1e-14), 0.5);
+  if (threadIdx.x < NCAND) {
+    const int r = 4 + 2 * threadIdx.x;
+    double Mt;
+    zerr[threadIdx.x] = zolotarev(ell, r, za + threadIdx.x * RMAX, zc + threadIdx.x * RMAX, &Mt);
+    zM[threadIdx.x] = Mt;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const double sigma = -c * c;
-    const double gam = fmin(lam[1] - sigma, sigma - lam[0]);
-    const double rho = fmax(s_hi - sigma, sigma - s_lo);
-    double ell = 0.9 * gam / rho;
-    ell = fmin(fmax(ell, 1e-14), 0.5);
-    double abest[RMAX], cbest[RMAX], Mbest = 1.0;
-    double at[RMAX], ct[RMAX], Mt;
-    int rbest = 0;
+    int best = -1;
     double prev = 1.0;
-    for (int r = 4; r <= RMAX; r += 2) {
-      double err = zolotarev(ell, r, at, ct, &Mt);
-      bool take = (rbest == 0) || err <= prev;
-      if (take) {
-        for (int j = 0; j < r; ++j) { abest[j] = at[j]; cbest[j] = ct[j]; }
-        Mbest = Mt;
-        rbest = r;
-      }
+    for (int t = 0; t < NCAND; ++t) {
+      const double err = zerr[t];
+      if (best < 0 || err <= prev) best = t;
       if (err < 1e-13 || err > 0.5 * prev) break;
       prev = err;
     }
+    const int rbest = 4 + 2 * best;
     pf[0] = sigma;
     pf[1] = rho;
-    pf[2] = Mbest;
+    pf[2] = zM[best];
     pf[3] = (double)rbest;
     for (int j = 0; j < rbest; ++j) {
-      pf[4 + j] = abest[j];
-      pf[4 + RMAX + j] = sqrt(cbest[j]);
+      pf[4 + j] = za[best * RMAX + j];
+      pf[4 + RMAX + j] = sqrt(zc[best * RMAX + j]);
     }
   }
 }
@@ -291,6 +336,9 @@ __global__ void k_filter_factor(const BlockDesc* D, char* ws, const int* info, i
 
 // Columns j of Z = 1/2 (E + M [T_s E + sum_q a_q Re((T_s - i beta_q)^-1 E)]),
 // E_ij = hash(i, j); the result (real) goes to the T-typed m x n buffer.
+// The pole sum is accumulated in a real buffer (the T-typed output itself
+// when T is real, else C_TMP, which is free at this point) so that every
+// pole moves 8 bytes of accumulator per entry.
 // (quaternion form: rows are then scaled by the phases, Y_q = D Z)
 template <class T>
 __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* ws, const int* info, int kramers) {
@@ -306,6 +354,7 @@ __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* 
   const double* dg = bufp<double>(ws, d, V_D);
   const double* eg = bufp<double>(ws, d, V_E);
   T* Y = bufp<T>(ws, d, C_Y);
+  double* acc = sizeof(T) == sizeof(double) ? reinterpret_cast<double*>(Y) : bufp<double>(ws, d, C_TMP);
   cplx* scr = bufp<cplx>(ws, d, Z_SCR);
   const double ir = 1.0 / rho;
   // acc = T_s E_j
@@ -313,7 +362,7 @@ __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* 
     double t = (dg[i] - sigma) * hash_uniform(i, j);
     if (i > 0) t += eg[i - 1] * hash_uniform(i - 1, j);
     if (i < m - 1) t += eg[i] * hash_uniform(i + 1, j);
-    Y[(long long)i * n + j] = treal<T>(t * ir);
+    acc[(long long)i * n + j] = t * ir;
   }
   for (int q = 0; q < r; ++q) {
     const cplx* F = bufp<cplx>(ws, d, F_FAC) + (long long)q * m * 5;
@@ -341,15 +390,14 @@ __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* 
       cplx y = scr[(long long)i * n + j];
       cplx t = y - f[2] * x1 - f[3] * x2;
       cplx x = t * f[1];
-      long long idx = (long long)i * n + j;
-      Y[idx] = treal<T>(re(Y[idx]) + aq * x.x);
+      acc[(long long)i * n + j] += aq * x.x;
       x2 = x1;
       x1 = x;
     }
   }
   for (int i = 0; i < m; ++i) {
     long long idx = (long long)i * n + j;
-    const double z = 0.5 * (hash_uniform(i, j) + M * re(Y[idx]));
+    const double z = 0.5 * (hash_uniform(i, j) + M * acc[idx]);
     if constexpr (sizeof(T) == sizeof(quat)) Y[idx] = z * bufp<quat>(ws, d, V_DEL)[i];
     else Y[idx] = treal<T>(z);
   }
@@ -385,8 +433,10 @@ __global__ void __launch_bounds__(256) k_tri_eig_q(const BlockDesc* D, char* ws,
   double lo, hi;
   gershgorin(sd, se, n, &lo, &hi, red);
   const double piv = 2.2e-308 * 16.0 * fmax(1.0, hi * hi);
-  if (threadIdx.x == 0) s_min = bisect(sd, se2, n, 0, lo, hi, piv);
-  if (threadIdx.x == 64 || (blockDim.x <= 64 && threadIdx.x == 0)) s_max = bisect(sd, se2, n, n - 1, lo, hi, piv);
+  __shared__ int cbuf[256];
+  __shared__ double xbuf[256];
+  multisect(sd, se2, n, 0, 1, lo, hi, piv, &s_min, cbuf, xbuf);
+  multisect(sd, se2, n, n - 1, 1, lo, hi, piv, &s_max, cbuf, xbuf);
   __syncthreads();
   if (threadIdx.x == 0) {
     double lmin = s_min, lmax = s_max;
@@ -479,7 +529,7 @@ __global__ void __launch_bounds__(256) k_invsqrt_cols(const BlockDesc* D, char* 
 void launch_tri_eig4c(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxm, double* eps,
                       double c, int kramers) {
   size_t shm = (size_t)(4 * maxm + 2) * sizeof(double);
-  hipLaunchKernelGGL(k_tri_eig4c, dim3(nblk), dim3(512), shm, s, D, ws, info, eps, c, kramers);
+  hipLaunchKernelGGL(k_tri_eig4c, dim3(nblk), dim3(1024), shm, s, D, ws, info, eps, c, kramers);
 }
 void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int kramers) {
   hipLaunchKernelGGL(k_filter_factor, dim3(RMAX, nblk), dim3(64), 0, s, D, ws, info, kramers);

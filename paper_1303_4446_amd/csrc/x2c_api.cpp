@@ -252,8 +252,8 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
     STAGE("prep");
     launch_init_info(s, info, nblk);
     launch_unpack(s, D, ws, info, nblk, maxN, S, Tm, V, W, tc ? 1 : 0);
-    launch_potrf(s, D, ws, info, nblk);
-    launch_trtri(s, D, ws, info, nblk);
+    launch_potrf(s, D, ws, info, nblk, maxN);
+    launch_trtri(s, D, ws, info, nblk, maxN);
     launch_expand<T>(s, D, ws, info, nblk, maxn, c);
   }
   {

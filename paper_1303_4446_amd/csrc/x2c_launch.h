@@ -9,8 +9,8 @@ namespace x2c {
 void launch_init_info(hipStream_t s, int* info, int nblk);
 void launch_unpack(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN, const double* S,
                    const double* T, const double* V, const double* W, int twocomp);
-void launch_potrf(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk);
-void launch_trtri(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk);
+void launch_potrf(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN);
+void launch_trtri(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN);
 template <class T>
 void launch_expand(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, double c);
 template <class T>
