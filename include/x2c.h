@@ -48,6 +48,15 @@ extern "C" {
 #endif
 
 typedef enum { X2C_SPINFREE = 1, X2C_TWOCOMP = 2 } x2c_mode;
+/* Arithmetic of the products of steps 3-5 (X, S~, L, the renormalisation and
+ * h).  X2C_FP64: FP64 products.  X2C_SPLIT_BF16: each FP64 operand row
+ * (column) is scaled by a power of two and cut into `ozaki_slices` 7-bit
+ * integer slices held exactly in bf16; the slice products run on the bf16
+ * matrix cores with exact FP32 partial sums, folded into FP64 (an error-free
+ * splitting of FP64 products).  The truncation error of a product entry is
+ * about K 2^(-7 s) times the product of the operand row and column maxima
+ * (K the inner dimension).  The Cholesky factors, the eigenvalue problems and
+ * the inverse square root are FP64 in both modes. */
 typedef enum { X2C_FP64 = 0, X2C_SPLIT_BF16 = 1 } x2c_prec;
 
 /* Reduction of the two Hermitian eigenproblems of a two-component block.
@@ -63,7 +72,7 @@ typedef enum { X2C_RED_QUATERNION = 0, X2C_RED_COMPLEX = 1 } x2c_reduction;
 typedef struct {
   int mode;          /* x2c_mode */
   int prec;          /* x2c_prec: arithmetic of the X / L / S~ / R product chain */
-  int ozaki_slices;  /* split precision only: bf16 slices per operand, 0 = automatic */
+  int ozaki_slices;  /* split precision only: slices per operand, 1..8; 0 = automatic (7) */
   double c;          /* speed of light in atomic units (> 0) */
   int reduction;     /* x2c_reduction (two-component only); 0 = quaternion */
 } x2c_options;

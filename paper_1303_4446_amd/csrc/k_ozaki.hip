@@ -1,0 +1,267 @@
+// Split-precision GEMM for the X / L / S~ / R product chain:
+//   C_b = alpha op(A_b) op(B_b) + beta C_b  (op in {N, H}, n_b x n_b, batched)
+// with FP64 accuracy emulated on bf16 matrix cores (Ozaki-type error-free
+// splitting).
+//
+// Every row i of op(A) is scaled by 2^-ea_i (ea_i = binary exponent of the
+// row's largest |entry|, so the scaled row lies in (-1, 1)) and cut into S
+// slices of 7 bits: y <- 128 y, q_s = rint(y), y <- y - q_s, so that
+// row = 2^ea_i sum_s 2^-7s q_s up to 2^(ea_i - 7S - 1).  Columns of op(B)
+// are cut the same way with their own exponents.  Every q_s is an integer of
+// magnitude <= 128, exact in bf16, so each bf16 product q_a q_b is exact and
+// a sum of up to 2^24 / (S 2^14) such products is exact in the FP32
+// accumulator of the matrix core.  Slice pairs (a, b) with a + b = g share
+// the weight 2^-7g; the pairs with g <= S + 1 are kept (the rest lie below
+// the truncation of the operands), accumulated exactly per g over 128 terms
+// of the inner dimension and folded into FP64 accumulators, which carry the
+// result.  Rounding therefore only happens in FP64.
+//
+// Complex operands use the real form with interleaved real / imaginary parts:
+// row 2i of A' is (Re a_ik, -Im a_ik) over k, row 2i+1 is (Im a_ik, Re a_ik),
+// rows 2k / 2k+1 of B' are Re / Im b_kj, so (A'B')_{2i,j} = Re (AB)_ij and
+// (A'B')_{2i+1,j} = Im (AB)_ij; a row exponent covers both parts of a row.
+//
+// Tiling (gfx950): 256 threads = 4 waves; the work-group covers 128 rows of
+// A' x 64 columns; wave w owns rows 32w..32w+31 as two 32 x 32 MFMA blocks
+// (v_mfma_f32_32x32x16_bf16).  The FP64 tiles are split on the fly into LDS
+// (all S slices of a 32-deep k chunk), so HBM traffic equals that of the
+// plain FP64 GEMM.
+#include "x2c_device.h"
+#include "x2c_launch.h"
+
+namespace x2c {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float floatx16;
+
+constexpr int OZ_M = 128, OZ_N = 64, OZ_KC = 32, OZ_LD = OZ_KC + 8;
+constexpr int OZ_FLUSH = 4;     // k chunks between folds into FP64 (128 terms)
+
+// binary exponent of the largest |entry| of each row (rows = 1) or column of a
+// T-typed n x n matrix; one wave per line.  grid = (ceil(n / 4), nblk)
+template <class T>
+__global__ void __launch_bounds__(256) k_line_exp(const BlockDesc* D, char* ws, const int* info, int dsel, int buf,
+                                                  int rows, int bufE) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = seldim(d, dsel);
+  const int line = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (line >= n) return;
+  const T* A = bufp<T>(ws, d, buf);
+  double mx = 0.0;
+  for (int k = lane; k < n; k += 64) {
+    const T v = rows ? A[(long long)line * n + k] : A[(long long)k * n + line];
+    mx = fmax(mx, fmax(fabs(re(v)), fabs(im(v))));
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if (lane == 0) {
+    int e = 0;
+    if (mx > 0.0) frexp(mx, &e);     // mx < 2^e
+    bufp<int>(ws, d, bufE)[line] = e;
+  }
+}
+
+template <int S>
+__device__ inline void split_slices(double x, double scale, __bf16* q) {
+  double y = x * scale;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    y *= 128.0;
+    const double r = rint(y);
+    y -= r;
+    q[s] = (__bf16)(float)r;
+  }
+}
+
+template <class T, int S>
+__global__ void __launch_bounds__(256) k_gemm_split(const BlockDesc* D, char* ws, const int* info, int dsel,
+                                                    int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta,
+                                                    int bufEA, int bufEB) {
+  constexpr bool CPLX = sizeof(T) == sizeof(cplx);
+  constexpr int RF = CPLX ? 2 : 1;          // real rows / k per element
+  const int b = blockIdx.z;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = seldim(d, dsel);
+  const int Mr = RF * n;
+  const int m0 = blockIdx.y * OZ_M, n0 = blockIdx.x * OZ_N;   // m0 in rows of A', n0 in columns
+  if (m0 >= Mr || n0 >= n) return;
+  const T* A = bufp<T>(ws, d, bufA);
+  const T* B = bufp<T>(ws, d, bufB);
+  T* C = bufp<T>(ws, d, bufC);
+  const int* ea = bufp<int>(ws, d, bufEA);
+  const int* eb = bufp<int>(ws, d, bufEB);
+
+  extern __shared__ __attribute__((aligned(16))) __bf16 oz_sm[];
+  __bf16* As = oz_sm;                          // S x OZ_M x OZ_LD
+  __bf16* Bs = oz_sm + S * OZ_M * OZ_LD;       // S x OZ_N x OZ_LD
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int l32 = lane & 31, lhi = lane >> 5;
+
+  floatx16 acc[S][2];
+  double acc64[2][16];
+#pragma unroll
+  for (int g = 0; g < S; ++g)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[g][h][j] = 0.0f;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc64[h][j] = 0.0;
+
+  // elements of op(A) per chunk: (OZ_M / RF) rows x (OZ_KC / RF) k
+  constexpr int AR = OZ_M / RF, AK = OZ_KC / RF, BK = OZ_KC / RF;
+  const int Kr = RF * n;
+  const int nchunks = (Kr + OZ_KC - 1) / OZ_KC;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int k0 = ch * AK;                   // first element-k of the chunk
+    // ---- split op(A) chunk into LDS
+#pragma unroll 1
+    for (int e = t; e < AR * AK; e += 256) {
+      int r, kk;
+      if (opA == 0) { r = e / AK; kk = e % AK; } else { kk = e / AR; r = e % AR; }
+      const int gi = m0 / RF + r, gk = k0 + kk;
+      T v = tzero<T>();
+      if (gi < n && gk < n) v = opA == 0 ? A[(long long)gi * n + gk] : conjg(A[(long long)gk * n + gi]);
+      const double sc = gi < n ? ldexp(1.0, -ea[gi]) : 0.0;
+      __bf16 qr[S], qi[S];
+      split_slices<S>(re(v), sc, qr);
+      if constexpr (CPLX) {
+        split_slices<S>(im(v), sc, qi);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          __bf16* p0 = As + (s * OZ_M + 2 * r) * OZ_LD + 2 * kk;
+          __bf16* p1 = p0 + OZ_LD;
+          p0[0] = qr[s];
+          p0[1] = -qi[s];
+          p1[0] = qi[s];
+          p1[1] = qr[s];
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s) As[(s * OZ_M + r) * OZ_LD + kk] = qr[s];
+      }
+    }
+    // ---- split op(B) chunk into LDS (stored column-major: [col][k])
+#pragma unroll 1
+    for (int e = t; e < BK * OZ_N; e += 256) {
+      int c, kk;
+      if (opB == 0) { kk = e / OZ_N; c = e % OZ_N; } else { c = e / BK; kk = e % BK; }
+      const int gk = k0 + kk, gj = n0 + c;
+      T v = tzero<T>();
+      if (gk < n && gj < n) v = opB == 0 ? B[(long long)gk * n + gj] : conjg(B[(long long)gj * n + gk]);
+      const double sc = gj < n ? ldexp(1.0, -eb[gj]) : 0.0;
+      __bf16 qr[S], qi[S];
+      split_slices<S>(re(v), sc, qr);
+      if constexpr (CPLX) {
+        split_slices<S>(im(v), sc, qi);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          __bf16* p = Bs + (s * OZ_N + c) * OZ_LD + 2 * kk;
+          p[0] = qr[s];
+          p[1] = qi[s];
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s) Bs[(s * OZ_N + c) * OZ_LD + kk] = qr[s];
+      }
+    }
+    __syncthreads();
+    // ---- slice-pair products on the matrix cores
+#pragma unroll
+    for (int ks = 0; ks < OZ_KC / 16; ++ks) {
+      bf16x8 af[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        af[s] = *reinterpret_cast<const bf16x8*>(As + (s * OZ_M + 32 * wave + l32) * OZ_LD + 16 * ks + 8 * lhi);
+#pragma unroll
+      for (int sb = 0; sb < S; ++sb) {
+        bf16x8 bf[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          bf[h] = *reinterpret_cast<const bf16x8*>(Bs + (sb * OZ_N + 32 * h + l32) * OZ_LD + 16 * ks + 8 * lhi);
+#pragma unroll
+        for (int sa = 0; sa < S - sb; ++sa)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[sa + sb][h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[sa], bf[h], acc[sa + sb][h], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    // ---- fold the exact FP32 group sums into FP64 (smallest weights first)
+    if ((ch + 1) % OZ_FLUSH == 0 || ch + 1 == nchunks) {
+#pragma unroll
+      for (int g = S - 1; g >= 0; --g) {
+        const double w = ldexp(1.0, -7 * (g + 2));
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            acc64[h][j] = fma((double)acc[g][h][j], w, acc64[h][j]);
+            acc[g][h][j] = 0.0f;
+          }
+      }
+    }
+  }
+  // ---- epilogue: undo the exponents, C = alpha P + beta C
+  const bool use_beta = (re(beta) != 0.0 || im(beta) != 0.0);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int col = n0 + 32 * h + l32;
+    if (col >= n) continue;
+#pragma unroll
+    for (int j = 0; j < 16; j += RF) {
+      const int rr = m0 + 32 * wave + 8 * (j / 4) + 4 * lhi + (j % 4);   // row of A'
+      const int i = rr / RF;
+      if (i >= n) continue;
+      const double sc = ldexp(1.0, ea[i] + eb[col]);
+      T p;
+      if constexpr (CPLX) p = cplx{acc64[h][j] * sc, acc64[h][j + 1] * sc};
+      else p = acc64[h][j] * sc;
+      const long long idx = (long long)i * n + col;
+      T v = alpha * p;
+      if (use_beta) v = mad(beta, C[idx], v);
+      C[idx] = v;
+    }
+  }
+}
+
+template <class T, int S>
+static void launch_split_s(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim,
+                           int dsel, int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta) {
+  constexpr int RF = sizeof(T) == sizeof(cplx) ? 2 : 1;
+  const size_t shm = (size_t)S * (OZ_M + OZ_N) * OZ_LD * sizeof(__bf16);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_split<T, S>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)shm);
+  dim3 grid((maxdim + OZ_N - 1) / OZ_N, (RF * maxdim + OZ_M - 1) / OZ_M, nblk);
+  hipLaunchKernelGGL((k_gemm_split<T, S>), grid, dim3(256), shm, s, D, ws, info, dsel, bufA, opA, bufB, opB, bufC,
+                     alpha, beta, (int)V_EXA, (int)V_EXB);
+}
+
+template <class T>
+void launch_gemm_split(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
+                       int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int slices) {
+  const dim3 lg((maxdim + 3) / 4, nblk);
+  hipLaunchKernelGGL(k_line_exp<T>, lg, dim3(256), 0, s, D, ws, info, dsel, bufA, opA == 0 ? 1 : 0, (int)V_EXA);
+  hipLaunchKernelGGL(k_line_exp<T>, lg, dim3(256), 0, s, D, ws, info, dsel, bufB, opB == 0 ? 0 : 1, (int)V_EXB);
+  switch (slices) {
+    case 1: launch_split_s<T, 1>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
+    case 2: launch_split_s<T, 2>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
+    case 3: launch_split_s<T, 3>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
+    case 4: launch_split_s<T, 4>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
+    case 5: launch_split_s<T, 5>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
+    case 6: launch_split_s<T, 6>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
+    case 7: launch_split_s<T, 7>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
+    default: launch_split_s<T, 8>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
+  }
+}
+
+template void launch_gemm_split<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int,
+                                        int, int, int, double, double, int);
+template void launch_gemm_split<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
+                                      int, int, cplx, cplx, int);
+
+}  // namespace x2c

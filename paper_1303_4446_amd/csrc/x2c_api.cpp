@@ -23,6 +23,8 @@ namespace {
 
 constexpr int MAX_N_2C = 256;   // 4c dimension 4N <= 1024
 constexpr int MAX_N_SF = 512;   // 4c dimension 2N <= 1024
+constexpr int MAX_SLICES = 8;   // split products: slices per operand
+constexpr int AUTO_SLICES = 7;  // default: keeps bound-state errors at the FP64 level up to Z = 79
 constexpr size_t ALIGN = 256;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
@@ -78,6 +80,8 @@ void block_sizes(int N, bool tc, size_t sz[NBUF]) {
   }
   sz[V_ET] = n * 32;
   sz[V_DEL] = n * 32;
+  sz[V_EXA] = n * 4;
+  sz[V_EXB] = n * 4;
   sz[W_VCUR] = m * es;
 }
 
@@ -86,7 +90,7 @@ bool valid_opts(const x2c_options* o) {
   if (o->mode != X2C_SPINFREE && o->mode != X2C_TWOCOMP) return false;
   if (o->prec != X2C_FP64 && o->prec != X2C_SPLIT_BF16) return false;
   if (!(o->c > 0.0) || !std::isfinite(o->c)) return false;
-  if (o->ozaki_slices < 0 || o->ozaki_slices > 16) return false;
+  if (o->ozaki_slices < 0 || o->ozaki_slices > MAX_SLICES) return false;
   if (o->reduction != X2C_RED_QUATERNION && o->reduction != X2C_RED_COMPLEX) return false;
   return true;
 }
@@ -247,6 +251,13 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   const T one = tcast<T>(1.0), zero = tcast<T>(0.0);
   const int OPN = 0, OPH = 1;
   const bool kramers = tc && o->reduction == X2C_RED_QUATERNION;
+  // products of the X / L / S~ / R chain: FP64, or split bf16 slices
+  const bool split = o->prec == X2C_SPLIT_BF16;
+  const int slices = o->ozaki_slices > 0 ? o->ozaki_slices : AUTO_SLICES;
+  auto chain_gemm = [&](int bA, int opA, int bB, int opB, int bC, T alpha, T beta) {
+    if (split) launch_gemm_split<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, slices);
+    else launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta);
+  };
 
   {
     STAGE("prep");
@@ -315,26 +326,26 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
     // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
     STAGE("x_solve");
     launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn, kramers ? C_A : C_Y);
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, OPN, C_LS, OPH, C_TMP2, one, zero);
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LTI, OPH, C_TMP2, OPN, C_X,
+    chain_gemm(C_TMP, OPN, C_LS, OPH, C_TMP2, one, zero);
+    chain_gemm(C_LTI, OPH, C_TMP2, OPN, C_X,
                    tcast<T>(std::sqrt(2.0) * c), zero);
   }
   {
     // S~ = S + X^H T X / 2c^2 ;  L = V + TX + (TX)^H + X^H (W/4c^2 - T) X
     STAGE("chain_SL");
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_T, OPN, C_X, OPN, C_TX, one, zero);
+    chain_gemm(C_T, OPN, C_X, OPN, C_TX, one, zero);
     launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_S, C_Q);
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_X, OPH, C_TX, OPN, C_Q, tcast<T>(1.0 / (2.0 * c * c)), one);
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_WPP, OPN, C_X, OPN, C_WX, one, zero);
+    chain_gemm(C_X, OPH, C_TX, OPN, C_Q, tcast<T>(1.0 / (2.0 * c * c)), one);
+    chain_gemm(C_WPP, OPN, C_X, OPN, C_WX, one, zero);
     launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_V, C_L);
     launch_add_herm<T>(s, D, ws, info, nblk, maxn, C_TX, C_L);
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_X, OPH, C_WX, OPN, C_L, one, one);
+    chain_gemm(C_X, OPH, C_WX, OPN, C_L, one, one);
   }
   {
     // Q = L_S^-1 S~ L_S^-H
     STAGE("chain_Q");
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LSI, OPN, C_Q, OPN, C_TMP, one, zero);
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, OPN, C_LSI, OPH, C_Q, one, zero);
+    chain_gemm(C_LSI, OPN, C_Q, OPN, C_TMP, one, zero);
+    chain_gemm(C_TMP, OPN, C_LSI, OPH, C_Q, one, zero);
   }
   if (!kramers) {
     {
@@ -372,14 +383,14 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   {
     // R = L_S^-H Q^-1/2 L_S^H
     STAGE("chain_R");
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_QMH, OPN, C_LS, OPH, C_TMP, one, zero);
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_LSI, OPH, C_TMP, OPN, C_R, one, zero);
+    chain_gemm(C_QMH, OPN, C_LS, OPH, C_TMP, one, zero);
+    chain_gemm(C_LSI, OPH, C_TMP, OPN, C_R, one, zero);
   }
   {
     // h = R^H (L R)
     STAGE("chain_h");
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_L, OPN, C_R, OPN, C_LR, one, zero);
-    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_R, OPH, C_LR, OPN, C_H, one, zero);
+    chain_gemm(C_L, OPN, C_R, OPN, C_LR, one, zero);
+    chain_gemm(C_R, OPH, C_LR, OPN, C_H, one, zero);
   }
   {
     STAGE("write");

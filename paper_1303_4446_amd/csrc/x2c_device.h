@@ -123,6 +123,9 @@ enum Buf : int {
   W_VCUR,
   // quaternion path: sub-diagonal quaternions and the phases making them real
   V_ET, V_DEL,
+  // split-precision products: binary exponents of the rows of op(A) and of
+  // the columns of op(B)
+  V_EXA, V_EXB,
   NBUF
 };
 
