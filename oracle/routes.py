@@ -273,3 +273,50 @@ def x2c_polar(S, T, V, W, c: float, twocomp: bool):
 def x2c(S, T, V, W, c: float, twocomp: bool):
     """Default oracle entry point (route 1)."""
     return x2c_direct(S, T, V, W, c, twocomp)
+
+
+# ----------------------------------------------------------------------------
+# DLU molecular Hamiltonian (Sec. III.A)
+# ----------------------------------------------------------------------------
+
+def atom_spinor_index(off: int, N: int, Ntot: int, twocomp: bool) -> np.ndarray:
+    """Molecular spin-orbital indices of an atom's functions in its own
+    [alpha; beta] order (molecular order: all alpha, then all beta)."""
+    a = np.arange(off, off + N)
+    return np.concatenate([a, Ntot + a]) if twocomp else a
+
+
+def x2c_dlu(S, T, V, W, Ns, c: float, twocomp: bool, return_parts: bool = False):
+    """Molecular h in the diagonal local approximation to the unitary
+    transformation: U^L and U^S are direct sums of atomic blocks (Eq.
+    dlutrans), each evaluated from the atom's own diagonal blocks of S, T, V, W
+    (Eq. r2ctransatom), and h follows from Eq. utrans with the full molecular
+    matrices:  h = U^L^H V U^L + U^L^H T U^S + U^S^H T U^L + U^S^H (W/4c^2 - T) U^S.
+
+    S, T, V: Ntot x Ntot; W: (4, Ntot, Ntot) (two-component) or W^0."""
+    Ns = [int(x) for x in Ns]
+    Ntot = int(sum(Ns))
+    W = np.asarray(W)
+    Sx, Tx, Vx, Wx = spinor_matrices(S, T, V, W, twocomp)
+    n = Sx.shape[0]
+    UL = np.zeros((n, n), dtype=Sx.dtype)
+    US = np.zeros((n, n), dtype=Sx.dtype)
+    parts = []
+    off = 0
+    for NA in Ns:
+        sl = slice(off, off + NA)
+        WA = W[:, sl, sl] if W.ndim == 3 else W[sl, sl]
+        if not twocomp and W.ndim == 3:
+            WA = WA[0]
+        _, _, p = x2c_direct(S[sl, sl], T[sl, sl], V[sl, sl], WA, c, twocomp, return_parts=True)
+        idx = atom_spinor_index(off, NA, Ntot, twocomp)
+        UL[np.ix_(idx, idx)] = p["R"]
+        US[np.ix_(idx, idx)] = p["X"] @ p["R"]
+        parts.append(dict(X=p["X"], R=p["R"]))
+        off += NA
+    Wp = Wx / (4.0 * c * c) - Tx
+    h = (UL.conj().T @ Vx @ UL + UL.conj().T @ Tx @ US
+         + US.conj().T @ Tx @ UL + US.conj().T @ Wp @ US)
+    if return_parts:
+        return h, parts
+    return h

@@ -3,5 +3,5 @@
 Shared by the CPU oracle, the tests and the benchmark; contains no part of the
 relativistic decoupling itself."""
 from .integrals import AtomBlock, Shell, build_block, rxgrad_real  # noqa: F401
-from .configs import (C_LIGHT, C_LIGHT_PAPER, ag_2c, ag309_dlu, atom_block,  # noqa: F401
-                      mixed_dlu, neon_s20, pack_blocks, shell_counts)
+from .configs import (C_LIGHT, C_LIGHT_PAPER, Molecule, ag13_molecule, ag_2c, ag309_dlu,  # noqa: F401
+                      atom_block, coupled_molecule, mixed_dlu, neon_s20, pack_blocks, shell_counts)

@@ -110,3 +110,80 @@ def pack_blocks(blocks: list[AtomBlock], twocomp: bool):
         else:
             W[o:o + n2] = b.W[0].ravel()
     return dict(S=S, T=T, V=V, W=W, Ns=Ns, in_off=in_off)
+
+
+# ----------------------------------------------------------------------------
+# coupled molecules (full molecular matrices for the DLU assembly)
+# ----------------------------------------------------------------------------
+
+class Molecule:
+    """Molecular scalar matrices over the atom-ordered basis: atom A's
+    functions occupy scalar indices off[A] .. off[A] + Ns[A]."""
+
+    def __init__(self, Z, S, T, V, W, Ns, scale):
+        self.Z = list(Z)
+        self.S, self.T, self.V, self.W = S, T, V, W      # W: (4, Ntot, Ntot)
+        self.Ns = np.asarray(Ns, dtype=np.int32)
+        self.off = np.concatenate([[0], np.cumsum(self.Ns)[:-1]]).astype(np.int64)
+        self.scale = scale
+
+    @property
+    def Ntot(self) -> int:
+        return int(self.Ns.sum())
+
+    def atom(self, A: int) -> AtomBlock:
+        o, n = int(self.off[A]), int(self.Ns[A])
+        sl = slice(o, o + n)
+        return AtomBlock(self.Z[A], self.S[sl, sl].copy(), self.T[sl, sl].copy(), self.V[sl, sl].copy(),
+                         self.W[:, sl, sl].copy())
+
+
+def coupled_molecule(blocks: list[AtomBlock], seed: int, scale: float = 1e-3) -> Molecule:
+    """Block-diagonal molecular matrices from atomic blocks plus a seeded
+    symmetric inter-atomic coupling: for scalar i, j on different atoms,
+    M_ij += scale exp(-|i - j| / 50) u_ij sqrt(|M_ii M_jj|), u_ij = u_ji ~ U(-1, 1),
+    for M in {S, T, V, W^0} (W^x, W^y, W^z stay atom-diagonal).  The scale is
+    halved until the smallest eigenvalues of S and T are at least half of
+    their block-diagonal values, so both stay positive definite."""
+    Ns = [b.N for b in blocks]
+    Ntot = int(sum(Ns))
+    off = np.concatenate([[0], np.cumsum(Ns)[:-1]])
+    S0 = np.zeros((Ntot, Ntot)); T0 = np.zeros((Ntot, Ntot)); V0 = np.zeros((Ntot, Ntot))
+    W0 = np.zeros((4, Ntot, Ntot))
+    atom_of = np.zeros(Ntot, dtype=np.int64)
+    for A, (b, o) in enumerate(zip(blocks, off)):
+        sl = slice(int(o), int(o) + b.N)
+        S0[sl, sl] = b.S; T0[sl, sl] = b.T; V0[sl, sl] = b.V; W0[:, sl, sl] = b.W
+        atom_of[sl] = A
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-1.0, 1.0, size=(Ntot, Ntot))
+    u = np.triu(u, 1)
+    u = u + u.T
+    idx = np.arange(Ntot)
+    shape = np.exp(-np.abs(idx[:, None] - idx[None, :]) / 50.0) * u
+    shape[atom_of[:, None] == atom_of[None, :]] = 0.0
+    lmin_s = np.linalg.eigvalsh(S0)[0]
+    lmin_t = np.linalg.eigvalsh(T0)[0]
+
+    def couple(M):
+        d = np.sqrt(np.abs(np.diag(M)))
+        return shape * np.outer(d, d)
+
+    cS, cT, cV, cW = couple(S0), couple(T0), couple(V0), couple(W0[0])
+    s = scale
+    for _ in range(60):
+        S = S0 + s * cS
+        T = T0 + s * cT
+        if np.linalg.eigvalsh(S)[0] >= 0.5 * lmin_s and np.linalg.eigvalsh(T)[0] >= 0.5 * lmin_t:
+            break
+        s *= 0.5
+    V = V0 + s * cV
+    W = W0.copy()
+    W[0] = W0[0] + s * cW
+    return Molecule([b.Z for b in blocks], S, T, V, W, Ns, s)
+
+
+def ag13_molecule(seed: int = 0) -> Molecule:
+    """Thirteen Z = 47 two-component blocks (4992 spinors) with the coupling
+    above: the full-versus-DLU workload."""
+    return coupled_molecule([ag_2c() for _ in range(13)], seed)
