@@ -143,6 +143,53 @@ int x2c_build_batched(const x2c_options* opts, int nblk, const int* N, const int
                       const int64_t* h_off, void* h, const int64_t* eps_off, double* eps, int* info,
                       void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * x2c_build_batched that also returns each block's decoupling matrices:
+ * X_b = C_S C_L^-1 (Appendix, Eq. defxmat) and the renormalisation R_b
+ * (Eq. ulnonortho), i.e. U^L_bb = R_b and U^S_bb = X_b R_b (Eq. usnonortho).
+ * X and R (device, either may be NULL) use the layout of h: block b's
+ * n_b x n_b matrix (float64 or complex128) at double offset h_off[b].
+ * A failed block gets zero X and R.  Other arguments and the return value as
+ * for x2c_build_batched.
+ */
+int x2c_build_batched_xr(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off,
+                         const double* S, const double* T, const double* V, const double* W,
+                         const int64_t* h_off, void* h, const int64_t* eps_off, double* eps, void* X,
+                         void* R, int* info, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Workspace size in bytes for x2c_dlu_assemble with `natom` atoms of scalar
+ * sizes N[0..natom) (host).  0 for invalid arguments.
+ */
+size_t x2c_dlu_workspace_bytes(const x2c_options* opts, int natom, const int* N);
+
+/*
+ * Molecular one-electron Hamiltonian in the DLU approximation (Sec. III.A):
+ * U^L and U^S are the direct sums of the atoms' R_A and X_A R_A (Eqs.
+ * dlutrans, r2ctransatom), and Eq. utrans is applied with the full molecular
+ * matrices, pair by pair:
+ *   h_AB = R_A^H [V_AB + T_AB X_B + X_A^H T_AB + X_A^H (W_AB/4c^2 - T_AB) X_B] R_B.
+ * Stream-ordered (does not synchronise).
+ *   N        host, natom scalar sizes; atom A's functions are molecular
+ *            scalar indices off_A .. off_A + N[A], off_A = N[0] + .. + N[A-1];
+ *            Ntot = sum of N.
+ *   T, V     molecular Ntot x Ntot (device, row-major float64).
+ *   W        spin-free: W^0 (Ntot x Ntot); two-component: W^0, W^x, W^y, W^z
+ *            contiguous (4 x Ntot x Ntot) (device).
+ *   u_off    host, natom double offsets of X_A and R_A in X and R (even in
+ *            two-component mode), e.g. the h_off of x2c_build_batched_xr.
+ *   X, R     device, the atoms' decoupling matrices (n_A x n_A each).
+ *   H        output (device): spin-free Ntot x Ntot float64; two-component
+ *            2Ntot x 2Ntot complex128 in the molecular spin-orbital order
+ *            [all alpha; all beta].  Every entry is written.
+ * The caller owns every buffer; the workspace holds the atom-pair products.
+ * Returns X2C_OK once enqueued, X2C_EINVAL (NULL pointer, N[A] out of range,
+ * odd u_off in two-component mode, workspace too small) or X2C_EHIP.
+ */
+int x2c_dlu_assemble(const x2c_options* opts, int natom, const int* N, const double* T, const double* V,
+                     const double* W, const int64_t* u_off, const void* X, const void* R, void* H,
+                     void* workspace, size_t ws_bytes, void* stream);
+
 /* Static description of a return or info code. */
 const char* x2c_strerror(int code);
 

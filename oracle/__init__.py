@@ -5,4 +5,4 @@ never by the GPU library or its Python binding.
 """
 from .routes import (X2CError, assemble_w, dirac_matrices, dirac_positive_spectrum,  # noqa: F401
                   atom_spinor_index, reduced_dirac, spectrum_of, spin_blockdiag, spinor_matrices,
-                  x2c, x2c_direct, x2c_dlu, x2c_kbasis, x2c_polar)
+                  x2c, x2c_direct, x2c_dlu, x2c_dlu_pair, x2c_kbasis, x2c_polar)

@@ -320,3 +320,25 @@ def x2c_dlu(S, T, V, W, Ns, c: float, twocomp: bool, return_parts: bool = False)
     if return_parts:
         return h, parts
     return h
+
+
+def x2c_dlu_pair(T, V, W, Ns, A: int, B: int, parts, c: float, twocomp: bool):
+    """One atom-pair block h_AB of the DLU Hamiltonian, i.e. Eq. utrans
+    restricted to the rows of atom A and the columns of atom B with the
+    block-diagonal U of Eq. dlutrans:
+    h_AB = U^L_AA^H V_AB U^L_BB + U^L_AA^H T_AB U^S_BB + U^S_AA^H T_AB U^L_BB
+           + U^S_AA^H (W_AB/4c^2 - T_AB) U^S_BB,
+    with parts[A] = dict(X=X_A, R=R_A) (U^L_AA = R_A, U^S_AA = X_A R_A)."""
+    Ns = [int(x) for x in Ns]
+    Ntot = int(sum(Ns))
+    off = np.concatenate([[0], np.cumsum(Ns)[:-1]]).astype(int)
+    W = np.asarray(W)
+    Tx, Vx, Wx = spinor_matrices(T, T, V, W, twocomp)[1:]
+    ia = atom_spinor_index(off[A], Ns[A], Ntot, twocomp)
+    ib = atom_spinor_index(off[B], Ns[B], Ntot, twocomp)
+    sub = lambda M: M[np.ix_(ia, ib)]
+    ULa, ULb = parts[A]["R"], parts[B]["R"]
+    USa, USb = parts[A]["X"] @ ULa, parts[B]["X"] @ ULb
+    Wp = sub(Wx) / (4.0 * c * c) - sub(Tx)
+    return (ULa.conj().T @ sub(Vx) @ ULb + ULa.conj().T @ sub(Tx) @ USb
+            + USa.conj().T @ sub(Tx) @ ULb + USa.conj().T @ Wp @ USb)

@@ -23,8 +23,9 @@ OK, EINVAL, EHIP, EBLOCK = 0, -1, -2, -3
 INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subspace degenerate",
               4: "positive-energy branch size != n", 5: "renormalisation matrix not PD", 6: "non-finite input"}
 
-EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_strerror",
-            "x2c_release", "x2c_trace_enable", "x2c_trace_read", "x2c_trace_reset")
+EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_build_batched_xr",
+            "x2c_dlu_workspace_bytes", "x2c_dlu_assemble", "x2c_strerror", "x2c_release", "x2c_trace_enable",
+            "x2c_trace_read", "x2c_trace_reset")
 
 
 class X2CError(RuntimeError):
@@ -63,6 +64,14 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.x2c_build_batched.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp,
                                       i64p, vp, i64p, vp, vp, vp, ctypes.c_size_t, vp]
     lib.x2c_build_batched.restype = i32
+    lib.x2c_build_batched_xr.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp,
+                                         i64p, vp, i64p, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.x2c_build_batched_xr.restype = i32
+    lib.x2c_dlu_workspace_bytes.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int)]
+    lib.x2c_dlu_workspace_bytes.restype = ctypes.c_size_t
+    lib.x2c_dlu_assemble.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), vp, vp, vp, i64p, vp, vp, vp,
+                                     vp, ctypes.c_size_t, vp]
+    lib.x2c_dlu_assemble.restype = i32
     lib.x2c_strerror.argtypes = [i32]
     lib.x2c_strerror.restype = ctypes.c_char_p
     lib.x2c_release.argtypes = []
@@ -172,6 +181,77 @@ def batch_to_device(packed: dict, twocomp: bool, device="cuda") -> Batch:
     f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
     return Batch(f(packed["S"]), f(packed["T"]), f(packed["V"]), f(packed["W"]),
                  np.asarray(packed["Ns"], dtype=np.int32), np.asarray(packed["in_off"], dtype=np.int64), twocomp)
+
+
+def build_batched_xr(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspace=None, stream=None,
+                     reduction: int = RED_QUATERNION):
+    """Enqueue x2c_build_batched_xr.  Returns (h, eps, info, X, R) device
+    tensors (X and R in the flat layout of h) and the workspace."""
+    torch = _torch()
+    lib = load()
+    dev = batch.S.device
+    h_off, eps_off, hsz, esz = batch.out_layout()
+    h = torch.empty(hsz, dtype=torch.float64, device=dev)
+    X = torch.empty(hsz, dtype=torch.float64, device=dev)
+    R = torch.empty(hsz, dtype=torch.float64, device=dev)
+    eps = torch.empty(esz, dtype=torch.float64, device=dev)
+    info = torch.empty(batch.nblk, dtype=torch.int32, device=dev)
+    wsb = workspace_bytes(batch.Ns, batch.twocomp, c, prec)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    opt = options(batch.twocomp, c, prec, slices, reduction)
+    Ns = np.ascontiguousarray(batch.Ns, dtype=np.int32)
+    i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
+    in_off, ho, eo = i64(batch.in_off), i64(h_off), i64(eps_off)
+    P = ctypes.POINTER(ctypes.c_int64)
+    f64 = lambda t: _dev(t, torch, torch.float64)
+    rc = lib.x2c_build_batched_xr(
+        ctypes.byref(opt), batch.nblk, Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), in_off.ctypes.data_as(P),
+        f64(batch.S), f64(batch.T), f64(batch.V), f64(batch.W), ho.ctypes.data_as(P), f64(h),
+        eo.ctypes.data_as(P), f64(eps), f64(X), f64(R), _dev(info, torch, torch.int32),
+        ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()), _stream_ptr(torch, stream))
+    if rc != OK:
+        raise X2CError(rc, strerror(rc))
+    return (h, eps, info, X, R), workspace
+
+
+def dlu_workspace_bytes(Ns, twocomp: bool, c: float = 137.0) -> int:
+    Ns = np.ascontiguousarray(Ns, dtype=np.int32)
+    opt = options(twocomp, c)
+    n = load().x2c_dlu_workspace_bytes(ctypes.byref(opt), len(Ns), Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if n == 0:
+        raise X2CError(EINVAL, "invalid atom sizes or options")
+    return int(n)
+
+
+def dlu_assemble(T, V, W, Ns, u_off, X, R, c: float, twocomp: bool, workspace=None, stream=None, H=None):
+    """Enqueue x2c_dlu_assemble: molecular T, V (Ntot x Ntot) and W (Ntot x Ntot
+    or 4 x Ntot x Ntot) device tensors, the atoms' X and R in the flat layout
+    given by u_off (double offsets).  Returns (H, workspace); H is
+    Ntot x Ntot float64 or 2Ntot x 2Ntot complex128."""
+    torch = _torch()
+    lib = load()
+    Ns = np.ascontiguousarray(Ns, dtype=np.int32)
+    Ntot = int(Ns.sum())
+    n = 2 * Ntot if twocomp else Ntot
+    dev = T.device
+    if H is None:
+        H = torch.empty((n, n), dtype=torch.complex128 if twocomp else torch.float64, device=dev)
+    wsb = dlu_workspace_bytes(Ns, twocomp, c)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    opt = options(twocomp, c)
+    uo = np.ascontiguousarray(u_off, dtype=np.int64)
+    f64 = lambda t: _dev(t, torch, torch.float64)
+    if not (H.is_cuda and H.is_contiguous() and H.numel() == n * n):
+        raise ValueError("H must be a contiguous device tensor of the molecular size")
+    rc = lib.x2c_dlu_assemble(ctypes.byref(opt), len(Ns), Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                              f64(T), f64(V), f64(W), uo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              f64(X), f64(R), ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                              ctypes.c_size_t(workspace.numel()), _stream_ptr(torch, stream))
+    if rc != OK:
+        raise X2CError(rc, strerror(rc))
+    return H, workspace
 
 
 def build_batched(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspace=None, out=None,

@@ -168,6 +168,85 @@ std::shared_ptr<Layout> get_plan(const x2c_options* o, int nblk, const int* N, c
   return L;
 }
 
+// ---------------------------------------------------------------- DLU assembly plans
+struct DluPlan {
+  std::vector<DluPair> pairs;
+  DluPair* pinned = nullptr;
+  size_t total = 0;
+  int Ntot = 0, maxn = 0;
+  ~DluPlan() {
+    if (pinned) (void)hipHostFree(pinned);
+  }
+};
+
+bool make_dlu_plan(const x2c_options* o, int natom, const int* N, const int64_t* u_off, DluPlan& P) {
+  const bool tc = o->mode == X2C_TWOCOMP;
+  const size_t es = tc ? 16 : 8;
+  const int mx = max_n(o->mode);
+  std::vector<int> off(natom, 0);
+  long long Ntot = 0;
+  for (int a = 0; a < natom; ++a) {
+    if (N[a] <= 0 || N[a] > mx) return false;
+    off[a] = (int)Ntot;
+    Ntot += N[a];
+  }
+  if (Ntot > (1 << 20)) return false;
+  P.Ntot = (int)Ntot;
+  P.pairs.clear();
+  for (int a = 0; a < natom; ++a)
+    for (int b = 0; b <= a; ++b) {
+      DluPair q;
+      std::memset(&q, 0, sizeof(q));
+      q.A = a; q.B = b;
+      q.nA = tc ? 2 * N[a] : N[a];
+      q.nB = tc ? 2 * N[b] : N[b];
+      q.oA = off[a]; q.oB = off[b];
+      if (u_off && (u_off[a] < 0 || (tc && (u_off[a] & 1)))) return false;
+      q.xA = u_off ? u_off[a] / (tc ? 2 : 1) : 0;
+      q.xB = u_off ? u_off[b] / (tc ? 2 : 1) : 0;
+      P.pairs.push_back(q);
+      P.maxn = std::max(P.maxn, q.nA);
+    }
+  size_t o2 = align_up(P.pairs.size() * sizeof(DluPair));
+  for (DluPair& q : P.pairs) {
+    const size_t sz = align_up((size_t)q.nA * q.nB * es);
+    q.t = (long long)o2; o2 += sz;
+    q.w = (long long)o2; o2 += sz;
+    q.l = (long long)o2; o2 += sz;
+    q.p = (long long)o2; o2 += sz;
+  }
+  P.total = o2;
+  return true;
+}
+
+std::map<std::vector<int64_t>, std::shared_ptr<DluPlan>> g_dlu_plans;
+
+std::shared_ptr<DluPlan> get_dlu_plan(const x2c_options* o, int natom, const int* N, const int64_t* u_off) {
+  std::vector<int64_t> key;
+  key.push_back(o->mode);
+  key.push_back(natom);
+  for (int a = 0; a < natom; ++a) {
+    key.push_back(N[a]);
+    key.push_back(u_off[a]);
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dlu_plans.find(key);
+  if (it != g_dlu_plans.end()) return it->second;
+  auto P = std::make_shared<DluPlan>();
+  if (!make_dlu_plan(o, natom, N, u_off, *P)) return nullptr;
+  void* pin = nullptr;
+  if (hipHostMalloc(&pin, P->pairs.size() * sizeof(DluPair), hipHostMallocDefault) == hipSuccess && pin) {
+    std::memcpy(pin, P->pairs.data(), P->pairs.size() * sizeof(DluPair));
+    P->pinned = static_cast<DluPair*>(pin);
+  }
+  if (g_dlu_plans.size() > 16) {
+    (void)hipDeviceSynchronize();
+    g_dlu_plans.clear();
+  }
+  g_dlu_plans.emplace(std::move(key), P);
+  return P;
+}
+
 // ---------------------------------------------------------------- tracing
 // When enabled, each stage of a call is bracketed by a pair of HIP events
 // recorded on the call's stream; x2c_trace_read folds finished pairs into
@@ -243,7 +322,7 @@ T tcast(double v) {
 // The stage sequence for one batch (all blocks advance stage by stage).
 template <class T>
 int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S, const double* Tm, const double* V,
-               const double* W, double* h, double* eps, int* info, char* ws, hipStream_t s) {
+               const double* W, double* h, double* eps, double* Xo, double* Ro, int* info, char* ws, hipStream_t s) {
   const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off);
   const bool tc = o->mode == X2C_TWOCOMP;
   const double c = o->c;
@@ -395,13 +474,16 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   {
     STAGE("write");
     launch_write_h<T>(s, D, ws, info, nblk, maxn, h, eps);
+    if (Xo) launch_write_buf<T>(s, D, ws, info, nblk, maxn, Xo, C_X);
+    if (Ro) launch_write_buf<T>(s, D, ws, info, nblk, maxn, Ro, C_R);
   }
   return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
 }
 
 int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off, const double* S, const double* T,
             const double* V, const double* W, const int64_t* h_off, void* h, const int64_t* eps_off, double* eps,
-            int* info, void* workspace, size_t ws_bytes, hipStream_t s, const Layout** out_layout) {
+            void* Xo, void* Ro, int* info, void* workspace, size_t ws_bytes, hipStream_t s,
+            const Layout** out_layout) {
   if (!valid_opts(o) || nblk <= 0 || !N || !S || !T || !V || !W || !h || !eps || !workspace) return X2C_EINVAL;
   std::shared_ptr<Layout> L = get_plan(o, nblk, N, in_off, h_off, eps_off);
   if (!L) return X2C_EINVAL;
@@ -415,8 +497,10 @@ int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
     return X2C_EHIP;
   if (!info) info = reinterpret_cast<int*>(ws + L->info_off);
   if (o->mode == X2C_TWOCOMP)
-    return run_stages<cplx>(o, *L, nblk, S, T, V, W, static_cast<double*>(h), eps, info, ws, s);
-  return run_stages<double>(o, *L, nblk, S, T, V, W, static_cast<double*>(h), eps, info, ws, s);
+    return run_stages<cplx>(o, *L, nblk, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
+                            static_cast<double*>(Ro), info, ws, s);
+  return run_stages<double>(o, *L, nblk, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
+                            static_cast<double*>(Ro), info, ws, s);
 }
 
 }  // namespace
@@ -437,7 +521,8 @@ int x2c_build(const x2c_options* opts, int N, const double* S, const double* T, 
   hipStream_t s = static_cast<hipStream_t>(stream);
   int64_t zero = 0;
   const Layout* L = nullptr;
-  int rc = enqueue(opts, 1, &N, &zero, S, T, V, W, &zero, h, &zero, eps, nullptr, workspace, ws_bytes, s, &L);
+  int rc = enqueue(opts, 1, &N, &zero, S, T, V, W, &zero, h, &zero, eps, nullptr, nullptr, nullptr, workspace,
+                   ws_bytes, s, &L);
   if (rc != X2C_OK) return rc;
   int info = 0;
   if (hipMemcpyAsync(&info, static_cast<char*>(workspace) + L->info_off, sizeof(int), hipMemcpyDeviceToHost, s) !=
@@ -454,8 +539,50 @@ int x2c_build_batched(const x2c_options* opts, int nblk, const int* N, const int
                       void* stream) {
   if (nblk == 0 && valid_opts(opts)) return X2C_OK;   // empty batch: nothing to do
   if (!in_off || !h_off || !eps_off || !info) return X2C_EINVAL;
-  return enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, info, workspace, ws_bytes,
+  return enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, nullptr, nullptr, info, workspace,
+                 ws_bytes, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int x2c_build_batched_xr(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off, const double* S,
+                         const double* T, const double* V, const double* W, const int64_t* h_off, void* h,
+                         const int64_t* eps_off, double* eps, void* X, void* R, int* info, void* workspace,
+                         size_t ws_bytes, void* stream) {
+  if (nblk == 0 && valid_opts(opts)) return X2C_OK;
+  if (!in_off || !h_off || !eps_off || !info) return X2C_EINVAL;
+  return enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, X, R, info, workspace, ws_bytes,
                  static_cast<hipStream_t>(stream), nullptr);
+}
+
+size_t x2c_dlu_workspace_bytes(const x2c_options* opts, int natom, const int* N) {
+  if (!valid_opts(opts) || natom <= 0 || !N) return 0;
+  DluPlan P;
+  if (!make_dlu_plan(opts, natom, N, nullptr, P)) return 0;
+  return P.total;
+}
+
+int x2c_dlu_assemble(const x2c_options* opts, int natom, const int* N, const double* T, const double* V,
+                     const double* W, const int64_t* u_off, const void* X, const void* R, void* H, void* workspace,
+                     size_t ws_bytes, void* stream) {
+  if (!valid_opts(opts) || natom <= 0 || !N || !u_off || !T || !V || !W || !X || !R || !H || !workspace)
+    return X2C_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::shared_ptr<DluPlan> P = get_dlu_plan(opts, natom, N, u_off);
+  if (!P) return X2C_EINVAL;
+  if (ws_bytes < P->total) return X2C_EINVAL;
+  char* ws = static_cast<char*>(workspace);
+  (void)hipGetLastError();
+  const void* src = P->pinned ? static_cast<const void*>(P->pinned) : static_cast<const void*>(P->pairs.data());
+  if (hipMemcpyAsync(ws, src, P->pairs.size() * sizeof(DluPair), hipMemcpyHostToDevice, s) != hipSuccess)
+    return X2C_EHIP;
+  const DluPair* dP = reinterpret_cast<const DluPair*>(ws);
+  const int np = (int)P->pairs.size();
+  if (opts->mode == X2C_TWOCOMP)
+    launch_dlu<cplx>(s, dP, np, P->maxn, P->maxn, ws, T, V, W, P->Ntot, opts->c, static_cast<const double*>(X),
+                     static_cast<const double*>(R), static_cast<double*>(H));
+  else
+    launch_dlu<double>(s, dP, np, P->maxn, P->maxn, ws, T, V, W, P->Ntot, opts->c, static_cast<const double*>(X),
+                       static_cast<const double*>(R), static_cast<double*>(H));
+  return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
 }
 
 const char* x2c_strerror(int code) {
@@ -479,6 +606,7 @@ void x2c_release(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     (void)hipDeviceSynchronize();
     g_plans.clear();
+    g_dlu_plans.clear();
   }
   std::lock_guard<std::mutex> lk(g_tmu);
   trace_collect();

@@ -147,6 +147,15 @@ struct BlockDesc {
   long long off[NBUF];
 };
 
+// One atom pair (A >= B) of the DLU molecular assembly.
+struct DluPair {
+  int A, B;           // atoms
+  int nA, nB;         // dimensions of their h blocks (N or 2N)
+  int oA, oB;         // scalar offsets of their functions in the molecule
+  long long xA, xB;   // element offsets of X_A / R_A and X_B / R_B in the X and R arrays
+  long long t, w, l, p;   // byte offsets of the pair's work buffers (T_AB / h_AB, W'', L, P)
+};
+
 template <class P>
 __device__ inline P* bufp(char* ws, const BlockDesc& d, int id) {
   return reinterpret_cast<P*>(ws + d.off[id]);

@@ -69,6 +69,13 @@ void launch_qct_scale(hipStream_t s, const BlockDesc* D, char* ws, const int* in
                       int dst);
 
 template <class T>
+void launch_write_buf(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, double* out,
+                      int buf);
+template <class T>
+void launch_dlu(hipStream_t s, const DluPair* P, int npairs, int maxnA, int maxnB, char* ws, const double* Tm,
+                const double* Vm, const double* Wm, int Ntot, double c, const double* X, const double* R, double* H);
+
+template <class T>
 void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn, int bufY);
 
 }  // namespace x2c

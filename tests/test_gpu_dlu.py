@@ -1,0 +1,144 @@
+"""DLU molecular assembly on the GPU (x2c_build_batched_xr + x2c_dlu_assemble,
+through the C ABI) against the oracle's DLU Hamiltonian (Sec. III.A, Eqs.
+dlutrans, r2ctransatom, utrans).
+
+Tolerances: the same 2e-10 x max|h| as the per-block h for the assembled
+Hamiltonian (the assembly adds six FP64 products of the same operands).  The
+intermediate X = sqrt2 c L_T^-H (Y_S Y_L^-1) L_S^H carries the conditioning of
+L_T (kappa up to ~2e6 in these bases) times that of the positive-energy basis
+block Y_L (kappa ~ 10), so X and R are compared at u * 2e6 * 10 ~ 2e-9 of
+their largest entry (structurally zero entries included)."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.routes as ox
+from x2c_inputs import C_LIGHT as C, atom_block, coupled_molecule, pack_blocks, ag13_molecule
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-10
+TOL_XR = 2e-9
+
+
+def _px():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1303_4446_amd as px
+    return px, torch
+
+
+def gpu_dlu(m, twocomp):
+    px, torch = _px()
+    atoms = [m.atom(A) for A in range(len(m.Ns))]
+    pk = pack_blocks(atoms, twocomp)
+    bt = px.batch_to_device(pk, twocomp)
+    print(f"  x2c_build_batched_xr natom={len(atoms)} twocomp={twocomp}", flush=True)
+    (h, eps, info, X, R), _ = px.build_batched_xr(bt, C)
+    h_off, _, _, _ = bt.out_layout()
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    W = m.W if twocomp else m.W[0]
+    print(f"  x2c_dlu_assemble Ntot={m.Ntot}", flush=True)
+    H, _ = px.dlu_assemble(d(m.T), d(m.V), d(W), m.Ns, h_off, X, R, C, twocomp)
+    torch.cuda.synchronize()
+    return H.cpu().numpy(), info.cpu().numpy(), X.cpu().numpy(), R.cpu().numpy(), h_off
+
+
+@pytest.mark.parametrize("twocomp", [False, True])
+def test_xr_outputs_match_oracle(twocomp):
+    px, torch = _px()
+    blocks = [atom_block(z) for z in (8, 47)]
+    pk = pack_blocks(blocks, twocomp)
+    bt = px.batch_to_device(pk, twocomp)
+    print(f"  x2c_build_batched_xr twocomp={twocomp}", flush=True)
+    (h, eps, info, X, R), _ = px.build_batched_xr(bt, C)
+    torch.cuda.synchronize()
+    Xs = px.unpack_h(X.cpu().numpy(), bt.Ns, twocomp)
+    Rs = px.unpack_h(R.cpu().numpy(), bt.Ns, twocomp)
+    hs = px.unpack_h(h.cpu().numpy(), bt.Ns, twocomp)
+    assert np.all(info.cpu().numpy() == 0)
+    for b, Xg, Rg, hg in zip(blocks, Xs, Rs, hs):
+        W = b.W if twocomp else b.W[0]
+        h0, _, parts = ox.x2c_direct(b.S, b.T, b.V, W, C, twocomp, return_parts=True)
+        assert np.abs(Xg - parts["X"]).max() <= TOL_XR * np.abs(parts["X"]).max()
+        assert np.abs(Rg - parts["R"]).max() <= TOL_XR * np.abs(parts["R"]).max()
+        assert np.abs(hg - h0).max() <= TOL * np.abs(h0).max()
+
+
+@pytest.mark.parametrize("twocomp", [False, True])
+def test_dlu_small_molecule_matches_oracle(twocomp):
+    """Three atoms of uneven sizes (24 / 32 / 31 functions): ragged pair
+    blocks and several 64-wide tiles."""
+    m = coupled_molecule([atom_block(z) for z in (1, 8, 6)], 0)
+    H, info, _, _, _ = gpu_dlu(m, twocomp)
+    assert np.all(info == 0)
+    W = m.W if twocomp else m.W[0]
+    h0 = ox.x2c_dlu(m.S, m.T, m.V, W, m.Ns, C, twocomp)
+    assert np.abs(H - h0).max() <= TOL * np.abs(h0).max()
+    assert np.abs(H - H.conj().T).max() <= 1e-13 * np.abs(h0).max()
+
+
+def test_dlu_uncoupled_equals_full_build_on_gpu():
+    """No coupling: the DLU Hamiltonian is the full molecular X2C, here
+    from the GPU's own full build of the whole molecule."""
+    px, torch = _px()
+    m = coupled_molecule([atom_block(z) for z in (1, 8, 6)], 0, scale=0.0)
+    H, info, _, _, _ = gpu_dlu(m, True)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    print(f"  x2c_build full N={m.Ntot}", flush=True)
+    hf, _ = px.build(d(m.S), d(m.T), d(m.V), d(m.W), C, True)
+    hf = hf.cpu().numpy()
+    assert np.abs(H - hf).max() <= TOL * np.abs(hf).max()
+
+
+def test_dlu_single_atom_is_the_block_h():
+    b = atom_block(29)
+    m = coupled_molecule([b], 0)
+    H, info, X, R, h_off = gpu_dlu(m, True)
+    h0, _ = ox.x2c_direct(b.S, b.T, b.V, b.W, C, True)
+    assert np.abs(H - h0).max() <= TOL * np.abs(h0).max()
+
+
+def test_dlu_ag13_sampled_pairs():
+    """Thirteen silver atoms (4992 spinors, H = 4992 x 4992 complex) at full
+    size: sampled atom-pair blocks against the oracle's pair formula, and
+    the Hermitian mirror of the upper triangle."""
+    px, torch = _px()
+    m = ag13_molecule(0)
+    H, info, X, R, h_off = gpu_dlu(m, True)
+    assert np.all(info == 0)
+    Ntot = m.Ntot
+    # every atom of this workload carries the same atomic block (the coupling
+    # only touches inter-atomic entries): one oracle decoupling serves all
+    a0 = m.atom(0)
+    for A in range(1, len(m.Ns)):
+        aA = m.atom(A)
+        assert np.array_equal(aA.S, a0.S) and np.array_equal(aA.W, a0.W) and np.array_equal(aA.V, a0.V)
+    _, _, p0 = ox.x2c_direct(a0.S, a0.T, a0.V, a0.W, C, True, return_parts=True)
+    parts = [dict(X=p0["X"], R=p0["R"])] * len(m.Ns)
+    scale = None
+    for (A, B) in [(0, 0), (5, 2), (12, 11), (3, 9)]:
+        print(f"  oracle pair ({A}, {B})", flush=True)
+        blk = ox.x2c_dlu_pair(m.T, m.V, m.W, m.Ns, A, B, parts, C, True)
+        ia = ox.atom_spinor_index(int(m.off[A]), int(m.Ns[A]), Ntot, True)
+        ib = ox.atom_spinor_index(int(m.off[B]), int(m.Ns[B]), Ntot, True)
+        scale = np.abs(blk).max() if scale is None else max(scale, np.abs(blk).max())
+        assert np.abs(H[np.ix_(ia, ib)] - blk).max() <= TOL * scale
+    # diagonal atom blocks: the oracle's own atomic h
+    a = m.atom(7)
+    h7, _ = ox.x2c_direct(a.S, a.T, a.V, a.W, C, True)
+    i7 = ox.atom_spinor_index(int(m.off[7]), int(m.Ns[7]), Ntot, True)
+    assert np.abs(H[np.ix_(i7, i7)] - h7).max() <= TOL * np.abs(h7).max()
+    rng = np.random.default_rng(5)
+    r, c = rng.integers(0, 2 * Ntot, 2000), rng.integers(0, 2 * Ntot, 2000)
+    assert np.abs(H[r, c] - np.conj(H[c, r])).max() <= 1e-13 * np.abs(H).max()
+
+
+def test_dlu_rejects_bad_arguments():
+    px, torch = _px()
+    m = coupled_molecule([atom_block(z) for z in (1, 8)], 0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    X = torch.zeros(4 * 2 * 64 * 64, dtype=torch.float64, device="cuda")
+    with pytest.raises(px.X2CError):   # odd offset of a complex block
+        px.dlu_assemble(d(m.T), d(m.V), d(m.W), m.Ns, [0, 3], X, X, C, True)

@@ -125,3 +125,17 @@ def test_planted_dlu_mistakes_are_caught(name, monkeypatch):
             return out
         monkeypatch.setattr(ox, "x2c_direct", direct_no_r)
     assert not _pins_pass(), f"mutant {name} survived"
+
+
+@pytest.mark.parametrize("twocomp", [False, True])
+def test_dlu_pair_blocks_tile_the_molecular_h(twocomp):
+    """The per-pair form (used for sampled checks at full size) reproduces
+    every block of the molecular DLU h."""
+    m = _mol()
+    h, parts = ox.x2c_dlu(m.S, m.T, m.V, _W(m, twocomp), m.Ns, C, twocomp, return_parts=True)
+    for A in range(len(BLOCKS)):
+        for B in range(len(BLOCKS)):
+            blk = ox.x2c_dlu_pair(m.T, m.V, _W(m, twocomp), m.Ns, A, B, parts, C, twocomp)
+            ia = ox.atom_spinor_index(int(m.off[A]), int(m.Ns[A]), m.Ntot, twocomp)
+            ib = ox.atom_spinor_index(int(m.off[B]), int(m.Ns[B]), m.Ntot, twocomp)
+            assert np.abs(blk - h[np.ix_(ia, ib)]).max() <= 1e-13 * np.abs(h).max()
