@@ -193,13 +193,27 @@ int x2c_dlu_assemble(const x2c_options* opts, int natom, const int* N, const dou
 /* Static description of a return or info code. */
 const char* x2c_strerror(int code);
 
-/* Drop cached launch plans and trace events (host-side resources only). */
+/* Drop cached launch plans, captured graphs and trace events. */
 void x2c_release(void);
+
+/*
+ * Graph replay of x2c_build / x2c_build_batched / x2c_build_batched_xr
+ * (Sec. III.A batching: all blocks of a batch advance stage by stage).  When
+ * on (the default), the first call with a given combination of block sizes,
+ * offsets, options and device pointers captures its whole launch sequence
+ * into a HIP graph (on a private stream of the library); later calls with the
+ * same combination replay that graph on the caller's stream.  Results are
+ * identical either way.  Calls made while tracing is enabled run eagerly.
+ * Returns the previous setting.
+ */
+int x2c_graph_enable(int on);
 
 /*
  * Tracing.  x2c_trace_enable(1) makes every later call bracket each of its
  * stages with a pair of HIP events recorded on the call's stream (no device
- * memory is allocated); x2c_trace_enable returns the previous setting.
+ * memory is allocated); level 2 also brackets every launch of the
+ * tridiagonal-reduction matvec kernel (entry "k_tri_matvec").
+ * x2c_trace_enable returns the previous level.
  * x2c_trace_read waits for the recorded events, folds them into per-stage
  * totals and returns the number of stages seen; for 0 <= idx < that number
  * it stores the stage name (static until x2c_trace_reset), the summed

@@ -24,8 +24,8 @@ INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subsp
               4: "positive-energy branch size != n", 5: "renormalisation matrix not PD", 6: "non-finite input"}
 
 EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_build_batched_xr",
-            "x2c_dlu_workspace_bytes", "x2c_dlu_assemble", "x2c_strerror", "x2c_release", "x2c_trace_enable",
-            "x2c_trace_read", "x2c_trace_reset")
+            "x2c_dlu_workspace_bytes", "x2c_dlu_assemble", "x2c_strerror", "x2c_release", "x2c_graph_enable",
+            "x2c_trace_enable", "x2c_trace_read", "x2c_trace_reset")
 
 
 class X2CError(RuntimeError):
@@ -76,6 +76,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.x2c_strerror.restype = ctypes.c_char_p
     lib.x2c_release.argtypes = []
     lib.x2c_release.restype = None
+    lib.x2c_graph_enable.argtypes = [i32]
+    lib.x2c_graph_enable.restype = i32
     lib.x2c_trace_enable.argtypes = [i32]
     lib.x2c_trace_enable.restype = i32
     lib.x2c_trace_read.argtypes = [i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
@@ -110,8 +112,16 @@ def workspace_bytes(Ns, twocomp: bool, c: float = 137.0, prec: int = FP64) -> in
     return int(n)
 
 
-def trace_enable(on: bool) -> bool:
-    return bool(load().x2c_trace_enable(1 if on else 0))
+def graph_enable(on: bool) -> bool:
+    """Turn graph capture / replay of the build calls on or off; returns the
+    previous setting."""
+    return bool(load().x2c_graph_enable(1 if on else 0))
+
+
+def trace_enable(on, level: int = 1) -> int:
+    """Stage tracing on (level 1; level 2 adds per-launch matvec events) or
+    off; returns the previous level."""
+    return int(load().x2c_trace_enable(level if on else 0))
 
 
 def trace_reset() -> None:

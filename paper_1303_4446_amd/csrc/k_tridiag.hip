@@ -852,8 +852,10 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
       const int nsmax = nst * (nst + 1) / 2;
       const long long items = (long long)nsmax * nblk;
       const int grid = (int)std::min<long long>(items, (long long)mv_grid);
+      void* kt = ktrace_begin("k_tri_matvec", s);
       hipLaunchKernelGGL(k_tri_matvec<T>, dim3(grid), dim3(256), 0, s, D, ws, info, dsel, bufA, bufV, bufHS, bufW,
                          k0, k, nblk, nsmax);
+      ktrace_end(kt, s);
       hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau,
                          bufW, bufV, bufHS, bufET, k0, i + 1, (i + 1 < kbmax) ? 1 : 2);
     }

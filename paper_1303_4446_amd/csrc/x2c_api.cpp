@@ -257,6 +257,7 @@ struct TraceRec {
 };
 std::mutex g_tmu;
 bool g_trace = false;
+int g_trace_level = 0;   // 1: stages; 2: stages and the reduction matvec launches
 std::vector<TraceRec> g_pending;
 std::vector<hipEvent_t> g_pool;
 std::vector<std::pair<std::string, std::pair<double, long long>>> g_totals;
@@ -313,6 +314,36 @@ void trace_collect() {
 }
 
 #define STAGE(nm) Stage stage_guard_(nm, s)
+
+}  // namespace
+
+// per-launch events of selected kernels (trace level 2)
+void* x2c::ktrace_begin(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (!g_trace || g_trace_level < 2) return nullptr;
+  hipEvent_t a = ev_get();
+  if (!a) return nullptr;
+  hipEventRecord(a, s);
+  auto* rec = new TraceRec{name, a, nullptr};
+  return rec;
+}
+
+void x2c::ktrace_end(void* h, hipStream_t s) {
+  if (!h) return;
+  auto* rec = static_cast<TraceRec*>(h);
+  std::lock_guard<std::mutex> lk(g_tmu);
+  hipEvent_t b = ev_get();
+  if (b) {
+    hipEventRecord(b, s);
+    rec->b = b;
+    g_pending.push_back(*rec);
+  } else {
+    g_pool.push_back(rec->a);
+  }
+  delete rec;
+}
+
+namespace {
 
 template <class T>
 T tcast(double v) {
@@ -480,6 +511,52 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
 }
 
+// descriptor upload + every stage of one call, enqueued on s
+int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S, const double* T, const double* V,
+                const double* W, void* h, double* eps, void* Xo, void* Ro, int* info, char* ws, hipStream_t s) {
+  const void* src = L.pinned ? static_cast<const void*>(L.pinned) : static_cast<const void*>(L.desc.data());
+  if (hipMemcpyAsync(ws + L.desc_off, src, L.desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return X2C_EHIP;
+  if (o->mode == X2C_TWOCOMP)
+    return run_stages<cplx>(o, L, nblk, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
+                            static_cast<double*>(Ro), info, ws, s);
+  return run_stages<double>(o, L, nblk, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
+                            static_cast<double*>(Ro), info, ws, s);
+}
+
+// ---------------------------------------------------------------- graphs
+// The whole launch sequence of a call (about 2N kernels per block size N,
+// most of them short column steps of the reductions) is captured once per
+// (plan, pointers, options) into a HIP graph and replayed afterwards; the
+// capture runs on a private stream of the library, the replay on the
+// caller's stream.  The descriptor upload is a node of the graph reading
+// the plan's page-locked copy, which the cached record keeps alive.
+struct GraphRec {
+  std::shared_ptr<Layout> plan;
+  hipGraphExec_t exec = nullptr;
+  ~GraphRec() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+std::mutex g_gmu;
+bool g_graph_on = true;
+std::map<std::vector<int64_t>, std::shared_ptr<GraphRec>> g_graphs;
+std::map<int, hipStream_t> g_capture_streams;
+
+hipStream_t capture_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  auto it = g_capture_streams.find(dev);
+  if (it != g_capture_streams.end()) return it->second;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  g_capture_streams[dev] = cs;
+  return cs;
+}
+
+int64_t as_key(const void* p) { return static_cast<int64_t>(reinterpret_cast<intptr_t>(p)); }
+
 int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off, const double* S, const double* T,
             const double* V, const double* W, const int64_t* h_off, void* h, const int64_t* eps_off, double* eps,
             void* Xo, void* Ro, int* info, void* workspace, size_t ws_bytes, hipStream_t s,
@@ -491,16 +568,58 @@ int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
   if (out_layout) *out_layout = L.get();
   char* ws = static_cast<char*>(workspace);
   (void)hipGetLastError();
-  const void* src = L->pinned ? static_cast<const void*>(L->pinned) : static_cast<const void*>(L->desc.data());
-  if (hipMemcpyAsync(ws + L->desc_off, src, L->desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, s) !=
-      hipSuccess)
-    return X2C_EHIP;
   if (!info) info = reinterpret_cast<int*>(ws + L->info_off);
-  if (o->mode == X2C_TWOCOMP)
-    return run_stages<cplx>(o, *L, nblk, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
-                            static_cast<double*>(Ro), info, ws, s);
-  return run_stages<double>(o, *L, nblk, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
-                            static_cast<double*>(Ro), info, ws, s);
+  bool tracing;
+  {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    tracing = g_trace;
+  }
+  std::unique_lock<std::mutex> gl(g_gmu);
+  if (!g_graph_on || tracing || !L->pinned) {
+    gl.unlock();
+    return enqueue_all(o, *L, nblk, S, T, V, W, h, eps, Xo, Ro, info, ws, s);
+  }
+  int64_t cbits;
+  std::memcpy(&cbits, &o->c, sizeof(cbits));
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const std::vector<int64_t> key = {as_key(L.get()), as_key(S), as_key(T), as_key(V), as_key(W), as_key(h),
+                                    as_key(eps), as_key(Xo), as_key(Ro), as_key(info), as_key(ws), o->mode,
+                                    o->prec, o->ozaki_slices, o->reduction, cbits, dev};
+  std::shared_ptr<GraphRec> rec;
+  auto it = g_graphs.find(key);
+  if (it != g_graphs.end()) {
+    rec = it->second;
+  } else {
+    hipStream_t cs = capture_stream();
+    if (!cs) return X2C_EHIP;
+    // the capture starts after the caller's pending work on s only matters at
+    // replay time; capturing itself enqueues nothing
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return X2C_EHIP;
+    const int rc = enqueue_all(o, *L, nblk, S, T, V, W, h, eps, Xo, Ro, info, ws, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (rc != X2C_OK || ec != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return rc != X2C_OK ? rc : X2C_EHIP;
+    }
+    rec = std::make_shared<GraphRec>();
+    rec->plan = L;
+    const hipError_t ei = hipGraphInstantiate(&rec->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      rec->exec = nullptr;
+      return X2C_EHIP;
+    }
+    if (g_graphs.size() >= 32) {
+      (void)hipDeviceSynchronize();
+      g_graphs.clear();
+    }
+    g_graphs.emplace(key, rec);
+  }
+  gl.unlock();
+  return hipGraphLaunch(rec->exec, s) == hipSuccess ? X2C_OK : X2C_EHIP;
 }
 
 }  // namespace
@@ -608,16 +727,28 @@ void x2c_release(void) {
     g_plans.clear();
     g_dlu_plans.clear();
   }
+  {
+    std::lock_guard<std::mutex> lk(g_gmu);
+    g_graphs.clear();
+  }
   std::lock_guard<std::mutex> lk(g_tmu);
   trace_collect();
   for (hipEvent_t e : g_pool) hipEventDestroy(e);
   g_pool.clear();
 }
 
+int x2c_graph_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_gmu);
+  int prev = g_graph_on ? 1 : 0;
+  g_graph_on = on != 0;
+  return prev;
+}
+
 int x2c_trace_enable(int on) {
   std::lock_guard<std::mutex> lk(g_tmu);
-  int prev = g_trace ? 1 : 0;
+  int prev = g_trace ? g_trace_level : 0;
   g_trace = on != 0;
+  g_trace_level = on;
   return prev;
 }
 

@@ -6,6 +6,11 @@
 
 namespace x2c {
 
+// Optional per-launch timing of selected kernels (no-ops unless the library
+// trace is enabled at level 2).
+void* ktrace_begin(const char* name, hipStream_t s);
+void ktrace_end(void* h, hipStream_t s);
+
 void launch_init_info(hipStream_t s, int* info, int nblk);
 void launch_unpack(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN, const double* S,
                    const double* T, const double* V, const double* W, int twocomp);

@@ -273,6 +273,49 @@ def test_split_precision_batched_mixed():
         check_against_oracle(blk.S, blk.T, blk.V, blk.W, C_LIGHT, True, hs[i], eps[i])
 
 
+def test_graph_replays_match_eager_runs():
+    """Graph capture / replay: three calls on the same device buffers with
+    different inputs (eager torch work and synchronisations in between); each
+    replay must reproduce, bit for bit, the eager (uncaptured) result of the
+    same inputs."""
+    px, torch = _px()
+    base = [atom_block(z) for z in (6, 47, 17)]
+    from x2c_inputs.integrals import scale_potential
+    variants = [[scale_potential(b, f) for b in base] for f in (1.0, 0.99, 1.01)]
+    packs = [pack_blocks(v, True) for v in variants]
+    bt = px.batch_to_device(packs[0], True)
+    h_off, eps_off, hsz, esz = bt.out_layout()
+    out = (torch.empty(hsz, dtype=torch.float64, device="cuda"),
+           torch.empty(esz, dtype=torch.float64, device="cuda"),
+           torch.empty(len(base), dtype=torch.int32, device="cuda"))
+    ws = None
+    eager = []
+    prev = px.graph_enable(False)
+    try:
+        for pk in packs:
+            for name in ("S", "T", "V", "W"):
+                getattr(bt, name).copy_(torch.from_numpy(pk[name]).cuda())
+            print("  eager call", flush=True)
+            (h, eps, info), ws = px.build_batched(bt, C_LIGHT, workspace=ws, out=out)
+            torch.cuda.synchronize()
+            eager.append((h.cpu().numpy().copy(), eps.cpu().numpy().copy()))
+        px.graph_enable(True)
+        for k in range(2):
+            for i, pk in enumerate(packs):
+                for name in ("S", "T", "V", "W"):
+                    getattr(bt, name).copy_(torch.from_numpy(pk[name]).cuda())
+                junk = torch.randn(1 << 20, device="cuda").sum()      # unrelated eager work
+                print(f"  graph call round {k} input {i}", flush=True)
+                (h, eps, info), ws = px.build_batched(bt, C_LIGHT, workspace=ws, out=out)
+                torch.cuda.synchronize()
+                assert float(junk) == float(junk)
+                assert np.all(info.cpu().numpy() == 0)
+                assert np.array_equal(h.cpu().numpy(), eager[i][0])
+                assert np.array_equal(eps.cpu().numpy(), eager[i][1])
+    finally:
+        px.graph_enable(prev)
+
+
 def test_determinism_two_calls():
     blocks = [atom_block(z) for z in (6, 47)]
     a = gpu_batched(blocks, True)
