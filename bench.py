@@ -88,6 +88,10 @@ def parse():
     ap.add_argument("--check-blocks", type=int, default=3, help="blocks checked against the oracle")
     ap.add_argument("--cpu-blocks", type=int, default=12, help="blocks in the CPU oracle sample (0 = skip)")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="eager launches instead of graph replay")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the workload, copy a device buffer of this size once (a plain copy kernel "
+                         "of known traffic for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -162,11 +166,22 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     c = C_LIGHT
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
+        del src, dst
     blocks, twocomp, desc = workload(args.workload, args.seed)
     prec = px.FP64 if args.prec == "fp64" else px.SPLIT_BF16
     red = px.RED_QUATERNION if args.reduction == "quaternion" else px.RED_COMPLEX
     pk = pack_blocks(blocks, twocomp)
     batch = px.batch_to_device(pk, twocomp)
+    if args.no_graph:
+        px.graph_enable(False)
     stream = torch.cuda.current_stream()
     print(f"# workload: {desc}; prec {args.prec}", file=sys.stderr, flush=True)
 

@@ -596,6 +596,154 @@ __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws
   }
 }
 
+// Sum over the four lanes of a quad (lanes 4t..4t+3) with DPP quad
+// permutations (no LDS traffic).
+__device__ inline double quad_sum(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  double y = x + __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false),
+                                  __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false));     // lane ^ 1
+  lo = __double2loint(y);
+  hi = __double2hiint(y);
+  return y + __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false),
+                              __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false));      // lane ^ 2
+}
+__device__ inline quat quad_sum(const quat& q) {
+  return quat{cplx{quad_sum(q.a.x), quad_sum(q.a.y)}, cplx{quad_sum(q.b.x), quad_sum(q.b.y)}};
+}
+
+// Quaternion matvec, one independent wave per 32 x 32 super-tile (persistent
+// over the batch; work-groups of one wave, so no work-group barriers).  The
+// wave issues the loads of all four 16 x 16 sub-tiles (three on the
+// diagonal) and of the two vector segments at once, then stages the
+// sub-tiles one by one through its own LDS tile.  Row sums: lane (i, q)
+// covers row i, columns 4q..4q+3; column sums: lane (j, q) covers column j,
+// rows 4q..4q+3; quads are reduced with DPP.  Output and panel dot products
+// as for k_tri_matvec (a diagonal super-tile writes its full Hermitian
+// product as the row partial).
+constexpr int MVW_HT = 16;
+
+__global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* ws, const int* info, int dsel,
+                                                     int bufA, int bufV, int bufHS, int bufW, int k0, int k,
+                                                     int nblk, int nsmax) {
+  constexpr int HT = MVW_HT, ST = 2 * HT, EPL = HT * HT / 64;
+  const int lane = threadIdx.x;
+  __shared__ quat tl[HT][HT + 1];
+  __shared__ quat vsh[2][ST];          // [0] row segment, [1] column segment
+  __shared__ quat racc[ST], cacc[ST];
+  const int total = nblk * nsmax;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const MvItem it = mv_decode(D, info, dsel, k, nblk, nsmax, item, ST);
+    if (!it.valid) continue;
+    const BlockDesc& d = D[it.b];
+    const quat* A = bufp<quat>(ws, d, bufA);
+    const quat* vg = bufp<quat>(ws, d, bufV);
+    quat* HS = bufp<quat>(ws, d, bufHS);
+    const int off = k + 1, len = it.len, n = it.n, nst = it.nst, SI = it.SI, SJ = it.SJ;
+    const bool diag = SI == SJ;
+    const int R0 = ST * SI, C0 = ST * SJ;
+    // ---- issue every load of the item
+    quat regs[4][EPL];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int a = s >> 1, bb = s & 1;
+      const bool skip = diag && a == 0 && bb == 1;
+      const bool dsub = diag && a == bb;
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) {
+        const int ii = lane / HT + (64 / HT) * q, jj = lane % HT;
+        const int r = R0 + HT * a + ii, c = C0 + HT * bb + jj;
+        regs[s][q] = (!skip && r < len && c < len && (!dsub || ii >= jj))
+                         ? A[(long long)(off + r) * n + off + c] : tzero<quat>();
+      }
+    }
+    {
+      const int seg = lane >> 5, t = lane & 31;
+      const int g = (seg == 0 ? R0 : C0) + t;
+      vsh[seg][t] = g < len ? vg[g] : tzero<quat>();
+    }
+    if (lane < ST) {
+      racc[lane] = tzero<quat>();
+      cacc[lane] = tzero<quat>();
+    }
+    wave_sync();
+    // ---- sub-tiles
+    const int i4 = lane >> 2, q4 = lane & 3;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int a = s >> 1, bb = s & 1;
+      if (diag && a == 0 && bb == 1) continue;
+      const bool dsub = diag && a == bb;
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) tl[lane / HT + (64 / HT) * q][lane % HT] = regs[s][q];
+      wave_sync();
+      // row sums: row i4, columns 4 q4 .. 4 q4 + 3
+      quat rs = tzero<quat>();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = 4 * q4 + t;
+        quat e = tl[i4][j];
+        if (dsub && j == i4) e = treal<quat>(re(e));
+        rs = mad(e, vsh[1][HT * bb + j], rs);
+      }
+      // column sums: column i4, rows 4 q4 .. 4 q4 + 3 (strictly below the diagonal)
+      quat cs = tzero<quat>();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = 4 * q4 + t;
+        if (!dsub || i > i4) cs = mad(conjg(tl[i][i4]), vsh[0][HT * a + i], cs);
+      }
+      rs = quad_sum(rs);
+      cs = quad_sum(cs);
+      if (q4 == 0) {
+        racc[HT * a + i4] = racc[HT * a + i4] + rs;
+        cacc[HT * bb + i4] = cacc[HT * bb + i4] + cs;
+      }
+      wave_sync();
+    }
+    // ---- partial sums out
+    if (lane < ST) {
+      if (diag) {
+        const int r = R0 + lane;
+        if (r < len) HS[(long long)SJ * len + r] = racc[lane] + cacc[lane];
+      } else {
+        const int r = R0 + lane, c = C0 + lane;
+        if (r < len) HS[(long long)SJ * len + r] = racc[lane];
+        if (c < len) HS[(long long)(nst + SI) * len + c] = cacc[lane];
+      }
+    }
+    if (diag) {
+      // this strip's part of the panel dot products (j < k - k0)
+      const int ip = k - k0;
+      const quat* Wp = bufp<quat>(ws, d, bufW);
+      const int j = lane & (HB - 1), half = lane >> 5;
+      quat s1 = tzero<quat>(), s2 = tzero<quat>();
+      if (j < ip) {
+        for (int t = 0; t < HT; ++t) {
+          const int r = R0 + HT * half + t;
+          if (r < len) {
+            const quat vr = vsh[0][HT * half + t];
+            s1 = mad(conjg(Wp[(long long)(off + r) * HB + j]), vr, s1);
+            s2 = mad(conjg(panel_v(A, n, k0, off + r, j)), vr, s2);
+          }
+        }
+      }
+      // halves: lanes j and j + 32
+      __shared__ quat tsum[2][HB];
+      if (half == 1) {
+        tsum[0][j] = s1;
+        tsum[1][j] = s2;
+      }
+      wave_sync();
+      if (half == 0) {
+        quat* TP = HS + (long long)2 * nst * len;
+        TP[((long long)SI * HB + j) * 2] = s1 + tsum[0][j];
+        TP[((long long)SI * HB + j) * 2 + 1] = s2 + tsum[1][j];
+      }
+      wave_sync();
+    }
+  }
+}
+
 // Trailing lower triangle (rows/cols >= k0 + kb): A -= V W^H + W V^H.
 // grid = (lower 32 x 32 tiles, nblk).
 template <class T>
@@ -841,6 +989,7 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const int mv_grid = 2 * ncu;          // two resident work-groups per CU (LDS-bound)
+  const int mvw_grid = 8 * ncu;         // one-wave work-groups (register-bound: 8 resident per CU)
   for (int k0 = 0; k0 < maxdim - 1; k0 += HB) {
     const int kbmax = std::min(HB, maxdim - 1 - k0);
     hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufW,
@@ -853,8 +1002,14 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
       const long long items = (long long)nsmax * nblk;
       const int grid = (int)std::min<long long>(items, (long long)mv_grid);
       void* kt = ktrace_begin("k_tri_matvec", s);
-      hipLaunchKernelGGL(k_tri_matvec<T>, dim3(grid), dim3(256), 0, s, D, ws, info, dsel, bufA, bufV, bufHS, bufW,
-                         k0, k, nblk, nsmax);
+      if constexpr (is_quat<T>()) {
+        const int wgrid = (int)std::min<long long>(items, (long long)mvw_grid);
+        hipLaunchKernelGGL(k_tri_matvec_w, dim3(wgrid), dim3(64), 0, s, D, ws, info, dsel, bufA, bufV, bufHS,
+                           bufW, k0, k, nblk, nsmax);
+      } else {
+        hipLaunchKernelGGL(k_tri_matvec<T>, dim3(grid), dim3(256), 0, s, D, ws, info, dsel, bufA, bufV, bufHS,
+                           bufW, k0, k, nblk, nsmax);
+      }
       ktrace_end(kt, s);
       hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau,
                          bufW, bufV, bufHS, bufET, k0, i + 1, (i + 1 < kbmax) ? 1 : 2);
