@@ -75,6 +75,23 @@ def matvec_bytes(Ns, twocomp: bool, reduction: str) -> tuple[float, int]:
     return total, launches
 
 
+def recorded_traffic(kernel_src: str, summary: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None when the kernel's source has changed
+    since the counters were taken (or the summary is missing)."""
+    import hashlib
+    try:
+        with open(os.path.join(HERE, summary)) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(("|", "#", "`")))
+        with open(os.path.join(HERE, kernel_src), "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        if kv.get("source_sha256_16", "").strip() != h:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,8 +254,13 @@ def main():
         per_launch_b = total_b / max(1, launches)
         avg_ms = mv[0] / mv[1]
         achieved = per_launch_b / (avg_ms / 1e3) / 1e9
-        roofline = {"bound": "hbm", "kernel": "k_tri_matvec", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+        traffic = None
+        if args.workload == "ag309" and twocomp and args.reduction == "quaternion":
+            traffic = recorded_traffic("paper_1303_4446_amd/csrc/k_tridiag.hip",
+                                       "profiles/k_tri_matvec_w_ag309_traffic.md")
+        roofline = {"bound": "hbm", "kernel": "k_tri_matvec_w" if (twocomp and args.reduction == "quaternion")
+                    else "k_tri_matvec", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                     "launch_us": avg_ms * 1e3, "bytes_per_launch": per_launch_b,
                     "launches_per_step": mv[1] / args.steps, "share_of_step": mv[0] / args.steps / ms_step}
     extra = {}
