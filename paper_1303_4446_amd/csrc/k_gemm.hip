@@ -95,17 +95,150 @@ k_gemm(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, int op
 }
 
 
+// ---------------------------------------------------------------- matrix cores
+// The same product on the FP64 matrix cores (v_mfma_f64_16x16x4f64): 64 x 64
+// tile per work-group, 32 x 32 per wave as 2 x 2 MFMA blocks; operands staged
+// through LDS as separate real / imaginary planes, so a complex multiply-add
+// is four real MFMAs (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br).  Each lane
+// supplies one double of A and one of B per MFMA (lane l: A[l % 16][l / 16],
+// B[l / 16][l % 16]; result C[l / 16 + 4 i][l % 16], i < 4), i.e. a quarter
+// of the LDS traffic per multiply-add of the register-tiled kernel above.
+// herm = 1: the result is Hermitian (as is beta C); only tiles on or below
+// the diagonal are computed, and each lower entry is also written, conjugated,
+// to its mirror position.
+typedef __attribute__((ext_vector_type(4))) double d4;
+constexpr int GM_T = 64, GM_K = 16, GM_LD = GM_K + 1;
+
+template <class T>
+__global__ void __launch_bounds__(256)
+k_gemm_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, int opA, int bufB, int opB, int bufC,
+            T alpha, T beta, int herm) {
+  constexpr bool CP = sizeof(T) == sizeof(cplx);
+  const int b = blockIdx.z;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = seldim(d, dsel);
+  const int m0 = blockIdx.y * GM_T, n0 = blockIdx.x * GM_T;
+  if (m0 >= n || n0 >= n) return;
+  if (herm && blockIdx.x > blockIdx.y) return;
+  const T* A = bufp<T>(ws, d, bufA);
+  const T* B = bufp<T>(ws, d, bufB);
+  T* C = bufp<T>(ws, d, bufC);
+  __shared__ double Ar[GM_T][GM_LD], Ai[GM_T][GM_LD];       // [row][k]
+  __shared__ double Br[GM_K][GM_T + 1], Bi[GM_K][GM_T + 1]; // [k][col]
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  d4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      cr[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+      ci[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  // software pipeline: the next k chunk is fetched into registers while the
+  // matrix cores work on the chunk in LDS
+  constexpr int NL = GM_T * GM_K / 256;       // elements per thread per operand
+  T na[NL], nb[NL];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int l = t + 256 * q;
+      int r, kk;
+      if (opA == 0) { r = l / GM_K; kk = l % GM_K; } else { kk = l / GM_T; r = l % GM_T; }
+      const int gr = m0 + r, gk = k0 + kk;
+      na[q] = (gr < n && gk < n) ? (opA == 0 ? A[(long long)gr * n + gk] : conjg(A[(long long)gk * n + gr]))
+                                 : tzero<T>();
+      int c;
+      if (opB == 0) { kk = l / GM_T; c = l % GM_T; } else { c = l / GM_K; kk = l % GM_K; }
+      const int gk2 = k0 + kk, gc = n0 + c;
+      nb[q] = (gk2 < n && gc < n) ? (opB == 0 ? B[(long long)gk2 * n + gc] : conjg(B[(long long)gc * n + gk2]))
+                                  : tzero<T>();
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int l = t + 256 * q;
+      int r, kk;
+      if (opA == 0) { r = l / GM_K; kk = l % GM_K; } else { kk = l / GM_T; r = l % GM_T; }
+      Ar[r][kk] = re(na[q]);
+      if constexpr (CP) Ai[r][kk] = im(na[q]);
+      int c;
+      if (opB == 0) { kk = l / GM_T; c = l % GM_T; } else { c = l / GM_K; kk = l % GM_K; }
+      Br[kk][c] = re(nb[q]);
+      if constexpr (CP) Bi[kk][c] = im(nb[q]);
+    }
+  };
+  fetch(0);
+  stash();
+  __syncthreads();
+  for (int k0 = 0; k0 < n; k0 += GM_K) {
+    const bool more = k0 + GM_K < n;
+    if (more) fetch(k0 + GM_K);
+#pragma unroll
+    for (int ks = 0; ks < GM_K; ks += 4) {
+      double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        ar[x] = Ar[wr + 16 * x + l16][ks + l4];
+        br[x] = Br[ks + l4][wc + 16 * x + l16];
+        if constexpr (CP) {
+          ai[x] = Ai[wr + 16 * x + l16][ks + l4];
+          bi[x] = Bi[ks + l4][wc + 16 * x + l16];
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          cr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], br[y], cr[x][y], 0, 0, 0);
+          if constexpr (CP) {
+            cr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[x], bi[y], cr[x][y], 0, 0, 0);
+            ci[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], bi[y], ci[x][y], 0, 0, 0);
+            ci[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[x], br[y], ci[x][y], 0, 0, 0);
+          }
+        }
+    }
+    __syncthreads();
+    if (more) {
+      stash();
+      __syncthreads();
+    }
+  }
+  const bool use_beta = (re(beta) != 0.0 || im(beta) != 0.0);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = m0 + wr + 16 * x + l4 + 4 * i, c = n0 + wc + 16 * y + l16;
+        if (r >= n || c >= n) continue;
+        if (herm && c > r) continue;
+        T p;
+        if constexpr (CP) p = cplx{cr[x][y][i], ci[x][y][i]};
+        else p = cr[x][y][i];
+        const long long idx = (long long)r * n + c;
+        T v = alpha * p;
+        if (use_beta) v = mad(beta, C[idx], v);
+        C[idx] = v;
+        if (herm && c < r) C[(long long)c * n + r] = conjg(v);
+      }
+}
+
 template <class T>
 void launch_gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
-                 int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta) {
-  int t = (maxdim + GB_M - 1) / GB_M;
-  hipLaunchKernelGGL(k_gemm<T>, dim3(t, t, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA, opA, bufB, opB, bufC,
-                     alpha, beta);
+                 int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int herm) {
+  int t = (maxdim + GM_T - 1) / GM_T;
+  hipLaunchKernelGGL(k_gemm_mfma<T>, dim3(t, t, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA, opA, bufB, opB,
+                     bufC, alpha, beta, herm);
 }
 
 template void launch_gemm<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int, int,
-                                  int, double, double);
+                                  int, double, double, int);
 template void launch_gemm<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int, int,
-                                int, cplx, cplx);
+                                int, cplx, cplx, int);
 
 }  // namespace x2c

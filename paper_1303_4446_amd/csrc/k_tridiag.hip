@@ -286,8 +286,10 @@ __device__ inline void wave_sync() {
 // phase: 0 = first column of a panel (no previous column to finish)
 //        1 = finish column k-1 (w), then build column k if it is in the panel
 //        2 = finish column k-1 only (last column of the panel)
+constexpr int COLT = 256;   // threads of the per-block column kernel
+
 template <class T>
-__global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
+__global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
                                                  int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS,
                                                  int bufET, int k0, int i, int phase) {
   constexpr int ST = 2 * Tiles<T>::HT;
@@ -324,7 +326,7 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
     const int off = kp + 1, len = n - kp - 1;
     const T tau = taus[kp];
     const int nst = (len + ST - 1) / ST;
-    for (int r = tid; r < len; r += 256) v[r] = vg[r];
+    for (int r = tid; r < len; r += COLT) v[r] = vg[r];
     if (build && tid < ip) {
       wk[tid] = conjg(Wp[(long long)k * HB + tid]);
       vk[tid] = conjg(panel_v(A, n, k0, k, tid));
@@ -344,7 +346,7 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
     // y_r = fixed-order sum of the super-tile partials minus the panel
     // corrections; the same pass accumulates the panel part of the update of
     // the next column
-    for (int r = tid; r < len; r += 256) {
+    for (int r = tid; r < len; r += COLT) {
       const int Sr = r / ST;
       T acc = tzero<T>();
       for (int SJ = 0; SJ <= Sr; ++SJ) acc = acc + HS[(long long)SJ * len + r];
@@ -362,7 +364,7 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
       colacc[r] = ca;
     }
     double dr = 0.0, di = 0.0;
-    for (int r = tid; r < len; r += 256) {
+    for (int r = tid; r < len; r += COLT) {
       T yt = tau * y[r];
       y[r] = yt;
       T pv = conjg(yt) * v[r];
@@ -377,7 +379,7 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
     }
     __syncthreads();
     const T alpha = sh_alpha;
-    for (int r = tid; r < len; r += 256) {
+    for (int r = tid; r < len; r += COLT) {
       T w = mad(alpha, v[r], y[r]);
       y[r] = w;
       Wp[(long long)(off + r) * HB + ip] = w;
@@ -386,7 +388,7 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
     if (!build) return;
     // column k = off: A[r][k] -= (panel columns < ip) + v_r conj(w_0) + w_r conj(v_0), v_0 = 1
     const T w0c = conjg(y[0]);
-    for (int r = tid; r < len; r += 256) {
+    for (int r = tid; r < len; r += COLT) {
       long long idx = (long long)(off + r) * n + k;
       T a = A[idx] - colacc[r] - v[r] * w0c - y[r];
       if (r == 0) a = treal<T>(re(a));
@@ -411,7 +413,7 @@ __global__ void __launch_bounds__(256) k_tri_col(const BlockDesc* D, char* ws, c
     if (tid == 0) ee[k] = sh_beta;
   }
   const int len = n - k - 1;
-  for (int r = tid; r < len; r += 256) vg[r] = v[r];
+  for (int r = tid; r < len; r += COLT) vg[r] = v[r];
   if (tid == 0) {
     dd[k] = re(A[(long long)k * n + k]);
     taus[k] = sh_tau;
@@ -992,7 +994,7 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
   const int mvw_grid = 8 * ncu;         // one-wave work-groups (register-bound: 8 resident per CU)
   for (int k0 = 0; k0 < maxdim - 1; k0 += HB) {
     const int kbmax = std::min(HB, maxdim - 1 - k0);
-    hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufW,
+    hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(COLT), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufW,
                        bufV, bufHS, bufET, k0, 0, 0);
     for (int i = 0; i < kbmax; ++i) {
       const int k = k0 + i;
@@ -1011,7 +1013,7 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
                            bufW, k0, k, nblk, nsmax);
       }
       ktrace_end(kt, s);
-      hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(256), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau,
+      hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(COLT), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau,
                          bufW, bufV, bufHS, bufET, k0, i + 1, (i + 1 < kbmax) ? 1 : 2);
     }
     const int len2 = maxdim - (k0 + kbmax);

@@ -364,9 +364,10 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   // products of the X / L / S~ / R chain: FP64, or split bf16 slices
   const bool split = o->prec == X2C_SPLIT_BF16;
   const int slices = o->ozaki_slices > 0 ? o->ozaki_slices : AUTO_SLICES;
-  auto chain_gemm = [&](int bA, int opA, int bB, int opB, int bC, T alpha, T beta) {
+  // herm = 1 marks products whose result (and beta C) is Hermitian
+  auto chain_gemm = [&](int bA, int opA, int bB, int opB, int bC, T alpha, T beta, int herm = 0) {
     if (split) launch_gemm_split<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, slices);
-    else launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta);
+    else launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, herm);
   };
 
   {
@@ -445,17 +446,17 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
     STAGE("chain_SL");
     chain_gemm(C_T, OPN, C_X, OPN, C_TX, one, zero);
     launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_S, C_Q);
-    chain_gemm(C_X, OPH, C_TX, OPN, C_Q, tcast<T>(1.0 / (2.0 * c * c)), one);
+    chain_gemm(C_X, OPH, C_TX, OPN, C_Q, tcast<T>(1.0 / (2.0 * c * c)), one, 1);
     chain_gemm(C_WPP, OPN, C_X, OPN, C_WX, one, zero);
     launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_V, C_L);
     launch_add_herm<T>(s, D, ws, info, nblk, maxn, C_TX, C_L);
-    chain_gemm(C_X, OPH, C_WX, OPN, C_L, one, one);
+    chain_gemm(C_X, OPH, C_WX, OPN, C_L, one, one, 1);
   }
   {
     // Q = L_S^-1 S~ L_S^-H
     STAGE("chain_Q");
     chain_gemm(C_LSI, OPN, C_Q, OPN, C_TMP, one, zero);
-    chain_gemm(C_TMP, OPN, C_LSI, OPH, C_Q, one, zero);
+    chain_gemm(C_TMP, OPN, C_LSI, OPH, C_Q, one, zero, 1);
   }
   if (!kramers) {
     {
@@ -500,7 +501,7 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
     // h = R^H (L R)
     STAGE("chain_h");
     chain_gemm(C_L, OPN, C_R, OPN, C_LR, one, zero);
-    chain_gemm(C_R, OPH, C_LR, OPN, C_H, one, zero);
+    chain_gemm(C_R, OPH, C_LR, OPN, C_H, one, zero, 1);
   }
   {
     STAGE("write");

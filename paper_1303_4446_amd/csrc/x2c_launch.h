@@ -33,9 +33,11 @@ template <class T>
 void launch_write_h(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, double* h,
                     double* eps);
 
+// herm = 1: the product is Hermitian (and so is beta C); only the lower
+// triangle is computed and mirrored
 template <class T>
 void launch_gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
-                 int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta);
+                 int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int herm = 0);
 
 template <class T>
 void launch_gemm_split(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
