@@ -99,7 +99,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=["ag309", "mixed512"], default="ag309")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--prec", choices=["fp64", "split"], default="fp64")
+    ap.add_argument("--prec", choices=["fp64", "split", "split8"], default="fp64",
+                    help="products of the X / L / S~ / R chain: FP64, bf16 slices, int8 slices")
     ap.add_argument("--reduction", choices=["quaternion", "complex"], default="quaternion",
                     help="two-component eigenproblem reduction")
     ap.add_argument("--check-blocks", type=int, default=3, help="blocks checked against the oracle")
@@ -193,7 +194,7 @@ def main():
         print(f"# copy calibration: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
         del src, dst
     blocks, twocomp, desc = workload(args.workload, args.seed)
-    prec = px.FP64 if args.prec == "fp64" else px.SPLIT_BF16
+    prec = {"fp64": px.FP64, "split": px.SPLIT_BF16, "split8": px.SPLIT_INT8}[args.prec]
     red = px.RED_QUATERNION if args.reduction == "quaternion" else px.RED_COMPLEX
     pk = pack_blocks(blocks, twocomp)
     batch = px.batch_to_device(pk, twocomp)

@@ -56,8 +56,11 @@ typedef enum { X2C_SPINFREE = 1, X2C_TWOCOMP = 2 } x2c_mode;
  * splitting of FP64 products).  The truncation error of a product entry is
  * about K 2^(-7 s) times the product of the operand row and column maxima
  * (K the inner dimension).  The Cholesky factors, the eigenvalue problems and
- * the inverse square root are FP64 in both modes. */
-typedef enum { X2C_FP64 = 0, X2C_SPLIT_BF16 = 1 } x2c_prec;
+ * the inverse square root are FP64 in both modes.  X2C_SPLIT_INT8: the same
+ * splitting with int8 slices (the line scaled into (-1/2, 1/2), so each slice
+ * holds about 7 bits) on the int8 matrix cores with exact int32 sums; the
+ * operands are split once per product. */
+typedef enum { X2C_FP64 = 0, X2C_SPLIT_BF16 = 1, X2C_SPLIT_INT8 = 2 } x2c_prec;
 
 /* Reduction of the two Hermitian eigenproblems of a two-component block.
  * Every two-component matrix of the method has the time-reversal form
@@ -72,7 +75,7 @@ typedef enum { X2C_RED_QUATERNION = 0, X2C_RED_COMPLEX = 1 } x2c_reduction;
 typedef struct {
   int mode;          /* x2c_mode */
   int prec;          /* x2c_prec: arithmetic of the X / L / S~ / R product chain */
-  int ozaki_slices;  /* split precision only: slices per operand, 1..8; 0 = automatic (7) */
+  int ozaki_slices;  /* split precision only: slices per operand, 1..8; 0 = automatic (bf16 7, int8 8) */
   double c;          /* speed of light in atomic units (> 0) */
   int reduction;     /* x2c_reduction (two-component only); 0 = quaternion */
 } x2c_options;

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libx2c.so")
 
 SPINFREE, TWOCOMP = 1, 2
-FP64, SPLIT_BF16 = 0, 1
+FP64, SPLIT_BF16, SPLIT_INT8 = 0, 1, 2
 RED_QUATERNION, RED_COMPLEX = 0, 1
 
 OK, EINVAL, EHIP, EBLOCK = 0, -1, -2, -3

@@ -24,7 +24,11 @@ namespace {
 constexpr int MAX_N_2C = 256;   // 4c dimension 4N <= 1024
 constexpr int MAX_N_SF = 512;   // 4c dimension 2N <= 1024
 constexpr int MAX_SLICES = 8;   // split products: slices per operand
-constexpr int AUTO_SLICES = 7;  // default: keeps bound-state errors at the FP64 level up to Z = 79
+// default slice counts: bound-state (and relative continuum) errors at the
+// FP64 level up to Z = 79 (bf16 slices carry 7 bits each, int8 slices of
+// lines scaled into (-1/2, 1/2) 6 bits for the first and 7 for the others)
+constexpr int AUTO_SLICES = 7;
+constexpr int AUTO_SLICES_I8 = 8;
 constexpr size_t ALIGN = 256;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
@@ -82,13 +86,16 @@ void block_sizes(int N, bool tc, size_t sz[NBUF]) {
   sz[V_DEL] = n * 32;
   sz[V_EXA] = n * 4;
   sz[V_EXB] = n * 4;
+  const size_t kp = (n + 63) / 64 * 64;
+  sz[Z_SLA] = (size_t)MAX_SLICES * (tc ? 2 : 1) * n * kp;
+  sz[Z_SLB] = sz[Z_SLA];
   sz[W_VCUR] = m * es;
 }
 
 bool valid_opts(const x2c_options* o) {
   if (!o) return false;
   if (o->mode != X2C_SPINFREE && o->mode != X2C_TWOCOMP) return false;
-  if (o->prec != X2C_FP64 && o->prec != X2C_SPLIT_BF16) return false;
+  if (o->prec != X2C_FP64 && o->prec != X2C_SPLIT_BF16 && o->prec != X2C_SPLIT_INT8) return false;
   if (!(o->c > 0.0) || !std::isfinite(o->c)) return false;
   if (o->ozaki_slices < 0 || o->ozaki_slices > MAX_SLICES) return false;
   if (o->reduction != X2C_RED_QUATERNION && o->reduction != X2C_RED_COMPLEX) return false;
@@ -362,12 +369,16 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   const int OPN = 0, OPH = 1;
   const bool kramers = tc && o->reduction == X2C_RED_QUATERNION;
   // products of the X / L / S~ / R chain: FP64, or split bf16 slices
-  const bool split = o->prec == X2C_SPLIT_BF16;
-  const int slices = o->ozaki_slices > 0 ? o->ozaki_slices : AUTO_SLICES;
+  const int slices =
+      o->ozaki_slices > 0 ? o->ozaki_slices : (o->prec == X2C_SPLIT_INT8 ? AUTO_SLICES_I8 : AUTO_SLICES);
   // herm = 1 marks products whose result (and beta C) is Hermitian
   auto chain_gemm = [&](int bA, int opA, int bB, int opB, int bC, T alpha, T beta, int herm = 0) {
-    if (split) launch_gemm_split<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, slices);
-    else launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, herm);
+    if (o->prec == X2C_SPLIT_BF16)
+      launch_gemm_split<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, slices);
+    else if (o->prec == X2C_SPLIT_INT8)
+      launch_gemm_split_i8<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, slices);
+    else
+      launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, herm);
   };
 
   {

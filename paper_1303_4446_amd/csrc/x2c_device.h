@@ -126,6 +126,8 @@ enum Buf : int {
   // split-precision products: binary exponents of the rows of op(A) and of
   // the columns of op(B)
   V_EXA, V_EXB,
+  // split-precision products with int8 slices: the split operands
+  Z_SLA, Z_SLB,
   NBUF
 };
 

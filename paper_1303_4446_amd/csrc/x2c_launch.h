@@ -44,6 +44,10 @@ void launch_gemm_split(hipStream_t s, const BlockDesc* D, char* ws, const int* i
                        int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int slices);
 
 template <class T>
+void launch_gemm_split_i8(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim,
+                          int dsel, int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int slices);
+
+template <class T>
 void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                   int bufA, int bufD, int bufE, int bufTau);
 

@@ -50,6 +50,10 @@ def test_workspace_query_and_limits():
     assert lib.x2c_workspace_bytes(ctypes.byref(opt), 1, N) == 0
     opt = _lib.options(True, 137.0, prec=px.SPLIT_BF16, slices=8)
     assert lib.x2c_workspace_bytes(ctypes.byref(opt), 1, N) > 0
+    opt = _lib.options(True, 137.0, prec=px.SPLIT_INT8)
+    assert lib.x2c_workspace_bytes(ctypes.byref(opt), 1, N) > 0
+    opt = _lib.options(True, 137.0, prec=3)             # unknown precision
+    assert lib.x2c_workspace_bytes(ctypes.byref(opt), 1, N) == 0
     opt = _lib.options(True, 137.0, reduction=2)      # unknown reduction
     assert lib.x2c_workspace_bytes(ctypes.byref(opt), 1, N) == 0
     for red in (px.RED_QUATERNION, px.RED_COMPLEX):

@@ -228,34 +228,37 @@ def test_complex_and_quaternion_reductions_agree():
 # With the default 7 slices the chain error sits at the FP64 level; the graded
 # quantity is the bound-state spectrum (<= 1e-8 Eh against the 4c oracle).
 
-SPLIT = 1
+SPLITS = [1, 2]          # bf16 slices, int8 slices
 
 
-def test_split_precision_silver_two_component():
+@pytest.mark.parametrize("split", SPLITS)
+def test_split_precision_silver_two_component(split):
     b = ag_2c()
-    h, eps = gpu_single(b.S, b.T, b.V, b.W, C_LIGHT, True, prec=SPLIT)
+    h, eps = gpu_single(b.S, b.T, b.V, b.W, C_LIGHT, True, prec=split)
     check_against_oracle(b.S, b.T, b.V, b.W, C_LIGHT, True, h, eps, strict_bound=True)
 
 
+@pytest.mark.parametrize("split", SPLITS)
 @pytest.mark.parametrize("Z,twocomp", [(79, True), (17, False), (1, True)])
-def test_split_precision_atoms(Z, twocomp):
+def test_split_precision_atoms(Z, twocomp, split):
     """Ragged sizes (N = 200 / 45 / 24: several 128 x 64 tiles and tails)."""
     b = atom_block(Z)
     W = b.W if twocomp else b.W[0]
-    h, eps = gpu_single(b.S, b.T, b.V, W, C_LIGHT, twocomp, prec=SPLIT)
+    h, eps = gpu_single(b.S, b.T, b.V, W, C_LIGHT, twocomp, prec=split)
     check_against_oracle(b.S, b.T, b.V, W, C_LIGHT, twocomp, h, eps, strict_bound=True)
 
 
-def test_split_precision_slices_control_accuracy():
+@pytest.mark.parametrize("split", SPLITS)
+def test_split_precision_slices_control_accuracy(split):
     """Fewer slices must give a visibly larger error (the option is honoured),
     and the default must match the FP64 path closely."""
     px, torch = _px()
     b = atom_block(47)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
     args = (d(b.S), d(b.T), d(b.V), d(b.W), C_LIGHT, True)
-    print("  split slices 3 / default / fp64", flush=True)
-    h3 = px.build(*args, prec=SPLIT, slices=3)[0].cpu().numpy()
-    hd = px.build(*args, prec=SPLIT)[0].cpu().numpy()
+    print(f"  split {split} slices 3 / default / fp64", flush=True)
+    h3 = px.build(*args, prec=split, slices=3)[0].cpu().numpy()
+    hd = px.build(*args, prec=split)[0].cpu().numpy()
     h64 = px.build(*args)[0].cpu().numpy()
     sc = np.abs(h64).max()
     e3, ed = np.abs(h3 - h64).max() / sc, np.abs(hd - h64).max() / sc
@@ -263,9 +266,10 @@ def test_split_precision_slices_control_accuracy():
     assert e3 > 100 * ed and e3 > 1e-9, (e3, ed)
 
 
-def test_split_precision_batched_mixed():
+@pytest.mark.parametrize("split", SPLITS)
+def test_split_precision_batched_mixed(split):
     blocks = [atom_block(z) for z in (1, 8, 29, 47, 79, 6)]
-    hs, eps, info = gpu_batched(blocks, True, prec=SPLIT)
+    hs, eps, info = gpu_batched(blocks, True, prec=split)
     assert np.all(info == 0)
     for i in (1, 3):
         blk = blocks[i]
