@@ -968,6 +968,129 @@ __global__ void __launch_bounds__(256) k_ormtr_blocked(const BlockDesc* D, char*
   }
 }
 
+// ---------------------------------------------------------------- quaternion Q on the matrix cores
+// Y <- Q Y for quaternion Y (nr x nc) with the same panels and Tf factors, the
+// three products of each panel (W = V^H Y, W <- Tf W, Y -= V W) done as real
+// products on v_mfma_f64_16x16x4f64.  A quaternion q = q0 + q1 i + q2 j + q3 k
+// (components in storage order a.x, a.y, b.x, b.y) acts on the left as the
+// real 4 x 4 matrix L(q), L[c][d] = s(c, d) q_{c xor d}; a quaternion matrix
+// product is the real product of the L-blocks of the left factor with the
+// right factor's entries as 4-vectors, and L(conj q) = L(q)^T.
+// Work-group: 64 columns of Y, wave w owns columns 16 w .. 16 w + 15.  W stays
+// in registers: the MFMA result layout (row l/16 + 4 i, column l % 16) holds
+// component l/16 of W[a][col] for a = 4 b + i, which is exactly the operand
+// layout the next two products read.
+__device__ constexpr signed char QSGN[4][4] = {{1, -1, -1, -1}, {1, 1, -1, 1}, {1, 1, 1, -1}, {1, -1, 1, 1}};
+typedef __attribute__((ext_vector_type(4))) double qd4;
+
+__global__ void __launch_bounds__(256) k_ormtr_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel,
+                                                      int bufA, int bufTf, int bufY, int csel) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int nr = seldim(d, dsel);
+  const int nc = seldim(d, csel);
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= nc || nr < 2) return;
+  const quat* A = bufp<quat>(ws, d, bufA);
+  const quat* Tfb = bufp<quat>(ws, d, bufTf);
+  double* Y = reinterpret_cast<double*>(bufp<quat>(ws, d, bufY));
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int l16 = lane & 15, l4 = lane >> 4;     // MFMA row / column index and k index
+  const int col = c0 + 16 * wave + l16;           // this lane's Y column (B operand, result)
+  const bool cok = col < nc;
+  constexpr int VRQ = 32;                         // V panel rows per LDS chunk
+  // per lane: A-operand row l16 = (quaternion l16 / 4, component c = l16 % 4),
+  // k index d = l4; L(q)[c][d] = s(c, d) q_{c xor d}
+  const int aq = l16 >> 2, cq = l16 & 3, ix = cq ^ l4;
+  const double sgn1 = QSGN[l4][cq], sgn2 = QSGN[cq][l4];
+  __shared__ quat Vs[VRQ][ORB + 1];
+  __shared__ quat Ts[ORB][ORB + 1];
+  const int np = (nr - 1 + ORB - 1) / ORB;
+  for (int j = np - 1; j >= 0; --j) {
+    const int k0 = j * ORB;
+    const int kb = min(ORB, nr - 1 - k0);
+    const int r0 = k0 + 1;
+    __syncthreads();
+    for (int l = t; l < ORB * ORB; l += 256) Ts[l / ORB][l % ORB] = Tfb[(long long)j * ORB * ORB + l];
+    // ---- W_real (128 x 16 per wave) = L(V)^T Y_real over the panel rows
+    qd4 w[8];
+#pragma unroll
+    for (int ob = 0; ob < 8; ++ob) w[ob] = qd4{0.0, 0.0, 0.0, 0.0};
+    for (int rc = r0; rc < nr; rc += VRQ) {
+      __syncthreads();
+      for (int l = t; l < VRQ * ORB; l += 256) {
+        const int rr = l / ORB, a = l % ORB, r = rc + rr;
+        Vs[rr][a] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<quat>();
+      }
+      __syncthreads();
+      const int rend = min(VRQ, nr - rc);
+      double ybuf[VRQ];                     // B operands of the chunk: component l4 of Y[r][col]
+#pragma unroll
+      for (int rr = 0; rr < VRQ; ++rr)
+        ybuf[rr] = (cok && rr < rend) ? Y[((long long)(rc + rr) * nc + col) * 4 + l4] : 0.0;
+#pragma unroll
+      for (int rr = 0; rr < VRQ; ++rr) {
+        const double y = ybuf[rr];
+        const double* vrow = reinterpret_cast<const double*>(&Vs[rr][0]);
+#pragma unroll
+        for (int ob = 0; ob < 8; ++ob) {
+          // A row l16 -> quaternion a = 4 ob + l16/4, component c = l16 % 4; k = d = l4:
+          // L(V)^T[c][d] = L(V)[d][c] = s(d, c) V_{c xor d}
+          const double av = sgn1 * vrow[4 * (4 * ob + aq) + ix];
+          w[ob] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, y, w[ob], 0, 0, 0);
+        }
+      }
+    }
+    // ---- W <- Tf W  (Tf upper triangular: only b >= a contributes)
+    qd4 w2[8];
+#pragma unroll
+    for (int ob = 0; ob < 8; ++ob) {
+      w2[ob] = qd4{0.0, 0.0, 0.0, 0.0};
+      const double* trow = reinterpret_cast<const double*>(&Ts[4 * ob + aq][0]);
+#pragma unroll
+      for (int bq = 0; bq < ORB; ++bq) {
+        if (bq >= 4 * ob) {
+          const double av = sgn2 * trow[4 * bq + ix];                          // L(Tf[a][b])[c][d]
+          const double bv = w[bq >> 2][bq & 3];                                 // component l4 of W[b][col]
+          w2[ob] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, w2[ob], 0, 0, 0);
+        }
+      }
+    }
+    // ---- Y -= L(V) W, four quaternion rows per MFMA block
+    for (int rc = r0; rc < nr; rc += VRQ) {
+      __syncthreads();
+      for (int l = t; l < VRQ * ORB; l += 256) {
+        const int rr = l / ORB, a = l % ORB, r = rc + rr;
+        Vs[rr][a] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<quat>();
+      }
+      __syncthreads();
+      const int rend = min(VRQ, nr - rc);
+      for (int rb = 0; rb < rend; rb += 4) {
+        qd4 acc = qd4{0.0, 0.0, 0.0, 0.0};
+        const double* vrow = reinterpret_cast<const double*>(&Vs[rb + aq][0]);   // quaternion row rb + l16/4
+#pragma unroll
+        for (int a = 0; a < ORB; ++a) {
+          const double av = sgn2 * vrow[4 * a + ix];                            // L(V[r][a])[c][d]
+          const double bv = w2[a >> 2][a & 3];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        // result: row l4 + 4 i = (quaternion row rb + i, component l4), column l16
+        if (cok) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = rc + rb + i;
+            if (rb + i < rend) {
+              const long long idx = ((long long)r * nc + col) * 4 + l4;
+              Y[idx] = Y[idx] - acc[i];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 template <class T>
 void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                   int bufA, int bufD, int bufE, int bufTau) {
@@ -1038,9 +1161,14 @@ void launch_ormtr_blocked(hipStream_t s, const BlockDesc* D, char* ws, const int
   int np = (maxdim - 1 + ORB - 1) / ORB;
   if (np < 1) np = 1;
   hipLaunchKernelGGL(k_larft<T>, dim3(np, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA, bufTau, bufTf);
-  constexpr int CW = Tiles<T>::CW;
-  hipLaunchKernelGGL(k_ormtr_blocked<T>, dim3((maxcols + CW - 1) / CW, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
-                     bufTf, bufY, csel);
+  if constexpr (is_quat<T>()) {
+    hipLaunchKernelGGL(k_ormtr_q_mfma, dim3((maxcols + 63) / 64, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
+                       bufTf, bufY, csel);
+  } else {
+    constexpr int CW = Tiles<T>::CW;
+    hipLaunchKernelGGL(k_ormtr_blocked<T>, dim3((maxcols + CW - 1) / CW, nblk), dim3(256), 0, s, D, ws, info, dsel,
+                       bufA, bufTf, bufY, csel);
+  }
 }
 template void launch_ormtr_blocked<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int,
                                            int, int, int, int);
