@@ -76,30 +76,6 @@ __global__ void k_phase_q(const BlockDesc* D, char* ws, const int* info, int nbl
   }
 }
 
-// Quaternion subspace block Y_q (n x n/2, in C_Y) -> complex Y (m x n, in C_A)
-// with rows [L_alpha, L_beta, S_alpha, S_beta] and the Kramers pair of
-// columns (2j, 2j+1): q = a + b j gives (a, -b*) and (b, a*).
-__global__ void k_quat_to_cplx_Y(const BlockDesc* D, char* ws, const int* info) {
-  const int b = blockIdx.y;
-  const BlockDesc& d = D[b];
-  if (info[b]) return;
-  const int N = d.N, n = d.n, h = n / 2;
-  const quat* Yq = bufp<quat>(ws, d, C_Y);
-  cplx* Y = bufp<cplx>(ws, d, C_A);
-  const long long tot = (long long)n * h;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(e / h), j = (int)(e % h);
-    const quat q = Yq[e];
-    const int ia = i < N ? i : n + (i - N);
-    const int ib = i < N ? N + i : n + N + (i - N);
-    Y[(long long)ia * n + 2 * j] = q.a;
-    Y[(long long)ia * n + 2 * j + 1] = q.b;
-    Y[(long long)ib * n + 2 * j] = cplx{-q.b.x, q.b.y};
-    Y[(long long)ib * n + 2 * j + 1] = cplx{q.a.x, -q.a.y};
-  }
-}
-
 // complex n x n ([alpha; beta], Kramers-structured) -> quaternion N x N
 __global__ void k_cplx_to_quat(const BlockDesc* D, char* ws, const int* info, int src, int dst) {
   const int b = blockIdx.y;
@@ -165,10 +141,6 @@ void launch_assemble_Aq(hipStream_t s, const BlockDesc* D, char* ws, const int* 
 }
 void launch_phase_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int dsel) {
   hipLaunchKernelGGL(k_phase_q, dim3((nblk + 63) / 64), dim3(64), 0, s, D, ws, info, nblk, dsel);
-}
-void launch_quat_to_cplx_Y(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn) {
-  hipLaunchKernelGGL(k_quat_to_cplx_Y, dim3(grid_for((long long)maxn * maxn / 2), nblk), dim3(256), 0, s, D, ws,
-                     info);
 }
 void launch_cplx_to_quat(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
                          int dst) {

@@ -14,11 +14,11 @@ constexpr int LB = 32;
 
 // Factor panel J (columns LB*J .. +jb, rows LB*J .. n-1) of Y_L in place.
 template <class T>
-__global__ void __launch_bounds__(256) k_lu_panel(const BlockDesc* D, char* ws, int* info, int J, int bufY) {
+__global__ void __launch_bounds__(256) k_lu_panel(const BlockDesc* D, char* ws, int* info, int J, int bufY, int dsel) {
   const int b = blockIdx.x;
   const BlockDesc& d = D[b];
   if (info[b]) return;
-  const int n = d.n, j0 = LB * J;
+  const int n = seldim(d, dsel), j0 = LB * J;
   if (j0 >= n) return;
   const int jb = min(LB, n - j0);
   T* A = bufp<T>(ws, d, bufY);
@@ -63,11 +63,7 @@ __global__ void __launch_bounds__(256) k_lu_panel(const BlockDesc* D, char* ws, 
         A[(long long)pp * n + c] = t;
       }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      T dj = A[(long long)j * n + j];
-      if constexpr (sizeof(T) == sizeof(double)) s_inv = treal<T>(1.0 / re(dj));
-      else s_inv = crecip(*reinterpret_cast<cplx*>(&dj));
-    }
+    if (threadIdx.x == 0) s_inv = tinv(A[(long long)j * n + j]);
     if (threadIdx.x < jb) rowj[threadIdx.x] = A[(long long)j * n + j0 + threadIdx.x];
     __syncthreads();
     const T inv = s_inv;
@@ -85,11 +81,12 @@ __global__ void __launch_bounds__(256) k_lu_panel(const BlockDesc* D, char* ws, 
 
 // U12 = L11^-1 A12 for the block row of panel J (unit lower L11); thread per column.
 template <class T>
-__global__ void __launch_bounds__(256) k_lu_trsm12(const BlockDesc* D, char* ws, const int* info, int J, int bufY) {
+__global__ void __launch_bounds__(256) k_lu_trsm12(const BlockDesc* D, char* ws, const int* info, int J, int bufY,
+                                                   int dsel) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
-  const int n = d.n, j0 = LB * J;
+  const int n = seldim(d, dsel), j0 = LB * J;
   if (j0 >= n) return;
   const int jb = min(LB, n - j0);
   T* A = bufp<T>(ws, d, bufY);
@@ -101,6 +98,16 @@ __global__ void __launch_bounds__(256) k_lu_trsm12(const BlockDesc* D, char* ws,
   __syncthreads();
   const int c = j0 + jb + blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
+  if constexpr (is_quat<T>()) {
+    // forward substitution in place (a register column of 32 quaternions
+    // would not fit): column entries re-read from memory
+    for (int i = 1; i < jb; ++i) {
+      T acc = A[(long long)(j0 + i) * n + c];
+      for (int k = 0; k < i; ++k) acc = acc - L11[i][k] * A[(long long)(j0 + k) * n + c];
+      A[(long long)(j0 + i) * n + c] = acc;
+    }
+    return;
+  }
   T col[LB];
 #pragma unroll
   for (int i = 0; i < LB; ++i) col[i] = i < jb ? A[(long long)(j0 + i) * n + c] : tzero<T>();
@@ -116,52 +123,63 @@ __global__ void __launch_bounds__(256) k_lu_trsm12(const BlockDesc* D, char* ws,
 
 // A22 -= L21 U12 (trailing rows/cols >= LB*J + jb), 64 x 64 output tiles.
 template <class T>
-__global__ void __launch_bounds__(256) k_lu_update(const BlockDesc* D, char* ws, const int* info, int J, int bufY) {
+struct LuTile {
+  static constexpr int UT = 64;   // trailing-update output tile
+};
+template <>
+struct LuTile<quat> {
+  static constexpr int UT = 32;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_lu_update(const BlockDesc* D, char* ws, const int* info, int J, int bufY,
+                                                   int dsel) {
+  constexpr int UT = LuTile<T>::UT, UR = UT / 16;
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
-  const int n = d.n, j0 = LB * J;
+  const int n = seldim(d, dsel), j0 = LB * J;
   if (j0 >= n) return;
   const int jb = min(LB, n - j0);
   const int t0 = j0 + jb, len = n - t0;
   if (len <= 0) return;
-  const int nt = (len + 63) / 64;
+  const int nt = (len + UT - 1) / UT;
   if ((int)blockIdx.x >= nt * nt) return;
-  const int r0 = t0 + 64 * (blockIdx.x / nt), c0 = t0 + 64 * (blockIdx.x % nt);
+  const int r0 = t0 + UT * (blockIdx.x / nt), c0 = t0 + UT * (blockIdx.x % nt);
   T* A = bufp<T>(ws, d, bufY);
-  __shared__ T Ls[64][LB + 1];
-  __shared__ T Us[LB][64 + 1];
-  for (int e = threadIdx.x; e < 64 * LB; e += 256) {
+  __shared__ T Ls[UT][LB + 1];
+  __shared__ T Us[LB][UT + 1];
+  for (int e = threadIdx.x; e < UT * LB; e += 256) {
     int i = e / LB, k = e % LB;
     Ls[i][k] = (r0 + i < n && k < jb) ? A[(long long)(r0 + i) * n + j0 + k] : tzero<T>();
-    int kk = e / 64, cc = e % 64;
+    int kk = e / UT, cc = e % UT;
     Us[kk][cc] = (kk < jb && c0 + cc < n) ? A[(long long)(j0 + kk) * n + c0 + cc] : tzero<T>();
   }
   __syncthreads();
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  T acc[4][4];
+  T acc[UR][UR];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < UR; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = tzero<T>();
+    for (int j = 0; j < UR; ++j) acc[i][j] = tzero<T>();
 #pragma unroll 4
   for (int k = 0; k < LB; ++k) {
-    T a[4], bb[4];
+    T a[UR], bb[UR];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = Ls[ty + 16 * i][k];
+    for (int i = 0; i < UR; ++i) a[i] = Ls[ty + 16 * i][k];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bb[j] = Us[k][tx + 16 * j];
+    for (int j = 0; j < UR; ++j) bb[j] = Us[k][tx + 16 * j];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < UR; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = mad(a[i], bb[j], acc[i][j]);
+      for (int j = 0; j < UR; ++j) acc[i][j] = mad(a[i], bb[j], acc[i][j]);
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < UR; ++i) {
     int r = r0 + ty + 16 * i;
     if (r >= n) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < UR; ++j) {
       int c = c0 + tx + 16 * j;
       if (c >= n) continue;
       long long idx = (long long)r * n + c;
@@ -175,11 +193,12 @@ __global__ void __launch_bounds__(256) k_lu_update(const BlockDesc* D, char* ws,
 //   lower: Z_J = (Z_J - Z_{>J} L_{>J,J}) L_JJ^-1, unit L (J descending)
 // Work-group: 64 rows x LB columns.
 template <class T, bool UPPER>
-__global__ void __launch_bounds__(256) k_rsolve_blk(const BlockDesc* D, char* ws, const int* info, int J, int bufY) {
+__global__ void __launch_bounds__(256) k_rsolve_blk(const BlockDesc* D, char* ws, const int* info, int J, int bufY,
+                                                    int dsel) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
-  const int n = d.n, j0 = LB * J;
+  const int n = seldim(d, dsel), j0 = LB * J;
   if (j0 >= n) return;
   const int jb = min(LB, n - j0);
   const int r0 = 64 * blockIdx.x;
@@ -239,9 +258,7 @@ __global__ void __launch_bounds__(256) k_rsolve_blk(const BlockDesc* D, char* ws
       for (int j = 0; j < jb; ++j) {
         T s = z[j];
         for (int i = 0; i < j; ++i) s = s - z[i] * Ms[i][j];
-        T u = Ms[j][j];
-        if constexpr (sizeof(T) == sizeof(double)) z[j] = treal<T>(re(s) / re(u));
-        else z[j] = cdiv(*reinterpret_cast<cplx*>(&s), *reinterpret_cast<cplx*>(&u));
+        z[j] = rdiv(s, Ms[j][j]);
       }
     } else {
       for (int j = jb - 1; j >= 0; --j) {
@@ -261,14 +278,15 @@ __global__ void __launch_bounds__(256) k_rsolve_blk(const BlockDesc* D, char* ws
 // X~ = W P_{n-1} ... P_0 (column interchanges in reverse pivot order), as a
 // gather into C_TMP.  One work-group per block.
 template <class T>
-__global__ void __launch_bounds__(256) k_permute_cols(const BlockDesc* D, char* ws, const int* info, int bufY) {
+__global__ void __launch_bounds__(256) k_permute_cols(const BlockDesc* D, char* ws, const int* info, int bufY,
+                                                      int dsel, int bufX) {
   const int b = blockIdx.x;
   const BlockDesc& d = D[b];
   if (info[b]) return;
-  const int n = d.n;
+  const int n = seldim(d, dsel);
   const int* piv = bufp<int>(ws, d, V_PIV);
   const T* W = bufp<T>(ws, d, bufY) + (long long)n * n;
-  T* X = bufp<T>(ws, d, C_TMP);
+  T* X = bufp<T>(ws, d, bufX);
   __shared__ int idx[1024];
   for (int c = threadIdx.x; c < n; c += blockDim.x) idx[c] = c;
   __syncthreads();
@@ -286,25 +304,29 @@ __global__ void __launch_bounds__(256) k_permute_cols(const BlockDesc* D, char* 
 }
 
 template <class T>
-void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn, int bufY) {
+void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn, int bufY, int dsel,
+                       int bufX) {
+  constexpr int UT = LuTile<T>::UT;
   const int nJ = (maxn + LB - 1) / LB;
   for (int J = 0; J < nJ; ++J) {
-    hipLaunchKernelGGL(k_lu_panel<T>, dim3(nblk), dim3(256), 0, s, D, ws, info, J, bufY);
+    hipLaunchKernelGGL(k_lu_panel<T>, dim3(nblk), dim3(256), 0, s, D, ws, info, J, bufY, dsel);
     const int rest = maxn - LB * J - LB;
     if (rest > 0) {
-      hipLaunchKernelGGL(k_lu_trsm12<T>, dim3((rest + 255) / 256, nblk), dim3(256), 0, s, D, ws, info, J, bufY);
-      const int nt = (rest + 63) / 64;
-      hipLaunchKernelGGL(k_lu_update<T>, dim3(nt * nt, nblk), dim3(256), 0, s, D, ws, info, J, bufY);
+      hipLaunchKernelGGL(k_lu_trsm12<T>, dim3((rest + 255) / 256, nblk), dim3(256), 0, s, D, ws, info, J, bufY,
+                         dsel);
+      const int nt = (rest + UT - 1) / UT;
+      hipLaunchKernelGGL(k_lu_update<T>, dim3(nt * nt, nblk), dim3(256), 0, s, D, ws, info, J, bufY, dsel);
     }
   }
   const int nr = (maxn + 63) / 64;
   for (int J = 0; J < nJ; ++J)
-    hipLaunchKernelGGL((k_rsolve_blk<T, true>), dim3(nr, nblk), dim3(256), 0, s, D, ws, info, J, bufY);
+    hipLaunchKernelGGL((k_rsolve_blk<T, true>), dim3(nr, nblk), dim3(256), 0, s, D, ws, info, J, bufY, dsel);
   for (int J = nJ - 1; J >= 0; --J)
-    hipLaunchKernelGGL((k_rsolve_blk<T, false>), dim3(nr, nblk), dim3(256), 0, s, D, ws, info, J, bufY);
-  hipLaunchKernelGGL(k_permute_cols<T>, dim3(nblk), dim3(256), 0, s, D, ws, info, bufY);
+    hipLaunchKernelGGL((k_rsolve_blk<T, false>), dim3(nr, nblk), dim3(256), 0, s, D, ws, info, J, bufY, dsel);
+  hipLaunchKernelGGL(k_permute_cols<T>, dim3(nblk), dim3(256), 0, s, D, ws, info, bufY, dsel, bufX);
 }
-template void launch_xsolve_blk<double>(hipStream_t, const BlockDesc*, char*, int*, int, int, int);
-template void launch_xsolve_blk<cplx>(hipStream_t, const BlockDesc*, char*, int*, int, int, int);
+template void launch_xsolve_blk<double>(hipStream_t, const BlockDesc*, char*, int*, int, int, int, int, int);
+template void launch_xsolve_blk<cplx>(hipStream_t, const BlockDesc*, char*, int*, int, int, int, int, int);
+template void launch_xsolve_blk<quat>(hipStream_t, const BlockDesc*, char*, int*, int, int, int, int, int);
 
 }  // namespace x2c

@@ -206,10 +206,6 @@ struct Tiles<quat> {
   static constexpr int CW = 32;
   static constexpr int VR = 16;
 };
-template <class T>
-constexpr bool is_quat() {
-  return sizeof(T) == sizeof(quat);
-}
 
 // Quaternion Householder reflector for column k (rows k+1..n-1): with
 // x0 = A[k+1][k], sigma = (x0/|x0|) ||x||, u = x + sigma e1, the Hermitian

@@ -441,13 +441,18 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
     {
       STAGE("backtransform_4c");
       launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxn, maxN, DIM_n, C_A, V_TAU, W_TF4, C_Y, DIM_N);
-      launch_quat_to_cplx_Y(s, D, ws, info, nblk, maxn);
     }
   }
   {
     // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
     STAGE("x_solve");
-    launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn, kramers ? C_A : C_Y);
+    if (kramers) {
+      // quaternion LU of the N x N block Y_L; X~ converted to the complex layout
+      launch_xsolve_blk<quat>(s, D, ws, info, nblk, maxN, C_Y, DIM_N, C_QMH);
+      launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_QMH, C_TMP);
+    } else {
+      launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn, C_Y, DIM_n, C_TMP);
+    }
     chain_gemm(C_TMP, OPN, C_LS, OPH, C_TMP2, one, zero);
     chain_gemm(C_LTI, OPH, C_TMP2, OPN, C_X,
                    tcast<T>(std::sqrt(2.0) * c), zero);

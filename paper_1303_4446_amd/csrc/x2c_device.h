@@ -94,6 +94,20 @@ __device__ inline cplx cdiv(cplx a, cplx b) {
 }
 __device__ inline cplx crecip(cplx b) { return cdiv(cplx{1.0, 0.0}, b); }
 
+template <class T>
+constexpr bool is_quat() {
+  return sizeof(T) == sizeof(quat);
+}
+
+// inverse and right division s u^-1 for every scalar type (quaternion inverse
+// = conj(q) / |q|^2; the order matters for quaternions)
+__device__ inline double tinv(double u) { return 1.0 / u; }
+__device__ inline cplx tinv(cplx u) { return crecip(u); }
+__device__ inline quat tinv(quat u) { return (1.0 / abs2(u)) * conjg(u); }
+__device__ inline double rdiv(double s, double u) { return s / u; }
+__device__ inline cplx rdiv(cplx s, cplx u) { return cdiv(s, u); }
+__device__ inline quat rdiv(quat s, quat u) { return s * tinv(u); }
+
 // ---------------------------------------------------------------- workspace
 // Named per-block buffers.  Offsets (bytes from the workspace base) are laid
 // out by the host plan; every block owns its own region.

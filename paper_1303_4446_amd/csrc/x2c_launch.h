@@ -71,7 +71,6 @@ void launch_invsqrt_cols(hipStream_t s, const BlockDesc* D, char* ws, const int*
 
 void launch_assemble_Aq(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, double c);
 void launch_phase_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int dsel);
-void launch_quat_to_cplx_Y(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn);
 void launch_cplx_to_quat(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
                          int dst);
 void launch_quat_to_cplx(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
@@ -86,7 +85,10 @@ template <class T>
 void launch_dlu(hipStream_t s, const DluPair* P, int npairs, int maxnA, int maxnB, char* ws, const double* Tm,
                 const double* Vm, const double* Wm, int Ntot, double c, const double* X, const double* R, double* H);
 
+// X~ = Y_S Y_L^-1 for the (2 dim) x dim matrix Y in bufY (dim selected by
+// dsel), result (dim x dim) in bufX
 template <class T>
-void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn, int bufY);
+void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn, int bufY, int dsel,
+                       int bufX);
 
 }  // namespace x2c
