@@ -285,14 +285,22 @@ __global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws
 __global__ void k_filter_factor(const BlockDesc* D, char* ws, const int* info, int kramers) {
   const int b = blockIdx.y, j = blockIdx.x;
   const BlockDesc& d = D[b];
-  if (info[b] || threadIdx.x != 0) return;
+  if (info[b]) return;
   const double* pf = bufp<double>(ws, d, P_FILT);
   const int r = (int)pf[3];
   if (j >= r) return;
   const int m = kramers ? d.n : d.m;
+  // the tridiagonal in LDS: the elimination below is one serial chain
+  extern __shared__ double ff_sm[];
+  double* dg = ff_sm;
+  double* eg = ff_sm + m;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    dg[i] = bufp<double>(ws, d, V_D)[i];
+    eg[i] = i < m - 1 ? bufp<double>(ws, d, V_E)[i] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   const double sigma = pf[0], rho = pf[1], beta = pf[4 + RMAX + j];
-  const double* dg = bufp<double>(ws, d, V_D);
-  const double* eg = bufp<double>(ws, d, V_E);
   cplx* F = bufp<cplx>(ws, d, F_FAC) + (long long)j * m * 5;
   const double ir = 1.0 / rho;
   // running diagonal / superdiagonal of the current row (after elimination)
@@ -347,7 +355,8 @@ __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* 
   if (info[b]) return;
   const int m = kramers ? d.n : d.m, n = kramers ? d.n / 2 : d.n;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  if (blockIdx.x * blockDim.x >= n) return;       // whole work-group beyond the columns
+  const bool active = j < n;
   const double* pf = bufp<double>(ws, d, P_FILT);
   const double sigma = pf[0], rho = pf[1], M = pf[2];
   const int r = (int)pf[3];
@@ -358,44 +367,59 @@ __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* 
   cplx* scr = bufp<cplx>(ws, d, Z_SCR);
   const double ir = 1.0 / rho;
   // acc = T_s E_j
-  for (int i = 0; i < m; ++i) {
+  for (int i = 0; active && i < m; ++i) {
     double t = (dg[i] - sigma) * hash_uniform(i, j);
     if (i > 0) t += eg[i - 1] * hash_uniform(i - 1, j);
     if (i < m - 1) t += eg[i] * hash_uniform(i + 1, j);
     acc[(long long)i * n + j] = t * ir;
   }
+  extern __shared__ cplx Fs[];          // the current pole's factors, m x 5
   for (int q = 0; q < r; ++q) {
     const cplx* F = bufp<cplx>(ws, d, F_FAC) + (long long)q * m * 5;
     const double aq = pf[4 + q];
-    // forward: y = L^-1 P b, streamed
-    cplx carry = {hash_uniform(0, j), 0.0};
-    for (int i = 0; i < m - 1; ++i) {
-      const cplx* f = F + (long long)i * 5;
-      cplx bnext = {hash_uniform(i + 1, j), 0.0};
-      cplx yi;
-      if (f[4].x == 0.0) {
-        yi = carry;
-        carry = bnext - f[0] * carry;
-      } else {
-        yi = bnext;
-        carry = carry - f[0] * bnext;
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * 5; e += blockDim.x) Fs[e] = F[e];
+    __syncthreads();
+    if (active) {
+      // forward: y = L^-1 P b, streamed
+      cplx carry = {hash_uniform(0, j), 0.0};
+      for (int i = 0; i < m - 1; ++i) {
+        const cplx* f = Fs + i * 5;
+        const cplx bnext = {hash_uniform(i + 1, j), 0.0};
+        const bool sw = f[4].x != 0.0;
+        const cplx yi = sw ? bnext : carry;
+        carry = sw ? carry - f[0] * bnext : bnext - f[0] * carry;
+        scr[(long long)i * n + j] = yi;
       }
-      scr[(long long)i * n + j] = yi;
-    }
-    scr[(long long)(m - 1) * n + j] = carry;
-    // backward: U x = y;  acc += a_q Re(x)
-    cplx x1 = {0.0, 0.0}, x2 = {0.0, 0.0};
-    for (int i = m - 1; i >= 0; --i) {
-      const cplx* f = F + (long long)i * 5;
-      cplx y = scr[(long long)i * n + j];
-      cplx t = y - f[2] * x1 - f[3] * x2;
-      cplx x = t * f[1];
-      acc[(long long)i * n + j] += aq * x.x;
-      x2 = x1;
-      x1 = x;
+      scr[(long long)(m - 1) * n + j] = carry;
+      // backward: U x = y;  acc += a_q Re(x).  Rows are taken in groups of 8
+      // whose loads are issued together, ahead of the recurrence.
+      cplx x1 = {0.0, 0.0}, x2 = {0.0, 0.0};
+      for (int i0 = m - 1; i0 >= 0; i0 -= 8) {
+        cplx yb[8];
+        double ab[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int i = i0 - k;
+          yb[k] = i >= 0 ? scr[(long long)i * n + j] : cplx{0.0, 0.0};
+          ab[k] = i >= 0 ? acc[(long long)i * n + j] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int i = i0 - k;
+          if (i >= 0) {
+            const cplx* f = Fs + i * 5;
+            const cplx t = yb[k] - f[2] * x1 - f[3] * x2;
+            const cplx x = t * f[1];
+            acc[(long long)i * n + j] = ab[k] + aq * x.x;
+            x2 = x1;
+            x1 = x;
+          }
+        }
+      }
     }
   }
-  for (int i = 0; i < m; ++i) {
+  for (int i = 0; active && i < m; ++i) {
     long long idx = (long long)i * n + j;
     const double z = 0.5 * (hash_uniform(i, j) + M * acc[idx]);
     if constexpr (sizeof(T) == sizeof(quat)) Y[idx] = z * bufp<quat>(ws, d, V_DEL)[i];
@@ -531,13 +555,19 @@ void launch_tri_eig4c(hipStream_t s, const BlockDesc* D, char* ws, int* info, in
   size_t shm = (size_t)(4 * maxm + 2) * sizeof(double);
   hipLaunchKernelGGL(k_tri_eig4c, dim3(nblk), dim3(1024), shm, s, D, ws, info, eps, c, kramers);
 }
-void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int kramers) {
-  hipLaunchKernelGGL(k_filter_factor, dim3(RMAX, nblk), dim3(64), 0, s, D, ws, info, kramers);
+void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int kramers,
+                          int maxm_filter) {
+  hipLaunchKernelGGL(k_filter_factor, dim3(RMAX, nblk), dim3(64), 2 * (size_t)maxm_filter * sizeof(double), s, D, ws,
+                     info, kramers);
 }
 template <class T>
 void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxrhs,
                          int kramers) {
-  hipLaunchKernelGGL(k_filter_solve<T>, dim3((maxrhs + 255) / 256, nblk), dim3(256), 0, s, D, ws, info, kramers);
+  const int maxm = kramers ? maxrhs * 2 : 2 * maxrhs;      // rows of the tridiagonal
+  const size_t shm = (size_t)maxm * 5 * sizeof(cplx);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter_solve<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)shm);
+  hipLaunchKernelGGL(k_filter_solve<T>, dim3((maxrhs + 255) / 256, nblk), dim3(256), shm, s, D, ws, info, kramers);
 }
 void launch_tri_eig_q(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxdim, int dsel) {
   size_t shm = (size_t)(3 * maxdim) * sizeof(double);

@@ -415,7 +415,7 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
     }
     {
       STAGE("projector_4c");
-      launch_filter_factor(s, D, ws, info, nblk, 0);
+      launch_filter_factor(s, D, ws, info, nblk, 0, maxm);
       launch_filter_solve<T>(s, D, ws, info, nblk, maxn, 0);
     }
     {
@@ -435,7 +435,7 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
     }
     {
       STAGE("projector_4c");
-      launch_filter_factor(s, D, ws, info, nblk, 1);
+      launch_filter_factor(s, D, ws, info, nblk, 1, maxn);
       launch_filter_solve<quat>(s, D, ws, info, nblk, maxn / 2, 1);
     }
     {

@@ -60,7 +60,8 @@ void launch_ormtr_blocked(hipStream_t s, const BlockDesc* D, char* ws, const int
 
 void launch_tri_eig4c(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxm, double* eps,
                       double c, int kramers);
-void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int kramers);
+void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int kramers,
+                          int maxm_filter);
 template <class T>
 void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxrhs,
                          int kramers);
