@@ -257,7 +257,7 @@ def main():
         achieved = per_launch_b / (avg_ms / 1e3) / 1e9
         traffic = None
         if args.workload == "ag309" and twocomp and args.reduction == "quaternion":
-            traffic = recorded_traffic("paper_1303_4446_amd/csrc/k_tridiag.hip",
+            traffic = recorded_traffic("paper_1303_4446_amd/csrc/k_matvec.hip",
                                        "profiles/k_tri_matvec_w_ag309_traffic.md")
         roofline = {"bound": "hbm", "kernel": "k_tri_matvec_w" if (twocomp and args.reduction == "quaternion")
                     else "k_tri_matvec", "achieved": achieved, "peak": PEAK_HBM_GBS,

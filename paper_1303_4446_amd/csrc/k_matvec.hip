@@ -1,0 +1,357 @@
+// Hermitian matrix-vector product of the trailing matrix, one launch per
+// column step of the blocked tridiagonalisation over the whole batch (the
+// memory-bound kernel of the reduction: the lower triangle is read once).
+#include "x2c_device.h"
+#include "x2c_launch.h"
+#include "x2c_tridiag.h"
+
+namespace x2c {
+
+// Lower-triangle matvec y = A[k+1:, k+1:] v_k, persistent over the batch.
+// Work items are (block, lower super-tile (SI, SJ) of 2 HT x 2 HT); a work-group
+// walks items blockIdx.x, +gridDim.x, ... and prefetches the next item's
+// sub-tile into registers while reducing the current one.  Wave w stages
+// sub-tile (w>>1, w&1) in LDS (for a diagonal super-tile the upper sub-tile
+// is the conjugate transpose of its mirror, so the block acts as a full
+// Hermitian block).  The four waves' sums are combined in a fixed order; the
+// super-tile writes its row partial HS[SJ*len + r] and, off the diagonal,
+// its column partial HS[(nst + SI)*len + c]; a diagonal super-tile also
+// writes its strip's part of the panel dot products (W^H v, V^H v).
+struct MvItem {
+  int valid, b, SI, SJ, len, n, nst;
+};
+
+__device__ inline MvItem mv_decode(const BlockDesc* D, const int* info, int dsel, int k, int nblk, int nsmax,
+                                   int item, int ST) {
+  MvItem it{0, 0, 0, 0, 0, 0, 0};
+  const int b = item / nsmax, st = item - (item / nsmax) * nsmax;
+  if (b >= nblk || info[b]) return it;
+  const int n = seldim(D[b], dsel);
+  const int len = n - k - 1;
+  if (len <= 0) return it;
+  const int nst = (len + ST - 1) / ST;
+  if (st >= nst * (nst + 1) / 2) return it;
+  int SI = (int)((sqrt(8.0 * st + 1.0) - 1.0) * 0.5);
+  while ((SI + 1) * (SI + 2) / 2 <= st) ++SI;
+  while (SI * (SI + 1) / 2 > st) --SI;
+  it.valid = 1;
+  it.b = b;
+  it.SI = SI;
+  it.SJ = st - SI * (SI + 1) / 2;
+  it.len = len;
+  it.n = n;
+  it.nst = nst;
+  return it;
+}
+
+template <class T>
+__device__ inline void mv_load(const BlockDesc* D, char* ws, int bufA, int k, const MvItem& it, int wi, int wj,
+                               int lane, T* regs) {
+  constexpr int HT = Tiles<T>::HT, ST = 2 * HT, EPL = HT * HT / 64, RPI = 64 / HT;
+  const T* A = bufp<T>(ws, D[it.b], bufA);
+  const int off = k + 1, len = it.len, n = it.n;
+  const bool diag = it.SI == it.SJ;
+  const int rowbase = ST * it.SI + HT * wi, colbase = ST * it.SJ + HT * wj;
+  const bool upper = diag && wi < wj, dsub = diag && wi == wj;
+  const int lr0 = upper ? colbase : rowbase, lc0 = upper ? rowbase : colbase;
+#pragma unroll
+  for (int q = 0; q < EPL; ++q) {
+    const int ii = lane / HT + RPI * q, jj = lane % HT;
+    const int r = lr0 + ii, c = lc0 + jj;
+    regs[q] = (r < len && c < len && (!dsub || ii >= jj)) ? A[(long long)(off + r) * n + off + c] : tzero<T>();
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
+                                                    int bufV, int bufHS, int bufW, int k0, int k, int nblk,
+                                                    int nsmax) {
+  constexpr int HT = Tiles<T>::HT, ST = 2 * HT, EPL = HT * HT / 64, RPI = 64 / HT;
+  constexpr int RPG = ST / 8;          // rows per group in the panel dot products
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wi = wave >> 1, wj = wave & 1;
+  __shared__ T tiles[4][HT][HT + 1];
+  __shared__ T comb[4][HT];
+  __shared__ T vsh[4][2][HT];
+  __shared__ T tpart[8][HB][2];
+  T (*tl)[HT + 1] = tiles[wave];
+  const int total = nblk * nsmax;
+  int item = blockIdx.x;
+  MvItem cur = mv_decode(D, info, dsel, k, nblk, nsmax, item, ST);
+  T regs[EPL];
+  if (cur.valid) mv_load<T>(D, ws, bufA, k, cur, wi, wj, lane, regs);
+  while (item < total) {
+    const int nitem = item + gridDim.x;
+    const MvItem nxt = mv_decode(D, info, dsel, k, nblk, nsmax, nitem, ST);
+    T nregs[EPL];
+    if (nxt.valid) mv_load<T>(D, ws, bufA, k, nxt, wi, wj, lane, nregs);
+    if (cur.valid) {
+      const BlockDesc& d = D[cur.b];
+      const T* vg = bufp<T>(ws, d, bufV);
+      T* HS = bufp<T>(ws, d, bufHS);
+      const int len = cur.len, nst = cur.nst, SI = cur.SI, SJ = cur.SJ;
+      const bool diag = SI == SJ;
+      const int rowbase = ST * SI + HT * wi, colbase = ST * SJ + HT * wj;
+      const bool upper = diag && wi < wj, dsub = diag && wi == wj;
+      if (lane < HT) {
+        const int c = colbase + lane;
+        vsh[wave][0][lane] = c < len ? vg[c] : tzero<T>();
+      } else if (lane < 2 * HT) {
+        const int r = rowbase + lane - HT;
+        vsh[wave][1][lane - HT] = r < len ? vg[r] : tzero<T>();
+      }
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) tl[lane / HT + RPI * q][lane % HT] = regs[q];
+      wave_sync();
+      if (upper) {
+        for (int e = lane; e < HT * HT; e += 64) {
+          int ii = e / HT, jj = e % HT;
+          if (ii < jj) {
+            T x = tl[ii][jj];
+            tl[ii][jj] = conjg(tl[jj][ii]);
+            tl[jj][ii] = conjg(x);
+          } else if (ii == jj) {
+            tl[ii][ii] = conjg(tl[ii][ii]);
+          }
+        }
+        wave_sync();
+      } else if (dsub) {
+        for (int e = lane; e < HT * HT; e += 64) {
+          int ii = e / HT, jj = e % HT;
+          if (ii < jj) tl[ii][jj] = conjg(tl[jj][ii]);
+          else if (ii == jj) tl[ii][jj] = treal<T>(re(tl[ii][jj]));
+        }
+        wave_sync();
+      }
+      T sum = tzero<T>();
+      if (lane < HT) {
+#pragma unroll 8
+        for (int jj = 0; jj < HT; ++jj) sum = mad(tl[lane][jj], vsh[wave][0][jj], sum);
+      } else if (lane < 2 * HT && !diag) {
+        const int jj = lane - HT;
+#pragma unroll 8
+        for (int ii = 0; ii < HT; ++ii) sum = mad(conjg(tl[ii][jj]), vsh[wave][1][ii], sum);
+      }
+      if (lane < HT && wj == 1) comb[wi][lane] = sum;
+      if (lane >= HT && lane < 2 * HT && wi == 1) comb[2 + wj][lane - HT] = sum;
+      __syncthreads();
+      if (lane < HT && wj == 0) {
+        int r = rowbase + lane;
+        if (r < len) HS[(long long)SJ * len + r] = sum + comb[wi][lane];
+      }
+      if (!diag && lane >= HT && lane < 2 * HT && wi == 0) {
+        int c = colbase + lane - HT;
+        if (c < len) HS[(long long)(nst + SI) * len + c] = sum + comb[2 + wj][lane - HT];
+      }
+      if (diag) {
+        // this strip's part of the panel dot products (j < k - k0):
+        // TP[SI][j] = (sum_r conj(W(off+r, j)) v_r, sum_r conj(V(off+r, j)) v_r)
+        const int ip = k - k0, off = k + 1, n = cur.n;
+        const T* A = bufp<T>(ws, d, bufA);
+        const T* Wp = bufp<T>(ws, d, bufW);
+        const int j = threadIdx.x & (HB - 1), g = threadIdx.x >> 5;
+        T s1 = tzero<T>(), s2 = tzero<T>();
+        if (j < ip) {
+#pragma unroll
+          for (int q = 0; q < RPG; ++q) {
+            const int r = ST * SI + RPG * g + q;
+            if (r < len) {
+              const T vr = vg[r];
+              s1 = mad(conjg(Wp[(long long)(off + r) * HB + j]), vr, s1);
+              s2 = mad(conjg(panel_v(A, n, k0, off + r, j)), vr, s2);
+            }
+          }
+        }
+        tpart[g][j][0] = s1;
+        tpart[g][j][1] = s2;
+        __syncthreads();
+        if (threadIdx.x < HB) {
+          T a1 = tzero<T>(), a2 = tzero<T>();
+          for (int gg = 0; gg < 8; ++gg) {
+            a1 = a1 + tpart[gg][threadIdx.x][0];
+            a2 = a2 + tpart[gg][threadIdx.x][1];
+          }
+          T* TP = HS + (long long)2 * nst * len;
+          TP[((long long)SI * HB + threadIdx.x) * 2] = a1;
+          TP[((long long)SI * HB + threadIdx.x) * 2 + 1] = a2;
+        }
+      }
+      __syncthreads();
+    }
+    item = nitem;
+    cur = nxt;
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) regs[q] = nregs[q];
+  }
+}
+
+// Sum over the four lanes of a quad (lanes 4t..4t+3) with DPP quad
+// permutations (no LDS traffic).
+__device__ inline double quad_sum(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  double y = x + __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false),
+                                  __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false));     // lane ^ 1
+  lo = __double2loint(y);
+  hi = __double2hiint(y);
+  return y + __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false),
+                              __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false));      // lane ^ 2
+}
+__device__ inline quat quad_sum(const quat& q) {
+  return quat{cplx{quad_sum(q.a.x), quad_sum(q.a.y)}, cplx{quad_sum(q.b.x), quad_sum(q.b.y)}};
+}
+
+// Quaternion matvec, one independent wave per 32 x 32 super-tile (persistent
+// over the batch; work-groups of one wave, so no work-group barriers).  The
+// wave issues the loads of all four 16 x 16 sub-tiles (three on the
+// diagonal) and of the two vector segments at once, then stages the
+// sub-tiles one by one through its own LDS tile.  Row sums: lane (i, q)
+// covers row i, columns 4q..4q+3; column sums: lane (j, q) covers column j,
+// rows 4q..4q+3; quads are reduced with DPP.  Output and panel dot products
+// as for k_tri_matvec (a diagonal super-tile writes its full Hermitian
+// product as the row partial).
+constexpr int MVW_HT = 16;
+
+__global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* ws, const int* info, int dsel,
+                                                     int bufA, int bufV, int bufHS, int bufW, int k0, int k,
+                                                     int nblk, int nsmax) {
+  constexpr int HT = MVW_HT, ST = 2 * HT, EPL = HT * HT / 64;
+  const int lane = threadIdx.x;
+  __shared__ quat tl[HT][HT + 1];
+  __shared__ quat vsh[2][ST];          // [0] row segment, [1] column segment
+  __shared__ quat racc[ST], cacc[ST];
+  const int total = nblk * nsmax;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const MvItem it = mv_decode(D, info, dsel, k, nblk, nsmax, item, ST);
+    if (!it.valid) continue;
+    const BlockDesc& d = D[it.b];
+    const quat* A = bufp<quat>(ws, d, bufA);
+    const quat* vg = bufp<quat>(ws, d, bufV);
+    quat* HS = bufp<quat>(ws, d, bufHS);
+    const int off = k + 1, len = it.len, n = it.n, nst = it.nst, SI = it.SI, SJ = it.SJ;
+    const bool diag = SI == SJ;
+    const int R0 = ST * SI, C0 = ST * SJ;
+    // ---- issue every load of the item
+    quat regs[4][EPL];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int a = s >> 1, bb = s & 1;
+      const bool skip = diag && a == 0 && bb == 1;
+      const bool dsub = diag && a == bb;
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) {
+        const int ii = lane / HT + (64 / HT) * q, jj = lane % HT;
+        const int r = R0 + HT * a + ii, c = C0 + HT * bb + jj;
+        regs[s][q] = (!skip && r < len && c < len && (!dsub || ii >= jj))
+                         ? A[(long long)(off + r) * n + off + c] : tzero<quat>();
+      }
+    }
+    {
+      const int seg = lane >> 5, t = lane & 31;
+      const int g = (seg == 0 ? R0 : C0) + t;
+      vsh[seg][t] = g < len ? vg[g] : tzero<quat>();
+    }
+    if (lane < ST) {
+      racc[lane] = tzero<quat>();
+      cacc[lane] = tzero<quat>();
+    }
+    wave_sync();
+    // ---- sub-tiles
+    const int i4 = lane >> 2, q4 = lane & 3;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int a = s >> 1, bb = s & 1;
+      if (diag && a == 0 && bb == 1) continue;
+      const bool dsub = diag && a == bb;
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) tl[lane / HT + (64 / HT) * q][lane % HT] = regs[s][q];
+      wave_sync();
+      // row sums: row i4, columns 4 q4 .. 4 q4 + 3
+      quat rs = tzero<quat>();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = 4 * q4 + t;
+        quat e = tl[i4][j];
+        if (dsub && j == i4) e = treal<quat>(re(e));
+        rs = mad(e, vsh[1][HT * bb + j], rs);
+      }
+      // column sums: column i4, rows 4 q4 .. 4 q4 + 3 (strictly below the diagonal)
+      quat cs = tzero<quat>();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = 4 * q4 + t;
+        if (!dsub || i > i4) cs = mad(conjg(tl[i][i4]), vsh[0][HT * a + i], cs);
+      }
+      rs = quad_sum(rs);
+      cs = quad_sum(cs);
+      if (q4 == 0) {
+        racc[HT * a + i4] = racc[HT * a + i4] + rs;
+        cacc[HT * bb + i4] = cacc[HT * bb + i4] + cs;
+      }
+      wave_sync();
+    }
+    // ---- partial sums out
+    if (lane < ST) {
+      if (diag) {
+        const int r = R0 + lane;
+        if (r < len) HS[(long long)SJ * len + r] = racc[lane] + cacc[lane];
+      } else {
+        const int r = R0 + lane, c = C0 + lane;
+        if (r < len) HS[(long long)SJ * len + r] = racc[lane];
+        if (c < len) HS[(long long)(nst + SI) * len + c] = cacc[lane];
+      }
+    }
+    if (diag) {
+      // this strip's part of the panel dot products (j < k - k0)
+      const int ip = k - k0;
+      const quat* Wp = bufp<quat>(ws, d, bufW);
+      const int j = lane & (HB - 1), half = lane >> 5;
+      quat s1 = tzero<quat>(), s2 = tzero<quat>();
+      if (j < ip) {
+        for (int t = 0; t < HT; ++t) {
+          const int r = R0 + HT * half + t;
+          if (r < len) {
+            const quat vr = vsh[0][HT * half + t];
+            s1 = mad(conjg(Wp[(long long)(off + r) * HB + j]), vr, s1);
+            s2 = mad(conjg(panel_v(A, n, k0, off + r, j)), vr, s2);
+          }
+        }
+      }
+      // halves: lanes j and j + 32
+      __shared__ quat tsum[2][HB];
+      if (half == 1) {
+        tsum[0][j] = s1;
+        tsum[1][j] = s2;
+      }
+      wave_sync();
+      if (half == 0) {
+        quat* TP = HS + (long long)2 * nst * len;
+        TP[((long long)SI * HB + j) * 2] = s1 + tsum[0][j];
+        TP[((long long)SI * HB + j) * 2 + 1] = s2 + tsum[1][j];
+      }
+      wave_sync();
+    }
+  }
+}
+
+template <class T>
+void launch_matvec(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int dsel, int bufA,
+                   int bufV, int bufHS, int bufW, int k0, int k, int nsmax, int ncu) {
+  const long long items = (long long)nsmax * nblk;
+  if constexpr (is_quat<T>()) {
+    const int wgrid = (int)std::min<long long>(items, 8LL * ncu);   // one-wave work-groups, 8 resident per CU
+    hipLaunchKernelGGL(k_tri_matvec_w, dim3(wgrid), dim3(64), 0, s, D, ws, info, dsel, bufA, bufV, bufHS, bufW, k0,
+                       k, nblk, nsmax);
+  } else {
+    const int grid = (int)std::min<long long>(items, 2LL * ncu);    // two resident work-groups per CU (LDS)
+    hipLaunchKernelGGL(k_tri_matvec<T>, dim3(grid), dim3(256), 0, s, D, ws, info, dsel, bufA, bufV, bufHS, bufW,
+                       k0, k, nblk, nsmax);
+  }
+}
+template void launch_matvec<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
+                                    int, int, int, int);
+template void launch_matvec<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
+                                  int, int, int, int);
+template void launch_matvec<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
+                                  int, int, int, int);
+
+}  // namespace x2c

@@ -1,0 +1,52 @@
+// Shared pieces of the blocked Householder tridiagonalisation kernels
+// (internal to libx2c).
+#pragma once
+#include "x2c_device.h"
+
+namespace x2c {
+
+// Tile sizes per scalar type (quaternions are 32 bytes: smaller tiles keep
+// every kernel within the 160 KB of LDS per CU).
+template <class T>
+struct Tiles {
+  static constexpr int HT = 32;   // matvec sub-tile (super-tile / strip = 2 HT)
+  static constexpr int TT = 32;   // rank-2k update tile
+  static constexpr int LR = 64;   // larft row chunk
+  static constexpr int CW = 64;   // back-transformation columns per work-group
+  static constexpr int VR = 32;   // back-transformation V row chunk
+};
+template <>
+struct Tiles<quat> {
+  static constexpr int HT = 16;
+  static constexpr int TT = 16;
+  static constexpr int LR = 16;
+  static constexpr int CW = 32;
+  static constexpr int VR = 16;
+};
+
+// panel width (reflectors per panel)
+constexpr int HB = 32;
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// element (r, a) of panel V whose first reflector is k0 (dimension nr)
+template <class T>
+__device__ inline T panel_v(const T* A, int nr, int k0, int r, int a) {
+  int row1 = k0 + a + 1;            // row of the implicit unit entry
+  if (r < row1) return tzero<T>();
+  if (r == row1) return treal<T>(1.0);
+  return A[(long long)r * nr + k0 + a];
+}
+
+// Hermitian matvec y = A[k+1:, k+1:] v_k of the reduction step k over the
+// whole batch (k_matvec.hip); partial sums into bufHS in the layout the
+// column kernel reads.
+template <class T>
+void launch_matvec(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int dsel, int bufA,
+                   int bufV, int bufHS, int bufW, int k0, int k, int nsmax, int ncu);
+
+}  // namespace x2c
