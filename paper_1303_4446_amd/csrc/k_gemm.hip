@@ -228,6 +228,139 @@ k_gemm_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, i
       }
 }
 
+// Quaternion form of the product (Kramers-structured two-component
+// matrices, N x N quaternions A + B j for the complex 2N x 2N matrix).  With
+// q = (Re a, Im a, Re b, Im b), left multiplication by x is the real 4 x 4
+// matrix with entries qmul_sign(c, d) x_{c xor d}, so a quaternion
+// multiply-add is 16 real ones and the N x N quaternion product needs half
+// the real multiply-adds of the complex 2N x 2N product.  Operands are staged
+// in LDS as four component planes; each wave runs 2 x 2 blocks of 16 x 16
+// quaternions, 16 MFMAs per block and k step of 4.  alpha, beta are real.
+constexpr int qmul_sign(int c, int d) {
+  return c == 0 ? (d == 0 ? 1 : -1)
+                : (d == 0 || d == c || (c == 1 && d == 3) || (c == 2 && d == 1) || (c == 3 && d == 2)) ? 1 : -1;
+}
+
+__global__ void __launch_bounds__(256)
+k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, int opA, int bufB, int opB,
+              int bufC, double alpha, double beta, int herm) {
+  const int b = blockIdx.z;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = seldim(d, dsel);
+  const int m0 = blockIdx.y * GM_T, n0 = blockIdx.x * GM_T;
+  if (m0 >= n || n0 >= n) return;
+  if (herm && blockIdx.x > blockIdx.y) return;
+  const quat* A = bufp<quat>(ws, d, bufA);
+  const quat* B = bufp<quat>(ws, d, bufB);
+  quat* C = bufp<quat>(ws, d, bufC);
+  __shared__ double As[4][GM_T][GM_LD];      // [component][row][k]
+  __shared__ double Bs[4][GM_K][GM_T + 1];   // [component][k][col]
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  d4 acc[2][2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[x][y][c] = d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int NL = GM_T * GM_K / 256;
+  quat na[NL], nb[NL];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int l = t + 256 * q;
+      int r, kk;
+      if (opA == 0) { r = l / GM_K; kk = l % GM_K; } else { kk = l / GM_T; r = l % GM_T; }
+      const int gr = m0 + r, gk = k0 + kk;
+      na[q] = (gr < n && gk < n) ? (opA == 0 ? A[(long long)gr * n + gk] : conjg(A[(long long)gk * n + gr]))
+                                 : tzero<quat>();
+      int cc;
+      if (opB == 0) { kk = l / GM_T; cc = l % GM_T; } else { cc = l / GM_K; kk = l % GM_K; }
+      const int gk2 = k0 + kk, gc = n0 + cc;
+      nb[q] = (gk2 < n && gc < n) ? (opB == 0 ? B[(long long)gk2 * n + gc] : conjg(B[(long long)gc * n + gk2]))
+                                  : tzero<quat>();
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int l = t + 256 * q;
+      int r, kk;
+      if (opA == 0) { r = l / GM_K; kk = l % GM_K; } else { kk = l / GM_T; r = l % GM_T; }
+      As[0][r][kk] = na[q].a.x;
+      As[1][r][kk] = na[q].a.y;
+      As[2][r][kk] = na[q].b.x;
+      As[3][r][kk] = na[q].b.y;
+      int cc;
+      if (opB == 0) { kk = l / GM_T; cc = l % GM_T; } else { cc = l / GM_K; kk = l % GM_K; }
+      Bs[0][kk][cc] = nb[q].a.x;
+      Bs[1][kk][cc] = nb[q].a.y;
+      Bs[2][kk][cc] = nb[q].b.x;
+      Bs[3][kk][cc] = nb[q].b.y;
+    }
+  };
+  fetch(0);
+  stash();
+  __syncthreads();
+  for (int k0 = 0; k0 < n; k0 += GM_K) {
+    const bool more = k0 + GM_K < n;
+    if (more) fetch(k0 + GM_K);
+#pragma unroll
+    for (int ks = 0; ks < GM_K; ks += 4) {
+      double a[2][4], an[2][4], bq[2][4];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          a[x][c] = As[c][wr + 16 * x + l16][ks + l4];
+          an[x][c] = -a[x][c];
+          bq[x][c] = Bs[c][ks + l4][wc + 16 * x + l16];
+        }
+#pragma unroll
+      for (int dd = 0; dd < 4; ++dd)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                  qmul_sign(c, dd) > 0 ? a[x][c ^ dd] : an[x][c ^ dd], bq[y][dd], acc[x][y][c], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      stash();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = m0 + wr + 16 * x + l4 + 4 * i, cc = n0 + wc + 16 * y + l16;
+        if (r >= n || cc >= n) continue;
+        if (herm && cc > r) continue;
+        const long long idx = (long long)r * n + cc;
+        quat v = {{alpha * acc[x][y][0][i], alpha * acc[x][y][1][i]},
+                  {alpha * acc[x][y][2][i], alpha * acc[x][y][3][i]}};
+        if (beta != 0.0) v = v + beta * C[idx];
+        C[idx] = v;
+        if (herm && cc < r) C[(long long)cc * n + r] = conjg(v);
+      }
+}
+
+void launch_gemm_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
+                   int bufA, int opA, int bufB, int opB, int bufC, double alpha, double beta, int herm) {
+  int t = (maxdim + GM_T - 1) / GM_T;
+  hipLaunchKernelGGL(k_gemm_q_mfma, dim3(t, t, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA, opA, bufB, opB,
+                     bufC, alpha, beta, herm);
+}
+
 template <class T>
 void launch_gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                  int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int herm) {

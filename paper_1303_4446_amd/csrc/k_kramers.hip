@@ -129,6 +129,69 @@ __global__ void k_qct_scale(const BlockDesc* D, char* ws, const int* info, int s
   }
 }
 
+// Quaternion (N x N) form of the two-component matrices of the product
+// chain: S, T, V, L_S, L_S^-1, L_T^-1 are real scalar matrices (spin
+// diagonal), W'' = W/4c^2 - T has a = (W^0 - 4c^2 T + i W^z)/4c^2 and
+// b = (W^y + i W^x)/4c^2 (Eq. defw in the [alpha; beta] order).
+__global__ void k_expand_q(const BlockDesc* D, char* ws, const int* info, double c) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int N = d.N;
+  const long long nn = (long long)N * N;
+  const double q4 = 1.0 / (4.0 * c * c);
+  const double* s = bufp<double>(ws, d, R_S);
+  const double* t = bufp<double>(ws, d, R_T);
+  const double* v = bufp<double>(ws, d, R_V);
+  const double* ls = bufp<double>(ws, d, R_LS);
+  const double* lsi = bufp<double>(ws, d, R_LSI);
+  const double* lti = bufp<double>(ws, d, R_LTI);
+  const double* w0 = bufp<double>(ws, d, R_W0);
+  const double* wx = bufp<double>(ws, d, R_W1);
+  const double* wy = bufp<double>(ws, d, R_W2);
+  const double* wz = bufp<double>(ws, d, R_W3);
+  quat* oS = bufp<quat>(ws, d, C_S);
+  quat* oT = bufp<quat>(ws, d, C_T);
+  quat* oV = bufp<quat>(ws, d, C_V);
+  quat* oW = bufp<quat>(ws, d, C_WPP);
+  quat* oLS = bufp<quat>(ws, d, C_LS);
+  quat* oLSI = bufp<quat>(ws, d, C_LSI);
+  quat* oLTI = bufp<quat>(ws, d, C_LTI);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double tv = t[e];
+    oS[e] = treal<quat>(s[e]);
+    oT[e] = treal<quat>(tv);
+    oV[e] = treal<quat>(v[e]);
+    oLS[e] = treal<quat>(ls[e]);
+    oLSI[e] = treal<quat>(lsi[e]);
+    oLTI[e] = treal<quat>(lti[e]);
+    oW[e] = quat{{w0[e] * q4 - tv, wz[e] * q4}, {wy[e] * q4, wx[e] * q4}};
+  }
+}
+
+// quaternion N x N workspace buffer -> complex 2N x 2N at out + h_off (zero
+// for a failed block, whose eigenvalues are zeroed too when eps is given)
+__global__ void k_write_q(const BlockDesc* D, char* ws, const int* info, double* out, int buf, double* eps) {
+  const BlockDesc& d = D[blockIdx.y];
+  const int N = d.N, n = d.n;
+  const bool ok = info[blockIdx.y] == 0;
+  const quat* Q = bufp<quat>(ws, d, buf);
+  cplx* C = reinterpret_cast<cplx*>(out + d.h_off);
+  const long long tot = (long long)N * N;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    const quat q = ok ? Q[e] : tzero<quat>();
+    C[(long long)i * n + j] = q.a;
+    C[(long long)i * n + N + j] = q.b;
+    C[(long long)(N + i) * n + j] = cplx{-q.b.x, q.b.y};
+    C[(long long)(N + i) * n + N + j] = cplx{q.a.x, -q.a.y};
+  }
+  if (!ok && eps)
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) eps[d.eps_off + k] = 0.0;
+}
+
 static int grid_for(long long elems) {
   long long g = (elems + 255) / 256;
   if (g > 256) g = 256;
@@ -156,6 +219,15 @@ void launch_qct_scale(hipStream_t s, const BlockDesc* D, char* ws, const int* in
                       int dst) {
   hipLaunchKernelGGL(k_qct_scale, dim3(grid_for((long long)maxN * maxN), nblk), dim3(256), 0, s, D, ws, info, src,
                      dst);
+}
+
+void launch_expand_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double c) {
+  hipLaunchKernelGGL(k_expand_q, dim3(grid_for((long long)maxN * maxN), nblk), dim3(256), 0, s, D, ws, info, c);
+}
+void launch_write_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double* out,
+                    int buf, double* eps) {
+  hipLaunchKernelGGL(k_write_q, dim3(grid_for((long long)maxN * maxN), nblk), dim3(256), 0, s, D, ws, info, out, buf,
+                     eps);
 }
 
 }  // namespace x2c

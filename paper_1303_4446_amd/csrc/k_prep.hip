@@ -319,7 +319,7 @@ template <class T>
 __global__ void k_add_herm(const BlockDesc* D, char* ws, const int* info, int src, int dst) {
   const BlockDesc& d = D[blockIdx.y];
   if (info[blockIdx.y]) return;
-  const int n = d.n;
+  const int n = is_quat<T>() ? d.N : d.n;
   const long long nn = (long long)n * n;
   const T* s = bufp<T>(ws, d, src);
   T* o = bufp<T>(ws, d, dst);
@@ -445,5 +445,7 @@ void launch_write_h(hipStream_t s, const BlockDesc* D, char* ws, const int* info
   template void launch_write_h<T>(hipStream_t, const BlockDesc*, char*, const int*, int, int, double*, double*);
 X2C_INST(double)
 X2C_INST(cplx)
+template void launch_copy<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int);
+template void launch_add_herm<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int);
 
 }  // namespace x2c

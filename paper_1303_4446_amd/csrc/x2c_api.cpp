@@ -365,7 +365,6 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   const bool tc = o->mode == X2C_TWOCOMP;
   const double c = o->c;
   const int maxN = L.maxN, maxn = L.maxn, maxm = L.maxm;
-  const T one = tcast<T>(1.0), zero = tcast<T>(0.0);
   const int OPN = 0, OPH = 1;
   const bool kramers = tc && o->reduction == X2C_RED_QUATERNION;
   // products of the X / L / S~ / R chain: FP64, or split bf16 slices
@@ -380,6 +379,21 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
     else
       launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, herm);
   };
+  // FP64 time-reversal-symmetric chain: quaternion N x N products (half the
+  // real multiply-adds of the complex 2N x 2N ones); real alpha, beta
+  const bool qchain = kramers && o->prec == X2C_FP64;
+  auto G = [&](int bA, int opA, int bB, int opB, int bC, double alpha, double beta, int herm = 0) {
+    if (qchain) launch_gemm_q(s, D, ws, info, nblk, maxN, DIM_N, bA, opA, bB, opB, bC, alpha, beta, herm);
+    else chain_gemm(bA, opA, bB, opB, bC, tcast<T>(alpha), tcast<T>(beta), herm);
+  };
+  auto copy_buf = [&](int src, int dst) {
+    if (qchain) launch_copy<quat>(s, D, ws, info, nblk, maxN, DIM_N, src, dst);
+    else launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, src, dst);
+  };
+  auto add_herm = [&](int src, int dst) {
+    if (qchain) launch_add_herm<quat>(s, D, ws, info, nblk, maxN, src, dst);
+    else launch_add_herm<T>(s, D, ws, info, nblk, maxn, src, dst);
+  };
 
   {
     STAGE("prep");
@@ -387,7 +401,8 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
     launch_unpack(s, D, ws, info, nblk, maxN, S, Tm, V, W, tc ? 1 : 0);
     launch_potrf(s, D, ws, info, nblk, maxN);
     launch_trtri(s, D, ws, info, nblk, maxN);
-    launch_expand<T>(s, D, ws, info, nblk, maxn, c);
+    if (qchain) launch_expand_q(s, D, ws, info, nblk, maxN, c);
+    else launch_expand<T>(s, D, ws, info, nblk, maxn, c);
   }
   {
     // scalar-level reduction: L_S^-1 V L_S^-T, L_S^-1 L_T, L_T^-1 W^q L_T^-T
@@ -447,32 +462,32 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
     // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
     STAGE("x_solve");
     if (kramers) {
-      // quaternion LU of the N x N block Y_L; X~ converted to the complex layout
+      // quaternion LU of the N x N block Y_L (X~ to the complex layout unless
+      // the chain runs on quaternions)
       launch_xsolve_blk<quat>(s, D, ws, info, nblk, maxN, C_Y, DIM_N, C_QMH);
-      launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_QMH, C_TMP);
+      if (!qchain) launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_QMH, C_TMP);
     } else {
       launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn, C_Y, DIM_n, C_TMP);
     }
-    chain_gemm(C_TMP, OPN, C_LS, OPH, C_TMP2, one, zero);
-    chain_gemm(C_LTI, OPH, C_TMP2, OPN, C_X,
-                   tcast<T>(std::sqrt(2.0) * c), zero);
+    G(qchain ? C_QMH : C_TMP, OPN, C_LS, OPH, C_TMP2, 1.0, 0.0);
+    G(C_LTI, OPH, C_TMP2, OPN, C_X, std::sqrt(2.0) * c, 0.0);
   }
   {
     // S~ = S + X^H T X / 2c^2 ;  L = V + TX + (TX)^H + X^H (W/4c^2 - T) X
     STAGE("chain_SL");
-    chain_gemm(C_T, OPN, C_X, OPN, C_TX, one, zero);
-    launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_S, C_Q);
-    chain_gemm(C_X, OPH, C_TX, OPN, C_Q, tcast<T>(1.0 / (2.0 * c * c)), one, 1);
-    chain_gemm(C_WPP, OPN, C_X, OPN, C_WX, one, zero);
-    launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, C_V, C_L);
-    launch_add_herm<T>(s, D, ws, info, nblk, maxn, C_TX, C_L);
-    chain_gemm(C_X, OPH, C_WX, OPN, C_L, one, one, 1);
+    G(C_T, OPN, C_X, OPN, C_TX, 1.0, 0.0);
+    copy_buf(C_S, C_Q);
+    G(C_X, OPH, C_TX, OPN, C_Q, 1.0 / (2.0 * c * c), 1.0, 1);
+    G(C_WPP, OPN, C_X, OPN, C_WX, 1.0, 0.0);
+    copy_buf(C_V, C_L);
+    add_herm(C_TX, C_L);
+    G(C_X, OPH, C_WX, OPN, C_L, 1.0, 1.0, 1);
   }
   {
     // Q = L_S^-1 S~ L_S^-H
     STAGE("chain_Q");
-    chain_gemm(C_LSI, OPN, C_Q, OPN, C_TMP, one, zero);
-    chain_gemm(C_TMP, OPN, C_LSI, OPH, C_Q, one, zero, 1);
+    G(C_LSI, OPN, C_Q, OPN, C_TMP, 1.0, 0.0);
+    G(C_TMP, OPN, C_LSI, OPH, C_Q, 1.0, 0.0, 1);
   }
   if (!kramers) {
     {
@@ -489,10 +504,11 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
       launch_ormtr_blocked<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, W_TFQ, C_QMH, DIM_n);
     }
   } else {
+    const int qrefl = qchain ? C_Q : C_TMP2;   // quaternion Q, then its reflectors
     {
       STAGE("tridiag_Q");
-      launch_cplx_to_quat(s, D, ws, info, nblk, maxN, C_Q, C_TMP2);
-      launch_hetrd_mk<quat>(s, D, ws, info, nblk, maxN, DIM_N, C_TMP2, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS,
+      if (!qchain) launch_cplx_to_quat(s, D, ws, info, nblk, maxN, C_Q, C_TMP2);
+      launch_hetrd_mk<quat>(s, D, ws, info, nblk, maxN, DIM_N, qrefl, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS,
                             V_ET);
       launch_phase_q(s, D, ws, info, nblk, DIM_N);
     }
@@ -501,29 +517,35 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
       STAGE("invsqrt_Q");
       launch_tri_eig_q(s, D, ws, info, nblk, maxN, DIM_N);
       launch_invsqrt_cols<quat>(s, D, ws, info, nblk, maxN, DIM_N, C_QMH);
-      launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxN, maxN, DIM_N, C_TMP2, V_TAUQ, W_TFQ, C_TMP, DIM_N);
+      launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxN, maxN, DIM_N, qrefl, V_TAUQ, W_TFQ, C_TMP, DIM_N);
       launch_qct_scale(s, D, ws, info, nblk, maxN, C_TMP, C_LR);
-      launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxN, maxN, DIM_N, C_TMP2, V_TAUQ, W_TFQ, C_LR, DIM_N);
-      launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_LR, C_QMH);
+      launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxN, maxN, DIM_N, qrefl, V_TAUQ, W_TFQ, C_LR, DIM_N);
+      if (!qchain) launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_LR, C_QMH);
     }
   }
   {
     // R = L_S^-H Q^-1/2 L_S^H
     STAGE("chain_R");
-    chain_gemm(C_QMH, OPN, C_LS, OPH, C_TMP, one, zero);
-    chain_gemm(C_LSI, OPH, C_TMP, OPN, C_R, one, zero);
+    G(qchain ? C_LR : C_QMH, OPN, C_LS, OPH, C_TMP, 1.0, 0.0);
+    G(C_LSI, OPH, C_TMP, OPN, C_R, 1.0, 0.0);
   }
   {
     // h = R^H (L R)
     STAGE("chain_h");
-    chain_gemm(C_L, OPN, C_R, OPN, C_LR, one, zero);
-    chain_gemm(C_R, OPH, C_LR, OPN, C_H, one, zero, 1);
+    G(C_L, OPN, C_R, OPN, C_LR, 1.0, 0.0);
+    G(C_R, OPH, C_LR, OPN, C_H, 1.0, 0.0, 1);
   }
   {
     STAGE("write");
-    launch_write_h<T>(s, D, ws, info, nblk, maxn, h, eps);
-    if (Xo) launch_write_buf<T>(s, D, ws, info, nblk, maxn, Xo, C_X);
-    if (Ro) launch_write_buf<T>(s, D, ws, info, nblk, maxn, Ro, C_R);
+    if (qchain) {
+      launch_write_q(s, D, ws, info, nblk, maxN, h, C_H, eps);
+      if (Xo) launch_write_q(s, D, ws, info, nblk, maxN, Xo, C_X, nullptr);
+      if (Ro) launch_write_q(s, D, ws, info, nblk, maxN, Ro, C_R, nullptr);
+    } else {
+      launch_write_h<T>(s, D, ws, info, nblk, maxn, h, eps);
+      if (Xo) launch_write_buf<T>(s, D, ws, info, nblk, maxn, Xo, C_X);
+      if (Ro) launch_write_buf<T>(s, D, ws, info, nblk, maxn, Ro, C_R);
+    }
   }
   return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
 }

@@ -74,6 +74,11 @@ void launch_assemble_Aq(hipStream_t s, const BlockDesc* D, char* ws, const int* 
 void launch_phase_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int dsel);
 void launch_cplx_to_quat(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
                          int dst);
+void launch_expand_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double c);
+void launch_write_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double* out,
+                    int buf, double* eps);
+void launch_gemm_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
+                   int bufA, int opA, int bufB, int opB, int bufC, double alpha, double beta, int herm);
 void launch_quat_to_cplx(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
                          int dst);
 void launch_qct_scale(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
