@@ -307,12 +307,27 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
       const int j = lane & (HB - 1), half = lane >> 5;
       quat s1 = tzero<quat>(), s2 = tzero<quat>();
       if (j < ip) {
-        for (int t = 0; t < HT; ++t) {
-          const int r = R0 + HT * half + t;
-          if (r < len) {
-            const quat vr = vsh[0][HT * half + t];
-            s1 = mad(conjg(Wp[(long long)(off + r) * HB + j]), vr, s1);
-            s2 = mad(conjg(panel_v(A, n, k0, off + r, j)), vr, s2);
+        // rows off + r lie below the unit entry of every reflector of the
+        // panel, so V is read as stored; loads go out in groups of PG rows
+        // (clamped in-range addresses, masked values) so that their
+        // latencies overlap
+        constexpr int PG = 8;
+#pragma unroll 1
+        for (int t0 = 0; t0 < HT; t0 += PG) {
+          quat wv[PG], pv[PG];
+#pragma unroll
+          for (int u = 0; u < PG; ++u) {
+            const int r = R0 + HT * half + t0 + u;
+            const long long row = off + (r < len ? r : len - 1);
+            wv[u] = Wp[row * HB + j];
+            pv[u] = A[row * n + k0 + j];
+          }
+#pragma unroll
+          for (int u = 0; u < PG; ++u) {
+            const int r = R0 + HT * half + t0 + u;
+            const quat vr = r < len ? vsh[0][HT * half + t0 + u] : tzero<quat>();
+            s1 = mad(conjg(wv[u]), vr, s1);
+            s2 = mad(conjg(pv[u]), vr, s2);
           }
         }
       }

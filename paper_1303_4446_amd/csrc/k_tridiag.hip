@@ -249,6 +249,22 @@ __device__ void make_reflector_q(quat* A, int n, int k, quat* vout, quat* tau_ou
 //        2 = finish column k-1 only (last column of the panel)
 constexpr int COLT = 256;   // threads of the per-block column kernel
 
+// sum over the four lanes of a quad (lanes 4i..4i+3), every lane gets the
+// same bits: (x0 + x1) + (x2 + x3)
+template <class T>
+__device__ inline T quad_allsum(T x) {
+  constexpr int ND = sizeof(T) / sizeof(double);
+  double* p = reinterpret_cast<double*>(&x);
+#pragma unroll
+  for (int c = 0; c < ND; ++c) {
+    double v = p[c];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    p[c] = v;
+  }
+  return x;
+}
+
 template <class T>
 __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
                                                  int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS,
@@ -307,23 +323,43 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     // y_r = fixed-order sum of the super-tile partials minus the panel
     // corrections; the same pass accumulates the panel part of the update of
     // the next column
-    for (int r = tid; r < len; r += COLT) {
+    // Four threads per row: thread q of the quad takes the super-tile
+    // partials S = q, q+4, ... and the panel columns j = q, q+4, ..., all of
+    // its loads issued before any is used (rows off + r lie below the unit
+    // entry of every panel reflector, so V is read as stored); the quad's
+    // sums are combined by lane exchange in a fixed pattern.
+    for (int r = tid >> 2; r < len; r += COLT / 4) {
+      const int q = tid & 3;
       const int Sr = r / ST;
-      T acc = tzero<T>();
-      for (int SJ = 0; SJ <= Sr; ++SJ) acc = acc + HS[(long long)SJ * len + r];
-      for (int SI = Sr + 1; SI < nst; ++SI) acc = acc + HS[(long long)(nst + SI) * len + r];
-      T ca = tzero<T>();
-      const int rr = off + r;
-#pragma unroll 4
-      for (int j = 0; j < ip; ++j) {
-        const T Vrj = panel_v(A, n, k0, rr, j);
-        const T Wrj = Wp[(long long)rr * HB + j];
-        acc = acc - Vrj * t1[j] - Wrj * t2[j];
-        ca = ca + Vrj * wk[j] + Wrj * vk[j];
+      const long long rr = off + r;
+      T acc = tzero<T>(), ca = tzero<T>();
+      for (int S = q; S < nst; S += 4)
+        acc = acc + HS[(long long)(S <= Sr ? S : nst + S) * len + r];
+      if (ip > 0) {
+        T vr[HB / 4], wr[HB / 4];
+#pragma unroll
+        for (int u = 0; u < HB / 4; ++u) {
+          const int j = min(q + 4 * u, ip - 1);
+          vr[u] = A[rr * n + k0 + j];
+          wr[u] = Wp[rr * HB + j];
+        }
+#pragma unroll
+        for (int u = 0; u < HB / 4; ++u) {
+          const int j = q + 4 * u;
+          if (j < ip) {
+            acc = acc - vr[u] * t1[j] - wr[u] * t2[j];
+            ca = ca + vr[u] * wk[j] + wr[u] * vk[j];
+          }
+        }
       }
-      y[r] = acc;
-      colacc[r] = ca;
+      acc = quad_allsum(acc);
+      ca = quad_allsum(ca);
+      if (q == 0) {
+        y[r] = acc;
+        colacc[r] = ca;
+      }
     }
+    __syncthreads();   // y, colacc are read below by other threads
     double dr = 0.0, di = 0.0;
     for (int r = tid; r < len; r += COLT) {
       T yt = tau * y[r];
