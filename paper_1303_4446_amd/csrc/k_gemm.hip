@@ -236,11 +236,6 @@ k_gemm_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, i
 // the real multiply-adds of the complex 2N x 2N product.  Operands are staged
 // in LDS as four component planes; each wave runs 2 x 2 blocks of 16 x 16
 // quaternions, 16 MFMAs per block and k step of 4.  alpha, beta are real.
-constexpr int qmul_sign(int c, int d) {
-  return c == 0 ? (d == 0 ? 1 : -1)
-                : (d == 0 || d == c || (c == 1 && d == 3) || (c == 2 && d == 1) || (c == 3 && d == 2)) ? 1 : -1;
-}
-
 __global__ void __launch_bounds__(256)
 k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, int opA, int bufB, int opB,
               int bufC, double alpha, double beta, int herm) {

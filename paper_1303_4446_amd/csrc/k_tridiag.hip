@@ -769,6 +769,126 @@ void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, 
   hipLaunchKernelGGL(k_hetrd<T>, dim3(nblk), dim3(1024), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau);
 }
 
+// ---------------------------------------------------------------- quaternion rank-2k update on the matrix cores
+// Trailing lower triangle A -= V W^H + W V^H = [V W] [W V]^H for quaternion
+// matrices: a product with contraction length 2 HB over 64 x 64 tiles on or
+// below the diagonal, operands staged per k chunk of 16 as four component
+// planes, 16 MFMAs (one per pair of components, signs of the quaternion
+// product) per 16 x 16 block and k step of 4.  grid = (lower tiles, nblk).
+constexpr int HQ_T = 64, HQ_K = 16;
+
+__global__ void __launch_bounds__(256) k_tri_her2k_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel,
+                                                          int bufA, int bufW, int k0) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = seldim(d, dsel);
+  if (k0 >= n - 1) return;
+  const int kb = min(HB, n - 1 - k0);
+  const int c0 = k0 + kb;
+  const int len = n - c0;
+  if (len <= 0) return;
+  const int nt = (len + HQ_T - 1) / HQ_T;
+  const int t = blockIdx.x;
+  if (t >= nt * (nt + 1) / 2) return;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  quat* A = bufp<quat>(ws, d, bufA);
+  const quat* Wp = bufp<quat>(ws, d, bufW);
+  const int m0 = c0 + HQ_T * I, n0 = c0 + HQ_T * J;
+  __shared__ double As[4][HQ_T][HQ_K + 1];   // [component][row][k]
+  __shared__ double Bs[4][HQ_K][HQ_T + 1];   // [component][k][col]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  qd4 acc[2][2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[x][y][c] = qd4{0.0, 0.0, 0.0, 0.0};
+  // column j of [V W] (wfirst = 0) or [W V] (wfirst = 1) at row `row`; zero
+  // beyond the matrix and for panel columns >= kb
+  auto opval = [&](int row, int j, int wfirst) -> quat {
+    const int half = j >= HB, a = j - HB * half;
+    if (row >= n || a >= kb) return tzero<quat>();
+    return (half != wfirst) ? Wp[(long long)row * HB + a] : panel_v(A, n, k0, row, a);
+  };
+  constexpr int NL = HQ_T * HQ_K / 256;
+  quat na[NL], nb[NL];
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int l = tid + 256 * q, r = l / HQ_K, kk = l % HQ_K;
+      na[q] = opval(m0 + r, kc + kk, 0);
+      nb[q] = conjg(opval(n0 + r, kc + kk, 1));
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int l = tid + 256 * q, r = l / HQ_K, kk = l % HQ_K;
+      As[0][r][kk] = na[q].a.x;
+      As[1][r][kk] = na[q].a.y;
+      As[2][r][kk] = na[q].b.x;
+      As[3][r][kk] = na[q].b.y;
+      Bs[0][kk][r] = nb[q].a.x;
+      Bs[1][kk][r] = nb[q].a.y;
+      Bs[2][kk][r] = nb[q].b.x;
+      Bs[3][kk][r] = nb[q].b.y;
+    }
+  };
+  fetch(0);
+  stash();
+  __syncthreads();
+  for (int kc = 0; kc < 2 * HB; kc += HQ_K) {
+    const bool more = kc + HQ_K < 2 * HB;
+    if (more) fetch(kc + HQ_K);
+#pragma unroll
+    for (int ks = 0; ks < HQ_K; ks += 4) {
+      double a[2][4], an[2][4], bq[2][4];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          a[x][c] = As[c][wr + 16 * x + l16][ks + l4];
+          an[x][c] = -a[x][c];
+          bq[x][c] = Bs[c][ks + l4][wc + 16 * x + l16];
+        }
+#pragma unroll
+      for (int dd = 0; dd < 4; ++dd)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                  qmul_sign(c, dd) > 0 ? a[x][c ^ dd] : an[x][c ^ dd], bq[y][dd], acc[x][y][c], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      stash();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = m0 + wr + 16 * x + l4 + 4 * i, c = n0 + wc + 16 * y + l16;
+        if (r >= n || c > r) continue;
+        const long long idx = (long long)r * n + c;
+        const quat u = {{acc[x][y][0][i], acc[x][y][1][i]}, {acc[x][y][2][i], acc[x][y][3][i]}};
+        A[idx] = A[idx] - u;
+      }
+}
+
 // Blocked multi-kernel reduction over the batch; falls back to the
 // one-work-group reduction when every block is small.
 template <class T>
@@ -801,9 +921,15 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
     }
     const int len2 = maxdim - (k0 + kbmax);
     if (len2 > 0) {
-      const int nt2 = (len2 + TT - 1) / TT;
-      hipLaunchKernelGGL(k_tri_her2k<T>, dim3(nt2 * (nt2 + 1) / 2, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
-                         bufW, k0);
+      if constexpr (is_quat<T>()) {
+        const int nt2 = (len2 + HQ_T - 1) / HQ_T;
+        hipLaunchKernelGGL(k_tri_her2k_q_mfma, dim3(nt2 * (nt2 + 1) / 2, nblk), dim3(256), 0, s, D, ws, info, dsel,
+                           bufA, bufW, k0);
+      } else {
+        const int nt2 = (len2 + TT - 1) / TT;
+        hipLaunchKernelGGL(k_tri_her2k<T>, dim3(nt2 * (nt2 + 1) / 2, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA,
+                           bufW, k0);
+      }
     }
   }
   hipLaunchKernelGGL(k_tri_last<T>, dim3((nblk + 255) / 256), dim3(256), 0, s, D, ws, info, nblk, dsel, bufA, bufD);

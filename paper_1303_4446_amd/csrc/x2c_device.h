@@ -59,6 +59,13 @@ __host__ __device__ inline quat operator*(quat x, quat y) {
   cplx b2c = {y.b.x, -y.b.y}, a2c = {y.a.x, -y.a.y};
   return {x.a * y.a - x.b * b2c, x.a * y.b + x.b * a2c};
 }
+// With components q = (Re a, Im a, Re b, Im b), (x y)_c = sum_d
+// qmul_sign(c, d) x_{c xor d} y_d: left multiplication by x is a signed
+// permutation of x's components as a real 4 x 4 matrix.
+constexpr int qmul_sign(int c, int d) {
+  return c == 0 ? (d == 0 ? 1 : -1)
+                : (d == 0 || d == c || (c == 1 && d == 3) || (c == 2 && d == 1) || (c == 3 && d == 2)) ? 1 : -1;
+}
 __host__ __device__ inline quat operator*(double s, quat x) { return {s * x.a, s * x.b}; }
 __host__ __device__ inline quat operator*(quat x, double s) { return {s * x.a, s * x.b}; }
 __host__ __device__ inline quat conjg(quat x) { return {{x.a.x, -x.a.y}, {-x.b.x, -x.b.y}}; }
