@@ -344,13 +344,22 @@ __global__ void k_filter_factor(const BlockDesc* D, char* ws, const int* info, i
 
 // Columns j of Z = 1/2 (E + M [T_s E + sum_q a_q Re((T_s - i beta_q)^-1 E)]),
 // E_ij = hash(i, j); the result (real) goes to the T-typed m x n buffer.
-// The pole sum is accumulated in a real buffer (the T-typed output itself
-// when T is real, else C_TMP, which is free at this point) so that every
-// pole moves 8 bytes of accumulator per entry.
-// (quaternion form: rows are then scaled by the phases, Y_q = D Z)
+// Work-group (column chunk, pole group g, block): group g takes the poles
+// q = g, g + G, ... and accumulates into its own real m x n partial (group 0
+// also holds T_s E); k_filter_finish adds the G partials in a fixed order.
+// Each solve is a forward elimination and a backward substitution along the
+// rows.  The forward sweep keeps only its state at every FK-th row
+// (checkpoints); the backward sweep re-runs the forward recurrence over one
+// chunk of FK rows from its checkpoint, in registers, and then substitutes
+// back through the chunk, so the per-row solve values never go to memory.
+// Partials: in the T-typed output when T is real and G = 1, else in C_TMP
+// (free at this point); checkpoints in Z_SCR.
+constexpr int FK = 16;
+
 template <class T>
-__global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* ws, const int* info, int kramers) {
-  const int b = blockIdx.y;
+__global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* ws, const int* info, int kramers,
+                                                      int G) {
+  const int b = blockIdx.z, g = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int m = kramers ? d.n : d.m, n = kramers ? d.n / 2 : d.n;
@@ -358,72 +367,109 @@ __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* 
   if (blockIdx.x * blockDim.x >= n) return;       // whole work-group beyond the columns
   const bool active = j < n;
   const double* pf = bufp<double>(ws, d, P_FILT);
-  const double sigma = pf[0], rho = pf[1], M = pf[2];
+  const double sigma = pf[0], rho = pf[1];
   const int r = (int)pf[3];
+  if (g >= r) return;
   const double* dg = bufp<double>(ws, d, V_D);
   const double* eg = bufp<double>(ws, d, V_E);
-  T* Y = bufp<T>(ws, d, C_Y);
-  double* acc = sizeof(T) == sizeof(double) ? reinterpret_cast<double*>(Y) : bufp<double>(ws, d, C_TMP);
-  cplx* scr = bufp<cplx>(ws, d, Z_SCR);
+  double* accb = (sizeof(T) == sizeof(double) && G == 1) ? reinterpret_cast<double*>(bufp<T>(ws, d, C_Y))
+                                                         : bufp<double>(ws, d, C_TMP);
+  double* acc = accb + (long long)g * m * n;
+  const int nck = (m + FK - 1) / FK;
+  cplx* ck = bufp<cplx>(ws, d, Z_SCR) + (long long)g * nck * n;
   const double ir = 1.0 / rho;
-  // acc = T_s E_j
-  for (int i = 0; active && i < m; ++i) {
-    double t = (dg[i] - sigma) * hash_uniform(i, j);
-    if (i > 0) t += eg[i - 1] * hash_uniform(i - 1, j);
-    if (i < m - 1) t += eg[i] * hash_uniform(i + 1, j);
-    acc[(long long)i * n + j] = t * ir;
+  if (g == 0) {
+    // acc = T_s E_j
+    for (int i = 0; active && i < m; ++i) {
+      double t = (dg[i] - sigma) * hash_uniform(i, j);
+      if (i > 0) t += eg[i - 1] * hash_uniform(i - 1, j);
+      if (i < m - 1) t += eg[i] * hash_uniform(i + 1, j);
+      acc[(long long)i * n + j] = t * ir;
+    }
   }
   extern __shared__ cplx Fs[];          // the current pole's factors, m x 5
-  for (int q = 0; q < r; ++q) {
+  bool fresh = g > 0;                   // partial not yet written
+  for (int q = g; q < r; q += G) {
     const cplx* F = bufp<cplx>(ws, d, F_FAC) + (long long)q * m * 5;
     const double aq = pf[4 + q];
     __syncthreads();
     for (int e = threadIdx.x; e < m * 5; e += blockDim.x) Fs[e] = F[e];
     __syncthreads();
     if (active) {
-      // forward: y = L^-1 P b, streamed
+      // forward: y = L^-1 P b; only the running carry at rows 0, FK, ... is kept
       cplx carry = {hash_uniform(0, j), 0.0};
-      for (int i = 0; i < m - 1; ++i) {
+      for (int i = 0; i < m; ++i) {
+        if (i % FK == 0) ck[(long long)(i / FK) * n + j] = carry;
+        if (i == m - 1) break;
         const cplx* f = Fs + i * 5;
         const cplx bnext = {hash_uniform(i + 1, j), 0.0};
-        const bool sw = f[4].x != 0.0;
-        const cplx yi = sw ? bnext : carry;
-        carry = sw ? carry - f[0] * bnext : bnext - f[0] * carry;
-        scr[(long long)i * n + j] = yi;
+        carry = f[4].x != 0.0 ? carry - f[0] * bnext : bnext - f[0] * carry;
       }
-      scr[(long long)(m - 1) * n + j] = carry;
-      // backward: U x = y;  acc += a_q Re(x).  Rows are taken in groups of 8
-      // whose loads are issued together, ahead of the recurrence.
+      // backward: U x = y;  acc += a_q Re(x), one chunk of FK rows at a time
       cplx x1 = {0.0, 0.0}, x2 = {0.0, 0.0};
-      for (int i0 = m - 1; i0 >= 0; i0 -= 8) {
-        cplx yb[8];
-        double ab[8];
+      for (int c = nck - 1; c >= 0; --c) {
+        const int i0 = c * FK;
+        cplx cy = ck[(long long)c * n + j];
+        double ab[FK];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int i = i0 - k;
-          yb[k] = i >= 0 ? scr[(long long)i * n + j] : cplx{0.0, 0.0};
-          ab[k] = i >= 0 ? acc[(long long)i * n + j] : 0.0;
+        for (int u = 0; u < FK; ++u) {
+          const int i = min(i0 + u, m - 1);
+          ab[u] = fresh ? 0.0 : acc[(long long)i * n + j];
+        }
+        cplx yb[FK];
+#pragma unroll
+        for (int u = 0; u < FK; ++u) {
+          const int i = i0 + u;
+          yb[u] = cy;
+          if (i < m - 1) {
+            const cplx* f = Fs + i * 5;
+            const cplx bnext = {hash_uniform(i + 1, j), 0.0};
+            const bool sw = f[4].x != 0.0;
+            yb[u] = sw ? bnext : cy;
+            cy = sw ? cy - f[0] * bnext : bnext - f[0] * cy;
+          }
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int i = i0 - k;
-          if (i >= 0) {
+        for (int u = FK - 1; u >= 0; --u) {
+          const int i = i0 + u;
+          if (i < m) {
             const cplx* f = Fs + i * 5;
-            const cplx t = yb[k] - f[2] * x1 - f[3] * x2;
+            const cplx t = yb[u] - f[2] * x1 - f[3] * x2;
             const cplx x = t * f[1];
-            acc[(long long)i * n + j] = ab[k] + aq * x.x;
+            acc[(long long)i * n + j] = ab[u] + aq * x.x;
             x2 = x1;
             x1 = x;
           }
         }
       }
     }
+    fresh = false;
   }
-  for (int i = 0; active && i < m; ++i) {
-    long long idx = (long long)i * n + j;
-    const double z = 0.5 * (hash_uniform(i, j) + M * acc[idx]);
-    if constexpr (sizeof(T) == sizeof(quat)) Y[idx] = z * bufp<quat>(ws, d, V_DEL)[i];
-    else Y[idx] = treal<T>(z);
+}
+
+// Y = 1/2 (E + M sum_g partial_g) (quaternion form: rows scaled by the
+// phases, Y_q = D Z).  grid = (chunks of m x n, nblk)
+template <class T>
+__global__ void k_filter_finish(const BlockDesc* D, char* ws, const int* info, int kramers, int G) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int m = kramers ? d.n : d.m, n = kramers ? d.n / 2 : d.n;
+  const double* pf = bufp<double>(ws, d, P_FILT);
+  const double M = pf[2];
+  const int ng = min(G, (int)pf[3]);
+  T* Y = bufp<T>(ws, d, C_Y);
+  const double* accb = (sizeof(T) == sizeof(double) && G == 1) ? reinterpret_cast<const double*>(Y)
+                                                               : bufp<double>(ws, d, C_TMP);
+  const long long tot = (long long)m * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    double sum = accb[e];
+    for (int g = 1; g < ng; ++g) sum += accb[(long long)g * tot + e];
+    const double z = 0.5 * (hash_uniform(i, j) + M * sum);
+    if constexpr (sizeof(T) == sizeof(quat)) Y[e] = z * bufp<quat>(ws, d, V_DEL)[i];
+    else Y[e] = treal<T>(z);
   }
 }
 
@@ -567,7 +613,13 @@ void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int*
   const size_t shm = (size_t)maxm * 5 * sizeof(cplx);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter_solve<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shm);
-  hipLaunchKernelGGL(k_filter_solve<T>, dim3((maxrhs + 255) / 256, nblk), dim3(256), shm, s, D, ws, info, kramers);
+  // pole groups: the quaternion form has room for four partials in C_TMP
+  const int G = kramers ? 4 : 1;
+  hipLaunchKernelGGL(k_filter_solve<T>, dim3((maxrhs + 255) / 256, G, nblk), dim3(256), shm, s, D, ws, info, kramers,
+                     G);
+  long long gx = ((long long)maxm * maxrhs + 255) / 256;
+  if (gx > 256) gx = 256;
+  hipLaunchKernelGGL(k_filter_finish<T>, dim3((int)gx, nblk), dim3(256), 0, s, D, ws, info, kramers, G);
 }
 void launch_tri_eig_q(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxdim, int dsel) {
   size_t shm = (size_t)(3 * maxdim) * sizeof(double);
