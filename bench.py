@@ -106,6 +106,8 @@ def parse():
     ap.add_argument("--check-blocks", type=int, default=3, help="blocks checked against the oracle")
     ap.add_argument("--cpu-blocks", type=int, default=12, help="blocks in the CPU oracle sample (0 = skip)")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--streams", type=int, choices=[1, 2], default=2,
+                    help="run the batch as two parts on two streams (2) or on one stream (1)")
     ap.add_argument("--no-graph", action="store_true", help="eager launches instead of graph replay")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the workload, copy a device buffer of this size once (a plain copy kernel "
@@ -200,6 +202,7 @@ def main():
     batch = px.batch_to_device(pk, twocomp)
     if args.no_graph:
         px.graph_enable(False)
+    px.stream_split(args.streams)
     stream = torch.cuda.current_stream()
     print(f"# workload: {desc}; prec {args.prec}", file=sys.stderr, flush=True)
 
@@ -277,7 +280,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "nblocks": nblk, "mode": "two-component" if twocomp else "spin-free",
-                   "prec": args.prec, "reduction": args.reduction, **acc},
+                   "prec": args.prec, "reduction": args.reduction, "streams": args.streams, **acc},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: round(v, 4) for k, v in sorted(stage_ms.items(), key=lambda kv: -kv[1])},

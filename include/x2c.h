@@ -212,6 +212,19 @@ void x2c_release(void);
 int x2c_graph_enable(int on);
 
 /*
+ * Two-stream execution of a batch (Sec. III.A: the per-block problems are
+ * independent).  ways = 2 (the default): a call with two or more blocks cuts
+ * the batch into two parts of about equal work (sum of N^3); the first part
+ * runs on the caller's stream, the second on an auxiliary stream of the
+ * library, forked from and joined back into the caller's stream with events
+ * (captured graphs contain both branches).  ways = 1: one stream.  Results
+ * are identical either way; calls made while tracing is enabled use one
+ * stream.  Other values leave the setting unchanged.  Returns the previous
+ * setting.
+ */
+int x2c_stream_split(int ways);
+
+/*
  * Tracing.  x2c_trace_enable(1) makes every later call bracket each of its
  * stages with a pair of HIP events recorded on the call's stream (no device
  * memory is allocated); level 2 also brackets every launch of the

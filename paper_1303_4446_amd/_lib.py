@@ -25,7 +25,7 @@ INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subsp
 
 EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_build_batched_xr",
             "x2c_dlu_workspace_bytes", "x2c_dlu_assemble", "x2c_strerror", "x2c_release", "x2c_graph_enable",
-            "x2c_trace_enable", "x2c_trace_read", "x2c_trace_reset")
+            "x2c_stream_split", "x2c_trace_enable", "x2c_trace_read", "x2c_trace_reset")
 
 
 class X2CError(RuntimeError):
@@ -78,6 +78,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.x2c_release.restype = None
     lib.x2c_graph_enable.argtypes = [i32]
     lib.x2c_graph_enable.restype = i32
+    lib.x2c_stream_split.argtypes = [i32]
+    lib.x2c_stream_split.restype = i32
     lib.x2c_trace_enable.argtypes = [i32]
     lib.x2c_trace_enable.restype = i32
     lib.x2c_trace_read.argtypes = [i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
@@ -116,6 +118,15 @@ def graph_enable(on: bool) -> bool:
     """Turn graph capture / replay of the build calls on or off; returns the
     previous setting."""
     return bool(load().x2c_graph_enable(1 if on else 0))
+
+
+def stream_split(ways: int) -> int:
+    """Run a batch of two or more blocks as two parts on two streams (2, the
+    default) or on the caller's stream only (1); returns the previous
+    setting."""
+    if ways not in (1, 2):
+        raise ValueError("ways must be 1 or 2")
+    return int(load().x2c_stream_split(int(ways)))
 
 
 def trace_enable(on, level: int = 1) -> int:

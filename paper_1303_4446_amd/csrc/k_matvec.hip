@@ -220,8 +220,11 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
   __shared__ quat vsh[2][ST];          // [0] row segment, [1] column segment
   __shared__ quat racc[ST], cacc[ST];
   const int total = nblk * nsmax;
+  // every other step walks the items in reverse, so that a launch starts on
+  // the matrices its predecessor read last (still in the memory-side cache)
+  const bool rev = k & 1;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    const MvItem it = mv_decode(D, info, dsel, k, nblk, nsmax, item, ST);
+    const MvItem it = mv_decode(D, info, dsel, k, nblk, nsmax, rev ? total - 1 - item : item, ST);
     if (!it.valid) continue;
     const BlockDesc& d = D[it.b];
     const quat* A = bufp<quat>(ws, d, bufA);

@@ -234,7 +234,7 @@ static void launch_split_s(hipStream_t s, const BlockDesc* D, char* ws, const in
                            int dsel, int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta) {
   constexpr int RF = sizeof(T) == sizeof(cplx) ? 2 : 1;
   const size_t shm = (size_t)S * (OZ_M + OZ_N) * OZ_LD * sizeof(__bf16);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_split<T, S>), hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_split<T, S>), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shm);
   dim3 grid((maxdim + OZ_N - 1) / OZ_N, (RF * maxdim + OZ_M - 1) / OZ_M, nblk);
   hipLaunchKernelGGL((k_gemm_split<T, S>), grid, dim3(256), shm, s, D, ws, info, dsel, bufA, opA, bufB, opB, bufC,

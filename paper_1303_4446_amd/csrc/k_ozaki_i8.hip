@@ -218,7 +218,7 @@ static void launch_i8_s(hipStream_t s, const BlockDesc* D, char* ws, const int* 
                         int bufC, T alpha, T beta) {
   constexpr int RF = sizeof(T) == sizeof(cplx) ? 2 : 1;
   const size_t shm = (size_t)S * (Q8_M + Q8_N) * Q8_LD;
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_i8<T, S>), hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_i8<T, S>), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shm);
   dim3 grid((maxdim + Q8_N - 1) / Q8_N, (RF * maxdim + Q8_M - 1) / Q8_M, nblk);
   hipLaunchKernelGGL((k_gemm_i8<T, S>), grid, dim3(256), shm, s, D, ws, info, dsel, bufC, alpha, beta, (int)Z_SLA,

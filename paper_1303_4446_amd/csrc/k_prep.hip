@@ -386,12 +386,12 @@ void launch_unpack(hipStream_t s, const BlockDesc* D, char* ws, int* info, int n
 }
 void launch_potrf(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN) {
   const size_t shm = ((size_t)maxN * (PB + 1) + (size_t)PB * (PK + 1)) * sizeof(double);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_potrf), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_potrf), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL(k_potrf, dim3(2, nblk), dim3(256), shm, s, D, ws, info);
 }
 void launch_trtri(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN) {
   const size_t shm = ((size_t)maxN * (PB + 1) + (size_t)PB * (PB + 1)) * sizeof(double);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trtri), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trtri), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL(k_trtri, dim3((maxN + PB - 1) / PB, 2, nblk), dim3(256), shm, s, D, ws, info);
 }
 static int grid_for(long long elems) {

@@ -611,7 +611,7 @@ void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int*
                          int kramers) {
   const int maxm = kramers ? maxrhs * 2 : 2 * maxrhs;      // rows of the tridiagonal
   const size_t shm = (size_t)maxm * 5 * sizeof(cplx);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter_solve<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter_solve<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shm);
   // pole groups: the quaternion form has room for four partials in C_TMP
   const int G = kramers ? 4 : 1;

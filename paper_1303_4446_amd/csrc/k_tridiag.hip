@@ -22,14 +22,17 @@
 namespace x2c {
 
 // Reflector for column k (rows k+1..n-1) into vout[0..len).  Returns through
-// shared scalars.  All threads call.
+// shared scalars.  All threads call.  col (may be null): LDS copy of the
+// column, col[i] = A[k+1+i][k], read instead of A.
 template <class T>
-__device__ void make_reflector(T* A, int n, int k, T* vout, T* tau_out, double* beta_out, double* red) {
+__device__ void make_reflector(T* A, int n, int k, T* vout, T* tau_out, double* beta_out, double* red,
+                               const T* col = nullptr) {
   const int len = n - k - 1;
+  auto ld = [&](int i) { return col ? col[i] : A[(long long)(k + 1 + i) * n + k]; };
   double xn2 = 0.0;
-  for (int i = 1 + threadIdx.x; i < len; i += blockDim.x) xn2 += abs2(A[(long long)(k + 1 + i) * n + k]);
+  for (int i = 1 + threadIdx.x; i < len; i += blockDim.x) xn2 += abs2(ld(i));
   xn2 = block_sum(xn2, red);
-  T alpha = A[(long long)(k + 1) * n + k];
+  T alpha = ld(0);
   double anrm2 = abs2(alpha);
   T tau;
   double beta;
@@ -54,7 +57,7 @@ __device__ void make_reflector(T* A, int n, int k, T* vout, T* tau_out, double* 
       vout[0] = treal<T>(1.0);
     } else {
       long long idx = (long long)(k + 1 + i) * n + k;
-      T x = trivial ? tzero<T>() : A[idx] * scale;
+      T x = trivial ? tzero<T>() : ld(i) * scale;
       vout[i] = x;
       A[idx] = x;
     }
@@ -194,12 +197,14 @@ __global__ void __launch_bounds__(1024) k_hetrd(const BlockDesc* D, char* ws, co
 // reflector I - 2 u u^H / u^H u maps x to -sigma e1.  Normalised to
 // v = u u0^-1 (v0 = 1) it is I - tau v v^H with real tau = 1 + |x0|/||x||.
 // beta_out = -sigma (quaternion sub-diagonal entry).
-__device__ void make_reflector_q(quat* A, int n, int k, quat* vout, quat* tau_out, quat* beta_out, double* red) {
+__device__ void make_reflector_q(quat* A, int n, int k, quat* vout, quat* tau_out, quat* beta_out, double* red,
+                                 const quat* col = nullptr) {
   const int len = n - k - 1;
+  auto ld = [&](int i) { return col ? col[i] : A[(long long)(k + 1 + i) * n + k]; };
   double xn2 = 0.0;
-  for (int i = 1 + threadIdx.x; i < len; i += blockDim.x) xn2 += abs2(A[(long long)(k + 1 + i) * n + k]);
+  for (int i = 1 + threadIdx.x; i < len; i += blockDim.x) xn2 += abs2(ld(i));
   xn2 = block_sum(xn2, red);
-  const quat x0 = A[(long long)(k + 1) * n + k];
+  const quat x0 = ld(0);
   const double a0 = sqrt(abs2(x0));
   const double xn = sqrt(a0 * a0 + xn2);
   const bool trivial = (xn2 == 0.0 && x0.a.y == 0.0 && x0.b.x == 0.0 && x0.b.y == 0.0);
@@ -217,7 +222,7 @@ __device__ void make_reflector_q(quat* A, int n, int k, quat* vout, quat* tau_ou
       vout[0] = treal<quat>(1.0);
     } else {
       long long idx = (long long)(k + 1 + i) * n + k;
-      quat x = trivial ? tzero<quat>() : A[idx] * uinv;
+      quat x = trivial ? tzero<quat>() : ld(i) * uinv;
       vout[i] = x;
       A[idx] = x;
     }
@@ -248,18 +253,19 @@ __device__ void make_reflector_q(quat* A, int n, int k, quat* vout, quat* tau_ou
 //        1 = finish column k-1 (w), then build column k if it is in the panel
 //        2 = finish column k-1 only (last column of the panel)
 constexpr int COLT = 256;   // threads of the per-block column kernel
+constexpr int CTPR = 4;     // threads per trailing row in its row loop
 
-// sum over the four lanes of a quad (lanes 4i..4i+3), every lane gets the
-// same bits: (x0 + x1) + (x2 + x3)
-template <class T>
-__device__ inline T quad_allsum(T x) {
+// sum over the G lanes of an aligned lane group, every lane gets the same
+// bits (pairwise tree: lane xor 1, then xor 2, ...)
+template <int G, class T>
+__device__ inline T group_allsum(T x) {
   constexpr int ND = sizeof(T) / sizeof(double);
   double* p = reinterpret_cast<double*>(&x);
 #pragma unroll
   for (int c = 0; c < ND; ++c) {
     double v = p[c];
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
     p[c] = v;
   }
   return x;
@@ -288,6 +294,7 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
   T* v = reinterpret_cast<T*>(smem);
   T* y = v + n;
   T* colacc = y + n;
+  T* acol = colacc + n;                 // column k (rows off..n-1) of A, updated in LDS
   __shared__ double red[32];
   __shared__ T sh_tau;
   __shared__ double sh_beta;
@@ -303,7 +310,10 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     const int off = kp + 1, len = n - kp - 1;
     const T tau = taus[kp];
     const int nst = (len + ST - 1) / ST;
-    for (int r = tid; r < len; r += COLT) v[r] = vg[r];
+    for (int r = tid; r < len; r += COLT) {
+      v[r] = vg[r];
+      if (build) acol[r] = A[(long long)(off + r) * n + k];
+    }
     if (build && tid < ip) {
       wk[tid] = conjg(Wp[(long long)k * HB + tid]);
       vk[tid] = conjg(panel_v(A, n, k0, k, tid));
@@ -312,6 +322,7 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     if (tid < ip) {
       T a1 = tzero<T>(), a2 = tzero<T>();
       const T* TP = HS + (long long)2 * nst * len;
+#pragma unroll 4
       for (int S = 0; S < nst; ++S) {
         a1 = a1 + TP[((long long)S * HB + tid) * 2];
         a2 = a2 + TP[((long long)S * HB + tid) * 2 + 1];
@@ -323,37 +334,37 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     // y_r = fixed-order sum of the super-tile partials minus the panel
     // corrections; the same pass accumulates the panel part of the update of
     // the next column
-    // Four threads per row: thread q of the quad takes the super-tile
-    // partials S = q, q+4, ... and the panel columns j = q, q+4, ..., all of
-    // its loads issued before any is used (rows off + r lie below the unit
-    // entry of every panel reflector, so V is read as stored); the quad's
-    // sums are combined by lane exchange in a fixed pattern.
-    for (int r = tid >> 2; r < len; r += COLT / 4) {
-      const int q = tid & 3;
+    // CTPR threads per row: thread q of the group takes the super-tile
+    // partials S = q, q+CTPR, ... and the panel columns j = q, q+CTPR, ...,
+    // all of its loads issued before any is used (rows off + r lie below the
+    // unit entry of every panel reflector, so V is read as stored); the
+    // group's sums are combined by lane exchange in a fixed pattern.
+    for (int r = tid / CTPR; r < len; r += COLT / CTPR) {
+      const int q = tid % CTPR;
       const int Sr = r / ST;
       const long long rr = off + r;
       T acc = tzero<T>(), ca = tzero<T>();
-      for (int S = q; S < nst; S += 4)
+      for (int S = q; S < nst; S += CTPR)
         acc = acc + HS[(long long)(S <= Sr ? S : nst + S) * len + r];
       if (ip > 0) {
-        T vr[HB / 4], wr[HB / 4];
+        T vr[HB / CTPR], wr[HB / CTPR];
 #pragma unroll
-        for (int u = 0; u < HB / 4; ++u) {
-          const int j = min(q + 4 * u, ip - 1);
+        for (int u = 0; u < HB / CTPR; ++u) {
+          const int j = min(q + CTPR * u, ip - 1);
           vr[u] = A[rr * n + k0 + j];
           wr[u] = Wp[rr * HB + j];
         }
 #pragma unroll
-        for (int u = 0; u < HB / 4; ++u) {
-          const int j = q + 4 * u;
+        for (int u = 0; u < HB / CTPR; ++u) {
+          const int j = q + CTPR * u;
           if (j < ip) {
             acc = acc - vr[u] * t1[j] - wr[u] * t2[j];
             ca = ca + vr[u] * wk[j] + wr[u] * vk[j];
           }
         }
       }
-      acc = quad_allsum(acc);
-      ca = quad_allsum(ca);
+      acc = group_allsum<CTPR>(acc);
+      ca = group_allsum<CTPR>(ca);
       if (q == 0) {
         y[r] = acc;
         colacc[r] = ca;
@@ -386,10 +397,10 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     // column k = off: A[r][k] -= (panel columns < ip) + v_r conj(w_0) + w_r conj(v_0), v_0 = 1
     const T w0c = conjg(y[0]);
     for (int r = tid; r < len; r += COLT) {
-      long long idx = (long long)(off + r) * n + k;
-      T a = A[idx] - colacc[r] - v[r] * w0c - y[r];
+      T a = acol[r] - colacc[r] - v[r] * w0c - y[r];
       if (r == 0) a = treal<T>(re(a));
-      A[idx] = a;
+      acol[r] = a;
+      if (r == 0) A[(long long)off * n + k] = a;   // diagonal; the rest is replaced by the reflector
     }
     __syncthreads();
   } else {
@@ -400,13 +411,13 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
   }
   if constexpr (is_quat<T>()) {
     __shared__ T sh_betaq;
-    make_reflector_q(A, n, k, v, &sh_tau, &sh_betaq, red);
+    make_reflector_q(A, n, k, v, &sh_tau, &sh_betaq, red, phase != 0 ? acol + 1 : nullptr);
     if (tid == 0) {
       ee[k] = sqrt(abs2(sh_betaq));
       bufp<T>(ws, d, bufET)[k] = sh_betaq;
     }
   } else {
-    make_reflector<T>(A, n, k, v, &sh_tau, &sh_beta, red);
+    make_reflector<T>(A, n, k, v, &sh_tau, &sh_beta, red, phase != 0 ? acol + 1 : nullptr);
     if (tid == 0) ee[k] = sh_beta;
   }
   const int len = n - k - 1;
@@ -901,9 +912,11 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
       return;
     }
   }
-  const size_t shm = 3 * (size_t)maxdim * sizeof(T);
+  const size_t shm = 4 * (size_t)maxdim * sizeof(T);   // v, y, colacc, acol of the column kernel
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tri_col<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)shm);
   int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   for (int k0 = 0; k0 < maxdim - 1; k0 += HB) {
     const int kbmax = std::min(HB, maxdim - 1 - k0);
     hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(COLT), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufW,

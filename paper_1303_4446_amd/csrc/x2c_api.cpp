@@ -359,9 +359,9 @@ T tcast(double v) {
 
 // The stage sequence for one batch (all blocks advance stage by stage).
 template <class T>
-int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S, const double* Tm, const double* V,
+int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const double* S, const double* Tm, const double* V,
                const double* W, double* h, double* eps, double* Xo, double* Ro, int* info, char* ws, hipStream_t s) {
-  const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off);
+  const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off) + b0;
   const bool tc = o->mode == X2C_TWOCOMP;
   const double c = o->c;
   const int maxN = L.maxN, maxn = L.maxn, maxm = L.maxm;
@@ -550,18 +550,75 @@ int run_stages(const x2c_options* o, const Layout& L, int nblk, const double* S,
   return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
 }
 
-// descriptor upload + every stage of one call, enqueued on s
+// Streams of the library (one set per device, default priority): the
+// capture stream of the graphs and the auxiliary stream of split batches.
+std::mutex g_smu;
+int g_split = 2;
+struct AuxStreams {
+  hipStream_t capture = nullptr, aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::map<int, AuxStreams> g_streams;
+
+AuxStreams* device_streams() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  AuxStreams& a = g_streams[dev];
+  if (!a.capture && hipStreamCreateWithFlags(&a.capture, hipStreamNonBlocking) != hipSuccess) a.capture = nullptr;
+  if (!a.aux && hipStreamCreateWithFlags(&a.aux, hipStreamNonBlocking) != hipSuccess) a.aux = nullptr;
+  if (!a.fork && hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess) a.fork = nullptr;
+  if (!a.join && hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess) a.join = nullptr;
+  return (a.capture && a.aux && a.fork && a.join) ? &a : nullptr;
+}
+
+// descriptor upload + every stage of one call, enqueued on s.  With
+// splitting on, the batch is cut into two parts of about equal work
+// (sum of N^3): the first runs on s, the second on the library's auxiliary
+// stream, forked from and joined back into s by events, so that the
+// latency-bound steps of one part (the per-column kernels of the
+// reductions, the LU panels) overlap the bandwidth- and matrix-core-bound
+// kernels of the other.  Blocks never share workspace, so the two parts are
+// independent.
 int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S, const double* T, const double* V,
-                const double* W, void* h, double* eps, void* Xo, void* Ro, int* info, char* ws, hipStream_t s) {
+                const double* W, void* h, double* eps, void* Xo, void* Ro, int* info, char* ws, hipStream_t s,
+                bool allow_split) {
   const void* src = L.pinned ? static_cast<const void*>(L.pinned) : static_cast<const void*>(L.desc.data());
   if (hipMemcpyAsync(ws + L.desc_off, src, L.desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, s) !=
       hipSuccess)
     return X2C_EHIP;
-  if (o->mode == X2C_TWOCOMP)
-    return run_stages<cplx>(o, L, nblk, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
-                            static_cast<double*>(Ro), info, ws, s);
-  return run_stages<double>(o, L, nblk, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
-                            static_cast<double*>(Ro), info, ws, s);
+  auto run = [&](int b0, int nb, hipStream_t st) {
+    if (o->mode == X2C_TWOCOMP)
+      return run_stages<cplx>(o, L, b0, nb, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
+                              static_cast<double*>(Ro), info + b0, ws, st);
+    return run_stages<double>(o, L, b0, nb, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
+                              static_cast<double*>(Ro), info + b0, ws, st);
+  };
+  std::unique_lock<std::mutex> lk(g_smu);
+  AuxStreams* as = (allow_split && g_split >= 2 && nblk >= 2) ? device_streams() : nullptr;
+  if (!as) {
+    lk.unlock();
+    return run(0, nblk, s);
+  }
+  double total = 0.0;
+  for (const BlockDesc& d : L.desc) total += (double)d.N * d.N * d.N;
+  int bs = 1;
+  double acc = (double)L.desc[0].N * L.desc[0].N * L.desc[0].N;
+  while (bs < nblk - 1 && acc < 0.5 * total) {
+    acc += (double)L.desc[bs].N * L.desc[bs].N * L.desc[bs].N;
+    ++bs;
+  }
+  if (hipEventRecord(as->fork, s) != hipSuccess || hipStreamWaitEvent(as->aux, as->fork, 0) != hipSuccess)
+    return X2C_EHIP;
+  const int r1 = run(0, bs, s);
+  const int r2 = run(bs, nblk - bs, as->aux);
+  if (hipEventRecord(as->join, as->aux) != hipSuccess || hipStreamWaitEvent(s, as->join, 0) != hipSuccess)
+    return X2C_EHIP;
+  return r1 != X2C_OK ? r1 : r2;
+}
+
+int split_ways() {
+  std::lock_guard<std::mutex> lk(g_smu);
+  return g_split;
 }
 
 // ---------------------------------------------------------------- graphs
@@ -581,17 +638,11 @@ struct GraphRec {
 std::mutex g_gmu;
 bool g_graph_on = true;
 std::map<std::vector<int64_t>, std::shared_ptr<GraphRec>> g_graphs;
-std::map<int, hipStream_t> g_capture_streams;
 
 hipStream_t capture_stream() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  auto it = g_capture_streams.find(dev);
-  if (it != g_capture_streams.end()) return it->second;
-  hipStream_t cs = nullptr;
-  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return nullptr;
-  g_capture_streams[dev] = cs;
-  return cs;
+  std::lock_guard<std::mutex> lk(g_smu);
+  AuxStreams* as = device_streams();
+  return as ? as->capture : nullptr;
 }
 
 int64_t as_key(const void* p) { return static_cast<int64_t>(reinterpret_cast<intptr_t>(p)); }
@@ -616,7 +667,7 @@ int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
   std::unique_lock<std::mutex> gl(g_gmu);
   if (!g_graph_on || tracing || !L->pinned) {
     gl.unlock();
-    return enqueue_all(o, *L, nblk, S, T, V, W, h, eps, Xo, Ro, info, ws, s);
+    return enqueue_all(o, *L, nblk, S, T, V, W, h, eps, Xo, Ro, info, ws, s, !tracing);
   }
   int64_t cbits;
   std::memcpy(&cbits, &o->c, sizeof(cbits));
@@ -624,7 +675,7 @@ int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
   (void)hipGetDevice(&dev);
   const std::vector<int64_t> key = {as_key(L.get()), as_key(S), as_key(T), as_key(V), as_key(W), as_key(h),
                                     as_key(eps), as_key(Xo), as_key(Ro), as_key(info), as_key(ws), o->mode,
-                                    o->prec, o->ozaki_slices, o->reduction, cbits, dev};
+                                    o->prec, o->ozaki_slices, o->reduction, cbits, dev, split_ways()};
   std::shared_ptr<GraphRec> rec;
   auto it = g_graphs.find(key);
   if (it != g_graphs.end()) {
@@ -635,7 +686,7 @@ int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
     // the capture starts after the caller's pending work on s only matters at
     // replay time; capturing itself enqueues nothing
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return X2C_EHIP;
-    const int rc = enqueue_all(o, *L, nblk, S, T, V, W, h, eps, Xo, Ro, info, ws, cs);
+    const int rc = enqueue_all(o, *L, nblk, S, T, V, W, h, eps, Xo, Ro, info, ws, cs, true);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &graph);
     if (rc != X2C_OK || ec != hipSuccess || !graph) {
@@ -774,6 +825,13 @@ void x2c_release(void) {
   trace_collect();
   for (hipEvent_t e : g_pool) hipEventDestroy(e);
   g_pool.clear();
+}
+
+int x2c_stream_split(int ways) {
+  std::lock_guard<std::mutex> lk(g_smu);
+  const int prev = g_split;
+  if (ways == 1 || ways == 2) g_split = ways;
+  return prev;
 }
 
 int x2c_graph_enable(int on) {

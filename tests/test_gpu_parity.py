@@ -320,6 +320,31 @@ def test_graph_replays_match_eager_runs():
         px.graph_enable(prev)
 
 
+def test_two_stream_split_matches_one_stream():
+    """The two-stream split of a batch changes only where blocks run: results
+    are bitwise those of the one-stream run (eager and graph replay)."""
+    px, torch = _px()
+    blocks = [atom_block(z) for z in (6, 47, 17, 1, 79)]
+    prev = px.stream_split(1)
+    try:
+        ref = gpu_batched(blocks, True)
+        for graph in (False, True):
+            pg = px.graph_enable(graph)
+            try:
+                px.stream_split(2)
+                for _ in range(2):
+                    print(f"  split call graph={graph}", flush=True)
+                    got = gpu_batched(blocks, True)
+                    assert np.array_equal(ref[2], got[2])
+                    for a, b in zip(ref[0] + ref[1], got[0] + got[1]):
+                        assert np.array_equal(a, b)
+            finally:
+                px.graph_enable(pg)
+                px.stream_split(1)
+    finally:
+        px.stream_split(prev)
+
+
 def test_determinism_two_calls():
     blocks = [atom_block(z) for z in (6, 47)]
     a = gpu_batched(blocks, True)
