@@ -106,8 +106,8 @@ def parse():
     ap.add_argument("--check-blocks", type=int, default=3, help="blocks checked against the oracle")
     ap.add_argument("--cpu-blocks", type=int, default=12, help="blocks in the CPU oracle sample (0 = skip)")
     ap.add_argument("--no-trace", action="store_true")
-    ap.add_argument("--streams", type=int, choices=[1, 2], default=2,
-                    help="run the batch as two parts on two streams (2) or on one stream (1)")
+    ap.add_argument("--streams", type=int, choices=[1, 2, 3, 4], default=4,
+                    help="run the batch as this many parts on as many streams")
     ap.add_argument("--no-graph", action="store_true", help="eager launches instead of graph replay")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the workload, copy a device buffer of this size once (a plain copy kernel "

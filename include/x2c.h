@@ -212,15 +212,15 @@ void x2c_release(void);
 int x2c_graph_enable(int on);
 
 /*
- * Two-stream execution of a batch (Sec. III.A: the per-block problems are
- * independent).  ways = 2 (the default): a call with two or more blocks cuts
- * the batch into two parts of about equal work (sum of N^3); the first part
- * runs on the caller's stream, the second on an auxiliary stream of the
- * library, forked from and joined back into the caller's stream with events
- * (captured graphs contain both branches).  ways = 1: one stream.  Results
- * are identical either way; calls made while tracing is enabled use one
- * stream.  Other values leave the setting unchanged.  Returns the previous
- * setting.
+ * Multi-stream execution of a batch (Sec. III.A: the per-block problems are
+ * independent).  ways in 2..4 (default 4): a call with two or more blocks
+ * cuts the batch into min(ways, blocks) parts of about equal work (sum of
+ * N^3); the first part runs on the caller's stream, the others on auxiliary
+ * streams of the library, forked from and joined back into the caller's
+ * stream with events (captured graphs contain every branch).  ways = 1: one
+ * stream.  Results are identical either way; calls made while tracing is
+ * enabled use one stream.  Other values leave the setting unchanged.
+ * Returns the previous setting.
  */
 int x2c_stream_split(int ways);
 

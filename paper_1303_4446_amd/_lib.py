@@ -121,11 +121,11 @@ def graph_enable(on: bool) -> bool:
 
 
 def stream_split(ways: int) -> int:
-    """Run a batch of two or more blocks as two parts on two streams (2, the
-    default) or on the caller's stream only (1); returns the previous
+    """Run a batch as up to `ways` parts of about equal work on as many
+    streams (1..4; 1 = the caller's stream only); returns the previous
     setting."""
-    if ways not in (1, 2):
-        raise ValueError("ways must be 1 or 2")
+    if ways not in (1, 2, 3, 4):
+        raise ValueError("ways must be 1, 2, 3 or 4")
     return int(load().x2c_stream_split(int(ways)))
 
 

@@ -552,11 +552,14 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
 
 // Streams of the library (one set per device, default priority): the
 // capture stream of the graphs and the auxiliary stream of split batches.
+constexpr int MAX_SPLIT = 4;
 std::mutex g_smu;
-int g_split = 2;
+int g_split = 4;
 struct AuxStreams {
-  hipStream_t capture = nullptr, aux = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t capture = nullptr;
+  hipStream_t aux[MAX_SPLIT - 1] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[MAX_SPLIT - 1] = {};
 };
 std::map<int, AuxStreams> g_streams;
 
@@ -564,17 +567,28 @@ AuxStreams* device_streams() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
   AuxStreams& a = g_streams[dev];
-  if (!a.capture && hipStreamCreateWithFlags(&a.capture, hipStreamNonBlocking) != hipSuccess) a.capture = nullptr;
-  if (!a.aux && hipStreamCreateWithFlags(&a.aux, hipStreamNonBlocking) != hipSuccess) a.aux = nullptr;
-  if (!a.fork && hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess) a.fork = nullptr;
-  if (!a.join && hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess) a.join = nullptr;
-  return (a.capture && a.aux && a.fork && a.join) ? &a : nullptr;
+  bool ok = true;
+  auto mk_stream = [&](hipStream_t& st) {
+    if (!st && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    ok = ok && st;
+  };
+  auto mk_event = [&](hipEvent_t& e) {
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+    ok = ok && e;
+  };
+  mk_stream(a.capture);
+  mk_event(a.fork);
+  for (int i = 0; i < MAX_SPLIT - 1; ++i) {
+    mk_stream(a.aux[i]);
+    mk_event(a.join[i]);
+  }
+  return ok ? &a : nullptr;
 }
 
 // descriptor upload + every stage of one call, enqueued on s.  With
-// splitting on, the batch is cut into two parts of about equal work
-// (sum of N^3): the first runs on s, the second on the library's auxiliary
-// stream, forked from and joined back into s by events, so that the
+// splitting on, the batch is cut into up to g_split parts of about equal
+// work (sum of N^3): the first runs on s, the others on auxiliary streams of
+// the library, forked from and joined back into s by events, so that the
 // latency-bound steps of one part (the per-column kernels of the
 // reductions, the LU panels) overlap the bandwidth- and matrix-core-bound
 // kernels of the other.  Blocks never share workspace, so the two parts are
@@ -594,26 +608,43 @@ int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S
                               static_cast<double*>(Ro), info + b0, ws, st);
   };
   std::unique_lock<std::mutex> lk(g_smu);
-  AuxStreams* as = (allow_split && g_split >= 2 && nblk >= 2) ? device_streams() : nullptr;
+  const int ways = std::min(g_split, nblk);
+  AuxStreams* as = (allow_split && ways >= 2) ? device_streams() : nullptr;
   if (!as) {
     lk.unlock();
     return run(0, nblk, s);
   }
+  // part boundaries at equal shares of the work
   double total = 0.0;
   for (const BlockDesc& d : L.desc) total += (double)d.N * d.N * d.N;
-  int bs = 1;
-  double acc = (double)L.desc[0].N * L.desc[0].N * L.desc[0].N;
-  while (bs < nblk - 1 && acc < 0.5 * total) {
-    acc += (double)L.desc[bs].N * L.desc[bs].N * L.desc[bs].N;
-    ++bs;
+  int bnd[MAX_SPLIT + 1];
+  bnd[0] = 0;
+  bnd[ways] = nblk;
+  {
+    double acc = 0.0;
+    int b = 0;
+    for (int p = 1; p < ways; ++p) {
+      while (b < nblk && acc < total * p / ways) {
+        acc += (double)L.desc[b].N * L.desc[b].N * L.desc[b].N;
+        ++b;
+      }
+      bnd[p] = std::min(std::max(b, bnd[p - 1] + 1), nblk - (ways - p));
+      b = bnd[p];
+    }
   }
-  if (hipEventRecord(as->fork, s) != hipSuccess || hipStreamWaitEvent(as->aux, as->fork, 0) != hipSuccess)
-    return X2C_EHIP;
-  const int r1 = run(0, bs, s);
-  const int r2 = run(bs, nblk - bs, as->aux);
-  if (hipEventRecord(as->join, as->aux) != hipSuccess || hipStreamWaitEvent(s, as->join, 0) != hipSuccess)
-    return X2C_EHIP;
-  return r1 != X2C_OK ? r1 : r2;
+  if (hipEventRecord(as->fork, s) != hipSuccess) return X2C_EHIP;
+  for (int p = 1; p < ways; ++p)
+    if (hipStreamWaitEvent(as->aux[p - 1], as->fork, 0) != hipSuccess) return X2C_EHIP;
+  int rc = X2C_OK;
+  for (int p = 0; p < ways; ++p) {
+    const int r = run(bnd[p], bnd[p + 1] - bnd[p], p == 0 ? s : as->aux[p - 1]);
+    if (rc == X2C_OK) rc = r;
+  }
+  for (int p = 1; p < ways; ++p)
+    if (hipEventRecord(as->join[p - 1], as->aux[p - 1]) != hipSuccess ||
+        hipStreamWaitEvent(s, as->join[p - 1], 0) != hipSuccess)
+      return X2C_EHIP;
+  return rc;
 }
 
 int split_ways() {
@@ -830,7 +861,7 @@ void x2c_release(void) {
 int x2c_stream_split(int ways) {
   std::lock_guard<std::mutex> lk(g_smu);
   const int prev = g_split;
-  if (ways == 1 || ways == 2) g_split = ways;
+  if (ways >= 1 && ways <= MAX_SPLIT) g_split = ways;
   return prev;
 }
 

@@ -320,9 +320,10 @@ def test_graph_replays_match_eager_runs():
         px.graph_enable(prev)
 
 
-def test_two_stream_split_matches_one_stream():
-    """The two-stream split of a batch changes only where blocks run: results
-    are bitwise those of the one-stream run (eager and graph replay)."""
+@pytest.mark.parametrize("ways", [2, 3, 4])
+def test_stream_split_matches_one_stream(ways):
+    """The multi-stream split of a batch changes only where blocks run:
+    results are bitwise those of the one-stream run (eager and graph)."""
     px, torch = _px()
     blocks = [atom_block(z) for z in (6, 47, 17, 1, 79)]
     prev = px.stream_split(1)
@@ -331,9 +332,9 @@ def test_two_stream_split_matches_one_stream():
         for graph in (False, True):
             pg = px.graph_enable(graph)
             try:
-                px.stream_split(2)
+                px.stream_split(ways)
                 for _ in range(2):
-                    print(f"  split call graph={graph}", flush=True)
+                    print(f"  split call ways={ways} graph={graph}", flush=True)
                     got = gpu_batched(blocks, True)
                     assert np.array_equal(ref[2], got[2])
                     for a, b in zip(ref[0] + ref[1], got[0] + got[1]):
