@@ -356,6 +356,180 @@ void launch_gemm_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info,
                      bufC, alpha, beta, herm);
 }
 
+// Products of a quaternion matrix with a real scalar matrix R (N x N,
+// row-major doubles: S, T and the Cholesky factors and inverses, which act on
+// both spin components alike).  side 0: C = alpha op(R) Q + beta C; side 1:
+// C = alpha Q op(R) + beta C; op(R) = R or R^T.  A real factor multiplies
+// each quaternion component separately, so one quaternion multiply-add is 4
+// real ones (4 MFMAs per 16 x 16 block and k step, against 16).  tri = 1 / 2:
+// op(R) is lower / upper triangular (entries outside the triangle are taken
+// as zero, whatever is stored), and the k range of each tile is cut to where
+// op(R) can be non-zero.
+template <int side>
+__global__ void __launch_bounds__(256)
+k_gemm_qr_mfma(const BlockDesc* D, char* ws, const int* info, int bufR, int opR, int tri, int bufQ, int bufC,
+               double alpha, double beta, int herm) {
+  const int b = blockIdx.z;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = d.N;
+  const int m0 = blockIdx.y * GM_T, n0 = blockIdx.x * GM_T;
+  if (m0 >= n || n0 >= n) return;
+  if (herm && blockIdx.x > blockIdx.y) return;
+  const double* R = bufp<double>(ws, d, bufR);
+  const quat* Q = bufp<quat>(ws, d, bufQ);
+  quat* C = bufp<quat>(ws, d, bufC);
+  // k range where op(R) may be non-zero for this tile
+  int kbeg = 0, kend = n;
+  if constexpr (side == 0) {     // op(R)[i][k], rows i in [m0, m0 + 64)
+    if (tri == 1) kend = min(n, m0 + GM_T);
+    if (tri == 2) kbeg = m0;
+  } else {                       // op(R)[k][j], columns j in [n0, n0 + 64)
+    if (tri == 2) kend = min(n, n0 + GM_T);
+    if (tri == 1) kbeg = n0;
+  }
+  __shared__ double Rs[GM_T * (GM_K + 1)];   // side 0: [row][k] (stride 17); side 1: [k][col] (stride 65)
+  __shared__ double Qs[4][GM_T * (GM_K + 1)];   // side 0: [k][col] (stride 65); side 1: [row][k] (stride 17)
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  d4 acc[2][2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[x][y][c] = d4{0.0, 0.0, 0.0, 0.0};
+  // element (i, j) of op(R), zero outside its triangle and the matrix
+  auto rval = [&](int i, int j) -> double {
+    if (i >= n || j >= n || (tri == 1 && j > i) || (tri == 2 && j < i)) return 0.0;
+    return opR == 0 ? R[(long long)i * n + j] : R[(long long)j * n + i];
+  };
+  constexpr int NL = GM_T * GM_K / 256;
+  double nr[NL];
+  quat nq[NL];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int l = t + 256 * q;
+      if constexpr (side == 0) {
+        // op(R) rows m0.., k chunk: consecutive threads along k (op N) or rows (op T)
+        int r, kk;
+        if (opR == 0) { r = l / GM_K; kk = l % GM_K; } else { kk = l / GM_T; r = l % GM_T; }
+        nr[q] = rval(m0 + r, k0 + kk);
+        const int kq = l / GM_T, cq = l % GM_T;
+        const int gk = k0 + kq, gc = n0 + cq;
+        nq[q] = (gk < n && gc < n) ? Q[(long long)gk * n + gc] : tzero<quat>();
+      } else {
+        int kk, cc;
+        if (opR == 0) { kk = l / GM_T; cc = l % GM_T; } else { cc = l / GM_K; kk = l % GM_K; }
+        nr[q] = rval(k0 + kk, n0 + cc);
+        const int rq = l / GM_K, kq = l % GM_K;
+        const int gr = m0 + rq, gk = k0 + kq;
+        nq[q] = (gr < n && gk < n) ? Q[(long long)gr * n + gk] : tzero<quat>();
+      }
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int l = t + 256 * q;
+      int qi;
+      if constexpr (side == 0) {
+        int r, kk;
+        if (opR == 0) { r = l / GM_K; kk = l % GM_K; } else { kk = l / GM_T; r = l % GM_T; }
+        Rs[r * (GM_K + 1) + kk] = nr[q];
+        qi = (l / GM_T) * (GM_T + 1) + l % GM_T;            // [k][col]
+      } else {
+        int kk, cc;
+        if (opR == 0) { kk = l / GM_T; cc = l % GM_T; } else { cc = l / GM_K; kk = l % GM_K; }
+        Rs[kk * (GM_T + 1) + cc] = nr[q];
+        qi = (l / GM_K) * (GM_K + 1) + l % GM_K;            // [row][k]
+      }
+      Qs[0][qi] = nq[q].a.x;
+      Qs[1][qi] = nq[q].a.y;
+      Qs[2][qi] = nq[q].b.x;
+      Qs[3][qi] = nq[q].b.y;
+    }
+  };
+  kbeg = (kbeg / GM_K) * GM_K;
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash();
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += GM_K) {
+    const bool more = k0 + GM_K < kend;
+    if (more) fetch(k0 + GM_K);
+#pragma unroll
+    for (int ks = 0; ks < GM_K; ks += 4) {
+      if constexpr (side == 0) {
+        double a[2], bq[2][4];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          a[x] = Rs[(wr + 16 * x + l16) * (GM_K + 1) + ks + l4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) bq[x][c] = Qs[c][(ks + l4) * (GM_T + 1) + wc + 16 * x + l16];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], bq[y][c], acc[x][y][c], 0, 0, 0);
+      } else {
+        double aq[2][4], bb[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          bb[x] = Rs[(ks + l4) * (GM_T + 1) + wc + 16 * x + l16];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) aq[x][c] = Qs[c][(wr + 16 * x + l16) * (GM_K + 1) + ks + l4];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[x][c], bb[y], acc[x][y][c], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (more) {
+      stash();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = m0 + wr + 16 * x + l4 + 4 * i, cc = n0 + wc + 16 * y + l16;
+        if (r >= n || cc >= n) continue;
+        if (herm && cc > r) continue;
+        const long long idx = (long long)r * n + cc;
+        quat v = {{alpha * acc[x][y][0][i], alpha * acc[x][y][1][i]},
+                  {alpha * acc[x][y][2][i], alpha * acc[x][y][3][i]}};
+        if (beta != 0.0) v = v + beta * C[idx];
+        C[idx] = v;
+        if (herm && cc < r) C[(long long)cc * n + r] = conjg(v);
+      }
+}
+
+void launch_gemm_qr(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int side,
+                    int bufR, int opR, int tri, int bufQ, int bufC, double alpha, double beta, int herm) {
+  int t = (maxN + GM_T - 1) / GM_T;
+  if (side == 0)
+    hipLaunchKernelGGL(k_gemm_qr_mfma<0>, dim3(t, t, nblk), dim3(256), 0, s, D, ws, info, bufR, opR, tri, bufQ,
+                       bufC, alpha, beta, herm);
+  else
+    hipLaunchKernelGGL(k_gemm_qr_mfma<1>, dim3(t, t, nblk), dim3(256), 0, s, D, ws, info, bufR, opR, tri, bufQ,
+                       bufC, alpha, beta, herm);
+}
+
 template <class T>
 void launch_gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                  int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int herm) {

@@ -130,9 +130,10 @@ __global__ void k_qct_scale(const BlockDesc* D, char* ws, const int* info, int s
 }
 
 // Quaternion (N x N) form of the two-component matrices of the product
-// chain: S, T, V, L_S, L_S^-1, L_T^-1 are real scalar matrices (spin
-// diagonal), W'' = W/4c^2 - T has a = (W^0 - 4c^2 T + i W^z)/4c^2 and
-// b = (W^y + i W^x)/4c^2 (Eq. defw in the [alpha; beta] order).
+// chain that enter as quaternion operands: S and V (real scalar matrices,
+// spin diagonal) and W'' = W/4c^2 - T with a = (W^0 - 4c^2 T + i W^z)/4c^2
+// and b = (W^y + i W^x)/4c^2 (Eq. defw in the [alpha; beta] order).  T and
+// the Cholesky factors enter the products as real matrices directly.
 __global__ void k_expand_q(const BlockDesc* D, char* ws, const int* info, double c) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
@@ -143,29 +144,18 @@ __global__ void k_expand_q(const BlockDesc* D, char* ws, const int* info, double
   const double* s = bufp<double>(ws, d, R_S);
   const double* t = bufp<double>(ws, d, R_T);
   const double* v = bufp<double>(ws, d, R_V);
-  const double* ls = bufp<double>(ws, d, R_LS);
-  const double* lsi = bufp<double>(ws, d, R_LSI);
-  const double* lti = bufp<double>(ws, d, R_LTI);
   const double* w0 = bufp<double>(ws, d, R_W0);
   const double* wx = bufp<double>(ws, d, R_W1);
   const double* wy = bufp<double>(ws, d, R_W2);
   const double* wz = bufp<double>(ws, d, R_W3);
   quat* oS = bufp<quat>(ws, d, C_S);
-  quat* oT = bufp<quat>(ws, d, C_T);
   quat* oV = bufp<quat>(ws, d, C_V);
   quat* oW = bufp<quat>(ws, d, C_WPP);
-  quat* oLS = bufp<quat>(ws, d, C_LS);
-  quat* oLSI = bufp<quat>(ws, d, C_LSI);
-  quat* oLTI = bufp<quat>(ws, d, C_LTI);
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
        e += (long long)gridDim.x * blockDim.x) {
     const double tv = t[e];
     oS[e] = treal<quat>(s[e]);
-    oT[e] = treal<quat>(tv);
     oV[e] = treal<quat>(v[e]);
-    oLS[e] = treal<quat>(ls[e]);
-    oLSI[e] = treal<quat>(lsi[e]);
-    oLTI[e] = treal<quat>(lti[e]);
     oW[e] = quat{{w0[e] * q4 - tv, wz[e] * q4}, {wy[e] * q4, wx[e] * q4}};
   }
 }

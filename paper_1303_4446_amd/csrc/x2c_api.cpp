@@ -386,6 +386,12 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
     if (qchain) launch_gemm_q(s, D, ws, info, nblk, maxN, DIM_N, bA, opA, bB, opB, bC, alpha, beta, herm);
     else chain_gemm(bA, opA, bB, opB, bC, tcast<T>(alpha), tcast<T>(beta), herm);
   };
+  // quaternion x real scalar matrix (R_* buffers): side 0 op(R) Q, side 1
+  // Q op(R); tri 1 / 2 = op(R) lower / upper triangular
+  auto GR = [&](int side, int bR, int opR, int tri, int bQ, int bC, double alpha, double beta, int herm = 0) {
+    launch_gemm_qr(s, D, ws, info, nblk, maxN, side, bR, opR, tri, bQ, bC, alpha, beta, herm);
+  };
+  const int LOWER = 1, UPPER = 2;
   auto copy_buf = [&](int src, int dst) {
     if (qchain) launch_copy<quat>(s, D, ws, info, nblk, maxN, DIM_N, src, dst);
     else launch_copy<T>(s, D, ws, info, nblk, maxn, DIM_n, src, dst);
@@ -469,13 +475,19 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
     } else {
       launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn, C_Y, DIM_n, C_TMP);
     }
-    G(qchain ? C_QMH : C_TMP, OPN, C_LS, OPH, C_TMP2, 1.0, 0.0);
-    G(C_LTI, OPH, C_TMP2, OPN, C_X, std::sqrt(2.0) * c, 0.0);
+    if (qchain) {
+      GR(1, R_LS, OPH, UPPER, C_QMH, C_TMP2, 1.0, 0.0);
+      GR(0, R_LTI, OPH, UPPER, C_TMP2, C_X, std::sqrt(2.0) * c, 0.0);
+    } else {
+      G(C_TMP, OPN, C_LS, OPH, C_TMP2, 1.0, 0.0);
+      G(C_LTI, OPH, C_TMP2, OPN, C_X, std::sqrt(2.0) * c, 0.0);
+    }
   }
   {
     // S~ = S + X^H T X / 2c^2 ;  L = V + TX + (TX)^H + X^H (W/4c^2 - T) X
     STAGE("chain_SL");
-    G(C_T, OPN, C_X, OPN, C_TX, 1.0, 0.0);
+    if (qchain) GR(0, R_T, OPN, 0, C_X, C_TX, 1.0, 0.0);
+    else G(C_T, OPN, C_X, OPN, C_TX, 1.0, 0.0);
     copy_buf(C_S, C_Q);
     G(C_X, OPH, C_TX, OPN, C_Q, 1.0 / (2.0 * c * c), 1.0, 1);
     G(C_WPP, OPN, C_X, OPN, C_WX, 1.0, 0.0);
@@ -486,8 +498,13 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
   {
     // Q = L_S^-1 S~ L_S^-H
     STAGE("chain_Q");
-    G(C_LSI, OPN, C_Q, OPN, C_TMP, 1.0, 0.0);
-    G(C_TMP, OPN, C_LSI, OPH, C_Q, 1.0, 0.0, 1);
+    if (qchain) {
+      GR(0, R_LSI, OPN, LOWER, C_Q, C_TMP, 1.0, 0.0);
+      GR(1, R_LSI, OPH, UPPER, C_TMP, C_Q, 1.0, 0.0, 1);
+    } else {
+      G(C_LSI, OPN, C_Q, OPN, C_TMP, 1.0, 0.0);
+      G(C_TMP, OPN, C_LSI, OPH, C_Q, 1.0, 0.0, 1);
+    }
   }
   if (!kramers) {
     {
@@ -526,8 +543,13 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
   {
     // R = L_S^-H Q^-1/2 L_S^H
     STAGE("chain_R");
-    G(qchain ? C_LR : C_QMH, OPN, C_LS, OPH, C_TMP, 1.0, 0.0);
-    G(C_LSI, OPH, C_TMP, OPN, C_R, 1.0, 0.0);
+    if (qchain) {
+      GR(1, R_LS, OPH, UPPER, C_LR, C_TMP, 1.0, 0.0);
+      GR(0, R_LSI, OPH, UPPER, C_TMP, C_R, 1.0, 0.0);
+    } else {
+      G(C_QMH, OPN, C_LS, OPH, C_TMP, 1.0, 0.0);
+      G(C_LSI, OPH, C_TMP, OPN, C_R, 1.0, 0.0);
+    }
   }
   {
     // h = R^H (L R)

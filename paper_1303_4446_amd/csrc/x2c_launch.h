@@ -77,6 +77,8 @@ void launch_cplx_to_quat(hipStream_t s, const BlockDesc* D, char* ws, const int*
 void launch_expand_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double c);
 void launch_write_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double* out,
                     int buf, double* eps);
+void launch_gemm_qr(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int side,
+                    int bufR, int opR, int tri, int bufQ, int bufC, double alpha, double beta, int herm);
 void launch_gemm_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                    int bufA, int opA, int bufB, int opB, int bufC, double alpha, double beta, int herm);
 void launch_quat_to_cplx(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
