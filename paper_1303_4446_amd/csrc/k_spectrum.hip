@@ -549,13 +549,27 @@ __global__ void __launch_bounds__(256) k_tri_eig_q(const BlockDesc* D, char* ws,
   }
 }
 
-// F[:, k] = sum_j w_j (T_Q + s_j I)^-1 e_k  (F written T-typed into C_TMP;
-// per-column scratch in C_TMP2).  grid = (ceil(n/256), nblk)
-// (quaternion form: rows scaled by the phases, F_q = D F)
+// F = sum_j w_j (T_Q + s_j I)^-1 (symmetric): column k of its lower
+// triangle, F[i][k] for i >= k, from the LDL^T factors of every node by a
+// forward sweep from row k and a backward sweep down to row k.  Work-group
+// (column chunk, node group g, block): group g takes the nodes j = g, g + G,
+// ... into its own real n x n partial; the forward sweep keeps its state at
+// every IK-th row and the backward sweep re-runs it chunk by chunk in
+// registers (as in k_filter_solve).  k_invsqrt_finish adds the partials in a
+// fixed order, mirrors the triangle and writes F T-typed into C_TMP
+// (quaternion form: rows scaled by the phases, F_q = D F).
+// Partials: in C_TMP itself when T is real and G = 1, else at the start of
+// the scratch buffer; checkpoints after them.
+constexpr int IK = 16;
+
+__device__ inline double* invsqrt_partials(const BlockDesc& d, char* ws, int n, int bufScr, bool real1) {
+  return real1 ? bufp<double>(ws, d, C_TMP) : bufp<double>(ws, d, bufScr);
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) k_invsqrt_cols(const BlockDesc* D, char* ws, const int* info, int dsel,
-                                                      int bufScr) {
-  const int b = blockIdx.y;
+                                                      int bufScr, int G) {
+  const int b = blockIdx.z, g = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int n = seldim(d, dsel);
@@ -563,35 +577,86 @@ __global__ void __launch_bounds__(256) k_invsqrt_cols(const BlockDesc* D, char* 
   if (k >= n) return;
   const double* pq = bufp<double>(ws, d, P_QUAD);
   const double* fac = bufp<double>(ws, d, Q_FAC);
-  T* F = bufp<T>(ws, d, C_TMP);
-  double* y = bufp<double>(ws, d, bufScr);   // n x n doubles of scratch
-  const int N = (int)pq[0];
-  for (int i = 0; i < n; ++i) F[(long long)i * n + k] = tzero<T>();
-  for (int j = 0; j < N; ++j) {
+  const int nodes = (int)pq[0];
+  const bool real1 = sizeof(T) == sizeof(double) && G == 1;
+  double* acc = invsqrt_partials(d, ws, n, bufScr, real1) + (long long)g * n * n;
+  const int nck = (n + IK - 1) / IK;
+  double* ck = (real1 ? bufp<double>(ws, d, bufScr) : invsqrt_partials(d, ws, n, bufScr, false) +
+                                                        (long long)G * n * n) +
+               (long long)g * nck * n;
+  bool fresh = true;
+  for (int j = g; j < nodes; j += G) {
     const double* f = fac + (long long)j * n * 2;
     const double w = pq[3 + j];
-    // forward L y = e_k (zeros above k), then z = D^-1 y
+    // forward L y = e_k from row k (y_k = 1); checkpoints of y at rows
+    // i = IK c > k
     double yi = 1.0;
-    y[(long long)k * n + k] = yi * f[2 * k + 1];
     for (int i = k + 1; i < n; ++i) {
       yi = -f[2 * (i - 1)] * yi;
-      y[(long long)i * n + k] = yi * f[2 * i + 1];
+      if (i % IK == 0) ck[(long long)(i / IK) * n + k] = yi;
     }
-    // backward L^T x = z
+    // backward L^T x = D^-1 y, rows n-1 .. k, one chunk of IK rows at a time
     double x = 0.0;
-    for (int i = n - 1; i >= 0; --i) {
-      double z = i >= k ? y[(long long)i * n + k] : 0.0;
-      x = z - f[2 * i] * x;
-      long long idx = (long long)i * n + k;
-      F[idx] = treal<T>(re(F[idx]) + w * x);
+    const int c0 = k / IK;
+    for (int c = nck - 1; c >= c0; --c) {
+      const int i0 = c * IK;
+      const int ib = max(i0, k);                  // first row of the chunk inside the triangle
+      double y = ib == k ? 1.0 : ck[(long long)c * n + k];
+      double zb[IK], ab[IK];
+#pragma unroll
+      for (int u = 0; u < IK; ++u) {
+        const int i = i0 + u;
+        const int ic = min(max(i, k), n - 1);
+        ab[u] = fresh ? 0.0 : acc[(long long)ic * n + k];
+      }
+#pragma unroll
+      for (int u = 0; u < IK; ++u) {
+        const int i = i0 + u;
+        if (i > ib && i < n) y = -f[2 * (i - 1)] * y;
+        zb[u] = (i >= ib && i < n) ? y * f[2 * i + 1] : 0.0;
+      }
+#pragma unroll
+      for (int u = IK - 1; u >= 0; --u) {
+        const int i = i0 + u;
+        if (i >= k && i < n) {
+          x = zb[u] - f[2 * i] * x;
+          acc[(long long)i * n + k] = ab[u] + w * x;
+        }
+      }
     }
+    fresh = false;
   }
-  if constexpr (sizeof(T) == sizeof(quat)) {
-    const quat* del = bufp<quat>(ws, d, V_DEL);
-    for (int i = 0; i < n; ++i) {
-      long long idx = (long long)i * n + k;
-      F[idx] = re(F[idx]) * del[i];
+}
+
+template <class T>
+__global__ void k_invsqrt_finish(const BlockDesc* D, char* ws, const int* info, int dsel, int bufScr, int G) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = seldim(d, dsel);
+  const int nodes = (int)bufp<double>(ws, d, P_QUAD)[0];
+  const int ng = min(G, nodes);
+  const bool real1 = sizeof(T) == sizeof(double) && G == 1;
+  const double* acc = invsqrt_partials(d, ws, n, bufScr, real1);
+  T* F = bufp<T>(ws, d, C_TMP);
+  const long long nn = (long long)n * n;
+  if (real1) {
+    // partial is F itself: mirror the lower triangle
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+         e += (long long)gridDim.x * blockDim.x) {
+      const int i = (int)(e / n), k = (int)(e % n);
+      if (k > i) F[e] = treal<T>(acc[(long long)k * n + i]);
     }
+    return;
+  }
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), k = (int)(e % n);
+    const long long src = i >= k ? e : (long long)k * n + i;
+    double v = acc[src];
+    for (int g = 1; g < ng; ++g) v += acc[(long long)g * nn + src];
+    if constexpr (sizeof(T) == sizeof(quat)) F[e] = v * bufp<quat>(ws, d, V_DEL)[i];
+    else F[e] = treal<T>(v);
   }
 }
 
@@ -628,8 +693,13 @@ void launch_tri_eig_q(hipStream_t s, const BlockDesc* D, char* ws, int* info, in
 template <class T>
 void launch_invsqrt_cols(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                          int bufScr) {
-  hipLaunchKernelGGL(k_invsqrt_cols<T>, dim3((maxdim + 255) / 256, nblk), dim3(256), 0, s, D, ws, info, dsel,
-                     bufScr);
+  // node groups: the quaternion form's scratch (C_QMH) holds four partials
+  const int G = is_quat<T>() ? 4 : 1;
+  hipLaunchKernelGGL(k_invsqrt_cols<T>, dim3((maxdim + 255) / 256, G, nblk), dim3(256), 0, s, D, ws, info, dsel,
+                     bufScr, G);
+  long long gx = ((long long)maxdim * maxdim + 255) / 256;
+  if (gx > 256) gx = 256;
+  hipLaunchKernelGGL(k_invsqrt_finish<T>, dim3((int)gx, nblk), dim3(256), 0, s, D, ws, info, dsel, bufScr, G);
 }
 template void launch_filter_solve<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int);
 template void launch_filter_solve<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int);
