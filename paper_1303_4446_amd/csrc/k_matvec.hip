@@ -21,14 +21,15 @@ struct MvItem {
   int valid, b, SI, SJ, len, n, nst;
 };
 
+// len (returned) counts the lead virtual rows of the tiling too
 __device__ inline MvItem mv_decode(const BlockDesc* D, const int* info, int dsel, int k, int nblk, int nsmax,
-                                   int item, int ST) {
+                                   int item, int ST, int lead) {
   MvItem it{0, 0, 0, 0, 0, 0, 0};
   const int b = item / nsmax, st = item - (item / nsmax) * nsmax;
   if (b >= nblk || info[b]) return it;
   const int n = seldim(D[b], dsel);
-  const int len = n - k - 1;
-  if (len <= 0) return it;
+  if (n - k - 1 <= 0) return it;
+  const int len = n - k - 1 + lead;
   const int nst = (len + ST - 1) / ST;
   if (st >= nst * (nst + 1) / 2) return it;
   int SI = (int)((sqrt(8.0 * st + 1.0) - 1.0) * 0.5);
@@ -77,12 +78,12 @@ __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws
   T (*tl)[HT + 1] = tiles[wave];
   const int total = nblk * nsmax;
   int item = blockIdx.x;
-  MvItem cur = mv_decode(D, info, dsel, k, nblk, nsmax, item, ST);
+  MvItem cur = mv_decode(D, info, dsel, k, nblk, nsmax, item, ST, 0);
   T regs[EPL];
   if (cur.valid) mv_load<T>(D, ws, bufA, k, cur, wi, wj, lane, regs);
   while (item < total) {
     const int nitem = item + gridDim.x;
-    const MvItem nxt = mv_decode(D, info, dsel, k, nblk, nsmax, nitem, ST);
+    const MvItem nxt = mv_decode(D, info, dsel, k, nblk, nsmax, nitem, ST, 0);
     T nregs[EPL];
     if (nxt.valid) mv_load<T>(D, ws, bufA, k, nxt, wi, wj, lane, nregs);
     if (cur.valid) {
@@ -223,14 +224,16 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
   // every other step walks the items in reverse, so that a launch starts on
   // the matrices its predecessor read last (still in the memory-side cache)
   const bool rev = k & 1;
+  // tile index r covers matrix row / column off + r; r < lead are virtual
+  const int lead = mv_lead<quat>(k), off = k + 1 - lead;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    const MvItem it = mv_decode(D, info, dsel, k, nblk, nsmax, rev ? total - 1 - item : item, ST);
+    const MvItem it = mv_decode(D, info, dsel, k, nblk, nsmax, rev ? total - 1 - item : item, ST, lead);
     if (!it.valid) continue;
     const BlockDesc& d = D[it.b];
     const quat* A = bufp<quat>(ws, d, bufA);
     const quat* vg = bufp<quat>(ws, d, bufV);
     quat* HS = bufp<quat>(ws, d, bufHS);
-    const int off = k + 1, len = it.len, n = it.n, nst = it.nst, SI = it.SI, SJ = it.SJ;
+    const int len = it.len, n = it.n, nst = it.nst, SI = it.SI, SJ = it.SJ;
     const bool diag = SI == SJ;
     const int R0 = ST * SI, C0 = ST * SJ;
     // ---- issue every load of the item
@@ -244,14 +247,14 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
       for (int q = 0; q < EPL; ++q) {
         const int ii = lane / HT + (64 / HT) * q, jj = lane % HT;
         const int r = R0 + HT * a + ii, c = C0 + HT * bb + jj;
-        regs[s][q] = (!skip && r < len && c < len && (!dsub || ii >= jj))
+        regs[s][q] = (!skip && r < len && c < len && r >= lead && c >= lead && (!dsub || ii >= jj))
                          ? A[(long long)(off + r) * n + off + c] : tzero<quat>();
       }
     }
     {
       const int seg = lane >> 5, t = lane & 31;
       const int g = (seg == 0 ? R0 : C0) + t;
-      vsh[seg][t] = g < len ? vg[g] : tzero<quat>();
+      vsh[seg][t] = (g >= lead && g < len) ? vg[g - lead] : tzero<quat>();
     }
     if (lane < ST) {
       racc[lane] = tzero<quat>();
@@ -321,7 +324,7 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
 #pragma unroll
           for (int u = 0; u < PG; ++u) {
             const int r = R0 + HT * half + t0 + u;
-            const long long row = off + (r < len ? r : len - 1);
+            const long long row = off + min(max(r, lead), len - 1);
             wv[u] = Wp[row * HB + j];
             pv[u] = A[row * n + k0 + j];
           }

@@ -309,7 +309,9 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     const int kp = k0 + ip;
     const int off = kp + 1, len = n - kp - 1;
     const T tau = taus[kp];
-    const int nst = (len + ST - 1) / ST;
+    // the matvec's tiling: lead virtual rows, then the len trailing rows
+    const int lead = mv_lead<T>(kp), lenp = len + lead;
+    const int nst = (lenp + ST - 1) / ST;
     for (int r = tid; r < len; r += COLT) {
       v[r] = vg[r];
       if (build) acol[r] = A[(long long)(off + r) * n + k];
@@ -321,7 +323,7 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     // panel dot products t1 = W^H v, t2 = V^H v from the matvec's per-strip partials
     if (tid < ip) {
       T a1 = tzero<T>(), a2 = tzero<T>();
-      const T* TP = HS + (long long)2 * nst * len;
+      const T* TP = HS + (long long)2 * nst * lenp;
 #pragma unroll 4
       for (int S = 0; S < nst; ++S) {
         a1 = a1 + TP[((long long)S * HB + tid) * 2];
@@ -341,11 +343,11 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     // group's sums are combined by lane exchange in a fixed pattern.
     for (int r = tid / CTPR; r < len; r += COLT / CTPR) {
       const int q = tid % CTPR;
-      const int Sr = r / ST;
+      const int rt = r + lead, Sr = rt / ST;
       const long long rr = off + r;
       T acc = tzero<T>(), ca = tzero<T>();
       for (int S = q; S < nst; S += CTPR)
-        acc = acc + HS[(long long)(S <= Sr ? S : nst + S) * len + r];
+        acc = acc + HS[(long long)(S <= Sr ? S : nst + S) * lenp + rt];
       if (ip > 0) {
         T vr[HB / CTPR], wr[HB / CTPR];
 #pragma unroll
@@ -923,7 +925,7 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
                        bufV, bufHS, bufET, k0, 0, 0);
     for (int i = 0; i < kbmax; ++i) {
       const int k = k0 + i;
-      const int len = maxdim - k - 1;
+      const int len = maxdim - k - 1 + mv_lead<T>(k);
       const int nst = (len + ST - 1) / ST;
       const int nsmax = nst * (nst + 1) / 2;
       void* kt = ktrace_begin("k_tri_matvec", s);

@@ -27,6 +27,15 @@ struct Tiles<quat> {
 // panel width (reflectors per panel)
 constexpr int HB = 32;
 
+// Leading virtual rows / columns of the matvec tiling at column step k.  The
+// quaternion tiles start on a 128-byte boundary (4 quaternions): the trailing
+// matrix (first row / column k + 1) is preceded by (k + 1) mod 4 zero rows /
+// columns in the tile grid, so that no tile row starts inside a cache line.
+template <class T>
+__host__ __device__ constexpr int mv_lead(int k) {
+  return is_quat<T>() ? ((k + 1) & 3) : 0;
+}
+
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
