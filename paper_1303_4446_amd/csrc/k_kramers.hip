@@ -130,10 +130,11 @@ __global__ void k_qct_scale(const BlockDesc* D, char* ws, const int* info, int s
 }
 
 // Quaternion (N x N) form of the two-component matrices of the product
-// chain that enter as quaternion operands: S and V (real scalar matrices,
-// spin diagonal) and W'' = W/4c^2 - T with a = (W^0 - 4c^2 T + i W^z)/4c^2
-// and b = (W^y + i W^x)/4c^2 (Eq. defw in the [alpha; beta] order).  T and
-// the Cholesky factors enter the products as real matrices directly.
+// chain that enter as quaternion operands: V (a real scalar matrix, spin
+// diagonal) and W'' = W/4c^2 - T with a = (W^0 - 4c^2 T + i W^z)/4c^2 and
+// b = (W^y + i W^x)/4c^2 (Eq. defw in the [alpha; beta] order).  T and the
+// Cholesky factors enter the products as real matrices directly; S only
+// through its Cholesky factor.
 __global__ void k_expand_q(const BlockDesc* D, char* ws, const int* info, double c) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
@@ -141,23 +142,32 @@ __global__ void k_expand_q(const BlockDesc* D, char* ws, const int* info, double
   const int N = d.N;
   const long long nn = (long long)N * N;
   const double q4 = 1.0 / (4.0 * c * c);
-  const double* s = bufp<double>(ws, d, R_S);
   const double* t = bufp<double>(ws, d, R_T);
   const double* v = bufp<double>(ws, d, R_V);
   const double* w0 = bufp<double>(ws, d, R_W0);
   const double* wx = bufp<double>(ws, d, R_W1);
   const double* wy = bufp<double>(ws, d, R_W2);
   const double* wz = bufp<double>(ws, d, R_W3);
-  quat* oS = bufp<quat>(ws, d, C_S);
   quat* oV = bufp<quat>(ws, d, C_V);
   quat* oW = bufp<quat>(ws, d, C_WPP);
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
        e += (long long)gridDim.x * blockDim.x) {
     const double tv = t[e];
-    oS[e] = treal<quat>(s[e]);
     oV[e] = treal<quat>(v[e]);
     oW[e] = quat{{w0[e] * q4 - tv, wz[e] * q4}, {wy[e] * q4, wx[e] * q4}};
   }
+}
+
+// quaternion N x N identity
+__global__ void k_eye_q(const BlockDesc* D, char* ws, const int* info, int buf) {
+  const BlockDesc& d = D[blockIdx.y];
+  if (info[blockIdx.y]) return;
+  const int N = d.N;
+  quat* Q = bufp<quat>(ws, d, buf);
+  const long long tot = (long long)N * N;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x)
+    Q[e] = treal<quat>(e / N == e % N ? 1.0 : 0.0);
 }
 
 // quaternion N x N workspace buffer -> complex 2N x 2N at out + h_off (zero
@@ -213,6 +223,9 @@ void launch_qct_scale(hipStream_t s, const BlockDesc* D, char* ws, const int* in
 
 void launch_expand_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double c) {
   hipLaunchKernelGGL(k_expand_q, dim3(grid_for((long long)maxN * maxN), nblk), dim3(256), 0, s, D, ws, info, c);
+}
+void launch_eye_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int buf) {
+  hipLaunchKernelGGL(k_eye_q, dim3(grid_for((long long)maxN * maxN), nblk), dim3(256), 0, s, D, ws, info, buf);
 }
 void launch_write_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double* out,
                     int buf, double* eps) {

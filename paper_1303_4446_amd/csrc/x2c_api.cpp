@@ -486,21 +486,27 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
   {
     // S~ = S + X^H T X / 2c^2 ;  L = V + TX + (TX)^H + X^H (W/4c^2 - T) X
     STAGE("chain_SL");
-    if (qchain) GR(0, R_T, OPN, 0, C_X, C_TX, 1.0, 0.0);
-    else G(C_T, OPN, C_X, OPN, C_TX, 1.0, 0.0);
-    copy_buf(C_S, C_Q);
-    G(C_X, OPH, C_TX, OPN, C_Q, 1.0 / (2.0 * c * c), 1.0, 1);
+    if (qchain) {
+      GR(0, R_T, OPN, 0, C_X, C_TX, 1.0, 0.0);
+    } else {
+      G(C_T, OPN, C_X, OPN, C_TX, 1.0, 0.0);
+      copy_buf(C_S, C_Q);
+      G(C_X, OPH, C_TX, OPN, C_Q, 1.0 / (2.0 * c * c), 1.0, 1);
+    }
     G(C_WPP, OPN, C_X, OPN, C_WX, 1.0, 0.0);
     copy_buf(C_V, C_L);
     add_herm(C_TX, C_L);
     G(C_X, OPH, C_WX, OPN, C_L, 1.0, 1.0, 1);
   }
   {
-    // Q = L_S^-1 S~ L_S^-H
+    // Q = L_S^-1 S~ L_S^-H.  With X = sqrt2 c L_T^-H X~ L_S^H this is
+    // I + X~^H X~ exactly (L_S^-1 S L_S^-H = I, and the T in X^H T X / 2c^2
+    // cancels against L_T^-1 L_T^-H), which the quaternion chain uses: one
+    // Hermitian product, no rounding through L_S^-1.
     STAGE("chain_Q");
     if (qchain) {
-      GR(0, R_LSI, OPN, LOWER, C_Q, C_TMP, 1.0, 0.0);
-      GR(1, R_LSI, OPH, UPPER, C_TMP, C_Q, 1.0, 0.0, 1);
+      launch_eye_q(s, D, ws, info, nblk, maxN, C_Q);
+      G(C_QMH, OPH, C_QMH, OPN, C_Q, 1.0, 1.0, 1);
     } else {
       G(C_LSI, OPN, C_Q, OPN, C_TMP, 1.0, 0.0);
       G(C_TMP, OPN, C_LSI, OPH, C_Q, 1.0, 0.0, 1);

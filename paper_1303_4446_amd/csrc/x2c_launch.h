@@ -75,6 +75,7 @@ void launch_phase_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info
 void launch_cplx_to_quat(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int src,
                          int dst);
 void launch_expand_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double c);
+void launch_eye_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int buf);
 void launch_write_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double* out,
                     int buf, double* eps);
 void launch_gemm_qr(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int side,
