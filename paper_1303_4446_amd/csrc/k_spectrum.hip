@@ -47,13 +47,14 @@ __device__ inline int sturm_count(const double* d, const double* e2, int n, doub
 }
 
 // Eigenvalues idx0 + k (k < ne, ascending indices) of tridiag(d, e) by
-// multisection over the whole work-group: the threads form groups of
-// P = blockDim / ne (at least 1); each group splits its eigenvalue's bracket
-// into P + 1 parts per step with one Sturm count per thread.  cbuf / xbuf:
-// blockDim ints / doubles of LDS.  Every thread must call it.
+// multisection over the work-group: the threads form groups of
+// P = min(blockDim / ne, pmax) (at least 1); each group splits its
+// eigenvalue's bracket into P + 1 parts per step with one Sturm count per
+// thread.  cbuf / xbuf: blockDim ints / doubles of LDS.  Every thread must
+// call it.
 __device__ void multisect(const double* d, const double* e2, int m, int idx0, int ne, double lo, double hi,
-                          double piv, double* out, int* cbuf, double* xbuf) {
-  const int P = max(1, (int)blockDim.x / max(ne, 1));
+                          double piv, double* out, int* cbuf, double* xbuf, int pmax = 1 << 30) {
+  const int P = max(1, min((int)blockDim.x / max(ne, 1), pmax));
   const int G = blockDim.x / P;
   const int grp = threadIdx.x / P, p = threadIdx.x - grp * P;
   for (int base = 0; base < ne; base += G) {
@@ -180,28 +181,11 @@ __device__ double zolotarev(double ell, int r, double* a, double* codd, double* 
 }
 
 // ---------------------------------------------------------------- 4c branch
-// One work-group per block.  Writes eps (positive branch, ascending), the
-// branch-size check (info 4) and the projector filter parameters.
-// kramers = 1: the tridiagonal is the real form of the quaternion reduced
-// matrix (dimension n, one eigenvalue per Kramers pair); each positive-energy
-// eigenvalue is written twice.
-__global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws, int* info, double* eps, double c,
-                                                    int kramers) {
-  const int b = blockIdx.x;
-  const BlockDesc& d = D[b];
-  if (info[b]) return;
-  const int m = kramers ? d.n : d.m, n = kramers ? d.n / 2 : d.n;
-  const double* dg = bufp<double>(ws, d, V_D);
-  const double* eg = bufp<double>(ws, d, V_E);
-  double* pf = bufp<double>(ws, d, P_FILT);
-  extern __shared__ char smem[];
-  double* sd = reinterpret_cast<double*>(smem);
-  double* se = sd + m;
-  double* se2 = se + m;
-  double* lam = se2 + m;     // n + 1 values
-  __shared__ double red[64];
+// Tridiagonal in LDS (d, e, e^2), its Gershgorin interval and the pivot
+// floor of the Sturm counts; block-wide, every thread gets the values.
+__device__ void tri_setup(const double* dg, const double* eg, int m, double* sd, double* se, double* se2,
+                          double* red, double* lo_out, double* hi_out, double* piv_out) {
   __shared__ double s_lo, s_hi, s_piv;
-  __shared__ int s_cnt;
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
     sd[i] = dg[i];
     if (i < m - 1) {
@@ -223,8 +207,36 @@ __global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws
     s_piv = 2.2e-308 * fmax(1.0, e) * 16.0;
     s_lo = lo;
     s_hi = hi;
-    s_cnt = sturm_count(sd, se2, m, -c * c, s_piv);
   }
+  __syncthreads();
+  *lo_out = s_lo;
+  *hi_out = s_hi;
+  *piv_out = s_piv;
+}
+
+// One work-group per block: the branch-size check (info 4), the two
+// eigenvalues next to sigma = -c^2 (lambda_{n-1} < sigma < lambda_n) and the
+// projector filter parameters.  Zolotarev candidates r = 4, 6, ..., RMAX:
+// their 2r elliptic-function values, then their r coefficients, are spread
+// over all threads; the smallest r that reaches 1e-13 (or stops improving)
+// is kept.  kramers = 1: the tridiagonal is the real form of the quaternion
+// reduced matrix (dimension n, one eigenvalue per Kramers pair).
+__global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws, int* info, double c, int kramers) {
+  const int b = blockIdx.x;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int m = kramers ? d.n : d.m, n = kramers ? d.n / 2 : d.n;
+  double* pf = bufp<double>(ws, d, P_FILT);
+  extern __shared__ char smem[];
+  double* sd = reinterpret_cast<double*>(smem);
+  double* se = sd + m;
+  double* se2 = se + m;
+  __shared__ double red[64];
+  __shared__ double lam[2];
+  __shared__ int s_cnt;
+  double lo, hi, piv;
+  tri_setup(bufp<double>(ws, d, V_D), bufp<double>(ws, d, V_E), m, sd, se, se2, red, &lo, &hi, &piv);
+  if (threadIdx.x == 0) s_cnt = sturm_count(sd, se2, m, -c * c, piv);
   __syncthreads();
   if (s_cnt != m - n) {
     if (threadIdx.x == 0) info[b] = 4;
@@ -232,30 +244,60 @@ __global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws
   }
   __shared__ int cbuf[1024];
   __shared__ double xbuf[1024];
-  multisect(sd, se2, m, n - 1, n + 1, s_lo, s_hi, s_piv, lam, cbuf, xbuf);
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    if (kramers) {
-      eps[d.eps_off + 2 * k] = lam[k + 1];
-      eps[d.eps_off + 2 * k + 1] = lam[k + 1];
-    } else {
-      eps[d.eps_off + k] = lam[k + 1];
-    }
-  }
-  // Zolotarev candidates r = 4, 6, ..., RMAX evaluated in parallel; the
-  // smallest r that reaches 1e-13 (or stops improving) is kept
+  // 16 counts per eigenvalue and step: a few more steps, far fewer counts
+  multisect(sd, se2, m, n - 1, 2, lo, hi, piv, lam, cbuf, xbuf, 16);
   constexpr int NCAND = (RMAX - 4) / 2 + 1;
+  constexpr int NCV = 2 * NCAND * (NCAND + 3);   // sum over candidates of 2r
+  constexpr int NCO = NCAND * (NCAND + 3);       // sum over candidates of r
   __shared__ double zerr[NCAND], zM[NCAND];
   __shared__ double za[NCAND * RMAX], zc[NCAND * RMAX];
+  __shared__ double cv[NCV];
+  __shared__ AGMSeq agm;
   const double sigma = -c * c;
   const double gam = fmin(lam[1] - sigma, sigma - lam[0]);
-  const double rho = fmax(s_hi - sigma, sigma - s_lo);
+  const double rho = fmax(hi - sigma, sigma - lo);
   double ell = 0.9 * gam / rho;
   ell = fmin(fmax(ell, 1e-14), 0.5);
+  // candidate q has r = 4 + 2q; its values start at 2q(q+3), its
+  // coefficients at q(q+3)
+  if (threadIdx.x == 0) agm_seq(ell, sqrt((1.0 - ell) * (1.0 + ell)), agm);   // modulus kp, complementary ell
+  __syncthreads();
+  const double Kp = 3.14159265358979323846 / (2.0 * agm.a[agm.N]);             // K(kp)
+  for (int f = threadIdx.x; f < NCV; f += blockDim.x) {
+    int q = 0;
+    while (q + 1 < NCAND && 2 * (q + 1) * (q + 4) <= f) ++q;
+    const int r = 4 + 2 * q, i = f - 2 * q * (q + 3) + 1;    // i = 1 .. 2r
+    double sn, cn;
+    ellip_sn_cn(i * Kp / (2 * r + 1), agm, &sn, &cn);
+    cv[f] = ell * ell * sn * sn / (cn * cn);
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < NCO; g += blockDim.x) {
+    int q = 0;
+    while (q + 1 < NCAND && (q + 1) * (q + 4) <= g) ++q;
+    const int r = 4 + 2 * q, j = g - q * (q + 3);
+    const double* cq = cv + 2 * q * (q + 3);
+    const double cj = cq[2 * j];
+    double num = 1.0, den = 1.0;
+    for (int k = 0; k < r; ++k) {
+      num *= cq[2 * k + 1] - cj;
+      if (k != j) den *= cq[2 * k] - cj;
+    }
+    za[q * RMAX + j] = num / den;
+    zc[q * RMAX + j] = cj;
+  }
+  __syncthreads();
   if (threadIdx.x < NCAND) {
-    const int r = 4 + 2 * threadIdx.x;
-    double Mt;
-    zerr[threadIdx.x] = zolotarev(ell, r, za + threadIdx.x * RMAX, zc + threadIdx.x * RMAX, &Mt);
-    zM[threadIdx.x] = Mt;
+    const int q = threadIdx.x, r = 4 + 2 * q;
+    auto zhat = [&](double x) {
+      double s2 = 1.0;
+      for (int j = 0; j < r; ++j) s2 += za[q * RMAX + j] / (x * x + zc[q * RMAX + j]);
+      return x * s2;
+    };
+    const double zl = zhat(ell), z1 = zhat(1.0);
+    const double M = 2.0 / (zl + z1);
+    zM[q] = M;
+    zerr[q] = fabs(M * z1 - 1.0);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -275,6 +317,41 @@ __global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws
     for (int j = 0; j < rbest; ++j) {
       pf[4 + j] = za[best * RMAX + j];
       pf[4 + RMAX + j] = sqrt(zc[best * RMAX + j]);
+    }
+  }
+}
+
+// The n positive-energy eigenvalues (indices n .. 2n-1 of the m = 2n), eps
+// ascending, by multisection; grid = (chunks of EPW eigenvalues, blocks).
+// kramers = 1: each eigenvalue is written twice (the Kramers pair).
+constexpr int EPW = 48;
+
+__global__ void __launch_bounds__(256) k_tri_eps4c(const BlockDesc* D, char* ws, const int* info, double* eps,
+                                                   int kramers) {
+  const int b = blockIdx.y;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int m = kramers ? d.n : d.m, n = kramers ? d.n / 2 : d.n;
+  const int k0 = blockIdx.x * EPW;
+  if (k0 >= n) return;
+  const int ne = min(EPW, n - k0);
+  extern __shared__ char smem[];
+  double* sd = reinterpret_cast<double*>(smem);
+  double* se = sd + m;
+  double* se2 = se + m;
+  __shared__ double red[64];
+  __shared__ double lam[EPW];
+  __shared__ int cbuf[256];
+  __shared__ double xbuf[256];
+  double lo, hi, piv;
+  tri_setup(bufp<double>(ws, d, V_D), bufp<double>(ws, d, V_E), m, sd, se, se2, red, &lo, &hi, &piv);
+  multisect(sd, se2, m, n + k0, ne, lo, hi, piv, lam, cbuf, xbuf);
+  for (int k = threadIdx.x; k < ne; k += blockDim.x) {
+    if (kramers) {
+      eps[d.eps_off + 2 * (k0 + k)] = lam[k];
+      eps[d.eps_off + 2 * (k0 + k) + 1] = lam[k];
+    } else {
+      eps[d.eps_off + k0 + k] = lam[k];
     }
   }
 }
@@ -663,8 +740,14 @@ __global__ void k_invsqrt_finish(const BlockDesc* D, char* ws, const int* info, 
 // ----------------------------------------------------------------- launchers
 void launch_tri_eig4c(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxm, double* eps,
                       double c, int kramers) {
-  size_t shm = (size_t)(4 * maxm + 2) * sizeof(double);
-  hipLaunchKernelGGL(k_tri_eig4c, dim3(nblk), dim3(1024), shm, s, D, ws, info, eps, c, kramers);
+  const size_t shm = (size_t)(3 * maxm) * sizeof(double);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tri_eig4c), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shm);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tri_eps4c), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shm);
+  hipLaunchKernelGGL(k_tri_eig4c, dim3(nblk), dim3(1024), shm, s, D, ws, info, c, kramers);
+  const int maxn = maxm / 2;
+  hipLaunchKernelGGL(k_tri_eps4c, dim3((maxn + EPW - 1) / EPW, nblk), dim3(256), shm, s, D, ws, info, eps, kramers);
 }
 void launch_filter_factor(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int kramers,
                           int maxm_filter) {
