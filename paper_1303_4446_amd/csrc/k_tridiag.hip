@@ -513,19 +513,34 @@ __global__ void __launch_bounds__(256) k_larft(const BlockDesc* D, char* ws, con
   const T* taus = bufp<T>(ws, d, bufTau);
   T* Tf = bufp<T>(ws, d, bufTf) + (long long)blockIdx.x * ORB * ORB;
   constexpr int LR = Tiles<T>::LR;
+  static_assert(LR >= ORB, "the T factor reuses the row-chunk buffer");
   __shared__ T Vs[LR][ORB + 1];
   __shared__ T G[ORB][ORB + 1];
-  __shared__ T Ts[ORB][ORB + 1];
-  // Gram matrix of the panel (upper part): thread t owns pairs p = t + 256 q
+  T (*Ts)[ORB + 1] = Vs;            // after the Gram matrix is complete
+  // Gram matrix of the panel (upper part): thread t owns pairs p = t + 256 q.
+  // Row chunks of LR: the next chunk is loaded into registers while the
+  // current one is reduced.
+  constexpr int PER = LR * ORB / 256;
   T acc[4];
   for (int q = 0; q < 4; ++q) acc[q] = tzero<T>();
+  T nv[PER];
+  auto fetch = [&](int r0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int l = threadIdx.x + 256 * q, rr = l / ORB, a = l % ORB, r = r0 + rr;
+      nv[q] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<T>();
+    }
+  };
+  fetch(k0 + 1);
   for (int r0 = k0 + 1; r0 < nr; r0 += LR) {
-    for (int l = threadIdx.x; l < LR * ORB; l += 256) {
-      int rr = l / ORB, a = l % ORB;
-      int r = r0 + rr;
-      Vs[rr][a] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<T>();
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int l = threadIdx.x + 256 * q;
+      Vs[l / ORB][l % ORB] = nv[q];
     }
     __syncthreads();
+    if (r0 + LR < nr) fetch(r0 + LR);
     for (int q = 0; q < 4; ++q) {
       int p = threadIdx.x + 256 * q;
       int a = p / ORB, c = p % ORB;
@@ -535,8 +550,8 @@ __global__ void __launch_bounds__(256) k_larft(const BlockDesc* D, char* ws, con
         acc[q] = s;
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int q = 0; q < 4; ++q) {
     int p = threadIdx.x + 256 * q;
     G[p / ORB][p % ORB] = acc[q];

@@ -19,7 +19,7 @@ template <>
 struct Tiles<quat> {
   static constexpr int HT = 16;
   static constexpr int TT = 16;
-  static constexpr int LR = 16;
+  static constexpr int LR = 32;
   static constexpr int CW = 32;
   static constexpr int VR = 16;
 };
