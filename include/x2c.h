@@ -161,6 +161,36 @@ int x2c_build_batched_xr(const x2c_options* opts, int nblk, const int* N, const 
                          void* R, int* info, void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * Picture-change transformation of one-electron property operators with
+ * the blocks' decoupling (Sec. II: U^L and U^S are needed for the picture
+ * change of property integrals; U^L_bb = R_b, U^S_bb = X_b R_b, Eqs.
+ * ulnonortho, usnonortho).  For a property whose matrix in the basis of
+ * the modified Dirac equation (Eq. moddiraceq: large components chi, small
+ * components sigma.p chi / 2c) is [[P_LL, P_LS], [P_SL, P_SS]], Eq. utrans
+ * with that matrix in place of D gives
+ *   P~_b = R^H [ P_LL + P_LS X + X^H P_SL + X^H P_SS X ] R.
+ * (A multiplicative operator O has P_LL = O, P_LS = P_SL = 0 and
+ * P_SS = W^O / 4c^2 with W^O built from <sigma.p chi|O|sigma.p chi> as in
+ * Eq. defw; the Hamiltonian itself is the case D.)
+ *   N, p_off host, nblk scalar sizes and double offsets of block b's
+ *            n_b x n_b matrices (n_b = N_b spin-free, 2 N_b two-component,
+ *            float64 or complex128 row-major), e.g. the h_off of
+ *            x2c_build_batched_xr.  The same offsets address PLL, PLS, PSL,
+ *            PSS, X, R and out.
+ *   PLL, PLS, PSL, PSS  device property blocks; PLS and PSL may be NULL
+ *            (zero blocks).
+ *   X, R     device, the blocks' decoupling matrices.
+ *   out      device output, same layout.
+ * The workspace is that of x2c_build_batched for the same blocks (size from
+ * x2c_workspace_bytes).  Stream-ordered.  Returns X2C_OK once enqueued,
+ * X2C_EINVAL (NULL pointer, N out of range, workspace too small) or
+ * X2C_EHIP.  opts->prec and opts->reduction are ignored (FP64 products).
+ */
+int x2c_picture_change(const x2c_options* opts, int nblk, const int* N, const int64_t* p_off, const double* PLL,
+                       const double* PLS, const double* PSL, const double* PSS, const void* X, const void* R,
+                       void* out, void* workspace, size_t ws_bytes, void* stream);
+
+/*
  * Workspace size in bytes for x2c_dlu_assemble with `natom` atoms of scalar
  * sizes N[0..natom) (host).  0 for invalid arguments.
  */

@@ -184,6 +184,39 @@ def x2c_direct(S, T, V, W, c: float, twocomp: bool, return_parts: bool = False):
 
 
 # ----------------------------------------------------------------------------
+# picture change of property operators (Sec. II: U^L and U^S are kept for the
+# picture-change transformation of property integrals; Eq. utrans)
+# ----------------------------------------------------------------------------
+
+def property_blocks(O, WO, c: float, twocomp: bool):
+    """4c matrix of a multiplicative one-electron operator O in the basis of
+    the modified Dirac equation (Eq. moddiraceq: large components chi, small
+    components sigma.p chi / 2c): P_LL = O (spin-diagonal, Eq. defstv),
+    P_LS = P_SL = 0, P_SS = W^O / 4c^2 with W^O = <sigma.p chi|O|sigma.p chi>
+    in the form of Eq. defw.  WO: (4, N, N) for two-component, W^O0 (N x N)
+    or (4, N, N) for spin-free."""
+    WO = np.asarray(WO)
+    if twocomp:
+        PLL = spin_blockdiag(O)
+        PSS = assemble_w(WO[0], WO[1], WO[2], WO[3]) / (4.0 * c * c)
+    else:
+        PLL = np.array(O, dtype=float)
+        PSS = np.array(WO[0] if WO.ndim == 3 else WO, dtype=float) / (4.0 * c * c)
+    zero = np.zeros_like(PLL)
+    return PLL, zero, zero.copy(), PSS
+
+
+def picture_change(PLL, PLS, PSL, PSS, X, R):
+    """Eq. utrans with a property's 4c matrix P = [[P_LL, P_LS], [P_SL, P_SS]]
+    in place of D, and the decoupling U^L = R, U^S = X R (Eqs. ulnonortho,
+    usnonortho): [U^L^H U^S^H] P [U^L; U^S]."""
+    UL = R
+    US = X @ R
+    return (UL.conj().T @ PLL @ UL + UL.conj().T @ PLS @ US
+            + US.conj().T @ PSL @ UL + US.conj().T @ PSS @ US)
+
+
+# ----------------------------------------------------------------------------
 # route 2: orthonormal kinetic eigenbasis (Sec. II.A)
 # ----------------------------------------------------------------------------
 

@@ -4,5 +4,5 @@ from ._lib import (EBLOCK, EHIP, EINVAL, EXPORTED, FP64, OK, RED_COMPLEX, RED_QU
                    SPLIT_INT8,
                    SPINFREE, TWOCOMP,
                    Batch, X2CError, batch_to_device, build, build_batched, build_batched_xr, dlu_assemble,
-                   dlu_workspace_bytes, graph_enable, load, max_n, stream_split, strerror,
+                   dlu_workspace_bytes, graph_enable, load, max_n, picture_change, stream_split, strerror,
                    trace_enable, trace_read, trace_reset, unpack_h, workspace_bytes)

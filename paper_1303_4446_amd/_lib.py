@@ -25,7 +25,7 @@ INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subsp
 
 EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_build_batched_xr",
             "x2c_dlu_workspace_bytes", "x2c_dlu_assemble", "x2c_strerror", "x2c_release", "x2c_graph_enable",
-            "x2c_stream_split", "x2c_trace_enable", "x2c_trace_read", "x2c_trace_reset")
+            "x2c_stream_split", "x2c_picture_change", "x2c_trace_enable", "x2c_trace_read", "x2c_trace_reset")
 
 
 class X2CError(RuntimeError):
@@ -72,6 +72,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.x2c_dlu_assemble.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), vp, vp, vp, i64p, vp, vp, vp,
                                      vp, ctypes.c_size_t, vp]
     lib.x2c_dlu_assemble.restype = i32
+    lib.x2c_picture_change.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp, vp, vp, vp,
+                                       vp, ctypes.c_size_t, vp]
+    lib.x2c_picture_change.restype = i32
     lib.x2c_strerror.argtypes = [i32]
     lib.x2c_strerror.restype = ctypes.c_char_p
     lib.x2c_release.argtypes = []
@@ -234,6 +237,33 @@ def build_batched_xr(batch: Batch, c: float, prec: int = FP64, slices: int = 0, 
     if rc != OK:
         raise X2CError(rc, strerror(rc))
     return (h, eps, info, X, R), workspace
+
+
+def picture_change(Ns, twocomp: bool, p_off, PLL, PSS, X, R, PLS=None, PSL=None, c: float = 137.0,
+                   workspace=None, stream=None, out=None):
+    """Enqueue x2c_picture_change: per block P~ = R^H [P_LL + P_LS X +
+    X^H P_SL + X^H P_SS X] R.  All matrices are flat device float64 tensors
+    in the layout of h (block b at double offset p_off[b]); PLS / PSL may be
+    None.  Returns (out, workspace)."""
+    torch = _torch()
+    lib = load()
+    dev = PLL.device
+    Ns = np.ascontiguousarray(Ns, dtype=np.int32)
+    po = np.ascontiguousarray(p_off, dtype=np.int64)
+    if out is None:
+        out = torch.empty_like(PLL)
+    wsb = workspace_bytes(Ns, twocomp, c)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    opt = options(twocomp, c)
+    f64 = lambda t: None if t is None else _dev(t, torch, torch.float64)
+    rc = lib.x2c_picture_change(
+        ctypes.byref(opt), len(Ns), Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+        po.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), f64(PLL), f64(PLS), f64(PSL), f64(PSS), f64(X), f64(R),
+        f64(out), ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()), _stream_ptr(torch, stream))
+    if rc != OK:
+        raise X2CError(rc, strerror(rc))
+    return out, workspace
 
 
 def dlu_workspace_bytes(Ns, twocomp: bool, c: float = 137.0) -> int:

@@ -36,6 +36,52 @@ void launch_write_buf(hipStream_t s, const BlockDesc* D, char* ws, const int* in
 template void launch_write_buf<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, double*, int);
 template void launch_write_buf<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, double*, int);
 
+// n x n T-typed matrix of every block at in + h_off -> workspace buffer
+// (zero when in is null)
+template <class T>
+__global__ void k_read_buf(const BlockDesc* D, char* ws, const int* info, const double* in, int buf) {
+  const BlockDesc& d = D[blockIdx.y];
+  if (info[blockIdx.y]) return;
+  const long long nn = (long long)d.n * d.n;
+  const T* src = in ? reinterpret_cast<const T*>(in + d.h_off) : nullptr;
+  T* o = bufp<T>(ws, d, buf);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long long)gridDim.x * blockDim.x)
+    o[e] = src ? src[e] : tzero<T>();
+}
+
+// dst += src (n x n workspace buffers)
+template <class T>
+__global__ void k_add_buf(const BlockDesc* D, char* ws, const int* info, int src, int dst) {
+  const BlockDesc& d = D[blockIdx.y];
+  if (info[blockIdx.y]) return;
+  const long long nn = (long long)d.n * d.n;
+  const T* a = bufp<T>(ws, d, src);
+  T* o = bufp<T>(ws, d, dst);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long long)gridDim.x * blockDim.x)
+    o[e] = o[e] + a[e];
+}
+
+template <class T>
+void launch_read_buf(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn,
+                     const double* in, int buf) {
+  long long g = ((long long)maxn * maxn + 255) / 256;
+  if (g > 256) g = 256;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_read_buf<T>, dim3((int)g, nblk), dim3(256), 0, s, D, ws, info, in, buf);
+}
+template <class T>
+void launch_add_buf(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, int src,
+                    int dst) {
+  long long g = ((long long)maxn * maxn + 255) / 256;
+  if (g > 256) g = 256;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_add_buf<T>, dim3((int)g, nblk), dim3(256), 0, s, D, ws, info, src, dst);
+}
+template void launch_read_buf<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, const double*, int);
+template void launch_read_buf<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, const double*, int);
+template void launch_add_buf<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int);
+template void launch_add_buf<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int);
+
 // V_AB -> L, T_AB -> Tb, W_AB / 4c^2 - T_AB -> Wb for every pair.
 template <class T>
 __global__ void k_dlu_gather(const DluPair* P, char* ws, const double* Tm, const double* Vm, const double* Wm,

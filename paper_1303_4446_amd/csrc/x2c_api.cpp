@@ -680,6 +680,40 @@ int split_ways() {
   return g_split;
 }
 
+// Picture change of a property, per block:
+//   P~ = R^H [P_LL + P_LS X + X^H P_SL + X^H P_SS X] R   (Eq. utrans)
+// with general (non-Hermitian) products, so that any operator is accepted.
+template <class T>
+int run_picture_change(const Layout& L, int nblk, const double* PLL, const double* PLS, const double* PSL,
+                       const double* PSS, const double* X, const double* R, double* out, char* ws, hipStream_t s) {
+  const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off);
+  int* info = reinterpret_cast<int*>(ws + L.info_off);
+  const int maxn = L.maxn;
+  const T one = tcast<T>(1.0), zero = tcast<T>(0.0);
+  launch_init_info(s, info, nblk);
+  launch_read_buf<T>(s, D, ws, info, nblk, maxn, X, C_X);
+  launch_read_buf<T>(s, D, ws, info, nblk, maxn, R, C_R);
+  launch_read_buf<T>(s, D, ws, info, nblk, maxn, PLL, C_L);
+  launch_read_buf<T>(s, D, ws, info, nblk, maxn, PSS, C_WPP);
+  // C_WX = P_SS X + P_SL
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_WPP, 0, C_X, 0, C_WX, one, zero, 0);
+  if (PSL) {
+    launch_read_buf<T>(s, D, ws, info, nblk, maxn, PSL, C_TMP);
+    launch_add_buf<T>(s, D, ws, info, nblk, maxn, C_TMP, C_WX);
+  }
+  // C_L = P_LL + P_LS X + X^H C_WX
+  if (PLS) {
+    launch_read_buf<T>(s, D, ws, info, nblk, maxn, PLS, C_TMP);
+    launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_TMP, 0, C_X, 0, C_L, one, one, 0);
+  }
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_X, 1, C_WX, 0, C_L, one, one, 0);
+  // R^H (C_L R)
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_L, 0, C_R, 0, C_LR, one, zero, 0);
+  launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, C_R, 1, C_LR, 0, C_H, one, zero, 0);
+  launch_write_buf<T>(s, D, ws, info, nblk, maxn, out, C_H);
+  return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
+}
+
 // ---------------------------------------------------------------- graphs
 // The whole launch sequence of a call (about 2N kernels per block size N,
 // most of them short column steps of the reductions) is captured once per
@@ -819,6 +853,29 @@ int x2c_build_batched_xr(const x2c_options* opts, int nblk, const int* N, const 
   if (!in_off || !h_off || !eps_off || !info) return X2C_EINVAL;
   return enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, X, R, info, workspace, ws_bytes,
                  static_cast<hipStream_t>(stream), nullptr);
+}
+
+int x2c_picture_change(const x2c_options* opts, int nblk, const int* N, const int64_t* p_off, const double* PLL,
+                       const double* PLS, const double* PSL, const double* PSS, const void* X, const void* R,
+                       void* out, void* workspace, size_t ws_bytes, void* stream) {
+  if (nblk == 0 && valid_opts(opts)) return X2C_OK;
+  if (!valid_opts(opts) || nblk < 0 || !N || !p_off || !PLL || !PSS || !X || !R || !out || !workspace)
+    return X2C_EINVAL;
+  std::shared_ptr<Layout> L = get_plan(opts, nblk, N, nullptr, p_off, nullptr);
+  if (!L) return X2C_EINVAL;
+  if (ws_bytes < L->total) return X2C_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  (void)hipGetLastError();
+  const void* src = L->pinned ? static_cast<const void*>(L->pinned) : static_cast<const void*>(L->desc.data());
+  if (hipMemcpyAsync(ws + L->desc_off, src, L->desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return X2C_EHIP;
+  const double* Xd = static_cast<const double*>(X);
+  const double* Rd = static_cast<const double*>(R);
+  double* o = static_cast<double*>(out);
+  if (opts->mode == X2C_TWOCOMP) return run_picture_change<cplx>(*L, nblk, PLL, PLS, PSL, PSS, Xd, Rd, o, ws, s);
+  return run_picture_change<double>(*L, nblk, PLL, PLS, PSL, PSS, Xd, Rd, o, ws, s);
 }
 
 size_t x2c_dlu_workspace_bytes(const x2c_options* opts, int natom, const int* N) {

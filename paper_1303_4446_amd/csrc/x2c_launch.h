@@ -91,6 +91,12 @@ template <class T>
 void launch_write_buf(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, double* out,
                       int buf);
 template <class T>
+void launch_read_buf(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn,
+                     const double* in, int buf);
+template <class T>
+void launch_add_buf(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxn, int src,
+                    int dst);
+template <class T>
 void launch_dlu(hipStream_t s, const DluPair* P, int npairs, int maxnA, int maxnB, char* ws, const double* Tm,
                 const double* Vm, const double* Wm, int Ntot, double c, const double* X, const double* R, double* H);
 
