@@ -92,6 +92,49 @@ def recorded_traffic(kernel_src: str, summary: str):
         return None
 
 
+def time_picture_change(px, torch, batch, twocomp, c, prec, red, stream, calls=3):
+    """Throughput of x2c_picture_change over the whole batch for the nuclear
+    attraction as the property (P_LL = V, P_SS = W / 4c^2 in the form of
+    Eq. defw, P_LS = P_SL = 0), with the batch's own X and R.  The property
+    matrices are assembled on the device from the batch's V and W."""
+    (_, _, info, X, R), ws = px.build_batched_xr(batch, c, prec=prec, stream=stream, reduction=red)
+    h_off, _, hsz, _ = batch.out_layout()
+    PLL = torch.zeros(hsz, dtype=torch.float64, device="cuda")
+    PSS = torch.zeros(hsz, dtype=torch.float64, device="cuda")
+    q4 = 1.0 / (4.0 * c * c)
+    for b, N in enumerate(batch.Ns):
+        N = int(N)
+        o, io = int(h_off[b]), int(batch.in_off[b])
+        V = batch.V[io:io + N * N].view(N, N)
+        if twocomp:
+            W = batch.W[4 * io:4 * io + 4 * N * N].view(4, N, N)
+            n = 2 * N
+            L = PLL[o:o + 2 * n * n].view(n, n, 2)
+            L[:N, :N, 0] = V
+            L[N:, N:, 0] = V
+            P = PSS[o:o + 2 * n * n].view(n, n, 2)
+            P[:N, :N, 0], P[:N, :N, 1] = q4 * W[0], q4 * W[3]
+            P[:N, N:, 0], P[:N, N:, 1] = q4 * W[2], q4 * W[1]
+            P[N:, :N, 0], P[N:, :N, 1] = -q4 * W[2], q4 * W[1]
+            P[N:, N:, 0], P[N:, N:, 1] = q4 * W[0], -q4 * W[3]
+        else:
+            PLL[o:o + N * N] = batch.V[io:io + N * N]
+            PSS[o:o + N * N] = q4 * batch.W[io:io + N * N]
+    out, ws = px.picture_change(batch.Ns, twocomp, h_off, PLL, PSS, X, R, c=c, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(calls):
+        px.picture_change(batch.Ns, twocomp, h_off, PLL, PSS, X, R, c=c, workspace=ws, stream=stream, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    if not bool(torch.isfinite(out).all()) or bool((info != 0).any()):
+        return None
+    return {"operator": "nuclear attraction (P_LL = V, P_SS = W/4c^2)", "ms_per_call": ms,
+            "blocks_per_s": len(batch.Ns) / (ms / 1e3)}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +149,7 @@ def parse():
     ap.add_argument("--check-blocks", type=int, default=3, help="blocks checked against the oracle")
     ap.add_argument("--cpu-blocks", type=int, default=12, help="blocks in the CPU oracle sample (0 = skip)")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--no-pct", action="store_true", help="skip the picture-change timing")
     ap.add_argument("--streams", type=int, choices=[1, 2, 3, 4], default=4,
                     help="run the batch as this many parts on as many streams")
     ap.add_argument("--no-graph", action="store_true", help="eager launches instead of graph replay")
@@ -273,6 +317,7 @@ def main():
         if fl is not None and st in stage_ms:
             extra[st + "_fp64_tflops"] = fl * nblk / (stage_ms[st] / 1e3) / 1e12
 
+    pct = None if args.no_pct else time_picture_change(px, torch, batch, twocomp, c, prec, red, stream)
     cpu = cpu_baseline(blocks, twocomp, c, args.cpu_blocks) if args.cpu_blocks > 0 else None
 
     line = {
@@ -285,6 +330,7 @@ def main():
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: round(v, 4) for k, v in sorted(stage_ms.items(), key=lambda kv: -kv[1])},
         "stage_rates": extra,
+        "picture_change": pct,
     }
     print(json.dumps(line), flush=True)
 
