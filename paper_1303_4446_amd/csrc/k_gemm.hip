@@ -105,14 +105,16 @@ k_gemm(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, int op
 // of the LDS traffic per multiply-add of the register-tiled kernel above.
 // herm = 1: the result is Hermitian (as is beta C); only tiles on or below
 // the diagonal are computed, and each lower entry is also written, conjugated,
-// to its mirror position.
+// to its mirror position.  tri: op(A) lower (1) / upper (2), op(B) lower (4)
+// / upper (8) triangular with zeros stored outside the triangle; the k range
+// of each tile is cut to where both can be non-zero.
 typedef __attribute__((ext_vector_type(4))) double d4;
 constexpr int GM_T = 64, GM_K = 16, GM_LD = GM_K + 1;
 
 template <class T>
 __global__ void __launch_bounds__(256)
 k_gemm_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, int opA, int bufB, int opB, int bufC,
-            T alpha, T beta, int herm) {
+            T alpha, T beta, int herm, int tri) {
   constexpr bool CP = sizeof(T) == sizeof(cplx);
   const int b = blockIdx.z;
   const BlockDesc& d = D[b];
@@ -171,11 +173,17 @@ k_gemm_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, i
       if constexpr (CP) Bi[kk][c] = im(nb[q]);
     }
   };
-  fetch(0);
+  int kbeg = 0, kend = n;
+  if (tri & 1) kend = min(kend, m0 + GM_T);
+  if (tri & 2) kbeg = max(kbeg, m0);
+  if (tri & 8) kend = min(kend, n0 + GM_T);
+  if (tri & 4) kbeg = max(kbeg, n0);
+  kbeg = (kbeg / GM_K) * GM_K;
+  fetch(kbeg);
   stash();
   __syncthreads();
-  for (int k0 = 0; k0 < n; k0 += GM_K) {
-    const bool more = k0 + GM_K < n;
+  for (int k0 = kbeg; k0 < kend; k0 += GM_K) {
+    const bool more = k0 + GM_K < kend;
     if (more) fetch(k0 + GM_K);
 #pragma unroll
     for (int ks = 0; ks < GM_K; ks += 4) {
@@ -532,15 +540,15 @@ void launch_gemm_qr(hipStream_t s, const BlockDesc* D, char* ws, const int* info
 
 template <class T>
 void launch_gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
-                 int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int herm) {
+                 int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int herm, int tri) {
   int t = (maxdim + GM_T - 1) / GM_T;
   hipLaunchKernelGGL(k_gemm_mfma<T>, dim3(t, t, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA, opA, bufB, opB,
-                     bufC, alpha, beta, herm);
+                     bufC, alpha, beta, herm, tri);
 }
 
 template void launch_gemm<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int, int,
-                                  int, double, double, int);
+                                  int, double, double, int, int);
 template void launch_gemm<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int, int,
-                                int, cplx, cplx, int);
+                                int, cplx, cplx, int, int);
 
 }  // namespace x2c

@@ -413,13 +413,15 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
   {
     // scalar-level reduction: L_S^-1 V L_S^-T, L_S^-1 L_T, L_T^-1 W^q L_T^-T
     STAGE("reduce");
-    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPN, R_V, OPN, R_TMP, 1.0, 0.0);
-    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LSI, OPH, R_ALL, 1.0, 0.0);
-    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPN, R_LT, OPN, R_B, 1.0, 0.0);
+    // (triangular factors: k ranges cut to their triangles; A lower = 1,
+    // B lower = 4, B upper = 8)
+    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPN, R_V, OPN, R_TMP, 1.0, 0.0, 0, 1);
+    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LSI, OPH, R_ALL, 1.0, 0.0, 0, 8);
+    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPN, R_LT, OPN, R_B, 1.0, 0.0, 0, 1 | 4);
     const int nq = tc ? 4 : 1;
     for (int q = 0; q < nq; ++q) {
-      launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LTI, OPN, R_W0 + q, OPN, R_TMP, 1.0, 0.0);
-      launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LTI, OPH, R_WR0 + q, 1.0, 0.0);
+      launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LTI, OPN, R_W0 + q, OPN, R_TMP, 1.0, 0.0, 0, 1);
+      launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LTI, OPH, R_WR0 + q, 1.0, 0.0, 0, 8);
     }
     if (!kramers) launch_assemble_A<T>(s, D, ws, info, nblk, maxm, c);
     else launch_assemble_Aq(s, D, ws, info, nblk, maxn, c);

@@ -37,7 +37,7 @@ void launch_write_h(hipStream_t s, const BlockDesc* D, char* ws, const int* info
 // triangle is computed and mirrored
 template <class T>
 void launch_gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
-                 int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int herm = 0);
+                 int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int herm = 0, int tri = 0);
 
 template <class T>
 void launch_gemm_split(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
