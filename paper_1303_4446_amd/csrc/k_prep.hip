@@ -160,10 +160,15 @@ __global__ void __launch_bounds__(256) k_trtri(const BlockDesc* D, char* ws, con
   extern __shared__ double sm[];
   double* xs = sm;                                  // rows j0.. x (PB + 1)
   double* U = sm + (size_t)(N - j0) * (PB + 1);     // PB x (PB + 1)
+  double* Ld = U + (size_t)PB * (PB + 1);           // diagonal block of L, PB x (PB + 1)
   const int t = threadIdx.x, c = t & (PB - 1), g = t >> 5;
   const int nc = min(PB, N - j0);
   for (int i0 = j0; i0 < N; i0 += PB) {
     const int ib = min(PB, N - i0);
+    for (int e = t; e < PB * PB; e += 256) {
+      const int ii = e / PB, kk = e % PB;
+      Ld[ii * (PB + 1) + kk] = (ii < ib && kk <= ii) ? L[(long long)(i0 + ii) * N + i0 + kk] : 0.0;
+    }
 #pragma unroll
     for (int q = 0; q < PB / 8; ++q) {
       const int ii = g + 8 * q;
@@ -175,12 +180,13 @@ __global__ void __launch_bounds__(256) k_trtri(const BlockDesc* D, char* ws, con
       }
     }
     __syncthreads();
+    // in-block forward substitution, one thread per column, L from LDS
     if (t < PB) {
       for (int ii = 0; ii < ib; ++ii) {
-        const double* Li = L + (long long)(i0 + ii) * N;
         double acc = ((i0 + ii) == (j0 + c) ? 1.0 : 0.0) - U[ii * (PB + 1) + c];
-        for (int kk = 0; kk < ii; ++kk) acc = fma(-Li[i0 + kk], xs[(i0 + kk - j0) * (PB + 1) + c], acc);
-        xs[(i0 + ii - j0) * (PB + 1) + c] = acc / Li[i0 + ii];
+        for (int kk = 0; kk < ii; ++kk)
+          acc = fma(-Ld[ii * (PB + 1) + kk], xs[(i0 + kk - j0) * (PB + 1) + c], acc);
+        xs[(i0 + ii - j0) * (PB + 1) + c] = acc / Ld[ii * (PB + 1) + ii];
       }
     }
     __syncthreads();
@@ -390,7 +396,7 @@ void launch_potrf(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nb
   hipLaunchKernelGGL(k_potrf, dim3(2, nblk), dim3(256), shm, s, D, ws, info);
 }
 void launch_trtri(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN) {
-  const size_t shm = ((size_t)maxN * (PB + 1) + (size_t)PB * (PB + 1)) * sizeof(double);
+  const size_t shm = ((size_t)maxN * (PB + 1) + 2 * (size_t)PB * (PB + 1)) * sizeof(double);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trtri), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL(k_trtri, dim3((maxN + PB - 1) / PB, 2, nblk), dim3(256), shm, s, D, ws, info);
 }
