@@ -10,7 +10,7 @@ namespace x2c {
 // ---------------------------------------------------------------- blocked
 // Blocked LU (panels of LB columns, partial pivoting with whole-row
 // interchanges) and blocked right-side triangular solves for X~ = Y_S Y_L^-1.
-constexpr int LB = 32;
+constexpr int LB = 16;
 
 // Factor panel J (columns LB*J .. +jb, rows LB*J .. n-1) of Y_L in place.
 template <class T>
@@ -207,12 +207,13 @@ __global__ void __launch_bounds__(256) k_rsolve_blk(const BlockDesc* D, char* ws
   T* Z = bufp<T>(ws, d, bufY) + (long long)n * n;      // Y_S block
   __shared__ T Zs[64][LB + 1];
   __shared__ T Ms[LB][LB + 1];
+  constexpr int CJ = LB / 8;                               // columns per thread
   const int tx = threadIdx.x & 7, ty = threadIdx.x >> 3;   // 8 x 32: cols tx + 8j, rows ty + 32 i
-  T acc[2][4];
+  T acc[2][CJ];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = tzero<T>();
+    for (int j = 0; j < CJ; ++j) acc[i][j] = tzero<T>();
   const int nJ = (n + LB - 1) / LB;
   const int kbeg = UPPER ? 0 : J + 1, kend = UPPER ? J : nJ;
   for (int kc = kbeg; kc < kend; ++kc) {
@@ -231,7 +232,7 @@ __global__ void __launch_bounds__(256) k_rsolve_blk(const BlockDesc* D, char* ws
     for (int k = 0; k < LB; ++k) {
       T a0 = Zs[ty][k], a1 = Zs[ty + 32][k];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < CJ; ++j) {
         T m = Ms[k][tx + 8 * j];
         acc[0][j] = mad(a0, m, acc[0][j]);
         acc[1][j] = mad(a1, m, acc[1][j]);
@@ -243,7 +244,7 @@ __global__ void __launch_bounds__(256) k_rsolve_blk(const BlockDesc* D, char* ws
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < CJ; ++j) {
       int r = r0 + ty + 32 * i, c = tx + 8 * j;
       Zs[ty + 32 * i][c] = (r < n && c < jb) ? Z[(long long)r * n + j0 + c] - acc[i][j] : tzero<T>();
     }
