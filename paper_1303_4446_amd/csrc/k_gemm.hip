@@ -244,7 +244,7 @@ k_gemm_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, i
 // the real multiply-adds of the complex 2N x 2N product.  Operands are staged
 // in LDS as four component planes; each wave runs 2 x 2 blocks of 16 x 16
 // quaternions, 16 MFMAs per block and k step of 4.  alpha, beta are real.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, int opA, int bufB, int opB,
               int bufC, double alpha, double beta, int herm) {
   const int b = blockIdx.z;
@@ -305,21 +305,21 @@ k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
       Bs[3][kk][cc] = nb[q].b.y;
     }
   };
-  fetch(0);
-  stash();
-  __syncthreads();
   for (int k0 = 0; k0 < n; k0 += GM_K) {
-    const bool more = k0 + GM_K < n;
-    if (more) fetch(k0 + GM_K);
+    // two waves per SIMD instead of a register prefetch: the other
+    // work-group's matrix-core work covers this one's loads
+    __syncthreads();
+    fetch(k0);
+    stash();
+    __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < GM_K; ks += 4) {
-      double a[2][4], an[2][4], bq[2][4];
+      double a[2][4], bq[2][4];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           a[x][c] = As[c][wr + 16 * x + l16][ks + l4];
-          an[x][c] = -a[x][c];
           bq[x][c] = Bs[c][ks + l4][wc + 16 * x + l16];
         }
 #pragma unroll
@@ -331,12 +331,7 @@ k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
 #pragma unroll
             for (int c = 0; c < 4; ++c)
               acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                  qmul_sign(c, dd) > 0 ? a[x][c ^ dd] : an[x][c ^ dd], bq[y][dd], acc[x][y][c], 0, 0, 0);
-    }
-    __syncthreads();
-    if (more) {
-      stash();
-      __syncthreads();
+                  qmul_sign(c, dd) > 0 ? a[x][c ^ dd] : -a[x][c ^ dd], bq[y][dd], acc[x][y][c], 0, 0, 0);
     }
   }
 #pragma unroll
