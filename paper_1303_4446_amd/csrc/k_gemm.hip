@@ -369,7 +369,7 @@ void launch_gemm_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info,
 // as zero, whatever is stored), and the k range of each tile is cut to where
 // op(R) can be non-zero.
 template <int side>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_gemm_qr_mfma(const BlockDesc* D, char* ws, const int* info, int bufR, int opR, int tri, int bufQ, int bufC,
                double alpha, double beta, int herm) {
   const int b = blockIdx.z;
@@ -456,14 +456,12 @@ k_gemm_qr_mfma(const BlockDesc* D, char* ws, const int* info, int bufR, int opR,
     }
   };
   kbeg = (kbeg / GM_K) * GM_K;
-  if (kbeg < kend) {
-    fetch(kbeg);
-    stash();
-  }
-  __syncthreads();
   for (int k0 = kbeg; k0 < kend; k0 += GM_K) {
-    const bool more = k0 + GM_K < kend;
-    if (more) fetch(k0 + GM_K);
+    // two waves per SIMD instead of a register prefetch
+    __syncthreads();
+    fetch(k0);
+    stash();
+    __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < GM_K; ks += 4) {
       if constexpr (side == 0) {
@@ -497,11 +495,6 @@ k_gemm_qr_mfma(const BlockDesc* D, char* ws, const int* info, int bufR, int opR,
             for (int c = 0; c < 4; ++c)
               acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[x][c], bb[y], acc[x][y][c], 0, 0, 0);
       }
-    }
-    __syncthreads();
-    if (more) {
-      stash();
-      __syncthreads();
     }
   }
 #pragma unroll

@@ -805,7 +805,7 @@ void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, 
 // product) per 16 x 16 block and k step of 4.  grid = (lower tiles, nblk).
 constexpr int HQ_T = 64, HQ_K = 16;
 
-__global__ void __launch_bounds__(256) k_tri_her2k_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel,
+__global__ void __launch_bounds__(256, 2) k_tri_her2k_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel,
                                                           int bufA, int bufW, int k0) {
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
@@ -869,21 +869,20 @@ __global__ void __launch_bounds__(256) k_tri_her2k_q_mfma(const BlockDesc* D, ch
       Bs[3][kk][r] = nb[q].b.y;
     }
   };
-  fetch(0);
-  stash();
-  __syncthreads();
   for (int kc = 0; kc < 2 * HB; kc += HQ_K) {
-    const bool more = kc + HQ_K < 2 * HB;
-    if (more) fetch(kc + HQ_K);
+    // two waves per SIMD instead of a register prefetch
+    __syncthreads();
+    fetch(kc);
+    stash();
+    __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < HQ_K; ks += 4) {
-      double a[2][4], an[2][4], bq[2][4];
+      double a[2][4], bq[2][4];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           a[x][c] = As[c][wr + 16 * x + l16][ks + l4];
-          an[x][c] = -a[x][c];
           bq[x][c] = Bs[c][ks + l4][wc + 16 * x + l16];
         }
 #pragma unroll
@@ -895,12 +894,7 @@ __global__ void __launch_bounds__(256) k_tri_her2k_q_mfma(const BlockDesc* D, ch
 #pragma unroll
             for (int c = 0; c < 4; ++c)
               acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                  qmul_sign(c, dd) > 0 ? a[x][c ^ dd] : an[x][c ^ dd], bq[y][dd], acc[x][y][c], 0, 0, 0);
-    }
-    __syncthreads();
-    if (more) {
-      stash();
-      __syncthreads();
+                  qmul_sign(c, dd) > 0 ? a[x][c ^ dd] : -a[x][c ^ dd], bq[y][dd], acc[x][y][c], 0, 0, 0);
     }
   }
 #pragma unroll
