@@ -5,6 +5,8 @@
 #include "x2c_launch.h"
 #include "x2c_tridiag.h"
 
+#include <hip/hip_ext.h>
+
 namespace x2c {
 
 // Lower-triangle matvec y = A[k+1:, k+1:] v_k, persistent over the batch.
@@ -356,23 +358,31 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
 
 template <class T>
 void launch_matvec(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int dsel, int bufA,
-                   int bufV, int bufHS, int bufW, int k0, int k, int nsmax, int ncu) {
+                   int bufV, int bufHS, int bufW, int k0, int k, int nsmax, int ncu, hipEvent_t ev0, hipEvent_t ev1) {
   const long long items = (long long)nsmax * nblk;
   if constexpr (is_quat<T>()) {
     const int wgrid = (int)std::min<long long>(items, 8LL * ncu);   // one-wave work-groups, 8 resident per CU
-    hipLaunchKernelGGL(k_tri_matvec_w, dim3(wgrid), dim3(64), 0, s, D, ws, info, dsel, bufA, bufV, bufHS, bufW, k0,
-                       k, nblk, nsmax);
+    if (ev0)   // traced (never inside a graph capture): start / stop recorded by the launch
+      hipExtLaunchKernelGGL(k_tri_matvec_w, dim3(wgrid), dim3(64), 0, s, ev0, ev1, 0, D, ws, info, dsel, bufA, bufV,
+                            bufHS, bufW, k0, k, nblk, nsmax);
+    else
+      hipLaunchKernelGGL(k_tri_matvec_w, dim3(wgrid), dim3(64), 0, s, D, ws, info, dsel, bufA, bufV, bufHS, bufW,
+                         k0, k, nblk, nsmax);
   } else {
     const int grid = (int)std::min<long long>(items, 2LL * ncu);    // two resident work-groups per CU (LDS)
-    hipLaunchKernelGGL(k_tri_matvec<T>, dim3(grid), dim3(256), 0, s, D, ws, info, dsel, bufA, bufV, bufHS, bufW,
-                       k0, k, nblk, nsmax);
+    if (ev0)
+      hipExtLaunchKernelGGL(k_tri_matvec<T>, dim3(grid), dim3(256), 0, s, ev0, ev1, 0, D, ws, info, dsel, bufA,
+                            bufV, bufHS, bufW, k0, k, nblk, nsmax);
+    else
+      hipLaunchKernelGGL(k_tri_matvec<T>, dim3(grid), dim3(256), 0, s, D, ws, info, dsel, bufA, bufV, bufHS, bufW,
+                         k0, k, nblk, nsmax);
   }
 }
 template void launch_matvec<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                    int, int, int, int);
+                                    int, int, int, int, hipEvent_t, hipEvent_t);
 template void launch_matvec<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                  int, int, int, int);
+                                  int, int, int, int, hipEvent_t, hipEvent_t);
 template void launch_matvec<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                  int, int, int, int);
+                                  int, int, int, int, hipEvent_t, hipEvent_t);
 
 }  // namespace x2c

@@ -937,9 +937,10 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
       const int len = maxdim - k - 1 + mv_lead<T>(k);
       const int nst = (len + ST - 1) / ST;
       const int nsmax = nst * (nst + 1) / 2;
-      void* kt = ktrace_begin("k_tri_matvec", s);
-      launch_matvec<T>(s, D, ws, info, nblk, dsel, bufA, bufV, bufHS, bufW, k0, k, nsmax, ncu);
-      ktrace_end(kt, s);
+      hipEvent_t ev0, ev1;
+      void* kt = ktrace_begin("k_tri_matvec", &ev0, &ev1);
+      launch_matvec<T>(s, D, ws, info, nblk, dsel, bufA, bufV, bufHS, bufW, k0, k, nsmax, ncu, ev0, ev1);
+      ktrace_end(kt);
       hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(COLT), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau,
                          bufW, bufV, bufHS, bufET, k0, i + 1, (i + 1 < kbmax) ? 1 : 2);
     }

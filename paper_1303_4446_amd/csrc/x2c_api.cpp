@@ -324,29 +324,29 @@ void trace_collect() {
 
 }  // namespace
 
-// per-launch events of selected kernels (trace level 2)
-void* x2c::ktrace_begin(const char* name, hipStream_t s) {
+// per-launch events of selected kernels (trace level 2), recorded by the
+// launch itself at the kernel's start and end
+void* x2c::ktrace_begin(const char* name, hipEvent_t* start, hipEvent_t* stop) {
+  *start = *stop = nullptr;
   std::lock_guard<std::mutex> lk(g_tmu);
   if (!g_trace || g_trace_level < 2) return nullptr;
   hipEvent_t a = ev_get();
   if (!a) return nullptr;
-  hipEventRecord(a, s);
-  auto* rec = new TraceRec{name, a, nullptr};
-  return rec;
+  hipEvent_t b = ev_get();
+  if (!b) {
+    g_pool.push_back(a);
+    return nullptr;
+  }
+  *start = a;
+  *stop = b;
+  return new TraceRec{name, a, b};
 }
 
-void x2c::ktrace_end(void* h, hipStream_t s) {
+void x2c::ktrace_end(void* h) {
   if (!h) return;
   auto* rec = static_cast<TraceRec*>(h);
   std::lock_guard<std::mutex> lk(g_tmu);
-  hipEvent_t b = ev_get();
-  if (b) {
-    hipEventRecord(b, s);
-    rec->b = b;
-    g_pending.push_back(*rec);
-  } else {
-    g_pool.push_back(rec->a);
-  }
+  g_pending.push_back(*rec);
   delete rec;
 }
 

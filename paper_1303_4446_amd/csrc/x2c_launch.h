@@ -8,8 +8,12 @@ namespace x2c {
 
 // Optional per-launch timing of selected kernels (no-ops unless the library
 // trace is enabled at level 2).
-void* ktrace_begin(const char* name, hipStream_t s);
-void ktrace_end(void* h, hipStream_t s);
+// per-launch timing of selected kernels (trace level 2): a pair of events
+// for the launch to record at the kernel's own start and end
+// (hipExtLaunchKernel), so that launch latency is not counted; both null
+// when tracing is off.  ktrace_end files the pair after the launch.
+void* ktrace_begin(const char* name, hipEvent_t* start, hipEvent_t* stop);
+void ktrace_end(void* h);
 
 void launch_init_info(hipStream_t s, int* info, int nblk);
 void launch_unpack(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN, const double* S,

@@ -56,6 +56,7 @@ __device__ inline T panel_v(const T* A, int nr, int k0, int r, int a) {
 // column kernel reads.
 template <class T>
 void launch_matvec(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int dsel, int bufA,
-                   int bufV, int bufHS, int bufW, int k0, int k, int nsmax, int ncu);
+                   int bufV, int bufHS, int bufW, int k0, int k, int nsmax, int ncu, hipEvent_t ev0 = nullptr,
+                   hipEvent_t ev1 = nullptr);
 
 }  // namespace x2c
