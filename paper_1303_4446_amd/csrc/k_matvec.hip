@@ -71,6 +71,7 @@ __global__ void __launch_bounds__(256) k_tri_matvec(const BlockDesc* D, char* ws
                                                     int nsmax) {
   constexpr int HT = Tiles<T>::HT, ST = 2 * HT, EPL = HT * HT / 64, RPI = 64 / HT;
   constexpr int RPG = ST / 8;          // rows per group in the panel dot products
+  static_assert(panel_width<T>() == HB, "eight row groups of 32 panel columns");
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wi = wave >> 1, wj = wave & 1;
   __shared__ T tiles[4][HT][HT + 1];
@@ -310,46 +311,53 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
     }
     if (diag) {
       // this strip's part of the panel dot products (j < k - k0)
+      // lane (g, j): panel column j, rows RG g .. RG g + RG - 1 of the strip
+      constexpr int PW = panel_width<quat>(), NG = 64 / PW, RG = ST / NG, PG = 8;
+      static_assert(RG % PG == 0, "row groups of PG loads");
       const int ip = k - k0;
       const quat* Wp = bufp<quat>(ws, d, bufW);
-      const int j = lane & (HB - 1), half = lane >> 5;
+      const int j = lane % PW, g = lane / PW;
       quat s1 = tzero<quat>(), s2 = tzero<quat>();
       if (j < ip) {
         // rows off + r lie below the unit entry of every reflector of the
         // panel, so V is read as stored; loads go out in groups of PG rows
         // (clamped in-range addresses, masked values) so that their
         // latencies overlap
-        constexpr int PG = 8;
 #pragma unroll 1
-        for (int t0 = 0; t0 < HT; t0 += PG) {
+        for (int t0 = 0; t0 < RG; t0 += PG) {
           quat wv[PG], pv[PG];
 #pragma unroll
           for (int u = 0; u < PG; ++u) {
-            const int r = R0 + HT * half + t0 + u;
+            const int r = R0 + RG * g + t0 + u;
             const long long row = off + min(max(r, lead), len - 1);
-            wv[u] = Wp[row * HB + j];
+            wv[u] = Wp[row * PW + j];
             pv[u] = A[row * n + k0 + j];
           }
 #pragma unroll
           for (int u = 0; u < PG; ++u) {
-            const int r = R0 + HT * half + t0 + u;
-            const quat vr = r < len ? vsh[0][HT * half + t0 + u] : tzero<quat>();
+            const int r = R0 + RG * g + t0 + u;
+            const quat vr = r < len ? vsh[0][RG * g + t0 + u] : tzero<quat>();
             s1 = mad(conjg(wv[u]), vr, s1);
             s2 = mad(conjg(pv[u]), vr, s2);
           }
         }
       }
-      // halves: lanes j and j + 32
-      __shared__ quat tsum[2][HB];
-      if (half == 1) {
-        tsum[0][j] = s1;
-        tsum[1][j] = s2;
+      // row groups 1 .. NG-1 are added to group 0 in order
+      __shared__ quat tsum[NG - 1][2][PW];
+      if (g > 0) {
+        tsum[g - 1][0][j] = s1;
+        tsum[g - 1][1][j] = s2;
       }
       wave_sync();
-      if (half == 0) {
+      if (g == 0) {
+#pragma unroll
+        for (int h = 0; h < NG - 1; ++h) {
+          s1 = s1 + tsum[h][0][j];
+          s2 = s2 + tsum[h][1][j];
+        }
         quat* TP = HS + (long long)2 * nst * len;
-        TP[((long long)SI * HB + j) * 2] = s1 + tsum[0][j];
-        TP[((long long)SI * HB + j) * 2 + 1] = s2 + tsum[1][j];
+        TP[((long long)SI * PW + j) * 2] = s1;
+        TP[((long long)SI * PW + j) * 2 + 1] = s2;
       }
       wave_sync();
     }

@@ -235,7 +235,7 @@ __device__ void make_reflector_q(quat* A, int n, int k, quat* vout, quat* tau_ou
 }
 
 // ---------------------------------------------------------------- blocked
-// Blocked reduction over the whole batch (panels of HB columns, lower
+// Blocked reduction over the whole batch (panels of PW columns, lower
 // triangle only).  Inside a panel the trailing matrix is left as it was at
 // the panel start; with the panel's reflectors V and companion vectors W the
 // current trailing matrix is A - V W^H - W V^H.  Per column k:
@@ -275,13 +275,13 @@ template <class T>
 __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
                                                  int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS,
                                                  int bufET, int k0, int i, int phase) {
-  constexpr int ST = 2 * Tiles<T>::HT;
+  constexpr int ST = 2 * Tiles<T>::HT, PW = panel_width<T>();
   const int b = blockIdx.x;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int n = seldim(d, dsel);
   if (k0 >= n - 1) return;
-  const int kb = min(HB, n - 1 - k0);
+  const int kb = min(PW, n - 1 - k0);
   T* A = bufp<T>(ws, d, bufA);
   double* dd = bufp<double>(ws, d, bufD);
   double* ee = bufp<double>(ws, d, bufE);
@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
   __shared__ T sh_tau;
   __shared__ double sh_beta;
   __shared__ T sh_alpha;
-  __shared__ T wk[HB], vk[HB], t1[HB], t2[HB];
+  __shared__ T wk[PW], vk[PW], t1[PW], t2[PW];
 
   const int k = k0 + i;                 // column to build (if any)
   const bool build = phase != 2 && i < kb;
@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
       if (build) acol[r] = A[(long long)(off + r) * n + k];
     }
     if (build && tid < ip) {
-      wk[tid] = conjg(Wp[(long long)k * HB + tid]);
+      wk[tid] = conjg(Wp[(long long)k * PW + tid]);
       vk[tid] = conjg(panel_v(A, n, k0, k, tid));
     }
     // panel dot products t1 = W^H v, t2 = V^H v from the matvec's per-strip partials
@@ -326,8 +326,8 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
       const T* TP = HS + (long long)2 * nst * lenp;
 #pragma unroll 4
       for (int S = 0; S < nst; ++S) {
-        a1 = a1 + TP[((long long)S * HB + tid) * 2];
-        a2 = a2 + TP[((long long)S * HB + tid) * 2 + 1];
+        a1 = a1 + TP[((long long)S * PW + tid) * 2];
+        a2 = a2 + TP[((long long)S * PW + tid) * 2 + 1];
       }
       t1[tid] = a1;
       t2[tid] = a2;
@@ -349,15 +349,15 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
       for (int S = q; S < nst; S += CTPR)
         acc = acc + HS[(long long)(S <= Sr ? S : nst + S) * lenp + rt];
       if (ip > 0) {
-        T vr[HB / CTPR], wr[HB / CTPR];
+        T vr[PW / CTPR], wr[PW / CTPR];
 #pragma unroll
-        for (int u = 0; u < HB / CTPR; ++u) {
+        for (int u = 0; u < PW / CTPR; ++u) {
           const int j = min(q + CTPR * u, ip - 1);
           vr[u] = A[rr * n + k0 + j];
-          wr[u] = Wp[rr * HB + j];
+          wr[u] = Wp[rr * PW + j];
         }
 #pragma unroll
-        for (int u = 0; u < HB / CTPR; ++u) {
+        for (int u = 0; u < PW / CTPR; ++u) {
           const int j = q + CTPR * u;
           if (j < ip) {
             acc = acc - vr[u] * t1[j] - wr[u] * t2[j];
@@ -392,7 +392,7 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     for (int r = tid; r < len; r += COLT) {
       T w = mad(alpha, v[r], y[r]);
       y[r] = w;
-      Wp[(long long)(off + r) * HB + ip] = w;
+      Wp[(long long)(off + r) * PW + ip] = w;
     }
     __syncthreads();
     if (!build) return;
@@ -435,13 +435,13 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
 template <class T>
 __global__ void __launch_bounds__(256) k_tri_her2k(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
                                                    int bufW, int k0) {
-  constexpr int TT = Tiles<T>::TT;
+  constexpr int TT = Tiles<T>::TT, PW = panel_width<T>();
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int n = seldim(d, dsel);
   if (k0 >= n - 1) return;
-  const int kb = min(HB, n - 1 - k0);
+  const int kb = min(PW, n - 1 - k0);
   const int c0 = k0 + kb;
   const int len = n - c0;
   if (len <= 0) return;
@@ -454,15 +454,15 @@ __global__ void __launch_bounds__(256) k_tri_her2k(const BlockDesc* D, char* ws,
   const int J = t - I * (I + 1) / 2;
   T* A = bufp<T>(ws, d, bufA);
   const T* Wp = bufp<T>(ws, d, bufW);
-  __shared__ T Vr[TT][HB + 1], Wr[TT][HB + 1], Vc[TT][HB + 1], Wc[TT][HB + 1];
-  for (int e = threadIdx.x; e < TT * HB; e += 256) {
-    int rr = e / HB, j = e % HB;
+  __shared__ T Vr[TT][PW + 1], Wr[TT][PW + 1], Vc[TT][PW + 1], Wc[TT][PW + 1];
+  for (int e = threadIdx.x; e < TT * PW; e += 256) {
+    int rr = e / PW, j = e % PW;
     int r = c0 + TT * I + rr, c = c0 + TT * J + rr;
     bool okr = r < n && j < kb, okc = c < n && j < kb;
     Vr[rr][j] = okr ? panel_v(A, n, k0, r, j) : tzero<T>();
-    Wr[rr][j] = okr ? Wp[(long long)r * HB + j] : tzero<T>();
+    Wr[rr][j] = okr ? Wp[(long long)r * PW + j] : tzero<T>();
     Vc[rr][j] = okc ? conjg(panel_v(A, n, k0, c, j)) : tzero<T>();
-    Wc[rr][j] = okc ? conjg(Wp[(long long)c * HB + j]) : tzero<T>();
+    Wc[rr][j] = okc ? conjg(Wp[(long long)c * PW + j]) : tzero<T>();
   }
   __syncthreads();
   for (int e = threadIdx.x; e < TT * TT; e += 256) {
@@ -471,7 +471,7 @@ __global__ void __launch_bounds__(256) k_tri_her2k(const BlockDesc* D, char* ws,
     if (r < n && c < n && c <= r) {
       T s = tzero<T>();
 #pragma unroll 8
-      for (int j = 0; j < HB; ++j) {
+      for (int j = 0; j < PW; ++j) {
         s = mad(Vr[rr][j], Wc[cc][j], s);
         s = mad(Wr[rr][j], Vc[cc][j], s);
       }
@@ -799,7 +799,7 @@ void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, 
 
 // ---------------------------------------------------------------- quaternion rank-2k update on the matrix cores
 // Trailing lower triangle A -= V W^H + W V^H = [V W] [W V]^H for quaternion
-// matrices: a product with contraction length 2 HB over 64 x 64 tiles on or
+// matrices: a product with contraction length 2 PW over 64 x 64 tiles on or
 // below the diagonal, operands staged per k chunk of 16 as four component
 // planes, 16 MFMAs (one per pair of components, signs of the quaternion
 // product) per 16 x 16 block and k step of 4.  grid = (lower tiles, nblk).
@@ -807,12 +807,13 @@ constexpr int HQ_T = 64, HQ_K = 16;
 
 __global__ void __launch_bounds__(256, 2) k_tri_her2k_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel,
                                                           int bufA, int bufW, int k0) {
+  constexpr int PW = panel_width<quat>();
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int n = seldim(d, dsel);
   if (k0 >= n - 1) return;
-  const int kb = min(HB, n - 1 - k0);
+  const int kb = min(PW, n - 1 - k0);
   const int c0 = k0 + kb;
   const int len = n - c0;
   if (len <= 0) return;
@@ -841,9 +842,9 @@ __global__ void __launch_bounds__(256, 2) k_tri_her2k_q_mfma(const BlockDesc* D,
   // column j of [V W] (wfirst = 0) or [W V] (wfirst = 1) at row `row`; zero
   // beyond the matrix and for panel columns >= kb
   auto opval = [&](int row, int j, int wfirst) -> quat {
-    const int half = j >= HB, a = j - HB * half;
+    const int half = j >= PW, a = j - PW * half;
     if (row >= n || a >= kb) return tzero<quat>();
-    return (half != wfirst) ? Wp[(long long)row * HB + a] : panel_v(A, n, k0, row, a);
+    return (half != wfirst) ? Wp[(long long)row * PW + a] : panel_v(A, n, k0, row, a);
   };
   constexpr int NL = HQ_T * HQ_K / 256;
   quat na[NL], nb[NL];
@@ -869,7 +870,7 @@ __global__ void __launch_bounds__(256, 2) k_tri_her2k_q_mfma(const BlockDesc* D,
       Bs[3][kk][r] = nb[q].b.y;
     }
   };
-  for (int kc = 0; kc < 2 * HB; kc += HQ_K) {
+  for (int kc = 0; kc < 2 * PW; kc += HQ_K) {
     // two waves per SIMD instead of a register prefetch
     __syncthreads();
     fetch(kc);
@@ -916,7 +917,7 @@ __global__ void __launch_bounds__(256, 2) k_tri_her2k_q_mfma(const BlockDesc* D,
 template <class T>
 void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                      int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS, int bufET) {
-  constexpr int ST = 2 * Tiles<T>::HT, TT = Tiles<T>::TT;
+  constexpr int ST = 2 * Tiles<T>::HT, TT = Tiles<T>::TT, PW = panel_width<T>();
   if constexpr (!is_quat<T>()) {
     if (maxdim <= 96) {
       launch_hetrd<T>(s, D, ws, info, nblk, maxdim, dsel, bufA, bufD, bufE, bufTau);
@@ -928,8 +929,8 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
                       (int)shm);
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  for (int k0 = 0; k0 < maxdim - 1; k0 += HB) {
-    const int kbmax = std::min(HB, maxdim - 1 - k0);
+  for (int k0 = 0; k0 < maxdim - 1; k0 += PW) {
+    const int kbmax = std::min(PW, maxdim - 1 - k0);
     hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(COLT), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufW,
                        bufV, bufHS, bufET, k0, 0, 0);
     for (int i = 0; i < kbmax; ++i) {

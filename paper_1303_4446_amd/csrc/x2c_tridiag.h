@@ -24,8 +24,17 @@ struct Tiles<quat> {
   static constexpr int VR = 16;
 };
 
-// panel width (reflectors per panel)
-constexpr int HB = 32;
+// panel width (reflectors per panel).  Every column step reads the rows of
+// the panel's V and W twice (the panel dot products and the corrections of
+// y and of the next column), 4 x width x len elements against the len^2 / 2
+// of the trailing triangle, while the rank-2k update after each panel reads
+// and writes the triangle once; 16 balances the two for the quaternion
+// reductions (whose panel update runs on the matrix cores at either width).
+template <class T>
+__host__ __device__ constexpr int panel_width() {
+  return is_quat<T>() ? 16 : 32;
+}
+constexpr int HB = 32;   // the widest panel (buffer sizes)
 
 // Leading virtual rows / columns of the matvec tiling at column step k.  The
 // quaternion tiles start on a 128-byte boundary (4 quaternions): the trailing
