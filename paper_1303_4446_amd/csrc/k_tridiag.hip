@@ -295,6 +295,7 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
   T* y = v + n;
   T* colacc = y + n;
   T* acol = colacc + n;                 // column k (rows off..n-1) of A, updated in LDS
+  T* tps = acol + n;                    // the matvec's panel dot partials (strips x PW x 2)
   __shared__ double red[32];
   __shared__ T sh_tau;
   __shared__ double sh_beta;
@@ -312,6 +313,10 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     // the matvec's tiling: lead virtual rows, then the len trailing rows
     const int lead = mv_lead<T>(kp), lenp = len + lead;
     const int nst = (lenp + ST - 1) / ST;
+    // every load of this part goes out before the first wait: v, column k,
+    // row k of the panel and the per-strip panel dot partials (staged in LDS)
+    const T* TP = HS + (long long)2 * nst * lenp;
+    for (int e = tid; e < nst * PW * 2; e += COLT) tps[e] = TP[e];
     for (int r = tid; r < len; r += COLT) {
       v[r] = vg[r];
       if (build) acol[r] = A[(long long)(off + r) * n + k];
@@ -320,14 +325,13 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
       wk[tid] = conjg(Wp[(long long)k * PW + tid]);
       vk[tid] = conjg(panel_v(A, n, k0, k, tid));
     }
-    // panel dot products t1 = W^H v, t2 = V^H v from the matvec's per-strip partials
+    __syncthreads();
+    // panel dot products t1 = W^H v, t2 = V^H v: the strips' partials in order
     if (tid < ip) {
       T a1 = tzero<T>(), a2 = tzero<T>();
-      const T* TP = HS + (long long)2 * nst * lenp;
-#pragma unroll 4
       for (int S = 0; S < nst; ++S) {
-        a1 = a1 + TP[((long long)S * PW + tid) * 2];
-        a2 = a2 + TP[((long long)S * PW + tid) * 2 + 1];
+        a1 = a1 + tps[(S * PW + tid) * 2];
+        a2 = a2 + tps[(S * PW + tid) * 2 + 1];
       }
       t1[tid] = a1;
       t2[tid] = a2;
@@ -335,29 +339,44 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     __syncthreads();
     // y_r = fixed-order sum of the super-tile partials minus the panel
     // corrections; the same pass accumulates the panel part of the update of
-    // the next column
-    // CTPR threads per row: thread q of the group takes the super-tile
-    // partials S = q, q+CTPR, ... and the panel columns j = q, q+CTPR, ...,
-    // all of its loads issued before any is used (rows off + r lie below the
-    // unit entry of every panel reflector, so V is read as stored); the
-    // group's sums are combined by lane exchange in a fixed pattern.
-    for (int r = tid / CTPR; r < len; r += COLT / CTPR) {
-      const int q = tid % CTPR;
+    // the next column.  CTPR threads per row: thread q of the group takes the
+    // super-tile partials S = q, q+CTPR, ... and the panel columns j = q,
+    // q+CTPR, ... (rows off + r lie below the unit entry of every panel
+    // reflector, so V is read as stored); the group's sums are combined by
+    // lane exchange in a fixed pattern.  Each group takes two rows per pass
+    // and issues the loads of both (the first NSU partials per thread, the
+    // panel rows; clamped in-range addresses, masked values) before using
+    // any, so that a pass costs one memory round trip.
+    constexpr int NSU = 4, PU = PW / CTPR, YR = COLT / CTPR;
+    const int q = tid % CTPR;
+    auto issue = [&](int r, T (&hp)[NSU], T (&vr)[PU], T (&wr)[PU]) {
       const int rt = r + lead, Sr = rt / ST;
       const long long rr = off + r;
-      T acc = tzero<T>(), ca = tzero<T>();
-      for (int S = q; S < nst; S += CTPR)
-        acc = acc + HS[(long long)(S <= Sr ? S : nst + S) * lenp + rt];
-      if (ip > 0) {
-        T vr[PW / CTPR], wr[PW / CTPR];
 #pragma unroll
-        for (int u = 0; u < PW / CTPR; ++u) {
+      for (int u = 0; u < NSU; ++u) {
+        const int S = min(q + CTPR * u, nst - 1);
+        hp[u] = HS[(long long)(S <= Sr ? S : nst + S) * lenp + rt];
+      }
+      if (ip > 0) {
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
           const int j = min(q + CTPR * u, ip - 1);
           vr[u] = A[rr * n + k0 + j];
           wr[u] = Wp[rr * PW + j];
         }
+      }
+    };
+    auto finish = [&](int r, const T (&hp)[NSU], const T (&vr)[PU], const T (&wr)[PU]) {
+      const int rt = r + lead, Sr = rt / ST;
+      T acc = tzero<T>(), ca = tzero<T>();
 #pragma unroll
-        for (int u = 0; u < PW / CTPR; ++u) {
+      for (int u = 0; u < NSU; ++u)
+        if (q + CTPR * u < nst) acc = acc + hp[u];
+      for (int S = q + CTPR * NSU; S < nst; S += CTPR)   // more than CTPR * NSU strips
+        acc = acc + HS[(long long)(S <= Sr ? S : nst + S) * lenp + rt];
+      if (ip > 0) {
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
           const int j = q + CTPR * u;
           if (j < ip) {
             acc = acc - vr[u] * t1[j] - wr[u] * t2[j];
@@ -371,6 +390,14 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
         y[r] = acc;
         colacc[r] = ca;
       }
+    };
+    for (int r = tid / CTPR; r < len; r += 2 * YR) {
+      T hpa[NSU], vra[PU], wra[PU], hpb[NSU], vrb[PU], wrb[PU];
+      const bool two = r + YR < len;      // the same for the CTPR lanes of a row
+      issue(r, hpa, vra, wra);
+      if (two) issue(r + YR, hpb, vrb, wrb);
+      finish(r, hpa, vra, wra);
+      if (two) finish(r + YR, hpb, vrb, wrb);
     }
     __syncthreads();   // y, colacc are read below by other threads
     double dr = 0.0, di = 0.0;
@@ -924,7 +951,8 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
       return;
     }
   }
-  const size_t shm = 4 * (size_t)maxdim * sizeof(T);   // v, y, colacc, acol of the column kernel
+  // v, y, colacc, acol and the panel dot partials of the column kernel
+  const size_t shm = (4 * (size_t)maxdim + (size_t)((maxdim + 3 + ST - 1) / ST) * PW * 2) * sizeof(T);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tri_col<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shm);
   int dev = 0, ncu = 256;
