@@ -49,6 +49,17 @@ def algorithmic_flops(stage: str, N: int, twocomp: bool) -> float | None:
     return None
 
 
+# The product chain after X~ (quaternion form, FP64): stages and their
+# algorithmic real flops per block in units of N^3 (N quaternion rows).  A
+# quaternion multiply-add is 16 real multiply-adds (32 flops), a real scalar
+# matrix times a quaternion 4 (8 flops); Hermitian outputs and triangular
+# real factors count half.  chain_SL: T X (8), W'' X (32), X^H (W'' X) (16);
+# chain_Q: X~^H X~ (16); chain_R: two triangular factors (4 + 4); chain_h:
+# L R (32), R^H (L R) (16).
+CHAIN_STAGES = ("chain_SL", "chain_Q", "chain_R", "chain_h")
+CHAIN_FLOPS_PER_N3 = 8 + 32 + 16 + 16 + 8 + 32 + 16
+
+
 def matvec_bytes(Ns, twocomp: bool, reduction: str) -> tuple[float, int]:
     """Algorithmic HBM bytes of all tridiagonal-reduction matvec launches of
     one step, and the number of launches.  Unit: one element of the lower
@@ -316,6 +327,12 @@ def main():
         fl = algorithmic_flops(st, int(batch.Ns.max()), twocomp)
         if fl is not None and st in stage_ms:
             extra[st + "_fp64_tflops"] = fl * nblk / (stage_ms[st] / 1e3) / 1e12
+    chain = [st for st in CHAIN_STAGES if st in stage_ms]
+    if twocomp and args.reduction == "quaternion" and args.prec == "fp64" and len(chain) == len(CHAIN_STAGES):
+        Nm = int(batch.Ns.max())
+        ms = sum(stage_ms[st] for st in chain)
+        extra["chain_fp64_tflops"] = CHAIN_FLOPS_PER_N3 * Nm ** 3 * nblk / (ms / 1e3) / 1e12
+        extra["chain_frac_of_fp64_peak"] = extra["chain_fp64_tflops"] / PEAK_FP64_TFLOPS
 
     pct = None if args.no_pct else time_picture_change(px, torch, batch, twocomp, c, prec, red, stream)
     cpu = cpu_baseline(blocks, twocomp, c, args.cpu_blocks) if args.cpu_blocks > 0 else None

@@ -1,0 +1,80 @@
+"""Host-side helpers of bench.py: algorithmic byte counts of the reduction
+matvec, the counter-profile reader and the chain flop count (no GPU)."""
+import hashlib
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def brute_matvec_bytes(Ns, dim_of, es, skip_small):
+    """Column by column: the matvec at step k reads the lower triangle
+    (diagonal included) of the trailing (d - k - 1)-square matrix."""
+    total, launches = 0.0, 0
+    dims = [dim_of(int(N)) for N in Ns]
+    if skip_small and max(dims) <= 96:
+        return 0.0, 0
+    launches = max(dims) - 1
+    for d in dims:
+        for k in range(d - 1):
+            L = d - k - 1
+            total += L * (L + 1) // 2 * es
+    return total, launches
+
+
+@pytest.mark.parametrize("Ns", [[5], [7, 3, 12], [40, 40]])
+def test_matvec_bytes_quaternion_matches_column_count(Ns):
+    tot, nl = bench.matvec_bytes(Ns, True, "quaternion")
+    b4, l4 = brute_matvec_bytes(Ns, lambda N: 2 * N, 32, False)
+    bq, lq = brute_matvec_bytes(Ns, lambda N: N, 32, False)
+    assert nl == l4 + lq
+    assert tot == pytest.approx(b4 + bq, rel=0, abs=0)
+
+
+def test_matvec_bytes_complex_and_real():
+    Ns = [30, 50]
+    tot, nl = bench.matvec_bytes(Ns, True, "complex")
+    b4, l4 = brute_matvec_bytes(Ns, lambda N: 4 * N, 16, False)
+    bq, lq = brute_matvec_bytes(Ns, lambda N: 2 * N, 16, False)
+    assert (tot, nl) == (b4 + bq, l4 + lq)
+    # spin-free: reductions of dimension <= 96 use the one-work-group kernel
+    tot, nl = bench.matvec_bytes([20, 40], False, "complex")
+    assert (tot, nl) == (0.0, 0)
+    tot, nl = bench.matvec_bytes([60], False, "complex")
+    b4, l4 = brute_matvec_bytes([60], lambda N: 2 * N, 8, True)
+    assert (tot, nl) == (b4, l4)
+
+
+def test_ag309_bytes_per_launch():
+    tot, nl = bench.matvec_bytes([192] * 309, True, "quaternion")
+    assert nl == 383 + 191
+    assert tot / nl == pytest.approx(1.82889e8, rel=1e-5)
+
+
+def test_chain_flops_unit():
+    # 5 quaternion products (2 full at 32 N^3 flops, 3 Hermitian at 16) and 3
+    # real-factor products (T X full at 8, two triangular at 4) after X~
+    assert bench.CHAIN_FLOPS_PER_N3 == 2 * 32 + 3 * 16 + 8 + 2 * 4
+
+
+def test_recorded_traffic_follows_the_source_hash(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    src.write_bytes(b"kernel source")
+    h = hashlib.sha256(b"kernel source").hexdigest()[:16]
+    prof = tmp_path / "p.md"
+    prof.write_text(f"# title\n\n| a | b |\n\nsource: k.hip\nsource_sha256_16: {h}\ntraffic_bytes_per_launch: 1.5e+08\n")
+    monkeypatch.setattr(bench, "HERE", str(tmp_path))
+    assert bench.recorded_traffic("k.hip", "p.md") == 1.5e8
+    src.write_bytes(b"kernel source, changed")
+    assert bench.recorded_traffic("k.hip", "p.md") is None
+    assert bench.recorded_traffic("k.hip", "missing.md") is None
+
+
+def test_committed_profile_matches_the_committed_kernel():
+    v = bench.recorded_traffic("paper_1303_4446_amd/csrc/k_matvec.hip", "profiles/k_tri_matvec_w_ag309_traffic.md")
+    assert v is not None and 1.0e8 < v < 1.0e9
