@@ -544,12 +544,23 @@ __global__ void __launch_bounds__(256) k_larft(const BlockDesc* D, char* ws, con
   __shared__ T Vs[LR][ORB + 1];
   __shared__ T G[ORB][ORB + 1];
   T (*Ts)[ORB + 1] = Vs;            // after the Gram matrix is complete
-  // Gram matrix of the panel (upper part): thread t owns pairs p = t + 256 q.
-  // Row chunks of LR: the next chunk is loaded into registers while the
-  // current one is reduced.
-  constexpr int PER = LR * ORB / 256;
-  T acc[4];
-  for (int q = 0; q < 4; ++q) acc[q] = tzero<T>();
+  // Gram matrix of the panel (strict upper part): thread t owns pairs
+  // p = t and t + 256 of the ORB (ORB - 1) / 2 pairs a < c, numbered
+  // column by column.  Row chunks of LR: the next chunk is loaded into
+  // registers while the current one is reduced.
+  constexpr int PER = LR * ORB / 256, NP = ORB * (ORB - 1) / 2;
+  static_assert(NP <= 512, "two pairs per thread");
+  T acc[2];
+  int pa[2], pc[2];
+  for (int q = 0; q < 2; ++q) {
+    acc[q] = tzero<T>();
+    const int p = min((int)threadIdx.x + 256 * q, NP - 1);
+    int c = (int)((1.0 + sqrt(1.0 + 8.0 * p)) * 0.5);
+    while (c * (c - 1) / 2 > p) --c;
+    while ((c + 1) * c / 2 <= p) ++c;
+    pa[q] = p - c * (c - 1) / 2;
+    pc[q] = c;
+  }
   T nv[PER];
   auto fetch = [&](int r0) {
 #pragma unroll
@@ -568,10 +579,9 @@ __global__ void __launch_bounds__(256) k_larft(const BlockDesc* D, char* ws, con
     }
     __syncthreads();
     if (r0 + LR < nr) fetch(r0 + LR);
-    for (int q = 0; q < 4; ++q) {
-      int p = threadIdx.x + 256 * q;
-      int a = p / ORB, c = p % ORB;
-      if (a < c) {
+    for (int q = 0; q < 2; ++q) {
+      if ((int)threadIdx.x + 256 * q < NP) {
+        const int a = pa[q], c = pc[q];
         T s = acc[q];
         for (int rr = 0; rr < LR; ++rr) s = mad(conjg(Vs[rr][a]), Vs[rr][c], s);
         acc[q] = s;
@@ -579,10 +589,8 @@ __global__ void __launch_bounds__(256) k_larft(const BlockDesc* D, char* ws, con
     }
   }
   __syncthreads();
-  for (int q = 0; q < 4; ++q) {
-    int p = threadIdx.x + 256 * q;
-    G[p / ORB][p % ORB] = acc[q];
-  }
+  for (int q = 0; q < 2; ++q)
+    if ((int)threadIdx.x + 256 * q < NP) G[pa[q]][pc[q]] = acc[q];
   for (int l = threadIdx.x; l < ORB * ORB; l += 256) Ts[l / ORB][l % ORB] = tzero<T>();
   __syncthreads();
   if (threadIdx.x == 0) Ts[0][0] = taus[k0];
