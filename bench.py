@@ -324,14 +324,14 @@ def main():
                     "launches_per_step": mv[1] / args.steps, "share_of_step": mv[0] / args.steps / ms_step}
     extra = {}
     for st in ("tridiag_4c", "backtransform_4c"):
-        fl = algorithmic_flops(st, int(batch.Ns.max()), twocomp)
-        if fl is not None and st in stage_ms:
-            extra[st + "_fp64_tflops"] = fl * nblk / (stage_ms[st] / 1e3) / 1e12
+        fl = [algorithmic_flops(st, int(N), twocomp) for N in batch.Ns]
+        if None not in fl and st in stage_ms:
+            extra[st + "_fp64_tflops"] = sum(fl) / (stage_ms[st] / 1e3) / 1e12
     chain = [st for st in CHAIN_STAGES if st in stage_ms]
     if twocomp and args.reduction == "quaternion" and args.prec == "fp64" and len(chain) == len(CHAIN_STAGES):
-        Nm = int(batch.Ns.max())
+        n3 = float(np.sum(np.asarray(batch.Ns, dtype=np.float64) ** 3))
         ms = sum(stage_ms[st] for st in chain)
-        extra["chain_fp64_tflops"] = CHAIN_FLOPS_PER_N3 * Nm ** 3 * nblk / (ms / 1e3) / 1e12
+        extra["chain_fp64_tflops"] = CHAIN_FLOPS_PER_N3 * n3 / (ms / 1e3) / 1e12
         extra["chain_frac_of_fp64_peak"] = extra["chain_fp64_tflops"] / PEAK_FP64_TFLOPS
 
     pct = None if args.no_pct else time_picture_change(px, torch, batch, twocomp, c, prec, red, stream)
