@@ -164,6 +164,8 @@ def parse():
     ap.add_argument("--streams", type=int, choices=[1, 2, 3, 4], default=4,
                     help="run the batch as this many parts on as many streams")
     ap.add_argument("--no-graph", action="store_true", help="eager launches instead of graph replay")
+    ap.add_argument("--autotune", action="store_true",
+                    help="before the warm-up, let x2c_autotune pick the launch shape (streams, matvec residency)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the workload, copy a device buffer of this size once (a plain copy kernel "
                          "of known traffic for scaling hardware byte counters)")
@@ -261,7 +263,14 @@ def main():
     stream = torch.cuda.current_stream()
     print(f"# workload: {desc}; prec {args.prec}", file=sys.stderr, flush=True)
 
-    (h, eps, info), ws = px.build_batched(batch, c, prec=prec, stream=stream, reduction=red)
+    tuned = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuned, out, ws = px.autotune(batch, c, prec=prec, stream=stream, reduction=red, reps=2)
+        print(f"# autotune: {tuned[0]} streams, matvec {tuned[1]} work-groups per CU "
+              f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    (h, eps, info), ws = px.build_batched(batch, c, prec=prec, stream=stream, reduction=red,
+                                          workspace=ws if tuned else None)
     out = (h, eps, info)
     for _ in range(max(0, args.warmup - 1)):
         px.build_batched(batch, c, prec=prec, workspace=ws, out=out, stream=stream, reduction=red)
@@ -342,7 +351,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "nblocks": nblk, "mode": "two-component" if twocomp else "spin-free",
-                   "prec": args.prec, "reduction": args.reduction, "streams": args.streams, **acc},
+                   "prec": args.prec, "reduction": args.reduction,
+                   "streams": tuned[0] if tuned else args.streams,
+                   "matvec_wg_per_cu": tuned[1] if tuned else 8, "autotuned": bool(tuned), **acc},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: round(v, 4) for k, v in sorted(stage_ms.items(), key=lambda kv: -kv[1])},

@@ -226,7 +226,8 @@ int x2c_dlu_assemble(const x2c_options* opts, int natom, const int* N, const dou
 /* Static description of a return or info code. */
 const char* x2c_strerror(int code);
 
-/* Drop cached launch plans, captured graphs and trace events. */
+/* Drop cached launch plans, captured graphs, tuned launch shapes and trace
+ * events. */
 void x2c_release(void);
 
 /*
@@ -253,6 +254,27 @@ int x2c_graph_enable(int on);
  * Returns the previous setting.
  */
 int x2c_stream_split(int ways);
+
+/*
+ * Autotuning of the launch shape of a batch class (Sec. III.A batching).
+ * Runs x2c_build_batched on the caller's batch (same arguments, same
+ * outputs written) once untimed and `reps` times timed, for every candidate
+ * shape: the batch split over 1..4 streams (as x2c_stream_split) times 4 or 8
+ * resident work-groups per CU for the persistent matvec of the quaternion
+ * reductions.  The fastest (HIP events on `stream`, summed over the reps) is
+ * kept for every later call with the same options and block sizes N[] and
+ * written to *ways_out and *mv_res_out (either may be NULL); batches of other
+ * classes keep x2c_stream_split's setting and 8 work-groups per CU.  All
+ * candidates give identical results.  Blocking: synchronises `stream` once
+ * per candidate.  Returns X2C_OK, X2C_EINVAL (arguments as for
+ * x2c_build_batched; reps outside 1..100) or X2C_EHIP, in which case the
+ * class's previous shape is kept.  Run it with tracing disabled (traced calls
+ * use one stream).  x2c_release() forgets every tuned shape.
+ */
+int x2c_autotune(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off, const double* S,
+                 const double* T, const double* V, const double* W, const int64_t* h_off, void* h,
+                 const int64_t* eps_off, double* eps, int* info, void* workspace, size_t ws_bytes, void* stream,
+                 int reps, int* ways_out, int* mv_res_out);
 
 /*
  * Tracing.  x2c_trace_enable(1) makes every later call bracket each of its

@@ -25,7 +25,8 @@ INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subsp
 
 EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_build_batched_xr",
             "x2c_dlu_workspace_bytes", "x2c_dlu_assemble", "x2c_strerror", "x2c_release", "x2c_graph_enable",
-            "x2c_stream_split", "x2c_picture_change", "x2c_trace_enable", "x2c_trace_read", "x2c_trace_reset")
+            "x2c_stream_split", "x2c_autotune", "x2c_picture_change", "x2c_trace_enable", "x2c_trace_read",
+            "x2c_trace_reset")
 
 
 class X2CError(RuntimeError):
@@ -83,6 +84,10 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.x2c_graph_enable.restype = i32
     lib.x2c_stream_split.argtypes = [i32]
     lib.x2c_stream_split.restype = i32
+    lib.x2c_autotune.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp, i64p, vp, i64p, vp,
+                                 vp, vp, ctypes.c_size_t, vp, i32, ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_int)]
+    lib.x2c_autotune.restype = i32
     lib.x2c_trace_enable.argtypes = [i32]
     lib.x2c_trace_enable.restype = i32
     lib.x2c_trace_read.argtypes = [i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
@@ -337,6 +342,46 @@ def build_batched(batch: Batch, c: float, prec: int = FP64, slices: int = 0, wor
     if rc != OK:
         raise X2CError(rc, strerror(rc))
     return (h, eps, info), workspace
+
+
+def autotune(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspace=None, out=None, stream=None,
+             reduction: int = RED_QUATERNION, reps: int = 3):
+    """x2c_autotune on the batch (writes the same outputs as build_batched).
+    Returns (ways, mv_res) of the fastest launch shape, the outputs and the
+    workspace."""
+    torch = _torch()
+    lib = load()
+    dev = batch.S.device
+    h_off, eps_off, hsz, esz = batch.out_layout()
+    if out is None:
+        out = (torch.empty(hsz, dtype=torch.float64, device=dev), torch.empty(esz, dtype=torch.float64, device=dev),
+               torch.empty(batch.nblk, dtype=torch.int32, device=dev))
+    h, eps, info = out
+    wsb = workspace_bytes(batch.Ns, batch.twocomp, c, prec)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    opt = options(batch.twocomp, c, prec, slices, reduction)
+    Ns = np.ascontiguousarray(batch.Ns, dtype=np.int32)
+    i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
+    in_off, ho, eo = i64(batch.in_off), i64(h_off), i64(eps_off)
+    P = ctypes.POINTER(ctypes.c_int64)
+    ways, res = ctypes.c_int(0), ctypes.c_int(0)
+    rc = lib.x2c_autotune(
+        ctypes.byref(opt), batch.nblk, Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), in_off.ctypes.data_as(P),
+        _dev(batch.S, torch, torch.float64), _dev(batch.T, torch, torch.float64),
+        _dev(batch.V, torch, torch.float64), _dev(batch.W, torch, torch.float64),
+        ho.ctypes.data_as(P), _dev(h, torch, torch.float64), eo.ctypes.data_as(P),
+        _dev(eps, torch, torch.float64), _dev(info, torch, torch.int32),
+        ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()), _stream_ptr(torch, stream),
+        int(reps), ctypes.byref(ways), ctypes.byref(res))
+    if rc != OK:
+        raise X2CError(rc, strerror(rc))
+    return (ways.value, res.value), out, workspace
+
+
+def release() -> None:
+    """x2c_release: drop cached plans, graphs, tuned launch shapes and trace events."""
+    load().x2c_release()
 
 
 def unpack_h(h_flat: np.ndarray, Ns, twocomp: bool):

@@ -366,10 +366,13 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
 
 template <class T>
 void launch_matvec(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int dsel, int bufA,
-                   int bufV, int bufHS, int bufW, int k0, int k, int nsmax, int ncu, hipEvent_t ev0, hipEvent_t ev1) {
+                   int bufV, int bufHS, int bufW, int k0, int k, int nsmax, int ncu, int mv_res, hipEvent_t ev0,
+                   hipEvent_t ev1) {
   const long long items = (long long)nsmax * nblk;
   if constexpr (is_quat<T>()) {
-    const int wgrid = (int)std::min<long long>(items, 8LL * ncu);   // one-wave work-groups, 8 resident per CU
+    // one-wave work-groups, mv_res (1..8) of them per CU
+    const long long res = std::max(1, std::min(8, mv_res));
+    const int wgrid = (int)std::min<long long>(items, res * ncu);
     if (ev0)   // traced (never inside a graph capture): start / stop recorded by the launch
       hipExtLaunchKernelGGL(k_tri_matvec_w, dim3(wgrid), dim3(64), 0, s, ev0, ev1, 0, D, ws, info, dsel, bufA, bufV,
                             bufHS, bufW, k0, k, nblk, nsmax);
@@ -387,10 +390,10 @@ void launch_matvec(hipStream_t s, const BlockDesc* D, char* ws, const int* info,
   }
 }
 template void launch_matvec<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                    int, int, int, int, hipEvent_t, hipEvent_t);
+                                    int, int, int, int, int, hipEvent_t, hipEvent_t);
 template void launch_matvec<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                  int, int, int, int, hipEvent_t, hipEvent_t);
+                                  int, int, int, int, int, hipEvent_t, hipEvent_t);
 template void launch_matvec<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                  int, int, int, int, hipEvent_t, hipEvent_t);
+                                  int, int, int, int, int, hipEvent_t, hipEvent_t);
 
 }  // namespace x2c

@@ -951,7 +951,8 @@ __global__ void __launch_bounds__(256, 2) k_tri_her2k_q_mfma(const BlockDesc* D,
 // one-work-group reduction when every block is small.
 template <class T>
 void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
-                     int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS, int bufET) {
+                     int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS, int bufET,
+                     int mv_res) {
   constexpr int ST = 2 * Tiles<T>::HT, TT = Tiles<T>::TT, PW = panel_width<T>();
   if constexpr (!is_quat<T>()) {
     if (maxdim <= 96) {
@@ -976,7 +977,7 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
       const int nsmax = nst * (nst + 1) / 2;
       hipEvent_t ev0, ev1;
       void* kt = ktrace_begin("k_tri_matvec", &ev0, &ev1);
-      launch_matvec<T>(s, D, ws, info, nblk, dsel, bufA, bufV, bufHS, bufW, k0, k, nsmax, ncu, ev0, ev1);
+      launch_matvec<T>(s, D, ws, info, nblk, dsel, bufA, bufV, bufHS, bufW, k0, k, nsmax, ncu, mv_res, ev0, ev1);
       ktrace_end(kt);
       hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(COLT), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau,
                          bufW, bufV, bufHS, bufET, k0, i + 1, (i + 1 < kbmax) ? 1 : 2);
@@ -997,11 +998,11 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
   hipLaunchKernelGGL(k_tri_last<T>, dim3((nblk + 255) / 256), dim3(256), 0, s, D, ws, info, nblk, dsel, bufA, bufD);
 }
 template void launch_hetrd_mk<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                      int, int, int, int, int);
+                                      int, int, int, int, int, int);
 template void launch_hetrd_mk<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                    int, int, int, int, int);
+                                    int, int, int, int, int, int);
 template void launch_hetrd_mk<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                    int, int, int, int, int);
+                                    int, int, int, int, int, int);
 
 template <class T>
 void launch_ormtr_blocked(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim,

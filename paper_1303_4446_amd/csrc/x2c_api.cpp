@@ -360,7 +360,8 @@ T tcast(double v) {
 // The stage sequence for one batch (all blocks advance stage by stage).
 template <class T>
 int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const double* S, const double* Tm, const double* V,
-               const double* W, double* h, double* eps, double* Xo, double* Ro, int* info, char* ws, hipStream_t s) {
+               const double* W, double* h, double* eps, double* Xo, double* Ro, int* info, char* ws, hipStream_t s,
+               int mv_res) {
   const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off) + b0;
   const bool tc = o->mode == X2C_TWOCOMP;
   const double c = o->c;
@@ -430,7 +431,7 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
     // positive-energy branch of the reduced 4c matrix (complex m x m form)
     {
       STAGE("tridiag_4c");
-      launch_hetrd_mk<T>(s, D, ws, info, nblk, maxm, DIM_m, C_A, V_D, V_E, V_TAU, W_PAN, W_VCUR, W_HS, V_ET);
+      launch_hetrd_mk<T>(s, D, ws, info, nblk, maxm, DIM_m, C_A, V_D, V_E, V_TAU, W_PAN, W_VCUR, W_HS, V_ET, mv_res);
     }
     {
       STAGE("branch_4c");
@@ -449,7 +450,7 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
     // the same on the quaternion n x n form (time-reversal structure)
     {
       STAGE("tridiag_4c");
-      launch_hetrd_mk<quat>(s, D, ws, info, nblk, maxn, DIM_n, C_A, V_D, V_E, V_TAU, W_PAN, W_VCUR, W_HS, V_ET);
+      launch_hetrd_mk<quat>(s, D, ws, info, nblk, maxn, DIM_n, C_A, V_D, V_E, V_TAU, W_PAN, W_VCUR, W_HS, V_ET, mv_res);
       launch_phase_q(s, D, ws, info, nblk, DIM_n);
     }
     {
@@ -517,7 +518,7 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
   if (!kramers) {
     {
       STAGE("tridiag_Q");
-      launch_hetrd_mk<T>(s, D, ws, info, nblk, maxn, DIM_n, C_Q, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS, V_ET);
+      launch_hetrd_mk<T>(s, D, ws, info, nblk, maxn, DIM_n, C_Q, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS, V_ET, mv_res);
     }
     {
       // Q^-1/2 = Q_h F Q_h^H, F = T_Q^-1/2 by quadrature
@@ -534,7 +535,7 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
       STAGE("tridiag_Q");
       if (!qchain) launch_cplx_to_quat(s, D, ws, info, nblk, maxN, C_Q, C_TMP2);
       launch_hetrd_mk<quat>(s, D, ws, info, nblk, maxN, DIM_N, qrefl, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS,
-                            V_ET);
+                            V_ET, mv_res);
       launch_phase_q(s, D, ws, info, nblk, DIM_N);
     }
     {
@@ -585,6 +586,31 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
 constexpr int MAX_SPLIT = 4;
 std::mutex g_smu;
 int g_split = 4;
+
+// Launch shape of a call: streams the batch is split over and resident
+// work-groups per CU of the reduction matvec.  x2c_autotune times the
+// candidates on the caller's batch and keeps the fastest per batch class
+// (options and block sizes); other batches take the defaults.
+struct Tune {
+  int ways, mv_res;
+};
+constexpr int MV_RES_DEFAULT = 8;
+std::map<std::vector<int64_t>, Tune> g_tunes;   // guarded by g_smu
+
+std::vector<int64_t> tune_key(const x2c_options* o, const Layout& L) {
+  std::vector<int64_t> k = {o->mode, o->prec, o->ozaki_slices, o->reduction};
+  for (const BlockDesc& d : L.desc) k.push_back(d.N);
+  return k;
+}
+// caller holds g_smu
+Tune tune_locked(const x2c_options* o, const Layout& L) {
+  auto it = g_tunes.find(tune_key(o, L));
+  return it != g_tunes.end() ? it->second : Tune{g_split, MV_RES_DEFAULT};
+}
+Tune tune_for(const x2c_options* o, const Layout& L) {
+  std::lock_guard<std::mutex> lk(g_smu);
+  return tune_locked(o, L);
+}
 struct AuxStreams {
   hipStream_t capture = nullptr;
   hipStream_t aux[MAX_SPLIT - 1] = {};
@@ -630,15 +656,16 @@ int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S
   if (hipMemcpyAsync(ws + L.desc_off, src, L.desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, s) !=
       hipSuccess)
     return X2C_EHIP;
+  std::unique_lock<std::mutex> lk(g_smu);
+  const Tune tn = tune_locked(o, L);
   auto run = [&](int b0, int nb, hipStream_t st) {
     if (o->mode == X2C_TWOCOMP)
       return run_stages<cplx>(o, L, b0, nb, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
-                              static_cast<double*>(Ro), info + b0, ws, st);
+                              static_cast<double*>(Ro), info + b0, ws, st, tn.mv_res);
     return run_stages<double>(o, L, b0, nb, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
-                              static_cast<double*>(Ro), info + b0, ws, st);
+                              static_cast<double*>(Ro), info + b0, ws, st, tn.mv_res);
   };
-  std::unique_lock<std::mutex> lk(g_smu);
-  const int ways = std::min(g_split, nblk);
+  const int ways = std::min(tn.ways, nblk);
   AuxStreams* as = (allow_split && ways >= 2) ? device_streams() : nullptr;
   if (!as) {
     lk.unlock();
@@ -677,10 +704,6 @@ int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S
   return rc;
 }
 
-int split_ways() {
-  std::lock_guard<std::mutex> lk(g_smu);
-  return g_split;
-}
 
 // Picture change of a property, per block:
 //   P~ = R^H [P_LL + P_LS X + X^H P_SL + X^H P_SS X] R   (Eq. utrans)
@@ -768,9 +791,10 @@ int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
   std::memcpy(&cbits, &o->c, sizeof(cbits));
   int dev = 0;
   (void)hipGetDevice(&dev);
+  const Tune tn = tune_for(o, *L);
   const std::vector<int64_t> key = {as_key(L.get()), as_key(S), as_key(T), as_key(V), as_key(W), as_key(h),
                                     as_key(eps), as_key(Xo), as_key(Ro), as_key(info), as_key(ws), o->mode,
-                                    o->prec, o->ozaki_slices, o->reduction, cbits, dev, split_ways()};
+                                    o->prec, o->ozaki_slices, o->reduction, cbits, dev, tn.ways, tn.mv_res};
   std::shared_ptr<GraphRec> rec;
   auto it = g_graphs.find(key);
   if (it != g_graphs.end()) {
@@ -939,10 +963,86 @@ void x2c_release(void) {
     std::lock_guard<std::mutex> lk(g_gmu);
     g_graphs.clear();
   }
+  {
+    std::lock_guard<std::mutex> lk(g_smu);
+    g_tunes.clear();
+  }
   std::lock_guard<std::mutex> lk(g_tmu);
   trace_collect();
   for (hipEvent_t e : g_pool) hipEventDestroy(e);
   g_pool.clear();
+}
+
+int x2c_autotune(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off, const double* S,
+                 const double* T, const double* V, const double* W, const int64_t* h_off, void* h,
+                 const int64_t* eps_off, double* eps, int* info, void* workspace, size_t ws_bytes, void* stream,
+                 int reps, int* ways_out, int* mv_res_out) {
+  if (!valid_opts(opts) || nblk <= 0 || !N || !in_off || !h_off || !eps_off || !info || !S || !T || !V || !W ||
+      !h || !eps || !workspace || reps < 1 || reps > 100)
+    return X2C_EINVAL;
+  std::shared_ptr<Layout> L = get_plan(opts, nblk, N, in_off, h_off, eps_off);
+  if (!L) return X2C_EINVAL;
+  if (ws_bytes < L->total) return X2C_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const std::vector<int64_t> key = tune_key(opts, *L);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return X2C_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return X2C_EHIP;
+  }
+  auto set = [&](Tune t) {
+    std::lock_guard<std::mutex> lk(g_smu);
+    g_tunes[key] = t;
+  };
+  bool had;
+  Tune prev;
+  {
+    std::lock_guard<std::mutex> lk(g_smu);
+    had = g_tunes.count(key) != 0;
+    prev = tune_locked(opts, *L);
+  }
+  Tune best = prev;
+  float best_ms = 0.0f;
+  bool have = false;
+  int rc = X2C_OK;
+  static const int kRes[] = {4, MV_RES_DEFAULT};
+  for (int ways = 1; ways <= MAX_SPLIT && rc == X2C_OK; ++ways) {
+    if (ways > 1 && ways > nblk) break;
+    for (int res : kRes) {
+      const Tune cand{ways, res};
+      set(cand);
+      // one untimed call (captures the candidate's graph), then reps timed ones
+      rc = enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, nullptr, nullptr, info, workspace,
+                   ws_bytes, s, nullptr);
+      if (rc == X2C_OK && hipEventRecord(e0, s) != hipSuccess) rc = X2C_EHIP;
+      for (int r = 0; r < reps && rc == X2C_OK; ++r)
+        rc = enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, nullptr, nullptr, info, workspace,
+                     ws_bytes, s, nullptr);
+      if (rc == X2C_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        rc = X2C_EHIP;
+      float ms = 0.0f;
+      if (rc == X2C_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = X2C_EHIP;
+      if (rc != X2C_OK) break;
+      if (!have || ms < best_ms) {
+        best = cand;
+        best_ms = ms;
+        have = true;
+      }
+    }
+  }
+  if (rc == X2C_OK || had) {
+    set(rc == X2C_OK ? best : prev);
+  } else {
+    std::lock_guard<std::mutex> lk(g_smu);
+    g_tunes.erase(key);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != X2C_OK) return rc;
+  if (ways_out) *ways_out = best.ways;
+  if (mv_res_out) *mv_res_out = best.mv_res;
+  return X2C_OK;
 }
 
 int x2c_stream_split(int ways) {

@@ -57,7 +57,8 @@ void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, 
 
 template <class T>
 void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
-                     int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS, int bufET);
+                     int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS, int bufET,
+                     int mv_res = 8);
 template <class T>
 void launch_ormtr_blocked(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim,
                           int maxcols, int dsel, int bufA, int bufTau, int bufTf, int bufY, int csel);

@@ -62,10 +62,11 @@ __device__ inline T panel_v(const T* A, int nr, int k0, int r, int a) {
 
 // Hermitian matvec y = A[k+1:, k+1:] v_k of the reduction step k over the
 // whole batch (k_matvec.hip); partial sums into bufHS in the layout the
-// column kernel reads.
+// column kernel reads.  mv_res: resident one-wave work-groups per CU of the
+// quaternion kernel's persistent grid (1..8).
 template <class T>
 void launch_matvec(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int dsel, int bufA,
-                   int bufV, int bufHS, int bufW, int k0, int k, int nsmax, int ncu, hipEvent_t ev0 = nullptr,
-                   hipEvent_t ev1 = nullptr);
+                   int bufV, int bufHS, int bufW, int k0, int k, int nsmax, int ncu, int mv_res,
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 }  // namespace x2c

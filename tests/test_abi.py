@@ -88,6 +88,16 @@ def test_null_arguments_rejected_without_gpu_work():
     rc = lib.x2c_picture_change(ctypes.byref(opt), 1, N.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                 off.ctypes.data_as(P), None, None, None, None, None, None, None, None, 0, None)
     assert rc == px.EINVAL
+    rc = lib.x2c_autotune(ctypes.byref(opt), 1, N.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                          off.ctypes.data_as(P), None, None, None, None, off.ctypes.data_as(P), None,
+                          off.ctypes.data_as(P), None, None, None, 0, None, 3, None, None)
+    assert rc == px.EINVAL
+    # reps out of range is rejected before the batch is looked at
+    fake = ctypes.c_void_p(16)
+    rc = lib.x2c_autotune(ctypes.byref(opt), 1, N.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                          off.ctypes.data_as(P), fake, fake, fake, fake, off.ctypes.data_as(P), fake,
+                          off.ctypes.data_as(P), fake, fake, fake, 0, None, 0, None, None)
+    assert rc == px.EINVAL
     # empty batch is a no-op
     rc = lib.x2c_build_batched(ctypes.byref(opt), 0, N.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                off.ctypes.data_as(P), None, None, None, None, off.ctypes.data_as(P), None,

@@ -346,6 +346,31 @@ def test_stream_split_matches_one_stream(ways):
         px.stream_split(prev)
 
 
+def test_autotune_keeps_results():
+    """x2c_autotune times every launch shape on the batch and keeps the
+    fastest for the batch's class: its outputs, and those of later calls
+    with the tuned shape, are bitwise those of the default shape."""
+    px, torch = _px()
+    blocks = [atom_block(z) for z in (8, 47, 29, 6, 17, 47)]
+    ref = gpu_batched(blocks, True)
+    pk = pack_blocks(blocks, True)
+    bt = px.batch_to_device(pk, True)
+    try:
+        print("  x2c_autotune nblk=6 twocomp=True reps=1", flush=True)
+        (ways, res), (h, eps, info), ws = px.autotune(bt, C_LIGHT, reps=1)
+        torch.cuda.synchronize()
+        assert 1 <= ways <= 4 and res in (4, 8)
+        assert np.array_equal(info.cpu().numpy(), ref[2])
+        for a, b in zip(ref[0], px.unpack_h(h.cpu().numpy(), bt.Ns, True)):
+            assert np.array_equal(a, b)
+        got = gpu_batched(blocks, True)     # runs with the tuned shape
+        for a, b in zip(ref[0] + ref[1], got[0] + got[1]):
+            assert np.array_equal(a, b)
+    finally:
+        torch.cuda.synchronize()
+        px.release()
+
+
 def test_determinism_two_calls():
     blocks = [atom_block(z) for z in (6, 47)]
     a = gpu_batched(blocks, True)
