@@ -250,7 +250,8 @@ int x2c_graph_enable(int on);
  * streams of the library, forked from and joined back into the caller's
  * stream with events (captured graphs contain every branch).  ways = 1: one
  * stream.  Results are identical either way; calls made while tracing is
- * enabled use one stream.  Other values leave the setting unchanged.
+ * enabled use one stream.  Other values leave the setting unchanged.  A
+ * batch class tuned by x2c_autotune uses its tuned split instead.
  * Returns the previous setting.
  */
 int x2c_stream_split(int ways);
