@@ -425,13 +425,17 @@ __global__ void k_filter_factor(const BlockDesc* D, char* ws, const int* info, i
 // q = g, g + G, ... and accumulates into its own real m x n partial (group 0
 // also holds T_s E); k_filter_finish adds the G partials in a fixed order.
 // Each solve is a forward elimination and a backward substitution along the
-// rows.  The forward sweep keeps only its state at every FK-th row
-// (checkpoints); the backward sweep re-runs the forward recurrence over one
-// chunk of FK rows from its checkpoint, in registers, and then substitutes
-// back through the chunk, so the per-row solve values never go to memory.
-// Partials: in the T-typed output when T is real and G = 1, else in C_TMP
-// (free at this point); checkpoints in Z_SCR.
-constexpr int FK = 16;
+// rows.  The forward sweeps (the pole's factors staged in LDS) keep only
+// their state at every FK-th row (checkpoints, per pole); the backward pass
+// then walks the rows in chunks of FK from the bottom: the chunk's factors
+// of every pole of the group are staged in LDS, and every pole re-runs its
+// forward recurrence from the checkpoint in registers and substitutes back
+// through the chunk, adding a_q Re(x) to the chunk's accumulator in pole
+// order.  The accumulator is written once per chunk; the substitution
+// carries of each pole wait in Z_SCR between chunks.  Partials: in the
+// T-typed output when T is real and G = 1, else in C_TMP (free at this
+// point); checkpoints and carries in Z_SCR.
+constexpr int FK = FILTER_CK;
 
 template <class T>
 __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* ws, const int* info, int kramers,
@@ -447,33 +451,27 @@ __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* 
   const double sigma = pf[0], rho = pf[1];
   const int r = (int)pf[3];
   if (g >= r) return;
+  const int nq = (r - g + G - 1) / G;             // poles g, g + G, ... of this group
   const double* dg = bufp<double>(ws, d, V_D);
   const double* eg = bufp<double>(ws, d, V_E);
   double* accb = (sizeof(T) == sizeof(double) && G == 1) ? reinterpret_cast<double*>(bufp<T>(ws, d, C_Y))
                                                          : bufp<double>(ws, d, C_TMP);
   double* acc = accb + (long long)g * m * n;
   const int nck = (m + FK - 1) / FK;
-  cplx* ck = bufp<cplx>(ws, d, Z_SCR) + (long long)g * nck * n;
+  cplx* ckb = bufp<cplx>(ws, d, Z_SCR);                    // [pole][chunk][column]
+  cplx* xs = ckb + (long long)RMAX * nck * n;              // [pole][column][2]
+  const cplx* Fb = bufp<cplx>(ws, d, F_FAC);
   const double ir = 1.0 / rho;
-  if (g == 0) {
-    // acc = T_s E_j
-    for (int i = 0; active && i < m; ++i) {
-      double t = (dg[i] - sigma) * hash_uniform(i, j);
-      if (i > 0) t += eg[i - 1] * hash_uniform(i - 1, j);
-      if (i < m - 1) t += eg[i] * hash_uniform(i + 1, j);
-      acc[(long long)i * n + j] = t * ir;
-    }
-  }
-  extern __shared__ cplx Fs[];          // the current pole's factors, m x 5
-  bool fresh = g > 0;                   // partial not yet written
+  extern __shared__ cplx Fs[];          // one pole's factors (m x 5), or a chunk of every pole's (nq x FK x 5)
+  // forward: y = L^-1 P b for every pole of the group; only the running
+  // carry at rows 0, FK, ... is kept
   for (int q = g; q < r; q += G) {
-    const cplx* F = bufp<cplx>(ws, d, F_FAC) + (long long)q * m * 5;
-    const double aq = pf[4 + q];
+    const cplx* F = Fb + (long long)q * m * 5;
     __syncthreads();
     for (int e = threadIdx.x; e < m * 5; e += blockDim.x) Fs[e] = F[e];
     __syncthreads();
     if (active) {
-      // forward: y = L^-1 P b; only the running carry at rows 0, FK, ... is kept
+      cplx* ck = ckb + (long long)q * nck * n;
       cplx carry = {hash_uniform(0, j), 0.0};
       for (int i = 0; i < m; ++i) {
         if (i % FK == 0) ck[(long long)(i / FK) * n + j] = carry;
@@ -482,45 +480,73 @@ __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* 
         const cplx bnext = {hash_uniform(i + 1, j), 0.0};
         carry = f[4].x != 0.0 ? carry - f[0] * bnext : bnext - f[0] * carry;
       }
-      // backward: U x = y;  acc += a_q Re(x), one chunk of FK rows at a time
-      cplx x1 = {0.0, 0.0}, x2 = {0.0, 0.0};
-      for (int c = nck - 1; c >= 0; --c) {
-        const int i0 = c * FK;
-        cplx cy = ck[(long long)c * n + j];
-        double ab[FK];
+      xs[((long long)q * n + j) * 2] = {0.0, 0.0};
+      xs[((long long)q * n + j) * 2 + 1] = {0.0, 0.0};
+    }
+  }
+  // backward: U x = y chunk by chunk; acc = [T_s E (group 0)] + sum_q a_q Re(x)
+  for (int c = nck - 1; c >= 0; --c) {
+    const int i0 = c * FK;
+    __syncthreads();
+    for (int e = threadIdx.x; e < nq * FK * 5; e += blockDim.x) {
+      const int qi = e / (FK * 5), w = e - qi * FK * 5, i = i0 + w / 5;
+      Fs[e] = i < m ? Fb[((long long)(g + G * qi) * m + i) * 5 + w % 5] : cplx{0.0, 0.0};
+    }
+    __syncthreads();
+    if (!active) continue;
+    double ab[FK];
 #pragma unroll
-        for (int u = 0; u < FK; ++u) {
-          const int i = min(i0 + u, m - 1);
-          ab[u] = fresh ? 0.0 : acc[(long long)i * n + j];
-        }
-        cplx yb[FK];
+    for (int u = 0; u < FK; ++u) {
+      const int i = i0 + u;
+      double t = 0.0;
+      if (g == 0 && i < m) {
+        t = (dg[i] - sigma) * hash_uniform(i, j);
+        if (i > 0) t += eg[i - 1] * hash_uniform(i - 1, j);
+        if (i < m - 1) t += eg[i] * hash_uniform(i + 1, j);
+        t = t * ir;
+      }
+      ab[u] = t;
+    }
+    for (int qi = 0; qi < nq; ++qi) {
+      const int q = g + G * qi;
+      const cplx* Fc = Fs + qi * FK * 5;
+      const double aq = pf[4 + q];
+      cplx* xq = xs + ((long long)q * n + j) * 2;
+      cplx x1 = xq[0], x2 = xq[1];
+      cplx cy = ckb[((long long)q * nck + c) * n + j];
+      cplx yb[FK];
 #pragma unroll
-        for (int u = 0; u < FK; ++u) {
-          const int i = i0 + u;
-          yb[u] = cy;
-          if (i < m - 1) {
-            const cplx* f = Fs + i * 5;
-            const cplx bnext = {hash_uniform(i + 1, j), 0.0};
-            const bool sw = f[4].x != 0.0;
-            yb[u] = sw ? bnext : cy;
-            cy = sw ? cy - f[0] * bnext : bnext - f[0] * cy;
-          }
-        }
-#pragma unroll
-        for (int u = FK - 1; u >= 0; --u) {
-          const int i = i0 + u;
-          if (i < m) {
-            const cplx* f = Fs + i * 5;
-            const cplx t = yb[u] - f[2] * x1 - f[3] * x2;
-            const cplx x = t * f[1];
-            acc[(long long)i * n + j] = ab[u] + aq * x.x;
-            x2 = x1;
-            x1 = x;
-          }
+      for (int u = 0; u < FK; ++u) {
+        const int i = i0 + u;
+        yb[u] = cy;
+        if (i < m - 1) {
+          const cplx* f = Fc + u * 5;
+          const cplx bnext = {hash_uniform(i + 1, j), 0.0};
+          const bool sw = f[4].x != 0.0;
+          yb[u] = sw ? bnext : cy;
+          cy = sw ? cy - f[0] * bnext : bnext - f[0] * cy;
         }
       }
+#pragma unroll
+      for (int u = FK - 1; u >= 0; --u) {
+        const int i = i0 + u;
+        if (i < m) {
+          const cplx* f = Fc + u * 5;
+          const cplx t = yb[u] - f[2] * x1 - f[3] * x2;
+          const cplx x = t * f[1];
+          ab[u] = ab[u] + aq * x.x;
+          x2 = x1;
+          x1 = x;
+        }
+      }
+      xq[0] = x1;
+      xq[1] = x2;
     }
-    fresh = false;
+#pragma unroll
+    for (int u = 0; u < FK; ++u) {
+      const int i = i0 + u;
+      if (i < m) acc[(long long)i * n + j] = ab[u];
+    }
   }
 }
 
@@ -758,7 +784,8 @@ template <class T>
 void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxrhs,
                          int kramers) {
   const int maxm = kramers ? maxrhs * 2 : 2 * maxrhs;      // rows of the tridiagonal
-  const size_t shm = (size_t)maxm * 5 * sizeof(cplx);
+  const int Gs = kramers ? 4 : 1;
+  const size_t shm = std::max((size_t)maxm, (size_t)((RMAX + Gs - 1) / Gs) * FK) * 5 * sizeof(cplx);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter_solve<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shm);
   // pole groups: the quaternion form has room for four partials in C_TMP

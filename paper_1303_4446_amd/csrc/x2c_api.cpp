@@ -56,7 +56,9 @@ void block_sizes(int N, bool tc, size_t sz[NBUF]) {
   for (int i = C_S; i <= C_TMP2; ++i) sz[i] = n * n * es;
   sz[C_A] = m * m * es;
   sz[C_Y] = m * n * es;
-  sz[Z_SCR] = m * n * 16;
+  // projector solves: checkpoints of every pole (RMAX x chunks x n) and two
+  // substitution carries per pole and column (complex)
+  sz[Z_SCR] = std::max(m * n, (size_t)RMAX * ((m + FILTER_CK - 1) / FILTER_CK) * n + 2 * (size_t)RMAX * n) * 16;
   sz[V_D] = m * 8;
   sz[V_E] = m * 8;
   sz[V_TAU] = m * es;

@@ -153,6 +153,7 @@ enum Buf : int {
 };
 
 constexpr int RMAX = 48;   // max Zolotarev pole pairs
+constexpr int FILTER_CK = 16;   // rows per checkpoint chunk of the projector solves
 constexpr int QMAX = 64;   // max quadrature nodes for the inverse square root
 // P_FILT layout (doubles): [0]=sigma [1]=rho [2]=M [3]=r [4..4+RMAX)=a_j [4+RMAX..4+2RMAX)=beta_j
 constexpr int PF_SIZE = 4 + 2 * RMAX;
