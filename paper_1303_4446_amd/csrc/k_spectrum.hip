@@ -425,16 +425,16 @@ __global__ void k_filter_factor(const BlockDesc* D, char* ws, const int* info, i
 // q = g, g + G, ... and accumulates into its own real m x n partial (group 0
 // also holds T_s E); k_filter_finish adds the G partials in a fixed order.
 // Each solve is a forward elimination and a backward substitution along the
-// rows.  The forward sweeps (the pole's factors staged in LDS) keep only
-// their state at every FK-th row (checkpoints, per pole); the backward pass
-// then walks the rows in chunks of FK from the bottom: the chunk's factors
-// of every pole of the group are staged in LDS, and every pole re-runs its
-// forward recurrence from the checkpoint in registers and substitutes back
-// through the chunk, adding a_q Re(x) to the chunk's accumulator in pole
-// order.  The accumulator is written once per chunk; the substitution
-// carries of each pole wait in Z_SCR between chunks.  Partials: in the
-// T-typed output when T is real and G = 1, else in C_TMP (free at this
-// point); checkpoints and carries in Z_SCR.
+// rows, both taken in chunks of FK rows with the chunk's factors of every
+// pole of the group staged in LDS and the chunk's entries of E drawn once
+// for all poles.  The forward pass (chunks from the top) keeps each pole's
+// state at every FK-th row (checkpoints); the backward pass (chunks from the
+// bottom) re-runs every pole's forward recurrence over the chunk from its
+// checkpoint in registers and substitutes back through the chunk, adding
+// a_q Re(x) to the chunk's accumulator in pole order, which is written once
+// per chunk.  Between chunks the carries of each pole wait in Z_SCR.
+// Partials: in the T-typed output when T is real and G = 1, else in C_TMP
+// (free at this point); checkpoints and carries in Z_SCR.
 constexpr int FK = FILTER_CK;
 
 template <class T>
@@ -462,47 +462,73 @@ __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* 
   cplx* xs = ckb + (long long)RMAX * nck * n;              // [pole][column][2]
   const cplx* Fb = bufp<cplx>(ws, d, F_FAC);
   const double ir = 1.0 / rho;
-  extern __shared__ cplx Fs[];          // one pole's factors (m x 5), or a chunk of every pole's (nq x FK x 5)
-  // forward: y = L^-1 P b for every pole of the group; only the running
-  // carry at rows 0, FK, ... is kept
-  for (int q = g; q < r; q += G) {
-    const cplx* F = Fb + (long long)q * m * 5;
-    __syncthreads();
-    for (int e = threadIdx.x; e < m * 5; e += blockDim.x) Fs[e] = F[e];
-    __syncthreads();
-    if (active) {
-      cplx* ck = ckb + (long long)q * nck * n;
-      cplx carry = {hash_uniform(0, j), 0.0};
-      for (int i = 0; i < m; ++i) {
-        if (i % FK == 0) ck[(long long)(i / FK) * n + j] = carry;
-        if (i == m - 1) break;
-        const cplx* f = Fs + i * 5;
-        const cplx bnext = {hash_uniform(i + 1, j), 0.0};
-        carry = f[4].x != 0.0 ? carry - f[0] * bnext : bnext - f[0] * carry;
-      }
-      xs[((long long)q * n + j) * 2] = {0.0, 0.0};
-      xs[((long long)q * n + j) * 2 + 1] = {0.0, 0.0};
-    }
-  }
-  // backward: U x = y chunk by chunk; acc = [T_s E (group 0)] + sum_q a_q Re(x)
-  for (int c = nck - 1; c >= 0; --c) {
-    const int i0 = c * FK;
+  extern __shared__ cplx Fs[];          // a chunk of rows of every pole's factors (nq x FK x 5)
+  // the chunk's factors of every pole of the group into LDS (all threads)
+  auto stage = [&](int i0) {
     __syncthreads();
     for (int e = threadIdx.x; e < nq * FK * 5; e += blockDim.x) {
       const int qi = e / (FK * 5), w = e - qi * FK * 5, i = i0 + w / 5;
       Fs[e] = i < m ? Fb[((long long)(g + G * qi) * m + i) * 5 + w % 5] : cplx{0.0, 0.0};
     }
     __syncthreads();
+  };
+  // forward: y = L^-1 P b for every pole of the group, chunk by chunk from
+  // the top; the carry at rows 0, FK, ... is kept (checkpoints), and between
+  // chunks it waits in the carry slot of the pole.  E's entries of a chunk
+  // are drawn once for all poles.
+  for (int c = 0; c < nck; ++c) {
+    const int i0 = c * FK;
+    stage(i0);
     if (!active) continue;
+    double hb[FK];                      // E_{i+1, j} for the chunk's rows i
+#pragma unroll
+    for (int u = 0; u < FK; ++u) hb[u] = i0 + u + 1 < m ? hash_uniform(i0 + u + 1, j) : 0.0;
+    for (int qi = 0; qi < nq; ++qi) {
+      const int q = g + G * qi;
+      const cplx* Fc = Fs + qi * FK * 5;
+      cplx* xq = xs + ((long long)q * n + j) * 2;
+      cplx carry = c == 0 ? cplx{hash_uniform(0, j), 0.0} : xq[0];
+      ckb[((long long)q * nck + c) * n + j] = carry;
+#pragma unroll
+      for (int u = 0; u < FK; ++u) {
+        const int i = i0 + u;
+        if (i < m - 1) {
+          const cplx* f = Fc + u * 5;
+          const cplx bnext = {hb[u], 0.0};
+          carry = f[4].x != 0.0 ? carry - f[0] * bnext : bnext - f[0] * carry;
+        }
+      }
+      if (c == nck - 1) {
+        xq[0] = {0.0, 0.0};             // the backward substitution starts from zero
+        xq[1] = {0.0, 0.0};
+      } else {
+        xq[0] = carry;
+      }
+    }
+  }
+  // backward: U x = y chunk by chunk from the bottom; every pole re-runs its
+  // forward recurrence over the chunk from the checkpoint in registers and
+  // substitutes back; acc = [T_s E (group 0)] + sum_q a_q Re(x), written once
+  // per chunk
+  for (int c = nck - 1; c >= 0; --c) {
+    const int i0 = c * FK;
+    stage(i0);
+    if (!active) continue;
+    double he[FK + 2];                  // E_{i, j} for i = i0 - 1 .. i0 + FK
+#pragma unroll
+    for (int v = 0; v < FK + 2; ++v) {
+      const int i = i0 - 1 + v;
+      he[v] = (i >= 0 && i < m) ? hash_uniform(i, j) : 0.0;
+    }
     double ab[FK];
 #pragma unroll
     for (int u = 0; u < FK; ++u) {
       const int i = i0 + u;
       double t = 0.0;
       if (g == 0 && i < m) {
-        t = (dg[i] - sigma) * hash_uniform(i, j);
-        if (i > 0) t += eg[i - 1] * hash_uniform(i - 1, j);
-        if (i < m - 1) t += eg[i] * hash_uniform(i + 1, j);
+        t = (dg[i] - sigma) * he[u + 1];
+        if (i > 0) t += eg[i - 1] * he[u];
+        if (i < m - 1) t += eg[i] * he[u + 2];
         t = t * ir;
       }
       ab[u] = t;
@@ -521,7 +547,7 @@ __global__ void __launch_bounds__(256) k_filter_solve(const BlockDesc* D, char* 
         yb[u] = cy;
         if (i < m - 1) {
           const cplx* f = Fc + u * 5;
-          const cplx bnext = {hash_uniform(i + 1, j), 0.0};
+          const cplx bnext = {he[u + 2], 0.0};
           const bool sw = f[4].x != 0.0;
           yb[u] = sw ? bnext : cy;
           cy = sw ? cy - f[0] * bnext : bnext - f[0] * cy;
@@ -785,7 +811,7 @@ void launch_filter_solve(hipStream_t s, const BlockDesc* D, char* ws, const int*
                          int kramers) {
   const int maxm = kramers ? maxrhs * 2 : 2 * maxrhs;      // rows of the tridiagonal
   const int Gs = kramers ? 4 : 1;
-  const size_t shm = std::max((size_t)maxm, (size_t)((RMAX + Gs - 1) / Gs) * FK) * 5 * sizeof(cplx);
+  const size_t shm = (size_t)((RMAX + Gs - 1) / Gs) * FK * 5 * sizeof(cplx);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter_solve<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shm);
   // pole groups: the quaternion form has room for four partials in C_TMP
