@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws
 // The n positive-energy eigenvalues (indices n .. 2n-1 of the m = 2n), eps
 // ascending, by multisection; grid = (chunks of EPW eigenvalues, blocks).
 // kramers = 1: each eigenvalue is written twice (the Kramers pair).
-constexpr int EPW = 48;
+constexpr int EPW = 64;
 
 __global__ void __launch_bounds__(256) k_tri_eps4c(const BlockDesc* D, char* ws, const int* info, double* eps,
                                                    int kramers) {

@@ -440,17 +440,17 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
   }
   if constexpr (is_quat<T>()) {
     __shared__ T sh_betaq;
-    make_reflector_q(A, n, k, v, &sh_tau, &sh_betaq, red, phase != 0 ? acol + 1 : nullptr);
+    make_reflector_q(A, n, k, vg, &sh_tau, &sh_betaq, red, phase != 0 ? acol + 1 : nullptr);
     if (tid == 0) {
       ee[k] = sqrt(abs2(sh_betaq));
       bufp<T>(ws, d, bufET)[k] = sh_betaq;
     }
   } else {
-    make_reflector<T>(A, n, k, v, &sh_tau, &sh_beta, red, phase != 0 ? acol + 1 : nullptr);
+    make_reflector<T>(A, n, k, vg, &sh_tau, &sh_beta, red, phase != 0 ? acol + 1 : nullptr);
     if (tid == 0) ee[k] = sh_beta;
   }
-  const int len = n - k - 1;
-  for (int r = tid; r < len; r += COLT) vg[r] = v[r];
+  // the reflector went straight to the global vector (the old one was read
+  // into LDS before the first barrier)
   if (tid == 0) {
     dd[k] = re(A[(long long)k * n + k]);
     taus[k] = sh_tau;
