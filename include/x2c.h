@@ -95,7 +95,8 @@ enum {
   X2C_INFO_OK = 0,
   X2C_INFO_S_NOT_SPD = 1,    /* Cholesky of S failed */
   X2C_INFO_T_NOT_SPD = 2,    /* Cholesky of T failed */
-  X2C_INFO_EIGEN = 3,        /* positive-energy subspace degenerate (singular large-component block) */
+  X2C_INFO_EIGEN = 3,        /* positive-energy subspace not resolved: singular large-component block,
+                                or the gap at -c^2 too narrow for the spectral projector */
   X2C_INFO_BRANCH = 4,       /* number of eigenvalues with eps + c^2 > 0 differs from n */
   X2C_INFO_RENORM = 5,       /* L_S^-1 S~ L_S^-H not positive definite */
   X2C_INFO_NONFINITE = 6     /* NaN or Inf in S, T, V or W */
@@ -232,7 +233,7 @@ void x2c_release(void);
 
 /*
  * Graph replay of x2c_build / x2c_build_batched / x2c_build_batched_xr
- * (Sec. III.A batching: all blocks of a batch advance stage by stage).  When
+ * (library infrastructure: all blocks of a batch advance stage by stage).  When
  * on (the default), the first call with a given combination of block sizes,
  * offsets, options and device pointers captures its whole launch sequence
  * into a HIP graph (on a private stream of the library); later calls with the
@@ -243,8 +244,8 @@ void x2c_release(void);
 int x2c_graph_enable(int on);
 
 /*
- * Multi-stream execution of a batch (Sec. III.A: the per-block problems are
- * independent).  ways in 2..4 (default 4): a call with two or more blocks
+ * Multi-stream execution of a batch (library infrastructure; the per-block
+ * problems are independent).  ways in 2..4 (default 4): a call with two or more blocks
  * cuts the batch into min(ways, blocks) parts of about equal work (sum of
  * N^3); the first part runs on the caller's stream, the others on auxiliary
  * streams of the library, forked from and joined back into the caller's
@@ -257,7 +258,7 @@ int x2c_graph_enable(int on);
 int x2c_stream_split(int ways);
 
 /*
- * Autotuning of the launch shape of a batch class (Sec. III.A batching).
+ * Autotuning of the launch shape of a batch class (library infrastructure).
  * Runs x2c_build_batched on the caller's batch (same arguments, same
  * outputs written) once untimed and `reps` times timed, for every candidate
  * shape: the batch split over 1..4 streams (as x2c_stream_split) times 4 or 8

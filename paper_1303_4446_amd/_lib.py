@@ -20,7 +20,7 @@ FP64, SPLIT_BF16, SPLIT_INT8 = 0, 1, 2
 RED_QUATERNION, RED_COMPLEX = 0, 1
 
 OK, EINVAL, EHIP, EBLOCK = 0, -1, -2, -3
-INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subspace degenerate",
+INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subspace not resolved",
               4: "positive-energy branch size != n", 5: "renormalisation matrix not PD", 6: "non-finite input"}
 
 EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_build_batched_xr",

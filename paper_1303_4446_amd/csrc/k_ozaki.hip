@@ -10,11 +10,15 @@
 // are cut the same way with their own exponents.  Every q_s is an integer of
 // magnitude <= 128, exact in bf16, so each bf16 product q_a q_b is exact and
 // a sum of up to 2^24 / (S 2^14) such products is exact in the FP32
-// accumulator of the matrix core.  Slice pairs (a, b) with a + b = g share
-// the weight 2^-7g; the pairs with g <= S + 1 are kept (the rest lie below
-// the truncation of the operands), accumulated exactly per g over 128 terms
-// of the inner dimension and folded into FP64 accumulators, which carry the
-// result.  Rounding therefore only happens in FP64.
+// accumulator of the matrix core.  With the slices numbered s = 1..S
+// (weight 2^-7s; |slice 1| <= 1, |slice s| <= 2^(6-7s) after it), slice pairs
+// (a, b) with a + b = g share the weight 2^-7g; the pairs with g <= S + 1
+// are kept (in the 0-based loop indices: sa + sb <= S - 1), accumulated
+// exactly per g over 128 terms of the inner dimension and folded into FP64
+// accumulators, which carry the result.  The dropped pairs (g >= S + 2) add
+// at most about (S - 1) 2^(-7S) per inner-dimension term, relative to the
+// product of the row and column maxima: the size of the operands' own
+// truncation.  Rounding therefore only happens in FP64.
 //
 // Complex operands use the real form with interleaved real / imaginary parts:
 // row 2i of A' is (Re a_ik, -Im a_ik) over k, row 2i+1 is (Im a_ik, Re a_ik),

@@ -6,9 +6,13 @@
 // so the scaled line lies in (-1/2, 1/2)) and cut into S slices
 // y <- 128 y, q_s = rint(y), y <- y - q_s, |q_s| <= 64.  The operands are
 // split once per product into int8 arrays (K contiguous, K padded to 64);
-// the product kernel forms every slice pair (a, b) with a + b = g <= S + 1 on
-// v_mfma_i32_32x32x32_i8, one int32 accumulator per g (|sum| <= S K 2^12,
-// exact for K < 2^16), and folds them into FP64 at the end.
+// the product kernel forms every slice pair (a, b) with a + b = g <= S + 1
+// (slices numbered s = 1..S, weight 2^-7s; in the 0-based loop indices
+// sa + sb <= S - 1) on v_mfma_i32_32x32x32_i8, one int32 accumulator per g
+// (|sum| <= S K 2^12, exact for K < 2^16), and folds them into FP64 at the
+// end.  The dropped pairs (g >= S + 2) add at most about (S - 1) 2^(-7S - 2)
+// per inner-dimension term relative to the product of the line maxima, the
+// size of the operands' own truncation.
 //
 // Complex operands: the real form has rows 2i (Re) and 2i+1 (Im) and a K
 // axis of two halves (real parts, then imaginary parts):

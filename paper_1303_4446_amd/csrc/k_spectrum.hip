@@ -247,6 +247,10 @@ __global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws
   // 16 counts per eigenvalue and step: a few more steps, far fewer counts
   multisect(sd, se2, m, n - 1, 2, lo, hi, piv, lam, cbuf, xbuf, 16);
   constexpr int NCAND = (RMAX - 4) / 2 + 1;
+  // largest accepted sign-approximation error: a leak of relative size e
+  // from the other branch moves X by about e kappa(Y_L), well below the
+  // FP64 forward error of the path for e <= 1e-11
+  constexpr double ZOL_ERR_MAX = 1e-11;
   constexpr int NCV = 2 * NCAND * (NCAND + 3);   // sum over candidates of 2r
   constexpr int NCO = NCAND * (NCAND + 3);       // sum over candidates of r
   __shared__ double zerr[NCAND], zM[NCAND];
@@ -309,6 +313,9 @@ __global__ void __launch_bounds__(1024) k_tri_eig4c(const BlockDesc* D, char* ws
       if (err < 1e-13 || err > 0.5 * prev) break;
       prev = err;
     }
+    // no order reaches the FP64 level: the gap at -c^2 is too narrow relative
+    // to the spectral radius for the projector to separate the two branches
+    if (!(zerr[best] <= ZOL_ERR_MAX)) info[b] = 3;
     const int rbest = 4 + 2 * best;
     pf[0] = sigma;
     pf[1] = rho;

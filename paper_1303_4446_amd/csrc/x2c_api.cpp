@@ -946,7 +946,7 @@ const char* x2c_strerror(int code) {
     case X2C_EBLOCK: return "block failed (see info)";
     case X2C_INFO_S_NOT_SPD: return "overlap matrix S not positive definite";
     case X2C_INFO_T_NOT_SPD: return "kinetic matrix T not positive definite";
-    case X2C_INFO_EIGEN: return "positive-energy subspace degenerate";
+    case X2C_INFO_EIGEN: return "positive-energy subspace not resolved";
     case X2C_INFO_BRANCH: return "positive-energy branch size differs from n";
     case X2C_INFO_RENORM: return "renormalisation matrix not positive definite";
     case X2C_INFO_NONFINITE: return "non-finite input";

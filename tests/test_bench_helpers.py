@@ -87,3 +87,42 @@ def test_committed_profile_is_readable():
     assert 1.0e8 < t < 1.0e9
     v = bench.recorded_traffic("paper_1303_4446_amd/csrc/k_matvec.hip", "profiles/k_tri_matvec_w_ag309_traffic.md")
     assert v is None or v == t
+
+
+@pytest.mark.parametrize("stage", ["tridiag_4c", "tridiag_Q", "backtransform_4c"])
+def test_quaternion_stage_flops_are_half_the_complex_ones(stage):
+    """The quaternion reductions do half the real arithmetic of the complex
+    reductions of the same two-component block; the complex counts are the
+    standard ones ((16/3) d^3 for a complex Hermitian tridiagonalisation of
+    dimension d, 8 d^2 r for applying its reflectors to d x r)."""
+    N = 192
+    q = bench.algorithmic_flops(stage, N, True, "quaternion")
+    cx = bench.algorithmic_flops(stage, N, True, "complex")
+    assert q == pytest.approx(cx / 2, rel=1e-15)
+    m, n = 4 * N, 2 * N
+    ref = {"tridiag_4c": 16 / 3 * m ** 3, "tridiag_Q": 16 / 3 * n ** 3, "backtransform_4c": 8 * m * m * n}[stage]
+    assert cx == pytest.approx(ref, rel=1e-15)
+    # spin-free: real symmetric (4/3) d^3 and 2 d^2 r
+    sf = bench.algorithmic_flops(stage, N, False)
+    ref_sf = {"tridiag_4c": 4 / 3 * (2 * N) ** 3, "tridiag_Q": 4 / 3 * N ** 3,
+              "backtransform_4c": 2 * (2 * N) ** 2 * N}[stage]
+    assert sf == pytest.approx(ref_sf, rel=1e-15)
+
+
+def test_score_reports_both_references_and_pass_flag():
+    """score(): per-eigenvalue distances of the spectrum of a given h against
+    the oracle's X2C spectrum and the 4c spectrum, with the pass flag at
+    1e-8 Eh on bound states."""
+    import oracle
+    from x2c_inputs import C_LIGHT, atom_block
+    import oracle.routes as ox
+    blk = atom_block(6)
+    refs = bench.oracle_references([blk], False, C_LIGHT, [0])
+    h0, e0 = ox.x2c_direct(blk.S, blk.T, blk.V, blk.W[0], C_LIGHT, False)
+    r = bench.score([blk], False, refs, [h0], [e0])
+    assert r["pass"] and r["max_dE_bound_vs_oracle_Eh"] < 1e-10 and r["max_deps_rel"] == 0.0
+    hb = h0 + 1e-6 * blk.S                    # every eigenvalue moves up by 1e-6 Eh
+    r = bench.score([blk], False, refs, [hb], [e0])
+    assert not r["pass"]
+    assert r["max_dE_bound_vs_oracle_Eh"] == pytest.approx(1e-6, rel=1e-3)
+    assert oracle.spectrum_of(hb, blk.S, False)[0] > refs[0]["ex"][0]
