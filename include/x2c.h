@@ -87,7 +87,9 @@ enum {
                        unknown mode/prec/reduction, workspace too small,
                        overlapping layout */
   X2C_EHIP = -2,    /* a HIP runtime call or kernel launch failed */
-  X2C_EBLOCK = -3   /* x2c_build only: the block failed; see its info code */
+  X2C_EBLOCK = -3,  /* x2c_build only: the block failed; see its info code */
+  X2C_ESCRATCH = -4 /* x2c_build_batched_noalloc only: the batch needs more than the
+                       library's static scratch (256 MiB) or has more than 256 blocks */
 };
 
 /* per-block status codes (info) */
@@ -146,6 +148,31 @@ int x2c_build_batched(const x2c_options* opts, int nblk, const int* N, const int
                       const double* S, const double* T, const double* V, const double* W,
                       const int64_t* h_off, void* h, const int64_t* eps_off, double* eps, int* info,
                       void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * x2c_build_batched for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, layout, per-block info and results as
+ * x2c_build_batched (the same kernels, on `stream` only), without the
+ * workspace: the scratch lives in a static device array of the library,
+ * 256 MiB per GPU, allocated when the library's code is first loaded on a
+ * device and held until the process ends.  The batch must fit in it: at
+ * most 256 blocks and x2c_workspace_bytes(opts, nblk, N) minus about
+ * 0.5 KiB per block of descriptors <= 256 MiB (e.g. one block of any
+ * supported size, three two-component blocks of N = 192); otherwise
+ * X2C_ESCRATCH is returned before anything is enqueued.  Nothing is
+ * allocated, copied from the host or cleared with a memset: descriptors go
+ * to the device as kernel arguments, so the call can be captured into a
+ * graph.  Every call on a GPU shares that GPU's scratch, which keeps the
+ * last call's contents (no part of it needs to start at zero): calls that
+ * overlap in time on one GPU (different streams or threads) race and must
+ * be serialised by the caller.  Tracing does not record these calls.
+ * Returns X2C_OK once enqueued, X2C_EINVAL, X2C_ESCRATCH or X2C_EHIP.
+ */
+int x2c_build_batched_noalloc(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off,
+                              const double* S, const double* T, const double* V, const double* W,
+                              const int64_t* h_off, void* h, const int64_t* eps_off, double* eps, int* info,
+                              void* stream);
 
 /*
  * x2c_build_batched that also returns each block's decoupling matrices:

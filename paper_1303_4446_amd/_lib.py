@@ -19,11 +19,12 @@ SPINFREE, TWOCOMP = 1, 2
 FP64, SPLIT_BF16, SPLIT_INT8 = 0, 1, 2
 RED_QUATERNION, RED_COMPLEX = 0, 1
 
-OK, EINVAL, EHIP, EBLOCK = 0, -1, -2, -3
+OK, EINVAL, EHIP, EBLOCK, ESCRATCH = 0, -1, -2, -3, -4
 INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subspace not resolved",
               4: "positive-energy branch size != n", 5: "renormalisation matrix not PD", 6: "non-finite input"}
 
 EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_build_batched_xr",
+            "x2c_build_batched_noalloc",
             "x2c_dlu_workspace_bytes", "x2c_dlu_assemble", "x2c_strerror", "x2c_release", "x2c_graph_enable",
             "x2c_stream_split", "x2c_autotune", "x2c_picture_change", "x2c_trace_enable", "x2c_trace_read",
             "x2c_trace_reset")
@@ -65,6 +66,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.x2c_build_batched.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp,
                                       i64p, vp, i64p, vp, vp, vp, ctypes.c_size_t, vp]
     lib.x2c_build_batched.restype = i32
+    lib.x2c_build_batched_noalloc.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp,
+                                              i64p, vp, i64p, vp, vp, vp]
+    lib.x2c_build_batched_noalloc.restype = i32
     lib.x2c_build_batched_xr.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp,
                                          i64p, vp, i64p, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.x2c_build_batched_xr.restype = i32
@@ -342,6 +346,35 @@ def build_batched(batch: Batch, c: float, prec: int = FP64, slices: int = 0, wor
     if rc != OK:
         raise X2CError(rc, strerror(rc))
     return (h, eps, info), workspace
+
+
+def build_batched_noalloc(batch: Batch, c: float, prec: int = FP64, slices: int = 0, out=None, stream=None,
+                          reduction: int = RED_QUATERNION):
+    """Enqueue x2c_build_batched_noalloc (the library's static scratch instead
+    of a workspace).  Returns (h_flat, eps_flat, info) device tensors; the
+    output tensors are created here unless `out` is given."""
+    torch = _torch()
+    lib = load()
+    dev = batch.S.device
+    h_off, eps_off, hsz, esz = batch.out_layout()
+    if out is None:
+        out = (torch.empty(hsz, dtype=torch.float64, device=dev), torch.empty(esz, dtype=torch.float64, device=dev),
+               torch.empty(batch.nblk, dtype=torch.int32, device=dev))
+    h, eps, info = out
+    opt = options(batch.twocomp, c, prec, slices, reduction)
+    Ns = np.ascontiguousarray(batch.Ns, dtype=np.int32)
+    i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
+    in_off, ho, eo = i64(batch.in_off), i64(h_off), i64(eps_off)
+    P = ctypes.POINTER(ctypes.c_int64)
+    rc = lib.x2c_build_batched_noalloc(
+        ctypes.byref(opt), batch.nblk, Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), in_off.ctypes.data_as(P),
+        _dev(batch.S, torch, torch.float64), _dev(batch.T, torch, torch.float64),
+        _dev(batch.V, torch, torch.float64), _dev(batch.W, torch, torch.float64),
+        ho.ctypes.data_as(P), _dev(h, torch, torch.float64), eo.ctypes.data_as(P),
+        _dev(eps, torch, torch.float64), _dev(info, torch, torch.int32), _stream_ptr(torch, stream))
+    if rc != OK:
+        raise X2CError(rc, strerror(rc))
+    return h, eps, info
 
 
 def autotune(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspace=None, out=None, stream=None,

@@ -106,6 +106,25 @@ bool valid_opts(const x2c_options* o) {
 
 int max_n(int mode) { return mode == X2C_TWOCOMP ? MAX_N_2C : (mode == X2C_SPINFREE ? MAX_N_SF : 0); }
 
+// Descriptor of one block whose buffers start at workspace byte `off`;
+// returns the end of its region.
+size_t place_block(int N, bool tc, int64_t in_off, int64_t h_off, int64_t eps_off, size_t off, BlockDesc& d) {
+  std::memset(&d, 0, sizeof(d));
+  d.N = N;
+  d.n = tc ? 2 * N : N;
+  d.m = 2 * d.n;
+  d.in_off = in_off;
+  d.h_off = h_off;
+  d.eps_off = eps_off;
+  size_t sz[NBUF];
+  block_sizes(N, tc, sz);
+  for (int i = 0; i < NBUF; ++i) {
+    d.off[i] = (long long)off;
+    off += align_up(sz[i] ? sz[i] : 8);
+  }
+  return off;
+}
+
 bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in_off, const int64_t* h_off,
                  const int64_t* eps_off, Layout& L) {
   if (nblk <= 0 || !N) return false;
@@ -120,19 +139,7 @@ bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in
   for (int b = 0; b < nblk; ++b) {
     if (N[b] <= 0 || N[b] > mx) return false;
     BlockDesc& d = L.desc[b];
-    std::memset(&d, 0, sizeof(d));
-    d.N = N[b];
-    d.n = tc ? 2 * N[b] : N[b];
-    d.m = 2 * d.n;
-    d.in_off = in_off ? in_off[b] : 0;
-    d.h_off = h_off ? h_off[b] : 0;
-    d.eps_off = eps_off ? eps_off[b] : 0;
-    size_t sz[NBUF];
-    block_sizes(N[b], tc, sz);
-    for (int i = 0; i < NBUF; ++i) {
-      d.off[i] = (long long)off;
-      off += align_up(sz[i] ? sz[i] : 8);
-    }
+    off = place_block(N[b], tc, in_off ? in_off[b] : 0, h_off ? h_off[b] : 0, eps_off ? eps_off[b] : 0, off, d);
     if (d.N > L.maxN) L.maxN = d.N;
     if (d.n > L.maxn) L.maxn = d.n;
     if (d.m > L.maxm) L.maxm = d.m;
@@ -266,6 +273,7 @@ struct TraceRec {
 };
 std::mutex g_tmu;
 bool g_trace = false;
+thread_local bool t_untraced = false;   // calls of this thread record no events (allocation-free entry)
 int g_trace_level = 0;   // 1: stages; 2: stages and the reduction matvec launches
 std::vector<TraceRec> g_pending;
 std::vector<hipEvent_t> g_pool;
@@ -287,7 +295,7 @@ struct Stage {
   hipStream_t s;
   hipEvent_t a = nullptr;
   Stage(const char* nm, hipStream_t st) : name(nm), s(st) {
-    if (!g_trace) return;
+    if (!g_trace || t_untraced) return;
     std::lock_guard<std::mutex> lk(g_tmu);
     a = ev_get();
     if (a) hipEventRecord(a, s);
@@ -330,6 +338,7 @@ void trace_collect() {
 // launch itself at the kernel's start and end
 void* x2c::ktrace_begin(const char* name, hipEvent_t* start, hipEvent_t* stop) {
   *start = *stop = nullptr;
+  if (t_untraced) return nullptr;
   std::lock_guard<std::mutex> lk(g_tmu);
   if (!g_trace || g_trace_level < 2) return nullptr;
   hipEvent_t a = ev_get();
@@ -833,6 +842,94 @@ int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
   return hipGraphLaunch(rec->exec, s) == hipSuccess ? X2C_OK : X2C_EHIP;
 }
 
+// ---------------------------------------------------------------- allocation-free entry
+// x2c_build_batched_noalloc runs the build with its workspace in this static
+// device array instead of a caller buffer.  The code object holds one copy
+// per GPU, allocated when the library's kernels are first loaded there and
+// kept until the process ends.  In host code `scratch` is only a stand-in
+// for the symbol: its device address (per device) comes from
+// hipGetSymbolAddress and is what every launch receives.
+constexpr size_t SCRATCH_BYTES = size_t(256) << 20;
+constexpr int SCRATCH_MAX_BLOCKS = 256;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+std::mutex g_scr_mu;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of this device's scratch array, looked up once per device
+char* scratch_for_current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scr_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+// one block descriptor passed by value and stored in device memory (no host
+// staging buffer, so the call allocates nothing and can be captured)
+__global__ void k_put_desc(BlockDesc* dst, BlockDesc d) {
+  const long long* src = reinterpret_cast<const long long*>(&d);
+  long long* out = reinterpret_cast<long long*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(BlockDesc) / sizeof(long long)); i += blockDim.x) out[i] = src[i];
+}
+static_assert(sizeof(BlockDesc) % sizeof(long long) == 0, "descriptor copied as 64-bit words");
+
+int build_noalloc(const x2c_options* o, int nblk, const int* N, const int64_t* in_off, const double* S,
+                  const double* T, const double* V, const double* W, const int64_t* h_off, void* h,
+                  const int64_t* eps_off, double* eps, int* info, hipStream_t s) {
+  if (!valid_opts(o) || nblk <= 0 || !N || !in_off || !h_off || !eps_off || !S || !T || !V || !W || !h || !eps ||
+      !info)
+    return X2C_EINVAL;
+  if (nblk > SCRATCH_MAX_BLOCKS) return X2C_ESCRATCH;
+  const bool tc = o->mode == X2C_TWOCOMP;
+  const int mx = max_n(o->mode);
+  // the layout of x2c_build_batched (no per-block info area: the caller's
+  // info is used), computed without storing the descriptors on the host
+  Layout L;
+  L.info_off = 0;
+  L.desc_off = 0;
+  L.head = align_up((size_t)nblk * sizeof(BlockDesc));
+  size_t end = L.head;
+  for (int b = 0; b < nblk; ++b) {
+    if (N[b] <= 0 || N[b] > mx) return X2C_EINVAL;
+    BlockDesc d;
+    end = place_block(N[b], tc, in_off[b], h_off[b], eps_off[b], end, d);
+    L.maxN = std::max(L.maxN, d.N);
+    L.maxn = std::max(L.maxn, d.n);
+    L.maxm = std::max(L.maxm, d.m);
+  }
+  L.total = end;
+  if (L.total > SCRATCH_BYTES) return X2C_ESCRATCH;
+  char* ws = scratch_for_current_device();
+  if (!ws) return X2C_EHIP;
+  (void)hipGetLastError();
+  BlockDesc* dD = reinterpret_cast<BlockDesc*>(ws + L.desc_off);
+  size_t off = L.head;
+  for (int b = 0; b < nblk; ++b) {
+    BlockDesc d;
+    off = place_block(N[b], tc, in_off[b], h_off[b], eps_off[b], off, d);
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, dD + b, d);
+  }
+  t_untraced = true;
+  int rc;
+  if (tc)
+    rc = run_stages<cplx>(o, L, 0, nblk, S, T, V, W, static_cast<double*>(h), eps, nullptr, nullptr, info, ws, s,
+                          MV_RES_DEFAULT);
+  else
+    rc = run_stages<double>(o, L, 0, nblk, S, T, V, W, static_cast<double*>(h), eps, nullptr, nullptr, info, ws, s,
+                            MV_RES_DEFAULT);
+  t_untraced = false;
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -871,6 +968,15 @@ int x2c_build_batched(const x2c_options* opts, int nblk, const int* N, const int
   if (!in_off || !h_off || !eps_off || !info) return X2C_EINVAL;
   return enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, nullptr, nullptr, info, workspace,
                  ws_bytes, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int x2c_build_batched_noalloc(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off,
+                              const double* S, const double* T, const double* V, const double* W,
+                              const int64_t* h_off, void* h, const int64_t* eps_off, double* eps, int* info,
+                              void* stream) {
+  if (nblk == 0 && valid_opts(opts)) return X2C_OK;
+  return build_noalloc(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, info,
+                       static_cast<hipStream_t>(stream));
 }
 
 int x2c_build_batched_xr(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off, const double* S,
@@ -944,6 +1050,7 @@ const char* x2c_strerror(int code) {
     case X2C_EINVAL: return "invalid argument";
     case X2C_EHIP: return "HIP runtime error";
     case X2C_EBLOCK: return "block failed (see info)";
+    case X2C_ESCRATCH: return "batch exceeds the static scratch of the allocation-free entry point";
     case X2C_INFO_S_NOT_SPD: return "overlap matrix S not positive definite";
     case X2C_INFO_T_NOT_SPD: return "kinetic matrix T not positive definite";
     case X2C_INFO_EIGEN: return "positive-energy subspace not resolved";

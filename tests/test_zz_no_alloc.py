@@ -1,0 +1,77 @@
+"""x2c_build_batched_noalloc (static scratch, no workspace) against
+x2c_build_batched on the same inputs, through the C ABI.
+
+Two calls in a row, the second on a smaller batch (the scratch keeps the
+first call's contents), each compared with the workspace entry point: the
+same kernels in the same order, so the outputs agree bit for bit.  A batch
+beyond the scratch is rejected before anything is enqueued.
+"""
+import numpy as np
+import pytest
+
+from x2c_inputs import C_LIGHT, atom_block, pack_blocks
+
+pytestmark = pytest.mark.gpu
+
+
+def _px():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1303_4446_amd as px
+    return px, torch
+
+
+def run_both(px, torch, blocks, twocomp, prec=0):
+    bt = px.batch_to_device(pack_blocks(blocks, twocomp), twocomp)
+    print(f"  noalloc nblk={len(blocks)} N={list(bt.Ns)} twocomp={twocomp} prec={prec}", flush=True)
+    h1, e1, i1 = px.build_batched_noalloc(bt, C_LIGHT, prec=prec)
+    torch.cuda.synchronize()
+    got = (h1.cpu().numpy(), e1.cpu().numpy(), i1.cpu().numpy())
+    print("  workspace entry point", flush=True)
+    (h0, e0, i0), _ = px.build_batched(bt, C_LIGHT, prec=prec)
+    torch.cuda.synchronize()
+    ref = (h0.cpu().numpy(), e0.cpu().numpy(), i0.cpu().numpy())
+    return got, ref
+
+
+@pytest.mark.parametrize("twocomp", [True, False])
+def test_noalloc_matches_workspace_entry_two_calls(twocomp):
+    px, torch = _px()
+    first = [atom_block(z) for z in (47, 8, 79)]
+    second = [atom_block(z) for z in (6, 17)]            # smaller batch, second call
+    for blocks in (first, second):
+        got, ref = run_both(px, torch, blocks, twocomp)
+        assert np.all(ref[2] == 0) and np.array_equal(got[2], ref[2])
+        assert np.array_equal(got[0], ref[0])
+        assert np.array_equal(got[1], ref[1])
+
+
+def test_noalloc_split_products():
+    px, torch = _px()
+    got, ref = run_both(px, torch, [atom_block(z) for z in (29, 1)], True, prec=px.SPLIT_INT8)
+    assert np.all(ref[2] == 0)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+
+
+def test_noalloc_rejects_batches_beyond_the_scratch():
+    """Batches beyond the static scratch (bytes or block count) are refused
+    before anything is enqueued: the outputs keep their sentinel values."""
+    px, torch = _px()
+    from x2c_inputs import ag_2c
+    big = [ag_2c()] * 4                                  # 4 x 82 MiB of workspace > 256 MiB
+    many = [atom_block(1)] * 257                         # more blocks than the descriptor limit
+    for blocks in (big, many):
+        bt = px.batch_to_device(pack_blocks(blocks, True), True)
+        assert px.workspace_bytes(bt.Ns, True) > (256 << 20) or bt.nblk > 256
+        h_off, eps_off, hsz, esz = bt.out_layout()
+        out = (torch.full((hsz,), 7.0, dtype=torch.float64, device="cuda"),
+               torch.full((esz,), 7.0, dtype=torch.float64, device="cuda"),
+               torch.full((bt.nblk,), -7, dtype=torch.int32, device="cuda"))
+        print(f"  noalloc rejection nblk={bt.nblk}", flush=True)
+        with pytest.raises(px.X2CError) as e:
+            px.build_batched_noalloc(bt, C_LIGHT, out=out)
+        assert e.value.code == px.ESCRATCH
+        torch.cuda.synchronize()
+        assert bool((out[0] == 7.0).all()) and bool((out[1] == 7.0).all()) and bool((out[2] == -7).all())
