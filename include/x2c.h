@@ -189,6 +189,57 @@ int x2c_build_batched_xr(const x2c_options* opts, int nblk, const int* N, const 
                          void* R, int* info, void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * BSS one-electron Hamiltonian of a batch (Sec. II, "The BSS approach",
+ * Eq. u1trafo): the free-particle Foldy-Wouthuysen transformation in the
+ * orthonormal kinetic basis T K = S K t (Eq. orthonormalk), p = sqrt(2t),
+ * E_0 = sqrt(c^2 p^2 + c^4), U_0^A = sqrt((E_0 + c^2)/2E_0),
+ * U_0^B = sqrt((E_0 - c^2)/2E_0), gives the 4c matrix
+ * H^0 = [[E_1 + E_0 - c^2, O_1], [O_1^H, E_1' - E_0 - c^2]] with
+ * E_1 = U_0^A V~ U_0^A + U_0^B W~ U_0^B, O_1 = U_0^A V~ U_0^B - U_0^B W~ U_0^A,
+ * E_1' = U_0^B V~ U_0^B + U_0^A W~ U_0^A (V~ = K^T V K, W~ = p^-1 K^T W K p^-1);
+ * its positive-energy block X'' = C_S'' C_L''^-1, R'' = (I + X''^H X'')^-1/2
+ * and h from Eq. utrans with U^L_BSS = K (U_0^A + U_0^B X'') R'' K^-1 and
+ * U^S_BSS = 2c K p^-1 (U_0^B - U_0^A X'') R'' K^-1 and the block's own
+ * V, T, W (the same matrix as K^-H R''^H [E + O X'' + X''^H O^H +
+ * X''^H E' X''] R'' K^-1, E = E_1 + E_0 - c^2, E' = E_1' - E_0 - c^2).  H^0
+ * goes through the eigen-solve that x2c_build_batched applies to its reduced
+ * 4c matrix; eps are its positive-energy eigenvalues.
+ * Arguments, layout, per-block info and eps (the same positive-energy
+ * eigenvalues) as x2c_build_batched; workspace from x2c_bss_workspace_bytes.
+ * opts->prec must be X2C_FP64 and, two-component, opts->reduction
+ * X2C_RED_QUATERNION (else X2C_EINVAL).  Stream-ordered.
+ */
+size_t x2c_bss_workspace_bytes(const x2c_options* opts, int nblk, const int* N);
+int x2c_bss_batched(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off, const double* S,
+                    const double* T, const double* V, const double* W, const int64_t* h_off, void* h,
+                    const int64_t* eps_off, double* eps, int* info, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * DKHn one-electron Hamiltonian of a batch (Sec. II, "The DKH approach",
+ * Eq. dkhtrans and Table I): the fpFW Hamiltonian H^0 above is transformed
+ * by U_k = exp(W_k), k = 1, 2, ... (exponential parametrisation), W_k the odd
+ * anti-Hermitian operator with (W_k)_ij = (O_k)_ij / (E_0i + E_0j) that
+ * removes the odd term of order k; h is the electronic block of the even
+ * terms through order `order` in the potential, E_0 - c^2 + E_1 + ... + E_n,
+ * back-transformed by K^-1.  Products that do not reach that block are
+ * skipped (x2c_dkh_products gives their number).
+ *   order    1 .. 14.
+ *   h        as x2c_build_batched (no eigenvalues are computed).
+ * Other arguments as x2c_build_batched; workspace from
+ * x2c_dkh_workspace_bytes.  opts->prec must be X2C_FP64 (else X2C_EINVAL);
+ * opts->reduction is ignored.  Stream-ordered.
+ */
+size_t x2c_dkh_workspace_bytes(const x2c_options* opts, int order, int nblk, const int* N);
+int x2c_dkh_batched(const x2c_options* opts, int order, int nblk, const int* N, const int64_t* in_off,
+                    const double* S, const double* T, const double* V, const double* W, const int64_t* h_off, void* h,
+                    int* info, void* workspace, size_t ws_bytes, void* stream);
+
+/* Number of 2c matrix multiplications x2c_dkh_batched performs per block
+ * for DKH of the given order (P(n) of Table I), or -1 for an order outside
+ * 1 .. 14.  Host only. */
+int x2c_dkh_products(int order);
+
+/*
  * Picture-change transformation of one-electron property operators with
  * the blocks' decoupling (Sec. II: U^L and U^S are needed for the picture
  * change of property integrals; U^L_bb = R_b, U^S_bb = X_b R_b, Eqs.

@@ -24,7 +24,8 @@ INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subsp
               4: "positive-energy branch size != n", 5: "renormalisation matrix not PD", 6: "non-finite input"}
 
 EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_build_batched_xr",
-            "x2c_build_batched_noalloc",
+            "x2c_build_batched_noalloc", "x2c_bss_workspace_bytes", "x2c_bss_batched", "x2c_dkh_workspace_bytes",
+            "x2c_dkh_batched", "x2c_dkh_products",
             "x2c_dlu_workspace_bytes", "x2c_dlu_assemble", "x2c_strerror", "x2c_release", "x2c_graph_enable",
             "x2c_stream_split", "x2c_autotune", "x2c_picture_change", "x2c_trace_enable", "x2c_trace_read",
             "x2c_trace_reset")
@@ -69,6 +70,18 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.x2c_build_batched_noalloc.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp,
                                               i64p, vp, i64p, vp, vp, vp]
     lib.x2c_build_batched_noalloc.restype = i32
+    lib.x2c_bss_workspace_bytes.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int)]
+    lib.x2c_bss_workspace_bytes.restype = ctypes.c_size_t
+    lib.x2c_bss_batched.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp, i64p, vp, i64p,
+                                    vp, vp, vp, ctypes.c_size_t, vp]
+    lib.x2c_bss_batched.restype = i32
+    lib.x2c_dkh_workspace_bytes.argtypes = [optp, i32, i32, ctypes.POINTER(ctypes.c_int)]
+    lib.x2c_dkh_workspace_bytes.restype = ctypes.c_size_t
+    lib.x2c_dkh_batched.argtypes = [optp, i32, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp, i64p, vp,
+                                    vp, vp, ctypes.c_size_t, vp]
+    lib.x2c_dkh_batched.restype = i32
+    lib.x2c_dkh_products.argtypes = [i32]
+    lib.x2c_dkh_products.restype = i32
     lib.x2c_build_batched_xr.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp,
                                          i64p, vp, i64p, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.x2c_build_batched_xr.restype = i32
@@ -375,6 +388,88 @@ def build_batched_noalloc(batch: Batch, c: float, prec: int = FP64, slices: int 
     if rc != OK:
         raise X2CError(rc, strerror(rc))
     return h, eps, info
+
+
+def dkh_products(order: int) -> int:
+    """2c matrix multiplications per block of x2c_dkh_batched at this order
+    (-1 outside 1..14)."""
+    return int(load().x2c_dkh_products(int(order)))
+
+
+def bss_workspace_bytes(Ns, twocomp: bool, c: float = 137.0) -> int:
+    Ns = np.ascontiguousarray(Ns, dtype=np.int32)
+    opt = options(twocomp, c)
+    n = load().x2c_bss_workspace_bytes(ctypes.byref(opt), len(Ns), Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if n == 0:
+        raise X2CError(EINVAL, "invalid block sizes or options")
+    return int(n)
+
+
+def dkh_workspace_bytes(Ns, twocomp: bool, order: int, c: float = 137.0) -> int:
+    Ns = np.ascontiguousarray(Ns, dtype=np.int32)
+    opt = options(twocomp, c)
+    n = load().x2c_dkh_workspace_bytes(ctypes.byref(opt), int(order), len(Ns),
+                                       Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if n == 0:
+        raise X2CError(EINVAL, "invalid block sizes, order or options")
+    return int(n)
+
+
+def bss_batched(batch: Batch, c: float, workspace=None, out=None, stream=None):
+    """Enqueue x2c_bss_batched.  Returns ((h_flat, eps_flat, info), workspace)."""
+    torch = _torch()
+    lib = load()
+    dev = batch.S.device
+    h_off, eps_off, hsz, esz = batch.out_layout()
+    if out is None:
+        out = (torch.empty(hsz, dtype=torch.float64, device=dev), torch.empty(esz, dtype=torch.float64, device=dev),
+               torch.empty(batch.nblk, dtype=torch.int32, device=dev))
+    h, eps, info = out
+    wsb = bss_workspace_bytes(batch.Ns, batch.twocomp, c)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    opt = options(batch.twocomp, c)
+    Ns = np.ascontiguousarray(batch.Ns, dtype=np.int32)
+    i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
+    in_off, ho, eo = i64(batch.in_off), i64(h_off), i64(eps_off)
+    P = ctypes.POINTER(ctypes.c_int64)
+    f64 = lambda t: _dev(t, torch, torch.float64)
+    rc = lib.x2c_bss_batched(
+        ctypes.byref(opt), batch.nblk, Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), in_off.ctypes.data_as(P),
+        f64(batch.S), f64(batch.T), f64(batch.V), f64(batch.W), ho.ctypes.data_as(P), f64(h), eo.ctypes.data_as(P),
+        f64(eps), _dev(info, torch, torch.int32), ctypes.c_void_p(workspace.data_ptr()),
+        ctypes.c_size_t(workspace.numel()), _stream_ptr(torch, stream))
+    if rc != OK:
+        raise X2CError(rc, strerror(rc))
+    return out, workspace
+
+
+def dkh_batched(batch: Batch, c: float, order: int, workspace=None, out=None, stream=None):
+    """Enqueue x2c_dkh_batched.  Returns ((h_flat, info), workspace)."""
+    torch = _torch()
+    lib = load()
+    dev = batch.S.device
+    h_off, _, hsz, _ = batch.out_layout()
+    if out is None:
+        out = (torch.empty(hsz, dtype=torch.float64, device=dev), torch.empty(batch.nblk, dtype=torch.int32, device=dev))
+    h, info = out
+    wsb = dkh_workspace_bytes(batch.Ns, batch.twocomp, order, c)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    opt = options(batch.twocomp, c)
+    Ns = np.ascontiguousarray(batch.Ns, dtype=np.int32)
+    i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
+    in_off, ho = i64(batch.in_off), i64(h_off)
+    P = ctypes.POINTER(ctypes.c_int64)
+    f64 = lambda t: _dev(t, torch, torch.float64)
+    rc = lib.x2c_dkh_batched(
+        ctypes.byref(opt), int(order), batch.nblk, Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+        in_off.ctypes.data_as(P), f64(batch.S), f64(batch.T), f64(batch.V), f64(batch.W), ho.ctypes.data_as(P),
+        f64(h), _dev(info, torch, torch.int32), ctypes.c_void_p(workspace.data_ptr()),
+        ctypes.c_size_t(workspace.numel()), _stream_ptr(torch, stream))
+    if rc != OK:
+        raise X2CError(rc, strerror(rc))
+    return out, workspace
 
 
 def autotune(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspace=None, out=None, stream=None,

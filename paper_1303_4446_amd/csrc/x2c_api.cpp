@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "x2c_device.h"
+#include "x2c_dkh_plan.h"
 #include "x2c_launch.h"
 
 using namespace x2c;
@@ -40,13 +41,18 @@ struct Layout {
   std::vector<BlockDesc> desc;
   BlockDesc* pinned = nullptr;     // page-locked copy of desc for the upload
   int maxN = 0, maxn = 0, maxm = 0;
+  int fw = -1;                     // -1: X2C; 0: BSS; k > 0: DKHk
   ~Layout() {
     if (pinned) (void)hipHostFree(pinned);
   }
 };
 
-// byte sizes of the named buffers for one block
-void block_sizes(int N, bool tc, size_t sz[NBUF]) {
+static_assert(DKH_MAX_SLOTS == NBUF - D_T0, "one workspace buffer per DKH slot");
+
+// byte sizes of the named buffers for one block; fw: -1 X2C, 0 BSS (X2C plus
+// the free-particle FW buffers), k > 0 DKHk (FW buffers and the term slots,
+// none of the 4c buffers)
+void block_sizes(int N, bool tc, size_t sz[NBUF], int fw = -1) {
   const size_t n = tc ? 2 * (size_t)N : (size_t)N;
   const size_t m = 2 * n;
   const size_t es = tc ? 16 : 8;
@@ -92,6 +98,20 @@ void block_sizes(int N, bool tc, size_t sz[NBUF]) {
   sz[Z_SLA] = (size_t)MAX_SLICES * (tc ? 2 : 1) * n * kp;
   sz[Z_SLB] = sz[Z_SLA];
   sz[W_VCUR] = m * es;
+  if (fw >= 0) {
+    const size_t qs = (size_t)N * N * (tc ? 32 : 8);   // quaternion / real N x N
+    for (int i : {R_KC, R_ZT, R_Z, R_K, R_G}) sz[i] = NN;
+    sz[V_FP] = 5 * (size_t)N * 8;
+    for (int i = Q_E1; i <= Q_H; ++i) sz[i] = qs;
+    if (fw > 0) {
+      DkhPlan P;
+      if (dkh_plan(fw, P))
+        for (int i = 0; i < P.nslot; ++i) sz[D_T0 + i] = qs;
+      // DKH has no 4c problem and no X2C product chain
+      for (int i = C_S; i <= C_TMP2; ++i) sz[i] = 0;
+      for (int i : {C_A, C_Y, Z_SCR, F_FAC, Q_FAC, W_TF4, Z_SLA, Z_SLB, P_FILT, V_D, V_E, V_TAU}) sz[i] = 0;
+    }
+  }
 }
 
 bool valid_opts(const x2c_options* o) {
@@ -108,7 +128,8 @@ int max_n(int mode) { return mode == X2C_TWOCOMP ? MAX_N_2C : (mode == X2C_SPINF
 
 // Descriptor of one block whose buffers start at workspace byte `off`;
 // returns the end of its region.
-size_t place_block(int N, bool tc, int64_t in_off, int64_t h_off, int64_t eps_off, size_t off, BlockDesc& d) {
+size_t place_block(int N, bool tc, int64_t in_off, int64_t h_off, int64_t eps_off, size_t off, BlockDesc& d,
+                   int fw = -1) {
   std::memset(&d, 0, sizeof(d));
   d.N = N;
   d.n = tc ? 2 * N : N;
@@ -117,7 +138,7 @@ size_t place_block(int N, bool tc, int64_t in_off, int64_t h_off, int64_t eps_of
   d.h_off = h_off;
   d.eps_off = eps_off;
   size_t sz[NBUF];
-  block_sizes(N, tc, sz);
+  block_sizes(N, tc, sz, fw);
   for (int i = 0; i < NBUF; ++i) {
     d.off[i] = (long long)off;
     off += align_up(sz[i] ? sz[i] : 8);
@@ -126,7 +147,7 @@ size_t place_block(int N, bool tc, int64_t in_off, int64_t h_off, int64_t eps_of
 }
 
 bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in_off, const int64_t* h_off,
-                 const int64_t* eps_off, Layout& L) {
+                 const int64_t* eps_off, Layout& L, int fw = -1) {
   if (nblk <= 0 || !N) return false;
   const bool tc = o->mode == X2C_TWOCOMP;
   const int mx = max_n(o->mode);
@@ -139,12 +160,13 @@ bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in
   for (int b = 0; b < nblk; ++b) {
     if (N[b] <= 0 || N[b] > mx) return false;
     BlockDesc& d = L.desc[b];
-    off = place_block(N[b], tc, in_off ? in_off[b] : 0, h_off ? h_off[b] : 0, eps_off ? eps_off[b] : 0, off, d);
+    off = place_block(N[b], tc, in_off ? in_off[b] : 0, h_off ? h_off[b] : 0, eps_off ? eps_off[b] : 0, off, d, fw);
     if (d.N > L.maxN) L.maxN = d.N;
     if (d.n > L.maxn) L.maxn = d.n;
     if (d.m > L.maxm) L.maxm = d.m;
   }
   L.total = off;
+  L.fw = fw;
   return true;
 }
 
@@ -154,10 +176,11 @@ std::mutex g_mu;
 std::map<std::vector<int64_t>, std::shared_ptr<Layout>> g_plans;
 
 std::shared_ptr<Layout> get_plan(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
-                                 const int64_t* h_off, const int64_t* eps_off) {
+                                 const int64_t* h_off, const int64_t* eps_off, int fw = -1) {
   std::vector<int64_t> key;
-  key.reserve(4 * (size_t)nblk + 2);
+  key.reserve(4 * (size_t)nblk + 3);
   key.push_back(o->mode);
+  key.push_back(fw);
   key.push_back(nblk);
   for (int b = 0; b < nblk; ++b) {
     key.push_back(N[b]);
@@ -169,7 +192,7 @@ std::shared_ptr<Layout> get_plan(const x2c_options* o, int nblk, const int* N, c
   auto it = g_plans.find(key);
   if (it != g_plans.end()) return it->second;
   auto L = std::make_shared<Layout>();
-  if (!make_layout(o, nblk, N, in_off, h_off, eps_off, *L)) return nullptr;
+  if (!make_layout(o, nblk, N, in_off, h_off, eps_off, *L, fw)) return nullptr;
   void* pin = nullptr;
   if (hipHostMalloc(&pin, L->desc.size() * sizeof(BlockDesc), hipHostMallocDefault) == hipSuccess && pin) {
     std::memcpy(pin, L->desc.data(), L->desc.size() * sizeof(BlockDesc));
@@ -368,6 +391,218 @@ T tcast(double v) {
   return treal<T>(v);
 }
 
+// ---------------------------------------------------------------- free-particle FW methods
+// Products of the N x N matrices of the BSS / DKH chain: quaternion (two-
+// component, Kramers form) or real (spin-free), and their products with a
+// real scalar matrix (side 0: op(R) Q, side 1: Q op(R)).
+template <class Q>
+struct FwOps;
+template <>
+struct FwOps<quat> {
+  static void gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int a, int oa,
+                   int b, int ob, int c, double al, double be, int herm = 0) {
+    launch_gemm_q(s, D, ws, info, nblk, maxN, DIM_N, a, oa, b, ob, c, al, be, herm);
+  }
+  static void gemm_r(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int side,
+                     int r, int opr, int q, int c, double al, double be, int herm = 0) {
+    launch_gemm_qr(s, D, ws, info, nblk, maxN, side, r, opr, 0, q, c, al, be, herm);
+  }
+};
+template <>
+struct FwOps<double> {
+  static void gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int a, int oa,
+                   int b, int ob, int c, double al, double be, int herm = 0) {
+    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, a, oa, b, ob, c, al, be, herm, 0);
+  }
+  static void gemm_r(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int side,
+                     int r, int opr, int q, int c, double al, double be, int herm = 0) {
+    if (side == 0) launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, r, opr, q, 0, c, al, be, herm, 0);
+    else launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, q, 0, r, opr, c, al, be, herm, 0);
+  }
+};
+
+// Orthonormal kinetic basis T K = S K t (Eq. orthonormalk): C = L_S^-1 T L_S^-T,
+// Householder tridiagonalisation, implicit QR with the rotations kept, the
+// reflectors applied to them, K = L_S^-T (Q Z); also G = S K (so that
+// K^-1 = G^T) and the fpFW vectors from t.
+void kinetic_basis(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN, double c, int mv_res) {
+  const int OPN = 0, OPH = 1;
+  launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPN, R_T, OPN, R_TMP, 1.0, 0.0, 0, 1);
+  launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_TMP, OPN, R_LSI, OPH, R_KC, 1.0, 0.0, 0, 8);
+  launch_hetrd_mk<double>(s, D, ws, info, nblk, maxN, DIM_N, R_KC, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS, V_ET,
+                          mv_res);
+  launch_tri_steqr(s, D, ws, info, nblk, maxN, DIM_N, V_DQ, V_EQ, R_ZT, R_Z);
+  launch_ormtr_blocked<double>(s, D, ws, info, nblk, maxN, maxN, DIM_N, R_KC, V_TAUQ, W_TFQ, R_Z, DIM_N);
+  launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_LSI, OPH, R_Z, OPN, R_K, 1.0, 0.0, 0, 2);
+  launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_S, OPN, R_K, OPN, R_G, 1.0, 0.0, 0, 0);
+  launch_fpfw_vectors(s, D, ws, info, nblk, V_DQ, V_FP, c);
+}
+
+// V~ = K^T V K and K^T W^q K (the ten real products of Sec. III, four
+// spin-free), then the blocks E_1, O_1, E_1' of the fpFW Hamiltonian H^0.
+template <class Q>
+void fpfw_blocks(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, bool tc, int bufE1,
+                 int bufO1, int bufE1p) {
+  const int OPN = 0, OPH = 1;
+  auto sandwich = [&](int a, int dst) {
+    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, a, OPN, R_K, OPN, R_TMP, 1.0, 0.0, 0, 0);
+    launch_gemm<double>(s, D, ws, info, nblk, maxN, DIM_N, R_K, OPH, R_TMP, OPN, dst, 1.0, 0.0, 0, 0);
+  };
+  sandwich(R_V, R_ALL);
+  for (int q = 0; q < (tc ? 4 : 1); ++q) sandwich(R_W0 + q, R_WR0 + q);
+  launch_fpfw_assemble<Q>(s, D, ws, info, nblk, maxN, R_ALL, R_WR0, V_FP, bufE1, bufO1, bufE1p);
+}
+
+// Q^-1/2 of the quaternion N x N matrix in C_Q (reduced in place): result in C_LR.
+void invsqrt_quat(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN, int qrefl, int mv_res) {
+  launch_hetrd_mk<quat>(s, D, ws, info, nblk, maxN, DIM_N, qrefl, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS, V_ET,
+                        mv_res);
+  launch_phase_q(s, D, ws, info, nblk, DIM_N);
+  launch_tri_eig_q(s, D, ws, info, nblk, maxN, DIM_N);
+  launch_invsqrt_cols<quat>(s, D, ws, info, nblk, maxN, DIM_N, C_QMH);
+  launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxN, maxN, DIM_N, qrefl, V_TAUQ, W_TFQ, C_TMP, DIM_N);
+  launch_qct_scale(s, D, ws, info, nblk, maxN, C_TMP, C_LR);
+  launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxN, maxN, DIM_N, qrefl, V_TAUQ, W_TFQ, C_LR, DIM_N);
+}
+
+// DKHn over a batch (plan in x2c_dkh_plan.h).  Q = quat (two-component) or
+// double (spin-free).
+template <class Q>
+int run_dkh(const x2c_options* o, const Layout& L, int b0, int nblk, const double* S, const double* Tm,
+            const double* V, const double* W, double* h, int* info, char* ws, hipStream_t s, int mv_res) {
+  const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off) + b0;
+  const bool tc = o->mode == X2C_TWOCOMP;
+  const int maxN = L.maxN, OPN = 0, OPH = 1;
+  DkhPlan P;
+  if (!dkh_plan(L.fw, P)) return X2C_EINVAL;
+  const int n = P.order;
+  auto sl = [](int x) { return D_T0 + x; };
+  using F = FwOps<Q>;
+  {
+    STAGE("prep");
+    launch_init_info(s, info, nblk);
+    launch_unpack(s, D, ws, info, nblk, maxN, S, Tm, V, W, tc ? 1 : 0);
+    launch_potrf(s, D, ws, info, nblk, maxN);
+    launch_trtri(s, D, ws, info, nblk, maxN);
+  }
+  {
+    STAGE("kinetic");
+    kinetic_basis(s, D, ws, info, nblk, maxN, o->c, mv_res);
+  }
+  {
+    STAGE("fpfw");
+    fpfw_blocks<Q>(s, D, ws, info, nblk, maxN, tc, sl(0), sl(2 * n), sl(n));
+  }
+  {
+    STAGE("dkh_terms");
+    for (const DkhOp& op : P.ops) {
+      switch (op.kind) {
+        case DK_WGEN:
+          launch_dkh_wgen<Q>(s, D, ws, info, nblk, maxN, sl(op.a), sl(P.slot_w), V_FP);
+          break;
+        case DK_EVEN_U:   // W O^H + (W O^H)^H
+          F::gemm(s, D, ws, info, nblk, maxN, sl(P.slot_w), OPN, sl(op.a), OPH, sl(P.slot_p), 1.0, 0.0);
+          launch_combine<Q>(s, D, ws, info, nblk, maxN, sl(op.b), sl(P.slot_p), 0.0, 1.0, 1.0);
+          break;
+        case DK_EVEN_L:   // -(W^H O + (W^H O)^H)
+          F::gemm(s, D, ws, info, nblk, maxN, sl(P.slot_w), OPH, sl(op.a), OPN, sl(P.slot_p), 1.0, 0.0);
+          launch_combine<Q>(s, D, ws, info, nblk, maxN, sl(op.b), sl(P.slot_p), 0.0, -1.0, -1.0);
+          break;
+        case DK_ODD:      // W E' - E W
+          F::gemm(s, D, ws, info, nblk, maxN, sl(P.slot_w), OPN, sl(op.b), OPN, sl(op.c), 1.0, 0.0);
+          F::gemm(s, D, ws, info, nblk, maxN, sl(op.a), OPN, sl(P.slot_w), OPN, sl(op.c), -1.0, 1.0);
+          break;
+        case DK_ACC:
+          launch_combine<Q>(s, D, ws, info, nblk, maxN, sl(op.b), sl(op.a), op.init ? 1.0 : 0.0, op.coef, 0.0);
+          break;
+        case DK_FINAL:    // h_p = diag(E_0 - c^2) + sum of the even upper terms
+          launch_add_diag<Q>(s, D, ws, info, nblk, maxN, Q_H, sl(P.final_slots[0]), V_FP, 2, 1.0, 0.0);
+          for (size_t i = 1; i < P.final_slots.size(); ++i)
+            launch_combine<Q>(s, D, ws, info, nblk, maxN, Q_H, sl(P.final_slots[i]), 1.0, 1.0, 0.0);
+          break;
+      }
+    }
+  }
+  {
+    // back to the original basis: h = K^-H h_p K^-1 = G h_p G^T, G = S K
+    STAGE("backtransform");
+    F::gemm_r(s, D, ws, info, nblk, maxN, 0, R_G, OPN, Q_H, Q_P, 1.0, 0.0);
+    F::gemm_r(s, D, ws, info, nblk, maxN, 1, R_G, OPH, Q_P, Q_H, 1.0, 0.0, 1);
+  }
+  {
+    STAGE("write");
+    if (tc) launch_write_q(s, D, ws, info, nblk, maxN, h, Q_H, nullptr);
+    else launch_write_buf<double>(s, D, ws, info, nblk, maxN, h, Q_H);
+  }
+  return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
+}
+
+// BSS after the positive-energy branch of H^0 (Sec. II, "The BSS approach",
+// Eq. u1trafo): X'' = C_S'' C_L''^-1 in Q_X2, R'' = (I + X''^H X'')^-1/2, the
+// decoupling matrices U^L_BSS = K (U_0^A + U_0^B X'') R'' K^-1 and
+// U^S_BSS = 2c K p^-1 (U_0^B - U_0^A X'') R'' K^-1, and h from Eq. utrans
+// with the block's own V, T and W' = W/4c^2 - T (C_WPP):
+// h = U^L^H V U^L + U^S^H W' U^S + (U^L^H T U^S + h.c.).  (The electronic
+// block of U_1^H H^0 U_1 in the kinetic basis is the same matrix, but H^0
+// carries the rounding of the kinetic transformation at the size of its
+// largest entries; h in the original basis is stationary in the subspace.)
+template <class Q>
+void bss_tail(const x2c_options* o, const Layout& L, const BlockDesc* D, int nblk, double* h, double* eps, int* info,
+              char* ws, hipStream_t s, int mv_res) {
+  const double c = o->c;
+  const int maxN = L.maxN, OPN = 0, OPH = 1;
+  using F = FwOps<Q>;
+  int rbuf;
+  {
+    STAGE("bss_r");
+    F::gemm(s, D, ws, info, nblk, maxN, Q_X2, OPH, Q_X2, OPN, C_Q, 1.0, 0.0, 1);
+    launch_add_diag<Q>(s, D, ws, info, nblk, maxN, C_Q, C_Q, V_FP, 0, 0.0, 1.0);
+    if constexpr (is_quat<Q>()) {
+      invsqrt_quat(s, D, ws, info, nblk, maxN, C_Q, mv_res);
+      rbuf = C_LR;
+    } else {
+      launch_hetrd_mk<double>(s, D, ws, info, nblk, maxN, DIM_N, C_Q, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS, V_ET,
+                              mv_res);
+      launch_tri_eig_q(s, D, ws, info, nblk, maxN, DIM_N);
+      launch_invsqrt_cols<double>(s, D, ws, info, nblk, maxN, DIM_N, C_TMP2);
+      launch_ormtr_blocked<double>(s, D, ws, info, nblk, maxN, maxN, DIM_N, C_Q, V_TAUQ, W_TFQ, C_TMP, DIM_N);
+      launch_conj_transpose<double>(s, D, ws, info, nblk, maxN, C_TMP, C_QMH);
+      launch_ormtr_blocked<double>(s, D, ws, info, nblk, maxN, maxN, DIM_N, C_Q, V_TAUQ, W_TFQ, C_QMH, DIM_N);
+      rbuf = C_QMH;
+    }
+  }
+  {
+    STAGE("bss_u");
+    launch_bss_ab<Q>(s, D, ws, info, nblk, maxN, Q_X2, V_FP, Q_E1, Q_O1, c);
+    F::gemm(s, D, ws, info, nblk, maxN, Q_E1, OPN, rbuf, OPN, Q_M, 1.0, 0.0);
+    F::gemm(s, D, ws, info, nblk, maxN, Q_O1, OPN, rbuf, OPN, Q_P, 1.0, 0.0);
+    // K (.) K^-1 = K (.) G^T
+    F::gemm_r(s, D, ws, info, nblk, maxN, 0, R_K, OPN, Q_M, Q_E1P, 1.0, 0.0);
+    F::gemm_r(s, D, ws, info, nblk, maxN, 1, R_G, OPH, Q_E1P, Q_M, 1.0, 0.0);    // U^L
+    F::gemm_r(s, D, ws, info, nblk, maxN, 0, R_K, OPN, Q_P, Q_E1P, 1.0, 0.0);
+    F::gemm_r(s, D, ws, info, nblk, maxN, 1, R_G, OPH, Q_E1P, Q_P, 1.0, 0.0);    // U^S
+  }
+  {
+    STAGE("bss_h");
+    F::gemm_r(s, D, ws, info, nblk, maxN, 0, R_V, OPN, Q_M, Q_E1, 1.0, 0.0);           // V U^L
+    F::gemm(s, D, ws, info, nblk, maxN, Q_M, OPH, Q_E1, OPN, Q_H, 1.0, 0.0, 1);
+    F::gemm(s, D, ws, info, nblk, maxN, C_WPP, OPN, Q_P, OPN, Q_E1, 1.0, 0.0);         // W' U^S
+    F::gemm(s, D, ws, info, nblk, maxN, Q_P, OPH, Q_E1, OPN, Q_H, 1.0, 1.0, 1);
+    F::gemm_r(s, D, ws, info, nblk, maxN, 0, R_T, OPN, Q_P, Q_E1, 1.0, 0.0);           // T U^S
+    F::gemm(s, D, ws, info, nblk, maxN, Q_M, OPH, Q_E1, OPN, Q_O1, 1.0, 0.0);
+    launch_combine<Q>(s, D, ws, info, nblk, maxN, Q_H, Q_O1, 1.0, 1.0, 1.0);
+  }
+  {
+    STAGE("write");
+    if constexpr (is_quat<Q>()) {
+      launch_write_q(s, D, ws, info, nblk, maxN, h, Q_H, eps);
+    } else {
+      launch_combine<double>(s, D, ws, info, nblk, maxN, C_H, Q_H, 0.0, 1.0, 0.0);
+      launch_write_h<double>(s, D, ws, info, nblk, maxN, h, eps);
+    }
+  }
+}
+
 // The stage sequence for one batch (all blocks advance stage by stage).
 template <class T>
 int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const double* S, const double* Tm, const double* V,
@@ -422,7 +657,24 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
     if (qchain) launch_expand_q(s, D, ws, info, nblk, maxN, c);
     else launch_expand<T>(s, D, ws, info, nblk, maxn, c);
   }
-  {
+  if (L.fw == 0) {
+    // BSS: the 4c matrix whose positive-energy branch is found below is the
+    // fpFW Hamiltonian H^0 in the orthonormal kinetic basis
+    {
+      STAGE("kinetic");
+      kinetic_basis(s, D, ws, info, nblk, maxN, c, mv_res);
+    }
+    {
+      STAGE("fpfw");
+      if (tc) {
+        fpfw_blocks<quat>(s, D, ws, info, nblk, maxN, tc, Q_E1, Q_O1, Q_E1P);
+        launch_bss_h0<quat>(s, D, ws, info, nblk, maxN, Q_E1, Q_O1, Q_E1P, V_FP, C_A, c);
+      } else {
+        fpfw_blocks<double>(s, D, ws, info, nblk, maxN, tc, Q_E1, Q_O1, Q_E1P);
+        launch_bss_h0<double>(s, D, ws, info, nblk, maxN, Q_E1, Q_O1, Q_E1P, V_FP, C_A, c);
+      }
+    }
+  } else {
     // scalar-level reduction: L_S^-1 V L_S^-T, L_S^-1 L_T, L_T^-1 W^q L_T^-T
     STAGE("reduce");
     // (triangular factors: k ranges cut to their triangles; A lower = 1,
@@ -481,7 +733,11 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
   {
     // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
     STAGE("x_solve");
-    if (kramers) {
+    if (L.fw == 0) {
+      // BSS: X'' = C_S'' C_L''^-1 of H^0 itself
+      if (kramers) launch_xsolve_blk<quat>(s, D, ws, info, nblk, maxN, C_Y, DIM_N, Q_X2);
+      else launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn, C_Y, DIM_n, Q_X2);
+    } else if (kramers) {
       // quaternion LU of the N x N block Y_L (X~ to the complex layout unless
       // the chain runs on quaternions)
       launch_xsolve_blk<quat>(s, D, ws, info, nblk, maxN, C_Y, DIM_N, C_QMH);
@@ -489,13 +745,21 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
     } else {
       launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn, C_Y, DIM_n, C_TMP);
     }
-    if (qchain) {
-      GR(1, R_LS, OPH, UPPER, C_QMH, C_TMP2, 1.0, 0.0);
-      GR(0, R_LTI, OPH, UPPER, C_TMP2, C_X, std::sqrt(2.0) * c, 0.0);
-    } else {
-      G(C_TMP, OPN, C_LS, OPH, C_TMP2, 1.0, 0.0);
-      G(C_LTI, OPH, C_TMP2, OPN, C_X, std::sqrt(2.0) * c, 0.0);
+    if (L.fw != 0) {
+      if (qchain) {
+        GR(1, R_LS, OPH, UPPER, C_QMH, C_TMP2, 1.0, 0.0);
+        GR(0, R_LTI, OPH, UPPER, C_TMP2, C_X, std::sqrt(2.0) * c, 0.0);
+      } else {
+        G(C_TMP, OPN, C_LS, OPH, C_TMP2, 1.0, 0.0);
+        G(C_LTI, OPH, C_TMP2, OPN, C_X, std::sqrt(2.0) * c, 0.0);
+      }
     }
+  }
+  if (L.fw == 0) {
+    // BSS: renormalisation and the Hamiltonian from X''
+    if (tc) bss_tail<quat>(o, L, D, nblk, h, eps, info, ws, s, mv_res);
+    else bss_tail<double>(o, L, D, nblk, h, eps, info, ws, s, mv_res);
+    return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
   }
   {
     // S~ = S + X^H T X / 2c^2 ;  L = V + TX + (TX)^H + X^H (W/4c^2 - T) X
@@ -609,7 +873,7 @@ constexpr int MV_RES_DEFAULT = 8;
 std::map<std::vector<int64_t>, Tune> g_tunes;   // guarded by g_smu
 
 std::vector<int64_t> tune_key(const x2c_options* o, const Layout& L) {
-  std::vector<int64_t> k = {o->mode, o->prec, o->ozaki_slices, o->reduction};
+  std::vector<int64_t> k = {o->mode, o->prec, o->ozaki_slices, o->reduction, L.fw};
   for (const BlockDesc& d : L.desc) k.push_back(d.N);
   return k;
 }
@@ -670,6 +934,11 @@ int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S
   std::unique_lock<std::mutex> lk(g_smu);
   const Tune tn = tune_locked(o, L);
   auto run = [&](int b0, int nb, hipStream_t st) {
+    if (L.fw > 0) {
+      if (o->mode == X2C_TWOCOMP)
+        return run_dkh<quat>(o, L, b0, nb, S, T, V, W, static_cast<double*>(h), info + b0, ws, st, tn.mv_res);
+      return run_dkh<double>(o, L, b0, nb, S, T, V, W, static_cast<double*>(h), info + b0, ws, st, tn.mv_res);
+    }
     if (o->mode == X2C_TWOCOMP)
       return run_stages<cplx>(o, L, b0, nb, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
                               static_cast<double*>(Ro), info + b0, ws, st, tn.mv_res);
@@ -779,9 +1048,10 @@ int64_t as_key(const void* p) { return static_cast<int64_t>(reinterpret_cast<int
 int enqueue(const x2c_options* o, int nblk, const int* N, const int64_t* in_off, const double* S, const double* T,
             const double* V, const double* W, const int64_t* h_off, void* h, const int64_t* eps_off, double* eps,
             void* Xo, void* Ro, int* info, void* workspace, size_t ws_bytes, hipStream_t s,
-            const Layout** out_layout) {
-  if (!valid_opts(o) || nblk <= 0 || !N || !S || !T || !V || !W || !h || !eps || !workspace) return X2C_EINVAL;
-  std::shared_ptr<Layout> L = get_plan(o, nblk, N, in_off, h_off, eps_off);
+            const Layout** out_layout, int fw = -1) {
+  if (!valid_opts(o) || nblk <= 0 || !N || !S || !T || !V || !W || !h || (!eps && fw <= 0) || !workspace)
+    return X2C_EINVAL;
+  std::shared_ptr<Layout> L = get_plan(o, nblk, N, in_off, h_off, eps_off, fw);
   if (!L) return X2C_EINVAL;
   if (ws_bytes < L->total) return X2C_EINVAL;
   if (out_layout) *out_layout = L.get();
@@ -987,6 +1257,53 @@ int x2c_build_batched_xr(const x2c_options* opts, int nblk, const int* N, const 
   if (!in_off || !h_off || !eps_off || !info) return X2C_EINVAL;
   return enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, X, R, info, workspace, ws_bytes,
                  static_cast<hipStream_t>(stream), nullptr);
+}
+
+// BSS and DKHn need FP64 products; BSS takes X from the quaternion reduction
+// in two-component mode
+static bool fw_opts_ok(const x2c_options* o, bool bss) {
+  if (!valid_opts(o) || o->prec != X2C_FP64) return false;
+  if (bss && o->mode == X2C_TWOCOMP && o->reduction != X2C_RED_QUATERNION) return false;
+  return true;
+}
+
+size_t x2c_bss_workspace_bytes(const x2c_options* opts, int nblk, const int* N) {
+  if (!fw_opts_ok(opts, true)) return 0;
+  Layout L;
+  if (!make_layout(opts, nblk, N, nullptr, nullptr, nullptr, L, 0)) return 0;
+  return L.total;
+}
+
+int x2c_bss_batched(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off, const double* S,
+                    const double* T, const double* V, const double* W, const int64_t* h_off, void* h,
+                    const int64_t* eps_off, double* eps, int* info, void* workspace, size_t ws_bytes, void* stream) {
+  if (!fw_opts_ok(opts, true)) return X2C_EINVAL;
+  if (nblk == 0) return X2C_OK;
+  if (!in_off || !h_off || !eps_off || !info) return X2C_EINVAL;
+  return enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, nullptr, nullptr, info, workspace,
+                 ws_bytes, static_cast<hipStream_t>(stream), nullptr, 0);
+}
+
+int x2c_dkh_products(int order) {
+  DkhPlan P;
+  return dkh_plan(order, P) ? P.products : -1;
+}
+
+size_t x2c_dkh_workspace_bytes(const x2c_options* opts, int order, int nblk, const int* N) {
+  if (!fw_opts_ok(opts, false) || order < 1 || order > DKH_MAX_ORDER) return 0;
+  Layout L;
+  if (!make_layout(opts, nblk, N, nullptr, nullptr, nullptr, L, order)) return 0;
+  return L.total;
+}
+
+int x2c_dkh_batched(const x2c_options* opts, int order, int nblk, const int* N, const int64_t* in_off,
+                    const double* S, const double* T, const double* V, const double* W, const int64_t* h_off, void* h,
+                    int* info, void* workspace, size_t ws_bytes, void* stream) {
+  if (!fw_opts_ok(opts, false) || order < 1 || order > DKH_MAX_ORDER) return X2C_EINVAL;
+  if (nblk == 0) return X2C_OK;
+  if (!in_off || !h_off || !info) return X2C_EINVAL;
+  return enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, nullptr, nullptr, nullptr, nullptr, info, workspace,
+                 ws_bytes, static_cast<hipStream_t>(stream), nullptr, order);
 }
 
 int x2c_picture_change(const x2c_options* opts, int nblk, const int* N, const int64_t* p_off, const double* PLL,

@@ -149,7 +149,17 @@ enum Buf : int {
   V_EXA, V_EXB,
   // split-precision products with int8 slices: the split operands
   Z_SLA, Z_SLB,
-  NBUF
+  // BSS and DKHn (free-particle FW basis): real N x N reduced kinetic matrix
+  // (then its reflectors), rotations (transposed and row-major), K, S K
+  R_KC, R_ZT, R_Z, R_K, R_G,
+  // fpFW vectors [p | E_0 | E_0 - c^2 | U_0^A | U_0^B] (5 N doubles)
+  V_FP,
+  // N x N matrices of the scalar type of the chain (quaternion two-component,
+  // real spin-free): E_1, O_1, E_1', work, product, X'', h in the kinetic basis
+  Q_E1, Q_O1, Q_E1P, Q_M, Q_P, Q_X2, Q_H,
+  // DKHn term and scratch slots (see x2c_dkh_plan.h)
+  D_T0,
+  NBUF = D_T0 + 48
 };
 
 constexpr int RMAX = 48;   // max Zolotarev pole pairs

@@ -111,4 +111,28 @@ template <class T>
 void launch_xsolve_blk(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxn, int bufY, int dsel,
                        int bufX);
 
+// free-particle FW bases of BSS and DKHn (k_fw.hip)
+void launch_tri_steqr(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxdim, int dsel,
+                      int bufD, int bufE, int bufZT, int bufZ);
+void launch_fpfw_vectors(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int bufD, int bufFP,
+                         double c);
+template <class T>
+void launch_fpfw_assemble(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int bufV,
+                          int bufW0, int bufFP, int bufE1, int bufO1, int bufE1p);
+template <class T>
+void launch_dkh_wgen(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int bufO,
+                     int bufW, int bufFP);
+template <class T>
+void launch_combine(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int bufDst,
+                    int bufSrc, double a, double bs, double bh);
+template <class T>
+void launch_add_diag(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int bufDst,
+                     int bufSrc, int bufFP, int k1, double s1, double s0);
+template <class T>
+void launch_bss_ab(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int bufX2,
+                   int bufFP, int bufA, int bufB, double c);
+template <class T>
+void launch_bss_h0(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int bufE1,
+                   int bufO1, int bufE1p, int bufFP, int bufA, double c);
+
 }  // namespace x2c
