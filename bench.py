@@ -52,6 +52,9 @@ PAPER_TIMINGS = [
      "hardware": "Intel Xeon X3460 2.8 GHz", "source": "Table tab:res4"},
     {"what": "X2C_loc, scalar-relativistic, Ag309 Oh (309 atomic blocks)", "seconds": 1875.0,
      "blocks_per_s": 309 / 1875.0, "hardware": "Intel Xeon X3460 2.8 GHz", "source": "Table tab:res4"},
+    {"what": "DKH2 / DKH3 / DKH4 / DKH8 / BSS, two-component (SO), DLU, Ag13 C1",
+     "seconds": {"dkh2": 13.2, "dkh3": 14.0, "dkh4": 15.3, "dkh8": 27.3, "bss": 21.6},
+     "hardware": "Intel Xeon E5430, one core", "source": "Table tab_cputime12c"},
 ]
 
 
@@ -188,6 +191,9 @@ def parse(argv=None):
                          "int8 slices")
     ap.add_argument("--split-steps", type=int, default=5,
                     help="timed steps of each split-precision comparison run (0 = skip the comparison)")
+    ap.add_argument("--fw-steps", type=int, default=5,
+                    help="timed steps of each BSS / DKHn run on the same batch (0 = skip)")
+    ap.add_argument("--dkh-orders", default="2,3,4,8", help="DKH orders timed in the BSS / DKHn comparison")
     ap.add_argument("--reduction", choices=["quaternion", "complex"], default="quaternion",
                     help="two-component eigenproblem reduction")
     ap.add_argument("--check-blocks", type=int, default=3, help="blocks checked against the oracle")
@@ -344,6 +350,50 @@ def time_steps(px, torch, batch, c, prec, red, stream, ws, out, steps):
     return ev0.elapsed_time(ev1)
 
 
+def time_fw(px, torch, batch, c, stream, steps, method, order=0):
+    """Blocks/s of x2c_bss_batched or x2c_dkh_batched on the batch (graph
+    replay, same launch as the X2C timing) and the host copy of h."""
+    run = (lambda ws=None, out=None: px.bss_batched(batch, c, workspace=ws, out=out, stream=stream)) \
+        if method == "bss" else \
+        (lambda ws=None, out=None: px.dkh_batched(batch, c, order, workspace=ws, out=out, stream=stream))
+    out, ws = run()
+    run(ws, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        run(ws, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    info = out[-1].cpu().numpy()
+    hs = px.unpack_h(out[0].cpu().numpy(), batch.Ns, batch.twocomp)
+    del ws, out
+    return ms, hs, info
+
+
+def score_fw(blocks, twocomp, c, refs, hs, method, order):
+    """Bound-state max|dE| of eig(h, S) against the positive 4c spectrum (the
+    method's own error for DKHn, exact decoupling for BSS) on the sampled
+    blocks, and h against the oracle on the first of them."""
+    import oracle
+    import oracle.fw as ofw
+    r = {"max_dE_bound_vs_4c_Eh": 0.0}
+    for i, ref in refs.items():
+        es = oracle.spectrum_of(hs[i], blocks[i].S, twocomp)
+        bd = ref["e4"] < 0
+        r["max_dE_bound_vs_4c_Eh"] = max(r["max_dE_bound_vs_4c_Eh"], float(np.abs(es - ref["e4"])[bd].max()))
+    if refs:
+        i = min(refs)
+        b = blocks[i]
+        W = b.W if twocomp else b.W[0]
+        h0 = ofw.bss(b.S, b.T, b.V, W, c, twocomp)[0] if method == "bss" else \
+            ofw.dkh(b.S, b.T, b.V, W, c, twocomp, order)
+        r["h_rel_err_vs_oracle"] = float(np.abs(hs[i] - h0).max() / np.abs(h0).max())
+        r["oracle_block"] = i
+    return r
+
+
 def host_outputs(px, out, batch, twocomp):
     h, eps, info = out
     info_h = info.cpu().numpy().copy()
@@ -434,6 +484,15 @@ def main():
             print(f"# split {name}: {ms / args.split_steps:.1f} ms per step", file=sys.stderr, flush=True)
             del so
 
+    # BSS and DKHn on the same batch (free-particle FW based decouplings)
+    fw_runs = {}
+    if args.fw_steps > 0 and args.prec == "fp64" and args.reduction == "quaternion":
+        for method, order in [("bss", 0)] + [("dkh", int(o)) for o in args.dkh_orders.split(",") if o]:
+            name = "bss" if method == "bss" else f"dkh{order}"
+            ms, fhs, finfo = time_fw(px, torch, batch, c, stream, args.fw_steps, method, order)
+            fw_runs[name] = dict(ms=ms, hs=fhs, info=finfo, method=method, order=order)
+            print(f"# {name}: {ms:.1f} ms per step", file=sys.stderr, flush=True)
+
     # traced pass over the same steps (eager launches, HIP events on the call's
     # stream around every stage and every matvec launch).  A first traced
     # step, not recorded, fills the library's event pool, and the events are
@@ -473,6 +532,20 @@ def main():
                            **{k: v for k, v in sc.items() if k != "checked_blocks"}}
             split[name]["faster_than_fp64"] = bool(r["ms"] < ms_step)
         print(f"# split {json.dumps(split)}", file=sys.stderr, flush=True)
+
+    fwres = None
+    if fw_runs:
+        fwres = {}
+        for name, r in fw_runs.items():
+            ok = bool(np.all(r["info"] == 0))
+            d = {"blocks_per_s": nblk / (r["ms"] / 1e3), "ms_per_step": r["ms"], "steps": args.fw_steps,
+                 "blocks_ok": ok}
+            if r["method"] == "dkh":
+                d["products_per_block"] = px.dkh_products(r["order"])
+            if ok:
+                d.update(score_fw(blocks, twocomp, c, refs, r["hs"], r["method"], r["order"]))
+            fwres[name] = d
+        print(f"# fw {json.dumps(fwres)}", file=sys.stderr, flush=True)
 
     mv = stages.pop("k_tri_matvec", None)
     stage_ms = {k: v[0] / max(1, v[1]) for k, v in stages.items()}
@@ -516,6 +589,7 @@ def main():
                    "matvec_wg_per_cu": tuned[1] if tuned else 8, "autotuned": bool(tuned)},
         "accuracy": acc,
         "split": split,
+        "bss_dkh": fwres,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_timings": PAPER_TIMINGS,
