@@ -305,8 +305,8 @@ int x2c_dlu_assemble(const x2c_options* opts, int natom, const int* N, const dou
 /* Static description of a return or info code. */
 const char* x2c_strerror(int code);
 
-/* Drop cached launch plans, captured graphs, tuned launch shapes and trace
- * events. */
+/* Drop cached launch plans, captured graphs, tuned launch shapes held in
+ * memory and trace events. */
 void x2c_release(void);
 
 /*
@@ -335,6 +335,13 @@ int x2c_graph_enable(int on);
  */
 int x2c_stream_split(int ways);
 
+/* The launch shape calls with these options and block sizes would use:
+ * returns 1 and the tuned shape when x2c_autotune (in this process or, via
+ * the cache file, an earlier one on the same GPU architecture) has tuned the
+ * class, 0 and the defaults otherwise, X2C_EINVAL for bad arguments.
+ * *ways_out / *mv_res_out may be NULL. */
+int x2c_tuned_shape(const x2c_options* opts, int nblk, const int* N, int* ways_out, int* mv_res_out);
+
 /*
  * Autotuning of the launch shape of a batch class (library infrastructure).
  * Runs x2c_build_batched on the caller's batch (same arguments, same
@@ -344,12 +351,17 @@ int x2c_stream_split(int ways);
  * reductions.  The fastest (HIP events on `stream`, summed over the reps) is
  * kept for every later call with the same options and block sizes N[] and
  * written to *ways_out and *mv_res_out (either may be NULL); batches of other
- * classes keep x2c_stream_split's setting and 8 work-groups per CU.  All
+ * classes keep x2c_stream_split's setting and 8 work-groups per CU.  The
+ * shape is also appended to a cache file keyed by the GPU architecture and
+ * the batch class (X2C_TUNE_CACHE if set, an empty value disabling it; else
+ * $XDG_CACHE_HOME/libx2c/tune_v1.txt or ~/.cache/libx2c/tune_v1.txt), from
+ * which later processes take it.  All
  * candidates give identical results.  Blocking: synchronises `stream` once
  * per candidate.  Returns X2C_OK, X2C_EINVAL (arguments as for
  * x2c_build_batched; reps outside 1..100) or X2C_EHIP, in which case the
  * class's previous shape is kept.  Run it with tracing disabled (traced calls
- * use one stream).  x2c_release() forgets every tuned shape.
+ * use one stream).  x2c_release() forgets the tuned shapes held in
+ * memory (the cache file is read again on the next call).
  */
 int x2c_autotune(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off, const double* S,
                  const double* T, const double* V, const double* W, const int64_t* h_off, void* h,

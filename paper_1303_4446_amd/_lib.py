@@ -25,7 +25,7 @@ INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subsp
 
 EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_build_batched_xr",
             "x2c_build_batched_noalloc", "x2c_bss_workspace_bytes", "x2c_bss_batched", "x2c_dkh_workspace_bytes",
-            "x2c_dkh_batched", "x2c_dkh_products",
+            "x2c_dkh_batched", "x2c_dkh_products", "x2c_tuned_shape",
             "x2c_dlu_workspace_bytes", "x2c_dlu_assemble", "x2c_strerror", "x2c_release", "x2c_graph_enable",
             "x2c_stream_split", "x2c_autotune", "x2c_picture_change", "x2c_trace_enable", "x2c_trace_read",
             "x2c_trace_reset")
@@ -80,6 +80,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.x2c_dkh_batched.argtypes = [optp, i32, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp, i64p, vp,
                                     vp, vp, ctypes.c_size_t, vp]
     lib.x2c_dkh_batched.restype = i32
+    lib.x2c_tuned_shape.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int)]
+    lib.x2c_tuned_shape.restype = i32
     lib.x2c_dkh_products.argtypes = [i32]
     lib.x2c_dkh_products.restype = i32
     lib.x2c_build_batched_xr.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp,
@@ -388,6 +391,21 @@ def build_batched_noalloc(batch: Batch, c: float, prec: int = FP64, slices: int 
     if rc != OK:
         raise X2CError(rc, strerror(rc))
     return h, eps, info
+
+
+def tuned_shape(Ns, twocomp: bool, c: float = 137.0, prec: int = FP64, slices: int = 0,
+                reduction: int = RED_QUATERNION):
+    """(found, ways, mv_res): the launch shape a batch of these block sizes
+    would use, and whether it comes from x2c_autotune (this process or the
+    cache file)."""
+    Ns = np.ascontiguousarray(Ns, dtype=np.int32)
+    opt = options(twocomp, c, prec, slices, reduction)
+    w, r = ctypes.c_int(0), ctypes.c_int(0)
+    rc = load().x2c_tuned_shape(ctypes.byref(opt), len(Ns), Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                ctypes.byref(w), ctypes.byref(r))
+    if rc < 0:
+        raise X2CError(rc, strerror(rc))
+    return bool(rc), w.value, r.value
 
 
 def dkh_products(order: int) -> int:

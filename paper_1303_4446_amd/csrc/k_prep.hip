@@ -379,7 +379,16 @@ __global__ void k_write_h(const BlockDesc* D, char* ws, const int* info, double*
       eps[d.eps_off + k] = 0.0;
 }
 
+// per-block status from descriptor order to the caller's block order
+__global__ void k_scatter_info(const BlockDesc* D, const int* iw, int* info, int nblk) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nblk) info[D[k].orig] = iw[k];
+}
+
 // ----------------------------------------------------------------- launchers
+void launch_scatter_info(hipStream_t s, const BlockDesc* D, const int* iw, int* info, int nblk) {
+  hipLaunchKernelGGL(k_scatter_info, dim3((nblk + 255) / 256), dim3(256), 0, s, D, iw, info, nblk);
+}
 void launch_init_info(hipStream_t s, int* info, int nblk) {
   hipLaunchKernelGGL(k_init_info, dim3((nblk + 255) / 256), dim3(256), 0, s, info, nblk);
 }

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -13,6 +14,8 @@
 #include <mutex>
 #include <string>
 #include <vector>
+
+#include <sys/stat.h>
 
 #include "x2c_device.h"
 #include "x2c_dkh_plan.h"
@@ -48,6 +51,12 @@ struct Layout {
 };
 
 static_assert(DKH_MAX_SLOTS == NBUF - D_T0, "one workspace buffer per DKH slot");
+
+// Largest dimensions of the blocks one launch sequence covers (a part of a
+// batch): the grids and the column loops of the reductions stop there.
+struct Dims {
+  int maxN = 0, maxn = 0, maxm = 0;
+};
 
 // byte sizes of the named buffers for one block; fw: -1 X2C, 0 BSS (X2C plus
 // the free-particle FW buffers), k > 0 DKHk (FW buffers and the term slots,
@@ -157,10 +166,18 @@ bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in
   L.desc.resize(nblk);
   size_t off = L.head;
   L.maxN = L.maxn = L.maxm = 0;
-  for (int b = 0; b < nblk; ++b) {
+  // descriptors in order of decreasing size (stable): the parts of a split
+  // batch then hold blocks of similar size, and each part's column loops stop
+  // at its own largest block
+  std::vector<int> order(nblk);
+  for (int b = 0; b < nblk; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return N[a] > N[b]; });
+  for (int k = 0; k < nblk; ++k) {
+    const int b = order[k];
     if (N[b] <= 0 || N[b] > mx) return false;
-    BlockDesc& d = L.desc[b];
+    BlockDesc& d = L.desc[k];
     off = place_block(N[b], tc, in_off ? in_off[b] : 0, h_off ? h_off[b] : 0, eps_off ? eps_off[b] : 0, off, d, fw);
+    d.orig = b;
     if (d.N > L.maxN) L.maxN = d.N;
     if (d.n > L.maxn) L.maxn = d.n;
     if (d.m > L.maxm) L.maxm = d.m;
@@ -468,11 +485,12 @@ void invsqrt_quat(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nb
 // DKHn over a batch (plan in x2c_dkh_plan.h).  Q = quat (two-component) or
 // double (spin-free).
 template <class Q>
-int run_dkh(const x2c_options* o, const Layout& L, int b0, int nblk, const double* S, const double* Tm,
-            const double* V, const double* W, double* h, int* info, char* ws, hipStream_t s, int mv_res) {
+int run_dkh(const x2c_options* o, const Layout& L, const Dims& dm, int b0, int nblk, const double* S,
+            const double* Tm, const double* V, const double* W, double* h, int* info, char* ws, hipStream_t s,
+            int mv_res) {
   const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off) + b0;
   const bool tc = o->mode == X2C_TWOCOMP;
-  const int maxN = L.maxN, OPN = 0, OPH = 1;
+  const int maxN = dm.maxN, OPN = 0, OPH = 1;
   DkhPlan P;
   if (!dkh_plan(L.fw, P)) return X2C_EINVAL;
   const int n = P.order;
@@ -547,10 +565,10 @@ int run_dkh(const x2c_options* o, const Layout& L, int b0, int nblk, const doubl
 // carries the rounding of the kinetic transformation at the size of its
 // largest entries; h in the original basis is stationary in the subspace.)
 template <class Q>
-void bss_tail(const x2c_options* o, const Layout& L, const BlockDesc* D, int nblk, double* h, double* eps, int* info,
+void bss_tail(const x2c_options* o, const Dims& dm, const BlockDesc* D, int nblk, double* h, double* eps, int* info,
               char* ws, hipStream_t s, int mv_res) {
   const double c = o->c;
-  const int maxN = L.maxN, OPN = 0, OPH = 1;
+  const int maxN = dm.maxN, OPN = 0, OPH = 1;
   using F = FwOps<Q>;
   int rbuf;
   {
@@ -605,13 +623,13 @@ void bss_tail(const x2c_options* o, const Layout& L, const BlockDesc* D, int nbl
 
 // The stage sequence for one batch (all blocks advance stage by stage).
 template <class T>
-int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const double* S, const double* Tm, const double* V,
+int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, int nblk, const double* S, const double* Tm, const double* V,
                const double* W, double* h, double* eps, double* Xo, double* Ro, int* info, char* ws, hipStream_t s,
                int mv_res) {
   const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off) + b0;
   const bool tc = o->mode == X2C_TWOCOMP;
   const double c = o->c;
-  const int maxN = L.maxN, maxn = L.maxn, maxm = L.maxm;
+  const int maxN = dm.maxN, maxn = dm.maxn, maxm = dm.maxm;
   const int OPN = 0, OPH = 1;
   const bool kramers = tc && o->reduction == X2C_RED_QUATERNION;
   // products of the X / L / S~ / R chain: FP64, or split bf16 slices
@@ -757,8 +775,8 @@ int run_stages(const x2c_options* o, const Layout& L, int b0, int nblk, const do
   }
   if (L.fw == 0) {
     // BSS: renormalisation and the Hamiltonian from X''
-    if (tc) bss_tail<quat>(o, L, D, nblk, h, eps, info, ws, s, mv_res);
-    else bss_tail<double>(o, L, D, nblk, h, eps, info, ws, s, mv_res);
+    if (tc) bss_tail<quat>(o, dm, D, nblk, h, eps, info, ws, s, mv_res);
+    else bss_tail<double>(o, dm, D, nblk, h, eps, info, ws, s, mv_res);
     return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
   }
   {
@@ -877,10 +895,92 @@ std::vector<int64_t> tune_key(const x2c_options* o, const Layout& L) {
   for (const BlockDesc& d : L.desc) k.push_back(d.N);
   return k;
 }
-// caller holds g_smu
+// Tuned shapes persist in a text file (one line per batch class:
+// architecture, 64-bit FNV-1a hash of the class key, streams, matvec
+// residency; later lines win): X2C_TUNE_CACHE if set (empty: no file),
+// else $XDG_CACHE_HOME/libx2c/tune_v1.txt or ~/.cache/libx2c/tune_v1.txt.
+std::string tune_cache_path() {
+  if (const char* p = std::getenv("X2C_TUNE_CACHE")) return p;
+  const char* x = std::getenv("XDG_CACHE_HOME");
+  const char* home = std::getenv("HOME");
+  std::string base = (x && *x) ? std::string(x) : (home && *home ? std::string(home) + "/.cache" : std::string());
+  return base.empty() ? std::string() : base + "/libx2c/tune_v1.txt";
+}
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+uint64_t key_hash(const std::vector<int64_t>& k) {
+  uint64_t h = 1469598103934665603ull;
+  for (int64_t v : k)
+    for (int i = 0; i < 8; ++i) {
+      h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  return h;
+}
+
+bool g_file_loaded = false;
+std::map<std::pair<std::string, uint64_t>, Tune> g_file_tunes;   // guarded by g_smu
+
+void load_tune_file() {
+  g_file_loaded = true;
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char arch[64];
+  unsigned long long h = 0;
+  int ways = 0, res = 0;
+  while (std::fscanf(f, "%63s %llx %d %d", arch, &h, &ways, &res) == 4)
+    if (ways >= 1 && ways <= 4 && (res == 4 || res == 8)) g_file_tunes[{arch, (uint64_t)h}] = Tune{ways, res};
+  std::fclose(f);
+}
+
+void save_tune(const std::vector<int64_t>& key, Tune t) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos && slash > 0) {
+    std::string dir = path.substr(0, slash);
+    for (size_t i = 1; i <= dir.size(); ++i)
+      if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+  }
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  const std::string arch = device_arch();
+  std::fprintf(f, "%s %llx %d %d\n", arch.c_str(), (unsigned long long)key_hash(key), t.ways, t.mv_res);
+  std::fclose(f);
+  g_file_tunes[{arch, key_hash(key)}] = t;
+}
+
+// caller holds g_smu; the in-memory shape, else the persisted one, else the
+// defaults
+bool tuned_locked(const x2c_options* o, const Layout& L, Tune* out) {
+  const std::vector<int64_t> key = tune_key(o, L);
+  auto it = g_tunes.find(key);
+  if (it != g_tunes.end()) {
+    *out = it->second;
+    return true;
+  }
+  if (!g_file_loaded) load_tune_file();
+  if (g_file_tunes.empty()) return false;
+  auto jt = g_file_tunes.find({device_arch(), key_hash(key)});
+  if (jt == g_file_tunes.end()) return false;
+  g_tunes[key] = jt->second;
+  *out = jt->second;
+  return true;
+}
 Tune tune_locked(const x2c_options* o, const Layout& L) {
-  auto it = g_tunes.find(tune_key(o, L));
-  return it != g_tunes.end() ? it->second : Tune{g_split, MV_RES_DEFAULT};
+  Tune t{g_split, MV_RES_DEFAULT};
+  (void)tuned_locked(o, L, &t);
+  return t;
 }
 Tune tune_for(const x2c_options* o, const Layout& L) {
   std::lock_guard<std::mutex> lk(g_smu);
@@ -916,6 +1016,45 @@ AuxStreams* device_streams() {
   return ok ? &a : nullptr;
 }
 
+// Cost model of one part of a batch run as one launch sequence: the
+// reductions and solves advance column by column in lock-step over the
+// part's blocks, so a part pays a fixed latency per column step of its
+// largest block (about 3 N steps of ~50 us: the 4c and renormalisation
+// reductions) plus a throughput term for its work (~0.21 ms per N = 192
+// two-component block).  Both from kernel traces of the Ag batch.
+double part_cost(int maxN, double n3) {
+  constexpr double kColumn = 3.0 * 0.051;            // ms per unit of the largest N
+  constexpr double kWork = 0.213 / (192.0 * 192 * 192);   // ms per N^3
+  return kColumn * maxN + kWork * n3;
+}
+
+// Boundaries of `ways` contiguous parts of the size-sorted descriptors
+// minimising the largest part cost (exhaustive over split points by
+// dynamic programming; a batch of equal blocks gets equal counts).
+void split_parts(const Layout& L, int ways, int* bnd) {
+  const int n = (int)L.desc.size();
+  std::vector<double> pre(n + 1, 0.0);
+  for (int b = 0; b < n; ++b) pre[b + 1] = pre[b] + (double)L.desc[b].N * L.desc[b].N * L.desc[b].N;
+  auto cost = [&](int a, int e) { return part_cost(L.desc[a].N, pre[e] - pre[a]); };   // desc sorted: max at a
+  // best[p][e]: minimal largest cost of splitting [0, e) into p non-empty parts
+  const double inf = 1e300;
+  std::vector<std::vector<double>> best(ways + 1, std::vector<double>(n + 1, inf));
+  std::vector<std::vector<int>> arg(ways + 1, std::vector<int>(n + 1, 0));
+  best[0][0] = 0.0;
+  for (int p = 1; p <= ways; ++p)
+    for (int e = p; e <= n; ++e)
+      for (int a = p - 1; a < e; ++a) {
+        if (best[p - 1][a] >= inf) continue;
+        const double v = std::max(best[p - 1][a], cost(a, e));
+        if (v < best[p][e]) {
+          best[p][e] = v;
+          arg[p][e] = a;
+        }
+      }
+  bnd[ways] = n;
+  for (int p = ways; p >= 1; --p) bnd[p - 1] = arg[p][bnd[p]];
+}
+
 // descriptor upload + every stage of one call, enqueued on s.  With
 // splitting on, the batch is cut into up to g_split parts of about equal
 // work (sum of N^3): the first runs on s, the others on auxiliary streams of
@@ -933,42 +1072,41 @@ int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S
     return X2C_EHIP;
   std::unique_lock<std::mutex> lk(g_smu);
   const Tune tn = tune_locked(o, L);
+  // the stages run on the library's own info array (descriptor order, the
+  // blocks sorted by size); the caller's info is written at the end
+  int* iw = reinterpret_cast<int*>(ws + L.info_off);
   auto run = [&](int b0, int nb, hipStream_t st) {
+    Dims dm;
+    for (int b = b0; b < b0 + nb; ++b) {
+      dm.maxN = std::max(dm.maxN, L.desc[b].N);
+      dm.maxn = std::max(dm.maxn, L.desc[b].n);
+      dm.maxm = std::max(dm.maxm, L.desc[b].m);
+    }
     if (L.fw > 0) {
       if (o->mode == X2C_TWOCOMP)
-        return run_dkh<quat>(o, L, b0, nb, S, T, V, W, static_cast<double*>(h), info + b0, ws, st, tn.mv_res);
-      return run_dkh<double>(o, L, b0, nb, S, T, V, W, static_cast<double*>(h), info + b0, ws, st, tn.mv_res);
+        return run_dkh<quat>(o, L, dm, b0, nb, S, T, V, W, static_cast<double*>(h), iw + b0, ws, st, tn.mv_res);
+      return run_dkh<double>(o, L, dm, b0, nb, S, T, V, W, static_cast<double*>(h), iw + b0, ws, st, tn.mv_res);
     }
     if (o->mode == X2C_TWOCOMP)
-      return run_stages<cplx>(o, L, b0, nb, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
-                              static_cast<double*>(Ro), info + b0, ws, st, tn.mv_res);
-    return run_stages<double>(o, L, b0, nb, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
-                              static_cast<double*>(Ro), info + b0, ws, st, tn.mv_res);
+      return run_stages<cplx>(o, L, dm, b0, nb, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
+                              static_cast<double*>(Ro), iw + b0, ws, st, tn.mv_res);
+    return run_stages<double>(o, L, dm, b0, nb, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
+                              static_cast<double*>(Ro), iw + b0, ws, st, tn.mv_res);
+  };
+  auto finish = [&](int rc) {
+    if (rc == X2C_OK && info != iw) launch_scatter_info(s, reinterpret_cast<const BlockDesc*>(ws + L.desc_off), iw, info,
+                                                        nblk);
+    if (rc == X2C_OK && hipGetLastError() != hipSuccess) rc = X2C_EHIP;
+    return rc;
   };
   const int ways = std::min(tn.ways, nblk);
   AuxStreams* as = (allow_split && ways >= 2) ? device_streams() : nullptr;
   if (!as) {
     lk.unlock();
-    return run(0, nblk, s);
+    return finish(run(0, nblk, s));
   }
-  // part boundaries at equal shares of the work
-  double total = 0.0;
-  for (const BlockDesc& d : L.desc) total += (double)d.N * d.N * d.N;
   int bnd[MAX_SPLIT + 1];
-  bnd[0] = 0;
-  bnd[ways] = nblk;
-  {
-    double acc = 0.0;
-    int b = 0;
-    for (int p = 1; p < ways; ++p) {
-      while (b < nblk && acc < total * p / ways) {
-        acc += (double)L.desc[b].N * L.desc[b].N * L.desc[b].N;
-        ++b;
-      }
-      bnd[p] = std::min(std::max(b, bnd[p - 1] + 1), nblk - (ways - p));
-      b = bnd[p];
-    }
-  }
+  split_parts(L, ways, bnd);
   if (hipEventRecord(as->fork, s) != hipSuccess) return X2C_EHIP;
   for (int p = 1; p < ways; ++p)
     if (hipStreamWaitEvent(as->aux[p - 1], as->fork, 0) != hipSuccess) return X2C_EHIP;
@@ -981,7 +1119,7 @@ int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S
     if (hipEventRecord(as->join[p - 1], as->aux[p - 1]) != hipSuccess ||
         hipStreamWaitEvent(s, as->join[p - 1], 0) != hipSuccess)
       return X2C_EHIP;
-  return rc;
+  return finish(rc);
 }
 
 
@@ -1186,16 +1324,18 @@ int build_noalloc(const x2c_options* o, int nblk, const int* N, const int64_t* i
   for (int b = 0; b < nblk; ++b) {
     BlockDesc d;
     off = place_block(N[b], tc, in_off[b], h_off[b], eps_off[b], off, d);
+    d.orig = b;
     hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, dD + b, d);
   }
   t_untraced = true;
+  const Dims dm{L.maxN, L.maxn, L.maxm};
   int rc;
   if (tc)
-    rc = run_stages<cplx>(o, L, 0, nblk, S, T, V, W, static_cast<double*>(h), eps, nullptr, nullptr, info, ws, s,
+    rc = run_stages<cplx>(o, L, dm, 0, nblk, S, T, V, W, static_cast<double*>(h), eps, nullptr, nullptr, info, ws, s,
                           MV_RES_DEFAULT);
   else
-    rc = run_stages<double>(o, L, 0, nblk, S, T, V, W, static_cast<double*>(h), eps, nullptr, nullptr, info, ws, s,
-                            MV_RES_DEFAULT);
+    rc = run_stages<double>(o, L, dm, 0, nblk, S, T, V, W, static_cast<double*>(h), eps, nullptr, nullptr, info, ws,
+                            s, MV_RES_DEFAULT);
   t_untraced = false;
   return rc;
 }
@@ -1392,6 +1532,8 @@ void x2c_release(void) {
   {
     std::lock_guard<std::mutex> lk(g_smu);
     g_tunes.clear();
+    g_file_tunes.clear();
+    g_file_loaded = false;
   }
   std::lock_guard<std::mutex> lk(g_tmu);
   trace_collect();
@@ -1459,6 +1601,10 @@ int x2c_autotune(const x2c_options* opts, int nblk, const int* N, const int64_t*
   }
   if (rc == X2C_OK || had) {
     set(rc == X2C_OK ? best : prev);
+    if (rc == X2C_OK) {
+      std::lock_guard<std::mutex> lk(g_smu);
+      save_tune(key, best);
+    }
   } else {
     std::lock_guard<std::mutex> lk(g_smu);
     g_tunes.erase(key);
@@ -1469,6 +1615,18 @@ int x2c_autotune(const x2c_options* opts, int nblk, const int* N, const int64_t*
   if (ways_out) *ways_out = best.ways;
   if (mv_res_out) *mv_res_out = best.mv_res;
   return X2C_OK;
+}
+
+int x2c_tuned_shape(const x2c_options* opts, int nblk, const int* N, int* ways_out, int* mv_res_out) {
+  if (!valid_opts(opts) || nblk <= 0 || !N) return X2C_EINVAL;
+  Layout L;
+  if (!make_layout(opts, nblk, N, nullptr, nullptr, nullptr, L)) return X2C_EINVAL;
+  std::lock_guard<std::mutex> lk(g_smu);
+  Tune t{g_split, MV_RES_DEFAULT};
+  const bool found = tuned_locked(opts, L, &t);
+  if (ways_out) *ways_out = t.ways;
+  if (mv_res_out) *mv_res_out = t.mv_res;
+  return found ? 1 : 0;
 }
 
 int x2c_stream_split(int ways) {

@@ -174,7 +174,7 @@ struct BlockDesc {
   int N;      // scalar basis functions of the block
   int n;      // dimension of h: N (spin-free) or 2N (two-component)
   int m;      // 4c dimension 2n
-  int pad;
+  int orig;   // the caller's index of the block (descriptors are sorted by size)
   long long in_off;   // element offset of S, T, V (W: in_off, or 4*in_off in 2c)
   long long h_off;    // double offset into h
   long long eps_off;  // double offset into eps

@@ -16,6 +16,7 @@ void* ktrace_begin(const char* name, hipEvent_t* start, hipEvent_t* stop);
 void ktrace_end(void* h);
 
 void launch_init_info(hipStream_t s, int* info, int nblk);
+void launch_scatter_info(hipStream_t s, const BlockDesc* D, const int* iw, int* info, int nblk);
 void launch_unpack(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN, const double* S,
                    const double* T, const double* V, const double* W, int twocomp);
 void launch_potrf(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN);

@@ -371,6 +371,50 @@ def test_autotune_keeps_results():
         px.release()
 
 
+def test_autotune_persists_across_release(tmp_path, monkeypatch):
+    """The tuned shape is written to the cache file (keyed by architecture
+    and batch class) and comes back from it after x2c_release() has dropped
+    the in-memory copy; an empty X2C_TUNE_CACHE disables the file."""
+    px, torch = _px()
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("X2C_TUNE_CACHE", str(cache))
+    px.release()
+    blocks = [atom_block(z) for z in (6, 17, 8)]
+    bt = px.batch_to_device(pack_blocks(blocks, True), True)
+    assert px.tuned_shape(bt.Ns, True)[0] is False
+    try:
+        print("  x2c_autotune nblk=3 reps=1 (persisted)", flush=True)
+        (ways, res), _, _ = px.autotune(bt, C_LIGHT, reps=1)
+        torch.cuda.synchronize()
+        assert px.tuned_shape(bt.Ns, True) == (True, ways, res)
+        px.release()
+        assert px.tuned_shape(bt.Ns, True) == (True, ways, res)
+        line = cache.read_text().split()
+        assert line[0].startswith("gfx") and int(line[2]) == ways and int(line[3]) == res
+        assert px.tuned_shape(bt.Ns[:2], True)[0] is False          # another class
+        monkeypatch.setenv("X2C_TUNE_CACHE", "")
+        px.release()
+        assert px.tuned_shape(bt.Ns, True)[0] is False
+    finally:
+        torch.cuda.synchronize()
+        px.release()
+
+
+def test_uneven_batch_order_does_not_change_results():
+    """Blocks are run in order of decreasing size internally; per-block
+    outputs and info codes stay in the caller's order (a failing block among
+    them keeps its own code)."""
+    px, torch = _px()
+    blocks = [atom_block(z) for z in (1, 79, 8, 47, 6)]
+    ref = [gpu_batched([b], True) for b in blocks]
+    got = gpu_batched(blocks, True)
+    assert np.all(got[2] == 0)
+    for i in range(len(blocks)):
+        h1, e1 = ref[i][0][0], ref[i][1][0]
+        assert np.abs(got[0][i] - h1).max() <= TOL_H * np.abs(h1).max()
+        assert np.abs(got[1][i] - e1).max() <= TOL_EPS * np.abs(e1).max()
+
+
 def test_determinism_two_calls():
     blocks = [atom_block(z) for z in (6, 47)]
     a = gpu_batched(blocks, True)

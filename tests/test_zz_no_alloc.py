@@ -2,9 +2,13 @@
 x2c_build_batched on the same inputs, through the C ABI.
 
 Two calls in a row, the second on a smaller batch (the scratch keeps the
-first call's contents), each compared with the workspace entry point: the
-same kernels in the same order, so the outputs agree bit for bit.  A batch
-beyond the scratch is rejected before anything is enqueued.
+first call's contents), each compared with the workspace entry point at the
+parity bar of the X2C tests (h to 2e-10 of its largest entry, eps to 1e-12,
+info codes exactly): the same kernels, but the workspace entry point runs
+the blocks in size-sorted parts whose launches stop at each part's largest
+block (small spin-free blocks then take the one-work-group reduction), so
+the two agree to rounding rather than bit for bit.  A batch beyond the
+scratch is rejected before anything is enqueued.
 """
 import numpy as np
 import pytest
@@ -35,6 +39,14 @@ def run_both(px, torch, blocks, twocomp, prec=0):
     return got, ref
 
 
+def close(got, ref):
+    """Flat h and eps of the two entry points at the parity bar (h blockwise
+    against its largest entry is implied by the flat maximum, which is the
+    largest block's)."""
+    assert np.abs(got[0] - ref[0]).max() <= 2e-10 * np.abs(ref[0]).max()
+    assert np.abs(got[1] - ref[1]).max() <= 1e-12 * np.abs(ref[1]).max()
+
+
 @pytest.mark.parametrize("twocomp", [True, False])
 def test_noalloc_matches_workspace_entry_two_calls(twocomp):
     px, torch = _px()
@@ -43,16 +55,14 @@ def test_noalloc_matches_workspace_entry_two_calls(twocomp):
     for blocks in (first, second):
         got, ref = run_both(px, torch, blocks, twocomp)
         assert np.all(ref[2] == 0) and np.array_equal(got[2], ref[2])
-        assert np.array_equal(got[0], ref[0])
-        assert np.array_equal(got[1], ref[1])
+        close(got, ref)
 
 
 def test_noalloc_split_products():
     px, torch = _px()
     got, ref = run_both(px, torch, [atom_block(z) for z in (29, 1)], True, prec=px.SPLIT_INT8)
-    assert np.all(ref[2] == 0)
-    for a, b in zip(got, ref):
-        assert np.array_equal(a, b)
+    assert np.all(ref[2] == 0) and np.array_equal(got[2], ref[2])
+    close(got, ref)
 
 
 def test_noalloc_rejects_batches_beyond_the_scratch():
