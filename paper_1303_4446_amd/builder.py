@@ -34,10 +34,10 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
+def _compile(src: str, build_dir: str = BUILD_DIR, extra=()) -> str:
+    os.makedirs(build_dir, exist_ok=True)
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc(), *HIP_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
            "-x", "hip", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -45,20 +45,24 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source for gfx950 and link libx2c.so (always rebuilds)."""
+def build(verbose: bool = False, out: str = LIB, build_dir: str = BUILD_DIR, extra=()) -> str:
+    """Compile every HIP source for gfx950 and link libx2c.so (always rebuilds).
+    `out`, `build_dir` and `extra` (more hipcc flags for every step) serve
+    instrumented builds such as the host sanitizer test."""
     jobs = min(len(SOURCES), max(1, min(8, os.cpu_count() or 1)))
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", "-Wl,--no-undefined", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+        objs = list(ex.map(lambda src: _compile(src, build_dir, tuple(extra)), SOURCES))
+    tmp = out + ".tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", *extra, f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    if not extra:
+        cmd.insert(3, "-Wl,--no-undefined")
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":
