@@ -98,14 +98,37 @@ enum {
   X2C_INFO_S_NOT_SPD = 1,    /* Cholesky of S failed */
   X2C_INFO_T_NOT_SPD = 2,    /* Cholesky of T failed */
   X2C_INFO_EIGEN = 3,        /* positive-energy subspace not resolved: singular large-component block,
-                                or the gap at -c^2 too narrow for the spectral projector */
+                                or the gap at -c^2 too narrow for the spectral projector (device-wide
+                                path: a Newton-Schulz iteration did not converge) */
   X2C_INFO_BRANCH = 4,       /* number of eigenvalues with eps + c^2 > 0 differs from n */
-  X2C_INFO_RENORM = 5,       /* L_S^-1 S~ L_S^-H not positive definite */
+  X2C_INFO_RENORM = 5,       /* L_S^-1 S~ L_S^-H not positive definite (device-wide path: its
+                                inverse square root iteration did not converge) */
   X2C_INFO_NONFINITE = 6     /* NaN or Inf in S, T, V or W */
 };
 
-/* Largest supported scalar block size N for a mode (0 for an unknown mode). */
+/* Largest supported scalar block size N for a mode (0 for an unknown mode):
+ * 4096 two-component (4c dimension 16384), 8192 spin-free.  Blocks up to
+ * 256 (two-component) / 512 (spin-free) run on the batched path: one
+ * work-group per block and column step of the reductions, many blocks at
+ * once, eigenvalues eps written out.  Larger blocks (a whole molecular matrix,
+ * the full transformation that the DLU scheme of Sec. III.A approximates)
+ * run on the device-wide path, one block at a time on the whole GPU: blocked
+ * Cholesky factors, the positive-energy branch from the spectral projector
+ * (I + sign(A + c^2 I)) / 2 of the reduced 4c matrix A by a scaled
+ * Newton-Schulz iteration, X~ and Q^-1/2 by Newton-Schulz inverse and inverse
+ * square root iterations; matrix products only.  That path does not compute
+ * eigenvalues: eps of such a block is NaN (h, X and R are as on the batched
+ * path).  BSS, DKHn, the DLU assembly and x2c_build_batched_noalloc take
+ * batched-path sizes only. */
 int x2c_max_n(int mode);
+
+/* Smallest N of a block that takes the device-wide path (see x2c_max_n), per
+ * mode.  n > 0 sets it (1 .. batched limit + 1), n = 0 restores the default
+ * (batched limit + 1), n < 0 only queries.  Returns the previous (or current)
+ * value, or X2C_EINVAL for an unknown mode or n above the default.  A setting
+ * for the whole process; workspace sizes depend on it.  Not thread-safe with
+ * concurrent builds of the same mode. */
+int x2c_device_wide_min_n(int mode, int n);
 
 /*
  * Workspace size in bytes needed by x2c_build_batched for `nblk` blocks of
@@ -122,7 +145,8 @@ size_t x2c_workspace_bytes(const x2c_options* opts, int nblk, const int* N);
  *            contiguous (4 x N x N) (device).
  *   h        output: spin-free N x N float64; two-component 2N x 2N complex128 (device).
  *   eps      output: the n positive-energy eigenvalues of Eq. moddiraceq,
- *            ascending, in Hartree (n = N or 2N) (device).
+ *            ascending, in Hartree (n = N or 2N); NaN on the device-wide
+ *            path (device).
  * Synchronises `stream`.  Returns X2C_OK, X2C_EINVAL, X2C_EHIP, or
  * X2C_EBLOCK with *info_out (host, may be NULL) set to the block's info code;
  * on X2C_EBLOCK h and eps are zero.

@@ -23,7 +23,7 @@ OK, EINVAL, EHIP, EBLOCK, ESCRATCH = 0, -1, -2, -3, -4
 INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subspace not resolved",
               4: "positive-energy branch size != n", 5: "renormalisation matrix not PD", 6: "non-finite input"}
 
-EXPORTED = ("x2c_max_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_build_batched_xr",
+EXPORTED = ("x2c_max_n", "x2c_device_wide_min_n", "x2c_workspace_bytes", "x2c_build", "x2c_build_batched", "x2c_build_batched_xr",
             "x2c_build_batched_noalloc", "x2c_bss_workspace_bytes", "x2c_bss_batched", "x2c_dkh_workspace_bytes",
             "x2c_dkh_batched", "x2c_dkh_products", "x2c_tuned_shape",
             "x2c_dlu_workspace_bytes", "x2c_dlu_assemble", "x2c_strerror", "x2c_release", "x2c_graph_enable",
@@ -59,6 +59,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     optp = ctypes.POINTER(_Options)
     lib.x2c_max_n.argtypes = [i32]
     lib.x2c_max_n.restype = i32
+    lib.x2c_device_wide_min_n.argtypes = [i32, i32]
+    lib.x2c_device_wide_min_n.restype = i32
     lib.x2c_workspace_bytes.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int)]
     lib.x2c_workspace_bytes.restype = ctypes.c_size_t
     lib.x2c_build.argtypes = [optp, i32, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp,
@@ -131,6 +133,17 @@ def strerror(code: int) -> str:
 
 def max_n(twocomp: bool) -> int:
     return load().x2c_max_n(TWOCOMP if twocomp else SPINFREE)
+
+
+def device_wide_min_n(twocomp: bool, n: int | None = None) -> int:
+    """Smallest block size N that takes the device-wide path (one block at a
+    time, whole-matrix products; no eigenvalues).  With n: set it (1 .. the
+    batched limit + 1; 0 restores the default) and return the previous value;
+    without: return the current value."""
+    r = load().x2c_device_wide_min_n(TWOCOMP if twocomp else SPINFREE, -1 if n is None else int(n))
+    if r < 0:
+        raise X2CError(r, "invalid device-wide threshold")
+    return int(r)
 
 
 def workspace_bytes(Ns, twocomp: bool, c: float = 137.0, prec: int = FP64) -> int:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libx2c.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["k_prep.hip", "k_gemm.hip", "k_tridiag.hip", "k_matvec.hip", "k_spectrum.hip", "k_lu.hip", "k_kramers.hip", "k_ozaki.hip", "k_ozaki_i8.hip", "k_dlu.hip", "k_fw.hip", "x2c_dkh_plan.cpp", "x2c_api.cpp"]
+SOURCES = ["k_prep.hip", "k_gemm.hip", "k_large.hip", "k_tridiag.hip", "k_matvec.hip", "k_spectrum.hip", "k_lu.hip", "k_kramers.hip", "k_ozaki.hip", "k_ozaki_i8.hip", "k_dlu.hip", "k_fw.hip", "x2c_dkh_plan.cpp", "x2c_api.cpp"]
 
 ARCH = os.environ.get("X2C_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = [

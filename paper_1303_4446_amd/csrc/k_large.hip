@@ -1,0 +1,637 @@
+// Device-wide path of one large block: a whole molecular matrix (the full,
+// non-local transformation that the local DLU scheme of Sec. III.A
+// approximates by atomic blocks) instead of a batch of atomic blocks.
+//
+// The per-block kernels of the batched path run one work-group per block and
+// column step; a 4c matrix of dimension ~10^4 needs the whole GPU instead,
+// and a Householder reduction of it would stream the trailing matrix from
+// HBM once per column (hundreds of GB).  This path uses matrix products:
+//
+//  * the Cholesky factors L_S, L_T and their inverses are blocked in 64 x 64
+//    tiles (one launch per panel step: diagonal tile, panel, trailing update;
+//    then one launch per tile row of the inverse);
+//  * the positive-energy branch (eps + c^2 > 0, Sec. II) of the reduced 4c
+//    matrix A is taken from the spectral projector
+//      P = (I + sign(A + c^2 I)) / 2,
+//    computed by a scaled Newton-Schulz iteration X <- a X - b X^3 on
+//    X_0 = (A + c^2 I) / ||A + c^2 I||_F (two Hermitian products per step);
+//  * with the column blocks of P on the large-component unit vectors,
+//    X~ = P_SL P_LL^-1: if Y = [Y_L; Y_S] spans the positive branch
+//    (orthonormal), P_LL = Y_L Y_L^H, P_SL = Y_S Y_L^H and P_SL P_LL^-1 =
+//    Y_S Y_L^-1, the X~ of Eq. defxmat in the reduced basis.  P_LL^-1 comes
+//    from the Newton-Schulz inverse iteration Z <- Z (2I - P_LL Z);
+//  * Q^-1/2 for the renormalisation (Eq. ulnonortho) from the coupled
+//    Newton-Schulz iteration Y <- Y U, Z <- U Z, U = (3I - Z Y) / 2 on
+//    Y_0 = Q / alpha (alpha >= the largest eigenvalue, a row-sum bound).
+//
+// Every iterate is a polynomial in one Hermitian matrix, so every product is
+// Hermitian and runs as a lower-triangle product (half the tiles).  The
+// iterations stop on the device: a gate word, passed to the product kernels
+// in place of the block status, turns the remaining launches of a converged
+// iteration into no-ops, so the host enqueues a fixed number of steps and
+// never waits.  The element type T is double (spin-free, 4c dimension 2N),
+// cplx (two-component, complex form, 4N) or quat (two-component quaternion
+// form, 2N quaternions).
+#include "x2c_device.h"
+#include "x2c_launch.h"
+
+namespace x2c {
+
+// ---------------------------------------------------------------- blocked Cholesky
+constexpr int LT = 64;   // tile edge
+
+// Factor the diagonal tile at k0 of L_S (blockIdx.x = 0) or L_T (1), which
+// holds S or T minus the updates of the earlier panels, and write the tile's
+// inverse into the diagonal tile of L_S^-1 / L_T^-1.  Rows and columns past
+// N are treated as the identity.
+__global__ void __launch_bounds__(256) k_lchol_diag(const BlockDesc* D, char* ws, int* info, int k0) {
+  const BlockDesc& d = D[0];
+  if (info[0]) return;
+  const int which = blockIdx.x, N = d.N;
+  double* A = bufp<double>(ws, d, which ? R_LT : R_LS);
+  double* X = bufp<double>(ws, d, which ? R_LTI : R_LSI);
+  __shared__ double a[LT][LT + 1], x[LT][LT + 1];
+  __shared__ int fail;
+  const int t = threadIdx.x;
+  const int nb = min(LT, N - k0);
+  for (int e = t; e < LT * LT; e += 256) {
+    const int r = e / LT, c = e % LT;
+    double v = 0.0;
+    if (r < nb && c < nb) {
+      if (c <= r) v = A[(long long)(k0 + r) * N + k0 + c];
+    } else if (r == c) {
+      v = 1.0;
+    }
+    a[r][c] = v;
+  }
+  if (t == 0) fail = 0;
+  __syncthreads();
+  for (int j = 0; j < LT; ++j) {
+    if (t == 0) {
+      const double p = a[j][j];
+      if (!(p > 0.0) || !isfinite(p)) fail = 1;
+      else a[j][j] = sqrt(p);
+    }
+    __syncthreads();
+    if (fail) break;
+    const double inv = 1.0 / a[j][j];
+    for (int r = j + 1 + t; r < LT; r += 256) a[r][j] *= inv;
+    __syncthreads();
+    for (int e = t; e < LT * LT; e += 256) {
+      const int r = e / LT, c = e % LT;
+      if (c > j && r >= c) a[r][c] -= a[r][j] * a[c][j];
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    // S failing takes precedence over T failing
+    if (t == 0) {
+      if (which == 0) atomicExch(&info[0], 1);
+      else atomicCAS(&info[0], 0, 2);
+    }
+    return;
+  }
+  // inverse of the lower-triangular tile, one column per thread
+  if (t < LT) {
+    const int c = t;
+    for (int i = 0; i < LT; ++i) {
+      if (i < c) {
+        x[i][c] = 0.0;
+        continue;
+      }
+      double s = i == c ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s = fma(-a[i][k], x[k][c], s);
+      x[i][c] = s / a[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < nb * nb; e += 256) {
+    const int r = e / nb, c = e % nb;
+    A[(long long)(k0 + r) * N + k0 + c] = c <= r ? a[r][c] : 0.0;
+    X[(long long)(k0 + r) * N + k0 + c] = c <= r ? x[r][c] : 0.0;
+  }
+}
+
+// 64 x 64 x 64 tile product on 256 threads (4 x 4 outputs each):
+// acc[i][j] += sum_q p[tr + 16 i][q] * qt[tc + 16 j][q]  (B given transposed)
+__device__ inline void tile_nt(const double (*p)[LT + 1], const double (*qt)[LT + 1], double acc[4][4], int tr,
+                               int tc) {
+  for (int q = 0; q < LT; ++q) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      av[i] = p[tr + 16 * i][q];
+      bv[i] = qt[tc + 16 * i][q];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+  }
+}
+
+// Panel below the diagonal tile: L_ik = A_ik L_kk^-T, one tile per
+// work-group (grid: row tiles below k0, matrix).
+__global__ void __launch_bounds__(256) k_lchol_panel(const BlockDesc* D, char* ws, const int* info, int k0) {
+  const BlockDesc& d = D[0];
+  if (info[0]) return;
+  const int N = d.N, which = blockIdx.y;
+  const int i0 = k0 + LT * (1 + blockIdx.x);
+  if (i0 >= N) return;
+  double* A = bufp<double>(ws, d, which ? R_LT : R_LS);
+  const double* X = bufp<double>(ws, d, which ? R_LTI : R_LSI);
+  __shared__ double a[LT][LT + 1], x[LT][LT + 1];
+  const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
+  const int rb = min(LT, N - i0), kb = min(LT, N - k0);
+  for (int e = t; e < LT * LT; e += 256) {
+    const int r = e / LT, c = e % LT;
+    a[r][c] = (r < rb && c < kb) ? A[(long long)(i0 + r) * N + k0 + c] : 0.0;
+    x[r][c] = (r < kb && c <= r) ? X[(long long)(k0 + r) * N + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  double acc[4][4] = {};
+  tile_nt(a, x, acc, tr, tc);   // (A_ik L_kk^-T)[r][c] = sum_q A_ik[r][q] Linv[c][q]
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = tr + 16 * i, c = tc + 16 * j;
+      if (r < rb && c < kb) A[(long long)(i0 + r) * N + k0 + c] = acc[i][j];
+    }
+}
+
+// Trailing update A_ij -= L_ik L_jk^T for the tiles j <= i below the panel
+// (grid: lower tile pairs, matrix).
+__global__ void __launch_bounds__(256) k_lchol_update(const BlockDesc* D, char* ws, const int* info, int k0) {
+  const BlockDesc& d = D[0];
+  if (info[0]) return;
+  const int N = d.N, which = blockIdx.y;
+  const int p = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= p) ++ti;
+  while (ti * (ti + 1) / 2 > p) --ti;
+  const int tj = p - ti * (ti + 1) / 2;
+  const int i0 = k0 + LT * (1 + ti), j0 = k0 + LT * (1 + tj);
+  if (i0 >= N || j0 >= N) return;
+  double* A = bufp<double>(ws, d, which ? R_LT : R_LS);
+  __shared__ double li[LT][LT + 1], lj[LT][LT + 1];
+  const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
+  const int rb = min(LT, N - i0), cb = min(LT, N - j0), kb = min(LT, N - k0);
+  for (int e = t; e < LT * LT; e += 256) {
+    const int r = e / LT, q = e % LT;
+    li[r][q] = (r < rb && q < kb) ? A[(long long)(i0 + r) * N + k0 + q] : 0.0;
+    lj[r][q] = (r < cb && q < kb) ? A[(long long)(j0 + r) * N + k0 + q] : 0.0;
+  }
+  __syncthreads();
+  double acc[4][4] = {};
+  tile_nt(li, lj, acc, tr, tc);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = tr + 16 * i, c = tc + 16 * j;
+      if (r < rb && c < cb) A[(long long)(i0 + r) * N + j0 + c] -= acc[i][j];
+    }
+}
+
+// Tile row ti of the inverse X = L^-1 (tiles j < ti; the diagonal tiles come
+// from k_lchol_diag):  X_ij = -X_ii sum_{j <= k < i} L_ik X_kj.
+__global__ void __launch_bounds__(256) k_ltri_row(const BlockDesc* D, char* ws, const int* info, int ti) {
+  const BlockDesc& d = D[0];
+  if (info[0]) return;
+  const int N = d.N, which = blockIdx.y, tj = blockIdx.x;
+  const double* L = bufp<double>(ws, d, which ? R_LT : R_LS);
+  double* X = bufp<double>(ws, d, which ? R_LTI : R_LSI);
+  __shared__ double l[LT][LT + 1], xt[LT][LT + 1];
+  const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
+  const int i0 = ti * LT, j0 = tj * LT, rb = min(LT, N - i0);
+  double acc[4][4] = {};
+  for (int tk = tj; tk < ti; ++tk) {
+    const int k0 = tk * LT;
+    __syncthreads();
+    for (int e = t; e < LT * LT; e += 256) {
+      const int r = e / LT, q = e % LT;
+      l[r][q] = r < rb ? L[(long long)(i0 + r) * N + k0 + q] : 0.0;
+      // transposed: xt[c][q] = X[k0 + q][j0 + c] (tiles k < i are full)
+      xt[q][r] = X[(long long)(k0 + r) * N + j0 + q];
+    }
+    __syncthreads();
+    tile_nt(l, xt, acc, tr, tc);
+  }
+  __syncthreads();
+  // s = acc (rows of the sum), then X_ij = -X_ii s
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) xt[tc + 16 * j][tr + 16 * i] = acc[i][j];   // xt[c][r] = s[r][c]
+  for (int e = t; e < LT * LT; e += 256) {
+    const int r = e / LT, q = e % LT;
+    l[r][q] = (r < rb && q <= r) ? X[(long long)(i0 + r) * N + i0 + q] : 0.0;
+  }
+  __syncthreads();
+  double out[4][4] = {};
+  tile_nt(l, xt, out, tr, tc);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = tr + 16 * i, c = tc + 16 * j;
+      if (r < rb) X[(long long)(i0 + r) * N + j0 + c] = -out[i][j];
+    }
+}
+
+// zero the strict upper triangles of L_S, L_T, L_S^-1, L_T^-1 (blockIdx.y)
+__global__ void k_lzero_upper(const BlockDesc* D, char* ws, const int* info) {
+  const BlockDesc& d = D[0];
+  if (info[0]) return;
+  const int ids[4] = {R_LS, R_LT, R_LSI, R_LTI};
+  double* A = bufp<double>(ws, d, ids[blockIdx.y]);
+  const int N = d.N;
+  const long long NN = (long long)N * N;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < NN; e += (long long)gridDim.x * blockDim.x)
+    if (e % N > e / N) A[e] = 0.0;
+}
+
+static int egrid(long long tot) {
+  long long g = (tot + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+void launch_large_cholesky(hipStream_t s, const BlockDesc* D, char* ws, int* info, int N) {
+  const int nt = (N + LT - 1) / LT;
+  for (int k = 0; k < nt; ++k) {
+    const int k0 = k * LT, r = nt - k - 1;
+    hipLaunchKernelGGL(k_lchol_diag, dim3(2), dim3(256), 0, s, D, ws, info, k0);
+    if (r == 0) break;
+    hipLaunchKernelGGL(k_lchol_panel, dim3(r, 2), dim3(256), 0, s, D, ws, info, k0);
+    hipLaunchKernelGGL(k_lchol_update, dim3(r * (r + 1) / 2, 2), dim3(256), 0, s, D, ws, info, k0);
+  }
+  for (int i = 1; i < nt; ++i) hipLaunchKernelGGL(k_ltri_row, dim3(i, 2), dim3(256), 0, s, D, ws, info, i);
+  hipLaunchKernelGGL(k_lzero_upper, dim3(egrid((long long)N * N), 4), dim3(256), 0, s, D, ws, info);
+}
+
+// ---------------------------------------------------------------- Newton-Schulz iterations
+// scaled cubic p(x) = a x - b x^3 for a spectrum in [l, 1] (in modulus):
+// a^2 = 27 (1 - l) / (4 (1 - l^3)) equalises p(l) and p(1), b = 4 a^3 / 27
+// puts the maximum p = 1 at x = 3 / (2a); a >= 3/2 (3/2 is the plain
+// Newton-Schulz step, the limit l -> 1).  Small moduli grow by a (up to
+// 3 sqrt3 / 2) per step; the new lower bound is min(p(l), p(1)).
+__device__ inline void ns_cubic(double l, double& a, double& b, double& lnext) {
+  a = sqrt(27.0 * (1.0 - l) / (4.0 * (1.0 - l * l * l)));
+  if (!(a >= 1.5)) a = 1.5;
+  b = 4.0 * a * a * a / 27.0;
+  lnext = fmin(a * l - b * l * l * l, a - b);
+  if (!(lnext > 0.0)) lnext = l;
+}
+
+__device__ inline NsPar* nspar(char* ws, const BlockDesc& d) { return bufp<NsPar>(ws, d, V_NS); }
+
+// start of an iteration phase: the gate follows the block status
+__global__ void k_ns_begin(const BlockDesc* D, char* ws, const int* info) {
+  NsPar* p = nspar(ws, D[0]);
+  p->gate = info[0];
+  p->conv = 0;
+  p->iters = 0;
+  p->acc = 0.0;
+  p->acc2 = 0.0;
+  p->rmax = 0ull;
+}
+
+// end of a phase: an iteration that did not converge fails the block
+__global__ void k_ns_end(const BlockDesc* D, char* ws, int* info, int code) {
+  NsPar* p = nspar(ws, D[0]);
+  if (info[0] == 0 && !p->conv) info[0] = code;
+  p->gate = info[0];
+}
+
+// ||A - sigma I||_F^2 into acc
+template <class T>
+__global__ void k_ns_fro(const BlockDesc* D, char* ws, int dsel, int buf, double sigma) {
+  const BlockDesc& d = D[0];
+  NsPar* p = nspar(ws, d);
+  if (p->gate) return;
+  __shared__ double sh[16];
+  const int n = seldim(d, dsel);
+  const T* A = bufp<T>(ws, d, buf);
+  const long long tot = (long long)n * n;
+  double s = 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    T v = A[e];
+    if (e / n == e % n) v = v - treal<T>(sigma);
+    s += abs2(v);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) atomicAdd(&p->acc, s);
+}
+
+// rho = ||A - sigma I||_F, X_0 = (A - sigma I) / rho in place, and the first
+// lower bound l_0 = gap / rho from the expected half-width of the gap
+__global__ void k_ns_start(const BlockDesc* D, char* ws, double sigma, double gap) {
+  NsPar* p = nspar(ws, D[0]);
+  if (p->gate) return;
+  double rho = sqrt(p->acc);
+  if (!(rho > 0.0) || !isfinite(rho)) {
+    p->gate = 1;   // no convergence: the phase end fails the block
+    return;
+  }
+  p->sigma = sigma;
+  p->rho = rho;
+  p->l = fmin(fmax(gap / rho, 1e-14), 0.99);
+  p->acc = 0.0;
+}
+
+template <class T>
+__global__ void k_ns_shift(const BlockDesc* D, char* ws, int dsel, int buf) {
+  const BlockDesc& d = D[0];
+  const NsPar* p = nspar(ws, d);
+  if (p->gate) return;
+  const int n = seldim(d, dsel);
+  T* A = bufp<T>(ws, d, buf);
+  const double inv = 1.0 / p->rho, sigma = p->sigma;
+  const long long tot = (long long)n * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    T v = A[e];
+    if (e / n == e % n) v = v - treal<T>(sigma);
+    A[e] = inv * v;
+  }
+}
+
+// polynomial factor of one step, in place on U = (product):
+//   kind 0 (sign):         U <- a I - b U   (U = X^2; scaled cubic of l)
+//   kind 1 (inverse):      U <- 2 I - U     (U = P Z)
+//   kind 2 (inverse sqrt): U <- (3 I - U) / 2  (U = Z Y)
+template <class T>
+__global__ void k_ns_poly(const BlockDesc* D, char* ws, int dsel, int buf, int kind) {
+  const BlockDesc& d = D[0];
+  const NsPar* p = nspar(ws, d);
+  if (p->gate) return;
+  const int n = seldim(d, dsel);
+  T* U = bufp<T>(ws, d, buf);
+  double dg, sc;
+  if (kind == 0) {
+    double a, b, ln;
+    ns_cubic(p->l, a, b, ln);
+    dg = a;
+    sc = -b;
+  } else if (kind == 1) {
+    dg = 2.0;
+    sc = -1.0;
+  } else {
+    dg = 1.5;
+    sc = -0.5;
+  }
+  const long long tot = (long long)n * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    T v = sc * U[e];
+    if (e / n == e % n) v = v + treal<T>(dg);
+    U[e] = v;
+  }
+}
+
+// dst <- src; with diff, acc += ||src - dst||_F^2 and acc2 += ||src||_F^2
+template <class T>
+__global__ void k_ns_accept(const BlockDesc* D, char* ws, int dsel, int src, int dst, int diff) {
+  const BlockDesc& d = D[0];
+  NsPar* p = nspar(ws, d);
+  if (p->gate) return;
+  __shared__ double sh[16];
+  const int n = seldim(d, dsel);
+  const T* S = bufp<T>(ws, d, src);
+  T* X = bufp<T>(ws, d, dst);
+  const long long tot = (long long)n * n;
+  double s1 = 0.0, s2 = 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const T v = S[e];
+    if (diff) {
+      s1 += abs2(v - X[e]);
+      s2 += abs2(v);
+    }
+    X[e] = v;
+  }
+  if (!diff) return;
+  s1 = block_sum(s1, sh);
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    atomicAdd(&p->acc, s1);
+    atomicAdd(&p->acc2, s2);
+  }
+}
+
+// end of a step: relative change d = ||X_new - X||_F / ||X_new||_F; the
+// iteration has converged once d <= tol (the next error is O(d^2))
+__global__ void k_ns_check(const BlockDesc* D, char* ws, int kind, double tol) {
+  NsPar* p = nspar(ws, D[0]);
+  if (p->gate) return;
+  p->iters += 1;
+  const double dd = sqrt(p->acc / fmax(p->acc2, 1e-300));
+  p->acc = 0.0;
+  p->acc2 = 0.0;
+  if (kind == 0) {
+    double a, b, ln;
+    ns_cubic(p->l, a, b, ln);
+    p->l = ln;
+  }
+  if (dd <= tol) {
+    p->conv = 1;
+    p->gate = 1;
+  }
+}
+
+// trace of the converged sign: the positive and negative branches must be
+// equally large (Sec. II), i.e. trace 0 (one work-group)
+template <class T>
+__global__ void k_ns_trace(const BlockDesc* D, char* ws, int* info, int dsel, int buf) {
+  const BlockDesc& d = D[0];
+  if (info[0]) return;
+  __shared__ double sh[16];
+  const int n = seldim(d, dsel);
+  const T* X = bufp<T>(ws, d, buf);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += re(X[(long long)i * n + i]);
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0 && !(fabs(s) < 0.5)) info[0] = 4;
+}
+
+// P = (I + X) / 2 on the large-component columns: P_LL = (I + X_LL) / 2,
+// P_SL = X_SL / 2 (h-sized, dimension h = 4c dimension / 2)
+template <class T>
+__global__ void k_ns_split(const BlockDesc* D, char* ws, const int* info, int dsel4, int bufX, int bufLL, int bufSL) {
+  const BlockDesc& d = D[0];
+  if (info[0]) return;
+  const int n4 = seldim(d, dsel4), h = n4 / 2;
+  const T* X = bufp<T>(ws, d, bufX);
+  T* PLL = bufp<T>(ws, d, bufLL);
+  T* PSL = bufp<T>(ws, d, bufSL);
+  const long long tot = (long long)h * h;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / h), j = (int)(e % h);
+    T v = 0.5 * X[(long long)i * n4 + j];
+    if (i == j) v = v + treal<T>(0.5);
+    PLL[e] = v;
+    PSL[e] = 0.5 * X[(long long)(h + i) * n4 + j];
+  }
+}
+
+template <class T>
+__global__ void k_ns_eye(const BlockDesc* D, char* ws, const int* info, int dsel, int buf) {
+  const BlockDesc& d = D[0];
+  if (info[0]) return;
+  const int n = seldim(d, dsel);
+  T* A = bufp<T>(ws, d, buf);
+  const long long tot = (long long)n * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x)
+    A[e] = treal<T>(e / n == e % n ? 1.0 : 0.0);
+}
+
+// largest row sum of moduli (>= the largest eigenvalue), one wave per row;
+// non-negative doubles order like their bit patterns
+template <class T>
+__global__ void k_ns_rowmax(const BlockDesc* D, char* ws, int dsel, int buf) {
+  const BlockDesc& d = D[0];
+  NsPar* p = nspar(ws, d);
+  if (p->gate) return;
+  const int n = seldim(d, dsel);
+  const T* A = bufp<T>(ws, d, buf);
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += sqrt(abs2(A[(long long)row * n + j]));
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) atomicMax(&p->rmax, (unsigned long long)__double_as_longlong(s));
+}
+
+// Y_0 = Q / alpha with alpha the row-sum bound
+template <class T>
+__global__ void k_ns_isq_start(const BlockDesc* D, char* ws, int dsel, int bufQ, int bufY) {
+  const BlockDesc& d = D[0];
+  NsPar* p = nspar(ws, d);
+  if (p->gate) return;
+  const double alpha = __longlong_as_double((long long)p->rmax);
+  if (!(alpha > 0.0) || !isfinite(alpha)) return;   // the phase end fails the block
+  if (blockIdx.x == 0 && threadIdx.x == 0) p->alpha = alpha;
+  const int n = seldim(d, dsel);
+  const T* Q = bufp<T>(ws, d, bufQ);
+  T* Y = bufp<T>(ws, d, bufY);
+  const double inv = 1.0 / alpha;
+  const long long tot = (long long)n * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x)
+    Y[e] = inv * Q[e];
+}
+
+// Q^-1/2 = Z / sqrt(alpha)
+template <class T>
+__global__ void k_ns_isq_finish(const BlockDesc* D, char* ws, const int* info, int dsel, int bufZ, int bufOut) {
+  const BlockDesc& d = D[0];
+  if (info[0]) return;
+  const NsPar* p = nspar(ws, d);
+  const int n = seldim(d, dsel);
+  const T* Z = bufp<T>(ws, d, bufZ);
+  T* O = bufp<T>(ws, d, bufOut);
+  const double sc = 1.0 / sqrt(p->alpha);
+  const long long tot = (long long)n * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x)
+    O[e] = sc * Z[e];
+}
+
+// eigenvalues are not produced by this path: NaN marks them
+__global__ void k_eps_nan(const BlockDesc* D, double* eps) {
+  const BlockDesc& d = D[0];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.n; k += gridDim.x * blockDim.x)
+    eps[d.eps_off + k] = __longlong_as_double(0x7ff8000000000000ll);
+}
+
+// ---------------------------------------------------------------- host side
+namespace {
+int* gate_of(const BlockDesc& hd, char* ws) {
+  return reinterpret_cast<int*>(ws + hd.off[V_NS] + offsetof(NsPar, gate));
+}
+
+template <class T>
+void gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* gate, int dim, int dsel, int A, int B, int C,
+          int herm) {
+  if constexpr (is_quat<T>()) launch_gemm_q(s, D, ws, gate, 1, dim, dsel, A, 0, B, 0, C, 1.0, 0.0, herm);
+  else launch_gemm<T>(s, D, ws, gate, 1, dim, dsel, A, 0, B, 0, C, treal<T>(1.0), tzero<T>(), herm, 0);
+}
+}  // namespace
+
+template <class T>
+void launch_large_sign(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
+                       int dim4, int bufX, int bufU, int bufN, double c, int maxit, double tol) {
+  const int* gate = gate_of(hd, ws);
+  const long long tot = (long long)dim4 * dim4;
+  const double sigma = -c * c;
+  hipLaunchKernelGGL(k_ns_begin, dim3(1), dim3(1), 0, s, D, ws, info);
+  hipLaunchKernelGGL(k_ns_fro<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufX, sigma);
+  hipLaunchKernelGGL(k_ns_start, dim3(1), dim3(1), 0, s, D, ws, sigma, 0.5 * c * c);
+  hipLaunchKernelGGL(k_ns_shift<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufX);
+  for (int it = 0; it < maxit; ++it) {
+    gemm<T>(s, D, ws, gate, dim4, dsel4, bufX, bufX, bufU, 1);
+    hipLaunchKernelGGL(k_ns_poly<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufU, 0);
+    gemm<T>(s, D, ws, gate, dim4, dsel4, bufX, bufU, bufN, 1);
+    hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufN, bufX, 1);
+    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(1), 0, s, D, ws, 0, tol);
+  }
+  hipLaunchKernelGGL(k_ns_end, dim3(1), dim3(1), 0, s, D, ws, info, 3);
+  hipLaunchKernelGGL(k_ns_trace<T>, dim3(1), dim3(256), 0, s, D, ws, info, dsel4, bufX);
+}
+
+template <class T>
+void launch_large_xtilde(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
+                         int dselh, int dimh, int bufX, int bufPLL, int bufPSL, int bufZ, int bufU, int bufN,
+                         int bufOut, int maxit, double tol) {
+  const int* gate = gate_of(hd, ws);
+  const long long tot = (long long)dimh * dimh;
+  hipLaunchKernelGGL(k_ns_split<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dsel4, bufX, bufPLL, bufPSL);
+  hipLaunchKernelGGL(k_ns_eye<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dselh, bufZ);
+  hipLaunchKernelGGL(k_ns_begin, dim3(1), dim3(1), 0, s, D, ws, info);
+  for (int it = 0; it < maxit; ++it) {
+    gemm<T>(s, D, ws, gate, dimh, dselh, bufPLL, bufZ, bufU, 1);
+    hipLaunchKernelGGL(k_ns_poly<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufU, 1);
+    gemm<T>(s, D, ws, gate, dimh, dselh, bufZ, bufU, bufN, 1);
+    hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufN, bufZ, 1);
+    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(1), 0, s, D, ws, 1, tol);
+  }
+  hipLaunchKernelGGL(k_ns_end, dim3(1), dim3(1), 0, s, D, ws, info, 3);
+  // X~ = P_SL P_LL^-1 (a general product: the gate is the block status again)
+  gemm<T>(s, D, ws, gate, dimh, dselh, bufPSL, bufZ, bufOut, 0);
+}
+
+template <class T>
+void launch_large_invsqrt(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dselh,
+                          int dimh, int bufQ, int bufY, int bufZ, int bufU, int bufN, int bufOut, int maxit,
+                          double tol) {
+  const int* gate = gate_of(hd, ws);
+  const long long tot = (long long)dimh * dimh;
+  hipLaunchKernelGGL(k_ns_begin, dim3(1), dim3(1), 0, s, D, ws, info);
+  hipLaunchKernelGGL(k_ns_rowmax<T>, dim3((dimh + 3) / 4), dim3(256), 0, s, D, ws, dselh, bufQ);
+  hipLaunchKernelGGL(k_ns_isq_start<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufQ, bufY);
+  hipLaunchKernelGGL(k_ns_eye<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dselh, bufZ);
+  for (int it = 0; it < maxit; ++it) {
+    gemm<T>(s, D, ws, gate, dimh, dselh, bufZ, bufY, bufU, 1);
+    hipLaunchKernelGGL(k_ns_poly<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufU, 2);
+    gemm<T>(s, D, ws, gate, dimh, dselh, bufY, bufU, bufN, 1);
+    hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufN, bufY, 0);
+    gemm<T>(s, D, ws, gate, dimh, dselh, bufU, bufZ, bufN, 1);
+    hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufN, bufZ, 1);
+    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(1), 0, s, D, ws, 2, tol);
+  }
+  hipLaunchKernelGGL(k_ns_end, dim3(1), dim3(1), 0, s, D, ws, info, 5);
+  hipLaunchKernelGGL(k_ns_isq_finish<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dselh, bufZ, bufOut);
+}
+
+void launch_eps_nan(hipStream_t s, const BlockDesc* D, double* eps) {
+  hipLaunchKernelGGL(k_eps_nan, dim3(16), dim3(256), 0, s, D, eps);
+}
+
+#define X2C_LARGE_INST(T)                                                                                          \
+  template void launch_large_sign<T>(hipStream_t, const BlockDesc*, const BlockDesc&, char*, int*, int, int, int, \
+                                     int, int, double, int, double);                                              \
+  template void launch_large_xtilde<T>(hipStream_t, const BlockDesc*, const BlockDesc&, char*, int*, int, int,    \
+                                       int, int, int, int, int, int, int, int, int, double);                      \
+  template void launch_large_invsqrt<T>(hipStream_t, const BlockDesc*, const BlockDesc&, char*, int*, int, int,   \
+                                        int, int, int, int, int, int, int, double);
+X2C_LARGE_INST(double)
+X2C_LARGE_INST(cplx)
+X2C_LARGE_INST(quat)
+
+}  // namespace x2c

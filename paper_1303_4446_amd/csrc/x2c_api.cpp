@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -25,8 +26,16 @@ using namespace x2c;
 
 namespace {
 
+// batched path (one work-group per block and column step)
 constexpr int MAX_N_2C = 256;   // 4c dimension 4N <= 1024
 constexpr int MAX_N_SF = 512;   // 4c dimension 2N <= 1024
+// device-wide path (one block at a time; products of the whole matrix)
+constexpr int WIDE_MAX_N_2C = 4096;
+constexpr int WIDE_MAX_N_SF = 8192;
+// Newton-Schulz iterations of the device-wide path: step limits and the
+// relative step change that ends them
+constexpr int NS_SIGN_IT = 48, NS_AUX_IT = 24;
+constexpr double NS_TOL = 1e-10;
 constexpr int MAX_SLICES = 8;   // split products: slices per operand
 // default slice counts: bound-state (and relative continuum) errors at the
 // FP64 level up to Z = 79 (bf16 slices carry 7 bits each, int8 slices of
@@ -45,6 +54,7 @@ struct Layout {
   BlockDesc* pinned = nullptr;     // page-locked copy of desc for the upload
   int maxN = 0, maxn = 0, maxm = 0;
   int fw = -1;                     // -1: X2C; 0: BSS; k > 0: DKHk
+  int nlarge = 0;                  // leading descriptors on the device-wide path
   ~Layout() {
     if (pinned) (void)hipHostFree(pinned);
   }
@@ -61,7 +71,7 @@ struct Dims {
 // byte sizes of the named buffers for one block; fw: -1 X2C, 0 BSS (X2C plus
 // the free-particle FW buffers), k > 0 DKHk (FW buffers and the term slots,
 // none of the 4c buffers)
-void block_sizes(int N, bool tc, size_t sz[NBUF], int fw = -1) {
+void block_sizes(int N, bool tc, size_t sz[NBUF], int fw = -1, bool large = false) {
   const size_t n = tc ? 2 * (size_t)N : (size_t)N;
   const size_t m = 2 * n;
   const size_t es = tc ? 16 : 8;
@@ -121,6 +131,15 @@ void block_sizes(int N, bool tc, size_t sz[NBUF], int fw = -1) {
       for (int i : {C_A, C_Y, Z_SCR, F_FAC, Q_FAC, W_TF4, Z_SLA, Z_SLB, P_FILT, V_D, V_E, V_TAU}) sz[i] = 0;
     }
   }
+  if (large) {
+    // no reductions, eigenvalue or filter solves; the iterations' matrices
+    for (int i : {C_Y, Z_SCR, V_D, V_E, V_TAU, V_DQ, V_EQ, V_TAUQ, V_PIV, P_FILT, P_QUAD, F_FAC, Q_FAC, W_TF4, W_TFQ,
+                  W_PAN, W_HS, W_VCUR, V_ET, V_DEL})
+      sz[i] = 0;
+    sz[C_G1] = sz[C_G2] = m * m * es;
+    for (int i = H_A; i <= H_E; ++i) sz[i] = n * n * es;
+    sz[V_NS] = sizeof(NsPar);
+  }
 }
 
 bool valid_opts(const x2c_options* o) {
@@ -133,12 +152,17 @@ bool valid_opts(const x2c_options* o) {
   return true;
 }
 
-int max_n(int mode) { return mode == X2C_TWOCOMP ? MAX_N_2C : (mode == X2C_SPINFREE ? MAX_N_SF : 0); }
+int small_max_n(int mode) { return mode == X2C_TWOCOMP ? MAX_N_2C : (mode == X2C_SPINFREE ? MAX_N_SF : 0); }
+int max_n(int mode) { return mode == X2C_TWOCOMP ? WIDE_MAX_N_2C : (mode == X2C_SPINFREE ? WIDE_MAX_N_SF : 0); }
+
+// smallest N that takes the device-wide path, per mode (x2c_device_wide_min_n)
+std::atomic<int> g_wide_from[3] = {{0}, {MAX_N_SF + 1}, {MAX_N_2C + 1}};
+int wide_from(int mode) { return (mode == X2C_TWOCOMP || mode == X2C_SPINFREE) ? g_wide_from[mode].load() : 0; }
 
 // Descriptor of one block whose buffers start at workspace byte `off`;
 // returns the end of its region.
 size_t place_block(int N, bool tc, int64_t in_off, int64_t h_off, int64_t eps_off, size_t off, BlockDesc& d,
-                   int fw = -1) {
+                   int fw = -1, bool large = false) {
   std::memset(&d, 0, sizeof(d));
   d.N = N;
   d.n = tc ? 2 * N : N;
@@ -147,7 +171,7 @@ size_t place_block(int N, bool tc, int64_t in_off, int64_t h_off, int64_t eps_of
   d.h_off = h_off;
   d.eps_off = eps_off;
   size_t sz[NBUF];
-  block_sizes(N, tc, sz, fw);
+  block_sizes(N, tc, sz, fw, large);
   for (int i = 0; i < NBUF; ++i) {
     d.off[i] = (long long)off;
     off += align_up(sz[i] ? sz[i] : 8);
@@ -159,16 +183,19 @@ bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in
                  const int64_t* eps_off, Layout& L, int fw = -1) {
   if (nblk <= 0 || !N) return false;
   const bool tc = o->mode == X2C_TWOCOMP;
-  const int mx = max_n(o->mode);
+  // BSS and DKHn run on the batched path only
+  const int mx = fw >= 0 ? small_max_n(o->mode) : max_n(o->mode);
+  const int wf = fw >= 0 ? mx + 1 : wide_from(o->mode);
   L.info_off = 0;
   L.desc_off = align_up((size_t)nblk * sizeof(int));
   L.head = align_up(L.desc_off + (size_t)nblk * sizeof(BlockDesc));
   L.desc.resize(nblk);
   size_t off = L.head;
   L.maxN = L.maxn = L.maxm = 0;
+  L.nlarge = 0;
   // descriptors in order of decreasing size (stable): the parts of a split
   // batch then hold blocks of similar size, and each part's column loops stop
-  // at its own largest block
+  // at its own largest block; blocks of the device-wide path come first
   std::vector<int> order(nblk);
   for (int b = 0; b < nblk; ++b) order[b] = b;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return N[a] > N[b]; });
@@ -176,8 +203,11 @@ bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in
     const int b = order[k];
     if (N[b] <= 0 || N[b] > mx) return false;
     BlockDesc& d = L.desc[k];
-    off = place_block(N[b], tc, in_off ? in_off[b] : 0, h_off ? h_off[b] : 0, eps_off ? eps_off[b] : 0, off, d, fw);
+    const bool large = N[b] >= wf;
+    off = place_block(N[b], tc, in_off ? in_off[b] : 0, h_off ? h_off[b] : 0, eps_off ? eps_off[b] : 0, off, d, fw,
+                      large);
     d.orig = b;
+    if (large) ++L.nlarge;
     if (d.N > L.maxN) L.maxN = d.N;
     if (d.n > L.maxn) L.maxn = d.n;
     if (d.m > L.maxm) L.maxm = d.m;
@@ -198,6 +228,7 @@ std::shared_ptr<Layout> get_plan(const x2c_options* o, int nblk, const int* N, c
   key.reserve(4 * (size_t)nblk + 3);
   key.push_back(o->mode);
   key.push_back(fw);
+  key.push_back(wide_from(o->mode));
   key.push_back(nblk);
   for (int b = 0; b < nblk; ++b) {
     key.push_back(N[b]);
@@ -238,7 +269,7 @@ struct DluPlan {
 bool make_dlu_plan(const x2c_options* o, int natom, const int* N, const int64_t* u_off, DluPlan& P) {
   const bool tc = o->mode == X2C_TWOCOMP;
   const size_t es = tc ? 16 : 8;
-  const int mx = max_n(o->mode);
+  const int mx = small_max_n(o->mode);
   std::vector<int> off(natom, 0);
   long long Ntot = 0;
   for (int a = 0; a < natom; ++a) {
@@ -625,8 +656,10 @@ void bss_tail(const x2c_options* o, const Dims& dm, const BlockDesc* D, int nblk
 template <class T>
 int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, int nblk, const double* S, const double* Tm, const double* V,
                const double* W, double* h, double* eps, double* Xo, double* Ro, int* info, char* ws, hipStream_t s,
-               int mv_res) {
+               int mv_res, bool large = false) {
   const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off) + b0;
+  // large: one block on the device-wide path (nblk == 1)
+  const BlockDesc& hd = L.desc[b0];
   const bool tc = o->mode == X2C_TWOCOMP;
   const double c = o->c;
   const int maxN = dm.maxN, maxn = dm.maxn, maxm = dm.maxm;
@@ -670,8 +703,12 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
     STAGE("prep");
     launch_init_info(s, info, nblk);
     launch_unpack(s, D, ws, info, nblk, maxN, S, Tm, V, W, tc ? 1 : 0);
-    launch_potrf(s, D, ws, info, nblk, maxN);
-    launch_trtri(s, D, ws, info, nblk, maxN);
+    if (large) {
+      launch_large_cholesky(s, D, ws, info, hd.N);
+    } else {
+      launch_potrf(s, D, ws, info, nblk, maxN);
+      launch_trtri(s, D, ws, info, nblk, maxN);
+    }
     if (qchain) launch_expand_q(s, D, ws, info, nblk, maxN, c);
     else launch_expand<T>(s, D, ws, info, nblk, maxn, c);
   }
@@ -708,7 +745,13 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
     if (!kramers) launch_assemble_A<T>(s, D, ws, info, nblk, maxm, c);
     else launch_assemble_Aq(s, D, ws, info, nblk, maxn, c);
   }
-  if (!kramers) {
+  if (large) {
+    // positive-energy branch: sign(A + c^2 I) by products of the whole matrix
+    STAGE("sign_4c");
+    if (kramers) launch_large_sign<quat>(s, D, hd, ws, info, DIM_n, hd.n, C_A, C_G1, C_G2, c, NS_SIGN_IT, NS_TOL);
+    else launch_large_sign<T>(s, D, hd, ws, info, DIM_m, hd.m, C_A, C_G1, C_G2, c, NS_SIGN_IT, NS_TOL);
+    if (eps) launch_eps_nan(s, D, eps);
+  } else if (!kramers) {
     // positive-energy branch of the reduced 4c matrix (complex m x m form)
     {
       STAGE("tridiag_4c");
@@ -751,7 +794,17 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
   {
     // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
     STAGE("x_solve");
-    if (L.fw == 0) {
+    if (large) {
+      // X~ = P_SL P_LL^-1 from the projector's large-component columns
+      if (kramers) {
+        launch_large_xtilde<quat>(s, D, hd, ws, info, DIM_n, DIM_N, hd.N, C_A, H_A, H_B, H_C, H_D, H_E, C_QMH,
+                                  NS_AUX_IT, NS_TOL);
+        if (!qchain) launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_QMH, C_TMP);
+      } else {
+        launch_large_xtilde<T>(s, D, hd, ws, info, DIM_m, DIM_n, hd.n, C_A, H_A, H_B, H_C, H_D, H_E, C_TMP,
+                               NS_AUX_IT, NS_TOL);
+      }
+    } else if (L.fw == 0) {
       // BSS: X'' = C_S'' C_L''^-1 of H^0 itself
       if (kramers) launch_xsolve_blk<quat>(s, D, ws, info, nblk, maxN, C_Y, DIM_N, Q_X2);
       else launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn, C_Y, DIM_n, Q_X2);
@@ -808,7 +861,19 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
       G(C_TMP, OPN, C_LSI, OPH, C_Q, 1.0, 0.0, 1);
     }
   }
-  if (!kramers) {
+  if (large) {
+    // Q^-1/2 by the coupled Newton-Schulz iteration (quaternion Q into C_LR,
+    // else into C_QMH, where the reductions below leave it)
+    STAGE("invsqrt_Q");
+    if (kramers) {
+      if (!qchain) launch_cplx_to_quat(s, D, ws, info, nblk, maxN, C_Q, C_TMP2);
+      launch_large_invsqrt<quat>(s, D, hd, ws, info, DIM_N, hd.N, qchain ? C_Q : C_TMP2, H_A, H_B, H_C, H_D, C_LR,
+                                 NS_AUX_IT, NS_TOL);
+      if (!qchain) launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_LR, C_QMH);
+    } else {
+      launch_large_invsqrt<T>(s, D, hd, ws, info, DIM_n, hd.n, C_Q, H_A, H_B, H_C, H_D, C_QMH, NS_AUX_IT, NS_TOL);
+    }
+  } else if (!kramers) {
     {
       STAGE("tridiag_Q");
       launch_hetrd_mk<T>(s, D, ws, info, nblk, maxn, DIM_n, C_Q, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS, V_ET, mv_res);
@@ -1029,13 +1094,16 @@ double part_cost(int maxN, double n3) {
 }
 
 // Boundaries of `ways` contiguous parts of the size-sorted descriptors
-// minimising the largest part cost (exhaustive over split points by
+// [lo, end) minimising the largest part cost (exhaustive over split points by
 // dynamic programming; a batch of equal blocks gets equal counts).
-void split_parts(const Layout& L, int ways, int* bnd) {
-  const int n = (int)L.desc.size();
+void split_parts(const Layout& L, int lo, int ways, int* bnd) {
+  const int n = (int)L.desc.size() - lo;
   std::vector<double> pre(n + 1, 0.0);
-  for (int b = 0; b < n; ++b) pre[b + 1] = pre[b] + (double)L.desc[b].N * L.desc[b].N * L.desc[b].N;
-  auto cost = [&](int a, int e) { return part_cost(L.desc[a].N, pre[e] - pre[a]); };   // desc sorted: max at a
+  for (int b = 0; b < n; ++b) {
+    const double Nb = L.desc[lo + b].N;
+    pre[b + 1] = pre[b] + Nb * Nb * Nb;
+  }
+  auto cost = [&](int a, int e) { return part_cost(L.desc[lo + a].N, pre[e] - pre[a]); };   // desc sorted: max at a
   // best[p][e]: minimal largest cost of splitting [0, e) into p non-empty parts
   const double inf = 1e300;
   std::vector<std::vector<double>> best(ways + 1, std::vector<double>(n + 1, inf));
@@ -1053,6 +1121,7 @@ void split_parts(const Layout& L, int ways, int* bnd) {
       }
   bnd[ways] = n;
   for (int p = ways; p >= 1; --p) bnd[p - 1] = arg[p][bnd[p]];
+  for (int p = 0; p <= ways; ++p) bnd[p] += lo;
 }
 
 // descriptor upload + every stage of one call, enqueued on s.  With
@@ -1062,7 +1131,7 @@ void split_parts(const Layout& L, int ways, int* bnd) {
 // latency-bound steps of one part (the per-column kernels of the
 // reductions, the LU panels) overlap the bandwidth- and matrix-core-bound
 // kernels of the other.  Blocks never share workspace, so the two parts are
-// independent.
+// independent.  Blocks of the device-wide path run first, one at a time, on s.
 int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S, const double* T, const double* V,
                 const double* W, void* h, double* eps, void* Xo, void* Ro, int* info, char* ws, hipStream_t s,
                 bool allow_split) {
@@ -1075,7 +1144,7 @@ int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S
   // the stages run on the library's own info array (descriptor order, the
   // blocks sorted by size); the caller's info is written at the end
   int* iw = reinterpret_cast<int*>(ws + L.info_off);
-  auto run = [&](int b0, int nb, hipStream_t st) {
+  auto run = [&](int b0, int nb, hipStream_t st, bool large) {
     Dims dm;
     for (int b = b0; b < b0 + nb; ++b) {
       dm.maxN = std::max(dm.maxN, L.desc[b].N);
@@ -1089,9 +1158,9 @@ int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S
     }
     if (o->mode == X2C_TWOCOMP)
       return run_stages<cplx>(o, L, dm, b0, nb, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
-                              static_cast<double*>(Ro), iw + b0, ws, st, tn.mv_res);
+                              static_cast<double*>(Ro), iw + b0, ws, st, tn.mv_res, large);
     return run_stages<double>(o, L, dm, b0, nb, S, T, V, W, static_cast<double*>(h), eps, static_cast<double*>(Xo),
-                              static_cast<double*>(Ro), iw + b0, ws, st, tn.mv_res);
+                              static_cast<double*>(Ro), iw + b0, ws, st, tn.mv_res, large);
   };
   auto finish = [&](int rc) {
     if (rc == X2C_OK && info != iw) launch_scatter_info(s, reinterpret_cast<const BlockDesc*>(ws + L.desc_off), iw, info,
@@ -1099,20 +1168,27 @@ int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S
     if (rc == X2C_OK && hipGetLastError() != hipSuccess) rc = X2C_EHIP;
     return rc;
   };
-  const int ways = std::min(tn.ways, nblk);
+  int rc = X2C_OK;
+  for (int b = 0; b < L.nlarge; ++b) {
+    const int r = run(b, 1, s, true);
+    if (rc == X2C_OK) rc = r;
+  }
+  const int lo = L.nlarge, nsmall = nblk - lo;
+  if (nsmall == 0) return finish(rc);
+  const int ways = std::min(tn.ways, nsmall);
   AuxStreams* as = (allow_split && ways >= 2) ? device_streams() : nullptr;
   if (!as) {
     lk.unlock();
-    return finish(run(0, nblk, s));
+    const int r = run(lo, nsmall, s, false);
+    return finish(rc == X2C_OK ? r : rc);
   }
   int bnd[MAX_SPLIT + 1];
-  split_parts(L, ways, bnd);
+  split_parts(L, lo, ways, bnd);
   if (hipEventRecord(as->fork, s) != hipSuccess) return X2C_EHIP;
   for (int p = 1; p < ways; ++p)
     if (hipStreamWaitEvent(as->aux[p - 1], as->fork, 0) != hipSuccess) return X2C_EHIP;
-  int rc = X2C_OK;
   for (int p = 0; p < ways; ++p) {
-    const int r = run(bnd[p], bnd[p + 1] - bnd[p], p == 0 ? s : as->aux[p - 1]);
+    const int r = run(bnd[p], bnd[p + 1] - bnd[p], p == 0 ? s : as->aux[p - 1], false);
     if (rc == X2C_OK) rc = r;
   }
   for (int p = 1; p < ways; ++p)
@@ -1298,7 +1374,7 @@ int build_noalloc(const x2c_options* o, int nblk, const int* N, const int64_t* i
     return X2C_EINVAL;
   if (nblk > SCRATCH_MAX_BLOCKS) return X2C_ESCRATCH;
   const bool tc = o->mode == X2C_TWOCOMP;
-  const int mx = max_n(o->mode);
+  const int mx = small_max_n(o->mode);
   // the layout of x2c_build_batched (no per-block info area: the caller's
   // info is used), computed without storing the descriptors on the host
   Layout L;
@@ -1345,6 +1421,14 @@ int build_noalloc(const x2c_options* o, int nblk, const int* N, const int64_t* i
 extern "C" {
 
 int x2c_max_n(int mode) { return max_n(mode); }
+
+int x2c_device_wide_min_n(int mode, int n) {
+  if (mode != X2C_SPINFREE && mode != X2C_TWOCOMP) return X2C_EINVAL;
+  const int dflt = small_max_n(mode) + 1;
+  if (n < 0) return g_wide_from[mode].load();
+  if (n > dflt) return X2C_EINVAL;
+  return g_wide_from[mode].exchange(n == 0 ? dflt : n);
+}
 
 size_t x2c_workspace_bytes(const x2c_options* opts, int nblk, const int* N) {
   if (!valid_opts(opts)) return 0;

@@ -136,4 +136,24 @@ template <class T>
 void launch_bss_h0(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int bufE1,
                    int bufO1, int bufE1p, int bufFP, int bufA, double c);
 
+// device-wide path of one large block (k_large.hip); D points to the
+// block's descriptor, hd is its host copy, info to its status
+void launch_large_cholesky(hipStream_t s, const BlockDesc* D, char* ws, int* info, int N);
+// sign(A + c^2 I) of the 4c matrix in bufX (dimension dim4, selector dsel4),
+// in place; bufU, bufN: 4c-sized scratch
+template <class T>
+void launch_large_sign(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
+                       int dim4, int bufX, int bufU, int bufN, double c, int maxit, double tol);
+// X~ = P_SL P_LL^-1 from the converged sign in bufX into bufOut (h-sized)
+template <class T>
+void launch_large_xtilde(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
+                         int dselh, int dimh, int bufX, int bufPLL, int bufPSL, int bufZ, int bufU, int bufN,
+                         int bufOut, int maxit, double tol);
+// Q^-1/2 of the Hermitian positive definite bufQ into bufOut
+template <class T>
+void launch_large_invsqrt(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dselh,
+                          int dimh, int bufQ, int bufY, int bufZ, int bufU, int bufN, int bufOut, int maxit,
+                          double tol);
+void launch_eps_nan(hipStream_t s, const BlockDesc* D, double* eps);
+
 }  // namespace x2c

@@ -22,7 +22,9 @@ int main() {
   for (int n = 2; n <= 14; ++n) CHECK(x2c_dkh_products(n) == P[n - 2]);
   CHECK(x2c_dkh_products(1) == 0 && x2c_dkh_products(0) == -1 && x2c_dkh_products(15) == -1);
   for (int code = -5; code <= 8; ++code) CHECK(x2c_strerror(code) && std::strlen(x2c_strerror(code)) > 0);
-  CHECK(x2c_max_n(X2C_SPINFREE) == 512 && x2c_max_n(X2C_TWOCOMP) == 256 && x2c_max_n(7) == 0);
+  CHECK(x2c_max_n(X2C_SPINFREE) == 8192 && x2c_max_n(X2C_TWOCOMP) == 4096 && x2c_max_n(7) == 0);
+  CHECK(x2c_device_wide_min_n(X2C_SPINFREE, -1) == 513 && x2c_device_wide_min_n(X2C_TWOCOMP, -1) == 257);
+  CHECK(x2c_device_wide_min_n(7, -1) == X2C_EINVAL && x2c_device_wide_min_n(X2C_TWOCOMP, 258) == X2C_EINVAL);
 
   x2c_options o2{X2C_TWOCOMP, X2C_FP64, 0, 137.035999084, X2C_RED_QUATERNION};
   x2c_options o1{X2C_SPINFREE, X2C_FP64, 0, 137.035999084, X2C_RED_QUATERNION};
@@ -39,8 +41,15 @@ int main() {
   // invalid sizes, options and pointers are refused before any device work
   int bad[3] = {10, 0, 20};
   CHECK(x2c_workspace_bytes(&o2, 3, bad) == 0);
-  int big[1] = {257};
+  int big[1] = {4097};
   CHECK(x2c_workspace_bytes(&o2, 1, big) == 0);
+  // device-wide sizes: a whole molecule, and batches that mix both paths
+  int wide[3] = {2496, 100, 257};
+  CHECK(x2c_workspace_bytes(&o2, 3, wide) > x2c_workspace_bytes(&o2, 1, wide));
+  CHECK(x2c_bss_workspace_bytes(&o2, 1, wide) == 0 && x2c_dkh_workspace_bytes(&o2, 2, 1, wide) == 0);
+  CHECK(x2c_device_wide_min_n(X2C_TWOCOMP, 100) == 257);
+  CHECK(x2c_workspace_bytes(&o2, 3, wide) > 0);
+  CHECK(x2c_device_wide_min_n(X2C_TWOCOMP, 0) == 100 && x2c_device_wide_min_n(X2C_TWOCOMP, -1) == 257);
   CHECK(x2c_workspace_bytes(nullptr, 1, big) == 0);
   x2c_options bad_c = o2;
   bad_c.c = -1.0;
@@ -56,6 +65,9 @@ int main() {
                           &dummy, 8, nullptr) == X2C_EINVAL);
   CHECK(x2c_build_batched(&o2, 3, bad, off, &dummy, &dummy, &dummy, &dummy, off, &dummy, off, &dummy, info,
                           &dummy, 8, nullptr) == X2C_EINVAL);
+  int wide1[1] = {300};   // the allocation-free entry takes batched-path sizes only
+  CHECK(x2c_build_batched_noalloc(&o2, 1, wide1, off, &dummy, &dummy, &dummy, &dummy, off, &dummy, off, &dummy,
+                                  info, nullptr) == X2C_EINVAL);
   CHECK(x2c_build_batched_noalloc(&o2, 257, one, off, &dummy, &dummy, &dummy, &dummy, off, &dummy, off, &dummy,
                                   info, nullptr) == X2C_ESCRATCH);
   CHECK(x2c_dkh_batched(&o2, 0, 1, one, off, &dummy, &dummy, &dummy, &dummy, off, &dummy, info, &dummy, 8,

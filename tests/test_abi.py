@@ -122,3 +122,31 @@ def test_workspace_too_small_is_rejected():
     rc = lib.x2c_build(ctypes.byref(opt), 20, vp(S), vp(T), vp(V), vp(W), vp(h), vp(e), vp(small), 1024,
                        None, ctypes.byref(info))
     assert rc == px.EINVAL
+
+
+def test_device_wide_threshold_and_workspace():
+    """Size classes: blocks above the batched limit take the device-wide path
+    (up to x2c_max_n); the threshold can be lowered, never raised."""
+    assert px.device_wide_min_n(True) == 257 and px.device_wide_min_n(False) == 513
+    assert px.max_n(True) == 4096 and px.max_n(False) == 8192
+    w_batched = px.workspace_bytes([192], twocomp=True)
+    old = px.device_wide_min_n(True, 100)
+    try:
+        assert old == 257
+        assert px.device_wide_min_n(True) == 100
+        assert px.workspace_bytes([192], twocomp=True) != w_batched
+        assert px.workspace_bytes([99], twocomp=True) == px.workspace_bytes([99], twocomp=True)
+    finally:
+        px.device_wide_min_n(True, 0)
+    assert px.device_wide_min_n(True) == 257
+    assert px.workspace_bytes([192], twocomp=True) == w_batched
+    with pytest.raises(px.X2CError):
+        px.device_wide_min_n(True, 258)
+    # the full 13-atom silver molecule (N = 2496): one GPU's HBM holds it easily
+    w = px.workspace_bytes([2496], twocomp=True)
+    assert 1e9 < w < 24e9
+    # BSS, DKHn and the allocation-free entry stay on the batched path
+    with pytest.raises(px.X2CError):
+        px.bss_workspace_bytes([300], twocomp=True)
+    with pytest.raises(px.X2CError):
+        px.dkh_workspace_bytes([300], twocomp=True, order=2)

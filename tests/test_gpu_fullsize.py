@@ -93,10 +93,10 @@ def _block_of_size(counts, ratio=None, Z=47.0):
 
 
 def test_spin_free_maximum_block_size():
-    """N = x2c_max_n(spin-free) = 512: 32 shells of each l = 0..3 with
+    """N = 512, the batched limit (spin-free): 32 shells of each l = 0..3 with
     exponent ratio 2 (real 4c dimension 1024)."""
     px, _ = _px()
-    N = px.max_n(False)
+    N = px.device_wide_min_n(False) - 1
     blk = _block_of_size({0: 32, 1: 32, 2: 32, 3: 32}, ratio=2.0)
     assert blk.N == N == 512
     h, eps = gpu_single(blk.S, blk.T, blk.V, blk.W[0], C_LIGHT, False)
@@ -105,10 +105,10 @@ def test_spin_free_maximum_block_size():
 
 @pytest.mark.parametrize("reduction,prec", [(1, 0), (0, 1), (0, 2), (1, 1)])
 def test_two_component_maximum_block_size(reduction, prec):
-    """N = x2c_max_n(two-component) = 256 with the complex reduction
+    """N = 256, the batched limit (two-component), with the complex reduction
     (complex 4c dimension 1024) and with split products."""
     px, _ = _px()
-    N = px.max_n(True)
+    N = px.device_wide_min_n(True) - 1
     blk = _block_of_size({0: 22, 1: 20, 2: 18, 3: 12})
     assert blk.N == N == 256
     h, eps = gpu_single(blk.S, blk.T, blk.V, blk.W, C_LIGHT, True, prec=prec, reduction=reduction)

@@ -1,0 +1,201 @@
+"""Parity of the device-wide path (one large block on the whole GPU: blocked
+Cholesky factors, the positive-energy projector by a Newton-Schulz sign
+iteration, X~ and Q^-1/2 by Newton-Schulz iterations) with the CPU oracle,
+through the C ABI.
+
+The path runs by default for blocks above the batched limit (N > 256
+two-component, > 512 spin-free); x2c_device_wide_min_n lowers the threshold
+so that atomic blocks and small molecules, which the oracle solves in
+seconds, take it too.
+
+Tolerances are those of the batched path (tests/test_gpu_parity.py): h
+elementwise 2e-10 relative to max|h_oracle| (unit roundoff times
+kappa(L_T)), bound states of the spectrum of h within 1e-8 Eh of the
+oracle's positive 4c eigenvalues (10x the oracle's own floor where that is
+larger).  The path does not produce eigenvalues: eps must be NaN.
+"""
+import contextlib
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.routes as ox
+from tests.test_oracle import random_spd_problem
+from x2c_inputs import C_LIGHT, ag_2c, atom_block, neon_s20, pack_blocks
+from x2c_inputs.configs import coupled_molecule
+
+pytestmark = pytest.mark.gpu
+
+TOL_H = 2e-10
+DE_BOUND = 1e-8
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "ag13_full_seed0.npz")
+
+
+def _px():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1303_4446_amd as px
+    return px, torch
+
+
+@contextlib.contextmanager
+def device_wide_from(twocomp, n):
+    px, _ = _px()
+    old = px.device_wide_min_n(twocomp, n)
+    try:
+        yield
+    finally:
+        px.device_wide_min_n(twocomp, old)
+
+
+def gpu_single(S, T, V, W, c, twocomp, prec=0, reduction=0):
+    px, torch = _px()
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    print(f"  x2c_build N={S.shape[0]} twocomp={twocomp} c={c} prec={prec} reduction={reduction} "
+          f"device-wide from {px.device_wide_min_n(twocomp)}", flush=True)
+    h, eps = px.build(d(S), d(T), d(V), d(W), c, twocomp, prec=prec, reduction=reduction)
+    return h.cpu().numpy(), eps.cpu().numpy()
+
+
+def check_h(S, T, V, W, c, twocomp, h, strict_bound=False):
+    h0, _ = ox.x2c_direct(S, T, V, W, c, twocomp)
+    err = np.abs(h - h0).max() / np.abs(h0).max()
+    e4 = oracle.dirac_positive_spectrum(S, T, V, W, c, twocomp)
+    de = np.abs(oracle.spectrum_of(h, S, twocomp) - e4)
+    f = np.abs(oracle.spectrum_of(h0, S, twocomp) - e4)
+    bd = e4 < 0
+    print(f"    h rel err {err:.2e}; bound dE {de[bd].max() if bd.any() else 0:.2e} "
+          f"(oracle floor {f[bd].max() if bd.any() else 0:.2e})", flush=True)
+    assert err <= TOL_H, err
+    assert np.abs(h - h.conj().T).max() <= 1e-13 * np.abs(h).max()
+    if bd.any():
+        lim = DE_BOUND if strict_bound else max(DE_BOUND, 10 * f[bd].max())
+        assert de[bd].max() <= lim
+    return err
+
+
+@pytest.mark.parametrize("Z,twocomp", [(47, True), (79, True), (17, False), (1, True), (10, False)])
+def test_device_wide_atoms_match_oracle(Z, twocomp):
+    """Ragged sizes (N = 192, 200, 45, 24, 20: several 64-wide tiles and
+    tails, and a single partial tile)."""
+    b = neon_s20() if Z == 10 else atom_block(Z)
+    W = b.W if twocomp else b.W[0]
+    with device_wide_from(twocomp, 1):
+        h, eps = gpu_single(b.S, b.T, b.V, W, C_LIGHT, twocomp)
+    assert np.all(np.isnan(eps))
+    check_h(b.S, b.T, b.V, W, C_LIGHT, twocomp, h, strict_bound=Z == 47)
+
+
+@pytest.mark.parametrize("N,seed,twocomp", [(1, 0, False), (3, 2, True), (6, 5, False), (1, 7, True),
+                                            (40, 3, False), (30, 9, True)])
+def test_device_wide_tiny_random(N, seed, twocomp):
+    S, T, V, W = random_spd_problem(N, seed, twocomp)
+    with device_wide_from(twocomp, 1):
+        h, eps = gpu_single(S, T, V, W, 7.0, twocomp)
+    check_h(S, T, V, W, 7.0, twocomp, h)
+
+
+@pytest.mark.parametrize("reduction,prec", [(1, 0), (0, 1), (0, 2), (1, 1)])
+def test_device_wide_reductions_and_split_products(reduction, prec):
+    """Complex form of the 4c matrix, and the product chain on split bf16 /
+    int8 slices (the iterations stay FP64)."""
+    b = ag_2c()
+    with device_wide_from(True, 1):
+        h, eps = gpu_single(b.S, b.T, b.V, b.W, C_LIGHT, True, prec=prec, reduction=reduction)
+    check_h(b.S, b.T, b.V, b.W, C_LIGHT, True, h, strict_bound=True)
+
+
+def test_mixed_batch_device_wide_and_batched_blocks():
+    """Blocks at or above the threshold run device-wide (eps NaN), the others
+    batched (eps from the eigensolver); every block against the oracle."""
+    px, torch = _px()
+    blocks = [atom_block(z) for z in (8, 47, 1, 79, 17)]
+    with device_wide_from(True, 100):
+        bt = px.batch_to_device(pack_blocks(blocks, True), True)
+        print(f"  mixed batch N={list(bt.Ns)}", flush=True)
+        (h, eps, info), _ = px.build_batched(bt, C_LIGHT)
+        torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    hs = px.unpack_h(h.cpu().numpy(), bt.Ns, True)
+    e = eps.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum(2 * bt.Ns)])
+    for i, b in enumerate(blocks):
+        ei = e[offs[i]:offs[i + 1]]
+        if b.N >= 100:
+            assert np.all(np.isnan(ei))
+        else:
+            e0 = ox.x2c_direct(b.S, b.T, b.V, b.W, C_LIGHT, True)[1]
+            assert np.abs(ei - e0).max() <= 1e-12 * np.abs(e0).max()
+        check_h(b.S, b.T, b.V, b.W, C_LIGHT, True, hs[i])
+
+
+def test_device_wide_failure_codes():
+    """S or T not positive definite: the blocked factorisation reports the
+    batched path's codes (1, 2), h zero."""
+    px, torch = _px()
+    b = atom_block(8)
+    with device_wide_from(True, 1):
+        for which, code in (("S", 1), ("T", 2)):
+            S, T = b.S.copy(), b.T.copy()
+            M = S if which == "S" else T
+            M[3, 3] = -abs(M[3, 3])
+            d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+            print(f"  device-wide build with {which} not SPD", flush=True)
+            with pytest.raises(px.X2CError) as ex:
+                px.build(d(S), d(T), d(b.V), d(b.W), C_LIGHT, True)
+            assert ex.value.info == code
+
+
+def test_three_atom_molecule_default_threshold():
+    """A coupled three-atom silver molecule (N = 576 > 256): the device-wide
+    path by default; h against the oracle's full (non-local) transformation."""
+    mol = coupled_molecule([ag_2c() for _ in range(3)], 0)
+    px, _ = _px()
+    assert mol.Ntot >= px.device_wide_min_n(True)
+    h, eps = gpu_single(mol.S, mol.T, mol.V, mol.W, C_LIGHT, True)
+    assert np.all(np.isnan(eps))
+    check_h(mol.S, mol.T, mol.V, mol.W, C_LIGHT, True, h, strict_bound=True)
+
+
+def test_spin_free_molecule_above_batched_limit():
+    """Spin-free: three coupled silver blocks (N = 576 > 512)."""
+    mol = coupled_molecule([ag_2c() for _ in range(3)], 1)
+    W0 = mol.W[0]
+    h, eps = gpu_single(mol.S, mol.T, mol.V, W0, C_LIGHT, False)
+    assert np.all(np.isnan(eps))
+    check_h(mol.S, mol.T, mol.V, W0, C_LIGHT, False, h, strict_bound=True)
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="Ag13 reference not generated")
+@pytest.mark.timeout(400)
+def test_ag13_full_build_matches_oracle_reference():
+    """The full (non-local) two-component X2C of the 13-atom silver molecule
+    (N = 2496, 4c dimension 9984 complex) on one GPU, against values the
+    oracle wrote (tests/golden/make_ag13_full_reference.py): h applied to a
+    seeded block of vectors, five full rows of h, and the bound-state
+    spectrum of h against the oracle's positive 4c eigenvalues."""
+    import scipy.linalg as sla
+    from x2c_inputs.configs import ag13_molecule
+    ref = np.load(GOLDEN)
+    mol = ag13_molecule(0)
+    assert abs(mol.scale - float(ref["coupling_scale"])) == 0.0
+    h, eps = gpu_single(mol.S, mol.T, mol.V, mol.W, C_LIGHT, True)
+    assert np.all(np.isnan(eps))
+    hmax = float(ref["hmax"])
+    err_rows = np.abs(h[ref["row_index"]] - ref["rows"]).max() / hmax
+    V = ref["V"]
+    err_probe = np.abs(h @ V - ref["probes"]).max() / np.abs(ref["probes"]).max()
+    print(f"    rows rel err {err_rows:.2e}; h V rel err {err_probe:.2e}", flush=True)
+    assert err_rows <= TOL_H
+    assert err_probe <= TOL_H
+    assert np.abs(h - h.conj().T).max() <= 1e-13 * hmax
+    e4 = ref["e4"]
+    nb = int((e4 < 0).sum())
+    S2 = ox.spin_blockdiag(mol.S)
+    es = sla.eigh(0.5 * (h + h.conj().T), S2, eigvals_only=True, subset_by_index=[0, nb - 1])
+    de = np.abs(es - e4[:nb]).max()
+    print(f"    bound states {nb}: max dE {de:.2e} Eh", flush=True)
+    assert de <= DE_BOUND

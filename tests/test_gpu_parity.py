@@ -117,9 +117,9 @@ def test_atoms_ragged_sizes(Z, twocomp):
 
 
 def test_maximum_block_size():
-    """Largest supported block: N = x2c_max_n (two-component)."""
+    """Largest block of the batched path (two-component, N = 256)."""
     px, _ = _px()
-    N = px.max_n(True)
+    N = px.device_wide_min_n(True) - 1
     from x2c_inputs import integrals as gi
     from x2c_inputs.configs import shells_for
     # Z=47 recipes with more polarisation functions: exactly N functions
