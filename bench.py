@@ -206,6 +206,14 @@ def parse(argv=None):
     ap.add_argument("--no-graph", action="store_true", help="eager launches instead of graph replay")
     ap.add_argument("--autotune", action="store_true",
                     help="before the warm-up, let x2c_autotune pick the launch shape (streams, matvec residency)")
+    ap.add_argument("--full-steps", type=int, default=2,
+                    help="timed full (non-local) builds of the 13-atom silver molecule against its DLU "
+                         "approximation (0 = skip)")
+    ap.add_argument("--full-precs", default="fp64,bf16", help="product-chain arithmetic of the full builds")
+    ap.add_argument("--only-full", action="store_true",
+                    help="run only the full-versus-DLU comparison (a profiling aid: prints its JSON object)")
+    ap.add_argument("--no-full-spectra", action="store_true",
+                    help="skip the CPU eigensolves that score the full and DLU spectra")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the workload, copy a device buffer of this size once (a plain copy kernel "
                          "of known traffic for scaling hardware byte counters)")
@@ -394,6 +402,118 @@ def score_fw(blocks, twocomp, c, refs, hs, method, order):
     return r
 
 
+def full_vs_dlu(px, torch, c, stream, steps, precs, spectra=True):
+    """The full (non-local) two-component X2C of the 13-atom silver molecule
+    (N = 2496, 4992 spinors, 4c dimension 9984; one block on the device-wide
+    path) against its DLU approximation (13 atomic blocks on the batched
+    path, then the molecular assembly of Eqs. dlutrans, r2ctransatom, utrans),
+    both timed on the GPU with the inputs resident.  Accuracy against values
+    the oracle wrote (tests/golden/ag13_full_seed0.npz: rows of h and h V for
+    a seeded V, the positive 4c eigenvalues): the full h is exact decoupling,
+    so its bound states match the 4c ones; the DLU h carries the local
+    approximation's error."""
+    import scipy.linalg as sla
+    from x2c_inputs import pack_blocks
+    from x2c_inputs.configs import ag13_molecule
+    mol = ag13_molecule(0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    S, T, V, W = d(mol.S), d(mol.T), d(mol.V), d(mol.W)
+    gold = os.path.join(HERE, "tests", "golden", "ag13_full_seed0.npz")
+    ref = np.load(gold) if os.path.exists(gold) else None
+    S2 = None
+    nb = None
+    if ref is not None:
+        e4 = ref["e4"]
+        nb = int((e4 < 0).sum())
+
+    def bound_de(h):
+        nonlocal S2
+        if ref is None or not spectra:
+            return None
+        if S2 is None:
+            S2 = np.zeros((2 * mol.Ntot, 2 * mol.Ntot))
+            S2[:mol.Ntot, :mol.Ntot] = mol.S
+            S2[mol.Ntot:, mol.Ntot:] = mol.S
+        es = sla.eigh(0.5 * (h + h.conj().T), S2, eigvals_only=True, subset_by_index=[0, nb - 1])
+        return float(np.abs(es - e4[:nb]).max())
+
+    def probe_err(h):
+        if ref is None:
+            return None
+        return float(max(np.abs(h @ ref["V"] - ref["probes"]).max() / np.abs(ref["probes"]).max(),
+                         np.abs(h[ref["row_index"]] - ref["rows"]).max() / float(ref["hmax"])))
+
+    res = {"workload": f"ag13_molecule(0): 13 coupled two-component Z=47 blocks, N={mol.Ntot}, "
+                       f"{2 * mol.Ntot} spinors, 4c dimension {4 * mol.Ntot} complex, coupling scale {mol.scale:g}",
+           "bound_states": nb, "steps": steps}
+    ws = torch.empty(px.workspace_bytes([mol.Ntot], True, c), dtype=torch.uint8, device="cuda")
+    names = {"fp64": px.FP64, "bf16": px.SPLIT_BF16, "int8": px.SPLIT_INT8}
+    full = {}
+    for name in precs:
+        p = names[name]
+        h, _ = px.build(S, T, V, W, c, True, prec=p, workspace=ws, stream=stream)   # warm-up
+        ts = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            h, eps = px.build(S, T, V, W, c, True, prec=p, workspace=ws, stream=stream)   # synchronises
+            ts.append((time.perf_counter() - t0) * 1e3)
+        hc = h.cpu().numpy()
+        full[name] = {"ms": statistics.median(ts), "h_rel_err_vs_oracle": probe_err(hc),
+                      "bound_dE_max": bound_de(hc), "eps_nan": bool(torch.isnan(eps).all().item())}
+        print(f"# full {name}: {full[name]}", file=sys.stderr, flush=True)
+        del h, hc
+    # traced pass of the FP64 build: stage times and the Newton-Schulz step
+    # counts; the sign iteration's products against the FP64 matrix-core peak
+    if "fp64" in full:
+        px.trace_reset()
+        px.trace_enable(True, level=1)
+        px.build(S, T, V, W, c, True, workspace=ws, stream=stream)
+        tr = px.trace_read()
+        px.trace_enable(False)
+        px.trace_reset()
+        st = {k: round(v[0], 3) for k, v in tr.items() if not k.endswith("_steps")}
+        steps_ns = {k[:-6]: int(v[1]) for k, v in tr.items() if k.endswith("_steps")}
+        n4, nh = 2 * mol.Ntot, mol.Ntot      # quaternion dimensions: 4c matrix, h
+        # one quaternion multiply-add = 32 real flops; a Hermitian product
+        # forms the lower triangle, n^2 (n + 1) / 2 multiply-adds
+        herm = lambda n: 32.0 * n * n * (n + 1) / 2
+        fl = {"sign_4c": steps_ns.get("sign_4c", 0) * 2 * herm(n4),
+              "x_solve": steps_ns.get("x_solve", 0) * 2 * herm(nh) + 32.0 * nh ** 3,
+              "invsqrt_Q": steps_ns.get("invsqrt_Q", 0) * 3 * herm(nh)}
+        rates = {k: fl[k] / (st[k] / 1e3) / 1e12 for k in fl if st.get(k)}
+        full["fp64"].update({"stages_ms": st, "newton_schulz_steps": steps_ns,
+                             "stage_fp64_tflops": {k: round(v, 2) for k, v in rates.items()}})
+        if "sign_4c" in rates:
+            full["fp64"]["roofline"] = {"bound": "mfma", "kernel": "k_gemm_q_mfma (sign iteration products)",
+                                        "achieved": rates["sign_4c"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                        "frac": rates["sign_4c"] / PEAK_FP64_TFLOPS,
+                                        "flops": fl["sign_4c"], "stage_ms": st["sign_4c"]}
+        print(f"# full fp64 traced: {st} steps {steps_ns} rates {rates}", file=sys.stderr, flush=True)
+    del ws
+    res["full"] = full
+    # DLU: the atomic blocks (batched path, X and R kept) and the assembly
+    atoms = [mol.atom(A) for A in range(len(mol.Ns))]
+    bt = px.batch_to_device(pack_blocks(atoms, True), True)
+    (hb, eb, info, X, R), wsb = px.build_batched_xr(bt, c, stream=stream)
+    h_off = bt.out_layout()[0]
+    H, wsa = px.dlu_assemble(T, V, W, mol.Ns, h_off, X, R, c, True, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        (hb, eb, info, X, R), wsb = px.build_batched_xr(bt, c, workspace=wsb, stream=stream)
+        H, wsa = px.dlu_assemble(T, V, W, mol.Ns, h_off, X, R, c, True, workspace=wsa, stream=stream, H=H)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    Hc = H.cpu().numpy()
+    res["dlu"] = {"ms": e0.elapsed_time(e1) / steps, "blocks_ok": bool((info.cpu().numpy() == 0).all()),
+                  "h_rel_err_vs_full_oracle": probe_err(Hc), "bound_dE_max": bound_de(Hc)}
+    print(f"# dlu: {res['dlu']}", file=sys.stderr, flush=True)
+    if "fp64" in full:
+        res["full_over_dlu_time"] = full["fp64"]["ms"] / res["dlu"]["ms"]
+    return res
+
+
 def host_outputs(px, out, batch, twocomp):
     h, eps, info = out
     info_h = info.cpu().numpy().copy()
@@ -408,8 +528,16 @@ def main():
                                    "(the per-block DLU build shards over blocks: each GPU runs "
                                    "its own share of the batch with no communication)"}))
         sys.exit(2)
-    blocks, twocomp, desc = workload(args.workload, args.seed)
     c_light = __import__("x2c_inputs").C_LIGHT
+    if args.only_full:
+        import torch
+        import paper_1303_4446_amd as px
+        precs = [p for p in args.full_precs.split(",") if p]
+        res = full_vs_dlu(px, torch, c_light, torch.cuda.current_stream(), max(1, args.full_steps), precs,
+                          spectra=not args.no_full_spectra)
+        print(json.dumps({"full_vs_dlu": res}), flush=True)
+        return
+    blocks, twocomp, desc = workload(args.workload, args.seed)
 
     # CPU baseline first: its worker processes are forked before the GPU is initialised
     cpu = None
@@ -577,6 +705,12 @@ def main():
         extra["chain_frac_of_fp64_peak"] = extra["chain_fp64_tflops"] / PEAK_FP64_TFLOPS
 
     pct = None if args.no_pct else time_picture_change(px, torch, batch, twocomp, c, prec, red, stream)
+    fvd = None
+    if args.full_steps > 0:
+        del out, ws
+        torch.cuda.empty_cache()
+        precs = [p for p in args.full_precs.split(",") if p]
+        fvd = full_vs_dlu(px, torch, c, stream, args.full_steps, precs, spectra=not args.no_full_spectra)
 
     line = {
         "metric": METRIC, "value": value, "unit": "blocks/s", "n_gpus": 1, "steps": args.steps,
@@ -596,6 +730,7 @@ def main():
         "stages_ms_per_step": {k: round(v, 4) for k, v in sorted(stage_ms.items(), key=lambda kv: -kv[1])},
         "stage_rates": extra,
         "picture_change": pct,
+        "full_vs_dlu": fvd,
     }
     print(json.dumps(line), flush=True)
 

@@ -14,7 +14,8 @@
 //    matrix A is taken from the spectral projector
 //      P = (I + sign(A + c^2 I)) / 2,
 //    computed by a scaled Newton-Schulz iteration X <- a X - b X^3 on
-//    X_0 = (A + c^2 I) / ||A + c^2 I||_F (two Hermitian products per step);
+//    X_0 = (A + c^2 I) / rho, rho the smaller of the Frobenius norm and the
+//    largest absolute row sum (two Hermitian products per step);
 //  * with the column blocks of P on the large-component unit vectors,
 //    X~ = P_SL P_LL^-1: if Y = [Y_L; Y_S] spans the positive branch
 //    (orthonormal), P_LL = Y_L Y_L^H, P_SL = Y_S Y_L^H and P_SL P_LL^-1 =
@@ -324,12 +325,14 @@ __global__ void k_ns_fro(const BlockDesc* D, char* ws, int dsel, int buf, double
   if (threadIdx.x == 0) atomicAdd(&p->acc, s);
 }
 
-// rho = ||A - sigma I||_F, X_0 = (A - sigma I) / rho in place, and the first
-// lower bound l_0 = gap / rho from the expected half-width of the gap
+// rho = min(||A - sigma I||_F, largest row sum of |A - sigma I|) (both bound
+// the spectral radius from above), X_0 = (A - sigma I) / rho in place, and
+// the first lower bound l_0 = gap / rho from the expected half-width of the
+// gap
 __global__ void k_ns_start(const BlockDesc* D, char* ws, double sigma, double gap) {
   NsPar* p = nspar(ws, D[0]);
   if (p->gate) return;
-  double rho = sqrt(p->acc);
+  double rho = fmin(sqrt(p->acc), __longlong_as_double((long long)p->rmax));
   if (!(rho > 0.0) || !isfinite(rho)) {
     p->gate = 1;   // no convergence: the phase end fails the block
     return;
@@ -338,6 +341,7 @@ __global__ void k_ns_start(const BlockDesc* D, char* ws, double sigma, double ga
   p->rho = rho;
   p->l = fmin(fmax(gap / rho, 1e-14), 0.99);
   p->acc = 0.0;
+  p->rmax = 0ull;
 }
 
 template <class T>
@@ -483,10 +487,10 @@ __global__ void k_ns_eye(const BlockDesc* D, char* ws, const int* info, int dsel
     A[e] = treal<T>(e / n == e % n ? 1.0 : 0.0);
 }
 
-// largest row sum of moduli (>= the largest eigenvalue), one wave per row;
-// non-negative doubles order like their bit patterns
+// largest row sum of the moduli of A - sigma I (>= its spectral radius), one
+// wave per row; non-negative doubles order like their bit patterns
 template <class T>
-__global__ void k_ns_rowmax(const BlockDesc* D, char* ws, int dsel, int buf) {
+__global__ void k_ns_rowmax(const BlockDesc* D, char* ws, int dsel, int buf, double sigma) {
   const BlockDesc& d = D[0];
   NsPar* p = nspar(ws, d);
   if (p->gate) return;
@@ -495,7 +499,11 @@ __global__ void k_ns_rowmax(const BlockDesc* D, char* ws, int dsel, int buf) {
   const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (row >= n) return;
   double s = 0.0;
-  for (int j = lane; j < n; j += 64) s += sqrt(abs2(A[(long long)row * n + j]));
+  for (int j = lane; j < n; j += 64) {
+    T v = A[(long long)row * n + j];
+    if (j == row) v = v - treal<T>(sigma);
+    s += sqrt(abs2(v));
+  }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if (lane == 0) atomicMax(&p->rmax, (unsigned long long)__double_as_longlong(s));
 }
@@ -562,6 +570,7 @@ void launch_large_sign(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, c
   const double sigma = -c * c;
   hipLaunchKernelGGL(k_ns_begin, dim3(1), dim3(1), 0, s, D, ws, info);
   hipLaunchKernelGGL(k_ns_fro<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufX, sigma);
+  hipLaunchKernelGGL(k_ns_rowmax<T>, dim3((dim4 + 3) / 4), dim3(256), 0, s, D, ws, dsel4, bufX, sigma);
   hipLaunchKernelGGL(k_ns_start, dim3(1), dim3(1), 0, s, D, ws, sigma, 0.5 * c * c);
   hipLaunchKernelGGL(k_ns_shift<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufX);
   for (int it = 0; it < maxit; ++it) {
@@ -603,7 +612,7 @@ void launch_large_invsqrt(hipStream_t s, const BlockDesc* D, const BlockDesc& hd
   const int* gate = gate_of(hd, ws);
   const long long tot = (long long)dimh * dimh;
   hipLaunchKernelGGL(k_ns_begin, dim3(1), dim3(1), 0, s, D, ws, info);
-  hipLaunchKernelGGL(k_ns_rowmax<T>, dim3((dimh + 3) / 4), dim3(256), 0, s, D, ws, dselh, bufQ);
+  hipLaunchKernelGGL(k_ns_rowmax<T>, dim3((dimh + 3) / 4), dim3(256), 0, s, D, ws, dselh, bufQ, 0.0);
   hipLaunchKernelGGL(k_ns_isq_start<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufQ, bufY);
   hipLaunchKernelGGL(k_ns_eye<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dselh, bufZ);
   for (int it = 0; it < maxit; ++it) {

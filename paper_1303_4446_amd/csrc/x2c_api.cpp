@@ -403,6 +403,28 @@ void trace_collect() {
 
 #define STAGE(nm) Stage stage_guard_(nm, s)
 
+// Trace mode only: the step count of the Newton-Schulz iteration that just
+// ran on the device-wide path, filed as a record with that count and no time
+// (the call waits for it; traced calls are diagnostic and never captured).
+void trace_iterations(const char* name, hipStream_t s, const BlockDesc& hd, char* ws) {
+  {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_trace || t_untraced) return;
+  }
+  int it = 0;
+  if (hipMemcpyAsync(&it, ws + hd.off[V_NS] + offsetof(NsPar, iters), sizeof(int), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (auto& t : g_totals)
+    if (t.first == name) {
+      t.second.second += it;
+      return;
+    }
+  g_totals.push_back({name, {0.0, (long long)it}});
+}
+
 }  // namespace
 
 // per-launch events of selected kernels (trace level 2), recorded by the
@@ -750,6 +772,7 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
     STAGE("sign_4c");
     if (kramers) launch_large_sign<quat>(s, D, hd, ws, info, DIM_n, hd.n, C_A, C_G1, C_G2, c, NS_SIGN_IT, NS_TOL);
     else launch_large_sign<T>(s, D, hd, ws, info, DIM_m, hd.m, C_A, C_G1, C_G2, c, NS_SIGN_IT, NS_TOL);
+    trace_iterations("sign_4c_steps", s, hd, ws);
     if (eps) launch_eps_nan(s, D, eps);
   } else if (!kramers) {
     // positive-energy branch of the reduced 4c matrix (complex m x m form)
@@ -804,6 +827,7 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
         launch_large_xtilde<T>(s, D, hd, ws, info, DIM_m, DIM_n, hd.n, C_A, H_A, H_B, H_C, H_D, H_E, C_TMP,
                                NS_AUX_IT, NS_TOL);
       }
+      trace_iterations("x_solve_steps", s, hd, ws);
     } else if (L.fw == 0) {
       // BSS: X'' = C_S'' C_L''^-1 of H^0 itself
       if (kramers) launch_xsolve_blk<quat>(s, D, ws, info, nblk, maxN, C_Y, DIM_N, Q_X2);
@@ -873,6 +897,7 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
     } else {
       launch_large_invsqrt<T>(s, D, hd, ws, info, DIM_n, hd.n, C_Q, H_A, H_B, H_C, H_D, C_QMH, NS_AUX_IT, NS_TOL);
     }
+    trace_iterations("invsqrt_Q_steps", s, hd, ws);
   } else if (!kramers) {
     {
       STAGE("tridiag_Q");
