@@ -20,10 +20,15 @@
 // product of the row and column maxima: the size of the operands' own
 // truncation.  Rounding therefore only happens in FP64.
 //
-// Complex operands use the real form with interleaved real / imaginary parts:
-// row 2i of A' is (Re a_ik, -Im a_ik) over k, row 2i+1 is (Im a_ik, Re a_ik),
-// rows 2k / 2k+1 of B' are Re / Im b_kj, so (A'B')_{2i,j} = Re (AB)_ij and
-// (A'B')_{2i+1,j} = Im (AB)_ij; a row exponent covers both parts of a row.
+// Complex and quaternion operands use the real form with interleaved
+// components (F = 2: Re, Im; F = 4: Re a, Im a, Re b, Im b of q = a + b j):
+//   A'[F i + c][F k + d] = sigma(c, d) a_ik[c xor d],   B'[F k + d][j] = b_kj[d],
+// with sigma the sign pattern of the quaternion product ((x y)_c =
+// sum_d sigma(c, d) x_{c xor d} y_d, which restricted to c, d < 2 is the
+// complex product), so that (A'B')_{F i + c, j} = component c of (AB)_ij; a
+// row exponent covers all components of a row.  herm = 1: the product is
+// Hermitian (and so is beta C): only tiles reaching the lower triangle run,
+// and each lower element is mirrored.
 //
 // Tiling (gfx950): 256 threads = 4 waves; the work-group covers 128 rows of
 // A' x 64 columns; wave w owns rows 32w..32w+31 as two 32 x 32 MFMA blocks
@@ -54,10 +59,7 @@ __global__ void __launch_bounds__(256) k_line_exp(const BlockDesc* D, char* ws, 
   if (line >= n) return;
   const T* A = bufp<T>(ws, d, buf);
   double mx = 0.0;
-  for (int k = lane; k < n; k += 64) {
-    const T v = rows ? A[(long long)line * n + k] : A[(long long)k * n + line];
-    mx = fmax(mx, fmax(fabs(re(v)), fabs(im(v))));
-  }
+  for (int k = lane; k < n; k += 64) mx = fmax(mx, amax(rows ? A[(long long)line * n + k] : A[(long long)k * n + line]));
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
   if (lane == 0) {
     int e = 0;
@@ -78,12 +80,34 @@ __device__ inline void split_slices(double x, double scale, __bf16* q) {
   }
 }
 
+// RF bf16 values to consecutive LDS entries (one store)
+template <int RF>
+__device__ inline void store_bf(__bf16* p, const __bf16* v) {
+  if constexpr (RF == 1) {
+    p[0] = v[0];
+  } else {
+    unsigned int w[RF / 2];
+#pragma unroll
+    for (int i = 0; i < RF / 2; ++i)
+      w[i] = (unsigned int)__builtin_bit_cast(unsigned short, v[2 * i]) |
+             ((unsigned int)__builtin_bit_cast(unsigned short, v[2 * i + 1]) << 16);
+    if constexpr (RF == 2) *reinterpret_cast<unsigned int*>(p) = w[0];
+    else *reinterpret_cast<uint2*>(p) = uint2{w[0], w[1]};
+  }
+}
+
+template <class T>
+__device__ inline T from_comps(const double* v) {
+  if constexpr (ncomp<T>() == 1) return v[0];
+  else if constexpr (ncomp<T>() == 2) return cplx{v[0], v[1]};
+  else return quat{{v[0], v[1]}, {v[2], v[3]}};
+}
+
 template <class T, int S>
 __global__ void __launch_bounds__(256) k_gemm_split(const BlockDesc* D, char* ws, const int* info, int dsel,
-                                                    int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta,
-                                                    int bufEA, int bufEB) {
-  constexpr bool CPLX = sizeof(T) == sizeof(cplx);
-  constexpr int RF = CPLX ? 2 : 1;          // real rows / k per element
+                                                    int bufA, int opA, int bufB, int opB, int bufC, double alpha,
+                                                    double beta, int herm, int bufEA, int bufEB) {
+  constexpr int RF = ncomp<T>();            // real rows / k per element
   const int b = blockIdx.z;
   const BlockDesc& d = D[b];
   if (info[b]) return;
@@ -91,6 +115,7 @@ __global__ void __launch_bounds__(256) k_gemm_split(const BlockDesc* D, char* ws
   const int Mr = RF * n;
   const int m0 = blockIdx.y * OZ_M, n0 = blockIdx.x * OZ_N;   // m0 in rows of A', n0 in columns
   if (m0 >= Mr || n0 >= n) return;
+  if (herm && n0 > (m0 + OZ_M) / RF - 1) return;   // tile above the diagonal
   const T* A = bufp<T>(ws, d, bufA);
   const T* B = bufp<T>(ws, d, bufB);
   T* C = bufp<T>(ws, d, bufC);
@@ -131,23 +156,18 @@ __global__ void __launch_bounds__(256) k_gemm_split(const BlockDesc* D, char* ws
       T v = tzero<T>();
       if (gi < n && gk < n) v = opA == 0 ? A[(long long)gi * n + gk] : conjg(A[(long long)gk * n + gi]);
       const double sc = gi < n ? ldexp(1.0, -ea[gi]) : 0.0;
-      __bf16 qr[S], qi[S];
-      split_slices<S>(re(v), sc, qr);
-      if constexpr (CPLX) {
-        split_slices<S>(im(v), sc, qi);
+      __bf16 q[RF][S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          __bf16* p0 = As + (s * OZ_M + 2 * r) * OZ_LD + 2 * kk;
-          __bf16* p1 = p0 + OZ_LD;
-          p0[0] = qr[s];
-          p0[1] = -qi[s];
-          p1[0] = qi[s];
-          p1[1] = qr[s];
+      for (int c = 0; c < RF; ++c) split_slices<S>(comp(v, c), sc, q[c]);
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int c = 0; c < RF; ++c) {
+          __bf16 row[RF];
+#pragma unroll
+          for (int dd = 0; dd < RF; ++dd) row[dd] = qmul_sign(c, dd) > 0 ? q[c ^ dd][s] : -q[c ^ dd][s];
+          store_bf<RF>(As + (s * OZ_M + RF * r + c) * OZ_LD + RF * kk, row);
         }
-      } else {
-#pragma unroll
-        for (int s = 0; s < S; ++s) As[(s * OZ_M + r) * OZ_LD + kk] = qr[s];
-      }
     }
     // ---- split op(B) chunk into LDS (stored column-major: [col][k])
 #pragma unroll 1
@@ -158,19 +178,15 @@ __global__ void __launch_bounds__(256) k_gemm_split(const BlockDesc* D, char* ws
       T v = tzero<T>();
       if (gk < n && gj < n) v = opB == 0 ? B[(long long)gk * n + gj] : conjg(B[(long long)gj * n + gk]);
       const double sc = gj < n ? ldexp(1.0, -eb[gj]) : 0.0;
-      __bf16 qr[S], qi[S];
-      split_slices<S>(re(v), sc, qr);
-      if constexpr (CPLX) {
-        split_slices<S>(im(v), sc, qi);
+      __bf16 q[RF][S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          __bf16* p = Bs + (s * OZ_N + c) * OZ_LD + 2 * kk;
-          p[0] = qr[s];
-          p[1] = qi[s];
-        }
-      } else {
+      for (int cc = 0; cc < RF; ++cc) split_slices<S>(comp(v, cc), sc, q[cc]);
 #pragma unroll
-        for (int s = 0; s < S; ++s) Bs[(s * OZ_N + c) * OZ_LD + kk] = qr[s];
+      for (int s = 0; s < S; ++s) {
+        __bf16 col[RF];
+#pragma unroll
+        for (int dd = 0; dd < RF; ++dd) col[dd] = q[dd][s];
+        store_bf<RF>(Bs + (s * OZ_N + c) * OZ_LD + RF * kk, col);
       }
     }
     __syncthreads();
@@ -210,8 +226,7 @@ __global__ void __launch_bounds__(256) k_gemm_split(const BlockDesc* D, char* ws
       }
     }
   }
-  // ---- epilogue: undo the exponents, C = alpha P + beta C
-  const bool use_beta = (re(beta) != 0.0 || im(beta) != 0.0);
+  // ---- epilogue: undo the exponents, C = alpha P + beta C (real alpha, beta)
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int col = n0 + 32 * h + l32;
@@ -220,52 +235,57 @@ __global__ void __launch_bounds__(256) k_gemm_split(const BlockDesc* D, char* ws
     for (int j = 0; j < 16; j += RF) {
       const int rr = m0 + 32 * wave + 8 * (j / 4) + 4 * lhi + (j % 4);   // row of A'
       const int i = rr / RF;
-      if (i >= n) continue;
+      if (i >= n || (herm && col > i)) continue;
       const double sc = ldexp(1.0, ea[i] + eb[col]);
-      T p;
-      if constexpr (CPLX) p = cplx{acc64[h][j] * sc, acc64[h][j + 1] * sc};
-      else p = acc64[h][j] * sc;
+      double vals[RF];
+#pragma unroll
+      for (int c = 0; c < RF; ++c) vals[c] = acc64[h][j + c] * sc;
       const long long idx = (long long)i * n + col;
-      T v = alpha * p;
-      if (use_beta) v = mad(beta, C[idx], v);
+      T v = alpha * from_comps<T>(vals);
+      if (beta != 0.0) v = v + beta * C[idx];
       C[idx] = v;
+      if (herm && col < i) C[(long long)col * n + i] = conjg(v);
     }
   }
 }
 
 template <class T, int S>
 static void launch_split_s(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim,
-                           int dsel, int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta) {
-  constexpr int RF = sizeof(T) == sizeof(cplx) ? 2 : 1;
+                           int dsel, int bufA, int opA, int bufB, int opB, int bufC, double alpha, double beta,
+                           int herm) {
+  constexpr int RF = ncomp<T>();
   const size_t shm = (size_t)S * (OZ_M + OZ_N) * OZ_LD * sizeof(__bf16);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_split<T, S>), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shm);
   dim3 grid((maxdim + OZ_N - 1) / OZ_N, (RF * maxdim + OZ_M - 1) / OZ_M, nblk);
   hipLaunchKernelGGL((k_gemm_split<T, S>), grid, dim3(256), shm, s, D, ws, info, dsel, bufA, opA, bufB, opB, bufC,
-                     alpha, beta, (int)V_EXA, (int)V_EXB);
+                     alpha, beta, herm, (int)V_EXA, (int)V_EXB);
 }
 
 template <class T>
 void launch_gemm_split(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
-                       int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int slices) {
+                       int bufA, int opA, int bufB, int opB, int bufC, double alpha, double beta, int slices,
+                       int herm) {
   const dim3 lg((maxdim + 3) / 4, nblk);
   hipLaunchKernelGGL(k_line_exp<T>, lg, dim3(256), 0, s, D, ws, info, dsel, bufA, opA == 0 ? 1 : 0, (int)V_EXA);
   hipLaunchKernelGGL(k_line_exp<T>, lg, dim3(256), 0, s, D, ws, info, dsel, bufB, opB == 0 ? 0 : 1, (int)V_EXB);
   switch (slices) {
-    case 1: launch_split_s<T, 1>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
-    case 2: launch_split_s<T, 2>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
-    case 3: launch_split_s<T, 3>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
-    case 4: launch_split_s<T, 4>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
-    case 5: launch_split_s<T, 5>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
-    case 6: launch_split_s<T, 6>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
-    case 7: launch_split_s<T, 7>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
-    default: launch_split_s<T, 8>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta); break;
+    case 1: launch_split_s<T, 1>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta, herm); break;
+    case 2: launch_split_s<T, 2>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta, herm); break;
+    case 3: launch_split_s<T, 3>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta, herm); break;
+    case 4: launch_split_s<T, 4>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta, herm); break;
+    case 5: launch_split_s<T, 5>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta, herm); break;
+    case 6: launch_split_s<T, 6>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta, herm); break;
+    case 7: launch_split_s<T, 7>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta, herm); break;
+    default: launch_split_s<T, 8>(s, D, ws, info, nblk, maxdim, dsel, bufA, opA, bufB, opB, bufC, alpha, beta, herm); break;
   }
 }
 
 template void launch_gemm_split<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int,
-                                        int, int, int, double, double, int);
+                                        int, int, int, double, double, int, int);
 template void launch_gemm_split<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
-                                      int, int, cplx, cplx, int);
+                                      int, int, double, double, int, int);
+template void launch_gemm_split<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,
+                                      int, int, double, double, int, int);
 
 }  // namespace x2c

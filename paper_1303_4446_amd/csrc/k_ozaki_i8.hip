@@ -14,13 +14,17 @@
 // per inner-dimension term relative to the product of the line maxima, the
 // size of the operands' own truncation.
 //
-// Complex operands: the real form has rows 2i (Re) and 2i+1 (Im) and a K
-// axis of two halves (real parts, then imaginary parts):
-//   A'[2i]   = [Re a_i, -Im a_i],   A'[2i+1] = [Im a_i, Re a_i],
-//   B'[:, j] = [Re b_j ; Im b_j],
-// so (A'B')_{2i,j} = Re (AB)_ij and (A'B')_{2i+1,j} = Im (AB)_ij.  The split
-// stores only Re and Im slices of each line; the product kernel builds A'
-// while staging (negating bytes of the Im slices where needed).
+// Complex and quaternion operands (F = 2, 4 real components): the real form
+// has rows F i + c and a K axis of F parts (part d holds component d of
+// every k):
+//   A'[F i + c] over part d = sigma(c, d) (component c xor d of row i of A),
+//   B'[:, j] over part d = component d of column j of B,
+// with sigma the sign pattern of the quaternion product (restricted to
+// c, d < 2 it is the complex product), so (A'B')_{F i + c, j} = component c
+// of (AB)_ij.  The split stores the F component slices of each line once;
+// the product kernel builds A' while staging (choosing the component and
+// negating bytes where sigma is -1).  herm = 1: Hermitian product, only the
+// tiles reaching the lower triangle run and each lower element is mirrored.
 #include "x2c_device.h"
 #include "x2c_launch.h"
 
@@ -42,7 +46,7 @@ __host__ __device__ inline int kpad64(int n) { return (n + 63) / 64 * 64; }
 template <class T>
 __global__ void __launch_bounds__(256) k_split_i8(const BlockDesc* D, char* ws, const int* info, int dsel, int buf,
                                                   int op, int side, int S, int bufOut, int bufE) {
-  constexpr bool CP = sizeof(T) == sizeof(cplx);
+  constexpr int parts = ncomp<T>();
   const int b = blockIdx.y;
   const BlockDesc& d = D[b];
   if (info[b]) return;
@@ -58,10 +62,7 @@ __global__ void __launch_bounds__(256) k_split_i8(const BlockDesc* D, char* ws, 
     return op == 0 ? v : conjg(v);
   };
   double mx = 0.0;
-  for (int k = lane; k < n; k += 64) {
-    const T v = elem(k);
-    mx = fmax(mx, fmax(fabs(re(v)), fabs(im(v))));
-  }
+  for (int k = lane; k < n; k += 64) mx = fmax(mx, amax(elem(k)));
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
   int e = 0;
   if (mx > 0.0) frexp(mx, &e);
@@ -71,11 +72,10 @@ __global__ void __launch_bounds__(256) k_split_i8(const BlockDesc* D, char* ws, 
   const int kp = kpad64(n);
   const long long plane = (long long)n * kp;          // one part of one slice
   signed char* out = bufp<signed char>(ws, d, bufOut);
-  const int parts = CP ? 2 : 1;
   for (int k = lane; k < kp; k += 64) {
     const T v = k < n ? elem(k) : tzero<T>();
     for (int p = 0; p < parts; ++p) {
-      double y = (p == 0 ? re(v) : im(v)) * sc;
+      double y = comp(v, p) * sc;
       for (int s = 0; s < S; ++s) {
         y *= 128.0;
         const double r = rint(y);
@@ -92,11 +92,18 @@ __device__ inline int neg_bytes(int x) {
   return ((y & 0x7F7F7F7F) + 0x01010101) ^ (y & 0x80808080);
 }
 
+template <class T>
+__device__ inline T from_comps_i8(const double* v) {
+  if constexpr (ncomp<T>() == 1) return v[0];
+  else if constexpr (ncomp<T>() == 2) return cplx{v[0], v[1]};
+  else return quat{{v[0], v[1]}, {v[2], v[3]}};
+}
+
 template <class T, int S>
 __global__ void __launch_bounds__(256) k_gemm_i8(const BlockDesc* D, char* ws, const int* info, int dsel, int bufC,
-                                                 T alpha, T beta, int bufSA, int bufSB, int bufEA, int bufEB) {
-  constexpr bool CP = sizeof(T) == sizeof(cplx);
-  constexpr int RF = CP ? 2 : 1;
+                                                 double alpha, double beta, int herm, int bufSA, int bufSB, int bufEA,
+                                                 int bufEB) {
+  constexpr int RF = ncomp<T>();
   const int b = blockIdx.z;
   const BlockDesc& d = D[b];
   if (info[b]) return;
@@ -104,6 +111,7 @@ __global__ void __launch_bounds__(256) k_gemm_i8(const BlockDesc* D, char* ws, c
   const int Mr = RF * n;
   const int m0 = blockIdx.y * Q8_M, n0 = blockIdx.x * Q8_N;   // m0: rows of A'
   if (m0 >= Mr || n0 >= n) return;
+  if (herm && n0 > (m0 + Q8_M) / RF - 1) return;   // tile above the diagonal
   const int kp = kpad64(n);
   const long long plane = (long long)n * kp;
   const signed char* SA = bufp<signed char>(ws, d, bufSA);
@@ -126,24 +134,21 @@ __global__ void __launch_bounds__(256) k_gemm_i8(const BlockDesc* D, char* ws, c
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[g][h][j] = 0;
 
-  const int nk = RF * kp / Q8_KC;            // chunks over the (two-part) K axis
+  const int nk = RF * kp / Q8_KC;            // chunks over the RF-part K axis
   for (int ch = 0; ch < nk; ++ch) {
-    const int half = (ch * Q8_KC) / kp;      // 0: real-part K half, 1: imaginary-part half
-    const int kc = ch * Q8_KC - half * kp;   // offset inside the half
+    const int half = (ch * Q8_KC) / kp;      // K part: the component of B'
+    const int kc = ch * Q8_KC - half * kp;   // offset inside the part
     // ---- stage A' rows (16-byte pieces: 4 per row per slice)
     for (int e = t; e < S * Q8_M * 4; e += 256) {
       const int s = e / (Q8_M * 4), rem = e % (Q8_M * 4), rr = rem / 4, piece = rem % 4;
       const int grow = m0 + rr;                 // row of A'
       i4 v = {0, 0, 0, 0};
       if (grow < Mr) {
-        const int i = grow / RF, reim = grow % RF;
-        // complex: row Re -> [Re | -Im], row Im -> [Im | Re]; real: [Re]
-        int part = 0;
-        bool neg = false;
-        if (CP) {
-          if (reim == 0) { part = half; neg = half == 1; }
-          else { part = 1 - half; }
-        }
+        const int i = grow / RF, cc = grow % RF;
+        // row component cc over K part `half`: component cc xor half of A,
+        // negated where the product's sign pattern is -1
+        const int part = cc ^ half;
+        const bool neg = qmul_sign(cc, half) < 0;
         const signed char* src = SA + ((long long)s * RF + part) * plane + (long long)i * kp + kc + 16 * piece;
         v = *reinterpret_cast<const i4*>(src);
         if (neg) {
@@ -187,7 +192,6 @@ __global__ void __launch_bounds__(256) k_gemm_i8(const BlockDesc* D, char* ws, c
     __syncthreads();
   }
   // ---- fold the exact group sums into FP64 (smallest weights first) and store
-  const bool use_beta = (re(beta) != 0.0 || im(beta) != 0.0);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int col = n0 + 32 * h + l32;
@@ -204,54 +208,58 @@ __global__ void __launch_bounds__(256) k_gemm_i8(const BlockDesc* D, char* ws, c
     for (int j = 0; j < 16; j += RF) {
       const int rr = m0 + 32 * wave + 8 * (j / 4) + 4 * lhi + (j % 4);
       const int i = rr / RF;
-      if (i >= n) continue;
+      if (i >= n || (herm && col > i)) continue;
       const double sc = ldexp(1.0, ea[i] + eb[col]);
-      T p;
-      if constexpr (CP) p = cplx{a64[j] * sc, a64[j + 1] * sc};
-      else p = a64[j] * sc;
+      double vals[RF];
+#pragma unroll
+      for (int c = 0; c < RF; ++c) vals[c] = a64[j + c] * sc;
       const long long idx = (long long)i * n + col;
-      T v = alpha * p;
-      if (use_beta) v = mad(beta, C[idx], v);
+      T v = alpha * from_comps_i8<T>(vals);
+      if (beta != 0.0) v = v + beta * C[idx];
       C[idx] = v;
+      if (herm && col < i) C[(long long)col * n + i] = conjg(v);
     }
   }
 }
 
 template <class T, int S>
 static void launch_i8_s(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
-                        int bufC, T alpha, T beta) {
-  constexpr int RF = sizeof(T) == sizeof(cplx) ? 2 : 1;
+                        int bufC, double alpha, double beta, int herm) {
+  constexpr int RF = ncomp<T>();
   const size_t shm = (size_t)S * (Q8_M + Q8_N) * Q8_LD;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_i8<T, S>), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shm);
   dim3 grid((maxdim + Q8_N - 1) / Q8_N, (RF * maxdim + Q8_M - 1) / Q8_M, nblk);
-  hipLaunchKernelGGL((k_gemm_i8<T, S>), grid, dim3(256), shm, s, D, ws, info, dsel, bufC, alpha, beta, (int)Z_SLA,
-                     (int)Z_SLB, (int)V_EXA, (int)V_EXB);
+  hipLaunchKernelGGL((k_gemm_i8<T, S>), grid, dim3(256), shm, s, D, ws, info, dsel, bufC, alpha, beta, herm,
+                     (int)Z_SLA, (int)Z_SLB, (int)V_EXA, (int)V_EXB);
 }
 
 template <class T>
 void launch_gemm_split_i8(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim,
-                          int dsel, int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int slices) {
+                          int dsel, int bufA, int opA, int bufB, int opB, int bufC, double alpha, double beta,
+                          int slices, int herm) {
   const dim3 lg((maxdim + 3) / 4, nblk);
   hipLaunchKernelGGL(k_split_i8<T>, lg, dim3(256), 0, s, D, ws, info, dsel, bufA, opA, 0, slices, (int)Z_SLA,
                      (int)V_EXA);
   hipLaunchKernelGGL(k_split_i8<T>, lg, dim3(256), 0, s, D, ws, info, dsel, bufB, opB, 1, slices, (int)Z_SLB,
                      (int)V_EXB);
   switch (slices) {
-    case 1: launch_i8_s<T, 1>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta); break;
-    case 2: launch_i8_s<T, 2>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta); break;
-    case 3: launch_i8_s<T, 3>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta); break;
-    case 4: launch_i8_s<T, 4>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta); break;
-    case 5: launch_i8_s<T, 5>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta); break;
-    case 6: launch_i8_s<T, 6>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta); break;
-    case 7: launch_i8_s<T, 7>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta); break;
-    default: launch_i8_s<T, 8>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta); break;
+    case 1: launch_i8_s<T, 1>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta, herm); break;
+    case 2: launch_i8_s<T, 2>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta, herm); break;
+    case 3: launch_i8_s<T, 3>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta, herm); break;
+    case 4: launch_i8_s<T, 4>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta, herm); break;
+    case 5: launch_i8_s<T, 5>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta, herm); break;
+    case 6: launch_i8_s<T, 6>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta, herm); break;
+    case 7: launch_i8_s<T, 7>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta, herm); break;
+    default: launch_i8_s<T, 8>(s, D, ws, info, nblk, maxdim, dsel, bufC, alpha, beta, herm); break;
   }
 }
 
 template void launch_gemm_split_i8<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int,
-                                           int, int, int, double, double, int);
+                                           int, int, int, double, double, int, int);
 template void launch_gemm_split_i8<cplx>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int,
-                                         int, int, int, cplx, cplx, int);
+                                         int, int, int, double, double, int, int);
+template void launch_gemm_split_i8<quat>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int,
+                                         int, int, int, double, double, int, int);
 
 }  // namespace x2c

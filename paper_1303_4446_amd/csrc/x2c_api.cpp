@@ -687,24 +687,31 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
   const int maxN = dm.maxN, maxn = dm.maxn, maxm = dm.maxm;
   const int OPN = 0, OPH = 1;
   const bool kramers = tc && o->reduction == X2C_RED_QUATERNION;
-  // products of the X / L / S~ / R chain: FP64, or split bf16 slices
+  // products of the X / L / S~ / R chain: FP64, or split bf16 / int8 slices
   const int slices =
       o->ozaki_slices > 0 ? o->ozaki_slices : (o->prec == X2C_SPLIT_INT8 ? AUTO_SLICES_I8 : AUTO_SLICES);
-  // herm = 1 marks products whose result (and beta C) is Hermitian
-  auto chain_gemm = [&](int bA, int opA, int bB, int opB, int bC, T alpha, T beta, int herm = 0) {
-    if (o->prec == X2C_SPLIT_BF16)
-      launch_gemm_split<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, slices);
-    else if (o->prec == X2C_SPLIT_INT8)
-      launch_gemm_split_i8<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, slices);
-    else
-      launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, herm);
-  };
-  // FP64 time-reversal-symmetric chain: quaternion N x N products (half the
-  // real multiply-adds of the complex 2N x 2N ones); real alpha, beta
-  const bool qchain = kramers && o->prec == X2C_FP64;
+  // Two-component blocks with the quaternion reduction run the whole chain
+  // on quaternion N x N matrices (time-reversal structure; half the real
+  // multiply-adds of the complex 2N x 2N products) in every precision; the
+  // others on the complex (real spin-free) n x n matrices.  herm = 1 marks
+  // products whose result (and beta C) is Hermitian: lower tiles only.
+  const bool qchain = kramers;
   auto G = [&](int bA, int opA, int bB, int opB, int bC, double alpha, double beta, int herm = 0) {
-    if (qchain) launch_gemm_q(s, D, ws, info, nblk, maxN, DIM_N, bA, opA, bB, opB, bC, alpha, beta, herm);
-    else chain_gemm(bA, opA, bB, opB, bC, tcast<T>(alpha), tcast<T>(beta), herm);
+    if (qchain) {
+      if (o->prec == X2C_SPLIT_BF16)
+        launch_gemm_split<quat>(s, D, ws, info, nblk, maxN, DIM_N, bA, opA, bB, opB, bC, alpha, beta, slices, herm);
+      else if (o->prec == X2C_SPLIT_INT8)
+        launch_gemm_split_i8<quat>(s, D, ws, info, nblk, maxN, DIM_N, bA, opA, bB, opB, bC, alpha, beta, slices,
+                                   herm);
+      else
+        launch_gemm_q(s, D, ws, info, nblk, maxN, DIM_N, bA, opA, bB, opB, bC, alpha, beta, herm);
+    } else if (o->prec == X2C_SPLIT_BF16) {
+      launch_gemm_split<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, slices, herm);
+    } else if (o->prec == X2C_SPLIT_INT8) {
+      launch_gemm_split_i8<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, alpha, beta, slices, herm);
+    } else {
+      launch_gemm<T>(s, D, ws, info, nblk, maxn, DIM_n, bA, opA, bB, opB, bC, tcast<T>(alpha), tcast<T>(beta), herm);
+    }
   };
   // quaternion x real scalar matrix (R_* buffers): side 0 op(R) Q, side 1
   // Q op(R); tri 1 / 2 = op(R) lower / upper triangular
@@ -822,7 +829,6 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
       if (kramers) {
         launch_large_xtilde<quat>(s, D, hd, ws, info, DIM_n, DIM_N, hd.N, C_A, H_A, H_B, H_C, H_D, H_E, C_QMH,
                                   NS_AUX_IT, NS_TOL);
-        if (!qchain) launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_QMH, C_TMP);
       } else {
         launch_large_xtilde<T>(s, D, hd, ws, info, DIM_m, DIM_n, hd.n, C_A, H_A, H_B, H_C, H_D, H_E, C_TMP,
                                NS_AUX_IT, NS_TOL);
@@ -833,10 +839,8 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
       if (kramers) launch_xsolve_blk<quat>(s, D, ws, info, nblk, maxN, C_Y, DIM_N, Q_X2);
       else launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn, C_Y, DIM_n, Q_X2);
     } else if (kramers) {
-      // quaternion LU of the N x N block Y_L (X~ to the complex layout unless
-      // the chain runs on quaternions)
+      // quaternion LU of the N x N block Y_L
       launch_xsolve_blk<quat>(s, D, ws, info, nblk, maxN, C_Y, DIM_N, C_QMH);
-      if (!qchain) launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_QMH, C_TMP);
     } else {
       launch_xsolve_blk<T>(s, D, ws, info, nblk, maxn, C_Y, DIM_n, C_TMP);
     }
@@ -890,10 +894,7 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
     // else into C_QMH, where the reductions below leave it)
     STAGE("invsqrt_Q");
     if (kramers) {
-      if (!qchain) launch_cplx_to_quat(s, D, ws, info, nblk, maxN, C_Q, C_TMP2);
-      launch_large_invsqrt<quat>(s, D, hd, ws, info, DIM_N, hd.N, qchain ? C_Q : C_TMP2, H_A, H_B, H_C, H_D, C_LR,
-                                 NS_AUX_IT, NS_TOL);
-      if (!qchain) launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_LR, C_QMH);
+      launch_large_invsqrt<quat>(s, D, hd, ws, info, DIM_N, hd.N, C_Q, H_A, H_B, H_C, H_D, C_LR, NS_AUX_IT, NS_TOL);
     } else {
       launch_large_invsqrt<T>(s, D, hd, ws, info, DIM_n, hd.n, C_Q, H_A, H_B, H_C, H_D, C_QMH, NS_AUX_IT, NS_TOL);
     }
@@ -913,10 +914,9 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
       launch_ormtr_blocked<T>(s, D, ws, info, nblk, maxn, maxn, DIM_n, C_Q, V_TAUQ, W_TFQ, C_QMH, DIM_n);
     }
   } else {
-    const int qrefl = qchain ? C_Q : C_TMP2;   // quaternion Q, then its reflectors
+    const int qrefl = C_Q;   // quaternion Q, then its reflectors
     {
       STAGE("tridiag_Q");
-      if (!qchain) launch_cplx_to_quat(s, D, ws, info, nblk, maxN, C_Q, C_TMP2);
       launch_hetrd_mk<quat>(s, D, ws, info, nblk, maxN, DIM_N, qrefl, V_DQ, V_EQ, V_TAUQ, W_PAN, W_VCUR, W_HS,
                             V_ET, mv_res);
       launch_phase_q(s, D, ws, info, nblk, DIM_N);
@@ -929,7 +929,6 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
       launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxN, maxN, DIM_N, qrefl, V_TAUQ, W_TFQ, C_TMP, DIM_N);
       launch_qct_scale(s, D, ws, info, nblk, maxN, C_TMP, C_LR);
       launch_ormtr_blocked<quat>(s, D, ws, info, nblk, maxN, maxN, DIM_N, qrefl, V_TAUQ, W_TFQ, C_LR, DIM_N);
-      if (!qchain) launch_quat_to_cplx(s, D, ws, info, nblk, maxN, C_LR, C_QMH);
     }
   }
   {

@@ -76,6 +76,21 @@ __host__ __device__ inline double abs1(quat x) { return abs1(x.a) + abs1(x.b); }
 __device__ inline quat mad(quat x, quat y, quat c) { return c + x * y; }
 __device__ inline quat mad(double s, quat y, quat c) { return {mad(s, y.a, c.a), mad(s, y.b, c.b)}; }
 
+// real components of an element (1 real, 2 complex, 4 quaternion:
+// (Re a, Im a, Re b, Im b)) and the largest of their moduli
+template <class T>
+constexpr int ncomp() {
+  return (int)(sizeof(T) / sizeof(double));
+}
+__host__ __device__ inline double comp(double v, int) { return v; }
+__host__ __device__ inline double comp(cplx v, int c) { return c == 0 ? v.x : v.y; }
+__host__ __device__ inline double comp(quat v, int c) {
+  return c == 0 ? v.a.x : (c == 1 ? v.a.y : (c == 2 ? v.b.x : v.b.y));
+}
+__host__ __device__ inline double amax(double v) { return fabs(v); }
+__host__ __device__ inline double amax(cplx v) { return fmax(fabs(v.x), fabs(v.y)); }
+__host__ __device__ inline double amax(quat v) { return fmax(amax(v.a), amax(v.b)); }
+
 template <class T> __host__ __device__ inline T tzero();
 template <> __host__ __device__ inline double tzero<double>() { return 0.0; }
 template <> __host__ __device__ inline cplx tzero<cplx>() { return {0.0, 0.0}; }

@@ -44,13 +44,17 @@ template <class T>
 void launch_gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                  int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int herm = 0, int tri = 0);
 
+// split-precision products (bf16 or int8 slices); T = double, cplx or quat;
+// real alpha, beta; herm = 1: Hermitian product (lower tiles, mirrored)
 template <class T>
 void launch_gemm_split(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
-                       int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int slices);
+                       int bufA, int opA, int bufB, int opB, int bufC, double alpha, double beta, int slices,
+                       int herm = 0);
 
 template <class T>
 void launch_gemm_split_i8(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim,
-                          int dsel, int bufA, int opA, int bufB, int opB, int bufC, T alpha, T beta, int slices);
+                          int dsel, int bufA, int opA, int bufB, int opB, int bufC, double alpha, double beta,
+                          int slices, int herm = 0);
 
 template <class T>
 void launch_hetrd(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
