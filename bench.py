@@ -175,8 +175,25 @@ def time_picture_change(px, torch, batch, twocomp, c, prec, red, stream, calls=3
     ms = e0.elapsed_time(e1) / calls
     if not bool(torch.isfinite(out).all()) or bool((info != 0).any()):
         return None
-    return {"operator": "nuclear attraction (P_LL = V, P_SS = W/4c^2)", "ms_per_call": ms,
-            "blocks_per_s": len(batch.Ns) / (ms / 1e3)}
+    res = {"operator": "nuclear attraction (P_LL = V, P_SS = W/4c^2)", "ms_per_call": ms,
+           "blocks_per_s": len(batch.Ns) / (ms / 1e3)}
+    if twocomp:
+        # the operator is time-even: the quaternion products of
+        # x2c_picture_change_kramers, checked against the complex products
+        outq, _ = px.picture_change(batch.Ns, True, h_off, PLL, PSS, X, R, c=c, workspace=ws, stream=stream,
+                                    time_even=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(calls):
+            px.picture_change(batch.Ns, True, h_off, PLL, PSS, X, R, c=c, workspace=ws, stream=stream, out=outq,
+                              time_even=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        msq = e0.elapsed_time(e1) / calls
+        dev = float((outq - out).abs().max() / out.abs().max())
+        res["time_even_quaternion"] = {"ms_per_call": msq, "blocks_per_s": len(batch.Ns) / (msq / 1e3),
+                                       "max_rel_diff_vs_complex": dev}
+    return res
 
 
 def parse(argv=None):

@@ -294,6 +294,25 @@ int x2c_picture_change(const x2c_options* opts, int nblk, const int* N, const in
                        void* out, void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * x2c_picture_change for time-even operators of two-component blocks (the
+ * same arguments, layout, workspace and return codes; opts->mode must be
+ * X2C_TWOCOMP).  Every two-component matrix of the method has the
+ * time-reversal form [[A, B], [-B*, A*]] in the [all alpha; all beta] basis
+ * (Sec. III.A, Kramers pairs); so has a time-even property's matrix, e.g.
+ * any spin-free multiplicative operator and its W^O (Eq. defw with O in
+ * place of V).  The five products then run on the quaternion N x N forms
+ * A + B j: half the real multiply-adds of x2c_picture_change.  Only the
+ * first N rows (the blocks A and B) of PLL, PLS, PSL, PSS, X and R are read,
+ * and out is written whole in that form; a time-odd operator (one whose
+ * matrix lacks the form, e.g. a magnetic one) gives a wrong result, which is
+ * not detected: use x2c_picture_change for it.
+ */
+int x2c_picture_change_kramers(const x2c_options* opts, int nblk, const int* N, const int64_t* p_off,
+                               const double* PLL, const double* PLS, const double* PSL, const double* PSS,
+                               const void* X, const void* R, void* out, void* workspace, size_t ws_bytes,
+                               void* stream);
+
+/*
  * Workspace size in bytes for x2c_dlu_assemble with `natom` atoms of scalar
  * sizes N[0..natom) (host).  0 for invalid arguments.
  */

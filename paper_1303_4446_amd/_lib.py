@@ -27,7 +27,7 @@ EXPORTED = ("x2c_max_n", "x2c_device_wide_min_n", "x2c_workspace_bytes", "x2c_bu
             "x2c_build_batched_noalloc", "x2c_bss_workspace_bytes", "x2c_bss_batched", "x2c_dkh_workspace_bytes",
             "x2c_dkh_batched", "x2c_dkh_products", "x2c_tuned_shape",
             "x2c_dlu_workspace_bytes", "x2c_dlu_assemble", "x2c_strerror", "x2c_release", "x2c_graph_enable",
-            "x2c_stream_split", "x2c_autotune", "x2c_picture_change", "x2c_trace_enable", "x2c_trace_read",
+            "x2c_stream_split", "x2c_autotune", "x2c_picture_change", "x2c_picture_change_kramers", "x2c_trace_enable", "x2c_trace_read",
             "x2c_trace_reset")
 
 
@@ -98,6 +98,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.x2c_picture_change.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp, vp, vp, vp,
                                        vp, ctypes.c_size_t, vp]
     lib.x2c_picture_change.restype = i32
+    lib.x2c_picture_change_kramers.argtypes = [optp, i32, ctypes.POINTER(ctypes.c_int), i64p, vp, vp, vp, vp, vp, vp, vp,
+                                       vp, ctypes.c_size_t, vp]
+    lib.x2c_picture_change_kramers.restype = i32
     lib.x2c_strerror.argtypes = [i32]
     lib.x2c_strerror.restype = ctypes.c_char_p
     lib.x2c_release.argtypes = []
@@ -278,11 +281,13 @@ def build_batched_xr(batch: Batch, c: float, prec: int = FP64, slices: int = 0, 
 
 
 def picture_change(Ns, twocomp: bool, p_off, PLL, PSS, X, R, PLS=None, PSL=None, c: float = 137.0,
-                   workspace=None, stream=None, out=None):
+                   workspace=None, stream=None, out=None, time_even: bool = False):
     """Enqueue x2c_picture_change: per block P~ = R^H [P_LL + P_LS X +
     X^H P_SL + X^H P_SS X] R.  All matrices are flat device float64 tensors
     in the layout of h (block b at double offset p_off[b]); PLS / PSL may be
-    None.  Returns (out, workspace)."""
+    None.  time_even (two-component only): x2c_picture_change_kramers, the
+    quaternion products for operators of time-reversal form.  Returns (out,
+    workspace)."""
     torch = _torch()
     lib = load()
     dev = PLL.device
@@ -295,7 +300,8 @@ def picture_change(Ns, twocomp: bool, p_off, PLL, PSS, X, R, PLS=None, PSL=None,
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
     opt = options(twocomp, c)
     f64 = lambda t: None if t is None else _dev(t, torch, torch.float64)
-    rc = lib.x2c_picture_change(
+    fn = lib.x2c_picture_change_kramers if time_even else lib.x2c_picture_change
+    rc = fn(
         ctypes.byref(opt), len(Ns), Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
         po.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), f64(PLL), f64(PLS), f64(PSL), f64(PSS), f64(X), f64(R),
         f64(out), ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()), _stream_ptr(torch, stream))

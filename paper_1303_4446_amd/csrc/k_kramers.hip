@@ -170,6 +170,23 @@ __global__ void k_eye_q(const BlockDesc* D, char* ws, const int* info, int buf) 
     Q[e] = treal<quat>(e / N == e % N ? 1.0 : 0.0);
 }
 
+// complex 2N x 2N matrix of time-reversal form [[A, B], [-B*, A*]] at
+// in + h_off -> quaternion N x N buffer A + B j (only the blocks A and B,
+// the first N rows, are read)
+__global__ void k_read_q(const BlockDesc* D, char* ws, const int* info, const double* in, int buf) {
+  const BlockDesc& d = D[blockIdx.y];
+  if (info[blockIdx.y]) return;
+  const int N = d.N, n = d.n;
+  const cplx* M = reinterpret_cast<const cplx*>(in + d.h_off);
+  quat* Q = bufp<quat>(ws, d, buf);
+  const long long tot = (long long)N * N;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    Q[e] = quat{M[(long long)i * n + j], M[(long long)i * n + N + j]};
+  }
+}
+
 // quaternion N x N workspace buffer -> complex 2N x 2N at out + h_off (zero
 // for a failed block, whose eigenvalues are zeroed too when eps is given)
 __global__ void k_write_q(const BlockDesc* D, char* ws, const int* info, double* out, int buf, double* eps) {
@@ -226,6 +243,10 @@ void launch_expand_q(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
 }
 void launch_eye_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int buf) {
   hipLaunchKernelGGL(k_eye_q, dim3(grid_for((long long)maxN * maxN), nblk), dim3(256), 0, s, D, ws, info, buf);
+}
+void launch_read_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, const double* in,
+                   int buf) {
+  hipLaunchKernelGGL(k_read_q, dim3(grid_for((long long)maxN * maxN), nblk), dim3(256), 0, s, D, ws, info, in, buf);
 }
 void launch_write_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double* out,
                     int buf, double* eps) {

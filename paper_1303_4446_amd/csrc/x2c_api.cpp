@@ -1257,6 +1257,37 @@ int run_picture_change(const Layout& L, int nblk, const double* PLL, const doubl
   return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
 }
 
+// The same for time-even operators of two-component blocks: every matrix has
+// the time-reversal form [[A, B], [-B*, A*]] (X and R always; P when the
+// operator is time-even, e.g. spin-free or spin-orbit multiplicative
+// operators), so the five products run on the quaternion N x N forms (half
+// the real multiply-adds of the complex 2N x 2N products).
+int run_picture_change_q(const Layout& L, int nblk, const double* PLL, const double* PLS, const double* PSL,
+                         const double* PSS, const double* X, const double* R, double* out, char* ws, hipStream_t s) {
+  const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off);
+  int* info = reinterpret_cast<int*>(ws + L.info_off);
+  const int maxN = L.maxN;
+  launch_init_info(s, info, nblk);
+  launch_read_q(s, D, ws, info, nblk, maxN, X, C_X);
+  launch_read_q(s, D, ws, info, nblk, maxN, R, C_R);
+  launch_read_q(s, D, ws, info, nblk, maxN, PLL, C_L);
+  launch_read_q(s, D, ws, info, nblk, maxN, PSS, C_WPP);
+  // C_WX = P_SS X + P_SL
+  if (PSL) launch_read_q(s, D, ws, info, nblk, maxN, PSL, C_WX);
+  launch_gemm_q(s, D, ws, info, nblk, maxN, DIM_N, C_WPP, 0, C_X, 0, C_WX, 1.0, PSL ? 1.0 : 0.0, 0);
+  // C_L = P_LL + P_LS X + X^H C_WX
+  if (PLS) {
+    launch_read_q(s, D, ws, info, nblk, maxN, PLS, C_TMP);
+    launch_gemm_q(s, D, ws, info, nblk, maxN, DIM_N, C_TMP, 0, C_X, 0, C_L, 1.0, 1.0, 0);
+  }
+  launch_gemm_q(s, D, ws, info, nblk, maxN, DIM_N, C_X, 1, C_WX, 0, C_L, 1.0, 1.0, 0);
+  // R^H (C_L R)
+  launch_gemm_q(s, D, ws, info, nblk, maxN, DIM_N, C_L, 0, C_R, 0, C_LR, 1.0, 0.0, 0);
+  launch_gemm_q(s, D, ws, info, nblk, maxN, DIM_N, C_R, 1, C_LR, 0, C_H, 1.0, 0.0, 0);
+  launch_write_q(s, D, ws, info, nblk, maxN, out, C_H, nullptr);
+  return hipGetLastError() == hipSuccess ? X2C_OK : X2C_EHIP;
+}
+
 // ---------------------------------------------------------------- graphs
 // The whole launch sequence of a call (about 2N kernels per block size N,
 // most of them short column steps of the reductions) is captured once per
@@ -1554,9 +1585,9 @@ int x2c_dkh_batched(const x2c_options* opts, int order, int nblk, const int* N, 
                  ws_bytes, static_cast<hipStream_t>(stream), nullptr, order);
 }
 
-int x2c_picture_change(const x2c_options* opts, int nblk, const int* N, const int64_t* p_off, const double* PLL,
+static int picture_change_impl(const x2c_options* opts, int nblk, const int* N, const int64_t* p_off, const double* PLL,
                        const double* PLS, const double* PSL, const double* PSS, const void* X, const void* R,
-                       void* out, void* workspace, size_t ws_bytes, void* stream) {
+                       void* out, void* workspace, size_t ws_bytes, void* stream, bool kramers) {
   if (nblk == 0 && valid_opts(opts)) return X2C_OK;
   if (!valid_opts(opts) || nblk < 0 || !N || !p_off || !PLL || !PSS || !X || !R || !out || !workspace)
     return X2C_EINVAL;
@@ -1573,8 +1604,23 @@ int x2c_picture_change(const x2c_options* opts, int nblk, const int* N, const in
   const double* Xd = static_cast<const double*>(X);
   const double* Rd = static_cast<const double*>(R);
   double* o = static_cast<double*>(out);
+  if (kramers) return run_picture_change_q(*L, nblk, PLL, PLS, PSL, PSS, Xd, Rd, o, ws, s);
   if (opts->mode == X2C_TWOCOMP) return run_picture_change<cplx>(*L, nblk, PLL, PLS, PSL, PSS, Xd, Rd, o, ws, s);
   return run_picture_change<double>(*L, nblk, PLL, PLS, PSL, PSS, Xd, Rd, o, ws, s);
+}
+
+int x2c_picture_change(const x2c_options* opts, int nblk, const int* N, const int64_t* p_off, const double* PLL,
+                       const double* PLS, const double* PSL, const double* PSS, const void* X, const void* R,
+                       void* out, void* workspace, size_t ws_bytes, void* stream) {
+  return picture_change_impl(opts, nblk, N, p_off, PLL, PLS, PSL, PSS, X, R, out, workspace, ws_bytes, stream, false);
+}
+
+int x2c_picture_change_kramers(const x2c_options* opts, int nblk, const int* N, const int64_t* p_off,
+                               const double* PLL, const double* PLS, const double* PSL, const double* PSS,
+                               const void* X, const void* R, void* out, void* workspace, size_t ws_bytes,
+                               void* stream) {
+  if (!opts || opts->mode != X2C_TWOCOMP) return X2C_EINVAL;
+  return picture_change_impl(opts, nblk, N, p_off, PLL, PLS, PSL, PSS, X, R, out, workspace, ws_bytes, stream, true);
 }
 
 size_t x2c_dlu_workspace_bytes(const x2c_options* opts, int natom, const int* N) {

@@ -88,6 +88,8 @@ void launch_expand_q(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
 void launch_eye_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int buf);
 void launch_write_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, double* out,
                     int buf, double* eps);
+void launch_read_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, const double* in,
+                   int buf);
 void launch_gemm_qr(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int side,
                     int bufR, int opR, int tri, int bufQ, int bufC, double alpha, double beta, int herm);
 void launch_gemm_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,

@@ -99,3 +99,42 @@ def test_identity_maps_to_metric_end_to_end(twocomp):
     for g, Sx in zip(got, S_l):
         assert np.abs(g - Sx).max() <= 2e-9 * np.abs(Sx).max()
 
+
+
+def test_time_even_quaternion_products_match_complex_and_oracle():
+    """x2c_picture_change_kramers: the nuclear attraction and the Dirac matrix
+    (time-even) through the quaternion products give the complex path's and
+    the oracle's results; a spin-free call is refused."""
+    px, torch = _px()
+    blocks = [atom_block(z) for z in (6, 47, 17, 1)]
+    Ns = np.array([b.S.shape[0] for b in blocks], dtype=np.int32)
+    n = 2 * Ns
+    hsz = n.astype(np.int64) ** 2 * 2
+    p_off = np.concatenate([[0], np.cumsum(hsz)[:-1]]).astype(np.int64)
+    Xs, Rs, Ps, Ss, Ts, Dss, refs_v, refs_d = [], [], [], [], [], [], [], []
+    for b in blocks:
+        _, _, parts = ox.x2c_direct(b.S, b.T, b.V, b.W, C, True, return_parts=True)
+        Sx, Tx, Vx, Wx = ox.spinor_matrices(b.S, b.T, b.V, b.W, True)
+        PLL, PLS, PSL, PSS = ox.property_blocks(b.V, b.W, C, True)
+        Xs.append(parts["X"]); Rs.append(parts["R"]); Ps.append(PLL); Ss.append(PSS); Ts.append(Tx)
+        Dss.append(Wx / (4.0 * C * C) - Tx)
+        refs_v.append(ox.picture_change(PLL, PLS, PSL, PSS, parts["X"], parts["R"]))
+        refs_d.append(ox.picture_change(Vx, Tx, Tx, Wx / (4.0 * C * C) - Tx, parts["X"], parts["R"]))
+    d = lambda mats: _dev(torch, _flat(mats, True))
+    X, R, Td = d(Xs), d(Rs), d(Ts)
+    print("  x2c_picture_change_kramers (nuclear attraction, Dirac matrix)", flush=True)
+    outq, ws = px.picture_change(Ns, True, p_off, d(Ps), d(Ss), X, R, c=C, time_even=True)
+    outc, _ = px.picture_change(Ns, True, p_off, d(Ps), d(Ss), X, R, c=C, workspace=ws)
+    outd, _ = px.picture_change(Ns, True, p_off, d(Ps), d(Dss), X, R, PLS=Td, PSL=Td, c=C, workspace=ws,
+                                time_even=True)
+    torch.cuda.synchronize()
+    gq = px.unpack_h(outq.cpu().numpy(), Ns, True)
+    gc = px.unpack_h(outc.cpu().numpy(), Ns, True)
+    gd = px.unpack_h(outd.cpu().numpy(), Ns, True)
+    for a, b_, r, dq, rd in zip(gq, gc, refs_v, gd, refs_d):
+        assert np.abs(a - r).max() <= 1e-11 * np.abs(r).max()
+        assert np.abs(a - b_).max() <= 1e-12 * np.abs(r).max()
+        assert np.abs(dq - rd).max() <= 1e-10 * np.abs(rd).max()
+    # spin-free blocks have no quaternion form
+    with pytest.raises(px.X2CError):
+        px.picture_change(Ns, False, p_off, d(Ps), d(Ss), X, R, c=C, time_even=True)
