@@ -199,3 +199,58 @@ def test_ag13_full_build_matches_oracle_reference():
     de = np.abs(es - e4[:nb]).max()
     print(f"    bound states {nb}: max dE {de:.2e} Eh", flush=True)
     assert de <= DE_BOUND
+
+
+def _uncoupled(blocks):
+    """Block-diagonal molecular S, T, V, W^q of the given atomic blocks (no
+    inter-atomic coupling)."""
+    Ns = [b.N for b in blocks]
+    Nt = int(sum(Ns))
+    S = np.zeros((Nt, Nt)); T = np.zeros((Nt, Nt)); V = np.zeros((Nt, Nt)); W = np.zeros((4, Nt, Nt))
+    o = 0
+    for b in blocks:
+        sl = slice(o, o + b.N)
+        S[sl, sl] = b.S; T[sl, sl] = b.T; V[sl, sl] = b.V; W[:, sl, sl] = b.W
+        o += b.N
+    return S, T, V, W, Ns
+
+
+@pytest.mark.parametrize("twocomp", [True, False])
+@pytest.mark.timeout(400)
+def test_maximum_size_uncoupled_molecule(twocomp):
+    """N = x2c_max_n (4096 two-component, 8192 spin-free): a block-diagonal
+    molecule of silver blocks and one block of another size.  The full
+    transformation of uncoupled atoms is the direct sum of the atomic ones
+    (Sec. III.A: the DLU approximation is exact then), so every diagonal
+    block must equal the oracle's atomic h and every other entry vanish."""
+    px, _ = _px()
+    from tests.test_gpu_fullsize import _block_of_size
+    Nmax = px.max_n(twocomp)
+    extra = _block_of_size({0: 22, 1: 20, 2: 18, 3: 12}) if twocomp else _block_of_size({0: 24, 1: 12, 2: 8, 3: 4})
+    ag = ag_2c()
+    k = (Nmax - extra.N) // ag.N
+    blocks = [ag] * (k // 2) + [extra] + [ag] * (k - k // 2)
+    S, T, V, W, Ns = _uncoupled(blocks)
+    assert S.shape[0] == Nmax
+    Wm = W if twocomp else W[0]
+    h, eps = gpu_single(S, T, V, Wm, C_LIGHT, twocomp)
+    assert np.all(np.isnan(eps))
+    refs = {}
+    for b in (ag, extra):
+        Wb = b.W if twocomp else b.W[0]
+        refs[id(b)] = ox.x2c_direct(b.S, b.T, b.V, Wb, C_LIGHT, twocomp)[0]
+    hmax = max(np.abs(r).max() for r in refs.values())
+    mask = np.zeros(h.shape, dtype=bool)
+    o = 0
+    worst = 0.0
+    for b in blocks:
+        idx = ox.atom_spinor_index(o, b.N, Nmax, twocomp)
+        r = refs[id(b)]
+        worst = max(worst, np.abs(h[np.ix_(idx, idx)] - r).max() / np.abs(r).max())
+        mask[np.ix_(idx, idx)] = True
+        o += b.N
+    off = np.abs(h[~mask]).max()
+    print(f"    N={Nmax}: diagonal blocks rel err {worst:.2e}; largest off-block entry {off:.2e} "
+          f"(max|h| {hmax:.2e})", flush=True)
+    assert worst <= TOL_H
+    assert off <= 1e-13 * hmax
