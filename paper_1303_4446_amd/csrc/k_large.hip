@@ -548,6 +548,184 @@ __global__ void k_eps_nan(const BlockDesc* D, double* eps) {
     eps[d.eps_off + k] = __longlong_as_double(0x7ff8000000000000ll);
 }
 
+// ---------------------------------------------------------------- whole-matrix quaternion products
+// C = A B (+ beta C) for one large quaternion matrix (the iterations' products:
+// no transposes).  A work-group computes a tile of TR = 16 RB rows x 64
+// columns: wave w owns column block w (16 columns) and all RB row blocks of
+// 16, 16 MFMAs (v_mfma_f64_16x16x4f64) per 16 x 16 block and k step of 4,
+// operands staged in LDS as four component planes, k chunks of 16.  PF: the
+// next chunk's operands are loaded into registers while the current one is
+// multiplied.  Tiles are enumerated (Hermitian products: only those reaching
+// the lower triangle), and consecutive tiles go to one XCD (work-group i runs
+// on XCD i mod 8), so that tiles sharing a row panel share an L2.  The row
+// height is chosen per launch by the wave-quantisation model of
+// launch_gemm_q_big.
+typedef __attribute__((ext_vector_type(4))) double d4;
+constexpr int BG_K = 16, BG_LD = BG_K + 1, BG_TC = 64;
+
+__host__ __device__ inline int big_row_tiles(int n, int TR, int herm, int ct, int ti) {
+  // column tiles of row tile ti
+  if (!herm) return ct;
+  const int last = min(n - 1, TR * ti + TR - 1);
+  return min(ct, last / BG_TC + 1);
+}
+
+template <int RB, int PF>
+__global__ void __launch_bounds__(256, 2) k_gemm_q_big(const BlockDesc* D, char* ws, const int* gate, int dsel,
+                                                       int bufA, int bufB, int bufC, double beta, int herm,
+                                                       int ntiles) {
+  constexpr int TR = 16 * RB;
+  if (gate[0]) return;
+  const BlockDesc& d = D[0];
+  const int n = seldim(d, dsel);
+  const int ct = (n + BG_TC - 1) / BG_TC;
+  // XCD-grouped tile index (the grid is a multiple of 8)
+  const int per = gridDim.x / 8;
+  int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= ntiles) return;
+  int ti = 0;
+  for (;;) {
+    const int c = big_row_tiles(n, TR, herm, ct, ti);
+    if (tile < c) break;
+    tile -= c;
+    ++ti;
+  }
+  const int m0 = ti * TR, n0 = tile * BG_TC;
+  const quat* A = bufp<quat>(ws, d, bufA);
+  const quat* B = bufp<quat>(ws, d, bufB);
+  quat* C = bufp<quat>(ws, d, bufC);
+  __shared__ double As[4][TR][BG_LD];        // [component][row][k]
+  __shared__ double Bs[4][BG_K][BG_TC + 1];  // [component][k][col]
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  d4 acc[RB][4];
+#pragma unroll
+  for (int x = 0; x < RB; ++x)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[x][c] = d4{0.0, 0.0, 0.0, 0.0};
+  quat ra[RB], rb[4];
+  // chunk k0: thread t loads A rows t / 16 + 16 q, k t % 16, and B row t / 64 + 4 q, column t % 64
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int r = m0 + (t >> 4) + 16 * q, k = k0 + (t & 15);
+      ra[q] = (r < n && k < n) ? A[(long long)r * n + k] : tzero<quat>();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + (t >> 6) + 4 * q, c = n0 + (t & 63);
+      rb[q] = (k < n && c < n) ? B[(long long)k * n + c] : tzero<quat>();
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int r = (t >> 4) + 16 * q, k = t & 15;
+      As[0][r][k] = ra[q].a.x;
+      As[1][r][k] = ra[q].a.y;
+      As[2][r][k] = ra[q].b.x;
+      As[3][r][k] = ra[q].b.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = (t >> 6) + 4 * q, c = t & 63;
+      Bs[0][k][c] = rb[q].a.x;
+      Bs[1][k][c] = rb[q].a.y;
+      Bs[2][k][c] = rb[q].b.x;
+      Bs[3][k][c] = rb[q].b.y;
+    }
+  };
+  const int wc = 16 * wave;
+  // (x y)_c = sum_e sigma(c, c xor e) x_e y_(c xor e): the signs sit on the B
+  // operand, whose four components per k step are kept in both signs
+  auto compute = [&]() {
+#pragma unroll 1
+    for (int ks = 0; ks < BG_K; ks += 4) {
+      double a[RB][4], bp[4], bn[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        bp[c] = Bs[c][ks + l4][wc + l16];
+        bn[c] = -bp[c];
+#pragma unroll
+        for (int x = 0; x < RB; ++x) a[x][c] = As[c][16 * x + l16][ks + l4];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int x = 0; x < RB; ++x)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            acc[x][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                a[x][e], qmul_sign(c, c ^ e) > 0 ? bp[c ^ e] : bn[c ^ e], acc[x][c], 0, 0, 0);
+    }
+  };
+  if (PF) {
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int k0 = 0; k0 < n; k0 += BG_K) {
+      const bool more = k0 + BG_K < n;
+      if (more) fetch(k0 + BG_K);
+      compute();
+      __syncthreads();
+      if (more) {
+        stash();
+        __syncthreads();
+      }
+    }
+  } else {
+    for (int k0 = 0; k0 < n; k0 += BG_K) {
+      __syncthreads();
+      fetch(k0);
+      stash();
+      __syncthreads();
+      compute();
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < RB; ++x)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = m0 + 16 * x + l4 + 4 * i, cc = n0 + wc + l16;
+      if (r >= n || cc >= n || (herm && cc > r)) continue;
+      const long long idx = (long long)r * n + cc;
+      quat v = {{acc[x][0][i], acc[x][1][i]}, {acc[x][2][i], acc[x][3][i]}};
+      if (beta != 0.0) v = v + beta * C[idx];
+      C[idx] = v;
+      if (herm && cc < r) C[(long long)cc * n + r] = conjg(v);
+    }
+}
+
+// tiles of a launch for row blocks RB, and the predicted time: rounds of 512
+// resident work-groups (two per CU) times the work of one tile
+static long long big_tiles(int n, int RB, int herm) {
+  const int TR = 16 * RB, rt = (n + TR - 1) / TR, ct = (n + BG_TC - 1) / BG_TC;
+  long long c = 0;
+  for (int i = 0; i < rt; ++i) c += big_row_tiles(n, TR, herm, ct, i);
+  return c;
+}
+
+template <int RB, int PF>
+void launch_gemm_q_big_v(hipStream_t s, const BlockDesc* D, char* ws, const int* gate, int n, int dsel, int bufA,
+                         int bufB, int bufC, double beta, int herm) {
+  const long long t = big_tiles(n, RB, herm);
+  const int g = (int)((t + 7) / 8 * 8);
+  hipLaunchKernelGGL((k_gemm_q_big<RB, PF>), dim3(g), dim3(256), 0, s, D, ws, gate, dsel, bufA, bufB, bufC, beta,
+                     herm, (int)t);
+}
+
+void launch_gemm_q_big(hipStream_t s, const BlockDesc* D, char* ws, const int* gate, int n, int dsel, int bufA,
+                       int bufB, int bufC, double beta, int herm) {
+  // RB = 5 keeps 254 VGPRs without the prefetch registers, RB = 4 fits them:
+  // measured on MI355X (quaternion 4992: Hermitian 29.9 ms RB 5 against 31.0
+  // RB 4; full 56.6 RB 4 against 59.9 RB 5), the model picks the faster in each
+  constexpr long long SLOTS = 512;
+  const long long c4 = (big_tiles(n, 4, herm) + SLOTS - 1) / SLOTS * 4;
+  const long long c5 = (big_tiles(n, 5, herm) + SLOTS - 1) / SLOTS * 5;
+  if (c5 < c4) launch_gemm_q_big_v<5, 0>(s, D, ws, gate, n, dsel, bufA, bufB, bufC, beta, herm);
+  else launch_gemm_q_big_v<4, 1>(s, D, ws, gate, n, dsel, bufA, bufB, bufC, beta, herm);
+}
+
 // ---------------------------------------------------------------- host side
 namespace {
 int* gate_of(const BlockDesc& hd, char* ws) {
@@ -557,7 +735,7 @@ int* gate_of(const BlockDesc& hd, char* ws) {
 template <class T>
 void gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* gate, int dim, int dsel, int A, int B, int C,
           int herm) {
-  if constexpr (is_quat<T>()) launch_gemm_q(s, D, ws, gate, 1, dim, dsel, A, 0, B, 0, C, 1.0, 0.0, herm);
+  if constexpr (is_quat<T>()) launch_gemm_q_big(s, D, ws, gate, dim, dsel, A, B, C, 0.0, herm);
   else launch_gemm<T>(s, D, ws, gate, 1, dim, dsel, A, 0, B, 0, C, treal<T>(1.0), tzero<T>(), herm, 0);
 }
 }  // namespace
