@@ -494,9 +494,10 @@ def full_vs_dlu(px, torch, c, stream, steps, precs, spectra=True):
         # one quaternion multiply-add = 32 real flops; a Hermitian product
         # forms the lower triangle, n^2 (n + 1) / 2 multiply-adds
         herm = lambda n: 32.0 * n * n * (n + 1) / 2
+        # sign: two Hermitian products per step; x_solve: the coupled
+        # iteration on P_LL (three per step) and X~ = (P_SL Z) Z (two general)
         fl = {"sign_4c": steps_ns.get("sign_4c", 0) * 2 * herm(n4),
-              "x_solve": steps_ns.get("x_solve", 0) * 2 * herm(nh) + 32.0 * nh ** 3,
-              "invsqrt_Q": steps_ns.get("invsqrt_Q", 0) * 3 * herm(nh)}
+              "x_solve": steps_ns.get("x_solve", 0) * 3 * herm(nh) + 2 * 32.0 * nh ** 3}
         rates = {k: fl[k] / (st[k] / 1e3) / 1e12 for k in fl if st.get(k)}
         full["fp64"].update({"stages_ms": st, "newton_schulz_steps": steps_ns,
                              "stage_fp64_tflops": {k: round(v, 2) for k, v in rates.items()}})

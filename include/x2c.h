@@ -101,8 +101,7 @@ enum {
                                 or the gap at -c^2 too narrow for the spectral projector (device-wide
                                 path: a Newton-Schulz iteration did not converge) */
   X2C_INFO_BRANCH = 4,       /* number of eigenvalues with eps + c^2 > 0 differs from n */
-  X2C_INFO_RENORM = 5,       /* L_S^-1 S~ L_S^-H not positive definite (device-wide path: its
-                                inverse square root iteration did not converge) */
+  X2C_INFO_RENORM = 5,       /* L_S^-1 S~ L_S^-H not positive definite */
   X2C_INFO_NONFINITE = 6     /* NaN or Inf in S, T, V or W */
 };
 
@@ -115,8 +114,9 @@ enum {
  * run on the device-wide path, one block at a time on the whole GPU: blocked
  * Cholesky factors, the positive-energy branch from the spectral projector
  * (I + sign(A + c^2 I)) / 2 of the reduced 4c matrix A by a scaled
- * Newton-Schulz iteration, X~ and Q^-1/2 by Newton-Schulz inverse and inverse
- * square root iterations; matrix products only.  That path does not compute
+ * Newton-Schulz iteration, X~ and Q^-1/2 together from one coupled
+ * Newton-Schulz iteration on the projector's large-component block; matrix
+ * products only.  That path does not compute
  * eigenvalues: eps of such a block is NaN (h, X and R are as on the batched
  * path).  BSS, DKHn, the DLU assembly and x2c_build_batched_noalloc take
  * batched-path sizes only. */

@@ -19,11 +19,12 @@
 //  * with the column blocks of P on the large-component unit vectors,
 //    X~ = P_SL P_LL^-1: if Y = [Y_L; Y_S] spans the positive branch
 //    (orthonormal), P_LL = Y_L Y_L^H, P_SL = Y_S Y_L^H and P_SL P_LL^-1 =
-//    Y_S Y_L^-1, the X~ of Eq. defxmat in the reduced basis.  P_LL^-1 comes
-//    from the Newton-Schulz inverse iteration Z <- Z (2I - P_LL Z);
-//  * Q^-1/2 for the renormalisation (Eq. ulnonortho) from the coupled
+//    Y_S Y_L^-1, the X~ of Eq. defxmat in the reduced basis;
+//  * and I + X~^H X~ = (Y_L Y_L^H)^-1 = P_LL^-1, so the Q^-1/2 of the
+//    renormalisation (Eq. ulnonortho) is P_LL^(1/2): one coupled
 //    Newton-Schulz iteration Y <- Y U, Z <- U Z, U = (3I - Z Y) / 2 on
-//    Y_0 = Q / alpha (alpha >= the largest eigenvalue, a row-sum bound).
+//    Y_0 = P_LL, Z_0 = I gives both P_LL^(1/2) and P_LL^(-1/2), and
+//    X~ = P_SL P_LL^(-1/2) P_LL^(-1/2).
 //
 // Every iterate is a polynomial in one Hermitian matrix, so every product is
 // Hermitian and runs as a lower-triangle product (half the tiles).  The
@@ -362,7 +363,6 @@ __global__ void k_ns_shift(const BlockDesc* D, char* ws, int dsel, int buf) {
 
 // polynomial factor of one step, in place on U = (product):
 //   kind 0 (sign):         U <- a I - b U   (U = X^2; scaled cubic of l)
-//   kind 1 (inverse):      U <- 2 I - U     (U = P Z)
 //   kind 2 (inverse sqrt): U <- (3 I - U) / 2  (U = Z Y)
 template <class T>
 __global__ void k_ns_poly(const BlockDesc* D, char* ws, int dsel, int buf, int kind) {
@@ -377,9 +377,6 @@ __global__ void k_ns_poly(const BlockDesc* D, char* ws, int dsel, int buf, int k
     ns_cubic(p->l, a, b, ln);
     dg = a;
     sc = -b;
-  } else if (kind == 1) {
-    dg = 2.0;
-    sc = -1.0;
   } else {
     dg = 1.5;
     sc = -0.5;
@@ -506,39 +503,6 @@ __global__ void k_ns_rowmax(const BlockDesc* D, char* ws, int dsel, int buf, dou
   }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if (lane == 0) atomicMax(&p->rmax, (unsigned long long)__double_as_longlong(s));
-}
-
-// Y_0 = Q / alpha with alpha the row-sum bound
-template <class T>
-__global__ void k_ns_isq_start(const BlockDesc* D, char* ws, int dsel, int bufQ, int bufY) {
-  const BlockDesc& d = D[0];
-  NsPar* p = nspar(ws, d);
-  if (p->gate) return;
-  const double alpha = __longlong_as_double((long long)p->rmax);
-  if (!(alpha > 0.0) || !isfinite(alpha)) return;   // the phase end fails the block
-  if (blockIdx.x == 0 && threadIdx.x == 0) p->alpha = alpha;
-  const int n = seldim(d, dsel);
-  const T* Q = bufp<T>(ws, d, bufQ);
-  T* Y = bufp<T>(ws, d, bufY);
-  const double inv = 1.0 / alpha;
-  const long long tot = (long long)n * n;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x)
-    Y[e] = inv * Q[e];
-}
-
-// Q^-1/2 = Z / sqrt(alpha)
-template <class T>
-__global__ void k_ns_isq_finish(const BlockDesc* D, char* ws, const int* info, int dsel, int bufZ, int bufOut) {
-  const BlockDesc& d = D[0];
-  if (info[0]) return;
-  const NsPar* p = nspar(ws, d);
-  const int n = seldim(d, dsel);
-  const T* Z = bufp<T>(ws, d, bufZ);
-  T* O = bufp<T>(ws, d, bufOut);
-  const double sc = 1.0 / sqrt(p->alpha);
-  const long long tot = (long long)n * n;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x)
-    O[e] = sc * Z[e];
 }
 
 // eigenvalues are not produced by this path: NaN marks them
@@ -762,48 +726,33 @@ void launch_large_sign(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, c
   hipLaunchKernelGGL(k_ns_trace<T>, dim3(1), dim3(256), 0, s, D, ws, info, dsel4, bufX);
 }
 
+// X~ and Q^-1/2 from one coupled Newton-Schulz iteration on P_LL: with P an
+// orthogonal projector, I + X~^H X~ = P_LL^-1 for X~ = P_SL P_LL^-1, so
+// Q^-1/2 = P_LL^(1/2).  Y_0 = P_LL (eigenvalues in (0, 1]), Z_0 = I,
+// U = (3I - Z Y) / 2, Y <- Y U, Z <- U Z: Y -> P_LL^(1/2) (into bufQmh),
+// Z -> P_LL^(-1/2); then X~ = (P_SL Z) Z.
 template <class T>
-void launch_large_xtilde(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
-                         int dselh, int dimh, int bufX, int bufPLL, int bufPSL, int bufZ, int bufU, int bufN,
-                         int bufOut, int maxit, double tol) {
+void launch_large_xrenorm(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
+                          int dselh, int dimh, int bufX, int bufPSL, int bufZ, int bufU, int bufN, int bufXt,
+                          int bufQmh, int maxit, double tol) {
   const int* gate = gate_of(hd, ws);
   const long long tot = (long long)dimh * dimh;
-  hipLaunchKernelGGL(k_ns_split<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dsel4, bufX, bufPLL, bufPSL);
+  hipLaunchKernelGGL(k_ns_split<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dsel4, bufX, bufQmh, bufPSL);
   hipLaunchKernelGGL(k_ns_eye<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dselh, bufZ);
   hipLaunchKernelGGL(k_ns_begin, dim3(1), dim3(1), 0, s, D, ws, info);
   for (int it = 0; it < maxit; ++it) {
-    gemm<T>(s, D, ws, gate, dimh, dselh, bufPLL, bufZ, bufU, 1);
-    hipLaunchKernelGGL(k_ns_poly<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufU, 1);
-    gemm<T>(s, D, ws, gate, dimh, dselh, bufZ, bufU, bufN, 1);
-    hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufN, bufZ, 1);
-    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(1), 0, s, D, ws, 1, tol);
-  }
-  hipLaunchKernelGGL(k_ns_end, dim3(1), dim3(1), 0, s, D, ws, info, 3);
-  // X~ = P_SL P_LL^-1 (a general product: the gate is the block status again)
-  gemm<T>(s, D, ws, gate, dimh, dselh, bufPSL, bufZ, bufOut, 0);
-}
-
-template <class T>
-void launch_large_invsqrt(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dselh,
-                          int dimh, int bufQ, int bufY, int bufZ, int bufU, int bufN, int bufOut, int maxit,
-                          double tol) {
-  const int* gate = gate_of(hd, ws);
-  const long long tot = (long long)dimh * dimh;
-  hipLaunchKernelGGL(k_ns_begin, dim3(1), dim3(1), 0, s, D, ws, info);
-  hipLaunchKernelGGL(k_ns_rowmax<T>, dim3((dimh + 3) / 4), dim3(256), 0, s, D, ws, dselh, bufQ, 0.0);
-  hipLaunchKernelGGL(k_ns_isq_start<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufQ, bufY);
-  hipLaunchKernelGGL(k_ns_eye<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dselh, bufZ);
-  for (int it = 0; it < maxit; ++it) {
-    gemm<T>(s, D, ws, gate, dimh, dselh, bufZ, bufY, bufU, 1);
+    gemm<T>(s, D, ws, gate, dimh, dselh, bufZ, bufQmh, bufU, 1);
     hipLaunchKernelGGL(k_ns_poly<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufU, 2);
-    gemm<T>(s, D, ws, gate, dimh, dselh, bufY, bufU, bufN, 1);
-    hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufN, bufY, 0);
+    gemm<T>(s, D, ws, gate, dimh, dselh, bufQmh, bufU, bufN, 1);
+    hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufN, bufQmh, 0);
     gemm<T>(s, D, ws, gate, dimh, dselh, bufU, bufZ, bufN, 1);
     hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufN, bufZ, 1);
     hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(1), 0, s, D, ws, 2, tol);
   }
-  hipLaunchKernelGGL(k_ns_end, dim3(1), dim3(1), 0, s, D, ws, info, 5);
-  hipLaunchKernelGGL(k_ns_isq_finish<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dselh, bufZ, bufOut);
+  hipLaunchKernelGGL(k_ns_end, dim3(1), dim3(1), 0, s, D, ws, info, 3);
+  // X~ = (P_SL Z) Z (general products: the gate is the block status again)
+  gemm<T>(s, D, ws, gate, dimh, dselh, bufPSL, bufZ, bufN, 0);
+  gemm<T>(s, D, ws, gate, dimh, dselh, bufN, bufZ, bufXt, 0);
 }
 
 void launch_eps_nan(hipStream_t s, const BlockDesc* D, double* eps) {
@@ -813,10 +762,8 @@ void launch_eps_nan(hipStream_t s, const BlockDesc* D, double* eps) {
 #define X2C_LARGE_INST(T)                                                                                          \
   template void launch_large_sign<T>(hipStream_t, const BlockDesc*, const BlockDesc&, char*, int*, int, int, int, \
                                      int, int, double, int, double);                                              \
-  template void launch_large_xtilde<T>(hipStream_t, const BlockDesc*, const BlockDesc&, char*, int*, int, int,    \
-                                       int, int, int, int, int, int, int, int, int, double);                      \
-  template void launch_large_invsqrt<T>(hipStream_t, const BlockDesc*, const BlockDesc&, char*, int*, int, int,   \
-                                        int, int, int, int, int, int, int, double);
+  template void launch_large_xrenorm<T>(hipStream_t, const BlockDesc*, const BlockDesc&, char*, int*, int, int,   \
+                                        int, int, int, int, int, int, int, int, int, double);
 X2C_LARGE_INST(double)
 X2C_LARGE_INST(cplx)
 X2C_LARGE_INST(quat)

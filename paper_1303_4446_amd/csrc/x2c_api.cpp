@@ -137,7 +137,7 @@ void block_sizes(int N, bool tc, size_t sz[NBUF], int fw = -1, bool large = fals
                   W_PAN, W_HS, W_VCUR, V_ET, V_DEL})
       sz[i] = 0;
     sz[C_G1] = sz[C_G2] = m * m * es;
-    for (int i = H_A; i <= H_E; ++i) sz[i] = n * n * es;
+    for (int i = H_A; i <= H_D; ++i) sz[i] = n * n * es;
     sz[V_NS] = sizeof(NsPar);
   }
 }
@@ -825,13 +825,15 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
     // X~ = Y_S Y_L^-1 ;  X = sqrt2 c L_T^-H X~ L_S^H
     STAGE("x_solve");
     if (large) {
-      // X~ = P_SL P_LL^-1 from the projector's large-component columns
+      // X~ = P_SL P_LL^-1 from the projector's large-component columns, and
+      // with it Q^-1/2 = P_LL^(1/2) (quaternion into C_LR, else into C_QMH,
+      // where the renormalisation below expects it)
       if (kramers) {
-        launch_large_xtilde<quat>(s, D, hd, ws, info, DIM_n, DIM_N, hd.N, C_A, H_A, H_B, H_C, H_D, H_E, C_QMH,
-                                  NS_AUX_IT, NS_TOL);
+        launch_large_xrenorm<quat>(s, D, hd, ws, info, DIM_n, DIM_N, hd.N, C_A, H_A, H_B, H_C, H_D, C_QMH, C_LR,
+                                   NS_AUX_IT, NS_TOL);
       } else {
-        launch_large_xtilde<T>(s, D, hd, ws, info, DIM_m, DIM_n, hd.n, C_A, H_A, H_B, H_C, H_D, H_E, C_TMP,
-                               NS_AUX_IT, NS_TOL);
+        launch_large_xrenorm<T>(s, D, hd, ws, info, DIM_m, DIM_n, hd.n, C_A, H_A, H_B, H_C, H_D, C_TMP, C_QMH,
+                                NS_AUX_IT, NS_TOL);
       }
       trace_iterations("x_solve_steps", s, hd, ws);
     } else if (L.fw == 0) {
@@ -875,7 +877,7 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
     add_herm(C_TX, C_L);
     G(C_X, OPH, C_WX, OPN, C_L, 1.0, 1.0, 1);
   }
-  {
+  if (!large) {
     // Q = L_S^-1 S~ L_S^-H.  With X = sqrt2 c L_T^-H X~ L_S^H this is
     // I + X~^H X~ exactly (L_S^-1 S L_S^-H = I, and the T in X^H T X / 2c^2
     // cancels against L_T^-1 L_T^-H), which the quaternion chain uses: one
@@ -890,15 +892,7 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
     }
   }
   if (large) {
-    // Q^-1/2 by the coupled Newton-Schulz iteration (quaternion Q into C_LR,
-    // else into C_QMH, where the reductions below leave it)
-    STAGE("invsqrt_Q");
-    if (kramers) {
-      launch_large_invsqrt<quat>(s, D, hd, ws, info, DIM_N, hd.N, C_Q, H_A, H_B, H_C, H_D, C_LR, NS_AUX_IT, NS_TOL);
-    } else {
-      launch_large_invsqrt<T>(s, D, hd, ws, info, DIM_n, hd.n, C_Q, H_A, H_B, H_C, H_D, C_QMH, NS_AUX_IT, NS_TOL);
-    }
-    trace_iterations("invsqrt_Q_steps", s, hd, ws);
+    // Q^-1/2 came with X~
   } else if (!kramers) {
     {
       STAGE("tridiag_Q");

@@ -173,9 +173,9 @@ enum Buf : int {
   // real spin-free): E_1, O_1, E_1', work, product, X'', h in the kinetic basis
   Q_E1, Q_O1, Q_E1P, Q_M, Q_P, Q_X2, Q_H,
   // device-wide path of a large block: two more 4c-sized matrices for the
-  // sign iteration, five h-sized ones for the inverse and inverse square
-  // root iterations, and the iteration parameters (NsPar)
-  C_G1, C_G2, H_A, H_B, H_C, H_D, H_E, V_NS,
+  // sign iteration, four h-sized ones for the iteration on P_LL (P_SL, the
+  // inverse square root, two products), and the iteration parameters (NsPar)
+  C_G1, C_G2, H_A, H_B, H_C, H_D, V_NS,
   // DKHn term and scratch slots (see x2c_dkh_plan.h)
   D_T0,
   NBUF = D_T0 + 48
@@ -194,9 +194,8 @@ constexpr int PQ_SIZE = 3 + 2 * QMAX;
 // non-zero once the current iteration has converged or the block has
 // failed; the product kernels take it in place of the block status.
 struct NsPar {
-  double sigma, rho, l;        // shift, Frobenius scale, lower bound of the moduli
+  double sigma, rho, l;        // shift, scale, lower bound of the moduli
   double acc, acc2;            // sums of squares of the step change and of the new iterate
-  double alpha, tr;            // inverse square root scale; spare
   unsigned long long rmax;     // largest row sum (bits of a non-negative double)
   int gate, conv, iters, pad;
 };

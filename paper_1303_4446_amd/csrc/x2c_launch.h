@@ -150,16 +150,12 @@ void launch_large_cholesky(hipStream_t s, const BlockDesc* D, char* ws, int* inf
 template <class T>
 void launch_large_sign(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
                        int dim4, int bufX, int bufU, int bufN, double c, int maxit, double tol);
-// X~ = P_SL P_LL^-1 from the converged sign in bufX into bufOut (h-sized)
+// X~ = P_SL P_LL^-1 into bufXt and Q^-1/2 = P_LL^(1/2) into bufQmh from one
+// coupled iteration on P_LL (the converged sign in bufX)
 template <class T>
-void launch_large_xtilde(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
-                         int dselh, int dimh, int bufX, int bufPLL, int bufPSL, int bufZ, int bufU, int bufN,
-                         int bufOut, int maxit, double tol);
-// Q^-1/2 of the Hermitian positive definite bufQ into bufOut
-template <class T>
-void launch_large_invsqrt(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dselh,
-                          int dimh, int bufQ, int bufY, int bufZ, int bufU, int bufN, int bufOut, int maxit,
-                          double tol);
+void launch_large_xrenorm(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
+                          int dselh, int dimh, int bufX, int bufPSL, int bufZ, int bufU, int bufN, int bufXt,
+                          int bufQmh, int maxit, double tol);
 void launch_eps_nan(hipStream_t s, const BlockDesc* D, double* eps);
 
 }  // namespace x2c
