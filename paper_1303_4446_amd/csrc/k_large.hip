@@ -254,7 +254,7 @@ __global__ void k_lzero_upper(const BlockDesc* D, char* ws, const int* info) {
 
 static int egrid(long long tot) {
   long long g = (tot + 255) / 256;
-  if (g > 4096) g = 4096;
+  if (g > NS_PARTS) g = NS_PARTS;
   if (g < 1) g = 1;
   return (int)g;
 }
@@ -294,9 +294,14 @@ __global__ void k_ns_begin(const BlockDesc* D, char* ws, const int* info) {
   p->gate = info[0];
   p->conv = 0;
   p->iters = 0;
-  p->acc = 0.0;
-  p->acc2 = 0.0;
   p->rmax = 0ull;
+}
+
+// sum of the partials part[w][0 .. np) in a fixed order (one work-group)
+__device__ inline double ns_sum(const NsPar* p, int w, int np, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += p->part[w][i];
+  return block_sum(s, sh);
 }
 
 // end of a phase: an iteration that did not converge fails the block
@@ -306,7 +311,7 @@ __global__ void k_ns_end(const BlockDesc* D, char* ws, int* info, int code) {
   p->gate = info[0];
 }
 
-// ||A - sigma I||_F^2 into acc
+// ||A - sigma I||_F^2: one partial per work-group
 template <class T>
 __global__ void k_ns_fro(const BlockDesc* D, char* ws, int dsel, int buf, double sigma) {
   const BlockDesc& d = D[0];
@@ -323,17 +328,20 @@ __global__ void k_ns_fro(const BlockDesc* D, char* ws, int dsel, int buf, double
     s += abs2(v);
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) atomicAdd(&p->acc, s);
+  if (threadIdx.x == 0) p->part[0][blockIdx.x] = s;
 }
 
 // rho = min(||A - sigma I||_F, largest row sum of |A - sigma I|) (both bound
 // the spectral radius from above), X_0 = (A - sigma I) / rho in place, and
 // the first lower bound l_0 = gap / rho from the expected half-width of the
 // gap
-__global__ void k_ns_start(const BlockDesc* D, char* ws, double sigma, double gap) {
+__global__ void k_ns_start(const BlockDesc* D, char* ws, double sigma, double gap, int np) {
   NsPar* p = nspar(ws, D[0]);
   if (p->gate) return;
-  double rho = fmin(sqrt(p->acc), __longlong_as_double((long long)p->rmax));
+  __shared__ double sh[16];
+  const double f2 = ns_sum(p, 0, np, sh);
+  if (threadIdx.x != 0) return;
+  double rho = fmin(sqrt(f2), __longlong_as_double((long long)p->rmax));
   if (!(rho > 0.0) || !isfinite(rho)) {
     p->gate = 1;   // no convergence: the phase end fails the block
     return;
@@ -341,7 +349,6 @@ __global__ void k_ns_start(const BlockDesc* D, char* ws, double sigma, double ga
   p->sigma = sigma;
   p->rho = rho;
   p->l = fmin(fmax(gap / rho, 1e-14), 0.99);
-  p->acc = 0.0;
   p->rmax = 0ull;
 }
 
@@ -389,7 +396,8 @@ __global__ void k_ns_poly(const BlockDesc* D, char* ws, int dsel, int buf, int k
   }
 }
 
-// dst <- src; with diff, acc += ||src - dst||_F^2 and acc2 += ||src||_F^2
+// dst <- src; with diff, the work-group's partials of ||src - dst||_F^2 and
+// ||src||_F^2
 template <class T>
 __global__ void k_ns_accept(const BlockDesc* D, char* ws, int dsel, int src, int dst, int diff) {
   const BlockDesc& d = D[0];
@@ -413,20 +421,21 @@ __global__ void k_ns_accept(const BlockDesc* D, char* ws, int dsel, int src, int
   s1 = block_sum(s1, sh);
   s2 = block_sum(s2, sh);
   if (threadIdx.x == 0) {
-    atomicAdd(&p->acc, s1);
-    atomicAdd(&p->acc2, s2);
+    p->part[0][blockIdx.x] = s1;
+    p->part[1][blockIdx.x] = s2;
   }
 }
 
 // end of a step: relative change d = ||X_new - X||_F / ||X_new||_F; the
 // iteration has converged once d <= tol (the next error is O(d^2))
-__global__ void k_ns_check(const BlockDesc* D, char* ws, int kind, double tol) {
+__global__ void k_ns_check(const BlockDesc* D, char* ws, int kind, double tol, int np) {
   NsPar* p = nspar(ws, D[0]);
   if (p->gate) return;
+  __shared__ double sh[16];
+  const double s1 = ns_sum(p, 0, np, sh), s2 = ns_sum(p, 1, np, sh);
+  if (threadIdx.x != 0) return;
   p->iters += 1;
-  const double dd = sqrt(p->acc / fmax(p->acc2, 1e-300));
-  p->acc = 0.0;
-  p->acc2 = 0.0;
+  const double dd = sqrt(s1 / fmax(s2, 1e-300));
   if (kind == 0) {
     double a, b, ln;
     ns_cubic(p->l, a, b, ln);
@@ -713,14 +722,14 @@ void launch_large_sign(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, c
   hipLaunchKernelGGL(k_ns_begin, dim3(1), dim3(1), 0, s, D, ws, info);
   hipLaunchKernelGGL(k_ns_fro<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufX, sigma);
   hipLaunchKernelGGL(k_ns_rowmax<T>, dim3((dim4 + 3) / 4), dim3(256), 0, s, D, ws, dsel4, bufX, sigma);
-  hipLaunchKernelGGL(k_ns_start, dim3(1), dim3(1), 0, s, D, ws, sigma, 0.5 * c * c);
+  hipLaunchKernelGGL(k_ns_start, dim3(1), dim3(256), 0, s, D, ws, sigma, 0.5 * c * c, egrid(tot));
   hipLaunchKernelGGL(k_ns_shift<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufX);
   for (int it = 0; it < maxit; ++it) {
     gemm<T>(s, D, ws, gate, dim4, dsel4, bufX, bufX, bufU, 1);
     hipLaunchKernelGGL(k_ns_poly<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufU, 0);
     gemm<T>(s, D, ws, gate, dim4, dsel4, bufX, bufU, bufN, 1);
     hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufN, bufX, 1);
-    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(1), 0, s, D, ws, 0, tol);
+    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(256), 0, s, D, ws, 0, tol, egrid(tot));
   }
   hipLaunchKernelGGL(k_ns_end, dim3(1), dim3(1), 0, s, D, ws, info, 3);
   hipLaunchKernelGGL(k_ns_trace<T>, dim3(1), dim3(256), 0, s, D, ws, info, dsel4, bufX);
@@ -747,7 +756,7 @@ void launch_large_xrenorm(hipStream_t s, const BlockDesc* D, const BlockDesc& hd
     hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufN, bufQmh, 0);
     gemm<T>(s, D, ws, gate, dimh, dselh, bufU, bufZ, bufN, 1);
     hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufN, bufZ, 1);
-    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(1), 0, s, D, ws, 2, tol);
+    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(256), 0, s, D, ws, 2, tol, egrid(tot));
   }
   hipLaunchKernelGGL(k_ns_end, dim3(1), dim3(1), 0, s, D, ws, info, 3);
   // X~ = (P_SL Z) Z (general products: the gate is the block status again)

@@ -193,11 +193,15 @@ constexpr int PQ_SIZE = 3 + 2 * QMAX;
 // device-wide path (one per large block, in its V_NS buffer).  `gate` is
 // non-zero once the current iteration has converged or the block has
 // failed; the product kernels take it in place of the block status.
+constexpr int NS_PARTS = 4096;   // work-groups of an elementwise pass, at most
 struct NsPar {
   double sigma, rho, l;        // shift, scale, lower bound of the moduli
-  double acc, acc2;            // sums of squares of the step change and of the new iterate
   unsigned long long rmax;     // largest row sum (bits of a non-negative double)
   int gate, conv, iters, pad;
+  // per-work-group partial sums of the last reduction (squares of the step
+  // change, of the new iterate), summed in a fixed order: the iteration is
+  // reproducible bit for bit
+  double part[2][NS_PARTS];
 };
 
 struct BlockDesc {

@@ -254,3 +254,71 @@ def test_maximum_size_uncoupled_molecule(twocomp):
           f"(max|h| {hmax:.2e})", flush=True)
     assert worst <= TOL_H
     assert off <= 1e-13 * hmax
+
+
+def test_device_wide_reproducible_and_graph_replays_match_eager():
+    """The device-wide path sums its convergence measures in a fixed order:
+    two eager calls and two graph replays (same buffers, unrelated eager
+    work in between) give the same bits."""
+    px, torch = _px()
+    blocks = [atom_block(47)]
+    with device_wide_from(True, 1):
+        bt = px.batch_to_device(pack_blocks(blocks, True), True)
+        h_off, eps_off, hsz, esz = bt.out_layout()
+        out = (torch.empty(hsz, dtype=torch.float64, device="cuda"),
+               torch.empty(esz, dtype=torch.float64, device="cuda"),
+               torch.empty(1, dtype=torch.int32, device="cuda"))
+        ws = None
+        got = []
+        prev = px.graph_enable(False)
+        try:
+            for graph in (False, False, True, True):
+                px.graph_enable(graph)
+                junk = torch.randn(1 << 20, device="cuda").sum()
+                print(f"  device-wide build, graph={graph}", flush=True)
+                (h, eps, info), ws = px.build_batched(bt, C_LIGHT, workspace=ws, out=out)
+                torch.cuda.synchronize()
+                assert float(junk) == float(junk)
+                assert int(info.cpu()[0]) == 0
+                got.append(h.cpu().numpy().copy())
+        finally:
+            px.graph_enable(prev)
+    for g in got[1:]:
+        assert np.array_equal(g, got[0])
+
+
+def test_device_wide_x_r_outputs_and_picture_change():
+    """x2c_build_batched_xr on a block above the batched limit (three coupled
+    silver atoms, N = 576): X and R against the oracle's (2e-9, the X and R
+    tolerance of the batched path), and the picture change of the nuclear
+    attraction with the GPU's X and R, complex and quaternion products,
+    against the oracle's formula with its own X and R."""
+    px, torch = _px()
+    mol = coupled_molecule([ag_2c() for _ in range(3)], 2)
+    from x2c_inputs import pack_blocks as pk_
+    from x2c_inputs.configs import AtomBlock
+    blk = AtomBlock(47, mol.S, mol.T, mol.V, mol.W)
+    bt = px.batch_to_device(pk_([blk], True), True)
+    print(f"  x2c_build_batched_xr N={mol.Ntot}", flush=True)
+    (h, eps, info, X, R), ws = px.build_batched_xr(bt, C_LIGHT)
+    torch.cuda.synchronize()
+    assert int(info.cpu()[0]) == 0
+    Xg = px.unpack_h(X.cpu().numpy(), bt.Ns, True)[0]
+    Rg = px.unpack_h(R.cpu().numpy(), bt.Ns, True)[0]
+    _, _, parts = ox.x2c_direct(mol.S, mol.T, mol.V, mol.W, C_LIGHT, True, return_parts=True)
+    ex = np.abs(Xg - parts["X"]).max() / np.abs(parts["X"]).max()
+    er = np.abs(Rg - parts["R"]).max() / np.abs(parts["R"]).max()
+    print(f"    X rel err {ex:.2e}, R rel err {er:.2e}", flush=True)
+    assert ex <= 2e-9 and er <= 2e-9
+    PLL, PLS, PSL, PSS = ox.property_blocks(mol.V, mol.W, C_LIGHT, True)
+    ref = ox.picture_change(PLL, PLS, PSL, PSS, parts["X"], parts["R"])
+    h_off = bt.out_layout()[0]
+    flat = lambda M: torch.from_numpy(np.ascontiguousarray(M, dtype=np.complex128).view(np.float64).ravel()).cuda()
+    for even in (False, True):
+        print(f"  picture change time_even={even}", flush=True)
+        out, _ = px.picture_change(bt.Ns, True, h_off, flat(PLL), flat(PSS), X, R, c=C_LIGHT, time_even=even)
+        torch.cuda.synchronize()
+        got = px.unpack_h(out.cpu().numpy(), bt.Ns, True)[0]
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"    picture change rel err {err:.2e}", flush=True)
+        assert err <= 1e-9
