@@ -322,3 +322,54 @@ def test_device_wide_x_r_outputs_and_picture_change():
         err = np.abs(got - ref).max() / np.abs(ref).max()
         print(f"    picture change rel err {err:.2e}", flush=True)
         assert err <= 1e-9
+
+
+def test_device_wide_failure_codes_in_one_batch():
+    """Blocks forced onto the device-wide path fail as on the batched path:
+    S or T not positive definite (1, 2), non-finite input (6), a singular S
+    (duplicated function, 1); their h and eps are zero, the good blocks are
+    unaffected.  c = 1 with Z = 79 leaves no gap at -c^2: the sign iteration
+    cannot converge or splits the spectrum unevenly (3 or 4)."""
+    px, torch = _px()
+    from x2c_inputs.integrals import AtomBlock
+    good = atom_block(8)
+
+    def mod(**kw):
+        d = dict(Z=good.Z, S=good.S.copy(), T=good.T.copy(), V=good.V.copy(), W=good.W.copy())
+        d.update(kw)
+        return AtomBlock(**d)
+
+    sbad = good.S.copy(); sbad[3, 3] = -1.0
+    tbad = good.T.copy(); tbad[2, 2] = -5.0
+    vnan = good.V.copy(); vnan[1, 4] = np.nan; vnan[4, 1] = np.nan
+    dup = neon_s20()
+    Sd, Td, Vd, Wd = dup.S.copy(), dup.T.copy(), dup.V.copy(), dup.W.copy()
+    for M in (Sd, Td, Vd, Wd[0]):
+        M[1, :] = M[0, :]; M[:, 1] = M[:, 0]
+    blocks = [good, mod(S=sbad), mod(T=tbad), mod(V=vnan), AtomBlock(Z=10.0, S=Sd, T=Td, V=Vd, W=Wd), good]
+    for twocomp in (False, True):
+        with device_wide_from(twocomp, 1):
+            bt = px.batch_to_device(pack_blocks(blocks, twocomp), twocomp)
+            print(f"  device-wide failure batch twocomp={twocomp}", flush=True)
+            (h, eps, info), _ = px.build_batched(bt, C_LIGHT)
+            torch.cuda.synchronize()
+        info = list(info.cpu().numpy())
+        assert info == [0, 1, 2, 6, 1, 0], info
+        hs = px.unpack_h(h.cpu().numpy(), bt.Ns, twocomp)
+        e = eps.cpu().numpy()
+        offs = np.concatenate([[0], np.cumsum(bt.Ns * (2 if twocomp else 1))])
+        for i in (1, 2, 3, 4):
+            assert not np.any(hs[i]) and not np.any(e[offs[i]:offs[i + 1]])
+        W = good.W if twocomp else good.W[0]
+        h0 = ox.x2c_direct(good.S, good.T, good.V, W, C_LIGHT, twocomp)[0]
+        for i in (0, 5):
+            assert np.abs(hs[i] - h0).max() <= TOL_H * np.abs(h0).max()
+    blk = atom_block(79)
+    with device_wide_from(False, 1):
+        bt = px.batch_to_device(pack_blocks([blk, atom_block(1)], False), False)
+        print("  device-wide branch failure (Z = 79, c = 1)", flush=True)
+        (h, eps, info), _ = px.build_batched(bt, 1.0)
+        torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    assert info[0] in (3, 4), info
+    assert not np.any(px.unpack_h(h.cpu().numpy(), bt.Ns, False)[0])
