@@ -47,8 +47,9 @@ constexpr int LT = 64;   // tile edge
 // inverse into the diagonal tile of L_S^-1 / L_T^-1.  Rows and columns past
 // N are treated as the identity.
 __global__ void __launch_bounds__(256) k_lchol_diag(const BlockDesc* D, char* ws, int* info, int k0) {
-  const BlockDesc& d = D[0];
-  if (info[0]) return;
+  const int b = blockIdx.z;
+  const BlockDesc& d = D[b];
+  if (info[b] || k0 >= d.N) return;
   const int which = blockIdx.x, N = d.N;
   double* A = bufp<double>(ws, d, which ? R_LT : R_LS);
   double* X = bufp<double>(ws, d, which ? R_LTI : R_LSI);
@@ -88,8 +89,8 @@ __global__ void __launch_bounds__(256) k_lchol_diag(const BlockDesc* D, char* ws
   if (fail) {
     // S failing takes precedence over T failing
     if (t == 0) {
-      if (which == 0) atomicExch(&info[0], 1);
-      else atomicCAS(&info[0], 0, 2);
+      if (which == 0) atomicExch(&info[b], 1);
+      else atomicCAS(&info[b], 0, 2);
     }
     return;
   }
@@ -135,8 +136,8 @@ __device__ inline void tile_nt(const double (*p)[LT + 1], const double (*qt)[LT 
 // Panel below the diagonal tile: L_ik = A_ik L_kk^-T, one tile per
 // work-group (grid: row tiles below k0, matrix).
 __global__ void __launch_bounds__(256) k_lchol_panel(const BlockDesc* D, char* ws, const int* info, int k0) {
-  const BlockDesc& d = D[0];
-  if (info[0]) return;
+  const BlockDesc& d = D[blockIdx.z];
+  if (info[blockIdx.z]) return;
   const int N = d.N, which = blockIdx.y;
   const int i0 = k0 + LT * (1 + blockIdx.x);
   if (i0 >= N) return;
@@ -165,8 +166,8 @@ __global__ void __launch_bounds__(256) k_lchol_panel(const BlockDesc* D, char* w
 // Trailing update A_ij -= L_ik L_jk^T for the tiles j <= i below the panel
 // (grid: lower tile pairs, matrix).
 __global__ void __launch_bounds__(256) k_lchol_update(const BlockDesc* D, char* ws, const int* info, int k0) {
-  const BlockDesc& d = D[0];
-  if (info[0]) return;
+  const BlockDesc& d = D[blockIdx.z];
+  if (info[blockIdx.z]) return;
   const int N = d.N, which = blockIdx.y;
   const int p = blockIdx.x;
   int ti = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
@@ -199,8 +200,8 @@ __global__ void __launch_bounds__(256) k_lchol_update(const BlockDesc* D, char* 
 // Tile row ti of the inverse X = L^-1 (tiles j < ti; the diagonal tiles come
 // from k_lchol_diag):  X_ij = -X_ii sum_{j <= k < i} L_ik X_kj.
 __global__ void __launch_bounds__(256) k_ltri_row(const BlockDesc* D, char* ws, const int* info, int ti) {
-  const BlockDesc& d = D[0];
-  if (info[0]) return;
+  const BlockDesc& d = D[blockIdx.z];
+  if (info[blockIdx.z] || ti * LT >= d.N) return;
   const int N = d.N, which = blockIdx.y, tj = blockIdx.x;
   const double* L = bufp<double>(ws, d, which ? R_LT : R_LS);
   double* X = bufp<double>(ws, d, which ? R_LTI : R_LSI);
@@ -242,8 +243,8 @@ __global__ void __launch_bounds__(256) k_ltri_row(const BlockDesc* D, char* ws, 
 
 // zero the strict upper triangles of L_S, L_T, L_S^-1, L_T^-1 (blockIdx.y)
 __global__ void k_lzero_upper(const BlockDesc* D, char* ws, const int* info) {
-  const BlockDesc& d = D[0];
-  if (info[0]) return;
+  const BlockDesc& d = D[blockIdx.z];
+  if (info[blockIdx.z]) return;
   const int ids[4] = {R_LS, R_LT, R_LSI, R_LTI};
   double* A = bufp<double>(ws, d, ids[blockIdx.y]);
   const int N = d.N;
@@ -259,17 +260,19 @@ static int egrid(long long tot) {
   return (int)g;
 }
 
-void launch_large_cholesky(hipStream_t s, const BlockDesc* D, char* ws, int* info, int N) {
-  const int nt = (N + LT - 1) / LT;
+// blocks of different N in one launch sequence: the grids cover the largest,
+// tiles past a block's own N exit
+void launch_large_cholesky(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN) {
+  const int nt = (maxN + LT - 1) / LT;
   for (int k = 0; k < nt; ++k) {
     const int k0 = k * LT, r = nt - k - 1;
-    hipLaunchKernelGGL(k_lchol_diag, dim3(2), dim3(256), 0, s, D, ws, info, k0);
+    hipLaunchKernelGGL(k_lchol_diag, dim3(2, 1, nblk), dim3(256), 0, s, D, ws, info, k0);
     if (r == 0) break;
-    hipLaunchKernelGGL(k_lchol_panel, dim3(r, 2), dim3(256), 0, s, D, ws, info, k0);
-    hipLaunchKernelGGL(k_lchol_update, dim3(r * (r + 1) / 2, 2), dim3(256), 0, s, D, ws, info, k0);
+    hipLaunchKernelGGL(k_lchol_panel, dim3(r, 2, nblk), dim3(256), 0, s, D, ws, info, k0);
+    hipLaunchKernelGGL(k_lchol_update, dim3(r * (r + 1) / 2, 2, nblk), dim3(256), 0, s, D, ws, info, k0);
   }
-  for (int i = 1; i < nt; ++i) hipLaunchKernelGGL(k_ltri_row, dim3(i, 2), dim3(256), 0, s, D, ws, info, i);
-  hipLaunchKernelGGL(k_lzero_upper, dim3(egrid((long long)N * N), 4), dim3(256), 0, s, D, ws, info);
+  for (int i = 1; i < nt; ++i) hipLaunchKernelGGL(k_ltri_row, dim3(i, 2, nblk), dim3(256), 0, s, D, ws, info, i);
+  hipLaunchKernelGGL(k_lzero_upper, dim3(egrid((long long)maxN * maxN), 4, nblk), dim3(256), 0, s, D, ws, info);
 }
 
 // ---------------------------------------------------------------- Newton-Schulz iterations
@@ -288,10 +291,16 @@ __device__ inline void ns_cubic(double l, double& a, double& b, double& lnext) {
 
 __device__ inline NsPar* nspar(char* ws, const BlockDesc& d) { return bufp<NsPar>(ws, d, V_NS); }
 
+// Kernels of the iterations run over the blocks of a launch: one-work-group
+// kernels take the block from blockIdx.x, elementwise passes from
+// blockIdx.y.  gate[b] is non-zero once block b's iteration has converged or
+// the block has failed.
+
 // start of an iteration phase: the gate follows the block status
-__global__ void k_ns_begin(const BlockDesc* D, char* ws, const int* info) {
-  NsPar* p = nspar(ws, D[0]);
-  p->gate = info[0];
+__global__ void k_ns_begin(const BlockDesc* D, char* ws, const int* info, int* gate) {
+  const int b = blockIdx.x;
+  NsPar* p = nspar(ws, D[b]);
+  gate[b] = info[b];
   p->conv = 0;
   p->iters = 0;
   p->rmax = 0ull;
@@ -305,18 +314,20 @@ __device__ inline double ns_sum(const NsPar* p, int w, int np, double* sh) {
 }
 
 // end of a phase: an iteration that did not converge fails the block
-__global__ void k_ns_end(const BlockDesc* D, char* ws, int* info, int code) {
-  NsPar* p = nspar(ws, D[0]);
-  if (info[0] == 0 && !p->conv) info[0] = code;
-  p->gate = info[0];
+__global__ void k_ns_end(const BlockDesc* D, char* ws, int* info, int* gate, int code) {
+  const int b = blockIdx.x;
+  const NsPar* p = nspar(ws, D[b]);
+  if (info[b] == 0 && !p->conv) info[b] = code;
+  gate[b] = info[b];
 }
 
 // ||A - sigma I||_F^2: one partial per work-group
 template <class T>
-__global__ void k_ns_fro(const BlockDesc* D, char* ws, int dsel, int buf, double sigma) {
-  const BlockDesc& d = D[0];
+__global__ void k_ns_fro(const BlockDesc* D, char* ws, const int* gate, int dsel, int buf, double sigma) {
+  const int b = blockIdx.y;
+  if (gate[b]) return;
+  const BlockDesc& d = D[b];
   NsPar* p = nspar(ws, d);
-  if (p->gate) return;
   __shared__ double sh[16];
   const int n = seldim(d, dsel);
   const T* A = bufp<T>(ws, d, buf);
@@ -335,15 +346,16 @@ __global__ void k_ns_fro(const BlockDesc* D, char* ws, int dsel, int buf, double
 // the spectral radius from above), X_0 = (A - sigma I) / rho in place, and
 // the first lower bound l_0 = gap / rho from the expected half-width of the
 // gap
-__global__ void k_ns_start(const BlockDesc* D, char* ws, double sigma, double gap, int np) {
-  NsPar* p = nspar(ws, D[0]);
-  if (p->gate) return;
+__global__ void k_ns_start(const BlockDesc* D, char* ws, int* gate, double sigma, double gap, int np) {
+  const int b = blockIdx.x;
+  if (gate[b]) return;
+  NsPar* p = nspar(ws, D[b]);
   __shared__ double sh[16];
   const double f2 = ns_sum(p, 0, np, sh);
   if (threadIdx.x != 0) return;
   double rho = fmin(sqrt(f2), __longlong_as_double((long long)p->rmax));
   if (!(rho > 0.0) || !isfinite(rho)) {
-    p->gate = 1;   // no convergence: the phase end fails the block
+    gate[b] = 1;   // no convergence: the phase end fails the block
     return;
   }
   p->sigma = sigma;
@@ -353,10 +365,11 @@ __global__ void k_ns_start(const BlockDesc* D, char* ws, double sigma, double ga
 }
 
 template <class T>
-__global__ void k_ns_shift(const BlockDesc* D, char* ws, int dsel, int buf) {
-  const BlockDesc& d = D[0];
+__global__ void k_ns_shift(const BlockDesc* D, char* ws, const int* gate, int dsel, int buf) {
+  const int b = blockIdx.y;
+  if (gate[b]) return;
+  const BlockDesc& d = D[b];
   const NsPar* p = nspar(ws, d);
-  if (p->gate) return;
   const int n = seldim(d, dsel);
   T* A = bufp<T>(ws, d, buf);
   const double inv = 1.0 / p->rho, sigma = p->sigma;
@@ -372,18 +385,19 @@ __global__ void k_ns_shift(const BlockDesc* D, char* ws, int dsel, int buf) {
 //   kind 0 (sign):         U <- a I - b U   (U = X^2; scaled cubic of l)
 //   kind 2 (inverse sqrt): U <- (3 I - U) / 2  (U = Z Y)
 template <class T>
-__global__ void k_ns_poly(const BlockDesc* D, char* ws, int dsel, int buf, int kind) {
-  const BlockDesc& d = D[0];
+__global__ void k_ns_poly(const BlockDesc* D, char* ws, const int* gate, int dsel, int buf, int kind) {
+  const int b = blockIdx.y;
+  if (gate[b]) return;
+  const BlockDesc& d = D[b];
   const NsPar* p = nspar(ws, d);
-  if (p->gate) return;
   const int n = seldim(d, dsel);
   T* U = bufp<T>(ws, d, buf);
   double dg, sc;
   if (kind == 0) {
-    double a, b, ln;
-    ns_cubic(p->l, a, b, ln);
+    double a, bc, ln;
+    ns_cubic(p->l, a, bc, ln);
     dg = a;
-    sc = -b;
+    sc = -bc;
   } else {
     dg = 1.5;
     sc = -0.5;
@@ -399,10 +413,11 @@ __global__ void k_ns_poly(const BlockDesc* D, char* ws, int dsel, int buf, int k
 // dst <- src; with diff, the work-group's partials of ||src - dst||_F^2 and
 // ||src||_F^2
 template <class T>
-__global__ void k_ns_accept(const BlockDesc* D, char* ws, int dsel, int src, int dst, int diff) {
-  const BlockDesc& d = D[0];
+__global__ void k_ns_accept(const BlockDesc* D, char* ws, const int* gate, int dsel, int src, int dst, int diff) {
+  const int b = blockIdx.y;
+  if (gate[b]) return;
+  const BlockDesc& d = D[b];
   NsPar* p = nspar(ws, d);
-  if (p->gate) return;
   __shared__ double sh[16];
   const int n = seldim(d, dsel);
   const T* S = bufp<T>(ws, d, src);
@@ -428,22 +443,23 @@ __global__ void k_ns_accept(const BlockDesc* D, char* ws, int dsel, int src, int
 
 // end of a step: relative change d = ||X_new - X||_F / ||X_new||_F; the
 // iteration has converged once d <= tol (the next error is O(d^2))
-__global__ void k_ns_check(const BlockDesc* D, char* ws, int kind, double tol, int np) {
-  NsPar* p = nspar(ws, D[0]);
-  if (p->gate) return;
+__global__ void k_ns_check(const BlockDesc* D, char* ws, int* gate, int kind, double tol, int np) {
+  const int b = blockIdx.x;
+  if (gate[b]) return;
+  NsPar* p = nspar(ws, D[b]);
   __shared__ double sh[16];
   const double s1 = ns_sum(p, 0, np, sh), s2 = ns_sum(p, 1, np, sh);
   if (threadIdx.x != 0) return;
   p->iters += 1;
   const double dd = sqrt(s1 / fmax(s2, 1e-300));
   if (kind == 0) {
-    double a, b, ln;
-    ns_cubic(p->l, a, b, ln);
+    double a, bc, ln;
+    ns_cubic(p->l, a, bc, ln);
     p->l = ln;
   }
   if (dd <= tol) {
     p->conv = 1;
-    p->gate = 1;
+    gate[b] = 1;
   }
 }
 
@@ -451,23 +467,24 @@ __global__ void k_ns_check(const BlockDesc* D, char* ws, int kind, double tol, i
 // equally large (Sec. II), i.e. trace 0 (one work-group)
 template <class T>
 __global__ void k_ns_trace(const BlockDesc* D, char* ws, int* info, int dsel, int buf) {
-  const BlockDesc& d = D[0];
-  if (info[0]) return;
+  const int b = blockIdx.x;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
   __shared__ double sh[16];
   const int n = seldim(d, dsel);
   const T* X = bufp<T>(ws, d, buf);
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) s += re(X[(long long)i * n + i]);
   s = block_sum(s, sh);
-  if (threadIdx.x == 0 && !(fabs(s) < 0.5)) info[0] = 4;
+  if (threadIdx.x == 0 && !(fabs(s) < 0.5)) info[b] = 4;
 }
 
 // P = (I + X) / 2 on the large-component columns: P_LL = (I + X_LL) / 2,
 // P_SL = X_SL / 2 (h-sized, dimension h = 4c dimension / 2)
 template <class T>
 __global__ void k_ns_split(const BlockDesc* D, char* ws, const int* info, int dsel4, int bufX, int bufLL, int bufSL) {
-  const BlockDesc& d = D[0];
-  if (info[0]) return;
+  const BlockDesc& d = D[blockIdx.y];
+  if (info[blockIdx.y]) return;
   const int n4 = seldim(d, dsel4), h = n4 / 2;
   const T* X = bufp<T>(ws, d, bufX);
   T* PLL = bufp<T>(ws, d, bufLL);
@@ -484,8 +501,8 @@ __global__ void k_ns_split(const BlockDesc* D, char* ws, const int* info, int ds
 
 template <class T>
 __global__ void k_ns_eye(const BlockDesc* D, char* ws, const int* info, int dsel, int buf) {
-  const BlockDesc& d = D[0];
-  if (info[0]) return;
+  const BlockDesc& d = D[blockIdx.y];
+  if (info[blockIdx.y]) return;
   const int n = seldim(d, dsel);
   T* A = bufp<T>(ws, d, buf);
   const long long tot = (long long)n * n;
@@ -496,10 +513,11 @@ __global__ void k_ns_eye(const BlockDesc* D, char* ws, const int* info, int dsel
 // largest row sum of the moduli of A - sigma I (>= its spectral radius), one
 // wave per row; non-negative doubles order like their bit patterns
 template <class T>
-__global__ void k_ns_rowmax(const BlockDesc* D, char* ws, int dsel, int buf, double sigma) {
-  const BlockDesc& d = D[0];
+__global__ void k_ns_rowmax(const BlockDesc* D, char* ws, const int* gate, int dsel, int buf, double sigma) {
+  const int b = blockIdx.y;
+  if (gate[b]) return;
+  const BlockDesc& d = D[b];
   NsPar* p = nspar(ws, d);
-  if (p->gate) return;
   const int n = seldim(d, dsel);
   const T* A = bufp<T>(ws, d, buf);
   const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -516,7 +534,7 @@ __global__ void k_ns_rowmax(const BlockDesc* D, char* ws, int dsel, int buf, dou
 
 // eigenvalues are not produced by this path: NaN marks them
 __global__ void k_eps_nan(const BlockDesc* D, double* eps) {
-  const BlockDesc& d = D[0];
+  const BlockDesc& d = D[blockIdx.y];
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.n; k += gridDim.x * blockDim.x)
     eps[d.eps_off + k] = __longlong_as_double(0x7ff8000000000000ll);
 }
@@ -701,38 +719,41 @@ void launch_gemm_q_big(hipStream_t s, const BlockDesc* D, char* ws, const int* g
 
 // ---------------------------------------------------------------- host side
 namespace {
-int* gate_of(const BlockDesc& hd, char* ws) {
-  return reinterpret_cast<int*>(ws + hd.off[V_NS] + offsetof(NsPar, gate));
-}
-
+// products of the iterations: one block on the whole-matrix kernel, several
+// blocks on the batched one (the gate array in place of the block status)
 template <class T>
-void gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* gate, int dim, int dsel, int A, int B, int C,
-          int herm) {
-  if constexpr (is_quat<T>()) launch_gemm_q_big(s, D, ws, gate, dim, dsel, A, B, C, 0.0, herm);
-  else launch_gemm<T>(s, D, ws, gate, 1, dim, dsel, A, 0, B, 0, C, treal<T>(1.0), tzero<T>(), herm, 0);
+void gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* gate, int nblk, int maxdim, int dsel, int A, int B,
+          int C, int herm) {
+  if constexpr (is_quat<T>()) {
+    if (nblk == 1) launch_gemm_q_big(s, D, ws, gate, maxdim, dsel, A, B, C, 0.0, herm);
+    else launch_gemm_q(s, D, ws, gate, nblk, maxdim, dsel, A, 0, B, 0, C, 1.0, 0.0, herm);
+  } else {
+    launch_gemm<T>(s, D, ws, gate, nblk, maxdim, dsel, A, 0, B, 0, C, treal<T>(1.0), tzero<T>(), herm, 0);
+  }
 }
 }  // namespace
 
 template <class T>
-void launch_large_sign(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
-                       int dim4, int bufX, int bufU, int bufN, double c, int maxit, double tol) {
-  const int* gate = gate_of(hd, ws);
-  const long long tot = (long long)dim4 * dim4;
+void launch_large_sign(hipStream_t s, const BlockDesc* D, char* ws, int* info, int* gate, int nblk, int dsel4,
+                       int maxdim4, int bufX, int bufU, int bufN, double c, int maxit, double tol) {
+  const long long tot = (long long)maxdim4 * maxdim4;
+  const int eg = egrid(tot);
+  const dim3 ge(eg, nblk);
   const double sigma = -c * c;
-  hipLaunchKernelGGL(k_ns_begin, dim3(1), dim3(1), 0, s, D, ws, info);
-  hipLaunchKernelGGL(k_ns_fro<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufX, sigma);
-  hipLaunchKernelGGL(k_ns_rowmax<T>, dim3((dim4 + 3) / 4), dim3(256), 0, s, D, ws, dsel4, bufX, sigma);
-  hipLaunchKernelGGL(k_ns_start, dim3(1), dim3(256), 0, s, D, ws, sigma, 0.5 * c * c, egrid(tot));
-  hipLaunchKernelGGL(k_ns_shift<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufX);
+  hipLaunchKernelGGL(k_ns_begin, dim3(nblk), dim3(1), 0, s, D, ws, info, gate);
+  hipLaunchKernelGGL(k_ns_fro<T>, ge, dim3(256), 0, s, D, ws, gate, dsel4, bufX, sigma);
+  hipLaunchKernelGGL(k_ns_rowmax<T>, dim3((maxdim4 + 3) / 4, nblk), dim3(256), 0, s, D, ws, gate, dsel4, bufX, sigma);
+  hipLaunchKernelGGL(k_ns_start, dim3(nblk), dim3(256), 0, s, D, ws, gate, sigma, 0.5 * c * c, eg);
+  hipLaunchKernelGGL(k_ns_shift<T>, ge, dim3(256), 0, s, D, ws, gate, dsel4, bufX);
   for (int it = 0; it < maxit; ++it) {
-    gemm<T>(s, D, ws, gate, dim4, dsel4, bufX, bufX, bufU, 1);
-    hipLaunchKernelGGL(k_ns_poly<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufU, 0);
-    gemm<T>(s, D, ws, gate, dim4, dsel4, bufX, bufU, bufN, 1);
-    hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dsel4, bufN, bufX, 1);
-    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(256), 0, s, D, ws, 0, tol, egrid(tot));
+    gemm<T>(s, D, ws, gate, nblk, maxdim4, dsel4, bufX, bufX, bufU, 1);
+    hipLaunchKernelGGL(k_ns_poly<T>, ge, dim3(256), 0, s, D, ws, gate, dsel4, bufU, 0);
+    gemm<T>(s, D, ws, gate, nblk, maxdim4, dsel4, bufX, bufU, bufN, 1);
+    hipLaunchKernelGGL(k_ns_accept<T>, ge, dim3(256), 0, s, D, ws, gate, dsel4, bufN, bufX, 1);
+    hipLaunchKernelGGL(k_ns_check, dim3(nblk), dim3(256), 0, s, D, ws, gate, 0, tol, eg);
   }
-  hipLaunchKernelGGL(k_ns_end, dim3(1), dim3(1), 0, s, D, ws, info, 3);
-  hipLaunchKernelGGL(k_ns_trace<T>, dim3(1), dim3(256), 0, s, D, ws, info, dsel4, bufX);
+  hipLaunchKernelGGL(k_ns_end, dim3(nblk), dim3(1), 0, s, D, ws, info, gate, 3);
+  hipLaunchKernelGGL(k_ns_trace<T>, dim3(nblk), dim3(256), 0, s, D, ws, info, dsel4, bufX);
 }
 
 // X~ and Q^-1/2 from one coupled Newton-Schulz iteration on P_LL: with P an
@@ -741,38 +762,39 @@ void launch_large_sign(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, c
 // U = (3I - Z Y) / 2, Y <- Y U, Z <- U Z: Y -> P_LL^(1/2) (into bufQmh),
 // Z -> P_LL^(-1/2); then X~ = (P_SL Z) Z.
 template <class T>
-void launch_large_xrenorm(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
-                          int dselh, int dimh, int bufX, int bufPSL, int bufZ, int bufU, int bufN, int bufXt,
+void launch_large_xrenorm(hipStream_t s, const BlockDesc* D, char* ws, int* info, int* gate, int nblk, int dsel4,
+                          int dselh, int maxdimh, int bufX, int bufPSL, int bufZ, int bufU, int bufN, int bufXt,
                           int bufQmh, int maxit, double tol) {
-  const int* gate = gate_of(hd, ws);
-  const long long tot = (long long)dimh * dimh;
-  hipLaunchKernelGGL(k_ns_split<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dsel4, bufX, bufQmh, bufPSL);
-  hipLaunchKernelGGL(k_ns_eye<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, info, dselh, bufZ);
-  hipLaunchKernelGGL(k_ns_begin, dim3(1), dim3(1), 0, s, D, ws, info);
+  const long long tot = (long long)maxdimh * maxdimh;
+  const int eg = egrid(tot);
+  const dim3 ge(eg, nblk);
+  hipLaunchKernelGGL(k_ns_split<T>, ge, dim3(256), 0, s, D, ws, info, dsel4, bufX, bufQmh, bufPSL);
+  hipLaunchKernelGGL(k_ns_eye<T>, ge, dim3(256), 0, s, D, ws, info, dselh, bufZ);
+  hipLaunchKernelGGL(k_ns_begin, dim3(nblk), dim3(1), 0, s, D, ws, info, gate);
   for (int it = 0; it < maxit; ++it) {
-    gemm<T>(s, D, ws, gate, dimh, dselh, bufZ, bufQmh, bufU, 1);
-    hipLaunchKernelGGL(k_ns_poly<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufU, 2);
-    gemm<T>(s, D, ws, gate, dimh, dselh, bufQmh, bufU, bufN, 1);
-    hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufN, bufQmh, 0);
-    gemm<T>(s, D, ws, gate, dimh, dselh, bufU, bufZ, bufN, 1);
-    hipLaunchKernelGGL(k_ns_accept<T>, dim3(egrid(tot)), dim3(256), 0, s, D, ws, dselh, bufN, bufZ, 1);
-    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(256), 0, s, D, ws, 2, tol, egrid(tot));
+    gemm<T>(s, D, ws, gate, nblk, maxdimh, dselh, bufZ, bufQmh, bufU, 1);
+    hipLaunchKernelGGL(k_ns_poly<T>, ge, dim3(256), 0, s, D, ws, gate, dselh, bufU, 2);
+    gemm<T>(s, D, ws, gate, nblk, maxdimh, dselh, bufQmh, bufU, bufN, 1);
+    hipLaunchKernelGGL(k_ns_accept<T>, ge, dim3(256), 0, s, D, ws, gate, dselh, bufN, bufQmh, 0);
+    gemm<T>(s, D, ws, gate, nblk, maxdimh, dselh, bufU, bufZ, bufN, 1);
+    hipLaunchKernelGGL(k_ns_accept<T>, ge, dim3(256), 0, s, D, ws, gate, dselh, bufN, bufZ, 1);
+    hipLaunchKernelGGL(k_ns_check, dim3(nblk), dim3(256), 0, s, D, ws, gate, 2, tol, eg);
   }
-  hipLaunchKernelGGL(k_ns_end, dim3(1), dim3(1), 0, s, D, ws, info, 3);
-  // X~ = (P_SL Z) Z (general products: the gate is the block status again)
-  gemm<T>(s, D, ws, gate, dimh, dselh, bufPSL, bufZ, bufN, 0);
-  gemm<T>(s, D, ws, gate, dimh, dselh, bufN, bufZ, bufXt, 0);
+  hipLaunchKernelGGL(k_ns_end, dim3(nblk), dim3(1), 0, s, D, ws, info, gate, 3);
+  // X~ = (P_SL Z) Z (general products: the gates are the block status again)
+  gemm<T>(s, D, ws, gate, nblk, maxdimh, dselh, bufPSL, bufZ, bufN, 0);
+  gemm<T>(s, D, ws, gate, nblk, maxdimh, dselh, bufN, bufZ, bufXt, 0);
 }
 
-void launch_eps_nan(hipStream_t s, const BlockDesc* D, double* eps) {
-  hipLaunchKernelGGL(k_eps_nan, dim3(16), dim3(256), 0, s, D, eps);
+void launch_eps_nan(hipStream_t s, const BlockDesc* D, double* eps, int nblk) {
+  hipLaunchKernelGGL(k_eps_nan, dim3(16, nblk), dim3(256), 0, s, D, eps);
 }
 
-#define X2C_LARGE_INST(T)                                                                                          \
-  template void launch_large_sign<T>(hipStream_t, const BlockDesc*, const BlockDesc&, char*, int*, int, int, int, \
-                                     int, int, double, int, double);                                              \
-  template void launch_large_xrenorm<T>(hipStream_t, const BlockDesc*, const BlockDesc&, char*, int*, int, int,   \
-                                        int, int, int, int, int, int, int, int, int, double);
+#define X2C_LARGE_INST(T)                                                                                         \
+  template void launch_large_sign<T>(hipStream_t, const BlockDesc*, char*, int*, int*, int, int, int, int, int, int, \
+                                     double, int, double);                                                       \
+  template void launch_large_xrenorm<T>(hipStream_t, const BlockDesc*, char*, int*, int*, int, int, int, int, int, \
+                                        int, int, int, int, int, int, int, double);
 X2C_LARGE_INST(double)
 X2C_LARGE_INST(cplx)
 X2C_LARGE_INST(quat)

@@ -47,8 +47,8 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t head = 0;                 // info + descriptors
-  size_t info_off = 0, desc_off = 0;
+  size_t head = 0;                 // info, iteration gates, descriptors
+  size_t info_off = 0, gate_off = 0, desc_off = 0;
   size_t total = 0;
   std::vector<BlockDesc> desc;
   BlockDesc* pinned = nullptr;     // page-locked copy of desc for the upload
@@ -187,7 +187,8 @@ bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in
   const int mx = fw >= 0 ? small_max_n(o->mode) : max_n(o->mode);
   const int wf = fw >= 0 ? mx + 1 : wide_from(o->mode);
   L.info_off = 0;
-  L.desc_off = align_up((size_t)nblk * sizeof(int));
+  L.gate_off = align_up((size_t)nblk * sizeof(int));
+  L.desc_off = align_up(L.gate_off + (size_t)nblk * sizeof(int));
   L.head = align_up(L.desc_off + (size_t)nblk * sizeof(BlockDesc));
   L.desc.resize(nblk);
   size_t off = L.head;
@@ -404,7 +405,7 @@ void trace_collect() {
 #define STAGE(nm) Stage stage_guard_(nm, s)
 
 // Trace mode only: the step count of the Newton-Schulz iteration that just
-// ran on the device-wide path, filed as a record with that count and no time
+// ran on the device-wide path (of its first, largest block), filed as a record with that count and no time
 // (the call waits for it; traced calls are diagnostic and never captured).
 void trace_iterations(const char* name, hipStream_t s, const BlockDesc& hd, char* ws) {
   {
@@ -680,7 +681,9 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
                const double* W, double* h, double* eps, double* Xo, double* Ro, int* info, char* ws, hipStream_t s,
                int mv_res, bool large = false) {
   const BlockDesc* D = reinterpret_cast<const BlockDesc*>(ws + L.desc_off) + b0;
-  // large: one block on the device-wide path (nblk == 1)
+  // large: the blocks run on the device-wide path; gate holds their
+  // iteration gates, hd is the first (largest) one
+  int* gate = reinterpret_cast<int*>(ws + L.gate_off) + b0;
   const BlockDesc& hd = L.desc[b0];
   const bool tc = o->mode == X2C_TWOCOMP;
   const double c = o->c;
@@ -733,7 +736,7 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
     launch_init_info(s, info, nblk);
     launch_unpack(s, D, ws, info, nblk, maxN, S, Tm, V, W, tc ? 1 : 0);
     if (large) {
-      launch_large_cholesky(s, D, ws, info, hd.N);
+      launch_large_cholesky(s, D, ws, info, nblk, maxN);
     } else {
       launch_potrf(s, D, ws, info, nblk, maxN);
       launch_trtri(s, D, ws, info, nblk, maxN);
@@ -777,10 +780,11 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
   if (large) {
     // positive-energy branch: sign(A + c^2 I) by products of the whole matrix
     STAGE("sign_4c");
-    if (kramers) launch_large_sign<quat>(s, D, hd, ws, info, DIM_n, hd.n, C_A, C_G1, C_G2, c, NS_SIGN_IT, NS_TOL);
-    else launch_large_sign<T>(s, D, hd, ws, info, DIM_m, hd.m, C_A, C_G1, C_G2, c, NS_SIGN_IT, NS_TOL);
+    if (kramers)
+      launch_large_sign<quat>(s, D, ws, info, gate, nblk, DIM_n, maxn, C_A, C_G1, C_G2, c, NS_SIGN_IT, NS_TOL);
+    else launch_large_sign<T>(s, D, ws, info, gate, nblk, DIM_m, maxm, C_A, C_G1, C_G2, c, NS_SIGN_IT, NS_TOL);
     trace_iterations("sign_4c_steps", s, hd, ws);
-    if (eps) launch_eps_nan(s, D, eps);
+    if (eps) launch_eps_nan(s, D, eps, nblk);
   } else if (!kramers) {
     // positive-energy branch of the reduced 4c matrix (complex m x m form)
     {
@@ -829,11 +833,11 @@ int run_stages(const x2c_options* o, const Layout& L, const Dims& dm, int b0, in
       // with it Q^-1/2 = P_LL^(1/2) (quaternion into C_LR, else into C_QMH,
       // where the renormalisation below expects it)
       if (kramers) {
-        launch_large_xrenorm<quat>(s, D, hd, ws, info, DIM_n, DIM_N, hd.N, C_A, H_A, H_B, H_C, H_D, C_QMH, C_LR,
-                                   NS_AUX_IT, NS_TOL);
+        launch_large_xrenorm<quat>(s, D, ws, info, gate, nblk, DIM_n, DIM_N, maxN, C_A, H_A, H_B, H_C, H_D, C_QMH,
+                                   C_LR, NS_AUX_IT, NS_TOL);
       } else {
-        launch_large_xrenorm<T>(s, D, hd, ws, info, DIM_m, DIM_n, hd.n, C_A, H_A, H_B, H_C, H_D, C_TMP, C_QMH,
-                                NS_AUX_IT, NS_TOL);
+        launch_large_xrenorm<T>(s, D, ws, info, gate, nblk, DIM_m, DIM_n, maxn, C_A, H_A, H_B, H_C, H_D, C_TMP,
+                                C_QMH, NS_AUX_IT, NS_TOL);
       }
       trace_iterations("x_solve_steps", s, hd, ws);
     } else if (L.fw == 0) {
@@ -1149,7 +1153,7 @@ void split_parts(const Layout& L, int lo, int ways, int* bnd) {
 // latency-bound steps of one part (the per-column kernels of the
 // reductions, the LU panels) overlap the bandwidth- and matrix-core-bound
 // kernels of the other.  Blocks never share workspace, so the two parts are
-// independent.  Blocks of the device-wide path run first, one at a time, on s.
+// independent.  Blocks of the device-wide path run first, together, on s.
 int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S, const double* T, const double* V,
                 const double* W, void* h, double* eps, void* Xo, void* Ro, int* info, char* ws, hipStream_t s,
                 bool allow_split) {
@@ -1187,10 +1191,7 @@ int enqueue_all(const x2c_options* o, const Layout& L, int nblk, const double* S
     return rc;
   };
   int rc = X2C_OK;
-  for (int b = 0; b < L.nlarge; ++b) {
-    const int r = run(b, 1, s, true);
-    if (rc == X2C_OK) rc = r;
-  }
+  if (L.nlarge > 0) rc = run(0, L.nlarge, s, true);
   const int lo = L.nlarge, nsmall = nblk - lo;
   if (nsmall == 0) return finish(rc);
   const int ways = std::min(tn.ways, nsmall);

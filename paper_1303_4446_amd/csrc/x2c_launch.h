@@ -142,20 +142,21 @@ template <class T>
 void launch_bss_h0(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxN, int bufE1,
                    int bufO1, int bufE1p, int bufFP, int bufA, double c);
 
-// device-wide path of one large block (k_large.hip); D points to the
-// block's descriptor, hd is its host copy, info to its status
-void launch_large_cholesky(hipStream_t s, const BlockDesc* D, char* ws, int* info, int N);
-// sign(A + c^2 I) of the 4c matrix in bufX (dimension dim4, selector dsel4),
-// in place; bufU, bufN: 4c-sized scratch
+// device-wide path of the large blocks (k_large.hip), nblk blocks from
+// descriptor D on; info and gate point to their status words and iteration
+// gates (nblk ints each); maxN, maxdim* are the largest dimensions among them
+void launch_large_cholesky(hipStream_t s, const BlockDesc* D, char* ws, int* info, int nblk, int maxN);
+// sign(A + c^2 I) of the 4c matrix in bufX (selector dsel4), in place;
+// bufU, bufN: 4c-sized scratch
 template <class T>
-void launch_large_sign(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
-                       int dim4, int bufX, int bufU, int bufN, double c, int maxit, double tol);
+void launch_large_sign(hipStream_t s, const BlockDesc* D, char* ws, int* info, int* gate, int nblk, int dsel4,
+                       int maxdim4, int bufX, int bufU, int bufN, double c, int maxit, double tol);
 // X~ = P_SL P_LL^-1 into bufXt and Q^-1/2 = P_LL^(1/2) into bufQmh from one
 // coupled iteration on P_LL (the converged sign in bufX)
 template <class T>
-void launch_large_xrenorm(hipStream_t s, const BlockDesc* D, const BlockDesc& hd, char* ws, int* info, int dsel4,
-                          int dselh, int dimh, int bufX, int bufPSL, int bufZ, int bufU, int bufN, int bufXt,
+void launch_large_xrenorm(hipStream_t s, const BlockDesc* D, char* ws, int* info, int* gate, int nblk, int dsel4,
+                          int dselh, int maxdimh, int bufX, int bufPSL, int bufZ, int bufU, int bufN, int bufXt,
                           int bufQmh, int maxit, double tol);
-void launch_eps_nan(hipStream_t s, const BlockDesc* D, double* eps);
+void launch_eps_nan(hipStream_t s, const BlockDesc* D, double* eps, int nblk);
 
 }  // namespace x2c

@@ -132,6 +132,27 @@ def test_mixed_batch_device_wide_and_batched_blocks():
         check_h(b.S, b.T, b.V, b.W, C_LIGHT, True, hs[i])
 
 
+@pytest.mark.parametrize("twocomp", [True, False])
+def test_many_blocks_device_wide_in_one_launch_sequence(twocomp):
+    """Every block of a batch of thirteen atoms (seven sizes, in no order)
+    forced onto the device-wide path: the blocks run together, each kernel
+    covering all of them up to the largest; each block against the oracle."""
+    px, torch = _px()
+    zs = (47, 1, 8, 79, 17, 10, 47, 6, 1, 36, 8, 79, 55)
+    blocks = [atom_block(z) for z in zs]
+    with device_wide_from(twocomp, 1):
+        bt = px.batch_to_device(pack_blocks(blocks, twocomp), twocomp)
+        print(f"  device-wide batch twocomp={twocomp} N={list(bt.Ns)}", flush=True)
+        (h, eps, info), _ = px.build_batched(bt, C_LIGHT)
+        torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    assert np.all(np.isnan(eps.cpu().numpy()))
+    hs = px.unpack_h(h.cpu().numpy(), bt.Ns, twocomp)
+    for i, b in enumerate(blocks):
+        W = b.W if twocomp else b.W[0]
+        check_h(b.S, b.T, b.V, W, C_LIGHT, twocomp, hs[i])
+
+
 def test_device_wide_failure_codes():
     """S or T not positive definite: the blocked factorisation reports the
     batched path's codes (1, 2), h zero."""
