@@ -509,24 +509,29 @@ def full_vs_dlu(px, torch, c, stream, steps, precs, spectra=True):
         print(f"# full fp64 traced: {st} steps {steps_ns} rates {rates}", file=sys.stderr, flush=True)
     del ws
     res["full"] = full
-    # DLU: the atomic blocks (batched path, X and R kept) and the assembly
+    # DLU: the atomic blocks (X and R kept) and the assembly; the atomic
+    # blocks by size (batched path, eigenvalues written), and by the faster
+    # path for this batch (thirteen blocks: device-wide, no eigenvalues)
     atoms = [mol.atom(A) for A in range(len(mol.Ns))]
     bt = px.batch_to_device(pack_blocks(atoms, True), True)
-    (hb, eb, info, X, R), wsb = px.build_batched_xr(bt, c, stream=stream)
     h_off = bt.out_layout()[0]
-    H, wsa = px.dlu_assemble(T, V, W, mol.Ns, h_off, X, R, c, True, stream=stream)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        (hb, eb, info, X, R), wsb = px.build_batched_xr(bt, c, workspace=wsb, stream=stream)
-        H, wsa = px.dlu_assemble(T, V, W, mol.Ns, h_off, X, R, c, True, workspace=wsa, stream=stream, H=H)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    Hc = H.cpu().numpy()
-    res["dlu"] = {"ms": e0.elapsed_time(e1) / steps, "blocks_ok": bool((info.cpu().numpy() == 0).all()),
-                  "h_rel_err_vs_full_oracle": probe_err(Hc), "bound_dE_max": bound_de(Hc)}
-    print(f"# dlu: {res['dlu']}", file=sys.stderr, flush=True)
+    for key, route in (("dlu", px.ROUTE_SIZE), ("dlu_auto_route", px.ROUTE_AUTO)):
+        (hb, eb, info, X, R), wsb = px.build_batched_xr(bt, c, stream=stream, route=route)
+        H, wsa = px.dlu_assemble(T, V, W, mol.Ns, h_off, X, R, c, True, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            (hb, eb, info, X, R), wsb = px.build_batched_xr(bt, c, workspace=wsb, stream=stream, route=route)
+            H, wsa = px.dlu_assemble(T, V, W, mol.Ns, h_off, X, R, c, True, workspace=wsa, stream=stream, H=H)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        Hc = H.cpu().numpy()
+        res[key] = {"ms": e0.elapsed_time(e1) / steps, "blocks_ok": bool((info.cpu().numpy() == 0).all()),
+                    "atomic_blocks_device_wide": bool(torch.isnan(eb).all().item()),
+                    "h_rel_err_vs_full_oracle": probe_err(Hc), "bound_dE_max": bound_de(Hc)}
+        print(f"# {key}: {res[key]}", file=sys.stderr, flush=True)
+        del wsb, wsa, X, R, hb, eb, H
     if "fp64" in full:
         res["full_over_dlu_time"] = full["fp64"]["ms"] / res["dlu"]["ms"]
     return res

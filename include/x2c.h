@@ -72,19 +72,35 @@ typedef enum { X2C_FP64 = 0, X2C_SPLIT_BF16 = 1, X2C_SPLIT_INT8 = 2 } x2c_prec;
  * spin-free blocks. */
 typedef enum { X2C_RED_QUATERNION = 0, X2C_RED_COMPLEX = 1 } x2c_reduction;
 
+/* Which path the blocks of a call take (see x2c_max_n for the two paths).
+ * X2C_ROUTE_SIZE: by block size, the device-wide path from
+ * x2c_device_wide_min_n on, the batched path below (eigenvalues written).
+ * X2C_ROUTE_DEVICE_WIDE: every block on the device-wide path (eps NaN).
+ * X2C_ROUTE_AUTO: for callers that do not need the eigenvalues: the blocks of
+ * batched-path size take the device-wide path together when the batch is
+ * small enough for that to be faster, else the batched path.  The estimate:
+ * sum over those blocks of N_b^1.5 below 1.7e5 (two-component, quaternion
+ * reduction; half that with the complex one) or 1.4e6 (spin-free), where the
+ * two paths' times cross for uniform batches of atomic blocks in FP64 on
+ * MI355X.  eps of a block is NaN whenever it took the device-wide path.
+ * BSS and DKHn (batched path only) ignore the route; the no-allocation entry
+ * point accepts X2C_ROUTE_SIZE only. */
+typedef enum { X2C_ROUTE_SIZE = 0, X2C_ROUTE_DEVICE_WIDE = 1, X2C_ROUTE_AUTO = 2 } x2c_route;
+
 typedef struct {
   int mode;          /* x2c_mode */
   int prec;          /* x2c_prec: arithmetic of the X / L / S~ / R product chain */
   int ozaki_slices;  /* split precision only: slices per operand, 1..8; 0 = automatic (bf16 7, int8 8) */
   double c;          /* speed of light in atomic units (> 0) */
   int reduction;     /* x2c_reduction (two-component only); 0 = quaternion */
+  int route;         /* x2c_route; 0 = by block size */
 } x2c_options;
 
 /* return codes */
 enum {
   X2C_OK = 0,
   X2C_EINVAL = -1,  /* bad argument: NULL pointer, N <= 0 or > x2c_max_n, c <= 0,
-                       unknown mode/prec/reduction, workspace too small,
+                       unknown mode/prec/reduction/route, workspace too small,
                        overlapping layout */
   X2C_EHIP = -2,    /* a HIP runtime call or kernel launch failed */
   X2C_EBLOCK = -3,  /* x2c_build only: the block failed; see its info code */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libx2c.so")
 SPINFREE, TWOCOMP = 1, 2
 FP64, SPLIT_BF16, SPLIT_INT8 = 0, 1, 2
 RED_QUATERNION, RED_COMPLEX = 0, 1
+ROUTE_SIZE, ROUTE_DEVICE_WIDE, ROUTE_AUTO = 0, 1, 2
 
 OK, EINVAL, EHIP, EBLOCK, ESCRATCH = 0, -1, -2, -3, -4
 INFO_NAMES = {0: "ok", 1: "S not SPD", 2: "T not SPD", 3: "positive-energy subspace not resolved",
@@ -40,7 +41,7 @@ class X2CError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("prec", ctypes.c_int), ("ozaki_slices", ctypes.c_int),
-                ("c", ctypes.c_double), ("reduction", ctypes.c_int)]
+                ("c", ctypes.c_double), ("reduction", ctypes.c_int), ("route", ctypes.c_int)]
 
 
 _LIB = None
@@ -126,8 +127,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
 
 
 def options(twocomp: bool, c: float, prec: int = FP64, slices: int = 0,
-            reduction: int = RED_QUATERNION) -> _Options:
-    return _Options(TWOCOMP if twocomp else SPINFREE, prec, slices, float(c), reduction)
+            reduction: int = RED_QUATERNION, route: int = 0) -> _Options:
+    return _Options(TWOCOMP if twocomp else SPINFREE, prec, slices, float(c), reduction, route)
 
 
 def strerror(code: int) -> str:
@@ -149,9 +150,10 @@ def device_wide_min_n(twocomp: bool, n: int | None = None) -> int:
     return int(r)
 
 
-def workspace_bytes(Ns, twocomp: bool, c: float = 137.0, prec: int = FP64) -> int:
+def workspace_bytes(Ns, twocomp: bool, c: float = 137.0, prec: int = FP64, route: int = 0,
+                    reduction: int = RED_QUATERNION) -> int:
     Ns = np.ascontiguousarray(Ns, dtype=np.int32)
-    opt = options(twocomp, c, prec)
+    opt = options(twocomp, c, prec, 0, reduction, route)
     n = load().x2c_workspace_bytes(ctypes.byref(opt), len(Ns), Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
     if n == 0:
         raise X2CError(EINVAL, "invalid block sizes or options")
@@ -249,7 +251,7 @@ def batch_to_device(packed: dict, twocomp: bool, device="cuda") -> Batch:
 
 
 def build_batched_xr(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspace=None, stream=None,
-                     reduction: int = RED_QUATERNION):
+                     reduction: int = RED_QUATERNION, route: int = 0):
     """Enqueue x2c_build_batched_xr.  Returns (h, eps, info, X, R) device
     tensors (X and R in the flat layout of h) and the workspace."""
     torch = _torch()
@@ -261,10 +263,10 @@ def build_batched_xr(batch: Batch, c: float, prec: int = FP64, slices: int = 0, 
     R = torch.empty(hsz, dtype=torch.float64, device=dev)
     eps = torch.empty(esz, dtype=torch.float64, device=dev)
     info = torch.empty(batch.nblk, dtype=torch.int32, device=dev)
-    wsb = workspace_bytes(batch.Ns, batch.twocomp, c, prec)
+    wsb = workspace_bytes(batch.Ns, batch.twocomp, c, prec, route, reduction)
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
-    opt = options(batch.twocomp, c, prec, slices, reduction)
+    opt = options(batch.twocomp, c, prec, slices, reduction, route)
     Ns = np.ascontiguousarray(batch.Ns, dtype=np.int32)
     i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
     in_off, ho, eo = i64(batch.in_off), i64(h_off), i64(eps_off)
@@ -350,7 +352,7 @@ def dlu_assemble(T, V, W, Ns, u_off, X, R, c: float, twocomp: bool, workspace=No
 
 
 def build_batched(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspace=None, out=None,
-                  stream=None, reduction: int = RED_QUATERNION):
+                  stream=None, reduction: int = RED_QUATERNION, route: int = 0):
     """Enqueue x2c_build_batched.  Returns (h_flat, eps_flat, info) device
     tensors (h_flat float64; complex blocks interleaved) and the workspace."""
     torch = _torch()
@@ -363,10 +365,10 @@ def build_batched(batch: Batch, c: float, prec: int = FP64, slices: int = 0, wor
         info = torch.empty(batch.nblk, dtype=torch.int32, device=dev)
     else:
         h, eps, info = out
-    wsb = workspace_bytes(batch.Ns, batch.twocomp, c, prec)
+    wsb = workspace_bytes(batch.Ns, batch.twocomp, c, prec, route, reduction)
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
-    opt = options(batch.twocomp, c, prec, slices, reduction)
+    opt = options(batch.twocomp, c, prec, slices, reduction, route)
     Ns = np.ascontiguousarray(batch.Ns, dtype=np.int32)
     i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
     in_off, ho, eo = i64(batch.in_off), i64(h_off), i64(eps_off)
@@ -510,7 +512,7 @@ def dkh_batched(batch: Batch, c: float, order: int, workspace=None, out=None, st
 
 
 def autotune(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspace=None, out=None, stream=None,
-             reduction: int = RED_QUATERNION, reps: int = 3):
+             reduction: int = RED_QUATERNION, reps: int = 3, route: int = 0):
     """x2c_autotune on the batch (writes the same outputs as build_batched).
     Returns (ways, mv_res) of the fastest launch shape, the outputs and the
     workspace."""
@@ -522,10 +524,10 @@ def autotune(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspac
         out = (torch.empty(hsz, dtype=torch.float64, device=dev), torch.empty(esz, dtype=torch.float64, device=dev),
                torch.empty(batch.nblk, dtype=torch.int32, device=dev))
     h, eps, info = out
-    wsb = workspace_bytes(batch.Ns, batch.twocomp, c, prec)
+    wsb = workspace_bytes(batch.Ns, batch.twocomp, c, prec, route, reduction)
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
-    opt = options(batch.twocomp, c, prec, slices, reduction)
+    opt = options(batch.twocomp, c, prec, slices, reduction, route)
     Ns = np.ascontiguousarray(batch.Ns, dtype=np.int32)
     i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
     in_off, ho, eo = i64(batch.in_off), i64(h_off), i64(eps_off)
@@ -566,7 +568,7 @@ def unpack_h(h_flat: np.ndarray, Ns, twocomp: bool):
 
 
 def build(S, T, V, W, c: float, twocomp: bool, prec: int = FP64, slices: int = 0, workspace=None, stream=None,
-          reduction: int = RED_QUATERNION):
+          reduction: int = RED_QUATERNION, route: int = 0):
     """x2c_build on one block given as device tensors (S, T, V: N x N;
     W: N x N (spin-free) or 4 x N x N).  Returns (h, eps) device tensors.
     Raises X2CError with .info on a failed block."""
@@ -577,8 +579,8 @@ def build(S, T, V, W, c: float, twocomp: bool, prec: int = FP64, slices: int = 0
     dev = S.device
     h = torch.empty((n, n), dtype=torch.complex128 if twocomp else torch.float64, device=dev)
     eps = torch.empty(n, dtype=torch.float64, device=dev)
-    opt = options(twocomp, c, prec, slices, reduction)
-    wsb = workspace_bytes([N], twocomp, c, prec)
+    opt = options(twocomp, c, prec, slices, reduction, route)
+    wsb = workspace_bytes([N], twocomp, c, prec, route, reduction)
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
     info = ctypes.c_int(0)

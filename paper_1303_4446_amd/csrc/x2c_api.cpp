@@ -149,6 +149,7 @@ bool valid_opts(const x2c_options* o) {
   if (!(o->c > 0.0) || !std::isfinite(o->c)) return false;
   if (o->ozaki_slices < 0 || o->ozaki_slices > MAX_SLICES) return false;
   if (o->reduction != X2C_RED_QUATERNION && o->reduction != X2C_RED_COMPLEX) return false;
+  if (o->route != X2C_ROUTE_SIZE && o->route != X2C_ROUTE_DEVICE_WIDE && o->route != X2C_ROUTE_AUTO) return false;
   return true;
 }
 
@@ -158,6 +159,23 @@ int max_n(int mode) { return mode == X2C_TWOCOMP ? WIDE_MAX_N_2C : (mode == X2C_
 // smallest N that takes the device-wide path, per mode (x2c_device_wide_min_n)
 std::atomic<int> g_wide_from[3] = {{0}, {MAX_N_SF + 1}, {MAX_N_2C + 1}};
 int wide_from(int mode) { return (mode == X2C_TWOCOMP || mode == X2C_SPINFREE) ? g_wide_from[mode].load() : 0; }
+
+// X2C_ROUTE_AUTO: whether the blocks below the device-wide threshold run
+// device-wide.  The batched path's time is set by its per-column latency (a
+// few hundred column steps of one work-group per block) up to dozens of
+// blocks and grows slowly beyond; the device-wide path's grows with the N^3
+// work of its products.  Measured crossovers for uniform batches of atomic
+// blocks (FP64, MI355X): two-component N = 103 near 120 blocks, N = 192 near
+// 64, N = 200 near 45; spin-free above 256 blocks of N = 200.  sum N_b^1.5
+// against one constant per mode follows these to within a factor of two.
+bool auto_device_wide(const x2c_options* o, int nblk, const int* N, int wf) {
+  double w = 0.0;
+  for (int b = 0; b < nblk; ++b)
+    if (N[b] < wf) w += std::pow((double)N[b], 1.5);
+  double lim = 1.4e6;
+  if (o->mode == X2C_TWOCOMP) lim = o->reduction == X2C_RED_COMPLEX ? 0.85e5 : 1.7e5;
+  return w < lim;
+}
 
 // Descriptor of one block whose buffers start at workspace byte `off`;
 // returns the end of its region.
@@ -185,7 +203,9 @@ bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in
   const bool tc = o->mode == X2C_TWOCOMP;
   // BSS and DKHn run on the batched path only
   const int mx = fw >= 0 ? small_max_n(o->mode) : max_n(o->mode);
-  const int wf = fw >= 0 ? mx + 1 : wide_from(o->mode);
+  int wf = fw >= 0 ? mx + 1 : wide_from(o->mode);
+  if (fw < 0 && (o->route == X2C_ROUTE_DEVICE_WIDE || (o->route == X2C_ROUTE_AUTO && auto_device_wide(o, nblk, N, wf))))
+    wf = 1;
   L.info_off = 0;
   L.gate_off = align_up((size_t)nblk * sizeof(int));
   L.desc_off = align_up(L.gate_off + (size_t)nblk * sizeof(int));
@@ -226,10 +246,12 @@ std::map<std::vector<int64_t>, std::shared_ptr<Layout>> g_plans;
 std::shared_ptr<Layout> get_plan(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
                                  const int64_t* h_off, const int64_t* eps_off, int fw = -1) {
   std::vector<int64_t> key;
-  key.reserve(4 * (size_t)nblk + 3);
+  key.reserve(4 * (size_t)nblk + 5);
   key.push_back(o->mode);
   key.push_back(fw);
   key.push_back(wide_from(o->mode));
+  key.push_back(o->route);
+  key.push_back(o->reduction);
   key.push_back(nblk);
   for (int b = 0; b < nblk; ++b) {
     key.push_back(N[b]);
@@ -1422,6 +1444,7 @@ int build_noalloc(const x2c_options* o, int nblk, const int* N, const int64_t* i
   if (!valid_opts(o) || nblk <= 0 || !N || !in_off || !h_off || !eps_off || !S || !T || !V || !W || !h || !eps ||
       !info)
     return X2C_EINVAL;
+  if (o->route != X2C_ROUTE_SIZE) return X2C_EINVAL;
   if (nblk > SCRATCH_MAX_BLOCKS) return X2C_ESCRATCH;
   const bool tc = o->mode == X2C_TWOCOMP;
   const int mx = small_max_n(o->mode);

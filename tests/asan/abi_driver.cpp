@@ -75,6 +75,20 @@ int main() {
   CHECK(x2c_bss_batched(&split, 1, one, off, &dummy, &dummy, &dummy, &dummy, off, &dummy, off, &dummy, info, &dummy,
                         8, nullptr) == X2C_EINVAL);
   CHECK(x2c_dlu_workspace_bytes(&o2, 13, std::vector<int>(13, 192).data()) > 0);
+  // routes: every block device-wide, or the faster path for the batch; the
+  // allocation-free entry takes the size route only
+  x2c_options dw = o2, au = o2, badr = o2;
+  dw.route = X2C_ROUTE_DEVICE_WIDE;
+  au.route = X2C_ROUTE_AUTO;
+  badr.route = 3;
+  int ag[1] = {192};
+  std::vector<int> ag309(309, 192);
+  CHECK(x2c_workspace_bytes(&badr, 1, ag) == 0);
+  CHECK(x2c_workspace_bytes(&dw, 1, ag) != x2c_workspace_bytes(&o2, 1, ag));
+  CHECK(x2c_workspace_bytes(&au, 1, ag) == x2c_workspace_bytes(&dw, 1, ag));
+  CHECK(x2c_workspace_bytes(&au, 309, ag309.data()) == x2c_workspace_bytes(&o2, 309, ag309.data()));
+  CHECK(x2c_build_batched_noalloc(&dw, 1, one, off, &dummy, &dummy, &dummy, &dummy, off, &dummy, off, &dummy, info,
+                                  nullptr) == X2C_EINVAL);
   std::printf("abi driver: %d failure(s)\n", fails);
   return fails ? 1 : 0;
 }

@@ -145,6 +145,17 @@ def test_device_wide_threshold_and_workspace():
     # the full 13-atom silver molecule (N = 2496): one GPU's HBM holds it easily
     w = px.workspace_bytes([2496], twocomp=True)
     assert 1e9 < w < 24e9
+    # routes: every block device-wide, or the faster path for the whole batch
+    # (device-wide for a few silver blocks, batched for 309 of them)
+    w_dw = px.workspace_bytes([192], twocomp=True, route=px.ROUTE_DEVICE_WIDE)
+    assert w_dw != w_batched
+    assert px.workspace_bytes([192], twocomp=True, route=px.ROUTE_AUTO) == w_dw
+    assert (px.workspace_bytes([192] * 13, twocomp=True, route=px.ROUTE_AUTO)
+            == px.workspace_bytes([192] * 13, twocomp=True, route=px.ROUTE_DEVICE_WIDE))
+    assert (px.workspace_bytes([192] * 309, twocomp=True, route=px.ROUTE_AUTO)
+            == px.workspace_bytes([192] * 309, twocomp=True))
+    with pytest.raises(px.X2CError):
+        px.workspace_bytes([192], twocomp=True, route=3)
     # BSS, DKHn and the allocation-free entry stay on the batched path
     with pytest.raises(px.X2CError):
         px.bss_workspace_bytes([300], twocomp=True)

@@ -153,6 +153,54 @@ def test_many_blocks_device_wide_in_one_launch_sequence(twocomp):
         check_h(b.S, b.T, b.V, W, C_LIGHT, twocomp, hs[i])
 
 
+def test_routes_device_wide_and_auto():
+    """X2C_ROUTE_DEVICE_WIDE puts every block on the device-wide path;
+    X2C_ROUTE_AUTO does so for a small batch (thirteen silver blocks: eps NaN)
+    and keeps the batched path for a large one (309 blocks: eps written).
+    h agrees with the size route's and with the oracle."""
+    px, torch = _px()
+    b = ag_2c()
+    h0 = ox.x2c_direct(b.S, b.T, b.V, b.W, C_LIGHT, True)[0]
+    bt = px.batch_to_device(pack_blocks([b] * 13, True), True)
+    ref = None
+    for route in (px.ROUTE_SIZE, px.ROUTE_DEVICE_WIDE, px.ROUTE_AUTO):
+        print(f"  13 silver blocks, route {route}", flush=True)
+        (h, eps, info), _ = px.build_batched(bt, C_LIGHT, route=route)
+        torch.cuda.synchronize()
+        assert np.all(info.cpu().numpy() == 0)
+        assert bool(torch.isnan(eps).all()) == (route != px.ROUTE_SIZE)
+        hs = px.unpack_h(h.cpu().numpy(), bt.Ns, True)
+        for hb in hs:
+            assert np.abs(hb - h0).max() <= TOL_H * np.abs(h0).max()
+        if ref is None:
+            ref = hs[0]
+        else:
+            assert np.abs(hs[0] - ref).max() <= TOL_H * np.abs(ref).max()
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    print("  one silver block, x2c_build, route auto", flush=True)
+    h1, e1 = px.build(d(b.S), d(b.T), d(b.V), d(b.W), C_LIGHT, True, route=px.ROUTE_AUTO)
+    assert bool(torch.isnan(e1).all())
+    assert np.abs(h1.cpu().numpy() - h0).max() <= TOL_H * np.abs(h0).max()
+    big = px.batch_to_device(pack_blocks([b] * 309, True), True)
+    print("  309 silver blocks, route auto", flush=True)
+    (h, eps, info), _ = px.build_batched(big, C_LIGHT, route=px.ROUTE_AUTO)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    assert bool(torch.isfinite(eps).all())
+    hl = px.unpack_h(h.cpu().numpy(), big.Ns, True)
+    for i in (0, 154, 308):
+        assert np.abs(hl[i] - h0).max() <= TOL_H * np.abs(h0).max()
+    sf = [atom_block(z) for z in (79, 36, 8)]
+    bs = px.batch_to_device(pack_blocks(sf, False), False)
+    print("  spin-free atoms, route auto", flush=True)
+    (h, eps, info), _ = px.build_batched(bs, C_LIGHT, route=px.ROUTE_AUTO)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0) and bool(torch.isnan(eps).all())
+    hs = px.unpack_h(h.cpu().numpy(), bs.Ns, False)
+    for i, a in enumerate(sf):
+        check_h(a.S, a.T, a.V, a.W[0], C_LIGHT, False, hs[i])
+
+
 def test_device_wide_failure_codes():
     """S or T not positive definite: the blocked factorisation reports the
     batched path's codes (1, 2), h zero."""
