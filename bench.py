@@ -119,17 +119,31 @@ def matvec_bytes(Ns, twocomp: bool, reduction: str) -> tuple[float, int]:
     return total, launches
 
 
-def recorded_traffic(kernel_src: str, summary: str):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, or None when the kernel's source has changed
-    since the counters were taken (or the summary is missing)."""
+# the dominant kernel's source and the headers whose code it inlines
+MATVEC_SOURCES = ("paper_1303_4446_amd/csrc/k_matvec.hip", "paper_1303_4446_amd/csrc/x2c_device.h",
+                  "paper_1303_4446_amd/csrc/x2c_tridiag.h")
+
+
+def sources_hash(kernel_srcs) -> str:
+    """First 16 hex digits of the SHA-256 of the files' bytes, in order."""
     import hashlib
+    srcs = (kernel_srcs,) if isinstance(kernel_srcs, str) else tuple(kernel_srcs)
+    h = hashlib.sha256()
+    for src in srcs:
+        with open(os.path.join(HERE, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel_srcs, summary: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None when the kernel's sources (the file
+    and the headers it inlines) have changed since the counters were taken
+    (or the summary is missing)."""
     try:
         with open(os.path.join(HERE, summary)) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(("|", "#", "`")))
-        with open(os.path.join(HERE, kernel_src), "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()[:16]
-        if kv.get("source_sha256_16", "").strip() != h:
+        if kv.get("source_sha256_16", "").strip() != sources_hash(kernel_srcs):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -708,7 +722,7 @@ def main():
         achieved = per_launch_b / (avg_ms / 1e3) / 1e9
         traffic = None
         if args.workload == "ag309" and twocomp and args.reduction == "quaternion":
-            traffic = recorded_traffic("paper_1303_4446_amd/csrc/k_matvec.hip",
+            traffic = recorded_traffic(MATVEC_SOURCES,
                                        "profiles/k_tri_matvec_w_ag309_traffic.md")
         roofline = {"bound": "hbm", "kernel": "k_tri_matvec_w" if (twocomp and args.reduction == "quaternion")
                     else "k_tri_matvec", "achieved": achieved, "peak": PEAK_HBM_GBS,

@@ -73,7 +73,18 @@ __host__ __device__ inline double re(quat x) { return x.a.x; }
 __host__ __device__ inline double im(quat x) { return x.a.y; }
 __host__ __device__ inline double abs2(quat x) { return abs2(x.a) + abs2(x.b); }
 __host__ __device__ inline double abs1(quat x) { return abs1(x.a) + abs1(x.b); }
-__device__ inline quat mad(quat x, quat y, quat c) { return c + x * y; }
+// c + x y as sixteen fused multiply-adds, each component accumulated into c
+// (the component form of the product above; signs as source negations)
+__device__ inline quat mad(quat x, quat y, quat c) {
+  const double xr = x.a.x, xi = x.a.y, xj = x.b.x, xk = x.b.y;
+  const double yr = y.a.x, yi = y.a.y, yj = y.b.x, yk = y.b.y;
+  quat r;
+  r.a.x = fma(-xk, yk, fma(-xj, yj, fma(-xi, yi, fma(xr, yr, c.a.x))));
+  r.a.y = fma(xj, yk, fma(-xk, yj, fma(xi, yr, fma(xr, yi, c.a.y))));
+  r.b.x = fma(xk, yi, fma(xj, yr, fma(-xi, yk, fma(xr, yj, c.b.x))));
+  r.b.y = fma(-xj, yi, fma(xk, yr, fma(xi, yj, fma(xr, yk, c.b.y))));
+  return r;
+}
 __device__ inline quat mad(double s, quat y, quat c) { return {mad(s, y.a, c.a), mad(s, y.b, c.b)}; }
 
 // real components of an element (1 real, 2 complex, 4 quaternion:

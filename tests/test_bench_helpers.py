@@ -73,6 +73,15 @@ def test_recorded_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     src.write_bytes(b"kernel source, changed")
     assert bench.recorded_traffic("k.hip", "p.md") is None
     assert bench.recorded_traffic("k.hip", "missing.md") is None
+    # several sources: an edit of an inlined header invalidates the figure too
+    hdr = tmp_path / "k.h"
+    hdr.write_bytes(b"header")
+    src.write_bytes(b"kernel source")
+    h2 = hashlib.sha256(b"kernel source" + b"header").hexdigest()[:16]
+    prof.write_text(f"source: k.hip, k.h\nsource_sha256_16: {h2}\ntraffic_bytes_per_launch: 2.5e+08\n")
+    assert bench.recorded_traffic(("k.hip", "k.h"), "p.md") == 2.5e8
+    hdr.write_bytes(b"header, changed")
+    assert bench.recorded_traffic(("k.hip", "k.h"), "p.md") is None
 
 
 def test_committed_profile_is_readable():
@@ -85,7 +94,7 @@ def test_committed_profile_is_readable():
     assert len(kv["source_sha256_16"].strip()) == 16
     t = float(kv["traffic_bytes_per_launch"])
     assert 1.0e8 < t < 1.0e9
-    v = bench.recorded_traffic("paper_1303_4446_amd/csrc/k_matvec.hip", "profiles/k_tri_matvec_w_ag309_traffic.md")
+    v = bench.recorded_traffic(bench.MATVEC_SOURCES, "profiles/k_tri_matvec_w_ag309_traffic.md")
     assert v is None or v == t
 
 
