@@ -127,8 +127,9 @@ enum {
  * work-group per block and column step of the reductions, many blocks at
  * once, eigenvalues eps written out.  Larger blocks (a whole molecular matrix,
  * the full transformation that the DLU scheme of Sec. III.A approximates)
- * run on the device-wide path, one block at a time on the whole GPU: blocked
- * Cholesky factors, the positive-energy branch from the spectral projector
+ * run on the device-wide path, all such blocks of a call together, each
+ * product spread over the whole GPU (one block: a whole-matrix product
+ * kernel; several: the batched one): blocked Cholesky factors, the positive-energy branch from the spectral projector
  * (I + sign(A + c^2 I)) / 2 of the reduced 4c matrix A by a scaled
  * Newton-Schulz iteration, X~ and Q^-1/2 together from one coupled
  * Newton-Schulz iteration on the projector's large-component block; matrix

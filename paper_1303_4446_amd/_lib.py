@@ -140,8 +140,8 @@ def max_n(twocomp: bool) -> int:
 
 
 def device_wide_min_n(twocomp: bool, n: int | None = None) -> int:
-    """Smallest block size N that takes the device-wide path (one block at a
-    time, whole-matrix products; no eigenvalues).  With n: set it (1 .. the
+    """Smallest block size N that takes the device-wide path (whole-matrix
+    products; no eigenvalues).  With n: set it (1 .. the
     batched limit + 1; 0 restores the default) and return the previous value;
     without: return the current value."""
     r = load().x2c_device_wide_min_n(TWOCOMP if twocomp else SPINFREE, -1 if n is None else int(n))
@@ -354,7 +354,11 @@ def dlu_assemble(T, V, W, Ns, u_off, X, R, c: float, twocomp: bool, workspace=No
 def build_batched(batch: Batch, c: float, prec: int = FP64, slices: int = 0, workspace=None, out=None,
                   stream=None, reduction: int = RED_QUATERNION, route: int = 0):
     """Enqueue x2c_build_batched.  Returns (h_flat, eps_flat, info) device
-    tensors (h_flat float64; complex blocks interleaved) and the workspace."""
+    tensors (h_flat float64; complex blocks interleaved) and the workspace.
+    route: ROUTE_SIZE (by block size), ROUTE_DEVICE_WIDE (every block on the
+    device-wide path, eps NaN) or ROUTE_AUTO (the faster path for the whole
+    batch when the eigenvalues are not needed; eps NaN where it took the
+    device-wide path)."""
     torch = _torch()
     lib = load()
     dev = batch.S.device

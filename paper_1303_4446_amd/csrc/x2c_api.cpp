@@ -29,7 +29,8 @@ namespace {
 // batched path (one work-group per block and column step)
 constexpr int MAX_N_2C = 256;   // 4c dimension 4N <= 1024
 constexpr int MAX_N_SF = 512;   // 4c dimension 2N <= 1024
-// device-wide path (one block at a time; products of the whole matrix)
+// device-wide path (matrix products of whole blocks, all such blocks of a
+// call together)
 constexpr int WIDE_MAX_N_2C = 4096;
 constexpr int WIDE_MAX_N_SF = 8192;
 // Newton-Schulz iterations of the device-wide path: step limits and the
