@@ -30,9 +30,10 @@
 // Hermitian (and so is beta C): only tiles reaching the lower triangle run,
 // and each lower element is mirrored.
 //
-// Tiling (gfx950): 256 threads = 4 waves; the work-group covers 128 rows of
-// A' x 64 columns; wave w owns rows 32w..32w+31 as two 32 x 32 MFMA blocks
-// (v_mfma_f32_32x32x16_bf16).  The FP64 tiles are split on the fly into LDS
+// Tiling (gfx950): 256 threads = 4 waves; the work-group covers 64 rows of
+// A' x 64 columns, each wave one 32 x 32 MFMA block (v_mfma_f32_32x32x16_bf16);
+// two work-groups fit a CU, so one stages its chunk while the other
+// multiplies.  The FP64 tiles are split on the fly into LDS
 // (all S slices of a 32-deep k chunk), so HBM traffic equals that of the
 // plain FP64 GEMM.
 #include "x2c_device.h"
@@ -43,7 +44,7 @@ namespace x2c {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float floatx16;
 
-constexpr int OZ_M = 128, OZ_N = 64, OZ_KC = 32, OZ_LD = OZ_KC + 8;
+constexpr int OZ_M = 64, OZ_N = 64, OZ_KC = 32, OZ_LD = OZ_KC + 8;
 constexpr int OZ_FLUSH = 4;     // k chunks between folds into FP64 (128 terms)
 
 // binary exponent of the largest |entry| of each row (rows = 1) or column of a
@@ -104,7 +105,7 @@ __device__ inline T from_comps(const double* v) {
 }
 
 template <class T, int S>
-__global__ void __launch_bounds__(256) k_gemm_split(const BlockDesc* D, char* ws, const int* info, int dsel,
+__global__ void __launch_bounds__(256, 2) k_gemm_split(const BlockDesc* D, char* ws, const int* info, int dsel,
                                                     int bufA, int opA, int bufB, int opB, int bufC, double alpha,
                                                     double beta, int herm, int bufEA, int bufEB) {
   constexpr int RF = ncomp<T>();            // real rows / k per element
@@ -127,19 +128,16 @@ __global__ void __launch_bounds__(256) k_gemm_split(const BlockDesc* D, char* ws
   __bf16* Bs = oz_sm + S * OZ_M * OZ_LD;       // S x OZ_N x OZ_LD
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int l32 = lane & 31, lhi = lane >> 5;
+  const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);   // this wave's 32 x 32 output block
 
-  floatx16 acc[S][2];
-  double acc64[2][16];
+  floatx16 acc[S];
+  double acc64[16];
 #pragma unroll
   for (int g = 0; g < S; ++g)
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int j = 0; j < 16; ++j) acc[g][j] = 0.0f;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) acc[g][h][j] = 0.0f;
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) acc64[h][j] = 0.0;
+  for (int j = 0; j < 16; ++j) acc64[j] = 0.0;
 
   // elements of op(A) per chunk: (OZ_M / RF) rows x (OZ_KC / RF) k
   constexpr int AR = OZ_M / RF, AK = OZ_KC / RF, BK = OZ_KC / RF;
@@ -196,18 +194,13 @@ __global__ void __launch_bounds__(256) k_gemm_split(const BlockDesc* D, char* ws
       bf16x8 af[S];
 #pragma unroll
       for (int s = 0; s < S; ++s)
-        af[s] = *reinterpret_cast<const bf16x8*>(As + (s * OZ_M + 32 * wave + l32) * OZ_LD + 16 * ks + 8 * lhi);
+        af[s] = *reinterpret_cast<const bf16x8*>(As + (s * OZ_M + wr + l32) * OZ_LD + 16 * ks + 8 * lhi);
 #pragma unroll
       for (int sb = 0; sb < S; ++sb) {
-        bf16x8 bf[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-          bf[h] = *reinterpret_cast<const bf16x8*>(Bs + (sb * OZ_N + 32 * h + l32) * OZ_LD + 16 * ks + 8 * lhi);
+        const bf16x8 bf = *reinterpret_cast<const bf16x8*>(Bs + (sb * OZ_N + wc + l32) * OZ_LD + 16 * ks + 8 * lhi);
 #pragma unroll
         for (int sa = 0; sa < S - sb; ++sa)
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            acc[sa + sb][h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[sa], bf[h], acc[sa + sb][h], 0, 0, 0);
+          acc[sa + sb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[sa], bf, acc[sa + sb], 0, 0, 0);
       }
     }
     __syncthreads();
@@ -217,29 +210,26 @@ __global__ void __launch_bounds__(256) k_gemm_split(const BlockDesc* D, char* ws
       for (int g = S - 1; g >= 0; --g) {
         const double w = ldexp(1.0, -7 * (g + 2));
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            acc64[h][j] = fma((double)acc[g][h][j], w, acc64[h][j]);
-            acc[g][h][j] = 0.0f;
-          }
+        for (int j = 0; j < 16; ++j) {
+          acc64[j] = fma((double)acc[g][j], w, acc64[j]);
+          acc[g][j] = 0.0f;
+        }
       }
     }
   }
   // ---- epilogue: undo the exponents, C = alpha P + beta C (real alpha, beta)
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int col = n0 + 32 * h + l32;
-    if (col >= n) continue;
+  {
+    const int col = n0 + wc + l32;
+    if (col >= n) return;
 #pragma unroll
     for (int j = 0; j < 16; j += RF) {
-      const int rr = m0 + 32 * wave + 8 * (j / 4) + 4 * lhi + (j % 4);   // row of A'
+      const int rr = m0 + wr + 8 * (j / 4) + 4 * lhi + (j % 4);   // row of A'
       const int i = rr / RF;
       if (i >= n || (herm && col > i)) continue;
       const double sc = ldexp(1.0, ea[i] + eb[col]);
       double vals[RF];
 #pragma unroll
-      for (int c = 0; c < RF; ++c) vals[c] = acc64[h][j + c] * sc;
+      for (int c = 0; c < RF; ++c) vals[c] = acc64[j + c] * sc;
       const long long idx = (long long)i * n + col;
       T v = alpha * from_comps<T>(vals);
       if (beta != 0.0) v = v + beta * C[idx];

@@ -34,7 +34,7 @@ typedef __attribute__((ext_vector_type(4))) int i4;
 typedef __attribute__((ext_vector_type(16))) int i16;
 
 constexpr int Q8_KC = 64;                  // k chunk (bytes of a slice row)
-constexpr int Q8_M = 128, Q8_N = 64;       // rows of A' x columns per work-group
+constexpr int Q8_M = 64, Q8_N = 64;        // rows of A' x columns per work-group (2 x 2 waves of 32 x 32)
 constexpr int Q8_LD = Q8_KC + 16;          // LDS row stride in bytes
 
 __host__ __device__ inline int kpad64(int n) { return (n + 63) / 64 * 64; }
@@ -100,7 +100,7 @@ __device__ inline T from_comps_i8(const double* v) {
 }
 
 template <class T, int S>
-__global__ void __launch_bounds__(256) k_gemm_i8(const BlockDesc* D, char* ws, const int* info, int dsel, int bufC,
+__global__ void __launch_bounds__(256, 2) k_gemm_i8(const BlockDesc* D, char* ws, const int* info, int dsel, int bufC,
                                                  double alpha, double beta, int herm, int bufSA, int bufSB, int bufEA,
                                                  int bufEB) {
   constexpr int RF = ncomp<T>();
@@ -125,14 +125,13 @@ __global__ void __launch_bounds__(256) k_gemm_i8(const BlockDesc* D, char* ws, c
   signed char* Bs = q8_sm + S * Q8_M * Q8_LD;           // S x Q8_N x Q8_LD
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int l32 = lane & 31, lhi = lane >> 5;
+  const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);   // this wave's 32 x 32 output block
 
-  i16 acc[S][2];
+  i16 acc[S];
 #pragma unroll
   for (int g = 0; g < S; ++g)
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) acc[g][h][j] = 0;
+    for (int j = 0; j < 16; ++j) acc[g][j] = 0;
 
   const int nk = RF * kp / Q8_KC;            // chunks over the RF-part K axis
   for (int ch = 0; ch < nk; ++ch) {
@@ -175,38 +174,32 @@ __global__ void __launch_bounds__(256) k_gemm_i8(const BlockDesc* D, char* ws, c
       i4 af[S];
 #pragma unroll
       for (int s = 0; s < S; ++s)
-        af[s] = *reinterpret_cast<const i4*>(As + (s * Q8_M + 32 * wave + l32) * Q8_LD + 32 * ks + 16 * lhi);
+        af[s] = *reinterpret_cast<const i4*>(As + (s * Q8_M + wr + l32) * Q8_LD + 32 * ks + 16 * lhi);
 #pragma unroll
       for (int sb = 0; sb < S; ++sb) {
-        i4 bf[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-          bf[h] = *reinterpret_cast<const i4*>(Bs + (sb * Q8_N + 32 * h + l32) * Q8_LD + 32 * ks + 16 * lhi);
+        const i4 bf = *reinterpret_cast<const i4*>(Bs + (sb * Q8_N + wc + l32) * Q8_LD + 32 * ks + 16 * lhi);
 #pragma unroll
         for (int sa = 0; sa < S - sb; ++sa)
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            acc[sa + sb][h] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[sa], bf[h], acc[sa + sb][h], 0, 0, 0);
+          acc[sa + sb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[sa], bf, acc[sa + sb], 0, 0, 0);
       }
     }
     __syncthreads();
   }
   // ---- fold the exact group sums into FP64 (smallest weights first) and store
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int col = n0 + 32 * h + l32;
+  {
+    const int col = n0 + wc + l32;
     double a64[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       double sacc = 0.0;
 #pragma unroll
-      for (int g = S - 1; g >= 0; --g) sacc = fma((double)acc[g][h][j], ldexp(1.0, -7 * (g + 2)), sacc);
+      for (int g = S - 1; g >= 0; --g) sacc = fma((double)acc[g][j], ldexp(1.0, -7 * (g + 2)), sacc);
       a64[j] = sacc;
     }
-    if (col >= n) continue;
+    if (col >= n) return;
 #pragma unroll
     for (int j = 0; j < 16; j += RF) {
-      const int rr = m0 + 32 * wave + 8 * (j / 4) + 4 * lhi + (j % 4);
+      const int rr = m0 + wr + 8 * (j / 4) + 4 * lhi + (j % 4);
       const int i = rr / RF;
       if (i >= n || (herm && col > i)) continue;
       const double sc = ldexp(1.0, ea[i] + eb[col]);
