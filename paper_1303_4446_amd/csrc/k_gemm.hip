@@ -244,44 +244,51 @@ k_gemm_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, i
 // the real multiply-adds of the complex 2N x 2N product.  Operands are staged
 // in LDS as four component planes; each wave runs 2 x 2 blocks of 16 x 16
 // quaternions, 16 MFMAs per block and k step of 4.  alpha, beta are real.
+//
+// TS = 64: 64 x 64 output tiles, each wave 2 x 2 blocks of 16 x 16; TS = 32
+// (for launches with few tiles): 32 x 32 tiles, one block per wave, four
+// times the work-groups.  The k order of every output element is the same
+// in both, so are the results.
+template <int TS>
 __global__ void __launch_bounds__(256, 2)
 k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA, int opA, int bufB, int opB,
               int bufC, double alpha, double beta, int herm) {
+  constexpr int XB = TS / 32;                 // 16 x 16 blocks per wave and dimension
   const int b = blockIdx.z;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int n = seldim(d, dsel);
-  const int m0 = blockIdx.y * GM_T, n0 = blockIdx.x * GM_T;
+  const int m0 = blockIdx.y * TS, n0 = blockIdx.x * TS;
   if (m0 >= n || n0 >= n) return;
   if (herm && blockIdx.x > blockIdx.y) return;
   const quat* A = bufp<quat>(ws, d, bufA);
   const quat* B = bufp<quat>(ws, d, bufB);
   quat* C = bufp<quat>(ws, d, bufC);
-  __shared__ double As[4][GM_T][GM_LD];      // [component][row][k]
-  __shared__ double Bs[4][GM_K][GM_T + 1];   // [component][k][col]
+  __shared__ double As[4][TS][GM_LD];      // [component][row][k]
+  __shared__ double Bs[4][GM_K][TS + 1];   // [component][k][col]
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int wr = (wave >> 1) * 16 * XB, wc = (wave & 1) * 16 * XB;
   const int l16 = lane & 15, l4 = lane >> 4;
-  d4 acc[2][2][4];
+  d4 acc[XB][XB][4];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < XB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < XB; ++y)
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[x][y][c] = d4{0.0, 0.0, 0.0, 0.0};
-  constexpr int NL = GM_T * GM_K / 256;
+  constexpr int NL = TS * GM_K / 256;
   quat na[NL], nb[NL];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
       const int l = t + 256 * q;
       int r, kk;
-      if (opA == 0) { r = l / GM_K; kk = l % GM_K; } else { kk = l / GM_T; r = l % GM_T; }
+      if (opA == 0) { r = l / GM_K; kk = l % GM_K; } else { kk = l / TS; r = l % TS; }
       const int gr = m0 + r, gk = k0 + kk;
       na[q] = (gr < n && gk < n) ? (opA == 0 ? A[(long long)gr * n + gk] : conjg(A[(long long)gk * n + gr]))
                                  : tzero<quat>();
       int cc;
-      if (opB == 0) { kk = l / GM_T; cc = l % GM_T; } else { cc = l / GM_K; kk = l % GM_K; }
+      if (opB == 0) { kk = l / TS; cc = l % TS; } else { cc = l / GM_K; kk = l % GM_K; }
       const int gk2 = k0 + kk, gc = n0 + cc;
       nb[q] = (gk2 < n && gc < n) ? (opB == 0 ? B[(long long)gk2 * n + gc] : conjg(B[(long long)gc * n + gk2]))
                                   : tzero<quat>();
@@ -292,13 +299,13 @@ k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
     for (int q = 0; q < NL; ++q) {
       const int l = t + 256 * q;
       int r, kk;
-      if (opA == 0) { r = l / GM_K; kk = l % GM_K; } else { kk = l / GM_T; r = l % GM_T; }
+      if (opA == 0) { r = l / GM_K; kk = l % GM_K; } else { kk = l / TS; r = l % TS; }
       As[0][r][kk] = na[q].a.x;
       As[1][r][kk] = na[q].a.y;
       As[2][r][kk] = na[q].b.x;
       As[3][r][kk] = na[q].b.y;
       int cc;
-      if (opB == 0) { kk = l / GM_T; cc = l % GM_T; } else { cc = l / GM_K; kk = l % GM_K; }
+      if (opB == 0) { kk = l / TS; cc = l % TS; } else { cc = l / GM_K; kk = l % GM_K; }
       Bs[0][kk][cc] = nb[q].a.x;
       Bs[1][kk][cc] = nb[q].a.y;
       Bs[2][kk][cc] = nb[q].b.x;
@@ -314,9 +321,9 @@ k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < GM_K; ks += 4) {
-      double a[2][4], bq[2][4];
+      double a[XB][4], bq[XB][4];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < XB; ++x)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           a[x][c] = As[c][wr + 16 * x + l16][ks + l4];
@@ -325,9 +332,9 @@ k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
 #pragma unroll
       for (int dd = 0; dd < 4; ++dd)
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < XB; ++x)
 #pragma unroll
-          for (int y = 0; y < 2; ++y)
+          for (int y = 0; y < XB; ++y)
 #pragma unroll
             for (int c = 0; c < 4; ++c)
               acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
@@ -335,9 +342,9 @@ k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
     }
   }
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < XB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < XB; ++y)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = m0 + wr + 16 * x + l4 + 4 * i, cc = n0 + wc + 16 * y + l16;
@@ -354,8 +361,16 @@ k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
 
 void launch_gemm_q(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                    int bufA, int opA, int bufB, int opB, int bufC, double alpha, double beta, int herm) {
-  int t = (maxdim + GM_T - 1) / GM_T;
-  hipLaunchKernelGGL(k_gemm_q_mfma, dim3(t, t, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA, opA, bufB, opB,
+  const int t = (maxdim + GM_T - 1) / GM_T;
+  // fewer 64 x 64 tiles than two resident work-groups per CU: 32 x 32 tiles
+  const long long tiles = (long long)nblk * (herm ? t * (t + 1) / 2 : t * t);
+  if (tiles < 2 * 256) {
+    const int t2 = (maxdim + 31) / 32;
+    hipLaunchKernelGGL(k_gemm_q_mfma<32>, dim3(t2, t2, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA, opA, bufB,
+                       opB, bufC, alpha, beta, herm);
+    return;
+  }
+  hipLaunchKernelGGL(k_gemm_q_mfma<64>, dim3(t, t, nblk), dim3(256), 0, s, D, ws, info, dsel, bufA, opA, bufB, opB,
                      bufC, alpha, beta, herm);
 }
 

@@ -719,13 +719,19 @@ void launch_gemm_q_big(hipStream_t s, const BlockDesc* D, char* ws, const int* g
 
 // ---------------------------------------------------------------- host side
 namespace {
-// products of the iterations: one block on the whole-matrix kernel, several
-// blocks on the batched one (the gate array in place of the block status)
+// products of the iterations: a large single block on the whole-matrix
+// kernel, anything else on the batched one (the gate array in place of the
+// block status)
 template <class T>
 void gemm(hipStream_t s, const BlockDesc* D, char* ws, const int* gate, int nblk, int maxdim, int dsel, int A, int B,
           int C, int herm) {
   if constexpr (is_quat<T>()) {
-    if (nblk == 1) launch_gemm_q_big(s, D, ws, gate, maxdim, dsel, A, B, C, 0.0, herm);
+    // the whole-matrix kernel for one block large enough to fill the GPU
+    // with its tiles (64 x 64 tiles: at least two per CU); else the batched
+    // kernel, which takes 32 x 32 tiles when there are few
+    const int t = (maxdim + 63) / 64;
+    if (nblk == 1 && (herm ? t * (t + 1) / 2 : t * t) >= 2 * 256)
+      launch_gemm_q_big(s, D, ws, gate, maxdim, dsel, A, B, C, 0.0, herm);
     else launch_gemm_q(s, D, ws, gate, nblk, maxdim, dsel, A, 0, B, 0, C, 1.0, 0.0, herm);
   } else {
     launch_gemm<T>(s, D, ws, gate, nblk, maxdim, dsel, A, 0, B, 0, C, treal<T>(1.0), tzero<T>(), herm, 0);

@@ -181,6 +181,18 @@ def test_mixed_512_block_batch_sampled():
                 check_against_oracle(blk.S, blk.T, blk.V, W, C_LIGHT, twocomp, hs[first], eps[first])
 
 
+def test_block_results_do_not_depend_on_the_batch():
+    """One silver block alone and the same block inside the 309-block batch:
+    the same bits (the batch changes the launch shapes: stream parts, matvec
+    grid, and 32 x 32 instead of 64 x 64 product tiles for the lone block,
+    but no block's arithmetic)."""
+    blocks = ag309_dlu(0)
+    hs, eps, info = gpu_batched(blocks, True)
+    h1, e1, i1 = gpu_batched([blocks[7]], True)
+    assert np.all(info == 0) and np.all(i1 == 0)
+    assert np.array_equal(h1[0], hs[7]) and np.array_equal(e1[0], eps[7])
+
+
 def test_ag309_full_batch_sampled():
     """The Ag309-like batch at full size in the benchmark's launch: every
     block satisfies the size-independent properties; a seeded sample of
