@@ -132,8 +132,8 @@ def test_mixed_batch_device_wide_and_batched_blocks():
         check_h(b.S, b.T, b.V, b.W, C_LIGHT, True, hs[i])
 
 
-@pytest.mark.parametrize("twocomp", [True, False])
-def test_many_blocks_device_wide_in_one_launch_sequence(twocomp):
+@pytest.mark.parametrize("twocomp,reduction", [(True, 0), (False, 0), (True, 1)])
+def test_many_blocks_device_wide_in_one_launch_sequence(twocomp, reduction):
     """Every block of a batch of thirteen atoms (seven sizes, in no order)
     forced onto the device-wide path: the blocks run together, each kernel
     covering all of them up to the largest; each block against the oracle."""
@@ -142,8 +142,8 @@ def test_many_blocks_device_wide_in_one_launch_sequence(twocomp):
     blocks = [atom_block(z) for z in zs]
     with device_wide_from(twocomp, 1):
         bt = px.batch_to_device(pack_blocks(blocks, twocomp), twocomp)
-        print(f"  device-wide batch twocomp={twocomp} N={list(bt.Ns)}", flush=True)
-        (h, eps, info), _ = px.build_batched(bt, C_LIGHT)
+        print(f"  device-wide batch twocomp={twocomp} reduction={reduction} N={list(bt.Ns)}", flush=True)
+        (h, eps, info), _ = px.build_batched(bt, C_LIGHT, reduction=reduction)
         torch.cuda.synchronize()
     assert np.all(info.cpu().numpy() == 0)
     assert np.all(np.isnan(eps.cpu().numpy()))
@@ -236,6 +236,26 @@ def test_spin_free_molecule_above_batched_limit():
     h, eps = gpu_single(mol.S, mol.T, mol.V, W0, C_LIGHT, False)
     assert np.all(np.isnan(eps))
     check_h(mol.S, mol.T, mol.V, W0, C_LIGHT, False, h, strict_bound=True)
+
+
+def test_molecule_and_atoms_device_wide_in_one_batch():
+    """A block above the batched limit (three coupled silver atoms, N = 576)
+    and two atoms (N = 24, 123) on the device-wide path in one call (the
+    route option puts the atoms there): each kernel covers all three, the
+    atoms' tiles stop at their own sizes; every block against the oracle."""
+    px, torch = _px()
+    from x2c_inputs.configs import AtomBlock
+    mol = coupled_molecule([ag_2c() for _ in range(3)], 0)
+    blocks = [atom_block(1), AtomBlock(47, mol.S, mol.T, mol.V, mol.W), atom_block(47)]
+    bt = px.batch_to_device(pack_blocks(blocks, True), True)
+    print(f"  device-wide batch N={list(bt.Ns)} (route device-wide)", flush=True)
+    (h, eps, info), _ = px.build_batched(bt, C_LIGHT, route=px.ROUTE_DEVICE_WIDE)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    assert bool(torch.isnan(eps).all())
+    hs = px.unpack_h(h.cpu().numpy(), bt.Ns, True)
+    for i, b in enumerate(blocks):
+        check_h(b.S, b.T, b.V, b.W, C_LIGHT, True, hs[i], strict_bound=(i == 1))
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="Ag13 reference not generated")
