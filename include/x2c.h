@@ -82,7 +82,10 @@ typedef enum { X2C_RED_QUATERNION = 0, X2C_RED_COMPLEX = 1 } x2c_reduction;
  * sum over those blocks of N_b^1.5 below 1.7e5 (two-component, quaternion
  * reduction; half that with the complex one) or 1.4e6 (spin-free), where the
  * two paths' times cross for uniform batches of atomic blocks in FP64 on
- * MI355X.  eps of a block is NaN whenever it took the device-wide path.
+ * MI355X; x2c_autotune with this route measures the choice for a batch
+ * class instead, and later calls of the class follow the measurement.
+ * x2c_workspace_bytes with this route covers either path.  eps of a block is
+ * NaN whenever it took the device-wide path.
  * BSS and DKHn (batched path only) ignore the route; the no-allocation entry
  * point accepts X2C_ROUTE_SIZE only. */
 typedef enum { X2C_ROUTE_SIZE = 0, X2C_ROUTE_DEVICE_WIDE = 1, X2C_ROUTE_AUTO = 2 } x2c_route;
@@ -415,7 +418,10 @@ int x2c_tuned_shape(const x2c_options* opts, int nblk, const int* N, int* ways_o
  * shape is also appended to a cache file keyed by the GPU architecture and
  * the batch class (X2C_TUNE_CACHE if set, an empty value disabling it; else
  * $XDG_CACHE_HOME/libx2c/tune_v1.txt or ~/.cache/libx2c/tune_v1.txt), from
- * which later processes take it.  All
+ * which later processes take it.  With X2C_ROUTE_AUTO the shapes are
+ * searched on the size route and the device-wide route is then timed
+ * against the best of them; the faster route is kept (and cached) for the
+ * class, and the outputs written are those of that route.  All launch-shape
  * candidates give identical results.  Blocking: synchronises `stream` once
  * per candidate.  Returns X2C_OK, X2C_EINVAL (arguments as for
  * x2c_build_batched; reps outside 1..100) or X2C_EHIP, in which case the

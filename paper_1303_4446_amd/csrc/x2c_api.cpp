@@ -178,6 +178,20 @@ bool auto_device_wide(const x2c_options* o, int nblk, const int* N, int wf) {
   return w < lim;
 }
 
+// the choice x2c_autotune measured for this batch class under
+// X2C_ROUTE_AUTO, if any (defined with the launch-shape cache)
+bool route_tuned(const x2c_options* o, int nblk, const int* N, bool* device_wide);
+
+// The route a call takes: X2C_ROUTE_AUTO resolves to the measured choice for
+// its batch class, else to the cost estimate above.  BSS and DKHn (fw >= 0)
+// keep the batched path.
+int effective_route(const x2c_options* o, int nblk, const int* N, int fw) {
+  if (fw >= 0 || o->route != X2C_ROUTE_AUTO) return o->route;
+  bool dw = false;
+  if (!route_tuned(o, nblk, N, &dw)) dw = auto_device_wide(o, nblk, N, wide_from(o->mode));
+  return dw ? X2C_ROUTE_DEVICE_WIDE : X2C_ROUTE_SIZE;
+}
+
 // Descriptor of one block whose buffers start at workspace byte `off`;
 // returns the end of its region.
 size_t place_block(int N, bool tc, int64_t in_off, int64_t h_off, int64_t eps_off, size_t off, BlockDesc& d,
@@ -205,8 +219,7 @@ bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in
   // BSS and DKHn run on the batched path only
   const int mx = fw >= 0 ? small_max_n(o->mode) : max_n(o->mode);
   int wf = fw >= 0 ? mx + 1 : wide_from(o->mode);
-  if (fw < 0 && (o->route == X2C_ROUTE_DEVICE_WIDE || (o->route == X2C_ROUTE_AUTO && auto_device_wide(o, nblk, N, wf))))
-    wf = 1;
+  if (fw < 0 && effective_route(o, nblk, N, fw) == X2C_ROUTE_DEVICE_WIDE) wf = 1;
   L.info_off = 0;
   L.gate_off = align_up((size_t)nblk * sizeof(int));
   L.desc_off = align_up(L.gate_off + (size_t)nblk * sizeof(int));
@@ -244,8 +257,12 @@ bool make_layout(const x2c_options* o, int nblk, const int* N, const int64_t* in
 std::mutex g_mu;
 std::map<std::vector<int64_t>, std::shared_ptr<Layout>> g_plans;
 
-std::shared_ptr<Layout> get_plan(const x2c_options* o, int nblk, const int* N, const int64_t* in_off,
+std::shared_ptr<Layout> get_plan(const x2c_options* o_in, int nblk, const int* N, const int64_t* in_off,
                                  const int64_t* h_off, const int64_t* eps_off, int fw = -1) {
+  // the automatic route resolved once, so that the key and the layout agree
+  x2c_options oe = *o_in;
+  oe.route = effective_route(o_in, nblk, N, fw);
+  const x2c_options* o = &oe;
   std::vector<int64_t> key;
   key.reserve(4 * (size_t)nblk + 5);
   key.push_back(o->mode);
@@ -1038,6 +1055,18 @@ uint64_t key_hash(const std::vector<int64_t>& k) {
 
 bool g_file_loaded = false;
 std::map<std::pair<std::string, uint64_t>, Tune> g_file_tunes;   // guarded by g_smu
+// route choices under X2C_ROUTE_AUTO (1 = device-wide), in memory and from
+// the file (lines with 0 streams); guarded by g_smu
+std::map<std::vector<int64_t>, int> g_route_tunes;
+std::map<std::pair<std::string, uint64_t>, int> g_file_routes;
+
+std::vector<int64_t> route_key(const x2c_options* o, int nblk, const int* N) {
+  std::vector<int64_t> k = {-7, o->mode, o->prec, o->ozaki_slices, o->reduction};
+  std::vector<int> ns(N, N + nblk);
+  std::stable_sort(ns.begin(), ns.end(), [](int a, int b) { return a > b; });
+  for (int n : ns) k.push_back(n);
+  return k;
+}
 
 void load_tune_file() {
   g_file_loaded = true;
@@ -1048,8 +1077,10 @@ void load_tune_file() {
   char arch[64];
   unsigned long long h = 0;
   int ways = 0, res = 0;
-  while (std::fscanf(f, "%63s %llx %d %d", arch, &h, &ways, &res) == 4)
+  while (std::fscanf(f, "%63s %llx %d %d", arch, &h, &ways, &res) == 4) {
     if (ways >= 1 && ways <= 4 && (res == 4 || res == 8)) g_file_tunes[{arch, (uint64_t)h}] = Tune{ways, res};
+    if (ways == 0 && (res == 0 || res == 1)) g_file_routes[{arch, (uint64_t)h}] = res;
+  }
   std::fclose(f);
 }
 
@@ -1068,6 +1099,35 @@ void save_tune(const std::vector<int64_t>& key, Tune t) {
   std::fprintf(f, "%s %llx %d %d\n", arch.c_str(), (unsigned long long)key_hash(key), t.ways, t.mv_res);
   std::fclose(f);
   g_file_tunes[{arch, key_hash(key)}] = t;
+}
+
+void save_route(const std::vector<int64_t>& key, int dw) {
+  const std::string path = tune_cache_path();
+  g_route_tunes[key] = dw;
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  const std::string arch = device_arch();
+  std::fprintf(f, "%s %llx 0 %d\n", arch.c_str(), (unsigned long long)key_hash(key), dw);
+  std::fclose(f);
+  g_file_routes[{arch, key_hash(key)}] = dw;
+}
+
+bool route_tuned(const x2c_options* o, int nblk, const int* N, bool* device_wide) {
+  const std::vector<int64_t> key = route_key(o, nblk, N);
+  std::lock_guard<std::mutex> lk(g_smu);
+  auto it = g_route_tunes.find(key);
+  if (it != g_route_tunes.end()) {
+    *device_wide = it->second != 0;
+    return true;
+  }
+  if (!g_file_loaded) load_tune_file();
+  if (g_file_routes.empty()) return false;
+  auto jt = g_file_routes.find({device_arch(), key_hash(key)});
+  if (jt == g_file_routes.end()) return false;
+  g_route_tunes[key] = jt->second;
+  *device_wide = jt->second != 0;
+  return true;
 }
 
 // caller holds g_smu; the in-memory shape, else the persisted one, else the
@@ -1506,6 +1566,18 @@ int x2c_device_wide_min_n(int mode, int n) {
 
 size_t x2c_workspace_bytes(const x2c_options* opts, int nblk, const int* N) {
   if (!valid_opts(opts)) return 0;
+  if (opts->route == X2C_ROUTE_AUTO) {
+    // either path, whichever the estimate or a later x2c_autotune picks
+    size_t w = 0;
+    for (int r : {X2C_ROUTE_SIZE, X2C_ROUTE_DEVICE_WIDE}) {
+      x2c_options o = *opts;
+      o.route = r;
+      Layout L;
+      if (!make_layout(&o, nblk, N, nullptr, nullptr, nullptr, L)) return 0;
+      w = std::max(w, L.total);
+    }
+    return w;
+  }
   Layout L;
   if (!make_layout(opts, nblk, N, nullptr, nullptr, nullptr, L)) return 0;
   return L.total;
@@ -1706,6 +1778,8 @@ void x2c_release(void) {
     std::lock_guard<std::mutex> lk(g_smu);
     g_tunes.clear();
     g_file_tunes.clear();
+    g_route_tunes.clear();
+    g_file_routes.clear();
     g_file_loaded = false;
   }
   std::lock_guard<std::mutex> lk(g_tmu);
@@ -1714,13 +1788,19 @@ void x2c_release(void) {
   g_pool.clear();
 }
 
-int x2c_autotune(const x2c_options* opts, int nblk, const int* N, const int64_t* in_off, const double* S,
+int x2c_autotune(const x2c_options* opts_in, int nblk, const int* N, const int64_t* in_off, const double* S,
                  const double* T, const double* V, const double* W, const int64_t* h_off, void* h,
                  const int64_t* eps_off, double* eps, int* info, void* workspace, size_t ws_bytes, void* stream,
                  int reps, int* ways_out, int* mv_res_out) {
-  if (!valid_opts(opts) || nblk <= 0 || !N || !in_off || !h_off || !eps_off || !info || !S || !T || !V || !W ||
+  if (!valid_opts(opts_in) || nblk <= 0 || !N || !in_off || !h_off || !eps_off || !info || !S || !T || !V || !W ||
       !h || !eps || !workspace || reps < 1 || reps > 100)
     return X2C_EINVAL;
+  // X2C_ROUTE_AUTO: the launch shapes are searched on the size route, then
+  // the device-wide route is timed against the best of them
+  const bool auto_route = opts_in->route == X2C_ROUTE_AUTO;
+  x2c_options o_size = *opts_in;
+  if (auto_route) o_size.route = X2C_ROUTE_SIZE;
+  const x2c_options* opts = &o_size;
   std::shared_ptr<Layout> L = get_plan(opts, nblk, N, in_off, h_off, eps_off);
   if (!L) return X2C_EINVAL;
   if (ws_bytes < L->total) return X2C_EINVAL;
@@ -1781,6 +1861,33 @@ int x2c_autotune(const x2c_options* opts, int nblk, const int* N, const int64_t*
   } else {
     std::lock_guard<std::mutex> lk(g_smu);
     g_tunes.erase(key);
+  }
+  if (rc == X2C_OK && auto_route) {
+    x2c_options o_dw = *opts_in;
+    o_dw.route = X2C_ROUTE_DEVICE_WIDE;
+    std::shared_ptr<Layout> Ld = get_plan(&o_dw, nblk, N, in_off, h_off, eps_off);
+    float ms = 0.0f;
+    bool timed = false;
+    if (Ld && ws_bytes >= Ld->total) {
+      rc = enqueue(&o_dw, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, nullptr, nullptr, info, workspace,
+                   ws_bytes, s, nullptr);
+      if (rc == X2C_OK && hipEventRecord(e0, s) != hipSuccess) rc = X2C_EHIP;
+      for (int r = 0; r < reps && rc == X2C_OK; ++r)
+        rc = enqueue(&o_dw, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, nullptr, nullptr, info, workspace,
+                     ws_bytes, s, nullptr);
+      if (rc == X2C_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        rc = X2C_EHIP;
+      if (rc == X2C_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = X2C_EHIP;
+      timed = rc == X2C_OK;
+    }
+    if (timed) {
+      std::lock_guard<std::mutex> lk(g_smu);
+      save_route(route_key(opts_in, nblk, N), ms < best_ms ? 1 : 0);
+    }
+    // the outputs are those of the chosen route
+    if (rc == X2C_OK && !(timed && ms < best_ms))
+      rc = enqueue(opts, nblk, N, in_off, S, T, V, W, h_off, h, eps_off, eps, nullptr, nullptr, info, workspace,
+                   ws_bytes, s, nullptr);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -4,6 +4,7 @@
 // result; AddressSanitizer / UndefinedBehaviorSanitizer abort on a fault.
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <vector>
 
 #include "x2c.h"
@@ -85,8 +86,10 @@ int main() {
   std::vector<int> ag309(309, 192);
   CHECK(x2c_workspace_bytes(&badr, 1, ag) == 0);
   CHECK(x2c_workspace_bytes(&dw, 1, ag) != x2c_workspace_bytes(&o2, 1, ag));
-  CHECK(x2c_workspace_bytes(&au, 1, ag) == x2c_workspace_bytes(&dw, 1, ag));
-  CHECK(x2c_workspace_bytes(&au, 309, ag309.data()) == x2c_workspace_bytes(&o2, 309, ag309.data()));
+  CHECK(x2c_workspace_bytes(&au, 1, ag) ==
+        std::max(x2c_workspace_bytes(&dw, 1, ag), x2c_workspace_bytes(&o2, 1, ag)));
+  CHECK(x2c_workspace_bytes(&au, 309, ag309.data()) ==
+        std::max(x2c_workspace_bytes(&dw, 309, ag309.data()), x2c_workspace_bytes(&o2, 309, ag309.data())));
   CHECK(x2c_build_batched_noalloc(&dw, 1, one, off, &dummy, &dummy, &dummy, &dummy, off, &dummy, off, &dummy, info,
                                   nullptr) == X2C_EINVAL);
   std::printf("abi driver: %d failure(s)\n", fails);

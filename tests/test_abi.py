@@ -149,13 +149,14 @@ def test_device_wide_threshold_and_workspace():
     # (device-wide for a few silver blocks, batched for 309 of them)
     w_dw = px.workspace_bytes([192], twocomp=True, route=px.ROUTE_DEVICE_WIDE)
     assert w_dw != w_batched
-    assert px.workspace_bytes([192], twocomp=True, route=px.ROUTE_AUTO) == w_dw
-    assert (px.workspace_bytes([192] * 13, twocomp=True, route=px.ROUTE_AUTO)
-            == px.workspace_bytes([192] * 13, twocomp=True, route=px.ROUTE_DEVICE_WIDE))
-    assert (px.workspace_bytes([192] * 309, twocomp=True, route=px.ROUTE_AUTO)
-            == px.workspace_bytes([192] * 309, twocomp=True))
     with pytest.raises(px.X2CError):
         px.workspace_bytes([192], twocomp=True, route=3)
+    # the automatic route's workspace covers either path (whichever a later
+    # x2c_autotune measures faster)
+    for Ns in ([192], [192] * 13, [192] * 309, [24, 123, 200]):
+        w_auto = px.workspace_bytes(Ns, twocomp=True, route=px.ROUTE_AUTO)
+        assert w_auto == max(px.workspace_bytes(Ns, twocomp=True),
+                             px.workspace_bytes(Ns, twocomp=True, route=px.ROUTE_DEVICE_WIDE))
     # BSS, DKHn and the allocation-free entry stay on the batched path
     with pytest.raises(px.X2CError):
         px.bss_workspace_bytes([300], twocomp=True)

@@ -412,6 +412,39 @@ def test_autotune_persists_across_release(tmp_path, monkeypatch):
         px.release()
 
 
+def test_autotune_measures_the_automatic_route(tmp_path, monkeypatch):
+    """X2C_ROUTE_AUTO under x2c_autotune: the launch shapes are searched on
+    the size route, the device-wide route is timed against the best, and the
+    faster one is kept for the batch class and written to the cache file.
+    Four silver blocks: the device-wide path (about 6 ms against 37 on the
+    batched one) wins by far; the outputs written are that path's (eps NaN,
+    h as on the size route), and later calls of the class follow it."""
+    px, torch = _px()
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("X2C_TUNE_CACHE", str(cache))
+    px.release()
+    blocks = [ag_2c()] * 4
+    bt = px.batch_to_device(pack_blocks(blocks, True), True)
+    try:
+        (h0, e0, i0), _ = px.build_batched(bt, C_LIGHT)
+        print("  x2c_autotune nblk=4 reps=1, route auto", flush=True)
+        (ways, res), (h, eps, info), _ = px.autotune(bt, C_LIGHT, reps=1, route=px.ROUTE_AUTO)
+        torch.cuda.synchronize()
+        assert np.all(info.cpu().numpy() == 0)
+        assert bool(torch.isnan(eps).all()) and bool(torch.isfinite(e0).all())
+        ref = h0.cpu().numpy()
+        assert np.abs(h.cpu().numpy() - ref).max() <= TOL_H * np.abs(ref).max()
+        lines = [l.split() for l in cache.read_text().splitlines() if l.strip()]
+        assert any(l[2] == "0" and l[3] == "1" for l in lines)          # the route line: device-wide
+        px.release()                                                    # the file keeps the choice
+        (h2, eps2, info2), _ = px.build_batched(bt, C_LIGHT, route=px.ROUTE_AUTO)
+        torch.cuda.synchronize()
+        assert bool(torch.isnan(eps2).all())
+    finally:
+        torch.cuda.synchronize()
+        px.release()
+
+
 def test_uneven_batch_order_does_not_change_results():
     """Blocks are run in order of decreasing size internally; per-block
     outputs and info codes stay in the caller's order (a failing block among
