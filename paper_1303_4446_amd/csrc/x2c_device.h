@@ -208,7 +208,7 @@ constexpr int NS_PARTS = 4096;   // work-groups of an elementwise pass, at most
 struct NsPar {
   double sigma, rho, l;        // shift, scale, lower bound of the moduli
   unsigned long long rmax;     // largest row sum (bits of a non-negative double)
-  int gate, conv, iters, pad;
+  int conv, iters;              // converged flag, steps taken (the gates sit in the workspace head)
   // per-work-group partial sums of the last reduction (squares of the step
   // change, of the new iterate), summed in a fixed order: the iteration is
   // reproducible bit for bit
