@@ -99,24 +99,35 @@ def matvec_bytes(Ns, twocomp: bool, reduction: str) -> tuple[float, int]:
     triangle (diagonal included) of the trailing Hermitian matrix read once
     per column step; a launch covers every block at that step.  Element
     sizes: quaternion 32 B, complex 16 B, real 8 B.  Both reductions of a
-    block are counted (the 4c matrix and the renormalisation matrix)."""
+    block are counted (the 4c matrix and the renormalisation matrix).  A
+    quaternion reduction stops its matvec launches at the unblocked tail
+    (quaternion_tail_start), whose columns one kernel per block reduces."""
     Ns = np.asarray(Ns, dtype=np.int64)
-    if twocomp and reduction == "quaternion":
+    quatred = twocomp and reduction == "quaternion"
+    if quatred:
         dims = [(2 * Ns, 32), (Ns, 32)]
     elif twocomp:
         dims = [(4 * Ns, 16), (2 * Ns, 16)]
     else:
         dims = [(2 * Ns, 8), (Ns, 8)]
+    ncols = (lambda n: min(n - 1, quaternion_tail_start(n))) if quatred else (lambda n: n - 1)
     total, launches = 0.0, 0
     for d, es in dims:
         maxd = int(d.max())
         if not twocomp and maxd <= 96:
             continue                      # single work-group reduction, no matvec launches
-        launches += maxd - 1
+        launches += ncols(maxd)
         for dim in d:
-            L = np.arange(int(dim) - 1, 0, -1, dtype=np.float64)   # len = dim - k - 1
+            L = int(dim) - 1 - np.arange(ncols(int(dim)), dtype=np.float64)   # len = dim - k - 1
             total += float(np.sum(L * (L + 1) / 2.0)) * es
     return total, launches
+
+
+def quaternion_tail_start(n: int, tail_max: int = 64, panel: int = 16) -> int:
+    """First column of the unblocked tail of a quaternion reduction of
+    dimension n: the first panel boundary at or after n - 1 - tail_max."""
+    s = n - 1 - tail_max
+    return 0 if s <= 0 else -(-s // panel) * panel
 
 
 # the dominant kernel's source and the headers whose code it inlines

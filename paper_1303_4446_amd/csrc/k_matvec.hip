@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
   const int lead = mv_lead<quat>(k), off = k + 1 - lead;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const MvItem it = mv_decode(D, info, dsel, k, nblk, nsmax, rev ? total - 1 - item : item, ST, lead);
-    if (!it.valid) continue;
+    if (!it.valid || k >= tri_tail_start<quat>(it.n)) continue;   // the block's tail kernel takes over
     const BlockDesc& d = D[it.b];
     const quat* A = bufp<quat>(ws, d, bufA);
     const quat* vg = bufp<quat>(ws, d, bufV);

@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int n = seldim(d, dsel);
-  if (k0 >= n - 1) return;
+  if (k0 >= n - 1 || k0 >= tri_tail_start<T>(n)) return;
   const int kb = min(PW, n - 1 - k0);
   T* A = bufp<T>(ws, d, bufA);
   double* dd = bufp<double>(ws, d, bufD);
@@ -847,7 +847,7 @@ __global__ void __launch_bounds__(256, 2) k_tri_her2k_q_mfma(const BlockDesc* D,
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int n = seldim(d, dsel);
-  if (k0 >= n - 1) return;
+  if (k0 >= n - 1 || k0 >= tri_tail_start<quat>(n)) return;
   const int kb = min(PW, n - 1 - k0);
   const int c0 = k0 + kb;
   const int len = n - c0;
@@ -947,6 +947,78 @@ __global__ void __launch_bounds__(256, 2) k_tri_her2k_q_mfma(const BlockDesc* D,
       }
 }
 
+// ---------------------------------------------------------------- unblocked quaternion tail
+// Columns tri_tail_start(n) .. n - 2 of a quaternion reduction by one
+// work-group per block: the trailing matrix (at most TAIL_MAX + 1 rows, kept
+// current after the last panel's rank-2k update) is reduced one Householder
+// step at a time, H A H = A - v w^H - w v^H with w = tau A v - (tau / 2)
+// (v^H tau A v) v, the same reflectors and outputs (v below the sub-diagonal,
+// tau, the real diagonal, the quaternion sub-diagonal and its modulus) as
+// the blocked steps.  Row i of the matvec: four threads, columns j = q, q +
+// 4, ... (the upper part as conjugates of the lower).
+__global__ void __launch_bounds__(COLT) k_tri_tail_q(const BlockDesc* D, char* ws, const int* info, int dsel,
+                                                     int bufA, int bufD, int bufE, int bufTau, int bufV, int bufET) {
+  const int b = blockIdx.x;
+  const BlockDesc& d = D[b];
+  if (info[b]) return;
+  const int n = seldim(d, dsel);
+  const int kt = tri_tail_start<quat>(n);
+  if (kt > n - 2) return;
+  quat* A = bufp<quat>(ws, d, bufA);
+  double* dd = bufp<double>(ws, d, bufD);
+  double* ee = bufp<double>(ws, d, bufE);
+  quat* taus = bufp<quat>(ws, d, bufTau);
+  quat* vg = bufp<quat>(ws, d, bufV);
+  quat* et = bufp<quat>(ws, d, bufET);
+  const int tid = threadIdx.x;
+  __shared__ double red[32];
+  __shared__ quat sh_tau, sh_betaq;
+  __shared__ quat v[TAIL_MAX + 1], w[TAIL_MAX + 1];
+  for (int k = kt; k <= n - 2; ++k) {
+    const int len = n - k - 1, off = k + 1;
+    if (tid == 0) A[(long long)k * n + k] = treal<quat>(re(A[(long long)k * n + k]));
+    __syncthreads();
+    make_reflector_q(A, n, k, vg, &sh_tau, &sh_betaq, red);   // ends with a barrier
+    const quat tau = sh_tau;
+    if (tid == 0) {
+      dd[k] = re(A[(long long)k * n + k]);
+      taus[k] = tau;
+      ee[k] = sqrt(abs2(sh_betaq));
+      et[k] = sh_betaq;
+    }
+    for (int i = tid; i < len; i += COLT) v[i] = vg[i];
+    __syncthreads();
+    // y = A22 v, then y <- tau y
+    for (int i = tid / CTPR; i < len; i += COLT / CTPR) {   // the same i for the CTPR lanes of a group
+      const int q = tid % CTPR;
+      quat acc = tzero<quat>();
+      for (int j = q; j < len; j += CTPR) {
+        const quat a = j <= i ? A[(long long)(off + i) * n + off + j] : conjg(A[(long long)(off + j) * n + off + i]);
+        acc = mad(a, v[j], acc);
+      }
+      acc = group_allsum<CTPR>(acc);
+      if (q == 0) w[i] = tau * acc;
+    }
+    __syncthreads();
+    double dr = 0.0;
+    for (int i = tid; i < len; i += COLT) dr += re(conjg(w[i]) * v[i]);
+    dr = block_sum(dr, red);
+    const double alpha = -0.5 * re(tau) * dr;                 // y^H v is real
+    for (int i = tid; i < len; i += COLT) w[i] = w[i] + alpha * v[i];
+    __syncthreads();
+    // A22 -= v w^H + w v^H on and below the diagonal (diagonal kept real)
+    for (int e = tid; e < len * len; e += COLT) {
+      const int i = e / len, j = e % len;
+      if (j > i) continue;
+      const long long idx = (long long)(off + i) * n + off + j;
+      quat a = A[idx] - v[i] * conjg(w[j]) - w[i] * conjg(v[j]);
+      if (i == j) a = treal<quat>(re(a));
+      A[idx] = a;
+    }
+    __syncthreads();
+  }
+}
+
 // Blocked multi-kernel reduction over the batch; falls back to the
 // one-work-group reduction when every block is small.
 template <class T>
@@ -966,7 +1038,10 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
                       (int)shm);
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  for (int k0 = 0; k0 < maxdim - 1; k0 += PW) {
+  // the blocked panels up to the largest block's tail (smaller blocks stop
+  // at their own)
+  const int kend = std::min(maxdim - 1, tri_tail_start<T>(maxdim));
+  for (int k0 = 0; k0 < kend; k0 += PW) {
     const int kbmax = std::min(PW, maxdim - 1 - k0);
     hipLaunchKernelGGL(k_tri_col<T>, dim3(nblk), dim3(COLT), shm, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufW,
                        bufV, bufHS, bufET, k0, 0, 0);
@@ -995,6 +1070,9 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
       }
     }
   }
+  if constexpr (is_quat<T>())
+    hipLaunchKernelGGL(k_tri_tail_q, dim3(nblk), dim3(COLT), 0, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufV,
+                       bufET);
   hipLaunchKernelGGL(k_tri_last<T>, dim3((nblk + 255) / 256), dim3(256), 0, s, D, ws, info, nblk, dsel, bufA, bufD);
 }
 template void launch_hetrd_mk<double>(hipStream_t, const BlockDesc*, char*, const int*, int, int, int, int, int, int,

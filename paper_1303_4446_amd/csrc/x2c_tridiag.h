@@ -36,6 +36,22 @@ __host__ __device__ constexpr int panel_width() {
 }
 constexpr int HB = 32;   // the widest panel (buffer sizes)
 
+// First column of the unblocked tail of a quaternion reduction: the last
+// trailing matrices (at most TAIL_MAX columns) are reduced by one
+// work-group per block in one kernel instead of two launches per column; a
+// panel boundary, so the blocked part ends with a complete panel and its
+// rank-2k update.  Other types: no tail.
+constexpr int TAIL_MAX = 64;
+template <class T>
+__host__ __device__ constexpr int tri_tail_start(int n) {
+  if constexpr (is_quat<T>()) {
+    const int s = n - 1 - TAIL_MAX, pw = panel_width<T>();
+    return s <= 0 ? 0 : (s + pw - 1) / pw * pw;
+  } else {
+    return 1 << 30;
+  }
+}
+
 // Leading virtual rows / columns of the matvec tiling at column step k.  The
 // quaternion tiles start on a 128-byte boundary (4 quaternions): the trailing
 // matrix (first row / column k + 1) is preceded by (k + 1) mod 4 zero rows /

@@ -6,8 +6,12 @@ Tolerances: the same 2e-10 x max|h| as the per-block h for the assembled
 Hamiltonian (the assembly adds six FP64 products of the same operands).  The
 intermediate X = sqrt2 c L_T^-H (Y_S Y_L^-1) L_S^H carries the conditioning of
 L_T (kappa up to ~2e6 in these bases) times that of the positive-energy basis
-block Y_L (kappa ~ 10), so X and R are compared at u * 2e6 * 10 ~ 2e-9 of
-their largest entry (structurally zero entries included)."""
+block Y_L (kappa ~ 10): u * 2e6 * 10 ~ 2e-9 of their largest entry
+(structurally zero entries included), a first-order estimate without a
+constant.  The same blocks reduced in different rounding orders (the
+tridiagonal reduction with its unblocked tail at 16, 32, 64 and 128 columns)
+land between 0.1 and 4 times it, so X and R are held to ten times the
+estimate, 2e-8."""
 import numpy as np
 import pytest
 
@@ -18,7 +22,7 @@ from x2c_inputs import C_LIGHT as C, atom_block, coupled_molecule, pack_blocks, 
 pytestmark = pytest.mark.gpu
 
 TOL = 2e-10
-TOL_XR = 2e-9
+TOL_XR = 2e-8
 
 
 def _px():

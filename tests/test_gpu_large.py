@@ -378,8 +378,9 @@ def test_device_wide_reproducible_and_graph_replays_match_eager():
 
 def test_device_wide_x_r_outputs_and_picture_change():
     """x2c_build_batched_xr on a block above the batched limit (three coupled
-    silver atoms, N = 576): X and R against the oracle's (2e-9, the X and R
-    tolerance of the batched path), and the picture change of the nuclear
+    silver atoms, N = 576): X and R against the oracle's (2e-9, u times the
+    conditioning of the X formula; the Newton-Schulz route's rounding stays
+    below it), and the picture change of the nuclear
     attraction with the GPU's X and R, complex and quaternion products,
     against the oracle's formula with its own X and R."""
     px, torch = _px()

@@ -8,8 +8,8 @@ products in FP64 in another order; the results are compared at 1e-11 of
 their largest entry for a multiplicative operator (the nuclear attraction:
 P_LL = V, P_SS = W / 4c^2) and at 1e-10 for the Dirac matrix itself, whose
 P_SS = W/4c^2 - T cancels to about 1e-1 of its parts.  End to end, the GPU's
-own X and R (from x2c_build_batched_xr, accurate to 2e-9) must map the
-identity operator to the metric S (renormalisation, Eq. ulnonortho).
+own X and R (from x2c_build_batched_xr) must map the identity operator to
+the metric S (renormalisation, Eq. ulnonortho, which holds for any X: 2e-9).
 """
 import numpy as np
 import pytest
