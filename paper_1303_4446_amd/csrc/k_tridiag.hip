@@ -949,74 +949,88 @@ __global__ void __launch_bounds__(256, 2) k_tri_her2k_q_mfma(const BlockDesc* D,
 
 // ---------------------------------------------------------------- unblocked quaternion tail
 // Columns tri_tail_start(n) .. n - 2 of a quaternion reduction by one
-// work-group per block: the trailing matrix (at most TAIL_MAX + 1 rows, kept
-// current after the last panel's rank-2k update) is reduced one Householder
-// step at a time, H A H = A - v w^H - w v^H with w = tau A v - (tau / 2)
-// (v^H tau A v) v, the same reflectors and outputs (v below the sub-diagonal,
-// tau, the real diagonal, the quaternion sub-diagonal and its modulus) as
-// the blocked steps.  Row i of the matvec: four threads, columns j = q, q +
-// 4, ... (the upper part as conjugates of the lower).
+// work-group per block.  The trailing matrix (m = n - tri_tail_start(n) <=
+// TAIL_MAX + 1 rows, current after the last panel's rank-2k update) is read
+// once into LDS as a column-major packed lower triangle and reduced there
+// one Householder step at a time: H A H = A - v w^H - w v^H with
+// w = tau A v - (tau / 2)(v^H tau A v) v.  The outputs are those of the
+// blocked steps: the reflector (below the sub-diagonal of A's column k), tau,
+// the real diagonal (also written back to A's diagonal), the quaternion
+// sub-diagonal and its modulus.  Row i of the matvec: four threads, columns
+// j = q, q + 4, ... (the upper part as conjugates of the lower).
+constexpr int TAIL_LDS = (TAIL_MAX + 1) * (TAIL_MAX + 2) / 2;   // packed lower triangle
+
 __global__ void __launch_bounds__(COLT) k_tri_tail_q(const BlockDesc* D, char* ws, const int* info, int dsel,
-                                                     int bufA, int bufD, int bufE, int bufTau, int bufV, int bufET) {
+                                                     int bufA, int bufD, int bufE, int bufTau, int bufET) {
   const int b = blockIdx.x;
   const BlockDesc& d = D[b];
   if (info[b]) return;
   const int n = seldim(d, dsel);
   const int kt = tri_tail_start<quat>(n);
   if (kt > n - 2) return;
+  const int m = n - kt;
   quat* A = bufp<quat>(ws, d, bufA);
   double* dd = bufp<double>(ws, d, bufD);
   double* ee = bufp<double>(ws, d, bufE);
   quat* taus = bufp<quat>(ws, d, bufTau);
-  quat* vg = bufp<quat>(ws, d, bufV);
   quat* et = bufp<quat>(ws, d, bufET);
   const int tid = threadIdx.x;
+  __shared__ quat L[TAIL_LDS];
+  __shared__ quat v[TAIL_MAX + 1], w[TAIL_MAX + 1];
   __shared__ double red[32];
   __shared__ quat sh_tau, sh_betaq;
-  __shared__ quat v[TAIL_MAX + 1], w[TAIL_MAX + 1];
-  for (int k = kt; k <= n - 2; ++k) {
-    const int len = n - k - 1, off = k + 1;
-    if (tid == 0) A[(long long)k * n + k] = treal<quat>(re(A[(long long)k * n + k]));
-    __syncthreads();
-    make_reflector_q(A, n, k, vg, &sh_tau, &sh_betaq, red);   // ends with a barrier
+  // element (i, j), i >= j, of the trailing matrix
+  auto at = [m](int i, int j) { return j * m - j * (j - 1) / 2 + (i - j); };
+  for (int e = tid; e < m * m; e += COLT) {            // rows of A: coalesced
+    const int i = e / m, j = e - (e / m) * m;
+    if (j > i) continue;
+    const quat a = A[(long long)(kt + i) * n + kt + j];
+    L[at(i, j)] = i == j ? treal<quat>(re(a)) : a;
+  }
+  __syncthreads();
+  for (int c = 0; c <= m - 2; ++c) {
+    const int k = kt + c, len = m - c - 1;
+    make_reflector_q(A, n, k, v, &sh_tau, &sh_betaq, red, &L[at(c + 1, c)]);   // ends with a barrier
     const quat tau = sh_tau;
     if (tid == 0) {
-      dd[k] = re(A[(long long)k * n + k]);
+      const quat dg = L[at(c, c)];
+      A[(long long)k * n + k] = dg;
+      dd[k] = re(dg);
       taus[k] = tau;
       ee[k] = sqrt(abs2(sh_betaq));
       et[k] = sh_betaq;
     }
-    for (int i = tid; i < len; i += COLT) v[i] = vg[i];
-    __syncthreads();
-    // y = A22 v, then y <- tau y
-    for (int i = tid / CTPR; i < len; i += COLT / CTPR) {   // the same i for the CTPR lanes of a group
-      const int q = tid % CTPR;
+    // w = tau A22 v
+    for (int r = tid / CTPR; r < len; r += COLT / CTPR) {   // the same r for the CTPR lanes of a group
+      const int q = tid % CTPR, i = c + 1 + r;
       quat acc = tzero<quat>();
-      for (int j = q; j < len; j += CTPR) {
-        const quat a = j <= i ? A[(long long)(off + i) * n + off + j] : conjg(A[(long long)(off + j) * n + off + i]);
-        acc = mad(a, v[j], acc);
+      for (int t = q; t < len; t += CTPR) {
+        const int j = c + 1 + t;
+        const quat a = j <= i ? L[at(i, j)] : conjg(L[at(j, i)]);
+        acc = mad(a, v[t], acc);
       }
       acc = group_allsum<CTPR>(acc);
-      if (q == 0) w[i] = tau * acc;
+      if (q == 0) w[r] = tau * acc;
     }
     __syncthreads();
     double dr = 0.0;
-    for (int i = tid; i < len; i += COLT) dr += re(conjg(w[i]) * v[i]);
+    for (int r = tid; r < len; r += COLT) dr += re(conjg(w[r]) * v[r]);
     dr = block_sum(dr, red);
     const double alpha = -0.5 * re(tau) * dr;                 // y^H v is real
-    for (int i = tid; i < len; i += COLT) w[i] = w[i] + alpha * v[i];
+    for (int r = tid; r < len; r += COLT) w[r] = w[r] + alpha * v[r];
     __syncthreads();
     // A22 -= v w^H + w v^H on and below the diagonal (diagonal kept real)
     for (int e = tid; e < len * len; e += COLT) {
-      const int i = e / len, j = e % len;
-      if (j > i) continue;
-      const long long idx = (long long)(off + i) * n + off + j;
-      quat a = A[idx] - v[i] * conjg(w[j]) - w[i] * conjg(v[j]);
-      if (i == j) a = treal<quat>(re(a));
-      A[idx] = a;
+      const int r = e / len, t = e - (e / len) * len;
+      if (t > r) continue;
+      const int idx = at(c + 1 + r, c + 1 + t);
+      quat a = L[idx] - v[r] * conjg(w[t]) - w[r] * conjg(v[t]);
+      if (r == t) a = treal<quat>(re(a));
+      L[idx] = a;
     }
     __syncthreads();
   }
+  if (tid == 0) A[(long long)(n - 1) * n + n - 1] = L[at(m - 1, m - 1)];   // read by k_tri_last
 }
 
 // Blocked multi-kernel reduction over the batch; falls back to the
@@ -1071,7 +1085,7 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
     }
   }
   if constexpr (is_quat<T>())
-    hipLaunchKernelGGL(k_tri_tail_q, dim3(nblk), dim3(COLT), 0, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau, bufV,
+    hipLaunchKernelGGL(k_tri_tail_q, dim3(nblk), dim3(COLT), 0, s, D, ws, info, dsel, bufA, bufD, bufE, bufTau,
                        bufET);
   hipLaunchKernelGGL(k_tri_last<T>, dim3((nblk + 255) / 256), dim3(256), 0, s, D, ws, info, nblk, dsel, bufA, bufD);
 }
