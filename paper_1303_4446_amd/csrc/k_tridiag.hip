@@ -752,17 +752,24 @@ __global__ void __launch_bounds__(256) k_ormtr_q_mfma(const BlockDesc* D, char* 
 #pragma unroll
     for (int ob = 0; ob < 8; ++ob) w[ob] = qd4{0.0, 0.0, 0.0, 0.0};
     for (int rc = r0; rc < nr; rc += VRQ) {
-      __syncthreads();
-      for (int l = t; l < VRQ * ORB; l += 256) {
-        const int rr = l / ORB, a = l % ORB, r = rc + rr;
-        Vs[rr][a] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<quat>();
-      }
-      __syncthreads();
       const int rend = min(VRQ, nr - rc);
       double ybuf[VRQ];                     // B operands of the chunk: component l4 of Y[r][col]
 #pragma unroll
-      for (int rr = 0; rr < VRQ; ++rr)
+      for (int rr = 0; rr < VRQ; ++rr)      // in flight while the panel rows are staged
         ybuf[rr] = (cok && rr < rend) ? Y[((long long)(rc + rr) * nc + col) * 4 + l4] : 0.0;
+      quat vpre[VRQ * ORB / 256];           // the chunk's panel rows, loaded before the barrier
+#pragma unroll
+      for (int q = 0; q < VRQ * ORB / 256; ++q) {
+        const int l = t + 256 * q, rr = l / ORB, a = l % ORB, r = rc + rr;
+        vpre[q] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<quat>();
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < VRQ * ORB / 256; ++q) {
+        const int l = t + 256 * q;
+        Vs[l / ORB][l % ORB] = vpre[q];
+      }
+      __syncthreads();
 #pragma unroll
       for (int rr = 0; rr < VRQ; ++rr) {
         const double y = ybuf[rr];
@@ -793,14 +800,27 @@ __global__ void __launch_bounds__(256) k_ormtr_q_mfma(const BlockDesc* D, char* 
     }
     // ---- Y -= L(V) W, four quaternion rows per MFMA block
     for (int rc = r0; rc < nr; rc += VRQ) {
-      __syncthreads();
-      for (int l = t; l < VRQ * ORB; l += 256) {
-        const int rr = l / ORB, a = l % ORB, r = rc + rr;
-        Vs[rr][a] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<quat>();
+      const int rend = min(VRQ, nr - rc);
+      double yv[VRQ];                       // this lane's entries of the chunk, loaded before the products
+#pragma unroll
+      for (int rr = 0; rr < VRQ; ++rr)
+        yv[rr] = (cok && rr < rend) ? Y[((long long)(rc + rr) * nc + col) * 4 + l4] : 0.0;
+      quat vpre[VRQ * ORB / 256];           // the chunk's panel rows, loaded before the barrier
+#pragma unroll
+      for (int q = 0; q < VRQ * ORB / 256; ++q) {
+        const int l = t + 256 * q, rr = l / ORB, a = l % ORB, r = rc + rr;
+        vpre[q] = (r < nr && a < kb) ? panel_v(A, nr, k0, r, a) : tzero<quat>();
       }
       __syncthreads();
-      const int rend = min(VRQ, nr - rc);
-      for (int rb = 0; rb < rend; rb += 4) {
+#pragma unroll
+      for (int q = 0; q < VRQ * ORB / 256; ++q) {
+        const int l = t + 256 * q;
+        Vs[l / ORB][l % ORB] = vpre[q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int rb = 0; rb < VRQ; rb += 4) {
+        if (rb >= rend) break;
         qd4 acc = qd4{0.0, 0.0, 0.0, 0.0};
         const double* vrow = reinterpret_cast<const double*>(&Vs[rb + aq][0]);   // quaternion row rb + l16/4
 #pragma unroll
@@ -814,10 +834,7 @@ __global__ void __launch_bounds__(256) k_ormtr_q_mfma(const BlockDesc* D, char* 
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int r = rc + rb + i;
-            if (rb + i < rend) {
-              const long long idx = ((long long)r * nc + col) * 4 + l4;
-              Y[idx] = Y[idx] - acc[i];
-            }
+            if (rb + i < rend) Y[((long long)r * nc + col) * 4 + l4] = yv[rb + i] - acc[i];
           }
         }
       }
