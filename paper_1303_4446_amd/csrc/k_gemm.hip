@@ -314,9 +314,10 @@ k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
   };
   for (int k0 = 0; k0 < n; k0 += GM_K) {
     // two waves per SIMD instead of a register prefetch: the other
-    // work-group's matrix-core work covers this one's loads
-    __syncthreads();
+    // work-group's matrix-core work covers this one's loads, which go out
+    // before the barrier
     fetch(k0);
+    __syncthreads();
     stash();
     __syncthreads();
 #pragma unroll
@@ -472,9 +473,10 @@ k_gemm_qr_mfma(const BlockDesc* D, char* ws, const int* info, int bufR, int opR,
   };
   kbeg = (kbeg / GM_K) * GM_K;
   for (int k0 = kbeg; k0 < kend; k0 += GM_K) {
-    // two waves per SIMD instead of a register prefetch
-    __syncthreads();
+    // two waves per SIMD instead of a register prefetch (the loads go out
+    // before the barrier)
     fetch(k0);
+    __syncthreads();
     stash();
     __syncthreads();
 #pragma unroll

@@ -666,8 +666,8 @@ __global__ void __launch_bounds__(256, 2) k_gemm_q_big(const BlockDesc* D, char*
     }
   } else {
     for (int k0 = 0; k0 < n; k0 += BG_K) {
+      fetch(k0);          // in flight during the barrier
       __syncthreads();
-      fetch(k0);
       stash();
       __syncthreads();
       compute();

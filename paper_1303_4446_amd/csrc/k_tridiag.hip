@@ -923,9 +923,10 @@ __global__ void __launch_bounds__(256, 2) k_tri_her2k_q_mfma(const BlockDesc* D,
     }
   };
   for (int kc = 0; kc < 2 * PW; kc += HQ_K) {
-    // two waves per SIMD instead of a register prefetch
-    __syncthreads();
+    // two waves per SIMD instead of a register prefetch (the loads go out
+    // before the barrier)
     fetch(kc);
+    __syncthreads();
     stash();
     __syncthreads();
 #pragma unroll
