@@ -210,6 +210,31 @@ def test_ag309_full_batch_sampled():
         check_against_oracle(blk.S, blk.T, blk.V, blk.W, C_LIGHT, True, hs[i], eps[i], strict_bound=True)
 
 
+def test_quaternion_tail_boundaries():
+    """Two-component blocks whose quaternion reductions straddle the start of
+    the unblocked tail (the last at most 64 columns of a reduction, from a
+    panel boundary): 4c dimensions 2N = 64 (all tail), 66, 80, 82, 96, 98,
+    130, 132 and renormalisation dimensions N = 65 (all tail, the largest
+    tail) and 66, in one ragged batch (the panel loop runs to the largest
+    block's tail, smaller blocks stop at their own) and N = 65 alone; every
+    block against the oracle.  c = 7, as for the tiny random problems: the
+    random spectra (|eps| < 20) would otherwise sit four orders of magnitude
+    inside the norm of the 4c matrix (~2c^2), where the eigenvalue
+    tolerance, relative to max|eps|, does not apply."""
+    from x2c_inputs.configs import AtomBlock
+    c = 7.0
+    Ns = (32, 33, 40, 41, 48, 49, 65, 66)
+    blocks = [AtomBlock(0.0, *random_spd_problem(N, 100 + N, True)) for N in Ns]
+    hs, eps, info = gpu_batched(blocks, True, c=c)
+    assert np.all(info == 0)
+    for blk, h, e in zip(blocks, hs, eps):
+        print(f"  oracle check N={blk.N}", flush=True)
+        check_against_oracle(blk.S, blk.T, blk.V, blk.W, c, True, h, e)
+    blk = blocks[Ns.index(65)]
+    h, e = gpu_single(blk.S, blk.T, blk.V, blk.W, c, True)
+    assert np.array_equal(h, hs[Ns.index(65)])
+
+
 @pytest.mark.parametrize("N,seed", [(3, 2), (5, 4)])
 def test_tiny_random_complex_reduction(N, seed):
     S, T, V, W = random_spd_problem(N, seed, True)
