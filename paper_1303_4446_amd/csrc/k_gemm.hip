@@ -261,6 +261,7 @@ k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
   const int m0 = blockIdx.y * TS, n0 = blockIdx.x * TS;
   if (m0 >= n || n0 >= n) return;
   if (herm && blockIdx.x > blockIdx.y) return;
+  const bool dtile = herm && blockIdx.x == blockIdx.y;   // diagonal tile of a Hermitian output
   const quat* A = bufp<quat>(ws, d, bufA);
   const quat* B = bufp<quat>(ws, d, bufB);
   quat* C = bufp<quat>(ws, d, bufC);
@@ -336,10 +337,11 @@ k_gemm_q_mfma(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
         for (int x = 0; x < XB; ++x)
 #pragma unroll
           for (int y = 0; y < XB; ++y)
+            if (!(dtile && wc + 16 * y > wr + 16 * x))   // 16 x 16 blocks above the diagonal are not written
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-              acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                  qmul_sign(c, dd) > 0 ? a[x][c ^ dd] : -a[x][c ^ dd], bq[y][dd], acc[x][y][c], 0, 0, 0);
+              for (int c = 0; c < 4; ++c)
+                acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                    qmul_sign(c, dd) > 0 ? a[x][c ^ dd] : -a[x][c ^ dd], bq[y][dd], acc[x][y][c], 0, 0, 0);
     }
   }
 #pragma unroll

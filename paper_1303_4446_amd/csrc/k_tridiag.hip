@@ -945,10 +945,11 @@ __global__ void __launch_bounds__(256, 2) k_tri_her2k_q_mfma(const BlockDesc* D,
         for (int x = 0; x < 2; ++x)
 #pragma unroll
           for (int y = 0; y < 2; ++y)
+            if (!(I == J && wc + 16 * y > wr + 16 * x))   // 16 x 16 blocks above the diagonal are not written
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-              acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                  qmul_sign(c, dd) > 0 ? a[x][c ^ dd] : -a[x][c ^ dd], bq[y][dd], acc[x][y][c], 0, 0, 0);
+              for (int c = 0; c < 4; ++c)
+                acc[x][y][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                    qmul_sign(c, dd) > 0 ? a[x][c ^ dd] : -a[x][c ^ dd], bq[y][dd], acc[x][y][c], 0, 0, 0);
     }
   }
 #pragma unroll
