@@ -388,6 +388,28 @@ def cpu_baseline(blocks, twocomp, c, per_core, runs=3):
 
 # ---------------------------------------------------------------------------
 
+def copy_rate_gbps(torch, mib: int = 1024, reps: int = 5) -> float:
+    """Bytes moved (read + written) per second by a plain device-to-device
+    copy of a mib-MiB buffer, median of reps copies timed with events: the
+    HBM rate this part reaches in practice, beside the published peak."""
+    n = (mib << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / (float(np.median(ms)) / 1e3) / 1e9
+
+
 def time_steps(px, torch, batch, c, prec, red, stream, ws, out, steps):
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -735,11 +757,17 @@ def main():
         if args.workload == "ag309" and twocomp and args.reduction == "quaternion":
             traffic = recorded_traffic(MATVEC_SOURCES,
                                        "profiles/k_tri_matvec_w_ag309_traffic.md")
+        copy_gbs = copy_rate_gbps(torch)
         roofline = {"bound": "hbm", "kernel": "k_tri_matvec_w" if (twocomp and args.reduction == "quaternion")
                     else "k_tri_matvec", "achieved": achieved, "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                     "launch_us": avg_ms * 1e3, "bytes_per_launch": per_launch_b,
-                    "launches_per_step": mv[1] / args.steps, "share_of_step": mv[0] / args.steps / ms_step}
+                    "launches_per_step": mv[1] / args.steps, "share_of_step": mv[0] / args.steps / ms_step,
+                    # the memory level the operands come from: the measured HBM traffic per
+                    # launch over the launch time, against a plain 1 GiB copy of this run
+                    "copy_GBps": copy_gbs,
+                    "traffic_GBps": None if traffic is None else traffic / (avg_ms / 1e3) / 1e9,
+                    "traffic_frac_of_copy": None if traffic is None else traffic / (avg_ms / 1e3) / 1e9 / copy_gbs}
     extra = {}
     for st in ("tridiag_4c", "tridiag_Q", "backtransform_4c"):
         fl = [algorithmic_flops(st, int(N), twocomp, args.reduction) for N in batch.Ns]
