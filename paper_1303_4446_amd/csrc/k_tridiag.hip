@@ -1053,7 +1053,9 @@ __global__ void __launch_bounds__(COLT) k_tri_tail_q(const BlockDesc* D, char* w
 }
 
 // Blocked multi-kernel reduction over the batch; falls back to the
-// one-work-group reduction when every block is small.
+// one-work-group reduction when every real or complex block is small.  The
+// quaternion reductions run their panels up to tri_tail_start and finish in
+// k_tri_tail_q.
 template <class T>
 void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                      int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS, int bufET,
