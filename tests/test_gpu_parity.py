@@ -213,9 +213,10 @@ def test_ag309_full_batch_sampled():
 def test_quaternion_tail_boundaries():
     """Two-component blocks whose quaternion reductions straddle the start of
     the unblocked tail (the last at most 64 columns of a reduction, from a
-    panel boundary): 4c dimensions 2N = 64 (all tail), 66, 80, 82, 96, 98,
-    130, 132 and renormalisation dimensions N = 65 (all tail, the largest
-    tail) and 66, in one ragged batch (the panel loop runs to the largest
+    panel boundary): 4c dimensions 2N = 2 and 4 (one and three tail steps),
+    64 (all tail), 66, 80, 82, 96, 98, 130, 132 and renormalisation
+    dimensions N = 1, 2, 65 (all tail, the largest tail) and 66, in one
+    ragged batch (the panel loop runs to the largest
     block's tail, smaller blocks stop at their own) and N = 65 alone; every
     block against the oracle.  c = 7, as for the tiny random problems: the
     random spectra (|eps| < 20) would otherwise sit four orders of magnitude
@@ -223,7 +224,7 @@ def test_quaternion_tail_boundaries():
     tolerance, relative to max|eps|, does not apply."""
     from x2c_inputs.configs import AtomBlock
     c = 7.0
-    Ns = (32, 33, 40, 41, 48, 49, 65, 66)
+    Ns = (1, 2, 32, 33, 40, 41, 48, 49, 65, 66)
     blocks = [AtomBlock(0.0, *random_spd_problem(N, 100 + N, True)) for N in Ns]
     hs, eps, info = gpu_batched(blocks, True, c=c)
     assert np.all(info == 0)
