@@ -751,6 +751,10 @@ def main():
     if mv is not None and mv[1] > 0:
         total_b, launches = matvec_bytes(batch.Ns, twocomp, args.reduction)
         per_launch_b = total_b / max(1, launches)
+        if abs(mv[1] / args.steps - launches) > 0.5:
+            # the byte model's column schedule no longer matches the library's
+            print(f"# warning: {mv[1] / args.steps:.0f} matvec launches per step traced, "
+                  f"{launches} in the byte model", file=sys.stderr, flush=True)
         avg_ms = mv[0] / mv[1]
         achieved = per_launch_b / (avg_ms / 1e3) / 1e9
         traffic = None
