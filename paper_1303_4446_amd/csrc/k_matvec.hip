@@ -20,18 +20,20 @@ namespace x2c {
 // its column partial HS[(nst + SI)*len + c]; a diagonal super-tile also
 // writes its strip's part of the panel dot products (W^H v, V^H v).
 struct MvItem {
-  int valid, b, SI, SJ, len, n, nst;
+  int valid, b, SI, SJ, len, n, nst, st;
 };
 
-// len (returned) counts the lead virtual rows of the tiling too
+// len (returned) counts the lead virtual rows of the tiling too; ST = 0: the
+// block's quaternion super-tile edge mv_st_q(len)
 __device__ inline MvItem mv_decode(const BlockDesc* D, const int* info, int dsel, int k, int nblk, int nsmax,
                                    int item, int ST, int lead) {
-  MvItem it{0, 0, 0, 0, 0, 0, 0};
+  MvItem it{0, 0, 0, 0, 0, 0, 0, 0};
   const int b = item / nsmax, st = item - (item / nsmax) * nsmax;
   if (b >= nblk || info[b]) return it;
   const int n = seldim(D[b], dsel);
   if (n - k - 1 <= 0) return it;
   const int len = n - k - 1 + lead;
+  if (ST == 0) ST = mv_st_q(len);
   const int nst = (len + ST - 1) / ST;
   if (st >= nst * (nst + 1) / 2) return it;
   int SI = (int)((sqrt(8.0 * st + 1.0) - 1.0) * 0.5);
@@ -44,6 +46,7 @@ __device__ inline MvItem mv_decode(const BlockDesc* D, const int* info, int dsel
   it.len = len;
   it.n = n;
   it.nst = nst;
+  it.st = ST;
   return it;
 }
 
@@ -204,25 +207,27 @@ __device__ inline quat quad_sum(const quat& q) {
   return quat{cplx{quad_sum(q.a.x), quad_sum(q.a.y)}, cplx{quad_sum(q.b.x), quad_sum(q.b.y)}};
 }
 
-// Quaternion matvec, one independent wave per 32 x 32 super-tile (persistent
-// over the batch; work-groups of one wave, so no work-group barriers).  The
-// wave issues the loads of all four 16 x 16 sub-tiles (three on the
-// diagonal) and of the two vector segments at once, then stages the
-// sub-tiles one by one through its own LDS tile.  Row sums: lane (i, q)
-// covers row i, columns 4q..4q+3; column sums: lane (j, q) covers column j,
-// rows 4q..4q+3; quads are reduced with DPP.  Output and panel dot products
+// Quaternion matvec, one independent wave per super-tile of st x st (st =
+// 64 or 32, mv_st_q; persistent over the batch; work-groups of one wave, so
+// no work-group barriers).  The wave walks the super-tile's 32 x 32
+// quadrants (three on the diagonal); for each it issues the loads of the four
+// 16 x 16 sub-tiles (three on a diagonal quadrant) at once, then stages them
+// one by one through its own LDS tile.  Row sums: lane (i, q) covers row i,
+// columns 4q..4q+3; column sums: lane (j, q) covers column j, rows
+// 4q..4q+3; quads are reduced with DPP and added into the super-tile's row
+// and column accumulators in a fixed order.  Output and panel dot products
 // as for k_tri_matvec (a diagonal super-tile writes its full Hermitian
-// product as the row partial).
+// product as the row partial), per strip of st rows.
 constexpr int MVW_HT = 16;
 
 __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* ws, const int* info, int dsel,
                                                      int bufA, int bufV, int bufHS, int bufW, int k0, int k,
                                                      int nblk, int nsmax) {
-  constexpr int HT = MVW_HT, ST = 2 * HT, EPL = HT * HT / 64;
+  constexpr int HT = MVW_HT, QT = 2 * HT, EPL = HT * HT / 64;
   const int lane = threadIdx.x;
   __shared__ quat tl[HT][HT + 1];
-  __shared__ quat vsh[2][ST];          // [0] row segment, [1] column segment
-  __shared__ quat racc[ST], cacc[ST];
+  __shared__ quat vsh[2][2 * QT];      // [0] row segment, [1] column segment
+  __shared__ quat racc[2 * QT], cacc[2 * QT];
   const int total = nblk * nsmax;
   // every other step walks the items in reverse, so that a launch starts on
   // the matrices its predecessor read last (still in the memory-side cache)
@@ -230,90 +235,97 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
   // tile index r covers matrix row / column off + r; r < lead are virtual
   const int lead = mv_lead<quat>(k), off = k + 1 - lead;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    const MvItem it = mv_decode(D, info, dsel, k, nblk, nsmax, rev ? total - 1 - item : item, ST, lead);
+    const MvItem it = mv_decode(D, info, dsel, k, nblk, nsmax, rev ? total - 1 - item : item, 0, lead);
     if (!it.valid || k >= tri_tail_start<quat>(it.n)) continue;   // the block's tail kernel takes over
     const BlockDesc& d = D[it.b];
     const quat* A = bufp<quat>(ws, d, bufA);
     const quat* vg = bufp<quat>(ws, d, bufV);
     quat* HS = bufp<quat>(ws, d, bufHS);
-    const int len = it.len, n = it.n, nst = it.nst, SI = it.SI, SJ = it.SJ;
+    const int len = it.len, n = it.n, nst = it.nst, SI = it.SI, SJ = it.SJ, st = it.st;
+    const int nq = st / QT;            // quadrants per side
     const bool diag = SI == SJ;
-    const int R0 = ST * SI, C0 = ST * SJ;
-    // ---- issue every load of the item
-    quat regs[4][EPL];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int a = s >> 1, bb = s & 1;
-      const bool skip = diag && a == 0 && bb == 1;
-      const bool dsub = diag && a == bb;
-#pragma unroll
-      for (int q = 0; q < EPL; ++q) {
-        const int ii = lane / HT + (64 / HT) * q, jj = lane % HT;
-        const int r = R0 + HT * a + ii, c = C0 + HT * bb + jj;
-        regs[s][q] = (!skip && r < len && c < len && r >= lead && c >= lead && (!dsub || ii >= jj))
-                         ? A[(long long)(off + r) * n + off + c] : tzero<quat>();
-      }
+    const int R0 = st * SI, C0 = st * SJ;
+    for (int t = lane; t < 2 * st; t += 64) {
+      const int seg = t / st, u = t - seg * st;
+      const int g = (seg == 0 ? R0 : C0) + u;
+      vsh[seg][u] = (g >= lead && g < len) ? vg[g - lead] : tzero<quat>();
     }
-    {
-      const int seg = lane >> 5, t = lane & 31;
-      const int g = (seg == 0 ? R0 : C0) + t;
-      vsh[seg][t] = (g >= lead && g < len) ? vg[g - lead] : tzero<quat>();
+    for (int t = lane; t < st; t += 64) {
+      racc[t] = tzero<quat>();
+      cacc[t] = tzero<quat>();
     }
-    if (lane < ST) {
-      racc[lane] = tzero<quat>();
-      cacc[lane] = tzero<quat>();
-    }
-    wave_sync();
-    // ---- sub-tiles
-    const int i4 = lane >> 2, q4 = lane & 3;
+    for (int qa = 0; qa < nq; ++qa)
+      for (int qb = 0; qb <= (diag ? qa : nq - 1); ++qb) {
+        const bool qd = diag && qa == qb;    // quadrant on the matrix diagonal
+        const int QR = QT * qa, QC = QT * qb;
+        // ---- issue every load of the quadrant
+        quat regs[4][EPL];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int a = s >> 1, bb = s & 1;
-      if (diag && a == 0 && bb == 1) continue;
-      const bool dsub = diag && a == bb;
+        for (int s = 0; s < 4; ++s) {
+          const int a = s >> 1, bb = s & 1;
+          const bool skip = qd && a == 0 && bb == 1;
+          const bool dsub = qd && a == bb;
 #pragma unroll
-      for (int q = 0; q < EPL; ++q) tl[lane / HT + (64 / HT) * q][lane % HT] = regs[s][q];
-      wave_sync();
-      // row sums: row i4, columns 4 q4 .. 4 q4 + 3
-      quat rs = tzero<quat>();
+          for (int q = 0; q < EPL; ++q) {
+            const int ii = lane / HT + (64 / HT) * q, jj = lane % HT;
+            const int r = R0 + QR + HT * a + ii, c = C0 + QC + HT * bb + jj;
+            regs[s][q] = (!skip && r < len && c < len && r >= lead && c >= lead && (!dsub || ii >= jj))
+                             ? A[(long long)(off + r) * n + off + c] : tzero<quat>();
+          }
+        }
+        wave_sync();
+        // ---- sub-tiles
+        const int i4 = lane >> 2, q4 = lane & 3;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int j = 4 * q4 + t;
-        quat e = tl[i4][j];
-        if (dsub && j == i4) e = treal<quat>(re(e));
-        rs = mad(e, vsh[1][HT * bb + j], rs);
+        for (int s = 0; s < 4; ++s) {
+          const int a = s >> 1, bb = s & 1;
+          if (qd && a == 0 && bb == 1) continue;
+          const bool dsub = qd && a == bb;
+#pragma unroll
+          for (int q = 0; q < EPL; ++q) tl[lane / HT + (64 / HT) * q][lane % HT] = regs[s][q];
+          wave_sync();
+          // row sums: row i4, columns 4 q4 .. 4 q4 + 3
+          quat rs = tzero<quat>();
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int j = 4 * q4 + t;
+            quat e = tl[i4][j];
+            if (dsub && j == i4) e = treal<quat>(re(e));
+            rs = mad(e, vsh[1][QC + HT * bb + j], rs);
+          }
+          // column sums: column i4, rows 4 q4 .. 4 q4 + 3 (strictly below the diagonal)
+          quat cs = tzero<quat>();
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int i = 4 * q4 + t;
+            if (!dsub || i > i4) cs = mad(conjg(tl[i][i4]), vsh[0][QR + HT * a + i], cs);
+          }
+          rs = quad_sum(rs);
+          cs = quad_sum(cs);
+          if (q4 == 0) {
+            racc[QR + HT * a + i4] = racc[QR + HT * a + i4] + rs;
+            cacc[QC + HT * bb + i4] = cacc[QC + HT * bb + i4] + cs;
+          }
+          wave_sync();
+        }
       }
-      // column sums: column i4, rows 4 q4 .. 4 q4 + 3 (strictly below the diagonal)
-      quat cs = tzero<quat>();
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int i = 4 * q4 + t;
-        if (!dsub || i > i4) cs = mad(conjg(tl[i][i4]), vsh[0][HT * a + i], cs);
-      }
-      rs = quad_sum(rs);
-      cs = quad_sum(cs);
-      if (q4 == 0) {
-        racc[HT * a + i4] = racc[HT * a + i4] + rs;
-        cacc[HT * bb + i4] = cacc[HT * bb + i4] + cs;
-      }
-      wave_sync();
-    }
     // ---- partial sums out
-    if (lane < ST) {
+    for (int t = lane; t < st; t += 64) {
       if (diag) {
-        const int r = R0 + lane;
-        if (r < len) HS[(long long)SJ * len + r] = racc[lane] + cacc[lane];
+        const int r = R0 + t;
+        if (r < len) HS[(long long)SJ * len + r] = racc[t] + cacc[t];
       } else {
-        const int r = R0 + lane, c = C0 + lane;
-        if (r < len) HS[(long long)SJ * len + r] = racc[lane];
-        if (c < len) HS[(long long)(nst + SI) * len + c] = cacc[lane];
+        const int r = R0 + t, c = C0 + t;
+        if (r < len) HS[(long long)SJ * len + r] = racc[t];
+        if (c < len) HS[(long long)(nst + SI) * len + c] = cacc[t];
       }
     }
     if (diag) {
       // this strip's part of the panel dot products (j < k - k0)
-      // lane (g, j): panel column j, rows RG g .. RG g + RG - 1 of the strip
-      constexpr int PW = panel_width<quat>(), NG = 64 / PW, RG = ST / NG, PG = 8;
-      static_assert(RG % PG == 0, "row groups of PG loads");
+      // lane (g, j): panel column j, rows rg g .. rg g + rg - 1 of the strip
+      constexpr int PW = panel_width<quat>(), NG = 64 / PW, PG = 8;
+      static_assert(QT / NG % PG == 0, "row groups of PG loads");
+      const int rg = st / NG;
       const int ip = k - k0;
       const quat* Wp = bufp<quat>(ws, d, bufW);
       const int j = lane % PW, g = lane / PW;
@@ -324,19 +336,19 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
         // (clamped in-range addresses, masked values) so that their
         // latencies overlap
 #pragma unroll 1
-        for (int t0 = 0; t0 < RG; t0 += PG) {
+        for (int t0 = 0; t0 < rg; t0 += PG) {
           quat wv[PG], pv[PG];
 #pragma unroll
           for (int u = 0; u < PG; ++u) {
-            const int r = R0 + RG * g + t0 + u;
+            const int r = R0 + rg * g + t0 + u;
             const long long row = off + min(max(r, lead), len - 1);
             wv[u] = Wp[row * PW + j];
             pv[u] = A[row * n + k0 + j];
           }
 #pragma unroll
           for (int u = 0; u < PG; ++u) {
-            const int r = R0 + RG * g + t0 + u;
-            const quat vr = r < len ? vsh[0][RG * g + t0 + u] : tzero<quat>();
+            const int r = R0 + rg * g + t0 + u;
+            const quat vr = r < len ? vsh[0][rg * g + t0 + u] : tzero<quat>();
             s1 = mad(conjg(wv[u]), vr, s1);
             s2 = mad(conjg(pv[u]), vr, s2);
           }
@@ -359,8 +371,8 @@ __global__ void __launch_bounds__(64) k_tri_matvec_w(const BlockDesc* D, char* w
         TP[((long long)SI * PW + j) * 2] = s1;
         TP[((long long)SI * PW + j) * 2 + 1] = s2;
       }
-      wave_sync();
     }
+    wave_sync();
   }
 }
 

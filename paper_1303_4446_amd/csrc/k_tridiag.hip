@@ -275,7 +275,7 @@ template <class T>
 __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, const int* info, int dsel, int bufA,
                                                  int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS,
                                                  int bufET, int k0, int i, int phase) {
-  constexpr int ST = 2 * Tiles<T>::HT, PW = panel_width<T>();
+  constexpr int PW = panel_width<T>();
   const int b = blockIdx.x;
   const BlockDesc& d = D[b];
   if (info[b]) return;
@@ -312,7 +312,9 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     const T tau = taus[kp];
     // the matvec's tiling: lead virtual rows, then the len trailing rows
     const int lead = mv_lead<T>(kp), lenp = len + lead;
-    const int nst = (lenp + ST - 1) / ST;
+    // the matvec's super-tile edge for this block and step
+    const int st = is_quat<T>() ? mv_st_q(lenp) : 2 * Tiles<T>::HT;
+    const int nst = (lenp + st - 1) / st;
     // every load of this part goes out before the first wait: v, column k,
     // row k of the panel and the per-strip panel dot partials (staged in LDS)
     const T* TP = HS + (long long)2 * nst * lenp;
@@ -350,7 +352,7 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
     constexpr int NSU = 4, PU = PW / CTPR, YR = COLT / CTPR;
     const int q = tid % CTPR;
     auto issue = [&](int r, T (&hp)[NSU], T (&vr)[PU], T (&wr)[PU]) {
-      const int rt = r + lead, Sr = rt / ST;
+      const int rt = r + lead, Sr = rt / st;
       const long long rr = off + r;
 #pragma unroll
       for (int u = 0; u < NSU; ++u) {
@@ -367,7 +369,7 @@ __global__ void __launch_bounds__(COLT) k_tri_col(const BlockDesc* D, char* ws, 
       }
     };
     auto finish = [&](int r, const T (&hp)[NSU], const T (&vr)[PU], const T (&wr)[PU]) {
-      const int rt = r + lead, Sr = rt / ST;
+      const int rt = r + lead, Sr = rt / st;
       T acc = tzero<T>(), ca = tzero<T>();
 #pragma unroll
       for (int u = 0; u < NSU; ++u)
@@ -1060,7 +1062,7 @@ template <class T>
 void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* info, int nblk, int maxdim, int dsel,
                      int bufA, int bufD, int bufE, int bufTau, int bufW, int bufV, int bufHS, int bufET,
                      int mv_res) {
-  constexpr int ST = 2 * Tiles<T>::HT, TT = Tiles<T>::TT, PW = panel_width<T>();
+  constexpr int ST = 2 * Tiles<T>::HT, TT = Tiles<T>::TT, PW = panel_width<T>();   // ST: the smallest edge
   if constexpr (!is_quat<T>()) {
     if (maxdim <= 96) {
       launch_hetrd<T>(s, D, ws, info, nblk, maxdim, dsel, bufA, bufD, bufE, bufTau);
@@ -1083,8 +1085,11 @@ void launch_hetrd_mk(hipStream_t s, const BlockDesc* D, char* ws, const int* inf
     for (int i = 0; i < kbmax; ++i) {
       const int k = k0 + i;
       const int len = maxdim - k - 1 + mv_lead<T>(k);
-      const int nst = (len + ST - 1) / ST;
-      const int nsmax = nst * (nst + 1) / 2;
+      // items per block: the most any block can have at this step (a
+      // quaternion block takes its super-tile edge from its own length)
+      auto items = [](int l, int e) { const int ns = (l + e - 1) / e; return ns * (ns + 1) / 2; };
+      const int nsmax = !is_quat<T>() ? items(len, ST)
+                        : std::max(items(len, mv_st_q(len)), items(std::min(len, MV_ST64_LEN), ST));
       hipEvent_t ev0, ev1;
       void* kt = ktrace_begin("k_tri_matvec", &ev0, &ev1);
       launch_matvec<T>(s, D, ws, info, nblk, dsel, bufA, bufV, bufHS, bufW, k0, k, nsmax, ncu, mv_res, ev0, ev1);

@@ -52,6 +52,15 @@ __host__ __device__ constexpr int tri_tail_start(int n) {
   }
 }
 
+// Super-tile edge of the quaternion matvec for a block whose tile grid at
+// this step (virtual lead rows included) has len rows: 64 x 64 items while
+// the trailing matrix is long (half the partial sums of 32 x 32 ones), 32 x
+// 32 once it is short (finer items).  A function of the block's own length,
+// so a block's results do not depend on its batch; the column kernel reads
+// the partials with the same edge.
+constexpr int MV_ST64_LEN = 192;
+__host__ __device__ constexpr int mv_st_q(int len) { return len > MV_ST64_LEN ? 64 : 32; }
+
 // Leading virtual rows / columns of the matvec tiling at column step k.  The
 // quaternion tiles start on a 128-byte boundary (4 quaternions): the trailing
 // matrix (first row / column k + 1) is preceded by (k + 1) mod 4 zero rows /
